@@ -1,0 +1,145 @@
+"""Burer-Monteiro ALM solve with L-BFGS and exact line search (paper Sections 2.1-2.2,
+Algorithm 1, appendix A.2), and the splitting (ADMM) phase (Section 2.2, eqs. 2.2-2.3,
+Algorithm 2).
+
+Test infrastructure only (see the package docstring).
+
+Where the paper defers to LoRADS/SDPLR for schedule details (initial multiplier,
+penalty schedule, inner tolerance, memory length), the numbers below are this
+project's own reading; the GPU library takes the same numbers from its own
+options struct (the two share numbers, not code):
+
+* y0 = 0; sigma0 = ||vec(C)||_1 / m unless given;
+* after each inner solve: y <- y + sigma (b - A(RR^T));
+  sigma <- min(sigma_factor * sigma, sigma_max_ratio * sigma0) when err1 did not
+  fall below feas_decrease * (previous err1);
+* inner L-BFGS stops when ||grad||_F <= eta_k * max(1, ||grad at its start||_F),
+  eta_0 = eta0, eta_{k+1} = max(eta_factor * eta_k, eta_min);
+* L-BFGS memory T = lbfgs_mem pairs from consecutive iterations; a pair failing
+  the curvature guard, or a direction that is not a descent direction, clears
+  the memory (the next direction is -grad);
+* stop when err1 <= tol and |err3| <= tol (the paper's mild re-opt criterion).
+"""
+
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import kernels as K
+from .lbfgs import accept_pair, two_loop
+from .problem import SDPProblem
+
+
+@dataclass
+class Options:
+    tol: float = 1e-5
+    lbfgs_mem: int = 4
+    max_outer: int = 300
+    max_inner: int = 2000
+    max_iter_total: int = 200000
+    sigma0: float = 0.0            # 0 selects ||vec(C)||_1 / m
+    sigma_factor: float = 2.0
+    sigma_max_ratio: float = 1e8
+    feas_decrease: float = 0.25
+    eta0: float = 1e-1
+    eta_factor: float = 0.25
+    eta_min: float = 1e-9
+    time_limit: float = 1e30
+
+
+@dataclass
+class SolveResult:
+    R: np.ndarray
+    y: np.ndarray
+    sigma: float
+    obj: float
+    dual: float
+    err1: float
+    err1_inf: float
+    err3: float
+    outer: int
+    inner: int
+    converged: bool
+    seconds: float
+    history: list = field(default_factory=list)
+
+
+def default_sigma0(prob: SDPProblem) -> float:
+    return max(prob.c_l1 / prob.m, 1e-8)
+
+
+def lbfgs_minimize(prob: SDPProblem, R, y, sigma, eta, opts: Options, budget: int):
+    """Minimise L(.; y, sigma) from R with Algorithm 1 and the exact step."""
+    G = K.gradient(prob, R, y, sigma)
+    gnorm = float(np.sqrt(np.sum(G * G)))
+    target = eta * max(1.0, gnorm)
+    pairs = []
+    it = 0
+    while it < min(opts.max_inner, budget):
+        if gnorm <= target:
+            break
+        D = two_loop(G, pairs)
+        c = K.linesearch_coeffs(prob, R, D, y, sigma)
+        if not c["a4"] < 0.0:
+            pairs = []
+            D = -G
+            c = K.linesearch_coeffs(prob, R, D, y, sigma)
+        tau = K.exact_step(c["a1"], c["a2"], c["a3"], c["a4"])
+        it += 1
+        if tau <= 0.0:
+            break
+        Rn = R + tau * D
+        Gn = K.gradient(prob, Rn, y, sigma)
+        s = tau * D
+        yv = Gn - G
+        if accept_pair(s, yv):
+            pairs.append((s, yv))
+            if len(pairs) > opts.lbfgs_mem:
+                pairs.pop(0)
+        else:
+            pairs = []
+        R, G = Rn, Gn
+        gnorm = float(np.sqrt(np.sum(G * G)))
+    return R, it, gnorm
+
+
+def alm_solve(prob: SDPProblem, R0: np.ndarray, y0=None, opts: Options | None = None,
+              log=None) -> SolveResult:
+    opts = opts or Options()
+    t0 = time.perf_counter()
+    R = np.array(R0, dtype=np.float64, copy=True)
+    y = np.zeros(prob.m) if y0 is None else np.array(y0, dtype=np.float64, copy=True)
+    sigma = opts.sigma0 if opts.sigma0 > 0 else default_sigma0(prob)
+    sigma_cap = sigma * opts.sigma_max_ratio
+    eta = opts.eta0
+    err1_prev = np.inf
+    total = 0
+    hist = []
+    converged = False
+    meas = K.alm_measures(prob, R, y)
+    outer = 0
+    for outer in range(1, opts.max_outer + 1):
+        R, it, gnorm = lbfgs_minimize(prob, R, y, sigma, eta, opts, opts.max_iter_total - total)
+        total += it
+        y = K.multiplier_estimate(prob, R, y, sigma)
+        meas = K.alm_measures(prob, R, y)
+        rec = dict(outer=outer, inner=it, sigma=sigma, gnorm=gnorm, **meas)
+        hist.append(rec)
+        if log is not None:
+            log(rec)
+        if meas["err1"] <= opts.tol and abs(meas["err3"]) <= opts.tol:
+            converged = True
+            break
+        if total >= opts.max_iter_total or time.perf_counter() - t0 > opts.time_limit:
+            break
+        if meas["err1"] > opts.feas_decrease * err1_prev:
+            sigma = min(sigma * opts.sigma_factor, sigma_cap)
+        err1_prev = meas["err1"]
+        eta = max(eta * opts.eta_factor, opts.eta_min)
+    return SolveResult(R=R, y=y, sigma=sigma, obj=meas["obj"], dual=meas["dual"],
+                       err1=meas["err1"], err1_inf=meas["err1_inf"], err3=meas["err3"],
+                       outer=outer, inner=total, converged=converged,
+                       seconds=time.perf_counter() - t0, history=hist)
