@@ -1,0 +1,254 @@
+/*
+ * lrsdp.h - C ABI of the MI355X (gfx950) low-rank SDP library.
+ *
+ * The library solves the linear SDP
+ *
+ *     min <C, X>   s.t.   A(X) = b,   X psd,   X = R R^T,  R in R^{n x r}
+ *
+ * (the problem statement of the paper's introduction, eq. prob:sdp, with the
+ * Burer-Monteiro factorisation of Section 2.1) for two constraint families:
+ *
+ *   MaxCut      C = -L(G,w)/4, A(X) = diag(X), b = 1   (paper, MaxCut section)
+ *   completion  C = I, A_k = E_{i,n1+j} + E_{n1+j,i}, b_k = 2 M_ij
+ *               (paper, matrix-completion section)
+ *
+ * Multiplier convention (the paper's appendix A.2 and its error measures):
+ *
+ *     L(R; y, sigma) = <C,RR^T> + y^T (b - A(RR^T)) + sigma/2 ||b - A(RR^T)||^2
+ *     ytil           = y + sigma (b - A(RR^T))
+ *     grad_R L       = 2 (C - A*(ytil)) R,      multiplier update  y <- ytil
+ *
+ * (the introduction's  lambda <- lambda + rho (A(RR^T) - b)  is the same method
+ * with lambda = -y and rho = sigma).
+ *
+ * Conventions for every call:
+ *   - Return value: LRSDP_OK (0) or a negative LRSDP_E* code; lrsdp_last_error()
+ *     returns a thread-local message for the last failing call.  No C++
+ *     exception crosses the ABI.
+ *   - "host" pointers are read (or written) during the call only and stay owned
+ *     by the caller.  "device" pointers are caller-owned HIP device memory on
+ *     the context's device; the library never frees them.
+ *   - Device work is enqueued on the stream given to lrsdp_ctx_create.  Calls
+ *     returning host results synchronise that stream; kernel entry points
+ *     (lrsdp_k_*) only enqueue.
+ *   - Factor matrices are row-major n x ld with ld >= r; element type is double
+ *     (LRSDP_F64) or float (LRSDP_F32, LRSDP_F32_BF16IN).  Pad columns r..ld-1
+ *     must hold zeros and are kept at zero.  ld * sizeof(element) must be a
+ *     multiple of 16 bytes.
+ *   - Handles are not thread-safe: use one context per host thread / stream.
+ */
+#ifndef LRSDP_H
+#define LRSDP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------------- */
+#define LRSDP_OK              0
+#define LRSDP_NOT_CONVERGED   1   /* solve stopped at a limit; result is valid   */
+#define LRSDP_EINVAL         -1   /* invalid argument or malformed input data    */
+#define LRSDP_ENOMEM         -2   /* caller buffer too small (message has size)  */
+#define LRSDP_EHIP           -3   /* HIP runtime error                           */
+#define LRSDP_ENUMERIC       -4   /* NaN/Inf met in a reduction                  */
+#define LRSDP_EUNSUPPORTED   -5   /* valid request not supported by this build   */
+
+/* ---- precisions (storage of R and the n x r work arrays) ------------------- */
+#define LRSDP_F64          0   /* everything in float64                          */
+#define LRSDP_F32          1   /* n x r arrays in float32, reductions in float64  */
+#define LRSDP_F32_BF16IN   2   /* as F32, plus a bfloat16 shadow of the gathered
+                                  SpMM operand (round-to-nearest-even)            */
+
+/* ---- problem kinds --------------------------------------------------------- */
+#define LRSDP_MAXCUT       1
+#define LRSDP_COMPLETION   2
+
+typedef struct lrsdp_ctx lrsdp_ctx;
+typedef struct lrsdp_problem lrsdp_problem;
+
+/* Last error message of the calling thread ("" if none). */
+const char *lrsdp_last_error(void);
+
+/* Library version string. */
+const char *lrsdp_version(void);
+
+/* ---- context ----------------------------------------------------------------
+ * Binds a HIP device and a stream (hipStream_t passed as void*, NULL = the
+ * default stream).  Allocates, once, a small device scratch area for reduction
+ * partials and solver state, and a pinned host block for status read-back.
+ * Errors: EINVAL (bad device), EHIP.
+ */
+int  lrsdp_ctx_create(int device, void *hip_stream, lrsdp_ctx **out);
+void lrsdp_ctx_destroy(lrsdp_ctx *ctx);
+
+/* ---- problems (host-side build) -------------------------------------------
+ * MaxCut on an undirected graph with n nodes and n_edges edges (u[e], v[e]),
+ * host int32 arrays; w = host float64 weights or NULL for unit weights.  Builds
+ * the CSR of C = -L/4 (off-diagonal C_ij = w_ij/4, diagonal kept separately as
+ * C_ii = -sum_j w_ij/4), b = 1.  Rejects (EINVAL) endpoints outside [0,n), self
+ * loops, repeated edges and non-finite weights.  When every weight is +1 or -1
+ * the values are stored implicitly in the column index.
+ */
+int lrsdp_problem_maxcut(int64_t n, int64_t n_edges, const int32_t *u,
+                         const int32_t *v, const double *w,
+                         lrsdp_problem **out);
+
+/* Matrix completion: n1 x n2 matrix, m observed entries (i[k], j[k]) with values
+ * Mij[k] (host arrays).  X has order n1 + n2, C = I, b_k = 2 Mij[k].  Rejects
+ * (EINVAL) out-of-range or repeated (i, j) and non-finite values.
+ */
+int lrsdp_problem_completion(int64_t n1, int64_t n2, int64_t m,
+                             const int32_t *i, const int32_t *j,
+                             const double *Mij, lrsdp_problem **out);
+
+void lrsdp_problem_destroy(lrsdp_problem *prob);
+
+typedef struct {
+    int     kind;        /* LRSDP_MAXCUT or LRSDP_COMPLETION                     */
+    int64_t n;           /* order of X                                           */
+    int64_t m;           /* number of constraints                                */
+    int64_t nnz;         /* stored off-diagonal nonzeros of the SpMM operator    */
+    int64_t n1, n2;      /* completion block sizes (0 for MaxCut)                */
+    int     weights;     /* MaxCut: 0 unit, 1 sign (+-1), 2 general               */
+    int64_t max_row_nnz; /* longest row of the SpMM operator                     */
+    double  c_l1;        /* ||vec(C)||_1                                         */
+    double  b_l1;        /* ||b||_1                                              */
+    double  b_inf;       /* ||b||_inf                                            */
+} lrsdp_problem_info;
+
+int lrsdp_problem_get_info(const lrsdp_problem *prob, lrsdp_problem_info *out);
+
+/* Bytes of device memory the problem occupies once uploaded. */
+int lrsdp_problem_device_bytes(const lrsdp_problem *prob, size_t *bytes);
+
+/* Copy the problem into caller-owned device memory `dev` of `bytes` bytes
+ * (ENOMEM if smaller than lrsdp_problem_device_bytes; the message states the
+ * size).  Synchronises the context stream.  `dev` must stay alive while the
+ * problem is used.  A problem is uploaded to one context at a time.
+ */
+int lrsdp_problem_upload(lrsdp_ctx *ctx, lrsdp_problem *prob, void *dev,
+                         size_t bytes);
+
+/* ---- solver options ---------------------------------------------------------
+ * Defaults (lrsdp_options_default): F64, T = 4 L-BFGS pairs, tol = 1e-5,
+ * sigma0 = 0 (selects ||vec(C)||_1 / m), sigma_factor = 2, sigma_max_ratio =
+ * 1e8, feas_decrease = 0.25, eta0 = 0.1, eta_factor = 0.25, eta_min = 1e-9,
+ * max_outer = 300, max_inner = 2000, max_iter_total = 200000,
+ * check_every = 8, time_limit_s = 1e30, refresh_every = 0 (off).
+ */
+typedef struct {
+    int     prec;             /* LRSDP_F64 / LRSDP_F32 / LRSDP_F32_BF16IN      */
+    int     rank;             /* r (columns of R actually used)                */
+    int     ld;               /* row stride of R and work arrays (>= rank)     */
+    int     lbfgs_mem;        /* T, 1..8                                       */
+    double  tol;              /* stop when err1 <= tol and |err3| <= tol       */
+    int     max_outer;
+    int     max_inner;        /* L-BFGS iterations per ALM subproblem          */
+    int64_t max_iter_total;
+    double  time_limit_s;
+    double  sigma0;           /* <= 0: ||vec(C)||_1 / m                        */
+    double  sigma_factor;     /* sigma growth when err1 stalls                 */
+    double  sigma_max_ratio;  /* sigma <= sigma_max_ratio * sigma0             */
+    double  feas_decrease;    /* stall test: err1 > feas_decrease * err1_prev  */
+    double  eta0;             /* inner tolerance factor of the first subproblem*/
+    double  eta_factor;
+    double  eta_min;
+    int     check_every;      /* L-BFGS iterations enqueued between host checks*/
+    int     refresh_every;    /* recompute C R exactly every k inner iterations
+                                 (0 = only at each ALM step)                   */
+    int     profile;          /* 1: time SpMM launches with HIP events         */
+    int     verbose;          /* 1: print one line per ALM step to stderr      */
+} lrsdp_options;
+
+void lrsdp_options_default(lrsdp_options *opts);
+
+typedef struct {
+    double  obj;          /* <C, RR^T>                                         */
+    double  dual;         /* b^T y                                             */
+    double  err1;         /* ||A(X) - b||_2 / (1 + ||b||_1)                    */
+    double  err1_inf;     /* ||A(X) - b||_2 / (1 + ||b||_inf)                  */
+    double  err3;         /* (obj - dual) / (1 + |obj| + |dual|)               */
+    double  sigma;        /* final penalty                                     */
+    double  seconds;      /* wall time of the solve (host clock)               */
+    int64_t outer;        /* ALM steps                                         */
+    int64_t inner;        /* total L-BFGS iterations                           */
+    int     status;       /* LRSDP_OK or LRSDP_NOT_CONVERGED                   */
+    int     spmm_launches;/* profiled SpMM launches (profile = 1)              */
+    double  spmm_ms;      /* summed duration of those launches (HIP events)    */
+    double  spmm_bytes;   /* algorithmic bytes of one SpMM launch              */
+} lrsdp_result;
+
+/* Device workspace the solve needs for this problem and these options. */
+int lrsdp_workspace_bytes(const lrsdp_problem *prob, const lrsdp_options *opts,
+                          size_t *bytes);
+
+/* Solve from the starting factor R (device, n x ld, element type of
+ * opts->prec; overwritten with the final factor) and multipliers y (device,
+ * m float64; in: y0, out: final y).  `ws` is caller-owned device memory of at
+ * least lrsdp_workspace_bytes.  Blocking.  Returns LRSDP_OK when converged,
+ * LRSDP_NOT_CONVERGED at a limit (res still filled), or an error code.
+ * The algorithm: ALM (Section 2.1) whose subproblem is minimised by L-BFGS
+ * (Algorithm 1, H0 = I) with the exact quartic line search of appendix A.2.
+ */
+int lrsdp_solve(lrsdp_ctx *ctx, lrsdp_problem *prob, const lrsdp_options *opts,
+                void *ws, size_t ws_bytes, void *R, double *y,
+                lrsdp_result *res);
+
+/* ---- kernel entry points (enqueue only; all pointers device) ----------------
+ * `prec` selects the element type of the n x ld arrays as above.
+ */
+
+/* Y = (C - A*(ytil)) V  (eq. At of Section 3.4); ytil (m float64) may be NULL
+ * (then Y = C V).  Y must not alias V. */
+int lrsdp_k_spmm(lrsdp_ctx *ctx, const lrsdp_problem *prob, int prec,
+                 const void *V, int64_t ld, const double *ytil, void *Y);
+
+/* out[k] = <A_k, U V^T> (m float64): the compressed outer product of Section
+ * 3.4 (MaxCut: row dot U_i.V_i; completion: 2 U_i . V_{n1+j}).  V may be NULL
+ * (then V = U). */
+int lrsdp_k_constraint(lrsdp_ctx *ctx, const lrsdp_problem *prob, int prec,
+                       const void *U, const void *V, int64_t ld, double *out);
+
+/* Exact line-search coefficients of appendix A.2 for direction D at R with
+ * multipliers y and penalty sigma.  out (device, 8 float64) receives
+ * {a1, a2, a3, a4, p1, p2, ||q1||^2, ||q2||^2}; q1, q2 (device, m float64) may
+ * be NULL or receive A(RD^T + DR^T) and A(DD^T).  `work` is a device n x ld
+ * array of the element type (scratch for C R and C D; 2 arrays). */
+int lrsdp_k_ls_coeffs(lrsdp_ctx *ctx, const lrsdp_problem *prob, int prec,
+                      const void *R, const void *D, int64_t ld,
+                      const double *y, double sigma, void *work,
+                      double *out, double *q1, double *q2);
+
+/* Step tau >= 0 minimising a1 t^4 + a2 t^3 + a3 t^2 + a4 t over t > 0 (roots of
+ * 4 a1 t^3 + 3 a2 t^2 + 2 a3 t + a4; the real root with the smallest quartic
+ * value, smaller t on ties; 0 when no positive step decreases it).  a: device
+ * 4 float64, tau: device 1 float64. */
+int lrsdp_k_cubic(lrsdp_ctx *ctx, const double *a, double *tau);
+
+/* ALM multiplier step and measures at R (Section 2.1; error measures of the
+ * experimental setting): y <- y + sigma (b - A(RR^T)) when sigma > 0 (y left
+ * unchanged when sigma == 0), then out (device, 8 float64) =
+ * {obj, dual = b^T y, ||A(RR^T) - b||_2, err1, err1_inf, err3, 0, 0}.
+ * `work` is a device n x ld scratch array of the element type. */
+int lrsdp_k_alm(lrsdp_ctx *ctx, const lrsdp_problem *prob, int prec,
+                const void *R, int64_t ld, double *y, double sigma, void *work,
+                double *out);
+
+/* Compact-form L-BFGS direction (Algorithm 1, H0 = I) for gradient G and k
+ * pairs s_t = S[t], y_t = Y[t] (oldest first; S, Y: host arrays of k device
+ * pointers each, k <= 8), all n x ld of the element type.  D = -H G, computed
+ * as the two-loop recursion on the Gram matrix of {G, s_t, y_t}.  Synchronises
+ * the stream (the Gram matrix is checked on the host); returns EINVAL if some
+ * <y_t, s_t> <= 0. */
+int lrsdp_k_lbfgs_dir(lrsdp_ctx *ctx, int prec, int64_t n, int64_t ld,
+                      const void *G, const void *const *S, const void *const *Y,
+                      int k, void *D);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LRSDP_H */

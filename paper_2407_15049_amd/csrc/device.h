@@ -1,0 +1,124 @@
+// Device helpers shared by the lrsdp kernels: 16-byte row chunks, lane-group
+// and wavefront reductions (64-wide wavefronts), deterministic block sums.
+#pragma once
+
+#include "internal.h"
+
+namespace lrsdp {
+
+// A row of an n x ld array is processed in 16-byte chunks: 2 doubles or 4 floats.
+template <typename S> struct Chunk;
+template <> struct Chunk<double> {
+    using V = double2;
+    static constexpr int N = 2;
+};
+template <> struct Chunk<float> {
+    using V = float4;
+    static constexpr int N = 4;
+};
+
+__device__ __forceinline__ double2 vzero(double2) { return make_double2(0.0, 0.0); }
+__device__ __forceinline__ float4 vzero(float4) { return make_float4(0.f, 0.f, 0.f, 0.f); }
+
+// a += w * b
+__device__ __forceinline__ void vfma(double2 &a, double w, const double2 &b) {
+    a.x = fma(w, b.x, a.x);
+    a.y = fma(w, b.y, a.y);
+}
+__device__ __forceinline__ void vfma(float4 &a, float w, const float4 &b) {
+    a.x = fmaf(w, b.x, a.x);
+    a.y = fmaf(w, b.y, a.y);
+    a.z = fmaf(w, b.z, a.z);
+    a.w = fmaf(w, b.w, a.w);
+}
+
+// float64 dot product of two chunks (float inputs promoted before the products)
+__device__ __forceinline__ double vdot(const double2 &a, const double2 &b) {
+    return fma(a.x, b.x, a.y * b.y);
+}
+__device__ __forceinline__ double vdot(const float4 &a, const float4 &b) {
+    double s = (double)a.x * (double)b.x;
+    s = fma((double)a.y, (double)b.y, s);
+    s = fma((double)a.z, (double)b.z, s);
+    s = fma((double)a.w, (double)b.w, s);
+    return s;
+}
+
+// Chunk <-> 4 doubles (x, y, z, w; unused lanes zero for double2)
+struct D4 {
+    double v[4];
+};
+__device__ __forceinline__ D4 widen(const double2 &a) { return D4{{a.x, a.y, 0.0, 0.0}}; }
+__device__ __forceinline__ D4 widen(const float4 &a) {
+    return D4{{(double)a.x, (double)a.y, (double)a.z, (double)a.w}};
+}
+__device__ __forceinline__ void narrow(const D4 &d, double2 &a) {
+    a.x = d.v[0];
+    a.y = d.v[1];
+}
+__device__ __forceinline__ void narrow(const D4 &d, float4 &a) {
+    a.x = (float)d.v[0];
+    a.y = (float)d.v[1];
+    a.z = (float)d.v[2];
+    a.w = (float)d.v[3];
+}
+
+template <typename V>
+__device__ __forceinline__ V ldg(const V *p) {
+    return *p;
+}
+
+// Sum over an aligned group of GS lanes (GS a power of two <= 64).
+template <int GS>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+    for (int o = GS / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, GS);
+    return v;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Reduce K per-thread sums over the block (kBlock threads) and write them to
+// out[0..K) (one row of the partials array).  Fixed order: deterministic.
+template <int K>
+__device__ __forceinline__ void block_sums_store(const double (&s)[K], double *out) {
+    __shared__ double sh[kBlock / 64][K > 0 ? K : 1];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double v = wave_sum(s[k]);
+        if (lane == 0) sh[wave][k] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < K) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) t += sh[w][threadIdx.x];
+        out[threadIdx.x] = t;
+    }
+}
+
+// Inside a single-block kernel: out[k] = sum_b part[b*stride + k], k < K,
+// b < nblk.  Fixed order (strided per thread, then a tree): deterministic.
+__device__ __forceinline__ void reduce_partials(const double *part, int nblk, int stride, int K,
+                                                double *out /* shared or global, K */) {
+    __shared__ double red[kBlock];
+    for (int k = 0; k < K; ++k) {
+        double t = 0.0;
+        for (int b = threadIdx.x; b < nblk; b += kBlock) t += part[(size_t)b * stride + k];
+        red[threadIdx.x] = t;
+        __syncthreads();
+        for (int h = kBlock / 2; h > 0; h >>= 1) {
+            if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[k] = red[0];
+        __syncthreads();
+    }
+}
+
+}  // namespace lrsdp

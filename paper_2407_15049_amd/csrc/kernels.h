@@ -1,0 +1,78 @@
+// Kernel launchers and the device-resident solver state.
+#pragma once
+
+#include "internal.h"
+
+namespace lrsdp {
+
+// Solver state kept in device memory: the host only enqueues kernels and reads
+// this block back every few iterations.
+struct SolverState {
+    // current L-BFGS subproblem
+    double tau;                          // last step
+    double sigma;                        // penalty
+    double sigma_cap;                    // sigma_max_ratio * sigma0
+    double eta;                          // inner tolerance factor
+    double target;                       // inner stop: ||G||_F <= target
+    double gnorm;                        // ||G_k||_F
+    double a[4];                         // quartic coefficients a1..a4
+    double taus[kMaxMem];                // step of the direction in each D slot
+    double gram[kMaxBasis * kMaxBasis];  // Gram matrix of the G/D ring slots
+    double coef[kMaxBasis];              // next direction = sum coef_j basis_j
+    // ALM measures after the last multiplier step
+    double obj, dual, res_norm, err1, err1_inf, err3, err1_prev;
+    // options copied at solve start
+    double tol, sigma_factor, feas_decrease, eta_factor, eta_min, b_l1, b_inf;
+    int64_t inner_total;
+    int max_inner;
+    int T;          // L-BFGS memory
+    int k;          // iteration within the subproblem
+    int nmem;       // valid pairs
+    int gk;         // G ring slot of the current gradient (0..T)
+    int dk;         // D ring slot of the current direction (0..T-1)
+    int done;       // 0 running; 1 gradient small; 2 max_inner; 3 no descent step
+    int converged;  // ALM stop test met
+    int numeric;    // NaN/Inf met
+    int refreshes;  // exact C R recomputations
+};
+
+// Pointers of the L-BFGS rings: G slots 0..T, D slots 0..T-1.  Basis index of
+// G slot g is g, of D slot d is T + 1 + d.
+template <typename S>
+struct Rings {
+    S *g[kMaxMem + 1];
+    S *d[kMaxMem];
+};
+
+enum EpiKind { kEpiPlain = 0, kEpiLS = 1, kEpiRefresh = 2 };
+
+// Arguments of one SpMM Y = C V (+ epilogue).  See spmm_maxcut.hip.
+struct SpmmArgs {
+    int epi = kEpiPlain;
+    const void *V = nullptr;        // gathered operand
+    void *Y = nullptr;              // output rows (C V, shifted for kEpiPlain)
+    const void *R = nullptr;        // kEpiLS: R rows
+    const void *aux = nullptr;      // kEpiLS: C R rows for p1 (nullable)
+    const double *ytil = nullptr;   // kEpiPlain: shift (nullable); kEpiLS: ytil
+    double *y = nullptr;            // kEpiRefresh: multipliers
+    double *rn = nullptr;           // kEpiRefresh: ||R_i||^2 out (nullable)
+    double sigma = 0.0;             // kEpiRefresh: y <- y - sigma (rn - 1) if > 0
+    double *q1 = nullptr;           // kEpiLS: optional per-constraint outputs
+    double *q2 = nullptr;
+    int64_t ld = 0;
+    double *partials = nullptr;     // per-block sums (kMaxSums stride)
+    const SolverState *st = nullptr;  // if set, skip when st->done != 0
+};
+
+// MaxCut SpMM; returns status, *nparts = rows written in partials.
+int spmm_maxcut(hipStream_t s, const DevCsr &P, int prec, const SpmmArgs &a, int *nparts);
+
+// Completion SpMM Y = (I - A*(ytil)) V and SDDMMs.
+int spmm_completion(hipStream_t s, const DevCompletion &P, int prec, const void *V, int64_t ld,
+                    const double *ytil, void *Y);
+
+// number of sums per partial row of each stage
+constexpr int kLsSums = 8;
+constexpr int kRefSums = 4;
+
+}  // namespace lrsdp

@@ -1,0 +1,392 @@
+// Host-side problem build (CSR of the SpMM operator, work lists) and upload.
+//
+// MaxCut (paper, MaxCut section): C = -L(G,w)/4 with the Laplacian
+// L_ij = -w_ij on edges and L_ii = sum_k w_ik, so C_ij = w_ij/4 off the
+// diagonal and C_ii = -sum_k w_ik/4; A(X) = diag(X), b = 1.
+//
+// Completion (paper, matrix-completion section): X = [[W1, M], [M^T, W2]] of
+// order n1 + n2, C = I, sample k = (i, j) gives A_k = E_{i,n1+j} + E_{n1+j,i}
+// and b_k = 2 M_ij.  The operator C - A*(y) then has unit diagonal and the
+// off-diagonal entries -y_k at (i, n1+j) and (n1+j, i), stored as a "top" CSR
+// (rows i, column j) and a "bottom" CSR (rows j, column i, sample id).
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+
+#include "internal.h"
+
+namespace lrsdp {
+
+static thread_local std::string g_last_error;
+
+int set_error(int code, const char *fmt, ...) {
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+void clear_error() { g_last_error.clear(); }
+
+}  // namespace lrsdp
+
+using namespace lrsdp;
+
+extern "C" const char *lrsdp_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" const char *lrsdp_version(void) { return "lrsdp 0.1 (gfx950)"; }
+
+namespace {
+
+// Light rows sorted by decreasing length inside windows of consecutive rows, so
+// a wavefront's groups walk rows of similar length while touching nearby rows.
+constexpr int64_t kWindow = 8192;
+
+void build_work_lists(lrsdp_problem *p, int64_t n) {
+    const auto &rp = p->row_ptr;
+    p->light.clear();
+    p->heavy.clear();
+    p->seg.clear();
+    p->heavy_seg.assign(1, 0);
+    std::vector<int32_t> win;
+    for (int64_t w0 = 0; w0 < n; w0 += kWindow) {
+        int64_t w1 = std::min(n, w0 + kWindow);
+        win.clear();
+        for (int64_t i = w0; i < w1; ++i) {
+            int64_t len = rp[i + 1] - rp[i];
+            if (len <= kSegLen) {
+                win.push_back((int32_t)i);
+            } else {
+                p->heavy.push_back((int32_t)i);
+                for (int64_t b = rp[i]; b < rp[i + 1]; b += kSegLen) {
+                    int4 s;
+                    s.x = (int32_t)i;
+                    s.y = (int32_t)b;
+                    s.z = (int32_t)std::min<int64_t>(b + kSegLen, rp[i + 1]);
+                    s.w = (int32_t)p->seg.size();
+                    p->seg.push_back(s);
+                }
+                p->heavy_seg.push_back((int32_t)p->seg.size());
+            }
+        }
+        std::stable_sort(win.begin(), win.end(), [&](int32_t a, int32_t b) {
+            return (rp[a + 1] - rp[a]) > (rp[b + 1] - rp[b]);
+        });
+        p->light.insert(p->light.end(), win.begin(), win.end());
+    }
+}
+
+}  // namespace
+
+extern "C" int lrsdp_problem_maxcut(int64_t n, int64_t n_edges, const int32_t *u,
+                                    const int32_t *v, const double *w,
+                                    lrsdp_problem **out) {
+    clear_error();
+    if (!out) return set_error(LRSDP_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || n > INT32_MAX - 1) return set_error(LRSDP_EINVAL, "n = %lld out of range", (long long)n);
+    if (n_edges < 0) return set_error(LRSDP_EINVAL, "n_edges < 0");
+    if (n_edges > 0 && (!u || !v)) return set_error(LRSDP_EINVAL, "edge arrays are NULL");
+    if (2 * n_edges > (int64_t)INT32_MAX) return set_error(LRSDP_EUNSUPPORTED, "2*n_edges exceeds int32 indexing");
+
+    int mode = kWUnit;
+    if (w) {
+        mode = kWSign;
+        for (int64_t e = 0; e < n_edges; ++e) {
+            if (!std::isfinite(w[e])) return set_error(LRSDP_EINVAL, "weight %lld is not finite", (long long)e);
+            if (w[e] != 1.0 && w[e] != -1.0) mode = kWGeneral;
+        }
+    }
+    std::vector<int64_t> deg(n + 1, 0);
+    for (int64_t e = 0; e < n_edges; ++e) {
+        int64_t a = u[e], b = v[e];
+        if (a < 0 || a >= n || b < 0 || b >= n)
+            return set_error(LRSDP_EINVAL, "edge %lld = (%lld, %lld) has an endpoint outside [0, %lld)",
+                             (long long)e, (long long)a, (long long)b, (long long)n);
+        if (a == b) return set_error(LRSDP_EINVAL, "edge %lld is a self loop at node %lld", (long long)e, (long long)a);
+        deg[a]++;
+        deg[b]++;
+    }
+    auto *p = new lrsdp_problem();
+    p->row_ptr.resize(n + 1);
+    p->row_ptr[0] = 0;
+    for (int64_t i = 0; i < n; ++i) p->row_ptr[i + 1] = (int32_t)(p->row_ptr[i] + deg[i]);
+    const int64_t nnz = p->row_ptr[n];
+    std::vector<int32_t> fill(p->row_ptr.begin(), p->row_ptr.end() - 1);
+    std::vector<double> wv(nnz);
+    p->col.resize(nnz);
+    for (int64_t e = 0; e < n_edges; ++e) {
+        double we = w ? w[e] : 1.0;
+        int32_t a = u[e], b = v[e];
+        int32_t pa = fill[a]++, pb = fill[b]++;
+        p->col[pa] = b;
+        p->col[pb] = a;
+        wv[pa] = we;
+        wv[pb] = we;
+    }
+    // sort each row by column (deterministic layout, duplicate detection)
+    std::vector<int32_t> idx;
+    std::vector<int32_t> ctmp;
+    std::vector<double> wtmp;
+    p->diag.assign(n, 0.0);
+    double c_l1 = 0.0;
+    int64_t max_row = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t b0 = p->row_ptr[i], b1 = p->row_ptr[i + 1];
+        int64_t len = b1 - b0;
+        max_row = std::max(max_row, len);
+        idx.resize(len);
+        std::iota(idx.begin(), idx.end(), 0);
+        std::sort(idx.begin(), idx.end(), [&](int32_t x, int32_t y) { return p->col[b0 + x] < p->col[b0 + y]; });
+        ctmp.resize(len);
+        wtmp.resize(len);
+        for (int64_t k = 0; k < len; ++k) {
+            ctmp[k] = p->col[b0 + idx[k]];
+            wtmp[k] = wv[b0 + idx[k]];
+        }
+        double wsum = 0.0;
+        for (int64_t k = 0; k < len; ++k) {
+            if (k > 0 && ctmp[k] == ctmp[k - 1]) {
+                int32_t c = ctmp[k];
+                delete p;
+                return set_error(LRSDP_EINVAL, "edge (%lld, %d) appears more than once", (long long)i, c);
+            }
+            p->col[b0 + k] = ctmp[k];
+            wv[b0 + k] = wtmp[k];
+            wsum += wtmp[k];
+            c_l1 += std::fabs(wtmp[k]) * 0.25;
+        }
+        p->diag[i] = -0.25 * wsum;
+        c_l1 += std::fabs(p->diag[i]);
+    }
+    if (mode == kWSign) {
+        for (int64_t k = 0; k < nnz; ++k)
+            if (wv[k] < 0) p->col[k] = (int32_t)((uint32_t)p->col[k] | 0x80000000u);
+    } else if (mode == kWGeneral) {
+        p->val.resize(nnz);
+        for (int64_t k = 0; k < nnz; ++k) p->val[k] = 0.25 * wv[k];
+    }
+    build_work_lists(p, n);
+    auto &I = p->info;
+    I.kind = LRSDP_MAXCUT;
+    I.n = n;
+    I.m = n;
+    I.nnz = nnz;
+    I.weights = mode;
+    I.max_row_nnz = max_row;
+    I.c_l1 = c_l1;
+    I.b_l1 = (double)n;
+    I.b_inf = 1.0;
+    *out = p;
+    return LRSDP_OK;
+}
+
+extern "C" int lrsdp_problem_completion(int64_t n1, int64_t n2, int64_t m, const int32_t *i,
+                                        const int32_t *j, const double *Mij,
+                                        lrsdp_problem **out) {
+    clear_error();
+    if (!out) return set_error(LRSDP_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n1 < 1 || n2 < 1 || n1 + n2 > INT32_MAX - 1) return set_error(LRSDP_EINVAL, "bad block sizes");
+    if (m < 0 || m > (int64_t)INT32_MAX) return set_error(LRSDP_EINVAL, "bad sample count");
+    if (m > 0 && (!i || !j || !Mij)) return set_error(LRSDP_EINVAL, "sample arrays are NULL");
+    for (int64_t k = 0; k < m; ++k) {
+        if (i[k] < 0 || i[k] >= n1 || j[k] < 0 || j[k] >= n2)
+            return set_error(LRSDP_EINVAL, "sample %lld = (%d, %d) out of range", (long long)k, i[k], j[k]);
+        if (!std::isfinite(Mij[k])) return set_error(LRSDP_EINVAL, "value %lld is not finite", (long long)k);
+    }
+    auto *p = new lrsdp_problem();
+    p->samp_i.assign(i, i + m);
+    p->samp_j.assign(j, j + m);
+    p->b.resize(m);
+    double b_l1 = 0.0, b_inf = 0.0;
+    for (int64_t k = 0; k < m; ++k) {
+        p->b[k] = 2.0 * Mij[k];
+        b_l1 += std::fabs(p->b[k]);
+        b_inf = std::max(b_inf, std::fabs(p->b[k]));
+    }
+    // top CSR: rows i, entries sorted by j, holding (j, k)
+    std::vector<int32_t> ord(m);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) {
+        return i[a] != i[b] ? i[a] < i[b] : j[a] < j[b];
+    });
+    for (int64_t t = 1; t < m; ++t)
+        if (i[ord[t]] == i[ord[t - 1]] && j[ord[t]] == j[ord[t - 1]]) {
+            delete p;
+            return set_error(LRSDP_EINVAL, "sample (%d, %d) appears more than once", i[ord[t]], j[ord[t]]);
+        }
+    p->top_ptr.assign(n1 + 1, 0);
+    for (int64_t k = 0; k < m; ++k) p->top_ptr[i[k] + 1]++;
+    for (int64_t r = 0; r < n1; ++r) p->top_ptr[r + 1] += p->top_ptr[r];
+    p->top_col.resize(m);
+    p->top_eid.resize(m);
+    for (int64_t t = 0; t < m; ++t) {
+        p->top_col[t] = j[ord[t]];
+        p->top_eid[t] = ord[t];
+    }
+    // bottom CSR: rows j, entries sorted by i, holding (i, k)
+    std::sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) {
+        return j[a] != j[b] ? j[a] < j[b] : i[a] < i[b];
+    });
+    p->bot_ptr.assign(n2 + 1, 0);
+    for (int64_t k = 0; k < m; ++k) p->bot_ptr[j[k] + 1]++;
+    for (int64_t r = 0; r < n2; ++r) p->bot_ptr[r + 1] += p->bot_ptr[r];
+    p->bot_row.resize(m);
+    p->bot_eid.resize(m);
+    for (int64_t t = 0; t < m; ++t) {
+        p->bot_row[t] = i[ord[t]];
+        p->bot_eid[t] = ord[t];
+    }
+    int64_t max_row = 0;
+    for (int64_t r = 0; r < n1; ++r) max_row = std::max<int64_t>(max_row, p->top_ptr[r + 1] - p->top_ptr[r]);
+    for (int64_t r = 0; r < n2; ++r) max_row = std::max<int64_t>(max_row, p->bot_ptr[r + 1] - p->bot_ptr[r]);
+    auto &I = p->info;
+    I.kind = LRSDP_COMPLETION;
+    I.n = n1 + n2;
+    I.m = m;
+    I.nnz = 2 * m;
+    I.n1 = n1;
+    I.n2 = n2;
+    I.weights = 0;
+    I.max_row_nnz = max_row;
+    I.c_l1 = (double)(n1 + n2);
+    I.b_l1 = b_l1;
+    I.b_inf = b_inf;
+    *out = p;
+    return LRSDP_OK;
+}
+
+extern "C" void lrsdp_problem_destroy(lrsdp_problem *prob) { delete prob; }
+
+extern "C" int lrsdp_problem_get_info(const lrsdp_problem *prob, lrsdp_problem_info *out) {
+    clear_error();
+    if (!prob || !out) return set_error(LRSDP_EINVAL, "NULL argument");
+    *out = prob->info;
+    return LRSDP_OK;
+}
+
+namespace {
+
+struct Layout {
+    size_t off = 0;
+    size_t take(size_t bytes) {
+        size_t o = (off + 255) & ~size_t(255);
+        off = o + bytes;
+        return o;
+    }
+};
+
+// Fills offsets for every device array of the problem; returns total bytes.
+size_t plan_device(const lrsdp_problem *p, size_t *offs) {
+    Layout L;
+    int k = 0;
+    auto add = [&](size_t bytes) { offs[k++] = L.take(bytes); };
+    if (p->info.kind == LRSDP_MAXCUT) {
+        add(p->row_ptr.size() * 4);
+        add(p->col.size() * 4);
+        add(p->val.size() * 8);
+        add(p->diag.size() * 8);
+        add(p->light.size() * 4);
+        add(p->seg.size() * sizeof(int4));
+        add(p->heavy.size() * 4);
+        add(p->heavy_seg.size() * 4);
+        add(p->seg.size() * 256);      // segment partial sums (<= 256 B per row)
+    } else {
+        add(p->top_ptr.size() * 4);
+        add(p->top_col.size() * 4);
+        add(p->top_eid.size() * 4);
+        add(p->bot_ptr.size() * 4);
+        add(p->bot_row.size() * 4);
+        add(p->bot_eid.size() * 4);
+        add(p->samp_i.size() * 4);
+        add(p->samp_j.size() * 4);
+        add(p->b.size() * 8);
+    }
+    return L.off + 256;
+}
+
+}  // namespace
+
+extern "C" int lrsdp_problem_device_bytes(const lrsdp_problem *prob, size_t *bytes) {
+    clear_error();
+    if (!prob || !bytes) return set_error(LRSDP_EINVAL, "NULL argument");
+    size_t offs[16];
+    *bytes = plan_device(prob, offs);
+    return LRSDP_OK;
+}
+
+extern "C" int lrsdp_problem_upload(lrsdp_ctx *ctx, lrsdp_problem *p, void *dev, size_t bytes) {
+    clear_error();
+    if (!ctx || !p || !dev) return set_error(LRSDP_EINVAL, "NULL argument");
+    size_t offs[16];
+    size_t need = plan_device(p, offs);
+    if (bytes < need)
+        return set_error(LRSDP_ENOMEM, "problem needs %zu device bytes, %zu given", need, bytes);
+    LRSDP_HIP_TRY(hipSetDevice(ctx->device));
+    char *base = static_cast<char *>(dev);
+    auto put = [&](size_t off, const void *src, size_t n) -> hipError_t {
+        if (n == 0) return hipSuccess;
+        return hipMemcpyAsync(base + off, src, n, hipMemcpyHostToDevice, ctx->stream);
+    };
+    if (p->info.kind == LRSDP_MAXCUT) {
+        LRSDP_HIP_TRY(put(offs[0], p->row_ptr.data(), p->row_ptr.size() * 4));
+        LRSDP_HIP_TRY(put(offs[1], p->col.data(), p->col.size() * 4));
+        LRSDP_HIP_TRY(put(offs[2], p->val.data(), p->val.size() * 8));
+        LRSDP_HIP_TRY(put(offs[3], p->diag.data(), p->diag.size() * 8));
+        LRSDP_HIP_TRY(put(offs[4], p->light.data(), p->light.size() * 4));
+        LRSDP_HIP_TRY(put(offs[5], p->seg.data(), p->seg.size() * sizeof(int4)));
+        LRSDP_HIP_TRY(put(offs[6], p->heavy.data(), p->heavy.size() * 4));
+        LRSDP_HIP_TRY(put(offs[7], p->heavy_seg.data(), p->heavy_seg.size() * 4));
+        DevCsr &c = p->csr;
+        c.row_ptr = (const int32_t *)(base + offs[0]);
+        c.col = (const int32_t *)(base + offs[1]);
+        c.val = p->val.empty() ? nullptr : (const double *)(base + offs[2]);
+        c.diag = (const double *)(base + offs[3]);
+        c.light = (const int32_t *)(base + offs[4]);
+        c.seg = (const int4 *)(base + offs[5]);
+        c.heavy = (const int32_t *)(base + offs[6]);
+        c.heavy_seg = (const int32_t *)(base + offs[7]);
+        c.seg_buf = base + offs[8];
+        c.n = p->info.n;
+        c.nnz = p->info.nnz;
+        c.n_light = (int64_t)p->light.size();
+        c.n_seg = (int64_t)p->seg.size();
+        c.n_heavy = (int64_t)p->heavy.size();
+        c.wmode = p->info.weights;
+    } else {
+        LRSDP_HIP_TRY(put(offs[0], p->top_ptr.data(), p->top_ptr.size() * 4));
+        LRSDP_HIP_TRY(put(offs[1], p->top_col.data(), p->top_col.size() * 4));
+        LRSDP_HIP_TRY(put(offs[2], p->top_eid.data(), p->top_eid.size() * 4));
+        LRSDP_HIP_TRY(put(offs[3], p->bot_ptr.data(), p->bot_ptr.size() * 4));
+        LRSDP_HIP_TRY(put(offs[4], p->bot_row.data(), p->bot_row.size() * 4));
+        LRSDP_HIP_TRY(put(offs[5], p->bot_eid.data(), p->bot_eid.size() * 4));
+        LRSDP_HIP_TRY(put(offs[6], p->samp_i.data(), p->samp_i.size() * 4));
+        LRSDP_HIP_TRY(put(offs[7], p->samp_j.data(), p->samp_j.size() * 4));
+        LRSDP_HIP_TRY(put(offs[8], p->b.data(), p->b.size() * 8));
+        DevCompletion &c = p->cmp;
+        c.top_ptr = (const int32_t *)(base + offs[0]);
+        c.top_col = (const int32_t *)(base + offs[1]);
+        c.top_eid = (const int32_t *)(base + offs[2]);
+        c.bot_ptr = (const int32_t *)(base + offs[3]);
+        c.bot_row = (const int32_t *)(base + offs[4]);
+        c.bot_eid = (const int32_t *)(base + offs[5]);
+        c.samp_i = (const int32_t *)(base + offs[6]);
+        c.samp_j = (const int32_t *)(base + offs[7]);
+        c.b = (const double *)(base + offs[8]);
+        c.n1 = p->info.n1;
+        c.n2 = p->info.n2;
+        c.m = p->info.m;
+    }
+    LRSDP_HIP_TRY(hipStreamSynchronize(ctx->stream));
+    p->dev = dev;
+    p->dev_bytes = bytes;
+    p->uploaded = true;
+    return LRSDP_OK;
+}

@@ -1,0 +1,574 @@
+// C ABI: context, options, device-resident solve driver, kernel entry points.
+//
+// The solve (Section 2.1 ALM, Algorithm 1 L-BFGS, appendix A.2 exact line
+// search) runs entirely on the device.  Per L-BFGS iteration the host enqueues
+//   spmm(LS)  -> ls_finalize -> update -> lbfgs_finalize -> combine
+// and reads the 3 KB state block back every `check_every` iterations.  Each
+// kernel returns at once when the state says the subproblem is finished, so
+// the iterations enqueued past convergence cost only their launches.
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+
+#include "kernels.h"
+
+namespace lrsdp {
+
+int launch_ls_finalize(hipStream_t, SolverState *, const double *, int, const double *, int);
+int launch_lbfgs_finalize(hipStream_t, SolverState *, const double *, int);
+int launch_init_finalize(hipStream_t, SolverState *, const double *, int, int);
+int launch_alm_finalize(hipStream_t, SolverState *, const double *, int, int);
+int launch_reduce(hipStream_t, const double *, int, int, double *);
+int launch_cubic(hipStream_t, const double *, double *);
+int launch_update_maxcut(hipStream_t, int, SolverState *, void *, const void *, const double *, double *,
+                         void *const *, void *const *, int, int64_t, int64_t, double *, int *);
+int launch_combine(hipStream_t, int, SolverState *, const double *, const void *const *, int, void *, int64_t,
+                   int64_t, double *, int *);
+int launch_grad_init_maxcut(hipStream_t, int, SolverState *, const void *, const void *, const double *,
+                            const double *, double *, void *, int64_t, int64_t, double *, int *);
+int launch_fill(hipStream_t, int, void *, int64_t);
+int launch_dots(hipStream_t, int, const void *, const void *const *, int, int64_t, int64_t, double *, int *);
+int launch_rowdot(hipStream_t, int, const void *, const void *, int64_t, int64_t, double *);
+int launch_ytil(hipStream_t, const double *, const double *, const double *, double, int64_t, double *);
+int launch_ls_out(hipStream_t, const double *, double, double *);
+int launch_alm_out(hipStream_t, const double *, double, double, double *);
+int launch_two_loop_pairs(hipStream_t, const double *, int, double *, int *);
+int launch_gather_gram(hipStream_t, const double *, int, int, double *);
+
+namespace {
+
+// ctx scratch layout (bytes)
+constexpr size_t kStateOff = 0;
+constexpr size_t kPartRows = 2 * kMaxBlocks;                 // rows per partials set
+constexpr size_t kPartBytes = kPartRows * kMaxSums * sizeof(double);
+constexpr size_t kPartLsOff = 8192;
+constexpr size_t kPartCbOff = kPartLsOff + kPartBytes;
+constexpr size_t kPartUpOff = kPartCbOff + kPartBytes;
+constexpr size_t kPartMiscOff = kPartUpOff + kPartBytes;
+constexpr size_t kSmallOff = kPartMiscOff + kPartBytes;      // 4096 doubles of small buffers
+constexpr size_t kScratchBytes = kSmallOff + 4096 * sizeof(double);
+
+template <typename T>
+T *at(void *base, size_t off) {
+    return reinterpret_cast<T *>(static_cast<char *>(base) + off);
+}
+
+int elem_size(int prec) { return prec == LRSDP_F64 ? 8 : 4; }
+
+int check_prec(int prec) {
+    if (prec != LRSDP_F64 && prec != LRSDP_F32 && prec != LRSDP_F32_BF16IN)
+        return set_error(LRSDP_EINVAL, "unknown precision %d", prec);
+    return LRSDP_OK;
+}
+
+int check_ld(int prec, int64_t ld) {
+    const int64_t rb = ld * elem_size(prec);
+    if (ld <= 0 || rb % 16 != 0 || rb > 256)
+        return set_error(LRSDP_EINVAL, "ld = %lld: ld * element size must be a positive multiple of 16, at most 256",
+                         (long long)ld);
+    return LRSDP_OK;
+}
+
+int check_problem(const lrsdp_problem *p) {
+    if (!p) return set_error(LRSDP_EINVAL, "problem is NULL");
+    if (!p->uploaded) return set_error(LRSDP_EINVAL, "problem has not been uploaded");
+    return LRSDP_OK;
+}
+
+// Algorithmic bytes of one MaxCut line-search SpMM launch (each array once):
+// work list + row pointers + column indices (+ values) + gathered D + own rows
+// of R and D read once + C D written + ytil + diagonal.
+double maxcut_spmm_bytes(const lrsdp_problem *p, int prec, int r) {
+    const double n = (double)p->info.n, nnz = (double)p->info.nnz, w = elem_size(prec);
+    double b = 4.0 * n + 4.0 * (n + 1) + 4.0 * nnz + 16.0 * n + 3.0 * n * r * w;
+    if (p->info.weights == kWGeneral) b += 8.0 * nnz;
+    return b;
+}
+
+}  // namespace
+}  // namespace lrsdp
+
+using namespace lrsdp;
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+extern "C" int lrsdp_ctx_create(int device, void *hip_stream, lrsdp_ctx **out) {
+    clear_error();
+    if (!out) return set_error(LRSDP_EINVAL, "out is NULL");
+    *out = nullptr;
+    int count = 0;
+    LRSDP_HIP_TRY(hipGetDeviceCount(&count));
+    if (device < 0 || device >= count) return set_error(LRSDP_EINVAL, "device %d not in [0, %d)", device, count);
+    LRSDP_HIP_TRY(hipSetDevice(device));
+    auto *c = new lrsdp_ctx();
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    c->scratch_bytes = kScratchBytes;
+    c->pinned_bytes = 8192;
+    hipError_t e = hipMalloc(&c->scratch, c->scratch_bytes);
+    if (e == hipSuccess) e = hipHostMalloc(&c->pinned, c->pinned_bytes, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreate(&c->ev0);
+    if (e == hipSuccess) e = hipEventCreate(&c->ev1);
+    if (e == hipSuccess) e = hipMemsetAsync(c->scratch, 0, c->scratch_bytes, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        lrsdp_ctx_destroy(c);
+        return set_error(LRSDP_EHIP, "context setup failed: %s", hipGetErrorString(e));
+    }
+    *out = c;
+    return LRSDP_OK;
+}
+
+extern "C" void lrsdp_ctx_destroy(lrsdp_ctx *c) {
+    if (!c) return;
+    hipSetDevice(c->device);
+    if (c->stream) hipStreamSynchronize(c->stream);
+    else hipDeviceSynchronize();
+    if (c->ev0) hipEventDestroy(c->ev0);
+    if (c->ev1) hipEventDestroy(c->ev1);
+    if (c->scratch) hipFree(c->scratch);
+    if (c->pinned) hipHostFree(c->pinned);
+    delete c;
+}
+
+// ---------------------------------------------------------------------------
+// options / workspace
+// ---------------------------------------------------------------------------
+extern "C" void lrsdp_options_default(lrsdp_options *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->prec = LRSDP_F64;
+    o->rank = 0;
+    o->ld = 0;
+    o->lbfgs_mem = 4;
+    o->tol = 1e-5;
+    o->max_outer = 300;
+    o->max_inner = 2000;
+    o->max_iter_total = 200000;
+    o->time_limit_s = 1e30;
+    o->sigma0 = 0.0;
+    o->sigma_factor = 2.0;
+    o->sigma_max_ratio = 1e8;
+    o->feas_decrease = 0.25;
+    o->eta0 = 1e-1;
+    o->eta_factor = 0.25;
+    o->eta_min = 1e-9;
+    o->check_every = 8;
+    o->refresh_every = 0;
+    o->profile = 0;
+    o->verbose = 0;
+}
+
+namespace {
+
+struct WsPlan {
+    size_t cd, gring[kMaxMem + 1], dring[kMaxMem], ytil, rn, total;
+};
+
+int plan_workspace(const lrsdp_problem *p, const lrsdp_options *o, WsPlan *w) {
+    if (!p || !o) return set_error(LRSDP_EINVAL, "NULL argument");
+    int rc = check_prec(o->prec);
+    if (rc) return rc;
+    if (o->lbfgs_mem < 1 || o->lbfgs_mem > kMaxMem)
+        return set_error(LRSDP_EINVAL, "lbfgs_mem = %d not in [1, %d]", o->lbfgs_mem, kMaxMem);
+    if (o->rank < 1 || o->ld < o->rank) return set_error(LRSDP_EINVAL, "need 1 <= rank <= ld");
+    rc = check_ld(o->prec, o->ld);
+    if (rc) return rc;
+    const size_t arr = (size_t)p->info.n * o->ld * elem_size(o->prec);
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        size_t r = (off + 255) & ~size_t(255);
+        off = r + b;
+        return r;
+    };
+    w->cd = take(arr);
+    for (int g = 0; g <= o->lbfgs_mem; ++g) w->gring[g] = take(arr);
+    for (int d = 0; d < o->lbfgs_mem; ++d) w->dring[d] = take(arr);
+    w->ytil = take((size_t)p->info.m * 8);
+    w->rn = take((size_t)p->info.n * 8);
+    w->total = off + 256;
+    return LRSDP_OK;
+}
+
+}  // namespace
+
+extern "C" int lrsdp_workspace_bytes(const lrsdp_problem *p, const lrsdp_options *o, size_t *bytes) {
+    clear_error();
+    if (!bytes) return set_error(LRSDP_EINVAL, "bytes is NULL");
+    WsPlan w;
+    int rc = plan_workspace(p, o, &w);
+    if (rc) return rc;
+    *bytes = w.total;
+    return LRSDP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// solve
+// ---------------------------------------------------------------------------
+namespace {
+
+int read_state(lrsdp_ctx *c, SolverState *h) {
+    SolverState *d = at<SolverState>(c->scratch, kStateOff);
+    LRSDP_HIP_TRY(hipMemcpyAsync(c->pinned, d, sizeof(SolverState), hipMemcpyDeviceToHost, c->stream));
+    LRSDP_HIP_TRY(hipStreamSynchronize(c->stream));
+    std::memcpy(h, c->pinned, sizeof(SolverState));
+    return LRSDP_OK;
+}
+
+int write_state(lrsdp_ctx *c, const SolverState &h) {
+    SolverState *d = at<SolverState>(c->scratch, kStateOff);
+    std::memcpy(c->pinned, &h, sizeof(SolverState));
+    LRSDP_HIP_TRY(hipMemcpyAsync(d, c->pinned, sizeof(SolverState), hipMemcpyHostToDevice, c->stream));
+    LRSDP_HIP_TRY(hipStreamSynchronize(c->stream));
+    return LRSDP_OK;
+}
+
+int solve_maxcut(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws, void *R, double *y,
+                 lrsdp_result *res) {
+    const auto t0 = std::chrono::steady_clock::now();
+    auto elapsed = [&]() { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); };
+    const int prec = o->prec == LRSDP_F64 ? LRSDP_F64 : LRSDP_F32;
+    const int T = o->lbfgs_mem;
+    const int64_t n = p->info.n, ld = o->ld;
+    hipStream_t s = c->stream;
+    WsPlan w;
+    int rc = plan_workspace(p, o, &w);
+    if (rc) return rc;
+    void *CD = ws + w.cd;
+    void *gring[kMaxMem + 1] = {};
+    void *dring[kMaxMem] = {};
+    for (int g = 0; g <= T; ++g) gring[g] = ws + w.gring[g];
+    for (int d = 0; d < T; ++d) dring[d] = ws + w.dring[d];
+    double *ytil = reinterpret_cast<double *>(ws + w.ytil);
+    double *rn = reinterpret_cast<double *>(ws + w.rn);
+    SolverState *st = at<SolverState>(c->scratch, kStateOff);
+    double *part_ls = at<double>(c->scratch, kPartLsOff);
+    double *part_cb = at<double>(c->scratch, kPartCbOff);
+    double *part_up = at<double>(c->scratch, kPartUpOff);
+    double *part_misc = at<double>(c->scratch, kPartMiscOff);
+    const void *basis[kMaxBasis];
+    for (int g = 0; g <= T; ++g) basis[g] = gring[g];
+    for (int d = 0; d < T; ++d) basis[T + 1 + d] = dring[d];
+
+    const double sigma0 = o->sigma0 > 0 ? o->sigma0 : std::max(p->info.c_l1 / (double)p->info.m, 1e-8);
+    SolverState h{};
+    h.sigma = sigma0;
+    h.sigma_cap = sigma0 * o->sigma_max_ratio;
+    h.eta = o->eta0;
+    h.err1_prev = INFINITY;
+    h.tol = o->tol;
+    h.sigma_factor = o->sigma_factor;
+    h.feas_decrease = o->feas_decrease;
+    h.eta_factor = o->eta_factor;
+    h.eta_min = o->eta_min;
+    h.b_l1 = p->info.b_l1;
+    h.b_inf = p->info.b_inf;
+    h.max_inner = o->max_inner;
+    h.T = T;
+    rc = write_state(c, h);
+    if (rc) return rc;
+    // zero the rings so stale slots hold finite values
+    for (int g = 0; g <= T; ++g)
+        if ((rc = launch_fill(s, prec, gring[g], n * ld))) return rc;
+    for (int d = 0; d < T; ++d)
+        if ((rc = launch_fill(s, prec, dring[d], n * ld))) return rc;
+
+    // profiling events
+    const int B = std::max(1, o->check_every);
+    std::vector<hipEvent_t> evs;
+    if (o->profile) {
+        evs.resize(2 * B);
+        for (auto &e : evs) LRSDP_HIP_TRY(hipEventCreate(&e));
+    }
+    auto free_events = [&]() {
+        for (auto &e : evs) hipEventDestroy(e);
+        evs.clear();
+    };
+    double spmm_ms = 0.0;
+    int spmm_n = 0;
+
+    // initial measures: C R, ||R_i||^2, no multiplier step
+    SpmmArgs ref;
+    ref.epi = kEpiRefresh;
+    ref.V = R;
+    ref.Y = CD;
+    ref.y = y;
+    ref.rn = rn;
+    ref.sigma = 0.0;
+    ref.ld = ld;
+    ref.partials = part_misc;
+    int np = 0;
+    if ((rc = spmm_maxcut(s, p->csr, prec, ref, &np))) return rc;
+    if ((rc = launch_alm_finalize(s, st, part_misc, np, 0))) return rc;
+
+    int status = LRSDP_NOT_CONVERGED;
+    int64_t outer = 0;
+    int64_t total_inner = 0;
+    double sigma_host = sigma0;
+    for (outer = 1; outer <= o->max_outer; ++outer) {
+        // subproblem start: ytil, G_0, D_0 = -G_0
+        int nb = 0, ncb = 0;
+        if ((rc = launch_grad_init_maxcut(s, prec, st, R, CD, y, rn, ytil, gring[0], n, ld, part_misc, &nb))) break;
+        int64_t left = o->max_iter_total - total_inner;
+        int k_limit = (int)std::min<int64_t>(o->max_inner, std::max<int64_t>(left, 0));
+        if ((rc = launch_init_finalize(s, st, part_misc, nb, k_limit))) break;
+        if ((rc = launch_combine(s, prec, st, nullptr, basis, 2 * T + 1, nullptr, n, ld, part_cb, &ncb))) break;
+        // L-BFGS iterations in batches of B
+        int64_t it = 0;
+        SolverState hs{};
+        for (;;) {
+            for (int b = 0; b < B; ++b, ++it) {
+                SpmmArgs ls;
+                ls.epi = kEpiLS;
+                ls.V = dring[it % T];
+                ls.Y = CD;
+                ls.R = R;
+                ls.ytil = ytil;
+                ls.ld = ld;
+                ls.partials = part_ls;
+                ls.st = st;
+                int nls = 0;
+                if (o->profile) LRSDP_HIP_TRY(hipEventRecord(evs[2 * b], s));
+                if ((rc = spmm_maxcut(s, p->csr, prec, ls, &nls))) break;
+                if (o->profile) LRSDP_HIP_TRY(hipEventRecord(evs[2 * b + 1], s));
+                if ((rc = launch_ls_finalize(s, st, part_ls, nls, part_cb, ncb))) break;
+                int nup = 0;
+                if ((rc = launch_update_maxcut(s, prec, st, R, CD, y, ytil, gring, dring, T, n, ld, part_up, &nup)))
+                    break;
+                if ((rc = launch_lbfgs_finalize(s, st, part_up, nup))) break;
+                if ((rc = launch_combine(s, prec, st, nullptr, basis, 2 * T + 1, nullptr, n, ld, part_cb, &ncb)))
+                    break;
+            }
+            if (rc) break;
+            int64_t k_before = hs.k;
+            if ((rc = read_state(c, &hs))) break;
+            if (o->profile) {
+                int ran = (int)std::min<int64_t>(B, std::max<int64_t>(0, hs.k - k_before));
+                for (int b = 0; b < ran; ++b) {
+                    float ms = 0.f;
+                    LRSDP_HIP_TRY(hipEventElapsedTime(&ms, evs[2 * b], evs[2 * b + 1]));
+                    spmm_ms += ms;
+                    spmm_n += 1;
+                }
+            }
+            if (hs.done || hs.numeric) break;
+            if (elapsed() > o->time_limit_s) break;
+            if (it > (int64_t)k_limit + 2 * B) {
+                rc = set_error(LRSDP_EHIP, "device state did not advance (iteration %lld)", (long long)it);
+                break;
+            }
+        }
+        if (rc) break;
+        total_inner = hs.inner_total;
+        if (hs.numeric) {
+            rc = set_error(LRSDP_ENUMERIC, "NaN/Inf in the L-BFGS iteration (outer %lld)", (long long)outer);
+            break;
+        }
+        // ALM step: y <- y + sigma (b - A(RR^T)), exact C R, measures
+        ref.sigma = sigma_host;
+        if ((rc = spmm_maxcut(s, p->csr, prec, ref, &np))) break;
+        if ((rc = launch_alm_finalize(s, st, part_misc, np, 1))) break;
+        if ((rc = read_state(c, &hs))) break;
+        if (o->verbose)
+            fprintf(stderr, "[lrsdp] outer %3lld inner %6lld sigma %.3e obj % .10e err1 %.3e err3 % .3e gnorm %.3e t %.3fs\n",
+                    (long long)outer, (long long)hs.inner_total, sigma_host, hs.obj, hs.err1, hs.err3, hs.gnorm,
+                    elapsed());
+        sigma_host = hs.sigma;
+        if (hs.numeric) {
+            rc = set_error(LRSDP_ENUMERIC, "NaN/Inf in the ALM measures (outer %lld)", (long long)outer);
+            break;
+        }
+        if (hs.converged) {
+            status = LRSDP_OK;
+            break;
+        }
+        if (hs.inner_total >= o->max_iter_total || elapsed() > o->time_limit_s) break;
+    }
+    free_events();
+    if (rc < 0) return rc;
+    SolverState hs{};
+    if ((rc = read_state(c, &hs))) return rc;
+    std::memset(res, 0, sizeof(*res));
+    res->obj = hs.obj;
+    res->dual = hs.dual;
+    res->err1 = hs.err1;
+    res->err1_inf = hs.err1_inf;
+    res->err3 = hs.err3;
+    res->sigma = hs.sigma;
+    res->seconds = elapsed();
+    res->outer = std::min<int64_t>(outer, o->max_outer);
+    res->inner = hs.inner_total;
+    res->status = status;
+    res->spmm_launches = spmm_n;
+    res->spmm_ms = spmm_ms;
+    res->spmm_bytes = maxcut_spmm_bytes(p, prec, o->rank);
+    return status;
+}
+
+}  // namespace
+
+extern "C" int lrsdp_solve(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, void *ws, size_t ws_bytes,
+                           void *R, double *y, lrsdp_result *res) {
+    clear_error();
+    if (!c || !o || !ws || !R || !y || !res) return set_error(LRSDP_EINVAL, "NULL argument");
+    int rc = check_problem(p);
+    if (rc) return rc;
+    WsPlan w;
+    if ((rc = plan_workspace(p, o, &w))) return rc;
+    if (ws_bytes < w.total) return set_error(LRSDP_ENOMEM, "workspace needs %zu bytes, %zu given", w.total, ws_bytes);
+    LRSDP_HIP_TRY(hipSetDevice(c->device));
+    if (p->info.kind == LRSDP_MAXCUT) return solve_maxcut(c, p, o, static_cast<char *>(ws), R, y, res);
+    return set_error(LRSDP_EUNSUPPORTED, "completion solve not available in this build");
+}
+
+// ---------------------------------------------------------------------------
+// kernel entry points
+// ---------------------------------------------------------------------------
+extern "C" int lrsdp_k_spmm(lrsdp_ctx *c, const lrsdp_problem *p, int prec, const void *V, int64_t ld,
+                            const double *ytil, void *Y) {
+    clear_error();
+    if (!c || !V || !Y) return set_error(LRSDP_EINVAL, "NULL argument");
+    int rc;
+    if ((rc = check_problem(p)) || (rc = check_prec(prec)) || (rc = check_ld(prec, ld))) return rc;
+    if (V == Y) return set_error(LRSDP_EINVAL, "Y must not alias V");
+    const int pr = prec == LRSDP_F64 ? LRSDP_F64 : LRSDP_F32;
+    if (p->info.kind == LRSDP_MAXCUT) {
+        SpmmArgs a;
+        a.epi = kEpiPlain;
+        a.V = V;
+        a.Y = Y;
+        a.ytil = ytil;
+        a.ld = ld;
+        int np = 0;
+        return spmm_maxcut(c->stream, p->csr, pr, a, &np);
+    }
+    return spmm_completion(c->stream, p->cmp, pr, V, ld, ytil, Y);
+}
+
+extern "C" int lrsdp_k_constraint(lrsdp_ctx *c, const lrsdp_problem *p, int prec, const void *U, const void *V,
+                                  int64_t ld, double *out) {
+    clear_error();
+    if (!c || !U || !out) return set_error(LRSDP_EINVAL, "NULL argument");
+    int rc;
+    if ((rc = check_problem(p)) || (rc = check_prec(prec)) || (rc = check_ld(prec, ld))) return rc;
+    const int pr = prec == LRSDP_F64 ? LRSDP_F64 : LRSDP_F32;
+    if (!V) V = U;
+    if (p->info.kind == LRSDP_MAXCUT) return launch_rowdot(c->stream, pr, U, V, p->info.n, ld, out);
+    return set_error(LRSDP_EUNSUPPORTED, "completion constraint map not available in this build");
+}
+
+extern "C" int lrsdp_k_ls_coeffs(lrsdp_ctx *c, const lrsdp_problem *p, int prec, const void *R, const void *D,
+                                 int64_t ld, const double *y, double sigma, void *work, double *out, double *q1,
+                                 double *q2) {
+    clear_error();
+    if (!c || !R || !D || !y || !work || !out) return set_error(LRSDP_EINVAL, "NULL argument");
+    int rc;
+    if ((rc = check_problem(p)) || (rc = check_prec(prec)) || (rc = check_ld(prec, ld))) return rc;
+    if (p->info.kind != LRSDP_MAXCUT)
+        return set_error(LRSDP_EUNSUPPORTED, "completion line search not available in this build");
+    const int pr = prec == LRSDP_F64 ? LRSDP_F64 : LRSDP_F32;
+    const int64_t n = p->info.n;
+    const size_t arr = (size_t)n * ld * elem_size(pr);
+    char *wk = static_cast<char *>(work);
+    void *CR = wk, *CDv = wk + arr;
+    double *ytil = reinterpret_cast<double *>(wk + 2 * arr);
+    double *part = at<double>(c->scratch, kPartLsOff);
+    double *sums = at<double>(c->scratch, kSmallOff);
+    hipStream_t s = c->stream;
+    // ytil = y + sigma (1 - ||R_i||^2)
+    if ((rc = launch_rowdot(s, pr, R, R, n, ld, ytil))) return rc;
+    if ((rc = launch_ytil(s, y, ytil, nullptr, sigma, n, ytil))) return rc;
+    SpmmArgs a;
+    a.epi = kEpiPlain;
+    a.V = R;
+    a.Y = CR;
+    a.ld = ld;
+    int np = 0;
+    if ((rc = spmm_maxcut(s, p->csr, pr, a, &np))) return rc;
+    SpmmArgs b;
+    b.epi = kEpiLS;
+    b.V = D;
+    b.Y = CDv;
+    b.R = R;
+    b.aux = CR;
+    b.ytil = ytil;
+    b.q1 = q1;
+    b.q2 = q2;
+    b.ld = ld;
+    b.partials = part;
+    if ((rc = spmm_maxcut(s, p->csr, pr, b, &np))) return rc;
+    if ((rc = launch_reduce(s, part, np, kLsSums, sums))) return rc;
+    return launch_ls_out(s, sums, sigma, out);
+}
+
+extern "C" int lrsdp_k_cubic(lrsdp_ctx *c, const double *a, double *tau) {
+    clear_error();
+    if (!c || !a || !tau) return set_error(LRSDP_EINVAL, "NULL argument");
+    return launch_cubic(c->stream, a, tau);
+}
+
+extern "C" int lrsdp_k_alm(lrsdp_ctx *c, const lrsdp_problem *p, int prec, const void *R, int64_t ld, double *y,
+                           double sigma, void *work, double *out) {
+    clear_error();
+    if (!c || !R || !y || !work || !out) return set_error(LRSDP_EINVAL, "NULL argument");
+    int rc;
+    if ((rc = check_problem(p)) || (rc = check_prec(prec)) || (rc = check_ld(prec, ld))) return rc;
+    if (p->info.kind != LRSDP_MAXCUT)
+        return set_error(LRSDP_EUNSUPPORTED, "completion ALM step not available in this build");
+    const int pr = prec == LRSDP_F64 ? LRSDP_F64 : LRSDP_F32;
+    double *part = at<double>(c->scratch, kPartMiscOff);
+    double *sums = at<double>(c->scratch, kSmallOff);
+    SpmmArgs a;
+    a.epi = kEpiRefresh;
+    a.V = R;
+    a.Y = work;
+    a.y = y;
+    a.sigma = sigma;
+    a.ld = ld;
+    a.partials = part;
+    int np = 0;
+    if ((rc = spmm_maxcut(c->stream, p->csr, pr, a, &np))) return rc;
+    if ((rc = launch_reduce(c->stream, part, np, 3, sums))) return rc;
+    return launch_alm_out(c->stream, sums, p->info.b_l1, p->info.b_inf, out);
+}
+
+extern "C" int lrsdp_k_lbfgs_dir(lrsdp_ctx *c, int prec, int64_t n, int64_t ld, const void *G,
+                                 const void *const *S, const void *const *Y, int k, void *D) {
+    clear_error();
+    if (!c || !G || !D || (k > 0 && (!S || !Y))) return set_error(LRSDP_EINVAL, "NULL argument");
+    if (k < 0 || k > kMaxMem) return set_error(LRSDP_EINVAL, "k = %d not in [0, %d]", k, kMaxMem);
+    int rc;
+    if ((rc = check_prec(prec)) || (rc = check_ld(prec, ld))) return rc;
+    const int pr = prec == LRSDP_F64 ? LRSDP_F64 : LRSDP_F32;
+    const int nb = 2 * k + 1;
+    const void *basis[kMaxBasis];
+    basis[0] = G;
+    for (int t = 0; t < k; ++t) {
+        basis[1 + t] = S[t];
+        basis[1 + k + t] = Y[t];
+    }
+    hipStream_t s = c->stream;
+    double *part = at<double>(c->scratch, kPartMiscOff);
+    double *small = at<double>(c->scratch, kSmallOff);
+    double *red = small;                      // nb sums
+    double *gram = small + 64;                // nb x nb
+    double *coef = small + 64 + 512;          // nb
+    int *flag = reinterpret_cast<int *>(small + 64 + 512 + 64);
+    for (int i = 0; i < nb; ++i) {
+        int nblk = 0;
+        if ((rc = launch_dots(s, pr, basis[i], basis, nb, n, ld, part, &nblk))) return rc;
+        if ((rc = launch_reduce(s, part, nblk, nb, red))) return rc;
+        if ((rc = launch_gather_gram(s, red, nb, i, gram))) return rc;
+    }
+    if ((rc = launch_two_loop_pairs(s, gram, k, coef, flag))) return rc;
+    int nblk = 0;
+    if ((rc = launch_combine(s, pr, nullptr, coef, basis, nb, D, n, ld, part, &nblk))) return rc;
+    int hflag = 0;
+    LRSDP_HIP_TRY(hipMemcpyAsync(c->pinned, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    LRSDP_HIP_TRY(hipStreamSynchronize(s));
+    std::memcpy(&hflag, c->pinned, sizeof(int));
+    if (hflag) return set_error(LRSDP_EINVAL, "a pair has <y_t, s_t> <= 0");
+    return LRSDP_OK;
+}

@@ -1,0 +1,706 @@
+// Streaming and single-workgroup kernels of the device-resident ALM/L-BFGS loop.
+//
+// The L-BFGS memory (Algorithm 1) is kept as two rings of n x ld arrays: the
+// last T+1 gradients G and the last T directions D.  Pair t of Algorithm 1 is
+// s_t = tau_t D_t and y_t = G_{t+1} - G_t.  The Gram matrix of the ring slots
+// is maintained incrementally (each sweep that writes a new G or D also takes
+// its dot products with every slot), so the two-loop recursion of Algorithm 1
+// runs on (2T+1)-vectors of coefficients in one thread; the new direction is
+// then formed by one streaming pass D = sum_j coef_j basis_j.  This is the same
+// recursion as Algorithm 1 (identical up to rounding) with two passes over the
+// history per iteration instead of 2T dependent passes.
+#include "device.h"
+#include "kernels.h"
+
+namespace lrsdp {
+
+// ---------------------------------------------------------------------------
+// Exact step of the quartic line search (appendix A.2), float64, one thread.
+//
+// f(t) = a1 t^4 + a2 t^3 + a3 t^2 + a4 t with a1 >= 0.  Local minima of f on
+// t > 0 are the roots where f' = 4a1 t^3 + 3a2 t^2 + 2a3 t + a4 crosses from
+// negative to positive, i.e. lie where f' is increasing: split (0, inf) at the
+// roots of f'' (a quadratic), bracket each sign change of f' on an increasing
+// piece and refine by safeguarded Newton/bisection.  Returns the minimiser with
+// the smallest f (smaller t on a tie) if f < 0 there, else 0.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Quartic {
+    double a1, a2, a3, a4;
+    __host__ __device__ double f(double t) const { return (((a1 * t + a2) * t + a3) * t + a4) * t; }
+    __host__ __device__ double d1(double t) const { return ((4.0 * a1 * t + 3.0 * a2) * t + 2.0 * a3) * t + a4; }
+    __host__ __device__ double d2(double t) const { return (12.0 * a1 * t + 6.0 * a2) * t + 2.0 * a3; }
+};
+
+// Root of f' in (lo, hi) with f'(lo) < 0 < f'(hi), f' increasing there.
+__host__ __device__ double refine_root(const Quartic &q, double lo, double hi) {
+    double t = 0.5 * (lo + hi);
+    for (int it = 0; it < 300; ++it) {
+        double v = q.d1(t);
+        if (v == 0.0) return t;
+        if (v < 0.0) lo = t; else hi = t;
+        double d = q.d2(t);
+        double tn = (d > 0.0) ? t - v / d : 0.5 * (lo + hi);
+        if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
+        if (hi - lo <= 4e-16 * fabs(hi)) return tn;
+        if (tn == t) return t;
+        t = tn;
+    }
+    return t;
+}
+
+// Smallest hi > lo with f'(hi) > 0 (f' -> +inf since a1 > 0 or a quadratic
+// with positive leading term); doubling from a scale guess.
+__host__ __device__ double bracket_up(const Quartic &q, double lo, double guess) {
+    double hi = fmax(guess, lo > 0.0 ? 2.0 * lo : 1e-300);
+    for (int it = 0; it < 2200 && !(q.d1(hi) > 0.0); ++it) hi *= 2.0;
+    return hi;
+}
+
+__host__ __device__ double exact_step(double a1, double a2, double a3, double a4) {
+    Quartic q{a1, a2, a3, a4};
+    double cand[2];
+    int nc = 0;
+    double scale = 1.0;
+    if (a3 != 0.0 && a4 != 0.0) scale = fabs(a4 / a3);
+    if (a1 > 0.0 || (a1 == 0.0 && a2 > 0.0)) {
+        // f' -> +inf.  Increasing pieces of f': where f'' >= 0.
+        // f'' = 12 a1 t^2 + 6 a2 t + 2 a3 (or 6 a2 t + 2 a3 when a1 = 0)
+        double tm = 0.0, tn = 0.0;  // f' increasing on (-inf, tm] and [tn, inf)
+        bool two = false;
+        if (a1 > 0.0) {
+            double A = 12.0 * a1, B = 6.0 * a2, C = 2.0 * a3;
+            double disc = B * B - 4.0 * A * C;
+            if (disc > 0.0) {
+                double sq = sqrt(disc);
+                double qq = -0.5 * (B + (B >= 0.0 ? sq : -sq));
+                double r1 = qq / A, r2 = (qq != 0.0) ? C / qq : -B / A;
+                tm = fmin(r1, r2);
+                tn = fmax(r1, r2);
+                two = true;
+            }
+        } else {
+            // f' = 3a2 t^2 + 2a3 t + a4 (a2 > 0): increasing on [-a3/(3a2), inf)
+            tn = -a3 / (3.0 * a2);
+            tm = -INFINITY;
+            two = true;
+        }
+        if (!two) {
+            if (q.d1(0.0) < 0.0) {
+                double hi = bracket_up(q, 0.0, scale);
+                cand[nc++] = refine_root(q, 0.0, hi);
+            }
+        } else {
+            if (tm > 0.0 && q.d1(0.0) < 0.0 && q.d1(tm) > 0.0) cand[nc++] = refine_root(q, 0.0, tm);
+            double s0 = fmax(0.0, tn);
+            if (q.d1(s0) < 0.0) {
+                double hi = bracket_up(q, s0, fmax(scale, 2.0 * s0));
+                cand[nc++] = refine_root(q, s0, hi);
+            }
+        }
+    } else if (a1 == 0.0 && a2 == 0.0) {
+        if (a3 > 0.0 && a4 < 0.0) cand[nc++] = -a4 / (2.0 * a3);
+    } else if (a1 == 0.0 && a2 < 0.0) {
+        // f' = 3a2 t^2 + 2a3 t + a4 opens downward: increasing on (-inf, -a3/(3a2)]
+        double tm = -a3 / (3.0 * a2);
+        if (tm > 0.0 && q.d1(0.0) < 0.0 && q.d1(tm) > 0.0) cand[nc++] = refine_root(q, 0.0, tm);
+    }
+    double best = 0.0, fbest = 0.0;
+    for (int c = 0; c < nc; ++c) {
+        double t = cand[c];
+        double ft = q.f(t);
+        if (t > 0.0 && (ft < fbest || (ft == fbest && t < best && ft < 0.0))) {
+            best = t;
+            fbest = ft;
+        }
+    }
+    return best;
+}
+
+// ---------------------------------------------------------------------------
+// Two-loop recursion of Algorithm 1 on coefficient vectors.
+// Basis index of G slot g is g (0..T), of D slot d is T+1+d.  The current
+// gradient is G slot gk; pair it (k-nmem <= it < k) has D in slot
+// (dk - (k-it)) mod T and gradients G_it, G_{it+1} in slots
+// (gk - (k-it)) mod (T+1) and the next one.
+// ---------------------------------------------------------------------------
+__device__ double gdot(const double *M, int NB, const double *u, const double *v) {
+    double s = 0.0;
+    for (int i = 0; i < NB; ++i) {
+        if (u[i] == 0.0) continue;
+        double t = 0.0;
+        for (int j = 0; j < NB; ++j) t += M[i * kMaxBasis + j] * v[j];
+        s += u[i] * t;
+    }
+    return s;
+}
+
+__device__ void two_loop_coef(SolverState *st) {
+    const int T = st->T, NB = 2 * T + 1, nmem = st->nmem, gk = st->gk, dk = st->dk;
+    const double *M = st->gram;
+    double q[kMaxBasis], sv[kMaxMem][kMaxBasis], yv[kMaxMem][kMaxBasis], alpha[kMaxMem], beta[kMaxMem];
+    for (int j = 0; j < NB; ++j) q[j] = 0.0;
+    q[gk] = -1.0;
+    for (int t = 0; t < nmem; ++t) {  // t = 0 oldest
+        int back = nmem - t;              // k - it
+        int ds = ((dk - back) % T + T) % T;
+        int g0 = ((gk - back) % (T + 1) + (T + 1)) % (T + 1);
+        int g1 = (g0 + 1) % (T + 1);
+        for (int j = 0; j < NB; ++j) {
+            sv[t][j] = 0.0;
+            yv[t][j] = 0.0;
+        }
+        sv[t][T + 1 + ds] = st->taus[ds];
+        yv[t][g1] += 1.0;
+        yv[t][g0] -= 1.0;
+        beta[t] = 1.0 / gdot(M, NB, yv[t], sv[t]);
+    }
+    for (int t = nmem - 1; t >= 0; --t) {
+        alpha[t] = beta[t] * gdot(M, NB, sv[t], q);
+        for (int j = 0; j < NB; ++j) q[j] -= alpha[t] * yv[t][j];
+    }
+    for (int t = 0; t < nmem; ++t) {
+        double c = alpha[t] - beta[t] * gdot(M, NB, yv[t], q);
+        for (int j = 0; j < NB; ++j) q[j] += c * sv[t][j];
+    }
+    // descent safeguard: <G_k, D> must be negative
+    double e[kMaxBasis];
+    for (int j = 0; j < NB; ++j) e[j] = 0.0;
+    e[gk] = 1.0;
+    double gd = gdot(M, NB, e, q);
+    if (!(gd < 0.0)) {
+        st->nmem = 0;
+        for (int j = 0; j < NB; ++j) q[j] = 0.0;
+        q[gk] = -1.0;
+    }
+    for (int j = 0; j < kMaxBasis; ++j) st->coef[j] = j < NB ? q[j] : 0.0;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Single-workgroup kernels
+// ---------------------------------------------------------------------------
+
+// Line-search stage: fold the previous combine pass's dots into the Gram
+// matrix, form a1..a4 and take the exact step.
+__global__ __launch_bounds__(kBlock) void k_ls_finalize(SolverState *st, const double *ls_part, int n_ls,
+                                                        const double *cb_part, int n_cb) {
+    if (st->done) return;
+    __shared__ double ls[kLsSums];
+    __shared__ double cb[kMaxBasis + 1];
+    reduce_partials(ls_part, n_ls, kMaxSums, kLsSums, ls);
+    reduce_partials(cb_part, n_cb, kMaxSums, kMaxBasis + 1, cb);
+    if (threadIdx.x != 0) return;
+    const int T = st->T, NB = 2 * T + 1, dcol = T + 1 + st->dk;
+    double *M = st->gram;
+    for (int j = 0; j < NB; ++j) {
+        if (j == dcol) continue;
+        M[dcol * kMaxBasis + j] = cb[j];
+        M[j * kMaxBasis + dcol] = cb[j];
+    }
+    M[dcol * kMaxBasis + dcol] = cb[kMaxBasis];
+    const double sigma = st->sigma;
+    const double a1 = 0.5 * sigma * ls[3];
+    const double a2 = sigma * ls[4];
+    const double a3 = ls[0] - ls[1] + 0.5 * sigma * ls[5];
+    const double a4 = M[st->gk * kMaxBasis + dcol];
+    st->a[0] = a1;
+    st->a[1] = a2;
+    st->a[2] = a3;
+    st->a[3] = a4;
+    bool finite = isfinite(a1) && isfinite(a2) && isfinite(a3) && isfinite(a4);
+    double tau = finite ? exact_step(a1, a2, a3, a4) : 0.0;
+    if (!finite) st->numeric = 1;
+    st->tau = tau;
+    st->taus[st->dk] = tau;
+    if (!(tau > 0.0)) {
+        st->done = 3;
+        st->k += 1;
+        st->inner_total += 1;
+    }
+}
+
+// L-BFGS stage: fold the update pass's dots (new gradient) into the Gram
+// matrix, apply the curvature guard to the new pair, advance the rings and
+// compute the next direction's coefficients.
+__global__ __launch_bounds__(kBlock) void k_lbfgs_finalize(SolverState *st, const double *up_part, int n_up) {
+    if (st->done) return;
+    __shared__ double raw[kMaxBasis];
+    reduce_partials(up_part, n_up, kMaxSums, kMaxBasis, raw);
+    if (threadIdx.x != 0) return;
+    const int T = st->T, NB = 2 * T + 1;
+    double us[kMaxBasis];
+    for (int j = 0; j < NB; ++j) us[j] = j <= T ? raw[j] : raw[kMaxMem + 1 + (j - T - 1)];
+    const int gk = st->gk, gk1 = (gk + 1) % (T + 1), ds = T + 1 + st->dk;
+    double *M = st->gram;
+    for (int j = 0; j < NB; ++j) {
+        M[gk1 * kMaxBasis + j] = us[j];
+        M[j * kMaxBasis + gk1] = us[j];
+    }
+    const double tau = st->tau;
+    const double ys = tau * (M[gk1 * kMaxBasis + ds] - M[gk * kMaxBasis + ds]);
+    const double yy = M[gk1 * kMaxBasis + gk1] - 2.0 * M[gk1 * kMaxBasis + gk] + M[gk * kMaxBasis + gk];
+    const double ss = tau * tau * M[ds * kMaxBasis + ds];
+    if (ys > 1e-12 * sqrt(fabs(yy * ss))) st->nmem = min(st->nmem + 1, T);
+    else st->nmem = 0;
+    st->k += 1;
+    st->inner_total += 1;
+    st->gk = gk1;
+    st->dk = (st->dk + 1) % T;
+    const double g2 = M[gk1 * kMaxBasis + gk1];
+    st->gnorm = sqrt(fmax(g2, 0.0));
+    if (!isfinite(g2)) {
+        st->numeric = 1;
+        st->done = 3;
+        return;
+    }
+    if (st->gnorm <= st->target) st->done = 1;
+    else if (st->k >= st->max_inner) st->done = 2;
+    else two_loop_coef(st);
+}
+
+// Start of a subproblem: gradient norm known, empty memory, D = -G.
+__global__ __launch_bounds__(kBlock) void k_init_finalize(SolverState *st, const double *part, int n_part,
+                                                          int k_limit) {
+    __shared__ double g2[1];
+    reduce_partials(part, n_part, kMaxSums, 1, g2);
+    if (threadIdx.x != 0) return;
+    for (int j = 0; j < kMaxBasis * kMaxBasis; ++j) st->gram[j] = 0.0;
+    st->gram[0] = g2[0];
+    st->gk = 0;
+    st->dk = 0;
+    st->k = 0;
+    st->nmem = 0;
+    st->max_inner = k_limit;
+    st->gnorm = sqrt(fmax(g2[0], 0.0));
+    st->target = st->eta * fmax(1.0, st->gnorm);
+    for (int j = 0; j < kMaxBasis; ++j) st->coef[j] = 0.0;
+    st->coef[0] = -1.0;
+    st->done = 0;
+    if (!isfinite(g2[0])) {
+        st->numeric = 1;
+        st->done = 3;
+    } else if (st->gnorm <= st->target) {
+        st->done = 1;
+    } else if (k_limit <= 0) {
+        st->done = 2;
+    }
+}
+
+// ALM step: measures after the multiplier update, stop test, penalty and
+// inner-tolerance schedules.  mode 0: initial point (no schedule update).
+__global__ __launch_bounds__(kBlock) void k_alm_finalize(SolverState *st, const double *part, int n_part,
+                                                         int mode) {
+    __shared__ double rs[3];
+    reduce_partials(part, n_part, kMaxSums, 3, rs);
+    if (threadIdx.x != 0) return;
+    const double obj = rs[0], dual = rs[1];
+    const double res_norm = sqrt(fmax(rs[2], 0.0));
+    st->obj = obj;
+    st->dual = dual;
+    st->res_norm = res_norm;
+    st->err1 = res_norm / (1.0 + st->b_l1);
+    st->err1_inf = res_norm / (1.0 + st->b_inf);
+    st->err3 = (obj - dual) / (1.0 + fabs(obj) + fabs(dual));
+    if (!isfinite(obj) || !isfinite(dual) || !isfinite(res_norm)) st->numeric = 1;
+    st->refreshes += 1;
+    if (mode == 0) return;
+    st->converged = (st->err1 <= st->tol && fabs(st->err3) <= st->tol) ? 1 : 0;
+    if (st->converged) return;
+    if (st->err1 > st->feas_decrease * st->err1_prev) st->sigma = fmin(st->sigma * st->sigma_factor, st->sigma_cap);
+    st->err1_prev = st->err1;
+    st->eta = fmax(st->eta * st->eta_factor, st->eta_min);
+}
+
+// Generic reduction of one partials set into out (device), K sums.
+__global__ __launch_bounds__(kBlock) void k_reduce(const double *part, int n_part, int K, double *out) {
+    reduce_partials(part, n_part, kMaxSums, K, out);
+}
+
+__global__ void k_cubic(const double *a, double *tau) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *tau = exact_step(a[0], a[1], a[2], a[3]);
+}
+
+// ---------------------------------------------------------------------------
+// Streaming kernels
+// ---------------------------------------------------------------------------
+
+template <typename S>
+struct UpdateArgs {
+    SolverState *st;
+    S *R;
+    const S *CD;
+    const double *y;
+    double *ytil;
+    Rings<S> rings;
+    int64_t n, ld;
+    double *partials;
+};
+
+// MaxCut update sweep for step tau along D_k:
+//   R <- R + tau D,  ytil_i <- y_i + sigma (1 - ||R_i||^2),
+//   G_{k+1} = 2 (C R_new - ytil_new o R_new) with C R_new = C R + tau C D and
+//   C R = G_k/2 + ytil_old o R_old (so C R need not be stored),
+// and the dot products of G_{k+1} with every ring slot (partials layout: G slot
+// g at g, D slot d at kMaxMem + 1 + d).
+template <typename S, int GS>
+__global__ __launch_bounds__(kBlock) void k_update_maxcut(UpdateArgs<S> a) {
+    using CV = typename Chunk<S>::V;
+    constexpr int NV = Chunk<S>::N;
+    constexpr int GPB = kBlock / GS;
+    SolverState *st = a.st;
+    if (st->done) return;
+    const double tau = st->tau, sigma = st->sigma;
+    const int T = st->T, gk = st->gk, gk1 = (gk + 1) % (T + 1), dk = st->dk;
+    const int lane = threadIdx.x % GS, grp = threadIdx.x / GS;
+    const bool active = lane * NV < a.ld;
+    const CV zero = vzero(CV{});
+    double s[kMaxBasis];
+#pragma unroll
+    for (int j = 0; j < kMaxBasis; ++j) s[j] = 0.0;
+    // ring pointers of the dynamic slots, selected with static indices
+    const S *D = nullptr;
+    const S *Go = nullptr;
+    S *Gn = nullptr;
+#pragma unroll
+    for (int g = 0; g <= kMaxMem; ++g) {
+        if (g == gk) Go = a.rings.g[g];
+        if (g == gk1) Gn = a.rings.g[g];
+    }
+#pragma unroll
+    for (int d = 0; d < kMaxMem; ++d)
+        if (d == dk) D = a.rings.d[d];
+    for (int64_t row = (int64_t)blockIdx.x * GPB + grp; row < a.n; row += (int64_t)gridDim.x * GPB) {
+        const int64_t off = row * a.ld + lane * NV;
+        CV r = zero, d = zero, cd = zero, go = zero;
+        if (active) {
+            r = *reinterpret_cast<const CV *>(a.R + off);
+            d = *reinterpret_cast<const CV *>(D + off);
+            cd = *reinterpret_cast<const CV *>(a.CD + off);
+            go = *reinterpret_cast<const CV *>(Go + off);
+        }
+        const double yold = a.ytil[row], yi = a.y[row];
+        D4 R0 = widen(r), Dd = widen(d), CDd = widen(cd), G0 = widen(go), Rn;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) Rn.v[c] = fma(tau, Dd.v[c], R0.v[c]);
+        CV rn_s;
+        narrow(Rn, rn_s);
+        Rn = widen(rn_s);
+        const double rn = group_sum<GS>(vdot(rn_s, rn_s));
+        const double ynew = yi + sigma * (1.0 - rn);
+        D4 Gv;
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            Gv.v[c] = G0.v[c] + 2.0 * tau * CDd.v[c] + 2.0 * yold * R0.v[c] - 2.0 * ynew * Rn.v[c];
+        CV gn_s;
+        narrow(Gv, gn_s);
+        if (active) {
+            *reinterpret_cast<CV *>(a.R + off) = rn_s;
+            *reinterpret_cast<CV *>(Gn + off) = gn_s;
+        }
+        if (lane == 0) a.ytil[row] = ynew;
+#pragma unroll
+        for (int g = 0; g <= kMaxMem; ++g) {
+            if (g <= T) {
+                CV b;
+                if (g == gk1) b = gn_s;
+                else if (g == gk) b = go;
+                else b = active ? *reinterpret_cast<const CV *>(a.rings.g[g] + off) : zero;
+                s[g] += vdot(gn_s, b);
+            }
+        }
+#pragma unroll
+        for (int dd = 0; dd < kMaxMem; ++dd) {
+            if (dd < T) {
+                CV b = (dd == dk) ? d : (active ? *reinterpret_cast<const CV *>(a.rings.d[dd] + off) : zero);
+                s[kMaxMem + 1 + dd] += vdot(gn_s, b);
+            }
+        }
+    }
+    block_sums_store<kMaxBasis>(s, a.partials + (size_t)blockIdx.x * kMaxSums);
+}
+
+template <typename S>
+struct CombineArgs {
+    SolverState *st;        // coefficients (solver) or nullptr
+    const double *coef;     // used when st == nullptr
+    const S *basis[kMaxBasis];
+    int nb;                 // basis size when st == nullptr
+    S *out;                 // used when st == nullptr
+    int64_t nchunks;        // n * ld / chunk
+    double *partials;       // dots of out with each basis entry, then ||out||^2
+};
+
+// out = sum_j coef_j basis_j, and <out, basis_j> (pre-update values) for all j
+// plus <out, out>.  In the solver the output is D slot dk, itself basis entry
+// T+1+dk (read before written by the same thread).
+template <typename S>
+__global__ __launch_bounds__(kBlock) void k_combine(CombineArgs<S> a) {
+    using CV = typename Chunk<S>::V;
+    const SolverState *st = a.st;
+    if (st && st->done) return;
+    const int NB = st ? 2 * st->T + 1 : a.nb;
+    const double *coef = st ? st->coef : a.coef;
+    S *out = a.out;
+    if (st) {
+        const int oj = st->T + 1 + st->dk;
+#pragma unroll
+        for (int j = 0; j < kMaxBasis; ++j)
+            if (j == oj) out = const_cast<S *>(a.basis[j]);
+    }
+    double cf[kMaxBasis];
+#pragma unroll
+    for (int j = 0; j < kMaxBasis; ++j) cf[j] = j < NB ? coef[j] : 0.0;
+    double s[kMaxBasis + 1];
+#pragma unroll
+    for (int j = 0; j <= kMaxBasis; ++j) s[j] = 0.0;
+    for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < a.nchunks; c += (int64_t)gridDim.x * kBlock) {
+        CV b[kMaxBasis];
+        D4 acc{{0.0, 0.0, 0.0, 0.0}};
+#pragma unroll
+        for (int j = 0; j < kMaxBasis; ++j) {
+            if (j < NB) {
+                b[j] = reinterpret_cast<const CV *>(a.basis[j])[c];
+                D4 w = widen(b[j]);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc.v[e] = fma(cf[j], w.v[e], acc.v[e]);
+            }
+        }
+        CV o;
+        narrow(acc, o);
+        reinterpret_cast<CV *>(out)[c] = o;
+#pragma unroll
+        for (int j = 0; j < kMaxBasis; ++j)
+            if (j < NB) s[j] += vdot(o, b[j]);
+        s[kMaxBasis] += vdot(o, o);
+    }
+    block_sums_store<kMaxBasis + 1>(s, a.partials + (size_t)blockIdx.x * kMaxSums);
+}
+
+template <typename S>
+struct GradInitArgs {
+    SolverState *st;
+    const S *R;
+    const S *CR;
+    const double *y;
+    const double *rn;   // ||R_i||^2
+    double *ytil;
+    S *G;
+    int64_t n, ld;
+    double *partials;
+};
+
+// Start of a subproblem (MaxCut): ytil = y + sigma (1 - ||R_i||^2),
+// G = 2 (C R - ytil o R), and ||G||^2.
+template <typename S, int GS>
+__global__ __launch_bounds__(kBlock) void k_grad_init_maxcut(GradInitArgs<S> a) {
+    using CV = typename Chunk<S>::V;
+    constexpr int NV = Chunk<S>::N;
+    constexpr int GPB = kBlock / GS;
+    const double sigma = a.st->sigma;
+    const int lane = threadIdx.x % GS, grp = threadIdx.x / GS;
+    const bool active = lane * NV < a.ld;
+    double s[1] = {0.0};
+    for (int64_t row = (int64_t)blockIdx.x * GPB + grp; row < a.n; row += (int64_t)gridDim.x * GPB) {
+        const int64_t off = row * a.ld + lane * NV;
+        const double yt = a.y[row] + sigma * (1.0 - a.rn[row]);
+        if (lane == 0) a.ytil[row] = yt;
+        if (!active) continue;
+        D4 r = widen(*reinterpret_cast<const CV *>(a.R + off));
+        D4 cr = widen(*reinterpret_cast<const CV *>(a.CR + off));
+        D4 g;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) g.v[c] = 2.0 * (cr.v[c] - yt * r.v[c]);
+        CV gs;
+        narrow(g, gs);
+        *reinterpret_cast<CV *>(a.G + off) = gs;
+        s[0] += vdot(gs, gs);
+    }
+    block_sums_store<1>(s, a.partials + (size_t)blockIdx.x * kMaxSums);
+}
+
+template <typename S>
+__global__ __launch_bounds__(kBlock) void k_fill(S *p, int64_t count, S v) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += (int64_t)gridDim.x * kBlock) p[i] = v;
+}
+
+template <typename S>
+struct DotsArgs {
+    const S *x;
+    const S *basis[kMaxBasis];
+    int nb;
+    int64_t nchunks;
+    double *partials;
+};
+
+// <x, basis_j> for j < nb (float64 sums)
+template <typename S>
+__global__ __launch_bounds__(kBlock) void k_dots(DotsArgs<S> a) {
+    using CV = typename Chunk<S>::V;
+    double s[kMaxBasis];
+#pragma unroll
+    for (int j = 0; j < kMaxBasis; ++j) s[j] = 0.0;
+    for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < a.nchunks; c += (int64_t)gridDim.x * kBlock) {
+        CV x = reinterpret_cast<const CV *>(a.x)[c];
+#pragma unroll
+        for (int j = 0; j < kMaxBasis; ++j)
+            if (j < a.nb) s[j] += vdot(x, reinterpret_cast<const CV *>(a.basis[j])[c]);
+    }
+    block_sums_store<kMaxBasis>(s, a.partials + (size_t)blockIdx.x * kMaxSums);
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers
+// ---------------------------------------------------------------------------
+static int grid_for(int64_t work_items, int per_block) {
+    int64_t need = (work_items + per_block - 1) / per_block;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(need, kMaxBlocks));
+}
+
+static int chunks_per_row(int prec, int64_t ld) { return (int)(ld * (prec == LRSDP_F64 ? 8 : 4) / 16); }
+
+int launch_ls_finalize(hipStream_t s, SolverState *st, const double *ls, int nls, const double *cb, int ncb) {
+    hipLaunchKernelGGL(k_ls_finalize, dim3(1), dim3(kBlock), 0, s, st, ls, nls, cb, ncb);
+    LRSDP_CHECK_LAUNCH();
+    return LRSDP_OK;
+}
+
+int launch_lbfgs_finalize(hipStream_t s, SolverState *st, const double *up, int nup) {
+    hipLaunchKernelGGL(k_lbfgs_finalize, dim3(1), dim3(kBlock), 0, s, st, up, nup);
+    LRSDP_CHECK_LAUNCH();
+    return LRSDP_OK;
+}
+
+int launch_init_finalize(hipStream_t s, SolverState *st, const double *part, int np, int k_limit) {
+    hipLaunchKernelGGL(k_init_finalize, dim3(1), dim3(kBlock), 0, s, st, part, np, k_limit);
+    LRSDP_CHECK_LAUNCH();
+    return LRSDP_OK;
+}
+
+int launch_alm_finalize(hipStream_t s, SolverState *st, const double *part, int np, int mode) {
+    hipLaunchKernelGGL(k_alm_finalize, dim3(1), dim3(kBlock), 0, s, st, part, np, mode);
+    LRSDP_CHECK_LAUNCH();
+    return LRSDP_OK;
+}
+
+int launch_reduce(hipStream_t s, const double *part, int np, int K, double *out) {
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, s, part, np, K, out);
+    LRSDP_CHECK_LAUNCH();
+    return LRSDP_OK;
+}
+
+int launch_cubic(hipStream_t s, const double *a, double *tau) {
+    hipLaunchKernelGGL(k_cubic, dim3(1), dim3(64), 0, s, a, tau);
+    LRSDP_CHECK_LAUNCH();
+    return LRSDP_OK;
+}
+
+template <typename S>
+static int update_t(hipStream_t s, const UpdateArgs<S> &a, int cpr, int *nb) {
+    if (cpr <= 4) {
+        *nb = grid_for(a.n, kBlock / 4);
+        hipLaunchKernelGGL((k_update_maxcut<S, 4>), dim3(*nb), dim3(kBlock), 0, s, a);
+    } else if (cpr <= 8) {
+        *nb = grid_for(a.n, kBlock / 8);
+        hipLaunchKernelGGL((k_update_maxcut<S, 8>), dim3(*nb), dim3(kBlock), 0, s, a);
+    } else {
+        *nb = grid_for(a.n, kBlock / 16);
+        hipLaunchKernelGGL((k_update_maxcut<S, 16>), dim3(*nb), dim3(kBlock), 0, s, a);
+    }
+    LRSDP_CHECK_LAUNCH();
+    return LRSDP_OK;
+}
+
+int launch_update_maxcut(hipStream_t s, int prec, SolverState *st, void *R, const void *CD, const double *y,
+                         double *ytil, void *const *gring, void *const *dring, int T, int64_t n, int64_t ld,
+                         double *partials, int *nb) {
+    const int cpr = chunks_per_row(prec, ld);
+    if (prec == LRSDP_F64) {
+        UpdateArgs<double> a{st, (double *)R, (const double *)CD, y, ytil, {}, n, ld, partials};
+        for (int g = 0; g <= T; ++g) a.rings.g[g] = (double *)gring[g];
+        for (int d = 0; d < T; ++d) a.rings.d[d] = (double *)dring[d];
+        return update_t(s, a, cpr, nb);
+    }
+    UpdateArgs<float> a{st, (float *)R, (const float *)CD, y, ytil, {}, n, ld, partials};
+    for (int g = 0; g <= T; ++g) a.rings.g[g] = (float *)gring[g];
+    for (int d = 0; d < T; ++d) a.rings.d[d] = (float *)dring[d];
+    return update_t(s, a, cpr, nb);
+}
+
+// basis: nb device arrays of n*ld elements; out = sum coef_j basis_j.
+int launch_combine(hipStream_t s, int prec, SolverState *st, const double *coef, const void *const *basis, int nb,
+                   void *out, int64_t n, int64_t ld, double *partials, int *nblk) {
+    const int64_t nch = n * ld * (prec == LRSDP_F64 ? 8 : 4) / 16;
+    *nblk = grid_for(nch, kBlock);
+    if (prec == LRSDP_F64) {
+        CombineArgs<double> a{st, coef, {}, nb, (double *)out, nch, partials};
+        for (int j = 0; j < nb; ++j) a.basis[j] = (const double *)basis[j];
+        hipLaunchKernelGGL(k_combine<double>, dim3(*nblk), dim3(kBlock), 0, s, a);
+    } else {
+        CombineArgs<float> a{st, coef, {}, nb, (float *)out, nch, partials};
+        for (int j = 0; j < nb; ++j) a.basis[j] = (const float *)basis[j];
+        hipLaunchKernelGGL(k_combine<float>, dim3(*nblk), dim3(kBlock), 0, s, a);
+    }
+    LRSDP_CHECK_LAUNCH();
+    return LRSDP_OK;
+}
+
+int launch_grad_init_maxcut(hipStream_t s, int prec, SolverState *st, const void *R, const void *CR,
+                            const double *y, const double *rn, double *ytil, void *G, int64_t n, int64_t ld,
+                            double *partials, int *nblk) {
+    const int cpr = chunks_per_row(prec, ld);
+    const int gs = cpr <= 4 ? 4 : (cpr <= 8 ? 8 : 16);
+    *nblk = grid_for(n, kBlock / gs);
+    if (prec == LRSDP_F64) {
+        GradInitArgs<double> a{st, (const double *)R, (const double *)CR, y, rn, ytil, (double *)G, n, ld, partials};
+        if (gs == 4) hipLaunchKernelGGL((k_grad_init_maxcut<double, 4>), dim3(*nblk), dim3(kBlock), 0, s, a);
+        else if (gs == 8) hipLaunchKernelGGL((k_grad_init_maxcut<double, 8>), dim3(*nblk), dim3(kBlock), 0, s, a);
+        else hipLaunchKernelGGL((k_grad_init_maxcut<double, 16>), dim3(*nblk), dim3(kBlock), 0, s, a);
+    } else {
+        GradInitArgs<float> a{st, (const float *)R, (const float *)CR, y, rn, ytil, (float *)G, n, ld, partials};
+        if (gs == 4) hipLaunchKernelGGL((k_grad_init_maxcut<float, 4>), dim3(*nblk), dim3(kBlock), 0, s, a);
+        else if (gs == 8) hipLaunchKernelGGL((k_grad_init_maxcut<float, 8>), dim3(*nblk), dim3(kBlock), 0, s, a);
+        else hipLaunchKernelGGL((k_grad_init_maxcut<float, 16>), dim3(*nblk), dim3(kBlock), 0, s, a);
+    }
+    LRSDP_CHECK_LAUNCH();
+    return LRSDP_OK;
+}
+
+int launch_fill(hipStream_t s, int prec, void *p, int64_t count) {
+    int nb = grid_for(count, kBlock);
+    if (prec == LRSDP_F64) hipLaunchKernelGGL(k_fill<double>, dim3(nb), dim3(kBlock), 0, s, (double *)p, count, 0.0);
+    else hipLaunchKernelGGL(k_fill<float>, dim3(nb), dim3(kBlock), 0, s, (float *)p, count, 0.0f);
+    LRSDP_CHECK_LAUNCH();
+    return LRSDP_OK;
+}
+
+int launch_fill_f64(hipStream_t s, double *p, int64_t count, double v) {
+    int nb = grid_for(count, kBlock);
+    hipLaunchKernelGGL(k_fill<double>, dim3(nb), dim3(kBlock), 0, s, p, count, v);
+    LRSDP_CHECK_LAUNCH();
+    return LRSDP_OK;
+}
+
+int launch_dots(hipStream_t s, int prec, const void *x, const void *const *basis, int nb, int64_t n, int64_t ld,
+                double *partials, int *nblk) {
+    const int64_t nch = n * ld * (prec == LRSDP_F64 ? 8 : 4) / 16;
+    *nblk = grid_for(nch, kBlock);
+    if (prec == LRSDP_F64) {
+        DotsArgs<double> a{(const double *)x, {}, nb, nch, partials};
+        for (int j = 0; j < nb; ++j) a.basis[j] = (const double *)basis[j];
+        hipLaunchKernelGGL(k_dots<double>, dim3(*nblk), dim3(kBlock), 0, s, a);
+    } else {
+        DotsArgs<float> a{(const float *)x, {}, nb, nch, partials};
+        for (int j = 0; j < nb; ++j) a.basis[j] = (const float *)basis[j];
+        hipLaunchKernelGGL(k_dots<float>, dim3(*nblk), dim3(kBlock), 0, s, a);
+    }
+    LRSDP_CHECK_LAUNCH();
+    return LRSDP_OK;
+}
+
+// host copy of the step rule for kernels that need it on the host side
+double exact_step_host(double a1, double a2, double a3, double a4) { return exact_step(a1, a2, a3, a4); }
+
+}  // namespace lrsdp

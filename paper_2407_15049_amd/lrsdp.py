@@ -1,0 +1,288 @@
+"""ctypes binding of ``liblrsdp.so`` (the C ABI declared in include/lrsdp.h).
+
+Argument marshalling only: every step of the solve runs in the library's HIP
+kernels.  Device buffers are torch tensors on the context's device; their
+pointers are handed to the library, which never allocates on the solve path.
+The binding raises ``LrsdpUnavailable`` when the built library is missing; it
+has no fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "liblrsdp.so")
+
+OK, NOT_CONVERGED = 0, 1
+EINVAL, ENOMEM, EHIP, ENUMERIC, EUNSUPPORTED = -1, -2, -3, -4, -5
+F64, F32, F32_BF16IN = 0, 1, 2
+MAXCUT, COMPLETION = 1, 2
+
+
+class LrsdpUnavailable(ImportError):
+    pass
+
+
+class LrsdpError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"lrsdp error {code}: {msg}")
+        self.code = code
+
+
+class Options(C.Structure):
+    _fields_ = [
+        ("prec", C.c_int), ("rank", C.c_int), ("ld", C.c_int), ("lbfgs_mem", C.c_int),
+        ("tol", C.c_double), ("max_outer", C.c_int), ("max_inner", C.c_int),
+        ("max_iter_total", C.c_int64), ("time_limit_s", C.c_double),
+        ("sigma0", C.c_double), ("sigma_factor", C.c_double), ("sigma_max_ratio", C.c_double),
+        ("feas_decrease", C.c_double), ("eta0", C.c_double), ("eta_factor", C.c_double),
+        ("eta_min", C.c_double), ("check_every", C.c_int), ("refresh_every", C.c_int),
+        ("profile", C.c_int), ("verbose", C.c_int),
+    ]
+
+
+class Result(C.Structure):
+    _fields_ = [
+        ("obj", C.c_double), ("dual", C.c_double), ("err1", C.c_double), ("err1_inf", C.c_double),
+        ("err3", C.c_double), ("sigma", C.c_double), ("seconds", C.c_double),
+        ("outer", C.c_int64), ("inner", C.c_int64), ("status", C.c_int),
+        ("spmm_launches", C.c_int), ("spmm_ms", C.c_double), ("spmm_bytes", C.c_double),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class ProblemInfo(C.Structure):
+    _fields_ = [
+        ("kind", C.c_int), ("n", C.c_int64), ("m", C.c_int64), ("nnz", C.c_int64),
+        ("n1", C.c_int64), ("n2", C.c_int64), ("weights", C.c_int), ("max_row_nnz", C.c_int64),
+        ("c_l1", C.c_double), ("b_l1", C.c_double), ("b_inf", C.c_double),
+    ]
+
+
+_P = C.c_void_p
+_I64 = C.c_int64
+_SIGS = {
+    "lrsdp_last_error": (C.c_char_p, []),
+    "lrsdp_version": (C.c_char_p, []),
+    "lrsdp_ctx_create": (C.c_int, [C.c_int, _P, C.POINTER(_P)]),
+    "lrsdp_ctx_destroy": (None, [_P]),
+    "lrsdp_problem_maxcut": (C.c_int, [_I64, _I64, _P, _P, _P, C.POINTER(_P)]),
+    "lrsdp_problem_completion": (C.c_int, [_I64, _I64, _I64, _P, _P, _P, C.POINTER(_P)]),
+    "lrsdp_problem_destroy": (None, [_P]),
+    "lrsdp_problem_get_info": (C.c_int, [_P, C.POINTER(ProblemInfo)]),
+    "lrsdp_problem_device_bytes": (C.c_int, [_P, C.POINTER(C.c_size_t)]),
+    "lrsdp_problem_upload": (C.c_int, [_P, _P, _P, C.c_size_t]),
+    "lrsdp_options_default": (None, [C.POINTER(Options)]),
+    "lrsdp_workspace_bytes": (C.c_int, [_P, C.POINTER(Options), C.POINTER(C.c_size_t)]),
+    "lrsdp_solve": (C.c_int, [_P, _P, C.POINTER(Options), _P, C.c_size_t, _P, _P, C.POINTER(Result)]),
+    "lrsdp_k_spmm": (C.c_int, [_P, _P, C.c_int, _P, _I64, _P, _P]),
+    "lrsdp_k_constraint": (C.c_int, [_P, _P, C.c_int, _P, _P, _I64, _P]),
+    "lrsdp_k_ls_coeffs": (C.c_int, [_P, _P, C.c_int, _P, _P, _I64, _P, C.c_double, _P, _P, _P, _P]),
+    "lrsdp_k_cubic": (C.c_int, [_P, _P, _P]),
+    "lrsdp_k_alm": (C.c_int, [_P, _P, C.c_int, _P, _I64, _P, C.c_double, _P, _P]),
+    "lrsdp_k_lbfgs_dir": (C.c_int, [_P, C.c_int, _I64, _I64, _P, _P, _P, C.c_int, _P]),
+}
+
+_lib = None
+
+
+def load():
+    """Load the built library (raises LrsdpUnavailable if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise LrsdpUnavailable(
+            f"{LIB_PATH} not found: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+    lib = C.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGS.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def _check(rc):
+    if rc < 0:
+        raise LrsdpError(rc, load().lrsdp_last_error().decode())
+    return rc
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _host(a, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data_as(C.c_void_p)
+
+
+def default_options(**kw) -> Options:
+    o = Options()
+    load().lrsdp_options_default(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise AttributeError(k)
+        setattr(o, k, v)
+    return o
+
+
+def padded_ld(rank: int, prec: int) -> int:
+    """Smallest row stride >= rank whose row bytes are a multiple of 16."""
+    per = 2 if prec == F64 else 4
+    return ((rank + per - 1) // per) * per
+
+
+def elem_dtype(prec: int):
+    import torch
+    return torch.float64 if prec == F64 else torch.float32
+
+
+class Context:
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        lib = load()
+        self.device = device
+        self.torch_device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.torch_device)
+        self.stream = stream
+        h = C.c_void_p()
+        _check(lib.lrsdp_ctx_create(device, C.c_void_p(stream.cuda_stream), C.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().lrsdp_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Problem:
+    """Host-built problem; ``upload`` places it in a torch-owned device buffer."""
+
+    def __init__(self, handle):
+        self.handle = handle
+        self.dev = None
+
+    @classmethod
+    def maxcut(cls, n, u, v, w=None):
+        lib = load()
+        ua, up = _host(u, np.int32)
+        va, vp = _host(v, np.int32)
+        if w is not None:
+            wa, wp = _host(w, np.float64)
+        else:
+            wp = None
+        h = C.c_void_p()
+        _check(lib.lrsdp_problem_maxcut(int(n), len(ua), up, vp, wp, C.byref(h)))
+        return cls(h)
+
+    @classmethod
+    def completion(cls, n1, n2, i, j, Mij):
+        lib = load()
+        ia, ip = _host(i, np.int32)
+        ja, jp = _host(j, np.int32)
+        ma, mp = _host(Mij, np.float64)
+        h = C.c_void_p()
+        _check(lib.lrsdp_problem_completion(int(n1), int(n2), len(ia), ip, jp, mp, C.byref(h)))
+        return cls(h)
+
+    @property
+    def info(self) -> ProblemInfo:
+        inf = ProblemInfo()
+        _check(load().lrsdp_problem_get_info(self.handle, C.byref(inf)))
+        return inf
+
+    def device_bytes(self) -> int:
+        b = C.c_size_t()
+        _check(load().lrsdp_problem_device_bytes(self.handle, C.byref(b)))
+        return b.value
+
+    def upload(self, ctx: Context):
+        import torch
+        nbytes = self.device_bytes()
+        self.dev = torch.empty(nbytes, dtype=torch.uint8, device=ctx.torch_device)
+        _check(load().lrsdp_problem_upload(ctx.handle, self.handle, _ptr(self.dev), nbytes))
+        return self
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().lrsdp_problem_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def workspace_bytes(prob: Problem, opts: Options) -> int:
+    b = C.c_size_t()
+    _check(load().lrsdp_workspace_bytes(prob.handle, C.byref(opts), C.byref(b)))
+    return b.value
+
+
+def solve(ctx: Context, prob: Problem, R, y, opts: Options, workspace=None):
+    """Run the solve in place on device tensors R (n x ld) and y (m, float64).
+
+    Returns (status, Result).  ``workspace`` may be a preallocated uint8 device
+    tensor of at least ``workspace_bytes`` bytes.
+    """
+    import torch
+    need = workspace_bytes(prob, opts)
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=ctx.torch_device)
+    res = Result()
+    rc = _check(load().lrsdp_solve(ctx.handle, prob.handle, C.byref(opts), _ptr(workspace),
+                                   workspace.numel(), _ptr(R), _ptr(y), C.byref(res)))
+    return rc, res
+
+
+# ---- kernel entry points --------------------------------------------------------
+def k_spmm(ctx, prob, prec, V, ytil, Y):
+    _check(load().lrsdp_k_spmm(ctx.handle, prob.handle, prec, _ptr(V), V.shape[1], _ptr(ytil), _ptr(Y)))
+
+
+def k_constraint(ctx, prob, prec, U, V, out):
+    _check(load().lrsdp_k_constraint(ctx.handle, prob.handle, prec, _ptr(U), _ptr(V), U.shape[1], _ptr(out)))
+
+
+def k_ls_coeffs(ctx, prob, prec, R, D, y, sigma, work, out, q1=None, q2=None):
+    _check(load().lrsdp_k_ls_coeffs(ctx.handle, prob.handle, prec, _ptr(R), _ptr(D), R.shape[1], _ptr(y),
+                                    float(sigma), _ptr(work), _ptr(out), _ptr(q1), _ptr(q2)))
+
+
+def k_cubic(ctx, a, tau):
+    _check(load().lrsdp_k_cubic(ctx.handle, _ptr(a), _ptr(tau)))
+
+
+def k_alm(ctx, prob, prec, R, y, sigma, work, out):
+    _check(load().lrsdp_k_alm(ctx.handle, prob.handle, prec, _ptr(R), R.shape[1], _ptr(y), float(sigma),
+                              _ptr(work), _ptr(out)))
+
+
+def k_lbfgs_dir(ctx, prec, G, S, Y, D):
+    k = len(S)
+    sp = (C.c_void_p * max(k, 1))(*[t.data_ptr() for t in S])
+    yp = (C.c_void_p * max(k, 1))(*[t.data_ptr() for t in Y])
+    _check(load().lrsdp_k_lbfgs_dir(ctx.handle, prec, G.shape[0], G.shape[1], _ptr(G),
+                                    C.cast(sp, C.c_void_p), C.cast(yp, C.c_void_p), k, _ptr(D)))

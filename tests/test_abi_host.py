@@ -1,0 +1,129 @@
+"""Host-side checks of the C-ABI library (no GPU needed).
+
+* the built library exports every function include/lrsdp.h declares;
+* the host problem builder validates its input and reports the same problem
+  constants as the oracle's own build;
+* the default solver options carry the same schedule numbers as the oracle.
+"""
+
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle.alm import Options as OracleOptions
+from oracle.problem import completion_problem, maxcut_problem
+from synth import chung_lu_edges, completion_instance, erdos_renyi_edges, pm1_weights
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+L = pytest.importorskip("paper_2407_15049_amd.lrsdp")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return L.load()
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "lrsdp.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lrsdp_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = header_functions()
+    assert len(names) >= 18
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(L.exported_symbols())
+
+
+def test_version(lib):
+    assert b"gfx950" in lib.lrsdp_version()
+
+
+@pytest.mark.parametrize("u,v,msg", [
+    ([0, 1], [1, 5], "outside"),
+    ([0, 2], [1, 2], "self loop"),
+    ([0, 1], [1, 0], "more than once"),
+    ([-1], [2], "outside"),
+])
+def test_maxcut_rejects_malformed_edges(u, v, msg):
+    with pytest.raises(L.LrsdpError) as e:
+        L.Problem.maxcut(5, u, v)
+    assert e.value.code == L.EINVAL and msg in str(e.value)
+
+
+def test_maxcut_rejects_nonfinite_weight():
+    with pytest.raises(L.LrsdpError):
+        L.Problem.maxcut(4, [0, 1], [1, 2], [1.0, np.nan])
+
+
+def test_completion_rejects_bad_samples():
+    with pytest.raises(L.LrsdpError):
+        L.Problem.completion(3, 3, [0, 0], [1, 1], [1.0, 2.0])      # repeated
+    with pytest.raises(L.LrsdpError):
+        L.Problem.completion(3, 3, [0, 3], [1, 1], [1.0, 2.0])      # out of range
+    with pytest.raises(L.LrsdpError):
+        L.Problem.completion(3, 3, [0], [1], [np.inf])
+
+
+@pytest.mark.parametrize("kind", ["unit", "pm1", "general", "cl"])
+def test_maxcut_constants_match_oracle(kind):
+    n, m = 300, 1200
+    if kind == "cl":
+        u, v = chung_lu_edges(n, m, 2.5, 5)
+    else:
+        u, v = erdos_renyi_edges(n, m, 4)
+    w = None
+    if kind == "pm1":
+        w = pm1_weights(m, 9)
+    elif kind == "general":
+        w = np.random.default_rng(2).uniform(-2, 3, m)
+    p = L.Problem.maxcut(n, u, v, w)
+    o = maxcut_problem(n, u, v, w)
+    info = p.info
+    assert info.kind == L.MAXCUT and info.n == n and info.m == n
+    assert info.nnz == 2 * m
+    assert info.weights == {"unit": 0, "cl": 0, "pm1": 1, "general": 2}[kind]
+    assert np.isclose(info.c_l1, o.c_l1, rtol=1e-12)
+    assert info.b_l1 == n and info.b_inf == 1.0
+    deg = np.bincount(np.concatenate([u, v]), minlength=n)
+    assert info.max_row_nnz == deg.max()
+
+
+def test_completion_constants_match_oracle():
+    i, j, Mij, _, _ = completion_instance(40, 30, 3, 6, seed=3)
+    p = L.Problem.completion(40, 30, i, j, Mij)
+    o = completion_problem(40, 30, i, j, Mij)
+    info = p.info
+    assert info.kind == L.COMPLETION and info.n == 70 and info.m == len(i)
+    assert np.isclose(info.b_l1, np.abs(o.b).sum()) and np.isclose(info.b_inf, np.abs(o.b).max())
+    assert np.isclose(info.c_l1, o.c_l1)
+
+
+def test_default_options_share_oracle_schedule():
+    o = L.default_options()
+    ref = OracleOptions()
+    for name in ["tol", "lbfgs_mem", "max_outer", "max_inner", "max_iter_total", "sigma_factor",
+                 "sigma_max_ratio", "feas_decrease", "eta0", "eta_factor", "eta_min"]:
+        assert getattr(o, name) == getattr(ref, name), name
+    assert o.sigma0 == ref.sigma0 == 0.0
+
+
+def test_workspace_validation():
+    u, v = erdos_renyi_edges(50, 100, 1)
+    p = L.Problem.maxcut(50, u, v)
+    with pytest.raises(L.LrsdpError):
+        L.workspace_bytes(p, L.default_options(rank=10, ld=10, prec=L.F32))   # 40 B rows
+    with pytest.raises(L.LrsdpError):
+        L.workspace_bytes(p, L.default_options(rank=10, ld=10, lbfgs_mem=9))
+    b4 = L.workspace_bytes(p, L.default_options(rank=10, ld=10, lbfgs_mem=4))
+    b2 = L.workspace_bytes(p, L.default_options(rank=10, ld=10, lbfgs_mem=2))
+    assert b4 > b2 >= (2 * 2 + 2) * 50 * 10 * 8
+
+
+def test_padded_ld():
+    assert L.padded_ld(20, L.F64) == 20 and L.padded_ld(26, L.F32) == 28 and L.padded_ld(10, L.F32) == 12
