@@ -23,7 +23,7 @@ import scipy.sparse.linalg as spla
 from .problem import SDPProblem
 
 
-def lambda_min(prob: SDPProblem, y: np.ndarray, dense_limit: int = 2500) -> float:
+def lambda_min(prob: SDPProblem, y: np.ndarray, dense_limit: int = 6000) -> float:
     S = (prob.C - prob.A_adj(y)).tocsr()
     if prob.n <= dense_limit:
         return float(sla.eigvalsh(S.toarray(), subset_by_index=[0, 0])[0])

@@ -102,23 +102,44 @@ __device__ __forceinline__ void block_sums_store(const double (&s)[K], double *o
     }
 }
 
-// Inside a single-block kernel: out[k] = sum_b part[b*stride + k], k < K,
-// b < nblk.  Fixed order (strided per thread, then a tree): deterministic.
-__device__ __forceinline__ void reduce_partials(const double *part, int nblk, int stride, int K,
-                                                double *out /* shared or global, K */) {
-    __shared__ double red[kBlock];
-    for (int k = 0; k < K; ++k) {
-        double t = 0.0;
-        for (int b = threadIdx.x; b < nblk; b += kBlock) t += part[(size_t)b * stride + k];
-        red[threadIdx.x] = t;
-        __syncthreads();
-        for (int h = kBlock / 2; h > 0; h >>= 1) {
-            if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) out[k] = red[0];
-        __syncthreads();
+// Inside a single-block kernel (blockDim.x == kBlock): out[k] = sum over rows b
+// < nrows of part[b * kMaxSums + k], k < K.  Each thread walks rows t, t+kBlock,
+// ... accumulating K sums, then a fixed wavefront/LDS tree: deterministic.
+// `out` is shared memory, valid for every thread on return.
+template <int K>
+__device__ __forceinline__ void reduce_rows(const double *part, int nrows, double *out) {
+    __shared__ double sh[kBlock / 64][K];
+    double acc[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] = 0.0;
+    for (int b = threadIdx.x; b < nrows; b += kBlock) {
+        const double *p = part + (size_t)b * kMaxSums;
+#pragma unroll
+        for (int k = 0; k < K; ++k) acc[k] += p[k];
     }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double v = wave_sum(acc[k]);
+        if (lane == 0) sh[wave][k] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < K) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) t += sh[w][threadIdx.x];
+        out[threadIdx.x] = t;
+    }
+    __syncthreads();
+}
+
+// Cooperative copy of a POD struct between global and shared memory.
+template <typename T>
+__device__ __forceinline__ void block_copy(T *dst, const T *src) {
+    static_assert(sizeof(T) % 8 == 0, "struct size must be a multiple of 8");
+    const uint64_t *s = reinterpret_cast<const uint64_t *>(src);
+    uint64_t *d = reinterpret_cast<uint64_t *>(dst);
+    for (int i = threadIdx.x; i < (int)(sizeof(T) / 8); i += blockDim.x) d[i] = s[i];
 }
 
 }  // namespace lrsdp

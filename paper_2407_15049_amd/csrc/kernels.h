@@ -55,7 +55,7 @@ struct SpmmArgs {
     const void *aux = nullptr;      // kEpiLS: C R rows for p1 (nullable)
     const double *ytil = nullptr;   // kEpiPlain: shift (nullable); kEpiLS: ytil
     double *y = nullptr;            // kEpiRefresh: multipliers
-    double *rn = nullptr;           // kEpiRefresh: ||R_i||^2 out (nullable)
+    double *rn = nullptr;           // kEpiRefresh / kEpiLS: ||R_i||^2 out (nullable)
     double sigma = 0.0;             // kEpiRefresh: y <- y - sigma (rn - 1) if > 0
     double *q1 = nullptr;           // kEpiLS: optional per-constraint outputs
     double *q2 = nullptr;

@@ -21,8 +21,9 @@ int launch_init_finalize(hipStream_t, SolverState *, const double *, int, int);
 int launch_alm_finalize(hipStream_t, SolverState *, const double *, int, int);
 int launch_reduce(hipStream_t, const double *, int, int, double *);
 int launch_cubic(hipStream_t, const double *, double *);
-int launch_update_maxcut(hipStream_t, int, SolverState *, void *, const void *, const double *, double *,
-                         void *const *, void *const *, int, int64_t, int64_t, double *, int *);
+int launch_update_maxcut(hipStream_t, int, SolverState *, void *, const void *, const double *, const double *,
+                         const double *, const double *, const double *, double *, void *const *, void *const *,
+                         int, int64_t, int64_t, double *, int *);
 int launch_combine(hipStream_t, int, SolverState *, const double *, const void *const *, int, void *, int64_t,
                    int64_t, double *, int *);
 int launch_grad_init_maxcut(hipStream_t, int, SolverState *, const void *, const void *, const double *,
@@ -164,7 +165,7 @@ extern "C" void lrsdp_options_default(lrsdp_options *o) {
 namespace {
 
 struct WsPlan {
-    size_t cd, gring[kMaxMem + 1], dring[kMaxMem], ytil, rn, total;
+    size_t cd, gring[kMaxMem + 1], dring[kMaxMem], ytil[2], rn, q1, q2, total;
 };
 
 int plan_workspace(const lrsdp_problem *p, const lrsdp_options *o, WsPlan *w) {
@@ -186,8 +187,11 @@ int plan_workspace(const lrsdp_problem *p, const lrsdp_options *o, WsPlan *w) {
     w->cd = take(arr);
     for (int g = 0; g <= o->lbfgs_mem; ++g) w->gring[g] = take(arr);
     for (int d = 0; d < o->lbfgs_mem; ++d) w->dring[d] = take(arr);
-    w->ytil = take((size_t)p->info.m * 8);
+    w->ytil[0] = take((size_t)p->info.m * 8);
+    w->ytil[1] = take((size_t)p->info.m * 8);
     w->rn = take((size_t)p->info.n * 8);
+    w->q1 = take((size_t)p->info.m * 8);
+    w->q2 = take((size_t)p->info.m * 8);
     w->total = off + 256;
     return LRSDP_OK;
 }
@@ -241,8 +245,10 @@ int solve_maxcut(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *w
     void *dring[kMaxMem] = {};
     for (int g = 0; g <= T; ++g) gring[g] = ws + w.gring[g];
     for (int d = 0; d < T; ++d) dring[d] = ws + w.dring[d];
-    double *ytil = reinterpret_cast<double *>(ws + w.ytil);
+    double *ytil[2] = {reinterpret_cast<double *>(ws + w.ytil[0]), reinterpret_cast<double *>(ws + w.ytil[1])};
     double *rn = reinterpret_cast<double *>(ws + w.rn);
+    double *q1 = reinterpret_cast<double *>(ws + w.q1);
+    double *q2 = reinterpret_cast<double *>(ws + w.q2);
     SolverState *st = at<SolverState>(c->scratch, kStateOff);
     double *part_ls = at<double>(c->scratch, kPartLsOff);
     double *part_cb = at<double>(c->scratch, kPartCbOff);
@@ -310,7 +316,8 @@ int solve_maxcut(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *w
     for (outer = 1; outer <= o->max_outer; ++outer) {
         // subproblem start: ytil, G_0, D_0 = -G_0
         int nb = 0, ncb = 0;
-        if ((rc = launch_grad_init_maxcut(s, prec, st, R, CD, y, rn, ytil, gring[0], n, ld, part_misc, &nb))) break;
+        if ((rc = launch_grad_init_maxcut(s, prec, st, R, CD, y, rn, ytil[0], gring[0], n, ld, part_misc, &nb)))
+            break;
         int64_t left = o->max_iter_total - total_inner;
         int k_limit = (int)std::min<int64_t>(o->max_inner, std::max<int64_t>(left, 0));
         if ((rc = launch_init_finalize(s, st, part_misc, nb, k_limit))) break;
@@ -325,7 +332,10 @@ int solve_maxcut(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *w
                 ls.V = dring[it % T];
                 ls.Y = CD;
                 ls.R = R;
-                ls.ytil = ytil;
+                ls.ytil = ytil[it % 2];
+                ls.q1 = q1;
+                ls.q2 = q2;
+                ls.rn = rn;
                 ls.ld = ld;
                 ls.partials = part_ls;
                 ls.st = st;
@@ -335,7 +345,8 @@ int solve_maxcut(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *w
                 if (o->profile) LRSDP_HIP_TRY(hipEventRecord(evs[2 * b + 1], s));
                 if ((rc = launch_ls_finalize(s, st, part_ls, nls, part_cb, ncb))) break;
                 int nup = 0;
-                if ((rc = launch_update_maxcut(s, prec, st, R, CD, y, ytil, gring, dring, T, n, ld, part_up, &nup)))
+                if ((rc = launch_update_maxcut(s, prec, st, R, CD, y, rn, q1, q2, ytil[it % 2], ytil[(it + 1) % 2],
+                                               gring, dring, T, n, ld, part_up, &nup)))
                     break;
                 if ((rc = launch_lbfgs_finalize(s, st, part_up, nup))) break;
                 if ((rc = launch_combine(s, prec, st, nullptr, basis, 2 * T + 1, nullptr, n, ld, part_cb, &ncb)))

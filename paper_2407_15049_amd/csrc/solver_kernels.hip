@@ -119,204 +119,224 @@ __host__ __device__ double exact_step(double a1, double a2, double a3, double a4
 }
 
 // ---------------------------------------------------------------------------
-// Two-loop recursion of Algorithm 1 on coefficient vectors.
-// Basis index of G slot g is g (0..T), of D slot d is T+1+d.  The current
-// gradient is G slot gk; pair it (k-nmem <= it < k) has D in slot
-// (dk - (k-it)) mod T and gradients G_it, G_{it+1} in slots
-// (gk - (k-it)) mod (T+1) and the next one.
+// Two-loop recursion of Algorithm 1 on coefficient vectors (one thread, on the
+// state copy in LDS).  Basis index of G slot g is g (0..T), of D slot d is
+// T+1+d.  The current gradient is G slot gk; pair it (k-nmem <= it < k) has
+// s_it = tau_it D_it with D_it in slot (dk - (k-it)) mod T, and
+// y_it = G_{it+1} - G_it with G_it in slot (gk - (k-it)) mod (T+1).  Each s_t
+// and y_t has one or two nonzero coefficients, so every inner product is a
+// row (or a difference of two rows) of the Gram matrix times q.
 // ---------------------------------------------------------------------------
-__device__ double gdot(const double *M, int NB, const double *u, const double *v) {
-    double s = 0.0;
-    for (int i = 0; i < NB; ++i) {
-        if (u[i] == 0.0) continue;
-        double t = 0.0;
-        for (int j = 0; j < NB; ++j) t += M[i * kMaxBasis + j] * v[j];
-        s += u[i] * t;
-    }
-    return s;
+__device__ double grow(const double *M, int i, int NB, const double *q) {
+    double t = 0.0;
+    for (int j = 0; j < NB; ++j) t += M[i * kMaxBasis + j] * q[j];
+    return t;
 }
 
-__device__ void two_loop_coef(SolverState *st) {
-    const int T = st->T, NB = 2 * T + 1, nmem = st->nmem, gk = st->gk, dk = st->dk;
-    const double *M = st->gram;
-    double q[kMaxBasis], sv[kMaxMem][kMaxBasis], yv[kMaxMem][kMaxBasis], alpha[kMaxMem], beta[kMaxMem];
+__device__ void two_loop_coef(SolverState &st) {
+    const int T = st.T, NB = 2 * T + 1, nmem = st.nmem, gk = st.gk, dk = st.dk;
+    const double *M = st.gram;
+    double q[kMaxBasis], alpha[kMaxMem], beta[kMaxMem];
+    int ds[kMaxMem], g0[kMaxMem], g1[kMaxMem];
+    double tau[kMaxMem];
     for (int j = 0; j < NB; ++j) q[j] = 0.0;
     q[gk] = -1.0;
     for (int t = 0; t < nmem; ++t) {  // t = 0 oldest
-        int back = nmem - t;              // k - it
-        int ds = ((dk - back) % T + T) % T;
-        int g0 = ((gk - back) % (T + 1) + (T + 1)) % (T + 1);
-        int g1 = (g0 + 1) % (T + 1);
-        for (int j = 0; j < NB; ++j) {
-            sv[t][j] = 0.0;
-            yv[t][j] = 0.0;
-        }
-        sv[t][T + 1 + ds] = st->taus[ds];
-        yv[t][g1] += 1.0;
-        yv[t][g0] -= 1.0;
-        beta[t] = 1.0 / gdot(M, NB, yv[t], sv[t]);
+        const int back = nmem - t;
+        ds[t] = T + 1 + ((dk - back) % T + T) % T;
+        g0[t] = ((gk - back) % (T + 1) + (T + 1)) % (T + 1);
+        g1[t] = (g0[t] + 1) % (T + 1);
+        tau[t] = st.taus[ds[t] - T - 1];
+        beta[t] = 1.0 / (tau[t] * (M[g1[t] * kMaxBasis + ds[t]] - M[g0[t] * kMaxBasis + ds[t]]));
     }
     for (int t = nmem - 1; t >= 0; --t) {
-        alpha[t] = beta[t] * gdot(M, NB, sv[t], q);
-        for (int j = 0; j < NB; ++j) q[j] -= alpha[t] * yv[t][j];
+        alpha[t] = beta[t] * tau[t] * grow(M, ds[t], NB, q);
+        q[g1[t]] -= alpha[t];
+        q[g0[t]] += alpha[t];
     }
     for (int t = 0; t < nmem; ++t) {
-        double c = alpha[t] - beta[t] * gdot(M, NB, yv[t], q);
-        for (int j = 0; j < NB; ++j) q[j] += c * sv[t][j];
+        const double yq = grow(M, g1[t], NB, q) - grow(M, g0[t], NB, q);
+        q[ds[t]] += (alpha[t] - beta[t] * yq) * tau[t];
     }
     // descent safeguard: <G_k, D> must be negative
-    double e[kMaxBasis];
-    for (int j = 0; j < NB; ++j) e[j] = 0.0;
-    e[gk] = 1.0;
-    double gd = gdot(M, NB, e, q);
-    if (!(gd < 0.0)) {
-        st->nmem = 0;
+    if (!(grow(M, gk, NB, q) < 0.0)) {
+        st.nmem = 0;
         for (int j = 0; j < NB; ++j) q[j] = 0.0;
         q[gk] = -1.0;
     }
-    for (int j = 0; j < kMaxBasis; ++j) st->coef[j] = j < NB ? q[j] : 0.0;
+    for (int j = 0; j < kMaxBasis; ++j) st.coef[j] = j < NB ? q[j] : 0.0;
 }
 
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// Single-workgroup kernels
+// Single-workgroup kernels.  Each stages the 3 KB state in LDS, reduces the
+// partial sums of the preceding grid kernel, runs its scalar logic in one
+// thread and writes the state back.
 // ---------------------------------------------------------------------------
 
 // Line-search stage: fold the previous combine pass's dots into the Gram
 // matrix, form a1..a4 and take the exact step.
-__global__ __launch_bounds__(kBlock) void k_ls_finalize(SolverState *st, const double *ls_part, int n_ls,
+__global__ __launch_bounds__(kBlock) void k_ls_finalize(SolverState *gst, const double *ls_part, int n_ls,
                                                         const double *cb_part, int n_cb) {
-    if (st->done) return;
+    __shared__ SolverState st;
     __shared__ double ls[kLsSums];
     __shared__ double cb[kMaxBasis + 1];
-    reduce_partials(ls_part, n_ls, kMaxSums, kLsSums, ls);
-    reduce_partials(cb_part, n_cb, kMaxSums, kMaxBasis + 1, cb);
-    if (threadIdx.x != 0) return;
-    const int T = st->T, NB = 2 * T + 1, dcol = T + 1 + st->dk;
-    double *M = st->gram;
-    for (int j = 0; j < NB; ++j) {
-        if (j == dcol) continue;
-        M[dcol * kMaxBasis + j] = cb[j];
-        M[j * kMaxBasis + dcol] = cb[j];
+    block_copy(&st, gst);
+    __syncthreads();
+    if (st.done) return;
+    reduce_rows<kLsSums>(ls_part, n_ls, ls);
+    reduce_rows<kMaxBasis + 1>(cb_part, n_cb, cb);
+    if (threadIdx.x == 0) {
+        const int T = st.T, NB = 2 * T + 1, dcol = T + 1 + st.dk;
+        double *M = st.gram;
+        for (int j = 0; j < NB; ++j) {
+            if (j == dcol) continue;
+            M[dcol * kMaxBasis + j] = cb[j];
+            M[j * kMaxBasis + dcol] = cb[j];
+        }
+        M[dcol * kMaxBasis + dcol] = cb[kMaxBasis];
+        const double sigma = st.sigma;
+        const double a1 = 0.5 * sigma * ls[3];
+        const double a2 = sigma * ls[4];
+        const double a3 = ls[0] - ls[1] + 0.5 * sigma * ls[5];
+        const double a4 = M[st.gk * kMaxBasis + dcol];
+        st.a[0] = a1;
+        st.a[1] = a2;
+        st.a[2] = a3;
+        st.a[3] = a4;
+        const bool finite = isfinite(a1) && isfinite(a2) && isfinite(a3) && isfinite(a4);
+        const double tau = finite ? exact_step(a1, a2, a3, a4) : 0.0;
+        if (!finite) st.numeric = 1;
+        st.tau = tau;
+        st.taus[st.dk] = tau;
+        if (!(tau > 0.0)) {
+            st.done = 3;
+            st.k += 1;
+            st.inner_total += 1;
+        }
     }
-    M[dcol * kMaxBasis + dcol] = cb[kMaxBasis];
-    const double sigma = st->sigma;
-    const double a1 = 0.5 * sigma * ls[3];
-    const double a2 = sigma * ls[4];
-    const double a3 = ls[0] - ls[1] + 0.5 * sigma * ls[5];
-    const double a4 = M[st->gk * kMaxBasis + dcol];
-    st->a[0] = a1;
-    st->a[1] = a2;
-    st->a[2] = a3;
-    st->a[3] = a4;
-    bool finite = isfinite(a1) && isfinite(a2) && isfinite(a3) && isfinite(a4);
-    double tau = finite ? exact_step(a1, a2, a3, a4) : 0.0;
-    if (!finite) st->numeric = 1;
-    st->tau = tau;
-    st->taus[st->dk] = tau;
-    if (!(tau > 0.0)) {
-        st->done = 3;
-        st->k += 1;
-        st->inner_total += 1;
-    }
+    __syncthreads();
+    block_copy(gst, &st);
 }
 
 // L-BFGS stage: fold the update pass's dots (new gradient) into the Gram
 // matrix, apply the curvature guard to the new pair, advance the rings and
 // compute the next direction's coefficients.
-__global__ __launch_bounds__(kBlock) void k_lbfgs_finalize(SolverState *st, const double *up_part, int n_up) {
-    if (st->done) return;
+__global__ __launch_bounds__(kBlock) void k_lbfgs_finalize(SolverState *gst, const double *up_part, int n_up) {
+    __shared__ SolverState st;
     __shared__ double raw[kMaxBasis];
-    reduce_partials(up_part, n_up, kMaxSums, kMaxBasis, raw);
-    if (threadIdx.x != 0) return;
-    const int T = st->T, NB = 2 * T + 1;
-    double us[kMaxBasis];
-    for (int j = 0; j < NB; ++j) us[j] = j <= T ? raw[j] : raw[kMaxMem + 1 + (j - T - 1)];
-    const int gk = st->gk, gk1 = (gk + 1) % (T + 1), ds = T + 1 + st->dk;
-    double *M = st->gram;
-    for (int j = 0; j < NB; ++j) {
-        M[gk1 * kMaxBasis + j] = us[j];
-        M[j * kMaxBasis + gk1] = us[j];
+    block_copy(&st, gst);
+    __syncthreads();
+    if (st.done) return;
+    reduce_rows<kMaxBasis>(up_part, n_up, raw);
+    if (threadIdx.x == 0) {
+        const int T = st.T, NB = 2 * T + 1;
+        const int gk = st.gk, gk1 = (gk + 1) % (T + 1), ds = T + 1 + st.dk;
+        double *M = st.gram;
+        for (int j = 0; j < NB; ++j) {
+            const double v = j <= T ? raw[j] : raw[kMaxMem + 1 + (j - T - 1)];
+            M[gk1 * kMaxBasis + j] = v;
+            M[j * kMaxBasis + gk1] = v;
+        }
+        const double tau = st.tau;
+        const double ys = tau * (M[gk1 * kMaxBasis + ds] - M[gk * kMaxBasis + ds]);
+        const double yy = M[gk1 * kMaxBasis + gk1] - 2.0 * M[gk1 * kMaxBasis + gk] + M[gk * kMaxBasis + gk];
+        const double ss = tau * tau * M[ds * kMaxBasis + ds];
+        if (ys > 1e-12 * sqrt(fabs(yy * ss))) st.nmem = min(st.nmem + 1, T);
+        else st.nmem = 0;
+        st.k += 1;
+        st.inner_total += 1;
+        st.gk = gk1;
+        st.dk = (st.dk + 1) % T;
+        const double g2 = M[gk1 * kMaxBasis + gk1];
+        st.gnorm = sqrt(fmax(g2, 0.0));
+        if (!isfinite(g2)) {
+            st.numeric = 1;
+            st.done = 3;
+        } else if (st.gnorm <= st.target) {
+            st.done = 1;
+        } else if (st.k >= st.max_inner) {
+            st.done = 2;
+        } else {
+            two_loop_coef(st);
+        }
     }
-    const double tau = st->tau;
-    const double ys = tau * (M[gk1 * kMaxBasis + ds] - M[gk * kMaxBasis + ds]);
-    const double yy = M[gk1 * kMaxBasis + gk1] - 2.0 * M[gk1 * kMaxBasis + gk] + M[gk * kMaxBasis + gk];
-    const double ss = tau * tau * M[ds * kMaxBasis + ds];
-    if (ys > 1e-12 * sqrt(fabs(yy * ss))) st->nmem = min(st->nmem + 1, T);
-    else st->nmem = 0;
-    st->k += 1;
-    st->inner_total += 1;
-    st->gk = gk1;
-    st->dk = (st->dk + 1) % T;
-    const double g2 = M[gk1 * kMaxBasis + gk1];
-    st->gnorm = sqrt(fmax(g2, 0.0));
-    if (!isfinite(g2)) {
-        st->numeric = 1;
-        st->done = 3;
-        return;
-    }
-    if (st->gnorm <= st->target) st->done = 1;
-    else if (st->k >= st->max_inner) st->done = 2;
-    else two_loop_coef(st);
+    __syncthreads();
+    block_copy(gst, &st);
 }
 
 // Start of a subproblem: gradient norm known, empty memory, D = -G.
-__global__ __launch_bounds__(kBlock) void k_init_finalize(SolverState *st, const double *part, int n_part,
+__global__ __launch_bounds__(kBlock) void k_init_finalize(SolverState *gst, const double *part, int n_part,
                                                           int k_limit) {
+    __shared__ SolverState st;
     __shared__ double g2[1];
-    reduce_partials(part, n_part, kMaxSums, 1, g2);
-    if (threadIdx.x != 0) return;
-    for (int j = 0; j < kMaxBasis * kMaxBasis; ++j) st->gram[j] = 0.0;
-    st->gram[0] = g2[0];
-    st->gk = 0;
-    st->dk = 0;
-    st->k = 0;
-    st->nmem = 0;
-    st->max_inner = k_limit;
-    st->gnorm = sqrt(fmax(g2[0], 0.0));
-    st->target = st->eta * fmax(1.0, st->gnorm);
-    for (int j = 0; j < kMaxBasis; ++j) st->coef[j] = 0.0;
-    st->coef[0] = -1.0;
-    st->done = 0;
-    if (!isfinite(g2[0])) {
-        st->numeric = 1;
-        st->done = 3;
-    } else if (st->gnorm <= st->target) {
-        st->done = 1;
-    } else if (k_limit <= 0) {
-        st->done = 2;
+    block_copy(&st, gst);
+    reduce_rows<1>(part, n_part, g2);
+    if (threadIdx.x == 0) {
+        for (int j = 0; j < kMaxBasis * kMaxBasis; ++j) st.gram[j] = 0.0;
+        st.gram[0] = g2[0];
+        st.gk = 0;
+        st.dk = 0;
+        st.k = 0;
+        st.nmem = 0;
+        st.max_inner = k_limit;
+        st.gnorm = sqrt(fmax(g2[0], 0.0));
+        st.target = st.eta * fmax(1.0, st.gnorm);
+        for (int j = 0; j < kMaxBasis; ++j) st.coef[j] = 0.0;
+        st.coef[0] = -1.0;
+        st.done = 0;
+        if (!isfinite(g2[0])) {
+            st.numeric = 1;
+            st.done = 3;
+        } else if (st.gnorm <= st.target) {
+            st.done = 1;
+        } else if (k_limit <= 0) {
+            st.done = 2;
+        }
     }
+    __syncthreads();
+    block_copy(gst, &st);
 }
 
 // ALM step: measures after the multiplier update, stop test, penalty and
 // inner-tolerance schedules.  mode 0: initial point (no schedule update).
-__global__ __launch_bounds__(kBlock) void k_alm_finalize(SolverState *st, const double *part, int n_part,
+__global__ __launch_bounds__(kBlock) void k_alm_finalize(SolverState *gst, const double *part, int n_part,
                                                          int mode) {
+    __shared__ SolverState st;
     __shared__ double rs[3];
-    reduce_partials(part, n_part, kMaxSums, 3, rs);
-    if (threadIdx.x != 0) return;
-    const double obj = rs[0], dual = rs[1];
-    const double res_norm = sqrt(fmax(rs[2], 0.0));
-    st->obj = obj;
-    st->dual = dual;
-    st->res_norm = res_norm;
-    st->err1 = res_norm / (1.0 + st->b_l1);
-    st->err1_inf = res_norm / (1.0 + st->b_inf);
-    st->err3 = (obj - dual) / (1.0 + fabs(obj) + fabs(dual));
-    if (!isfinite(obj) || !isfinite(dual) || !isfinite(res_norm)) st->numeric = 1;
-    st->refreshes += 1;
-    if (mode == 0) return;
-    st->converged = (st->err1 <= st->tol && fabs(st->err3) <= st->tol) ? 1 : 0;
-    if (st->converged) return;
-    if (st->err1 > st->feas_decrease * st->err1_prev) st->sigma = fmin(st->sigma * st->sigma_factor, st->sigma_cap);
-    st->err1_prev = st->err1;
-    st->eta = fmax(st->eta * st->eta_factor, st->eta_min);
+    block_copy(&st, gst);
+    reduce_rows<3>(part, n_part, rs);
+    if (threadIdx.x == 0) {
+        const double obj = rs[0], dual = rs[1];
+        const double res_norm = sqrt(fmax(rs[2], 0.0));
+        st.obj = obj;
+        st.dual = dual;
+        st.res_norm = res_norm;
+        st.err1 = res_norm / (1.0 + st.b_l1);
+        st.err1_inf = res_norm / (1.0 + st.b_inf);
+        st.err3 = (obj - dual) / (1.0 + fabs(obj) + fabs(dual));
+        if (!isfinite(obj) || !isfinite(dual) || !isfinite(res_norm)) st.numeric = 1;
+        st.refreshes += 1;
+        if (mode != 0) {
+            st.converged = (st.err1 <= st.tol && fabs(st.err3) <= st.tol) ? 1 : 0;
+            if (!st.converged) {
+                if (st.err1 > st.feas_decrease * st.err1_prev)
+                    st.sigma = fmin(st.sigma * st.sigma_factor, st.sigma_cap);
+                st.err1_prev = st.err1;
+                st.eta = fmax(st.eta * st.eta_factor, st.eta_min);
+            }
+        }
+    }
+    __syncthreads();
+    block_copy(gst, &st);
 }
 
-// Generic reduction of one partials set into out (device), K sums.
-__global__ __launch_bounds__(kBlock) void k_reduce(const double *part, int n_part, int K, double *out) {
-    reduce_partials(part, n_part, kMaxSums, K, out);
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_reduce(const double *part, int n_part, double *out) {
+    __shared__ double r[K];
+    reduce_rows<K>(part, n_part, r);
+    if (threadIdx.x < K) out[threadIdx.x] = r[threadIdx.x];
 }
 
 __global__ void k_cubic(const double *a, double *tau) {
@@ -333,88 +353,84 @@ struct UpdateArgs {
     S *R;
     const S *CD;
     const double *y;
-    double *ytil;
+    const double *rn;        // ||R_i||^2 of the current R (SpMM epilogue)
+    const double *q1;        // 2 R_i . D_i
+    const double *q2;        // ||D_i||^2
+    const double *ytil_in;   // multiplier estimate used for the current G
+    double *ytil_out;        // multiplier estimate of the new R
     Rings<S> rings;
-    int64_t n, ld;
+    int64_t nchunks;         // n * chunks per row
+    int cpr;                 // 16-byte chunks per row
     double *partials;
 };
 
-// MaxCut update sweep for step tau along D_k:
-//   R <- R + tau D,  ytil_i <- y_i + sigma (1 - ||R_i||^2),
+// MaxCut update sweep for step tau along D_k (one thread per 16-byte chunk):
+//   R <- R + tau D,
+//   ||R_new,i||^2 = ||R_i||^2 + tau q1_i + tau^2 q2_i,
+//   ytil_i <- y_i + sigma (1 - ||R_new,i||^2),
 //   G_{k+1} = 2 (C R_new - ytil_new o R_new) with C R_new = C R + tau C D and
 //   C R = G_k/2 + ytil_old o R_old (so C R need not be stored),
 // and the dot products of G_{k+1} with every ring slot (partials layout: G slot
 // g at g, D slot d at kMaxMem + 1 + d).
-template <typename S, int GS>
+template <typename S>
 __global__ __launch_bounds__(kBlock) void k_update_maxcut(UpdateArgs<S> a) {
     using CV = typename Chunk<S>::V;
-    constexpr int NV = Chunk<S>::N;
-    constexpr int GPB = kBlock / GS;
     SolverState *st = a.st;
     if (st->done) return;
     const double tau = st->tau, sigma = st->sigma;
     const int T = st->T, gk = st->gk, gk1 = (gk + 1) % (T + 1), dk = st->dk;
-    const int lane = threadIdx.x % GS, grp = threadIdx.x / GS;
-    const bool active = lane * NV < a.ld;
-    const CV zero = vzero(CV{});
     double s[kMaxBasis];
 #pragma unroll
     for (int j = 0; j < kMaxBasis; ++j) s[j] = 0.0;
-    // ring pointers of the dynamic slots, selected with static indices
-    const S *D = nullptr;
-    const S *Go = nullptr;
-    S *Gn = nullptr;
+    const CV *D = nullptr;
+    const CV *Go = nullptr;
+    CV *Gn = nullptr;
 #pragma unroll
     for (int g = 0; g <= kMaxMem; ++g) {
-        if (g == gk) Go = a.rings.g[g];
-        if (g == gk1) Gn = a.rings.g[g];
+        if (g == gk) Go = reinterpret_cast<const CV *>(a.rings.g[g]);
+        if (g == gk1) Gn = reinterpret_cast<CV *>(a.rings.g[g]);
     }
 #pragma unroll
     for (int d = 0; d < kMaxMem; ++d)
-        if (d == dk) D = a.rings.d[d];
-    for (int64_t row = (int64_t)blockIdx.x * GPB + grp; row < a.n; row += (int64_t)gridDim.x * GPB) {
-        const int64_t off = row * a.ld + lane * NV;
-        CV r = zero, d = zero, cd = zero, go = zero;
-        if (active) {
-            r = *reinterpret_cast<const CV *>(a.R + off);
-            d = *reinterpret_cast<const CV *>(D + off);
-            cd = *reinterpret_cast<const CV *>(a.CD + off);
-            go = *reinterpret_cast<const CV *>(Go + off);
-        }
-        const double yold = a.ytil[row], yi = a.y[row];
-        D4 R0 = widen(r), Dd = widen(d), CDd = widen(cd), G0 = widen(go), Rn;
+        if (d == dk) D = reinterpret_cast<const CV *>(a.rings.d[d]);
+    CV *R = reinterpret_cast<CV *>(a.R);
+    const CV *CD = reinterpret_cast<const CV *>(a.CD);
+    for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < a.nchunks; c += (int64_t)gridDim.x * kBlock) {
+        const int64_t row = c / a.cpr;
+        const CV r = R[c], d = D[c], cd = CD[c], go = Go[c];
+        const double yold = a.ytil_in[row];
+        const double rnn = a.rn[row] + tau * (a.q1[row] + tau * a.q2[row]);
+        const double ynew = a.y[row] + sigma * (1.0 - rnn);
+        const D4 R0 = widen(r), Dd = widen(d), CDd = widen(cd), G0 = widen(go);
+        D4 Rn;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) Rn.v[c] = fma(tau, Dd.v[c], R0.v[c]);
+        for (int e = 0; e < 4; ++e) Rn.v[e] = fma(tau, Dd.v[e], R0.v[e]);
         CV rn_s;
         narrow(Rn, rn_s);
         Rn = widen(rn_s);
-        const double rn = group_sum<GS>(vdot(rn_s, rn_s));
-        const double ynew = yi + sigma * (1.0 - rn);
         D4 Gv;
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
-            Gv.v[c] = G0.v[c] + 2.0 * tau * CDd.v[c] + 2.0 * yold * R0.v[c] - 2.0 * ynew * Rn.v[c];
+        for (int e = 0; e < 4; ++e)
+            Gv.v[e] = G0.v[e] + 2.0 * tau * CDd.v[e] + 2.0 * yold * R0.v[e] - 2.0 * ynew * Rn.v[e];
         CV gn_s;
         narrow(Gv, gn_s);
-        if (active) {
-            *reinterpret_cast<CV *>(a.R + off) = rn_s;
-            *reinterpret_cast<CV *>(Gn + off) = gn_s;
-        }
-        if (lane == 0) a.ytil[row] = ynew;
+        R[c] = rn_s;
+        Gn[c] = gn_s;
+        if (c - row * a.cpr == 0) a.ytil_out[row] = ynew;
 #pragma unroll
         for (int g = 0; g <= kMaxMem; ++g) {
             if (g <= T) {
                 CV b;
                 if (g == gk1) b = gn_s;
                 else if (g == gk) b = go;
-                else b = active ? *reinterpret_cast<const CV *>(a.rings.g[g] + off) : zero;
+                else b = reinterpret_cast<const CV *>(a.rings.g[g])[c];
                 s[g] += vdot(gn_s, b);
             }
         }
 #pragma unroll
         for (int dd = 0; dd < kMaxMem; ++dd) {
             if (dd < T) {
-                CV b = (dd == dk) ? d : (active ? *reinterpret_cast<const CV *>(a.rings.d[dd] + off) : zero);
+                const CV b = (dd == dk) ? d : reinterpret_cast<const CV *>(a.rings.d[dd])[c];
                 s[kMaxMem + 1 + dd] += vdot(gn_s, b);
             }
         }
@@ -586,7 +602,15 @@ int launch_alm_finalize(hipStream_t s, SolverState *st, const double *part, int 
 }
 
 int launch_reduce(hipStream_t s, const double *part, int np, int K, double *out) {
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, s, part, np, K, out);
+    switch (K) {
+#define LRSDP_RED(k) \
+    case k: hipLaunchKernelGGL(k_reduce<k>, dim3(1), dim3(kBlock), 0, s, part, np, out); break;
+        LRSDP_RED(1) LRSDP_RED(2) LRSDP_RED(3) LRSDP_RED(4) LRSDP_RED(5) LRSDP_RED(6) LRSDP_RED(7)
+        LRSDP_RED(8) LRSDP_RED(9) LRSDP_RED(10) LRSDP_RED(11) LRSDP_RED(12) LRSDP_RED(13) LRSDP_RED(14)
+        LRSDP_RED(15) LRSDP_RED(16) LRSDP_RED(17) LRSDP_RED(18)
+#undef LRSDP_RED
+        default: return set_error(LRSDP_EINVAL, "reduction width %d unsupported", K);
+    }
     LRSDP_CHECK_LAUNCH();
     return LRSDP_OK;
 }
@@ -597,36 +621,28 @@ int launch_cubic(hipStream_t s, const double *a, double *tau) {
     return LRSDP_OK;
 }
 
-template <typename S>
-static int update_t(hipStream_t s, const UpdateArgs<S> &a, int cpr, int *nb) {
-    if (cpr <= 4) {
-        *nb = grid_for(a.n, kBlock / 4);
-        hipLaunchKernelGGL((k_update_maxcut<S, 4>), dim3(*nb), dim3(kBlock), 0, s, a);
-    } else if (cpr <= 8) {
-        *nb = grid_for(a.n, kBlock / 8);
-        hipLaunchKernelGGL((k_update_maxcut<S, 8>), dim3(*nb), dim3(kBlock), 0, s, a);
+int launch_update_maxcut(hipStream_t s, int prec, SolverState *st, void *R, const void *CD, const double *y,
+                         const double *rn, const double *q1, const double *q2, const double *ytil_in,
+                         double *ytil_out, void *const *gring, void *const *dring, int T, int64_t n, int64_t ld,
+                         double *partials, int *nb) {
+    const int cpr = chunks_per_row(prec, ld);
+    const int64_t nch = n * cpr;
+    *nb = grid_for(nch, kBlock);
+    if (prec == LRSDP_F64) {
+        UpdateArgs<double> a{st, (double *)R, (const double *)CD, y, rn, q1, q2, ytil_in, ytil_out, {}, nch, cpr,
+                             partials};
+        for (int g = 0; g <= T; ++g) a.rings.g[g] = (double *)gring[g];
+        for (int d = 0; d < T; ++d) a.rings.d[d] = (double *)dring[d];
+        hipLaunchKernelGGL(k_update_maxcut<double>, dim3(*nb), dim3(kBlock), 0, s, a);
     } else {
-        *nb = grid_for(a.n, kBlock / 16);
-        hipLaunchKernelGGL((k_update_maxcut<S, 16>), dim3(*nb), dim3(kBlock), 0, s, a);
+        UpdateArgs<float> a{st, (float *)R, (const float *)CD, y, rn, q1, q2, ytil_in, ytil_out, {}, nch, cpr,
+                            partials};
+        for (int g = 0; g <= T; ++g) a.rings.g[g] = (float *)gring[g];
+        for (int d = 0; d < T; ++d) a.rings.d[d] = (float *)dring[d];
+        hipLaunchKernelGGL(k_update_maxcut<float>, dim3(*nb), dim3(kBlock), 0, s, a);
     }
     LRSDP_CHECK_LAUNCH();
     return LRSDP_OK;
-}
-
-int launch_update_maxcut(hipStream_t s, int prec, SolverState *st, void *R, const void *CD, const double *y,
-                         double *ytil, void *const *gring, void *const *dring, int T, int64_t n, int64_t ld,
-                         double *partials, int *nb) {
-    const int cpr = chunks_per_row(prec, ld);
-    if (prec == LRSDP_F64) {
-        UpdateArgs<double> a{st, (double *)R, (const double *)CD, y, ytil, {}, n, ld, partials};
-        for (int g = 0; g <= T; ++g) a.rings.g[g] = (double *)gring[g];
-        for (int d = 0; d < T; ++d) a.rings.d[d] = (double *)dring[d];
-        return update_t(s, a, cpr, nb);
-    }
-    UpdateArgs<float> a{st, (float *)R, (const float *)CD, y, ytil, {}, n, ld, partials};
-    for (int g = 0; g <= T; ++g) a.rings.g[g] = (float *)gring[g];
-    for (int d = 0; d < T; ++d) a.rings.d[d] = (float *)dring[d];
-    return update_t(s, a, cpr, nb);
 }
 
 // basis: nb device arrays of n*ld elements; out = sum coef_j basis_j.

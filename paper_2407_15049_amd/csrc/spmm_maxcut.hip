@@ -19,7 +19,8 @@
 //      kEpiLS       CD_i = (C D)_i, plus the row terms of the exact line search
 //                   (appendix A.2) for MaxCut: p2_i = CD_i.D_i, q1_i = 2 R_i.D_i,
 //                   q2_i = ||D_i||^2, summed as p2, ytil.q2, ytil.q1, q2.q2,
-//                   q1.q2, q1.q1 and (optionally) p1 = 2 sum CR_i.D_i
+//                   q1.q2, q1.q1 and (optionally) p1 = 2 sum CR_i.D_i; optionally
+//                   stores q1_i, q2_i and ||R_i||^2 per row
 //      kEpiRefresh  CR_i = (C R)_i, obj_i = R_i.CR_i, res_i = ||R_i||^2 - 1,
 //                   optional multiplier step y_i <- y_i - sigma res_i; sums
 //                   obj, b^T y, ||res||^2
@@ -99,6 +100,7 @@ __device__ __forceinline__ void epilogue(const DevCsr &P, const SpmmArgs &a, int
         double p2 = group_sum<GS>(vdot(acc, d));
         double q1 = 2.0 * group_sum<GS>(vdot(r, d));
         double q2 = group_sum<GS>(vdot(d, d));
+        double rr = a.rn ? group_sum<GS>(vdot(r, r)) : 0.0;
         double p1 = 0.0;
         if (a.aux) {
             const CV cr = active ? *reinterpret_cast<const CV *>((const S *)a.aux + off) : zero;
@@ -115,6 +117,7 @@ __device__ __forceinline__ void epilogue(const DevCsr &P, const SpmmArgs &a, int
             s[6] += p1;
             if (a.q1) a.q1[row] = q1;
             if (a.q2) a.q2[row] = q2;
+            if (a.rn) a.rn[row] = rr;
         }
     } else {  // kEpiRefresh: V = R
         const CV r = active ? *reinterpret_cast<const CV *>((const S *)a.V + off) : zero;
