@@ -202,7 +202,9 @@ int lrsdp_solve(lrsdp_ctx *ctx, lrsdp_problem *prob, const lrsdp_options *opts,
  */
 
 /* Y = (C - A*(ytil)) V  (eq. At of Section 3.4); ytil (m float64) may be NULL
- * (then Y = C V).  Y must not alias V. */
+ * (then Y = C V).  Y must not alias V.  With prec = LRSDP_F32_BF16IN (MaxCut
+ * only) V is bfloat16 with row stride ld rounded up to a multiple of 8 and Y
+ * is float32 with row stride ld; products accumulate in float32. */
 int lrsdp_k_spmm(lrsdp_ctx *ctx, const lrsdp_problem *prob, int prec,
                  const void *V, int64_t ld, const double *ytil, void *Y);
 
@@ -215,8 +217,8 @@ int lrsdp_k_constraint(lrsdp_ctx *ctx, const lrsdp_problem *prob, int prec,
 /* Exact line-search coefficients of appendix A.2 for direction D at R with
  * multipliers y and penalty sigma.  out (device, 8 float64) receives
  * {a1, a2, a3, a4, p1, p2, ||q1||^2, ||q2||^2}; q1, q2 (device, m float64) may
- * be NULL or receive A(RD^T + DR^T) and A(DD^T).  `work` is a device n x ld
- * array of the element type (scratch for C R and C D; 2 arrays). */
+ * be NULL or receive A(RD^T + DR^T) and A(DD^T).  `work` is device scratch of
+ * at least 2*n*ld*(element bytes) + 16*m bytes. */
 int lrsdp_k_ls_coeffs(lrsdp_ctx *ctx, const lrsdp_problem *prob, int prec,
                       const void *R, const void *D, int64_t ld,
                       const double *y, double sigma, void *work,
@@ -232,7 +234,8 @@ int lrsdp_k_cubic(lrsdp_ctx *ctx, const double *a, double *tau);
  * experimental setting): y <- y + sigma (b - A(RR^T)) when sigma > 0 (y left
  * unchanged when sigma == 0), then out (device, 8 float64) =
  * {obj, dual = b^T y, ||A(RR^T) - b||_2, err1, err1_inf, err3, 0, 0}.
- * `work` is a device n x ld scratch array of the element type. */
+ * `work` is device scratch of at least max(n*ld*(element bytes), 8*m) bytes
+ * (MaxCut: receives C R; completion: receives A(RR^T)). */
 int lrsdp_k_alm(lrsdp_ctx *ctx, const lrsdp_problem *prob, int prec,
                 const void *R, int64_t ld, double *y, double sigma, void *work,
                 double *out);

@@ -50,6 +50,20 @@ __global__ void k_ls_out(const double *s, double sigma, double *out) {
     out[7] = s[3];
 }
 
+// completion: sums {0, ytil.q2, ytil.q1, q2.q2, q1.q2, q1.q1, 0} and d = {<D,R>, <D,D>}
+__global__ void k_ls_out_cmp(const double *s, const double *d, double sigma, double *out) {
+    if (threadIdx.x != 0) return;
+    const double p1 = 2.0 * d[0], p2 = d[1];
+    out[0] = 0.5 * sigma * s[3];
+    out[1] = sigma * s[4];
+    out[2] = p2 - s[1] + 0.5 * sigma * s[5];
+    out[3] = p1 - s[2];
+    out[4] = p1;
+    out[5] = p2;
+    out[6] = s[5];
+    out[7] = s[3];
+}
+
 // out = {obj, dual, ||res||, err1, err1_inf, err3, 0, 0} from {obj, b.y, ||res||^2}
 __global__ void k_alm_out(const double *s, double b_l1, double b_inf, double *out) {
     if (threadIdx.x != 0) return;
@@ -131,6 +145,12 @@ int launch_ytil(hipStream_t s, const double *y, const double *a, const double *b
 
 int launch_ls_out(hipStream_t s, const double *sums, double sigma, double *out) {
     hipLaunchKernelGGL(k_ls_out, dim3(1), dim3(64), 0, s, sums, sigma, out);
+    LRSDP_CHECK_LAUNCH();
+    return LRSDP_OK;
+}
+
+int launch_ls_out_cmp(hipStream_t s, const double *sums, const double *d, double sigma, double *out) {
+    hipLaunchKernelGGL(k_ls_out_cmp, dim3(1), dim3(64), 0, s, sums, d, sigma, out);
     LRSDP_CHECK_LAUNCH();
     return LRSDP_OK;
 }

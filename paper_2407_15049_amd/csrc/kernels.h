@@ -49,7 +49,9 @@ enum EpiKind { kEpiPlain = 0, kEpiLS = 1, kEpiRefresh = 2 };
 // Arguments of one SpMM Y = C V (+ epilogue).  See spmm_maxcut.hip.
 struct SpmmArgs {
     int epi = kEpiPlain;
-    const void *V = nullptr;        // gathered operand
+    const void *V = nullptr;        // gathered operand (bfloat16 for LRSDP_F32_BF16IN)
+    const void *Vown = nullptr;     // kEpiLS with bfloat16 input: float32 copy of V
+    int64_t ldv = 0;                // row stride of V (set by spmm_maxcut)
     void *Y = nullptr;              // output rows (C V, shifted for kEpiPlain)
     const void *R = nullptr;        // kEpiLS: R rows
     const void *aux = nullptr;      // kEpiLS: C R rows for p1 (nullable)
@@ -70,6 +72,10 @@ int spmm_maxcut(hipStream_t s, const DevCsr &P, int prec, const SpmmArgs &a, int
 // Completion SpMM Y = (I - A*(ytil)) V and SDDMMs.
 int spmm_completion(hipStream_t s, const DevCompletion &P, int prec, const void *V, int64_t ld,
                     const double *ytil, void *Y);
+
+// Row stride (elements) of the bfloat16 copy of an n x ld float32 array:
+// ld rounded up to a multiple of 8 (16-byte rows).
+inline int64_t bf16_ld(int64_t ld) { return (ld + 7) / 8 * 8; }
 
 // number of sums per partial row of each stage
 constexpr int kLsSums = 8;

@@ -15,7 +15,7 @@
 
 namespace lrsdp {
 
-int launch_ls_finalize(hipStream_t, SolverState *, const double *, int, const double *, int);
+int launch_ls_finalize(hipStream_t, SolverState *, const double *, int, const double *, int, int);
 int launch_lbfgs_finalize(hipStream_t, SolverState *, const double *, int);
 int launch_init_finalize(hipStream_t, SolverState *, const double *, int, int);
 int launch_alm_finalize(hipStream_t, SolverState *, const double *, int, int);
@@ -25,7 +25,7 @@ int launch_update_maxcut(hipStream_t, int, SolverState *, void *, const void *, 
                          const double *, const double *, const double *, double *, void *const *, void *const *,
                          int, int64_t, int64_t, double *, int *);
 int launch_combine(hipStream_t, int, SolverState *, const double *, const void *const *, int, void *, int64_t,
-                   int64_t, double *, int *);
+                   int64_t, double *, int *, uint16_t *);
 int launch_grad_init_maxcut(hipStream_t, int, SolverState *, const void *, const void *, const double *,
                             const double *, double *, void *, int64_t, int64_t, double *, int *);
 int launch_fill(hipStream_t, int, void *, int64_t);
@@ -36,6 +36,16 @@ int launch_ls_out(hipStream_t, const double *, double, double *);
 int launch_alm_out(hipStream_t, const double *, double, double, double *);
 int launch_two_loop_pairs(hipStream_t, const double *, int, double *, int *);
 int launch_gather_gram(hipStream_t, const double *, int, int, double *);
+int launch_ls_out_cmp(hipStream_t, const double *, const double *, double, double *);
+int cmp_grad(hipStream_t, const DevCompletion &, int, const SolverState *, const void *, const double *,
+             void *const *, void *const *, int, int64_t, double *, int, int *);
+int cmp_sddmm(hipStream_t, const DevCompletion &, int, int, const void *, const void *, int64_t, double *, double *,
+              double *, const double *, double *, double, double *, const SolverState *, int *);
+int cmp_samples(hipStream_t, const DevCompletion &, const SolverState *, double *, const double *, const double *,
+                const double *, double *);
+int cmp_ytil(hipStream_t, const DevCompletion &, const SolverState *, double, const double *, const double *,
+             double *);
+int axpy_state(hipStream_t, int, const SolverState *, void *, const void *, int64_t, int64_t);
 
 namespace {
 
@@ -85,6 +95,14 @@ double maxcut_spmm_bytes(const lrsdp_problem *p, int prec, int r) {
     double b = 4.0 * n + 4.0 * (n + 1) + 4.0 * nnz + 16.0 * n + 3.0 * n * r * w;
     if (p->info.weights == kWGeneral) b += 8.0 * nnz;
     return b;
+}
+
+// Algorithmic bytes of one completion gradient SpMM launch: row pointers, per
+// entry partner index + sample id + ytil, R read, G written, and the 2T ring
+// slots read for the dot products.
+double completion_grad_bytes(const lrsdp_problem *p, int prec, int r, int T) {
+    const double n = (double)p->info.n, m = (double)p->info.m, w = elem_size(prec);
+    return 4.0 * (n + 2) + 2.0 * m * 16.0 + (2.0 + 2.0 * T) * n * r * w;
 }
 
 }  // namespace
@@ -165,7 +183,7 @@ extern "C" void lrsdp_options_default(lrsdp_options *o) {
 namespace {
 
 struct WsPlan {
-    size_t cd, gring[kMaxMem + 1], dring[kMaxMem], ytil[2], rn, q1, q2, total;
+    size_t cd, gring[kMaxMem + 1], dring[kMaxMem], ytil[2], rn, q1, q2, acon, shadow, total;
 };
 
 int plan_workspace(const lrsdp_problem *p, const lrsdp_options *o, WsPlan *w) {
@@ -192,6 +210,8 @@ int plan_workspace(const lrsdp_problem *p, const lrsdp_options *o, WsPlan *w) {
     w->rn = take((size_t)p->info.n * 8);
     w->q1 = take((size_t)p->info.m * 8);
     w->q2 = take((size_t)p->info.m * 8);
+    w->acon = take((size_t)p->info.m * 8);
+    w->shadow = take(o->prec == LRSDP_F32_BF16IN ? (size_t)p->info.n * bf16_ld(o->ld) * 2 : 0);
     w->total = off + 256;
     return LRSDP_OK;
 }
@@ -229,8 +249,9 @@ int write_state(lrsdp_ctx *c, const SolverState &h) {
     return LRSDP_OK;
 }
 
-int solve_maxcut(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws, void *R, double *y,
-                 lrsdp_result *res) {
+int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws, void *R, double *y,
+               lrsdp_result *res) {
+    const bool mc = p->info.kind == LRSDP_MAXCUT;
     const auto t0 = std::chrono::steady_clock::now();
     auto elapsed = [&]() { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); };
     const int prec = o->prec == LRSDP_F64 ? LRSDP_F64 : LRSDP_F32;
@@ -249,6 +270,9 @@ int solve_maxcut(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *w
     double *rn = reinterpret_cast<double *>(ws + w.rn);
     double *q1 = reinterpret_cast<double *>(ws + w.q1);
     double *q2 = reinterpret_cast<double *>(ws + w.q2);
+    double *acon = reinterpret_cast<double *>(ws + w.acon);
+    const bool bf = o->prec == LRSDP_F32_BF16IN && mc;
+    uint16_t *shadow = bf ? reinterpret_cast<uint16_t *>(ws + w.shadow) : nullptr;
     SolverState *st = at<SolverState>(c->scratch, kStateOff);
     double *part_ls = at<double>(c->scratch, kPartLsOff);
     double *part_cb = at<double>(c->scratch, kPartCbOff);
@@ -280,6 +304,7 @@ int solve_maxcut(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *w
         if ((rc = launch_fill(s, prec, gring[g], n * ld))) return rc;
     for (int d = 0; d < T; ++d)
         if ((rc = launch_fill(s, prec, dring[d], n * ld))) return rc;
+    if (bf && (rc = launch_fill(s, LRSDP_F32, shadow, n * bf16_ld(ld) / 2))) return rc;
 
     // profiling events
     const int B = std::max(1, o->check_every);
@@ -295,19 +320,34 @@ int solve_maxcut(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *w
     double spmm_ms = 0.0;
     int spmm_n = 0;
 
-    // initial measures: C R, ||R_i||^2, no multiplier step
-    SpmmArgs ref;
-    ref.epi = kEpiRefresh;
-    ref.V = R;
-    ref.Y = CD;
-    ref.y = y;
-    ref.rn = rn;
-    ref.sigma = 0.0;
-    ref.ld = ld;
-    ref.partials = part_misc;
-    int np = 0;
-    if ((rc = spmm_maxcut(s, p->csr, prec, ref, &np))) return rc;
-    if ((rc = launch_alm_finalize(s, st, part_misc, np, 0))) return rc;
+    // ALM measures at R, with the multiplier step y <- y + sigma (b - A(RR^T))
+    // when sigma > 0.  MaxCut: exact C R (into CD), ||R_i||^2; completion:
+    // constraint values a = A(RR^T) and ||R||_F^2.
+    auto alm_refresh = [&](double sigma, int mode) -> int {
+        int r2 = 0, np = 0;
+        if (mc) {
+            SpmmArgs ref;
+            ref.epi = kEpiRefresh;
+            ref.V = R;
+            ref.Y = CD;
+            ref.y = y;
+            ref.rn = rn;
+            ref.sigma = sigma;
+            ref.ld = ld;
+            ref.partials = part_misc;
+            if ((r2 = spmm_maxcut(s, p->csr, prec, ref, &np))) return r2;
+        } else {
+            int nb1 = 0, nb2 = 0;
+            if ((r2 = cmp_sddmm(s, p->cmp, prec, 2, R, nullptr, ld, acon, nullptr, nullptr, nullptr, y, sigma,
+                                part_misc, nullptr, &nb1)))
+                return r2;
+            const void *rb[1] = {R};
+            if ((r2 = launch_dots(s, prec, R, rb, 1, n, ld, part_misc + (size_t)nb1 * kMaxSums, &nb2))) return r2;
+            np = nb1 + nb2;
+        }
+        return launch_alm_finalize(s, st, part_misc, np, mode);
+    };
+    if ((rc = alm_refresh(0.0, 0))) return rc;
 
     int status = LRSDP_NOT_CONVERGED;
     int64_t outer = 0;
@@ -316,20 +356,76 @@ int solve_maxcut(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *w
     for (outer = 1; outer <= o->max_outer; ++outer) {
         // subproblem start: ytil, G_0, D_0 = -G_0
         int nb = 0, ncb = 0;
-        if ((rc = launch_grad_init_maxcut(s, prec, st, R, CD, y, rn, ytil[0], gring[0], n, ld, part_misc, &nb)))
-            break;
+        if (mc) {
+            if ((rc = launch_grad_init_maxcut(s, prec, st, R, CD, y, rn, ytil[0], gring[0], n, ld, part_misc, &nb)))
+                break;
+        } else {
+            if ((rc = cmp_ytil(s, p->cmp, st, 0.0, acon, y, ytil[0]))) break;
+            if ((rc = cmp_grad(s, p->cmp, prec, st, R, ytil[0], gring, dring, T, ld, part_misc, 0, &nb))) break;
+        }
         int64_t left = o->max_iter_total - total_inner;
         int k_limit = (int)std::min<int64_t>(o->max_inner, std::max<int64_t>(left, 0));
         if ((rc = launch_init_finalize(s, st, part_misc, nb, k_limit))) break;
-        if ((rc = launch_combine(s, prec, st, nullptr, basis, 2 * T + 1, nullptr, n, ld, part_cb, &ncb))) break;
-        // L-BFGS iterations in batches of B
-        int64_t it = 0;
+        if ((rc = launch_combine(s, prec, st, nullptr, basis, 2 * T + 1, nullptr, n, ld, part_cb, &ncb, shadow))) break;
+        // L-BFGS iterations in batches of B.  `it` indexes the ring slots (reset
+        // by a gradient refresh); `done_it` counts every enqueued iteration.
+        int64_t it = 0, done_it = 0, since_refresh = 0;
         SolverState hs{};
         for (;;) {
-            for (int b = 0; b < B; ++b, ++it) {
+            if (o->refresh_every > 0 && since_refresh >= o->refresh_every) {
+                // exact C R (MaxCut) / constraint values (completion), gradient,
+                // memory restart; same multipliers, penalty and target
+                since_refresh = 0;
+                it = 0;
+                int nb2 = 0;
+                if (mc) {
+                    SpmmArgs ref;
+                    ref.epi = kEpiRefresh;
+                    ref.V = R;
+                    ref.Y = CD;
+                    ref.y = y;
+                    ref.rn = rn;
+                    ref.sigma = 0.0;
+                    ref.ld = ld;
+                    ref.partials = part_misc;
+                    int np2 = 0;
+                    if ((rc = spmm_maxcut(s, p->csr, prec, ref, &np2))) break;
+                    if ((rc = launch_grad_init_maxcut(s, prec, st, R, CD, y, rn, ytil[0], gring[0], n, ld, part_misc,
+                                                      &nb2)))
+                        break;
+                } else {
+                    if ((rc = cmp_sddmm(s, p->cmp, prec, 2, R, nullptr, ld, acon, nullptr, nullptr, nullptr, y, 0.0,
+                                        part_misc, nullptr, &nb2)))
+                        break;
+                    if ((rc = cmp_ytil(s, p->cmp, st, 0.0, acon, y, ytil[0]))) break;
+                    if ((rc = cmp_grad(s, p->cmp, prec, st, R, ytil[0], gring, dring, T, ld, part_misc, 0, &nb2)))
+                        break;
+                }
+                if ((rc = launch_init_finalize(s, st, part_misc, nb2, -1))) break;
+                if ((rc = launch_combine(s, prec, st, nullptr, basis, 2 * T + 1, nullptr, n, ld, part_cb, &ncb,
+                                         shadow)))
+                    break;
+            }
+            for (int b = 0; b < B && !mc; ++b, ++it, ++done_it, ++since_refresh) {
+                int nls = 0, nup = 0;
+                if ((rc = cmp_sddmm(s, p->cmp, prec, 1, R, dring[it % T], ld, nullptr, q1, q2, ytil[0], nullptr, 0.0,
+                                    part_ls, st, &nls)))
+                    break;
+                if ((rc = launch_ls_finalize(s, st, part_ls, nls, part_cb, ncb, LRSDP_COMPLETION))) break;
+                if ((rc = cmp_samples(s, p->cmp, st, acon, q1, q2, y, ytil[0]))) break;
+                if ((rc = axpy_state(s, prec, st, R, dring[it % T], n, ld))) break;
+                if (o->profile) LRSDP_HIP_TRY(hipEventRecord(evs[2 * b], s));
+                if ((rc = cmp_grad(s, p->cmp, prec, st, R, ytil[0], gring, dring, T, ld, part_up, -1, &nup))) break;
+                if (o->profile) LRSDP_HIP_TRY(hipEventRecord(evs[2 * b + 1], s));
+                if ((rc = launch_lbfgs_finalize(s, st, part_up, nup))) break;
+                if ((rc = launch_combine(s, prec, st, nullptr, basis, 2 * T + 1, nullptr, n, ld, part_cb, &ncb, shadow)))
+                    break;
+            }
+            for (int b = 0; b < B && mc; ++b, ++it, ++done_it, ++since_refresh) {
                 SpmmArgs ls;
                 ls.epi = kEpiLS;
-                ls.V = dring[it % T];
+                ls.V = bf ? (const void *)shadow : dring[it % T];
+                ls.Vown = dring[it % T];
                 ls.Y = CD;
                 ls.R = R;
                 ls.ytil = ytil[it % 2];
@@ -341,15 +437,15 @@ int solve_maxcut(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *w
                 ls.st = st;
                 int nls = 0;
                 if (o->profile) LRSDP_HIP_TRY(hipEventRecord(evs[2 * b], s));
-                if ((rc = spmm_maxcut(s, p->csr, prec, ls, &nls))) break;
+                if ((rc = spmm_maxcut(s, p->csr, bf ? LRSDP_F32_BF16IN : prec, ls, &nls))) break;
                 if (o->profile) LRSDP_HIP_TRY(hipEventRecord(evs[2 * b + 1], s));
-                if ((rc = launch_ls_finalize(s, st, part_ls, nls, part_cb, ncb))) break;
+                if ((rc = launch_ls_finalize(s, st, part_ls, nls, part_cb, ncb, LRSDP_MAXCUT))) break;
                 int nup = 0;
                 if ((rc = launch_update_maxcut(s, prec, st, R, CD, y, rn, q1, q2, ytil[it % 2], ytil[(it + 1) % 2],
                                                gring, dring, T, n, ld, part_up, &nup)))
                     break;
                 if ((rc = launch_lbfgs_finalize(s, st, part_up, nup))) break;
-                if ((rc = launch_combine(s, prec, st, nullptr, basis, 2 * T + 1, nullptr, n, ld, part_cb, &ncb)))
+                if ((rc = launch_combine(s, prec, st, nullptr, basis, 2 * T + 1, nullptr, n, ld, part_cb, &ncb, shadow)))
                     break;
             }
             if (rc) break;
@@ -366,8 +462,8 @@ int solve_maxcut(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *w
             }
             if (hs.done || hs.numeric) break;
             if (elapsed() > o->time_limit_s) break;
-            if (it > (int64_t)k_limit + 2 * B) {
-                rc = set_error(LRSDP_EHIP, "device state did not advance (iteration %lld)", (long long)it);
+            if (done_it > (int64_t)k_limit + 2 * B) {
+                rc = set_error(LRSDP_EHIP, "device state did not advance (iteration %lld)", (long long)done_it);
                 break;
             }
         }
@@ -378,9 +474,7 @@ int solve_maxcut(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *w
             break;
         }
         // ALM step: y <- y + sigma (b - A(RR^T)), exact C R, measures
-        ref.sigma = sigma_host;
-        if ((rc = spmm_maxcut(s, p->csr, prec, ref, &np))) break;
-        if ((rc = launch_alm_finalize(s, st, part_misc, np, 1))) break;
+        if ((rc = alm_refresh(sigma_host, 1))) break;
         if ((rc = read_state(c, &hs))) break;
         if (o->verbose)
             fprintf(stderr, "[lrsdp] outer %3lld inner %6lld sigma %.3e obj % .10e err1 %.3e err3 % .3e gnorm %.3e t %.3fs\n",
@@ -414,7 +508,7 @@ int solve_maxcut(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *w
     res->status = status;
     res->spmm_launches = spmm_n;
     res->spmm_ms = spmm_ms;
-    res->spmm_bytes = maxcut_spmm_bytes(p, prec, o->rank);
+    res->spmm_bytes = mc ? maxcut_spmm_bytes(p, prec, o->rank) : completion_grad_bytes(p, prec, o->rank, T);
     return status;
 }
 
@@ -430,8 +524,7 @@ extern "C" int lrsdp_solve(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *
     if ((rc = plan_workspace(p, o, &w))) return rc;
     if (ws_bytes < w.total) return set_error(LRSDP_ENOMEM, "workspace needs %zu bytes, %zu given", w.total, ws_bytes);
     LRSDP_HIP_TRY(hipSetDevice(c->device));
-    if (p->info.kind == LRSDP_MAXCUT) return solve_maxcut(c, p, o, static_cast<char *>(ws), R, y, res);
-    return set_error(LRSDP_EUNSUPPORTED, "completion solve not available in this build");
+    return solve_impl(c, p, o, static_cast<char *>(ws), R, y, res);
 }
 
 // ---------------------------------------------------------------------------
@@ -453,8 +546,10 @@ extern "C" int lrsdp_k_spmm(lrsdp_ctx *c, const lrsdp_problem *p, int prec, cons
         a.ytil = ytil;
         a.ld = ld;
         int np = 0;
-        return spmm_maxcut(c->stream, p->csr, pr, a, &np);
+        return spmm_maxcut(c->stream, p->csr, prec, a, &np);
     }
+    if (prec == LRSDP_F32_BF16IN)
+        return set_error(LRSDP_EUNSUPPORTED, "bfloat16 input is implemented for the MaxCut SpMM only");
     return spmm_completion(c->stream, p->cmp, pr, V, ld, ytil, Y);
 }
 
@@ -467,7 +562,9 @@ extern "C" int lrsdp_k_constraint(lrsdp_ctx *c, const lrsdp_problem *p, int prec
     const int pr = prec == LRSDP_F64 ? LRSDP_F64 : LRSDP_F32;
     if (!V) V = U;
     if (p->info.kind == LRSDP_MAXCUT) return launch_rowdot(c->stream, pr, U, V, p->info.n, ld, out);
-    return set_error(LRSDP_EUNSUPPORTED, "completion constraint map not available in this build");
+    int nb = 0;
+    return cmp_sddmm(c->stream, p->cmp, pr, 0, U, V, ld, out, nullptr, nullptr, nullptr, nullptr, 0.0, nullptr,
+                     nullptr, &nb);
 }
 
 extern "C" int lrsdp_k_ls_coeffs(lrsdp_ctx *c, const lrsdp_problem *p, int prec, const void *R, const void *D,
@@ -477,12 +574,33 @@ extern "C" int lrsdp_k_ls_coeffs(lrsdp_ctx *c, const lrsdp_problem *p, int prec,
     if (!c || !R || !D || !y || !work || !out) return set_error(LRSDP_EINVAL, "NULL argument");
     int rc;
     if ((rc = check_problem(p)) || (rc = check_prec(prec)) || (rc = check_ld(prec, ld))) return rc;
-    if (p->info.kind != LRSDP_MAXCUT)
-        return set_error(LRSDP_EUNSUPPORTED, "completion line search not available in this build");
     const int pr = prec == LRSDP_F64 ? LRSDP_F64 : LRSDP_F32;
     const int64_t n = p->info.n;
     const size_t arr = (size_t)n * ld * elem_size(pr);
     char *wk = static_cast<char *>(work);
+    if (p->info.kind == LRSDP_COMPLETION) {
+        // a = A(RR^T), ytil = y + sigma (b - a), sample terms, then p1 = 2<R,D>, p2 = ||D||^2
+        const int64_t m = p->info.m;
+        double *acon = reinterpret_cast<double *>(wk);
+        double *yt = acon + m;
+        double *part = at<double>(c->scratch, kPartLsOff);
+        double *sums = at<double>(c->scratch, kSmallOff);
+        double *d2 = sums + 16;
+        hipStream_t s = c->stream;
+        int nb = 0;
+        if ((rc = cmp_sddmm(s, p->cmp, pr, 0, R, R, ld, acon, nullptr, nullptr, nullptr, nullptr, 0.0, nullptr,
+                            nullptr, &nb)))
+            return rc;
+        if ((rc = cmp_ytil(s, p->cmp, nullptr, sigma, acon, y, yt))) return rc;
+        if ((rc = cmp_sddmm(s, p->cmp, pr, 1, R, D, ld, nullptr, q1, q2, yt, nullptr, 0.0, part, nullptr, &nb)))
+            return rc;
+        if ((rc = launch_reduce(s, part, nb, kLsSums, sums))) return rc;
+        const void *rd[2] = {R, D};
+        double *part2 = at<double>(c->scratch, kPartMiscOff);
+        if ((rc = launch_dots(s, pr, D, rd, 2, n, ld, part2, &nb))) return rc;
+        if ((rc = launch_reduce(s, part2, nb, 2, d2))) return rc;
+        return launch_ls_out_cmp(s, sums, d2, sigma, out);
+    }
     void *CR = wk, *CDv = wk + arr;
     double *ytil = reinterpret_cast<double *>(wk + 2 * arr);
     double *part = at<double>(c->scratch, kPartLsOff);
@@ -526,11 +644,19 @@ extern "C" int lrsdp_k_alm(lrsdp_ctx *c, const lrsdp_problem *p, int prec, const
     if (!c || !R || !y || !work || !out) return set_error(LRSDP_EINVAL, "NULL argument");
     int rc;
     if ((rc = check_problem(p)) || (rc = check_prec(prec)) || (rc = check_ld(prec, ld))) return rc;
-    if (p->info.kind != LRSDP_MAXCUT)
-        return set_error(LRSDP_EUNSUPPORTED, "completion ALM step not available in this build");
     const int pr = prec == LRSDP_F64 ? LRSDP_F64 : LRSDP_F32;
     double *part = at<double>(c->scratch, kPartMiscOff);
     double *sums = at<double>(c->scratch, kSmallOff);
+    if (p->info.kind == LRSDP_COMPLETION) {
+        int nb1 = 0, nb2 = 0;
+        if ((rc = cmp_sddmm(c->stream, p->cmp, pr, 2, R, nullptr, ld, static_cast<double *>(work), nullptr, nullptr,
+                            nullptr, y, sigma, part, nullptr, &nb1)))
+            return rc;
+        const void *rb[1] = {R};
+        if ((rc = launch_dots(c->stream, pr, R, rb, 1, p->info.n, ld, part + (size_t)nb1 * kMaxSums, &nb2))) return rc;
+        if ((rc = launch_reduce(c->stream, part, nb1 + nb2, 3, sums))) return rc;
+        return launch_alm_out(c->stream, sums, p->info.b_l1, p->info.b_inf, out);
+    }
     SpmmArgs a;
     a.epi = kEpiRefresh;
     a.V = R;
@@ -575,7 +701,7 @@ extern "C" int lrsdp_k_lbfgs_dir(lrsdp_ctx *c, int prec, int64_t n, int64_t ld, 
     }
     if ((rc = launch_two_loop_pairs(s, gram, k, coef, flag))) return rc;
     int nblk = 0;
-    if ((rc = launch_combine(s, pr, nullptr, coef, basis, nb, D, n, ld, part, &nblk))) return rc;
+    if ((rc = launch_combine(s, pr, nullptr, coef, basis, nb, D, n, ld, part, &nblk, nullptr))) return rc;
     int hflag = 0;
     LRSDP_HIP_TRY(hipMemcpyAsync(c->pinned, flag, sizeof(int), hipMemcpyDeviceToHost, s));
     LRSDP_HIP_TRY(hipStreamSynchronize(s));

@@ -177,8 +177,10 @@ __device__ void two_loop_coef(SolverState &st) {
 
 // Line-search stage: fold the previous combine pass's dots into the Gram
 // matrix, form a1..a4 and take the exact step.
+// kind: LRSDP_MAXCUT (p2 summed by the SpMM epilogue) or LRSDP_COMPLETION
+// (C = I, so p2 = <C, D D^T> = ||D||_F^2, a Gram entry).
 __global__ __launch_bounds__(kBlock) void k_ls_finalize(SolverState *gst, const double *ls_part, int n_ls,
-                                                        const double *cb_part, int n_cb) {
+                                                        const double *cb_part, int n_cb, int kind) {
     __shared__ SolverState st;
     __shared__ double ls[kLsSums];
     __shared__ double cb[kMaxBasis + 1];
@@ -199,7 +201,8 @@ __global__ __launch_bounds__(kBlock) void k_ls_finalize(SolverState *gst, const 
         const double sigma = st.sigma;
         const double a1 = 0.5 * sigma * ls[3];
         const double a2 = sigma * ls[4];
-        const double a3 = ls[0] - ls[1] + 0.5 * sigma * ls[5];
+        const double p2 = kind == LRSDP_COMPLETION ? M[dcol * kMaxBasis + dcol] : ls[0];
+        const double a3 = p2 - ls[1] + 0.5 * sigma * ls[5];
         const double a4 = M[st.gk * kMaxBasis + dcol];
         st.a[0] = a1;
         st.a[1] = a2;
@@ -267,6 +270,8 @@ __global__ __launch_bounds__(kBlock) void k_lbfgs_finalize(SolverState *gst, con
 }
 
 // Start of a subproblem: gradient norm known, empty memory, D = -G.
+// k_limit < 0: restart inside a subproblem after an exact gradient refresh
+// (iteration count, limit and target kept).
 __global__ __launch_bounds__(kBlock) void k_init_finalize(SolverState *gst, const double *part, int n_part,
                                                           int k_limit) {
     __shared__ SolverState st;
@@ -274,15 +279,19 @@ __global__ __launch_bounds__(kBlock) void k_init_finalize(SolverState *gst, cons
     block_copy(&st, gst);
     reduce_rows<1>(part, n_part, g2);
     if (threadIdx.x == 0) {
+        const bool restart = k_limit < 0;
         for (int j = 0; j < kMaxBasis * kMaxBasis; ++j) st.gram[j] = 0.0;
         st.gram[0] = g2[0];
         st.gk = 0;
         st.dk = 0;
-        st.k = 0;
         st.nmem = 0;
-        st.max_inner = k_limit;
         st.gnorm = sqrt(fmax(g2[0], 0.0));
-        st.target = st.eta * fmax(1.0, st.gnorm);
+        if (!restart) {
+            st.k = 0;
+            st.max_inner = k_limit;
+            st.target = st.eta * fmax(1.0, st.gnorm);
+        }
+        k_limit = st.max_inner - st.k;
         for (int j = 0; j < kMaxBasis; ++j) st.coef[j] = 0.0;
         st.coef[0] = -1.0;
         st.done = 0;
@@ -447,7 +456,17 @@ struct CombineArgs {
     S *out;                 // used when st == nullptr
     int64_t nchunks;        // n * ld / chunk
     double *partials;       // dots of out with each basis entry, then ||out||^2
+    uint16_t *shadow;       // float32 only: bfloat16 copy of out (row stride ldb), or nullptr
+    int64_t ld, ldb;
 };
+
+// float32 -> bfloat16, round to nearest, ties to even (NaN kept quiet)
+__device__ __forceinline__ uint16_t bf16_rne(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
 
 // out = sum_j coef_j basis_j, and <out, basis_j> (pre-update values) for all j
 // plus <out, out>.  In the solver the output is D slot dk, itself basis entry
@@ -487,6 +506,16 @@ __global__ __launch_bounds__(kBlock) void k_combine(CombineArgs<S> a) {
         CV o;
         narrow(acc, o);
         reinterpret_cast<CV *>(out)[c] = o;
+        if constexpr (sizeof(S) == 4) {
+            if (a.shadow) {
+                const int64_t e = c * 4, row = e / a.ld, col = e - row * a.ld;
+                const D4 w = widen(o);
+                uint2 pk;
+                pk.x = (uint32_t)bf16_rne((float)w.v[0]) | ((uint32_t)bf16_rne((float)w.v[1]) << 16);
+                pk.y = (uint32_t)bf16_rne((float)w.v[2]) | ((uint32_t)bf16_rne((float)w.v[3]) << 16);
+                *reinterpret_cast<uint2 *>(a.shadow + row * a.ldb + col) = pk;
+            }
+        }
 #pragma unroll
         for (int j = 0; j < kMaxBasis; ++j)
             if (j < NB) s[j] += vdot(o, b[j]);
@@ -577,8 +606,9 @@ static int grid_for(int64_t work_items, int per_block) {
 
 static int chunks_per_row(int prec, int64_t ld) { return (int)(ld * (prec == LRSDP_F64 ? 8 : 4) / 16); }
 
-int launch_ls_finalize(hipStream_t s, SolverState *st, const double *ls, int nls, const double *cb, int ncb) {
-    hipLaunchKernelGGL(k_ls_finalize, dim3(1), dim3(kBlock), 0, s, st, ls, nls, cb, ncb);
+int launch_ls_finalize(hipStream_t s, SolverState *st, const double *ls, int nls, const double *cb, int ncb,
+                       int kind) {
+    hipLaunchKernelGGL(k_ls_finalize, dim3(1), dim3(kBlock), 0, s, st, ls, nls, cb, ncb, kind);
     LRSDP_CHECK_LAUNCH();
     return LRSDP_OK;
 }
@@ -647,15 +677,15 @@ int launch_update_maxcut(hipStream_t s, int prec, SolverState *st, void *R, cons
 
 // basis: nb device arrays of n*ld elements; out = sum coef_j basis_j.
 int launch_combine(hipStream_t s, int prec, SolverState *st, const double *coef, const void *const *basis, int nb,
-                   void *out, int64_t n, int64_t ld, double *partials, int *nblk) {
+                   void *out, int64_t n, int64_t ld, double *partials, int *nblk, uint16_t *shadow) {
     const int64_t nch = n * ld * (prec == LRSDP_F64 ? 8 : 4) / 16;
     *nblk = grid_for(nch, kBlock);
     if (prec == LRSDP_F64) {
-        CombineArgs<double> a{st, coef, {}, nb, (double *)out, nch, partials};
+        CombineArgs<double> a{st, coef, {}, nb, (double *)out, nch, partials, nullptr, ld, ld};
         for (int j = 0; j < nb; ++j) a.basis[j] = (const double *)basis[j];
         hipLaunchKernelGGL(k_combine<double>, dim3(*nblk), dim3(kBlock), 0, s, a);
     } else {
-        CombineArgs<float> a{st, coef, {}, nb, (float *)out, nch, partials};
+        CombineArgs<float> a{st, coef, {}, nb, (float *)out, nch, partials, shadow, ld, bf16_ld(ld)};
         for (int j = 0; j < nb; ++j) a.basis[j] = (const float *)basis[j];
         hipLaunchKernelGGL(k_combine<float>, dim3(*nblk), dim3(kBlock), 0, s, a);
     }

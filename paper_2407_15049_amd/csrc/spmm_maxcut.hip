@@ -25,6 +25,9 @@
 //                   optional multiplier step y_i <- y_i - sigma res_i; sums
 //                   obj, b^T y, ||res||^2
 //  * Per-block sums go to a fixed-grid partials array (deterministic).
+//  * BF16 input (float32 path only): the gathered operand is a bfloat16 copy
+//    (row stride ldb = ld rounded up to 8); a lane then covers 8 columns, i.e.
+//    two float32 chunks of the output, and accumulates in float32.
 #include "device.h"
 #include "kernels.h"
 
@@ -42,13 +45,37 @@ __device__ __forceinline__ S edge_weight(const DevCsr &P, int e, int32_t c) {
     }
 }
 
-// acc += sum_{e in [beg, end)} C_{row, col[e]} V_{col[e]}  (this lane's chunk)
-template <typename S, int W>
-__device__ __forceinline__ void gather(const DevCsr &P, const S *__restrict__ V, int64_t ld,
-                                       int beg, int end, int lane, bool active,
-                                       typename Chunk<S>::V &acc) {
+// 8 bfloat16 values (16 bytes) -> two float4
+__device__ __forceinline__ void bf16x8_to_f32(const uint4 &u, float4 &lo, float4 &hi) {
+    lo.x = __uint_as_float(u.x << 16);
+    lo.y = __uint_as_float(u.x & 0xffff0000u);
+    lo.z = __uint_as_float(u.y << 16);
+    lo.w = __uint_as_float(u.y & 0xffff0000u);
+    hi.x = __uint_as_float(u.z << 16);
+    hi.y = __uint_as_float(u.z & 0xffff0000u);
+    hi.z = __uint_as_float(u.w << 16);
+    hi.w = __uint_as_float(u.w & 0xffff0000u);
+}
+
+// One gathered neighbour row chunk: NC = 1 -> one 16-byte chunk of S; NC = 2
+// (BF16 input) -> 8 bfloat16 values widened to two float4.
+template <typename S, int NC>
+__device__ __forceinline__ void load_nbr(const void *V, int64_t j, int64_t ldv, int lane,
+                                         typename Chunk<S>::V (&v)[NC]) {
     using CV = typename Chunk<S>::V;
-    constexpr int NV = Chunk<S>::N;
+    if constexpr (NC == 1) {
+        v[0] = *reinterpret_cast<const CV *>((const S *)V + j * ldv + lane * Chunk<S>::N);
+    } else {
+        const uint4 u = *reinterpret_cast<const uint4 *>((const uint16_t *)V + j * ldv + lane * 8);
+        bf16x8_to_f32(u, v[0], v[1]);
+    }
+}
+
+// acc += sum_{e in [beg, end)} C_{row, col[e]} V_{col[e]}  (this lane's chunks)
+template <typename S, int W, int NC>
+__device__ __forceinline__ void gather(const DevCsr &P, const void *__restrict__ V, int64_t ldv, int beg, int end,
+                                       int lane, bool active, typename Chunk<S>::V (&acc)[NC]) {
+    using CV = typename Chunk<S>::V;
     const int32_t *__restrict__ col = P.col;
     int e = beg;
     for (; e + 4 <= end; e += 4) {
@@ -56,56 +83,90 @@ __device__ __forceinline__ void gather(const DevCsr &P, const S *__restrict__ V,
         S w0 = edge_weight<S, W>(P, e, c0), w1 = edge_weight<S, W>(P, e + 1, c1);
         S w2 = edge_weight<S, W>(P, e + 2, c2), w3 = edge_weight<S, W>(P, e + 3, c3);
         if (active) {
-            const CV v0 = *reinterpret_cast<const CV *>(V + (int64_t)(c0 & 0x7fffffff) * ld + lane * NV);
-            const CV v1 = *reinterpret_cast<const CV *>(V + (int64_t)(c1 & 0x7fffffff) * ld + lane * NV);
-            const CV v2 = *reinterpret_cast<const CV *>(V + (int64_t)(c2 & 0x7fffffff) * ld + lane * NV);
-            const CV v3 = *reinterpret_cast<const CV *>(V + (int64_t)(c3 & 0x7fffffff) * ld + lane * NV);
-            vfma(acc, w0, v0);
-            vfma(acc, w1, v1);
-            vfma(acc, w2, v2);
-            vfma(acc, w3, v3);
+            CV v0[NC], v1[NC], v2[NC], v3[NC];
+            load_nbr<S, NC>(V, c0 & 0x7fffffff, ldv, lane, v0);
+            load_nbr<S, NC>(V, c1 & 0x7fffffff, ldv, lane, v1);
+            load_nbr<S, NC>(V, c2 & 0x7fffffff, ldv, lane, v2);
+            load_nbr<S, NC>(V, c3 & 0x7fffffff, ldv, lane, v3);
+#pragma unroll
+            for (int q = 0; q < NC; ++q) {
+                vfma(acc[q], w0, v0[q]);
+                vfma(acc[q], w1, v1[q]);
+                vfma(acc[q], w2, v2[q]);
+                vfma(acc[q], w3, v3[q]);
+            }
         }
     }
     for (; e < end; ++e) {
         int32_t c0 = col[e];
         S w0 = edge_weight<S, W>(P, e, c0);
         if (active) {
-            const CV v0 = *reinterpret_cast<const CV *>(V + (int64_t)(c0 & 0x7fffffff) * ld + lane * NV);
-            vfma(acc, w0, v0);
+            CV v0[NC];
+            load_nbr<S, NC>(V, c0 & 0x7fffffff, ldv, lane, v0);
+#pragma unroll
+            for (int q = 0; q < NC; ++q) vfma(acc[q], w0, v0[q]);
         }
     }
 }
 
-// Per-row epilogue.  Every lane of the group calls it (inactive lanes hold
-// zero chunks); lane 0 of the group adds the row's terms into s[].
-template <typename S, int GS, int EPI>
-__device__ __forceinline__ void epilogue(const DevCsr &P, const SpmmArgs &a, int row, int lane,
-                                         bool active, typename Chunk<S>::V acc, double (&s)[kLsSums]) {
+// Per-row epilogue.  Every lane of the group calls it (inactive chunks hold
+// zeros); lane 0 of the group adds the row's terms into s[].  Lane `lane` owns
+// output chunks lane*NC + q, q < NC.
+template <typename S, int GS, int EPI, int NC>
+__device__ __forceinline__ void epilogue(const DevCsr &P, const SpmmArgs &a, int row, int lane, bool active,
+                                         typename Chunk<S>::V (&acc)[NC], double (&s)[kLsSums]) {
     using CV = typename Chunk<S>::V;
     constexpr int NV = Chunk<S>::N;
-    const int64_t off = (int64_t)row * a.ld + lane * NV;
     const S dg = (S)P.diag[row];
-    CV zero = vzero(CV{});
+    const CV zero = vzero(CV{});
+    int64_t off[NC];
+    bool act[NC];
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+        const int ci = lane * NC + q;
+        act[q] = active && ci * NV < a.ld;
+        off[q] = (int64_t)row * a.ld + ci * NV;
+    }
     if constexpr (EPI == kEpiPlain) {
-        const CV v = active ? *reinterpret_cast<const CV *>((const S *)a.V + off) : zero;
+        CV v[NC];
+        if constexpr (NC == 1) {
+            v[0] = act[0] ? *reinterpret_cast<const CV *>((const S *)a.V + off[0]) : zero;
+        } else {
+            // own row from the bfloat16 input (lanes past the row hold zeros)
+#pragma unroll
+            for (int q = 0; q < NC; ++q) v[q] = zero;
+            if (active) load_nbr<S, NC>(a.V, row, a.ldv, lane, v);
+        }
         S shift = dg;
         if (a.ytil) shift = (S)((double)P.diag[row] - a.ytil[row]);
-        vfma(acc, shift, v);
-        if (active) *reinterpret_cast<CV *>((S *)a.Y + off) = acc;
-    } else if constexpr (EPI == kEpiLS) {
-        const CV d = active ? *reinterpret_cast<const CV *>((const S *)a.V + off) : zero;
-        const CV r = active ? *reinterpret_cast<const CV *>((const S *)a.R + off) : zero;
-        vfma(acc, dg, d);
-        if (active) *reinterpret_cast<CV *>((S *)a.Y + off) = acc;
-        double p2 = group_sum<GS>(vdot(acc, d));
-        double q1 = 2.0 * group_sum<GS>(vdot(r, d));
-        double q2 = group_sum<GS>(vdot(d, d));
-        double rr = a.rn ? group_sum<GS>(vdot(r, r)) : 0.0;
-        double p1 = 0.0;
-        if (a.aux) {
-            const CV cr = active ? *reinterpret_cast<const CV *>((const S *)a.aux + off) : zero;
-            p1 = 2.0 * group_sum<GS>(vdot(cr, d));
+#pragma unroll
+        for (int q = 0; q < NC; ++q) {
+            vfma(acc[q], shift, v[q]);
+            if (act[q]) *reinterpret_cast<CV *>((S *)a.Y + off[q]) = acc[q];
         }
+    } else if constexpr (EPI == kEpiLS) {
+        const S *Dn = (const S *)(NC == 1 ? a.V : a.Vown);   // own row of D in the storage type
+        double p2 = 0.0, q1 = 0.0, q2 = 0.0, rr = 0.0, p1 = 0.0;
+#pragma unroll
+        for (int q = 0; q < NC; ++q) {
+            const CV d = act[q] ? *reinterpret_cast<const CV *>(Dn + off[q]) : zero;
+            const CV r = act[q] ? *reinterpret_cast<const CV *>((const S *)a.R + off[q]) : zero;
+            vfma(acc[q], dg, d);
+            if (act[q]) *reinterpret_cast<CV *>((S *)a.Y + off[q]) = acc[q];
+            p2 += vdot(acc[q], d);
+            q1 += vdot(r, d);
+            q2 += vdot(d, d);
+            if (a.rn) rr += vdot(r, r);
+            if (a.aux) {
+                const CV cr = act[q] ? *reinterpret_cast<const CV *>((const S *)a.aux + off[q]) : zero;
+                p1 += vdot(cr, d);
+            }
+        }
+        p2 = group_sum<GS>(p2);
+        q1 = 2.0 * group_sum<GS>(q1);
+        q2 = group_sum<GS>(q2);
+        if (a.rn) rr = group_sum<GS>(rr);
+        if (a.aux) p1 = 2.0 * group_sum<GS>(p1);
         if (lane == 0) {
             const double yt = a.ytil[row];
             s[0] += p2;
@@ -119,12 +180,18 @@ __device__ __forceinline__ void epilogue(const DevCsr &P, const SpmmArgs &a, int
             if (a.q2) a.q2[row] = q2;
             if (a.rn) a.rn[row] = rr;
         }
-    } else {  // kEpiRefresh: V = R
-        const CV r = active ? *reinterpret_cast<const CV *>((const S *)a.V + off) : zero;
-        vfma(acc, dg, r);
-        if (active && a.Y) *reinterpret_cast<CV *>((S *)a.Y + off) = acc;
-        double obj = group_sum<GS>(vdot(r, acc));
-        double rn = group_sum<GS>(vdot(r, r));
+    } else {  // kEpiRefresh: V = R (storage type, NC = 1)
+        double obj = 0.0, rn = 0.0;
+#pragma unroll
+        for (int q = 0; q < NC; ++q) {
+            const CV r = act[q] ? *reinterpret_cast<const CV *>((const S *)a.V + off[q]) : zero;
+            vfma(acc[q], dg, r);
+            if (act[q] && a.Y) *reinterpret_cast<CV *>((S *)a.Y + off[q]) = acc[q];
+            obj += vdot(r, acc[q]);
+            rn += vdot(r, r);
+        }
+        obj = group_sum<GS>(obj);
+        rn = group_sum<GS>(rn);
         if (lane == 0) {
             double res = rn - 1.0;
             double yi = a.y[row];
@@ -140,78 +207,93 @@ __device__ __forceinline__ void epilogue(const DevCsr &P, const SpmmArgs &a, int
     }
 }
 
-template <typename S, int GS, int W, int EPI>
+// lane owns gathered chunk `lane` (NC = 1: chunk of S; NC = 2: 8 bfloat16)
+template <typename S, int NC>
+__device__ __forceinline__ bool lane_active(const SpmmArgs &a, int lane) {
+    return NC == 1 ? lane * Chunk<S>::N < a.ld : lane * 8 < a.ld;
+}
+
+template <typename S, int GS, int W, int EPI, int NC>
 __global__ __launch_bounds__(kBlock) void k_spmm_light(DevCsr P, SpmmArgs a) {
     using CV = typename Chunk<S>::V;
-    constexpr int NV = Chunk<S>::N;
     constexpr int GPB = kBlock / GS;
     if (a.st && a.st->done) return;
     const int lane = threadIdx.x % GS;
     const int grp = threadIdx.x / GS;
-    const bool active = lane * NV < a.ld;
+    const bool active = lane_active<S, NC>(a, lane);
     double s[kLsSums] = {0, 0, 0, 0, 0, 0, 0, 0};
-    const S *V = (const S *)a.V;
     for (int64_t it = (int64_t)blockIdx.x * GPB + grp; it < P.n_light; it += (int64_t)gridDim.x * GPB) {
         const int row = P.light[it];
         const int beg = P.row_ptr[row], end = P.row_ptr[row + 1];
-        CV acc = vzero(CV{});
-        gather<S, W>(P, V, a.ld, beg, end, lane, active, acc);
-        epilogue<S, GS, EPI>(P, a, row, lane, active, acc, s);
+        CV acc[NC];
+#pragma unroll
+        for (int q = 0; q < NC; ++q) acc[q] = vzero(CV{});
+        gather<S, W, NC>(P, a.V, a.ldv, beg, end, lane, active, acc);
+        epilogue<S, GS, EPI, NC>(P, a, row, lane, active, acc, s);
     }
     if constexpr (EPI != kEpiPlain) block_sums_store<kLsSums>(s, a.partials + (size_t)blockIdx.x * kMaxSums);
 }
 
-// Segments of heavy rows: partial sums to seg_buf (256 bytes per segment).
-template <typename S, int GS, int W>
+// Segments of heavy rows: partial sums to seg_buf (16 chunks = 256 bytes per segment).
+template <typename S, int GS, int W, int NC>
 __global__ __launch_bounds__(kBlock) void k_spmm_segments(DevCsr P, SpmmArgs a) {
     using CV = typename Chunk<S>::V;
-    constexpr int NV = Chunk<S>::N;
     constexpr int GPB = kBlock / GS;
     if (a.st && a.st->done) return;
     const int lane = threadIdx.x % GS;
     const int grp = threadIdx.x / GS;
-    const bool active = lane * NV < a.ld;
-    const S *V = (const S *)a.V;
+    const bool active = lane_active<S, NC>(a, lane);
     CV *buf = (CV *)P.seg_buf;
     for (int64_t it = (int64_t)blockIdx.x * GPB + grp; it < P.n_seg; it += (int64_t)gridDim.x * GPB) {
         const int4 sg = P.seg[it];
-        CV acc = vzero(CV{});
-        gather<S, W>(P, V, a.ld, sg.y, sg.z, lane, active, acc);
-        if (active) buf[(int64_t)sg.w * 16 + lane] = acc;
+        CV acc[NC];
+#pragma unroll
+        for (int q = 0; q < NC; ++q) acc[q] = vzero(CV{});
+        gather<S, W, NC>(P, a.V, a.ldv, sg.y, sg.z, lane, active, acc);
+        if (active) {
+#pragma unroll
+            for (int q = 0; q < NC; ++q) buf[(int64_t)sg.w * 16 + lane * NC + q] = acc[q];
+        }
     }
 }
 
 // One workgroup per heavy row: add its segment sums in a fixed order, then run
 // the epilogue with lane group 0.
-template <typename S, int GS, int EPI>
+template <typename S, int GS, int EPI, int NC>
 __global__ __launch_bounds__(kBlock) void k_spmm_fixup(DevCsr P, SpmmArgs a, int part_base) {
     using CV = typename Chunk<S>::V;
-    constexpr int NV = Chunk<S>::N;
     constexpr int GPB = kBlock / GS;
     if (a.st && a.st->done) return;
     const int lane = threadIdx.x % GS;
     const int grp = threadIdx.x / GS;
-    const bool active = lane * NV < a.ld;
+    const bool active = lane_active<S, NC>(a, lane);
     const CV *buf = (const CV *)P.seg_buf;
-    __shared__ CV sh[GPB][GS];
+    __shared__ CV sh[GPB][GS * NC];
     double s[kLsSums] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int64_t h = blockIdx.x; h < P.n_heavy; h += gridDim.x) {
         const int row = P.heavy[h];
         const int s0 = P.heavy_seg[h], s1 = P.heavy_seg[h + 1];
-        CV acc = vzero(CV{});
-        for (int q = s0 + grp; q < s1; q += GPB) {
+        CV acc[NC];
+#pragma unroll
+        for (int q = 0; q < NC; ++q) acc[q] = vzero(CV{});
+        for (int g = s0 + grp; g < s1; g += GPB) {
             if (active) {
-                const CV v = buf[(int64_t)q * 16 + lane];
-                vfma(acc, (S)1, v);
+#pragma unroll
+                for (int q = 0; q < NC; ++q) vfma(acc[q], (S)1, buf[(int64_t)g * 16 + lane * NC + q]);
             }
         }
-        sh[grp][lane] = acc;
+#pragma unroll
+        for (int q = 0; q < NC; ++q) sh[grp][lane * NC + q] = acc[q];
         __syncthreads();
         if (grp == 0) {
-            CV t = vzero(CV{});
+            CV t[NC];
+#pragma unroll
+            for (int q = 0; q < NC; ++q) {
+                t[q] = vzero(CV{});
 #pragma unroll 4
-            for (int g = 0; g < GPB; ++g) vfma(t, (S)1, sh[g][lane]);
-            epilogue<S, GS, EPI>(P, a, row, lane, active, t, s);
+                for (int g = 0; g < GPB; ++g) vfma(t[q], (S)1, sh[g][lane * NC + q]);
+            }
+            epilogue<S, GS, EPI, NC>(P, a, row, lane, active, t, s);
         }
         __syncthreads();
     }
@@ -219,64 +301,71 @@ __global__ __launch_bounds__(kBlock) void k_spmm_fixup(DevCsr P, SpmmArgs a, int
         block_sums_store<kLsSums>(s, a.partials + (size_t)(part_base + blockIdx.x) * kMaxSums);
 }
 
-template <typename S, int GS, int W, int EPI>
+template <typename S, int GS, int W, int EPI, int NC>
 int launch(hipStream_t st, const DevCsr &P, const SpmmArgs &a, int *nparts) {
     constexpr int GPB = kBlock / GS;
     int nb1 = 0, nb3 = 0;
     if (P.n_light > 0) {
         int64_t need = (P.n_light + GPB - 1) / GPB;
         nb1 = (int)std::min<int64_t>(need, kMaxBlocks);
-        hipLaunchKernelGGL((k_spmm_light<S, GS, W, EPI>), dim3(nb1), dim3(kBlock), 0, st, P, a);
+        hipLaunchKernelGGL((k_spmm_light<S, GS, W, EPI, NC>), dim3(nb1), dim3(kBlock), 0, st, P, a);
         LRSDP_CHECK_LAUNCH();
     }
     if (P.n_heavy > 0) {
         int64_t need = (P.n_seg + GPB - 1) / GPB;
         int nb2 = (int)std::min<int64_t>(need, 4 * kMaxBlocks);
-        hipLaunchKernelGGL((k_spmm_segments<S, GS, W>), dim3(nb2), dim3(kBlock), 0, st, P, a);
+        hipLaunchKernelGGL((k_spmm_segments<S, GS, W, NC>), dim3(nb2), dim3(kBlock), 0, st, P, a);
         LRSDP_CHECK_LAUNCH();
         nb3 = (int)std::min<int64_t>(P.n_heavy, kMaxBlocks);
-        hipLaunchKernelGGL((k_spmm_fixup<S, GS, EPI>), dim3(nb3), dim3(kBlock), 0, st, P, a, nb1);
+        hipLaunchKernelGGL((k_spmm_fixup<S, GS, EPI, NC>), dim3(nb3), dim3(kBlock), 0, st, P, a, nb1);
         LRSDP_CHECK_LAUNCH();
     }
     *nparts = nb1 + nb3;
     return LRSDP_OK;
 }
 
-template <typename S, int GS, int EPI>
+template <typename S, int GS, int EPI, int NC>
 int launch_w(hipStream_t st, const DevCsr &P, const SpmmArgs &a, int *nparts) {
     switch (P.wmode) {
-        case kWUnit: return launch<S, GS, kWUnit, EPI>(st, P, a, nparts);
-        case kWSign: return launch<S, GS, kWSign, EPI>(st, P, a, nparts);
-        default: return launch<S, GS, kWGeneral, EPI>(st, P, a, nparts);
+        case kWUnit: return launch<S, GS, kWUnit, EPI, NC>(st, P, a, nparts);
+        case kWSign: return launch<S, GS, kWSign, EPI, NC>(st, P, a, nparts);
+        default: return launch<S, GS, kWGeneral, EPI, NC>(st, P, a, nparts);
     }
 }
 
-template <typename S, int EPI>
+template <typename S, int EPI, int NC>
 int launch_gs(hipStream_t st, const DevCsr &P, const SpmmArgs &a, int *nparts) {
-    const int chunks = (int)(a.ld * (int64_t)sizeof(S) / 16);
-    if (chunks <= 4) return launch_w<S, 4, EPI>(st, P, a, nparts);
-    if (chunks <= 8) return launch_w<S, 8, EPI>(st, P, a, nparts);
-    return launch_w<S, 16, EPI>(st, P, a, nparts);
+    // gathered 16-byte chunks per row
+    const int chunks = NC == 1 ? (int)(a.ld * (int64_t)sizeof(S) / 16) : (int)((a.ld + 7) / 8);
+    if (chunks <= 4) return launch_w<S, 4, EPI, NC>(st, P, a, nparts);
+    if (chunks <= 8) return launch_w<S, 8, EPI, NC>(st, P, a, nparts);
+    return launch_w<S, 16, EPI, NC>(st, P, a, nparts);
 }
 
-template <typename S>
+template <typename S, int NC>
 int launch_epi(hipStream_t st, const DevCsr &P, const SpmmArgs &a, int *nparts) {
     switch (a.epi) {
-        case kEpiPlain: return launch_gs<S, kEpiPlain>(st, P, a, nparts);
-        case kEpiLS: return launch_gs<S, kEpiLS>(st, P, a, nparts);
-        default: return launch_gs<S, kEpiRefresh>(st, P, a, nparts);
+        case kEpiPlain: return launch_gs<S, kEpiPlain, NC>(st, P, a, nparts);
+        case kEpiLS: return launch_gs<S, kEpiLS, NC>(st, P, a, nparts);
+        default: return launch_gs<S, kEpiRefresh, 1>(st, P, a, nparts);
     }
 }
 
 }  // namespace
 
-int spmm_maxcut(hipStream_t st, const DevCsr &P, int prec, const SpmmArgs &a, int *nparts) {
+int spmm_maxcut(hipStream_t st, const DevCsr &P, int prec, const SpmmArgs &a_in, int *nparts) {
     const int64_t esz = prec == LRSDP_F64 ? 8 : 4;
+    SpmmArgs a = a_in;
     if (a.ld <= 0 || (a.ld * esz) % 16 != 0 || a.ld * esz > 256)
         return set_error(LRSDP_EINVAL, "ld = %lld: row bytes must be a positive multiple of 16, at most 256",
                          (long long)a.ld);
-    if (prec == LRSDP_F64) return launch_epi<double>(st, P, a, nparts);
-    return launch_epi<float>(st, P, a, nparts);
+    const bool bf = prec == LRSDP_F32_BF16IN && a.epi != kEpiRefresh;
+    if (bf && a.epi == kEpiLS && !a.Vown)
+        return set_error(LRSDP_EINVAL, "bfloat16 line-search SpMM needs the float32 operand");
+    a.ldv = bf ? bf16_ld(a.ld) : a.ld;
+    if (prec == LRSDP_F64) return launch_epi<double, 1>(st, P, a, nparts);
+    if (bf) return launch_epi<float, 2>(st, P, a, nparts);
+    return launch_epi<float, 1>(st, P, a, nparts);
 }
 
 }  // namespace lrsdp

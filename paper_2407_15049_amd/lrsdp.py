@@ -140,7 +140,8 @@ def default_options(**kw) -> Options:
 
 
 def padded_ld(rank: int, prec: int) -> int:
-    """Smallest row stride >= rank whose row bytes are a multiple of 16."""
+    """Smallest row stride >= rank whose row bytes are a multiple of 16 (the
+    float32 stride for LRSDP_F32_BF16IN)."""
     per = 2 if prec == F64 else 4
     return ((rank + per - 1) // per) * per
 

@@ -9,7 +9,7 @@ def dev_factor(A, prec, ld=None, device="cuda:0"):
     """numpy (n, r) -> zero-padded torch (n, ld) in the precision's storage type."""
     import torch
     n, r = A.shape
-    ld = ld or L.padded_ld(r, prec)
+    ld = ld or L.padded_ld(r, L.F64 if prec == L.F64 else L.F32)
     t = torch.zeros((n, ld), dtype=L.elem_dtype(prec), device=device)
     t[:, :r] = torch.from_numpy(np.ascontiguousarray(A)).to(device=device, dtype=t.dtype)
     return t

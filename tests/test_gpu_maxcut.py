@@ -255,7 +255,7 @@ def gpu_solve(ctx, n, u, v, w, R0, prec, **kw):
     import torch
     r = R0.shape[1]
     prob = L.Problem.maxcut(n, u, v, w).upload(ctx)
-    opts = L.default_options(prec=prec, rank=r, ld=L.padded_ld(r, prec), **kw)
+    opts = L.default_options(prec=prec, rank=r, ld=L.padded_ld(r, L.F64 if prec == L.F64 else L.F32), **kw)
     Rd = dev_factor(R0, prec)
     yd = torch.zeros(n, dtype=torch.float64, device="cuda")
     rc, res = L.solve(ctx, prob, Rd, yd, opts)
@@ -323,3 +323,51 @@ def test_solve_reports_limits(ctx):
     R0 = init_factor(n, r, 5)
     rc, res, _, _ = gpu_solve(ctx, n, u, v, w, R0, L.F64, max_outer=1)
     assert rc == L.NOT_CONVERGED and res.outer == 1 and res.err1 > 0
+
+
+@pytest.mark.parametrize("case", ["er_1k", "pm1_ragged", "general", "cl_heavy", "isolated"])
+def test_spmm_bf16_input_parity(ctx, case):
+    # bfloat16 gathered operand, float32 accumulation and output
+    import torch
+    n, r, prob, op = setup(ctx, case)
+    print_case(test="spmm_bf16", case=case, n=n, r=r)
+    ld = L.padded_ld(r, L.F32)
+    ldb = (ld + 7) // 8 * 8
+    rng = np.random.default_rng(17)
+    Vb = torch.from_numpy(rng.standard_normal((n, r)).astype(np.float32)).to(torch.bfloat16)
+    V = Vb.to(torch.float64).numpy()                 # exact values the device holds
+    Vd = torch.zeros((n, ldb), dtype=torch.bfloat16, device="cuda")
+    Vd[:, :r] = Vb.cuda()
+    ytil = rng.standard_normal(n)
+    Yd = torch.full((n, ld), np.nan, dtype=torch.float32, device="cuda")
+    L._check(L.load().lrsdp_k_spmm(ctx.handle, prob.handle, L.F32_BF16IN, L._ptr(Vd), ld,
+                                   L._ptr(dev_vec(ytil)), L._ptr(Yd)))
+    torch.cuda.synchronize()
+    Y = host(Yd)
+    assert np.all(Y[:, r:] == 0.0)
+    Yo = K.spmm(op, ytil, V)
+    bound = abs(op.C) @ np.abs(V) + np.abs(ytil)[:, None] * np.abs(V)
+    assert np.all(np.abs(Y[:, :r] - Yo) <= 1e-4 * bound + 1e-300)
+
+
+def test_solve_bf16_input_er_1k(ctx):
+    n, u, v, w, _ = graph("er_1k")
+    print_case(test="solve", case="er_1k", prec="bf16in", r=12)
+    R0 = init_factor(n, 12, 15052)
+    rc, res, R, y = gpu_solve(ctx, n, u, v, w, R0, L.F32_BF16IN, refresh_every=25)
+    rc64, res64, _, _ = gpu_solve(ctx, n, u, v, w, R0, L.F64)
+    op = maxcut_problem(n, u, v, w)
+    m = K.alm_measures(op, R, y)
+    print("BF16IN", res.as_dict(), "F64", res64.as_dict(), "oracle-measured", m)
+    assert rc == L.OK
+    assert m["err1"] <= 1e-5 and abs(m["err3"]) <= 1e-5
+    assert abs(res.obj - res64.obj) <= 1e-4 * abs(res64.obj)
+
+
+def test_solve_refresh_every_matches(ctx):
+    n, u, v, w, r = graph("er_1k")
+    R0 = init_factor(n, r, 15050)
+    rc, res, R, y = gpu_solve(ctx, n, u, v, w, R0, L.F64, refresh_every=16)
+    ores = alm_solve(maxcut_problem(n, u, v, w), R0, opts=OOptions())
+    assert rc == L.OK
+    assert abs(res.obj - ores.obj) <= 1e-5 * abs(ores.obj)
