@@ -133,8 +133,8 @@ int lrsdp_problem_upload(lrsdp_ctx *ctx, lrsdp_problem *prob, void *dev,
                          size_t bytes);
 
 /* ---- solver options ---------------------------------------------------------
- * Defaults (lrsdp_options_default): F64, T = 4 L-BFGS pairs, tol = 1e-5,
- * sigma0 = 0 (selects ||vec(C)||_1 / m), sigma_factor = 2, sigma_max_ratio =
+ * Defaults (lrsdp_options_default): F64, T = 2 L-BFGS pairs, tol = 1e-5,
+ * sigma0 = 0 (selects 4 ||vec(C)||_1 / m), sigma_factor = 2, sigma_max_ratio =
  * 1e8, feas_decrease = 0.25, eta0 = 0.1, eta_factor = 0.25, eta_min = 1e-9,
  * max_outer = 300, max_inner = 2000, max_iter_total = 200000,
  * check_every = 8, time_limit_s = 1e30, refresh_every = 0 (off).
@@ -149,7 +149,7 @@ typedef struct {
     int     max_inner;        /* L-BFGS iterations per ALM subproblem          */
     int64_t max_iter_total;
     double  time_limit_s;
-    double  sigma0;           /* <= 0: ||vec(C)||_1 / m                        */
+    double  sigma0;           /* <= 0: 4 ||vec(C)||_1 / m                      */
     double  sigma_factor;     /* sigma growth when err1 stalls                 */
     double  sigma_max_ratio;  /* sigma <= sigma_max_ratio * sigma0             */
     double  feas_decrease;    /* stall test: err1 > feas_decrease * err1_prev  */
@@ -249,6 +249,46 @@ int lrsdp_k_alm(lrsdp_ctx *ctx, const lrsdp_problem *prob, int prec,
 int lrsdp_k_lbfgs_dir(lrsdp_ctx *ctx, int prec, int64_t n, int64_t ld,
                       const void *G, const void *const *S, const void *const *Y,
                       int k, void *D);
+
+/* ---- learned warm start (MaxCut) -------------------------------------------
+ * The paper has no warm start; this is the project's extension: a per-node MLP
+ * 16 -> 64 -> 64 -> 2 (tanh hidden layers, float32 parameters laid out as
+ * W1[64][16], b1[64], W2[64][64], b2[64], W3[2][64], b3[2]) maps 16 local graph
+ * features of node i to (t_i, s_i); the warm start is y0_i = -t_i a_i / 4 with
+ * a_i = sum_j |w_ij|, and sigma0 = (default sigma0) * exp(mean_i s_i).  Only
+ * MaxCut problems are accepted (others: EUNSUPPORTED).
+ */
+
+/* Number of float32 parameters (5378). */
+int lrsdp_mlp_param_count(void);
+
+/* feat (device n x 16 float32, row-major) = node features of the problem's
+ * graph; stats: device scratch of 4 float32 per node. */
+int lrsdp_ws_features(lrsdp_ctx *ctx, const lrsdp_problem *prob, float *feat, float *stats);
+
+/* Training targets from a solved problem: target (device n x 2 float32) =
+ * (-4 y_i / a_i, log_sigma_ratio) (first entry 0 for isolated nodes); stats as
+ * filled by lrsdp_ws_features, y the solution multipliers (device float64). */
+int lrsdp_ws_targets(lrsdp_ctx *ctx, const lrsdp_problem *prob, const float *stats, const double *y,
+                     double log_sigma_ratio, float *target);
+
+/* out (device n x 2 float32) = MLP(feat). */
+int lrsdp_mlp_forward(lrsdp_ctx *ctx, const float *params, const float *feat, int64_t n, float *out);
+
+/* grad (device nparam float32) and *loss (device float64) of
+ * L = (1/n) sum_i ||MLP(feat_i) - target_i||^2, target device n x 2 float32.
+ * work: device float32 scratch of 256 * (nparam + 1).  Deterministic. */
+int lrsdp_mlp_grad(lrsdp_ctx *ctx, const float *params, const float *feat, const float *target, int64_t n,
+                   float *grad, double *loss, float *work);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8; step counts from 1) on
+ * device arrays of nparam float32. */
+int lrsdp_mlp_adam(lrsdp_ctx *ctx, float *params, float *m, float *v, const float *grad, int step, float lr);
+
+/* Warm start for the problem: y0 (device m float64) and *sigma0 (host).
+ * work: device float32 scratch of 22 n.  Synchronises the stream. */
+int lrsdp_warmstart(lrsdp_ctx *ctx, const lrsdp_problem *prob, const float *params, float *work, double *y0,
+                    double *sigma0);
 
 #ifdef __cplusplus
 }

@@ -9,13 +9,13 @@ penalty schedule, inner tolerance, memory length), the numbers below are this
 project's own reading; the GPU library takes the same numbers from its own
 options struct (the two share numbers, not code):
 
-* y0 = 0; sigma0 = ||vec(C)||_1 / m unless given;
+* y0 = 0; sigma0 = 4 ||vec(C)||_1 / m unless given;
 * after each inner solve: y <- y + sigma (b - A(RR^T));
   sigma <- min(sigma_factor * sigma, sigma_max_ratio * sigma0) when err1 did not
   fall below feas_decrease * (previous err1);
 * inner L-BFGS stops when ||grad||_F <= eta_k * max(1, ||grad at its start||_F),
   eta_0 = eta0, eta_{k+1} = max(eta_factor * eta_k, eta_min);
-* L-BFGS memory T = lbfgs_mem pairs from consecutive iterations; a pair failing
+* L-BFGS memory T = lbfgs_mem (default 2) pairs from consecutive iterations; a pair failing
   the curvature guard, or a direction that is not a descent direction, clears
   the memory (the next direction is -grad);
 * stop when err1 <= tol and |err3| <= tol (the paper's mild re-opt criterion).
@@ -36,11 +36,11 @@ from .problem import SDPProblem
 @dataclass
 class Options:
     tol: float = 1e-5
-    lbfgs_mem: int = 4
+    lbfgs_mem: int = 2
     max_outer: int = 300
     max_inner: int = 2000
     max_iter_total: int = 200000
-    sigma0: float = 0.0            # 0 selects ||vec(C)||_1 / m
+    sigma0: float = 0.0            # 0 selects 4 ||vec(C)||_1 / m
     sigma_factor: float = 2.0
     sigma_max_ratio: float = 1e8
     feas_decrease: float = 0.25
@@ -68,7 +68,7 @@ class SolveResult:
 
 
 def default_sigma0(prob: SDPProblem) -> float:
-    return max(prob.c_l1 / prob.m, 1e-8)
+    return max(4.0 * prob.c_l1 / prob.m, 1e-8)
 
 
 def lbfgs_minimize(prob: SDPProblem, R, y, sigma, eta, opts: Options, budget: int):

@@ -21,6 +21,7 @@ SOURCES = [
     "solver_kernels.hip",
     "entry_kernels.hip",
     "completion.hip",
+    "warmstart.hip",
     "solver.hip",
 ]
 

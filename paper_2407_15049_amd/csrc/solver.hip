@@ -161,7 +161,7 @@ extern "C" void lrsdp_options_default(lrsdp_options *o) {
     o->prec = LRSDP_F64;
     o->rank = 0;
     o->ld = 0;
-    o->lbfgs_mem = 4;
+    o->lbfgs_mem = 2;
     o->tol = 1e-5;
     o->max_outer = 300;
     o->max_inner = 2000;
@@ -282,7 +282,7 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
     for (int g = 0; g <= T; ++g) basis[g] = gring[g];
     for (int d = 0; d < T; ++d) basis[T + 1 + d] = dring[d];
 
-    const double sigma0 = o->sigma0 > 0 ? o->sigma0 : std::max(p->info.c_l1 / (double)p->info.m, 1e-8);
+    const double sigma0 = o->sigma0 > 0 ? o->sigma0 : std::max(4.0 * p->info.c_l1 / (double)p->info.m, 1e-8);
     SolverState h{};
     h.sigma = sigma0;
     h.sigma_cap = sigma0 * o->sigma_max_ratio;
@@ -707,5 +707,89 @@ extern "C" int lrsdp_k_lbfgs_dir(lrsdp_ctx *c, int prec, int64_t n, int64_t ld, 
     LRSDP_HIP_TRY(hipStreamSynchronize(s));
     std::memcpy(&hflag, c->pinned, sizeof(int));
     if (hflag) return set_error(LRSDP_EINVAL, "a pair has <y_t, s_t> <= 0");
+    return LRSDP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// learned warm start
+// ---------------------------------------------------------------------------
+namespace lrsdp {
+int ws_features(hipStream_t, const DevCsr &, float *, float4 *);
+int mlp_forward(hipStream_t, const float *, const float *, int64_t, float *);
+int mlp_grad(hipStream_t, const float *, const float *, const float *, int64_t, float *, double *, float *);
+int mlp_adam(hipStream_t, float *, float *, float *, const float *, int, float);
+int warm_y0(hipStream_t, const float *, const float4 *, int64_t, double *, double *, double *);
+int mlp_param_count();
+int ws_targets(hipStream_t, const float4 *, const double *, int64_t, double, float *);
+}  // namespace lrsdp
+
+extern "C" int lrsdp_ws_targets(lrsdp_ctx *c, const lrsdp_problem *p, const float *stats, const double *y,
+                                double log_sigma_ratio, float *target) {
+    clear_error();
+    if (!c || !stats || !y || !target) return set_error(LRSDP_EINVAL, "NULL argument");
+    int rc;
+    if ((rc = check_problem(p))) return rc;
+    if (p->info.kind != LRSDP_MAXCUT) return set_error(LRSDP_EUNSUPPORTED, "warm start is for MaxCut problems");
+    return ws_targets(c->stream, reinterpret_cast<const float4 *>(stats), y, p->info.n, log_sigma_ratio, target);
+}
+
+extern "C" int lrsdp_mlp_param_count(void) { return mlp_param_count(); }
+
+extern "C" int lrsdp_ws_features(lrsdp_ctx *c, const lrsdp_problem *p, float *feat, float *stats) {
+    clear_error();
+    if (!c || !feat || !stats) return set_error(LRSDP_EINVAL, "NULL argument");
+    int rc;
+    if ((rc = check_problem(p))) return rc;
+    if (p->info.kind != LRSDP_MAXCUT) return set_error(LRSDP_EUNSUPPORTED, "warm start is for MaxCut problems");
+    if (((uintptr_t)feat | (uintptr_t)stats) % 16) return set_error(LRSDP_EINVAL, "buffers must be 16-byte aligned");
+    return ws_features(c->stream, p->csr, feat, reinterpret_cast<float4 *>(stats));
+}
+
+extern "C" int lrsdp_mlp_forward(lrsdp_ctx *c, const float *params, const float *feat, int64_t n, float *out) {
+    clear_error();
+    if (!c || !params || !feat || !out || n < 0) return set_error(LRSDP_EINVAL, "bad argument");
+    if (n == 0) return LRSDP_OK;
+    return mlp_forward(c->stream, params, feat, n, out);
+}
+
+extern "C" int lrsdp_mlp_grad(lrsdp_ctx *c, const float *params, const float *feat, const float *target, int64_t n,
+                              float *grad, double *loss, float *work) {
+    clear_error();
+    if (!c || !params || !feat || !target || !grad || !work || n <= 0) return set_error(LRSDP_EINVAL, "bad argument");
+    return mlp_grad(c->stream, params, feat, target, n, grad, loss, work);
+}
+
+extern "C" int lrsdp_mlp_adam(lrsdp_ctx *c, float *params, float *m, float *v, const float *grad, int step, float lr) {
+    clear_error();
+    if (!c || !params || !m || !v || !grad || step < 1) return set_error(LRSDP_EINVAL, "bad argument");
+    return mlp_adam(c->stream, params, m, v, grad, step, lr);
+}
+
+extern "C" int lrsdp_warmstart(lrsdp_ctx *c, const lrsdp_problem *p, const float *params, float *work, double *y0,
+                               double *sigma0) {
+    clear_error();
+    if (!c || !params || !work || !y0 || !sigma0) return set_error(LRSDP_EINVAL, "NULL argument");
+    int rc;
+    if ((rc = check_problem(p))) return rc;
+    if (p->info.kind != LRSDP_MAXCUT) return set_error(LRSDP_EUNSUPPORTED, "warm start is for MaxCut problems");
+    if ((uintptr_t)work % 16) return set_error(LRSDP_EINVAL, "work must be 16-byte aligned");
+    const int64_t n = p->info.n;
+    float *feat = work;
+    float4 *stats = reinterpret_cast<float4 *>(work + 16 * n);
+    float *out = work + 20 * n;
+    double *part = at<double>(c->scratch, kPartMiscOff);
+    double *sum = at<double>(c->scratch, kSmallOff);
+    hipStream_t s = c->stream;
+    if ((rc = ws_features(s, p->csr, feat, stats))) return rc;
+    if ((rc = mlp_forward(s, params, feat, n, out))) return rc;
+    if ((rc = warm_y0(s, out, stats, n, y0, part, sum))) return rc;
+    double hsum = 0.0;
+    LRSDP_HIP_TRY(hipMemcpyAsync(c->pinned, sum, sizeof(double), hipMemcpyDeviceToHost, s));
+    LRSDP_HIP_TRY(hipStreamSynchronize(s));
+    std::memcpy(&hsum, c->pinned, sizeof(double));
+    const double base = std::max(4.0 * p->info.c_l1 / (double)p->info.m, 1e-8);
+    const double mean = n > 0 ? hsum / (double)n : 0.0;
+    if (!std::isfinite(mean)) return set_error(LRSDP_ENUMERIC, "warm-start penalty prediction is not finite");
+    *sigma0 = base * std::exp(std::max(-10.0, std::min(10.0, mean)));
     return LRSDP_OK;
 }

@@ -88,6 +88,13 @@ _SIGS = {
     "lrsdp_k_cubic": (C.c_int, [_P, _P, _P]),
     "lrsdp_k_alm": (C.c_int, [_P, _P, C.c_int, _P, _I64, _P, C.c_double, _P, _P]),
     "lrsdp_k_lbfgs_dir": (C.c_int, [_P, C.c_int, _I64, _I64, _P, _P, _P, C.c_int, _P]),
+    "lrsdp_mlp_param_count": (C.c_int, []),
+    "lrsdp_ws_features": (C.c_int, [_P, _P, _P, _P]),
+    "lrsdp_mlp_forward": (C.c_int, [_P, _P, _P, _I64, _P]),
+    "lrsdp_mlp_grad": (C.c_int, [_P, _P, _P, _P, _I64, _P, _P, _P]),
+    "lrsdp_mlp_adam": (C.c_int, [_P, _P, _P, _P, _P, C.c_int, C.c_float]),
+    "lrsdp_warmstart": (C.c_int, [_P, _P, _P, _P, _P, C.POINTER(C.c_double)]),
+    "lrsdp_ws_targets": (C.c_int, [_P, _P, _P, _P, C.c_double, _P]),
 }
 
 _lib = None
@@ -287,3 +294,37 @@ def k_lbfgs_dir(ctx, prec, G, S, Y, D):
     yp = (C.c_void_p * max(k, 1))(*[t.data_ptr() for t in Y])
     _check(load().lrsdp_k_lbfgs_dir(ctx.handle, prec, G.shape[0], G.shape[1], _ptr(G),
                                     C.cast(sp, C.c_void_p), C.cast(yp, C.c_void_p), k, _ptr(D)))
+
+
+# ---- learned warm start ----------------------------------------------------------
+def mlp_param_count() -> int:
+    return load().lrsdp_mlp_param_count()
+
+
+def ws_features(ctx, prob, feat, stats):
+    _check(load().lrsdp_ws_features(ctx.handle, prob.handle, _ptr(feat), _ptr(stats)))
+
+
+def mlp_forward(ctx, params, feat, out):
+    _check(load().lrsdp_mlp_forward(ctx.handle, _ptr(params), _ptr(feat), feat.shape[0], _ptr(out)))
+
+
+def mlp_grad(ctx, params, feat, target, grad, loss, work):
+    _check(load().lrsdp_mlp_grad(ctx.handle, _ptr(params), _ptr(feat), _ptr(target), feat.shape[0],
+                                 _ptr(grad), _ptr(loss), _ptr(work)))
+
+
+def mlp_adam(ctx, params, m, v, grad, step, lr):
+    _check(load().lrsdp_mlp_adam(ctx.handle, _ptr(params), _ptr(m), _ptr(v), _ptr(grad), int(step), float(lr)))
+
+
+def warmstart(ctx, prob, params, work, y0):
+    """Fill y0 (device float64) and return the predicted sigma0."""
+    s = C.c_double()
+    _check(load().lrsdp_warmstart(ctx.handle, prob.handle, _ptr(params), _ptr(work), _ptr(y0), C.byref(s)))
+    return s.value
+
+
+def ws_targets(ctx, prob, stats, y, log_sigma_ratio, target):
+    _check(load().lrsdp_ws_targets(ctx.handle, prob.handle, _ptr(stats), _ptr(y), float(log_sigma_ratio),
+                                   _ptr(target)))
