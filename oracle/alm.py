@@ -48,6 +48,10 @@ class Options:
     eta_factor: float = 0.25
     eta_min: float = 1e-9
     time_limit: float = 1e30
+    phase2: bool = False           # switch to the splitting phase (Section 2.2)
+    switch_err1: float = 1e-3      # ... once err1 <= switch_err1 after an ALM step
+    admm_check: int = 10
+    max_admm: int = 5000
 
 
 @dataclass
@@ -133,6 +137,12 @@ def alm_solve(prob: SDPProblem, R0: np.ndarray, y0=None, opts: Options | None = 
         if meas["err1"] <= opts.tol and abs(meas["err3"]) <= opts.tol:
             converged = True
             break
+        if opts.phase2 and meas["err1"] <= opts.switch_err1:
+            R, _, _, y, meas, it2 = admm_phase(prob, R, y, sigma, tol=opts.tol, max_iter=opts.max_admm,
+                                               check_every=opts.admm_check)
+            hist.append(dict(outer=outer, admm=it2, sigma=sigma, **meas))
+            converged = meas["err1"] <= opts.tol and abs(meas["err3"]) <= opts.tol
+            break
         if total >= opts.max_iter_total or time.perf_counter() - t0 > opts.time_limit:
             break
         if meas["err1"] > opts.feas_decrease * err1_prev:
@@ -143,3 +153,72 @@ def alm_solve(prob: SDPProblem, R0: np.ndarray, y0=None, opts: Options | None = 
                        err1=meas["err1"], err1_inf=meas["err1_inf"], err3=meas["err3"],
                        outer=outer, inner=total, converged=converged,
                        seconds=time.perf_counter() - t0, history=hist)
+
+
+# ---------------------------------------------------------------------------
+# Splitting (ADMM) phase, Section 2.2 (LoRADS): X = U V^T with the penalty
+# sigma/2 ||U - V||^2, in the appendix sign convention
+#   L(U, V, y) = <C, U V^T> + y^T (b - A(U V^T)) + sigma/2 ||b - A(U V^T)||^2
+#                + sigma/2 ||U - V||^2.
+# ---------------------------------------------------------------------------
+
+def split_operator(prob: SDPProblem, V: np.ndarray, sigma: float):
+    """The positive definite map of eq. 2.2 for the U-step: U -> sigma A*(A(U V^T)) V + sigma U."""
+    def apply(U):
+        return sigma * (prob.A_adj(prob.A_of(U, V)) @ V) + sigma * U
+    return apply
+
+
+def split_rhs(prob: SDPProblem, V: np.ndarray, y: np.ndarray, sigma: float) -> np.ndarray:
+    """Right-hand side of eq. 2.2 for the U-step: -C V + A*(y) V + sigma A*(b) V + sigma V."""
+    return -(prob.C @ V) + prob.A_adj(y) @ V + sigma * (prob.A_adj(prob.b) @ V) + sigma * V
+
+
+def cg(apply, B, X0, eps, K):
+    """Conjugate gradients (Algorithm 2, no preconditioner) for apply(X) = B."""
+    X = X0.copy()
+    r = B - apply(X)
+    if np.sqrt(np.sum(r * r)) <= eps:
+        return X, 0
+    p = r.copy()
+    rr = float(np.sum(r * r))
+    for k in range(K):
+        Q = apply(p)
+        alpha = rr / float(np.sum(p * Q))
+        X = X + alpha * p
+        r = r - alpha * Q
+        rr_new = float(np.sum(r * r))
+        if np.sqrt(rr_new) <= eps:
+            return X, k + 1
+        p = r + (rr_new / rr) * p
+        rr = rr_new
+    return X, K
+
+
+def admm_step(prob: SDPProblem, U, V, y, sigma, cg_tol=1e-12, cg_iters=1000):
+    """One splitting iteration: U-step and V-step by CG on eq. 2.2, then the
+    multiplier step y <- y + sigma (b - A(U V^T))."""
+    B = split_rhs(prob, V, y, sigma)
+    U, _ = cg(split_operator(prob, V, sigma), B, U, cg_tol * max(1.0, np.linalg.norm(B)), cg_iters)
+    B = split_rhs(prob, U, y, sigma)
+    V, _ = cg(split_operator(prob, U, sigma), B, V, cg_tol * max(1.0, np.linalg.norm(B)), cg_iters)
+    y = y + sigma * (prob.b - prob.A_of(U, V))
+    return U, V, y
+
+
+def admm_phase(prob: SDPProblem, R, y, sigma, tol=1e-5, max_iter=2000, check_every=10, log=None):
+    """Run splitting iterations from U = V = R until err1 and |err3| at
+    R = (U + V)/2 are below tol (checked every `check_every` iterations)."""
+    U, V = R.copy(), R.copy()
+    meas = K.alm_measures(prob, R, y)
+    it = 0
+    for it in range(1, max_iter + 1):
+        U, V, y = admm_step(prob, U, V, y, sigma)
+        if it % check_every == 0 or it == max_iter:
+            Rm = 0.5 * (U + V)
+            meas = K.alm_measures(prob, Rm, y)
+            if log is not None:
+                log(dict(it=it, **meas))
+            if meas["err1"] <= tol and abs(meas["err3"]) <= tol:
+                break
+    return 0.5 * (U + V), U, V, y, meas, it
