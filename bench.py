@@ -38,7 +38,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-f32", action="store_true")
+    ap.add_argument("--no-f32", action="store_true", help="skip the float32 / warm-start / bf16 paths")
+    ap.add_argument("--no-warm", action="store_true", help="skip the learned warm start")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample")
     ap.add_argument("--instances", default=",".join(INSTANCES))
@@ -129,21 +130,61 @@ def main():
     spmm_bytes = sum(res.spmm_bytes * res.spmm_launches for v in recs.values() for _, res in v)
     achieved = (spmm_bytes / 1e9) / (spmm_ms / 1e3) if spmm_ms > 0 else None
 
-    paths = {"f64": {}, "f32": {}}
+    paths = {"f64": {}}
     for run in runs:
         dt, res = recs[run["name"]][-1]
         paths["f64"][run["name"]] = dict(
             seconds=round(dt, 4), outer=res.outer, inner=res.inner, obj=res.obj, err1=res.err1,
             err3=res.err3, spmm_us=round(1e3 * res.spmm_ms / max(res.spmm_launches, 1), 2))
+    def record(path, run, dt, res, extra=None):
+        o64 = paths["f64"][run["name"]]["obj"]
+        rec = dict(seconds=round(dt, 4), outer=res.outer, inner=res.inner, obj=res.obj, err1=res.err1,
+                   err3=res.err3, obj_rel_vs_f64=abs(res.obj - o64) / abs(o64),
+                   spmm_us=round(1e3 * res.spmm_ms / max(res.spmm_launches, 1), 2))
+        rec.update(extra or {})
+        paths.setdefault(path, {})[run["name"]] = rec
+        log(f"{path} {run['name']} {dt:.3f}s outer {res.outer} inner {res.inner} obj {res.obj:.8e}")
+
     if not args.no_f32:
         for run in runs:
             dt, res = solve(run, L.F32)
-            o64 = paths["f64"][run["name"]]["obj"]
-            paths["f32"][run["name"]] = dict(
-                seconds=round(dt, 4), outer=res.outer, inner=res.inner, obj=res.obj, err1=res.err1,
-                err3=res.err3, obj_rel_vs_f64=abs(res.obj - o64) / abs(o64),
-                spmm_us=round(1e3 * res.spmm_ms / max(res.spmm_launches, 1), 2))
-            log(f"f32 {run['name']} {dt:.3f}s outer {res.outer} inner {res.inner}")
+            record("f32", run, dt, res)
+        # bfloat16 gathered operand (float32 iterate, exact gradient every 25 iterations)
+        for run in runs:
+            p = run["per"][L.F32]
+            o = L.default_options(prec=L.F32_BF16IN, rank=run["r"], ld=p["opts"].ld, profile=1, refresh_every=25)
+            ws = torch.empty(L.workspace_bytes(run["prob"], o), dtype=torch.uint8, device=dev)
+            p["R"].copy_(p["R0"])
+            p["y"].zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rc, res = L.solve(ctx, run["prob"], p["R"], p["y"], o, workspace=ws)
+            torch.cuda.synchronize()
+            record("f32_bf16in", run, time.perf_counter() - t0, res, dict(converged=rc == L.OK))
+            del ws
+        if not args.no_warm:
+            from paper_2407_15049_amd import warmstart as W
+            t0 = time.perf_counter()
+            data = W.make_training_set(ctx, log=log)
+            t1 = time.perf_counter()
+            params, hist = W.train(ctx, data, steps=400, lr=3e-3, log=log)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            del data
+            warm_info = dict(train_graphs=len(W.TRAIN_SPECS), label_solves_s=round(t1 - t0, 2),
+                             train_s=round(t2 - t1, 2), loss_first=hist[0][1], loss_last=hist[-1][1])
+            for run in runs:
+                p = run["per"][L.F32]
+                p["R"].copy_(p["R0"])
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()           # prediction time counts toward the solve
+                y0, sigma0 = W.warm_start(ctx, run["prob"], params)
+                p["y"].copy_(y0)
+                o = L.default_options(prec=L.F32, rank=run["r"], ld=p["opts"].ld, profile=1, sigma0=sigma0)
+                rc, res = L.solve(ctx, run["prob"], p["R"], p["y"], o, workspace=p["ws"])
+                torch.cuda.synchronize()
+                record("f32_warm", run, time.perf_counter() - t0, res, dict(sigma0=sigma0, converged=rc == L.OK))
+            paths["f32_warm"]["model"] = warm_info
 
     if args.copy_calibration:
         a = torch.ones(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
@@ -171,7 +212,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "instances": names, "tol": 1e-5, "path": "plain FP64 ALM + L-BFGS",
-                   "lbfgs_mem": 4},
+                   "lbfgs_mem": runs[0]["per"][L.F64]["opts"].lbfgs_mem},
         "roofline": {
             "kernel": "spmm (MaxCut, line-search epilogue)",
             "bound": "hbm",

@@ -137,7 +137,8 @@ int lrsdp_problem_upload(lrsdp_ctx *ctx, lrsdp_problem *prob, void *dev,
  * sigma0 = 0 (selects 4 ||vec(C)||_1 / m), sigma_factor = 2, sigma_max_ratio =
  * 1e8, feas_decrease = 0.25, eta0 = 0.1, eta_factor = 0.25, eta_min = 1e-9,
  * max_outer = 300, max_inner = 2000, max_iter_total = 200000,
- * check_every = 8, time_limit_s = 1e30, refresh_every = 0 (off).
+ * check_every = 8, time_limit_s = 1e30, refresh_every = 0 (off), phase2 = 0,
+ * switch_err1 = 1e-3, admm_check = 10, max_admm = 5000.
  */
 typedef struct {
     int     prec;             /* LRSDP_F64 / LRSDP_F32 / LRSDP_F32_BF16IN      */
@@ -161,6 +162,11 @@ typedef struct {
                                  (0 = only at each ALM step)                   */
     int     profile;          /* 1: time SpMM launches with HIP events         */
     int     verbose;          /* 1: print one line per ALM step to stderr      */
+    int     phase2;           /* 1: switch to the splitting (ADMM) phase of
+                                 Section 2.2 once err1 <= switch_err1 (MaxCut) */
+    double  switch_err1;      /* ALM -> splitting threshold on err1            */
+    int     admm_check;       /* splitting iterations between measure checks   */
+    int     max_admm;         /* splitting iterations at most                  */
 } lrsdp_options;
 
 void lrsdp_options_default(lrsdp_options *opts);
@@ -179,6 +185,7 @@ typedef struct {
     int     spmm_launches;/* profiled SpMM launches (profile = 1)              */
     double  spmm_ms;      /* summed duration of those launches (HIP events)    */
     double  spmm_bytes;   /* algorithmic bytes of one SpMM launch              */
+    int64_t admm_iters;   /* splitting-phase iterations (phase2 = 1)           */
 } lrsdp_result;
 
 /* Device workspace the solve needs for this problem and these options. */
@@ -239,6 +246,13 @@ int lrsdp_k_cubic(lrsdp_ctx *ctx, const double *a, double *tau);
 int lrsdp_k_alm(lrsdp_ctx *ctx, const lrsdp_problem *prob, int prec,
                 const void *R, int64_t ld, double *y, double sigma, void *work,
                 double *out);
+
+/* `iters` splitting iterations (Section 2.2, eqs. 2.2-2.3; MaxCut only) in
+ * place: U <- argmin_U L(U, V, y), V <- argmin_V L(U, V, y), each solved
+ * exactly per row, then y <- y + sigma (b - A(U V^T)).  U, V device n x ld,
+ * y device m float64. */
+int lrsdp_k_admm(lrsdp_ctx *ctx, const lrsdp_problem *prob, int prec, void *U, void *V, int64_t ld,
+                 double *y, double sigma, int iters);
 
 /* Compact-form L-BFGS direction (Algorithm 1, H0 = I) for gradient G and k
  * pairs s_t = S[t], y_t = Y[t] (oldest first; S, Y: host arrays of k device

@@ -44,7 +44,7 @@ struct Rings {
     S *d[kMaxMem];
 };
 
-enum EpiKind { kEpiPlain = 0, kEpiLS = 1, kEpiRefresh = 2 };
+enum EpiKind { kEpiPlain = 0, kEpiLS = 1, kEpiRefresh = 2, kEpiSplit = 3 };
 
 // Arguments of one SpMM Y = C V (+ epilogue).  See spmm_maxcut.hip.
 struct SpmmArgs {
@@ -58,7 +58,7 @@ struct SpmmArgs {
     const double *ytil = nullptr;   // kEpiPlain: shift (nullable); kEpiLS: ytil
     double *y = nullptr;            // kEpiRefresh: multipliers
     double *rn = nullptr;           // kEpiRefresh / kEpiLS: ||R_i||^2 out (nullable)
-    double sigma = 0.0;             // kEpiRefresh: y <- y - sigma (rn - 1) if > 0
+    double sigma = 0.0;             // kEpiRefresh: y <- y - sigma (rn - 1) if > 0; kEpiSplit: penalty
     double *q1 = nullptr;           // kEpiLS: optional per-constraint outputs
     double *q2 = nullptr;
     int64_t ld = 0;

@@ -29,6 +29,7 @@ int launch_combine(hipStream_t, int, SolverState *, const double *, const void *
 int launch_grad_init_maxcut(hipStream_t, int, SolverState *, const void *, const void *, const double *,
                             const double *, double *, void *, int64_t, int64_t, double *, int *);
 int launch_fill(hipStream_t, int, void *, int64_t);
+int launch_avg(hipStream_t, int, const void *, const void *, void *, int64_t);
 int launch_dots(hipStream_t, int, const void *, const void *const *, int, int64_t, int64_t, double *, int *);
 int launch_rowdot(hipStream_t, int, const void *, const void *, int64_t, int64_t, double *);
 int launch_ytil(hipStream_t, const double *, const double *, const double *, double, int64_t, double *);
@@ -178,6 +179,10 @@ extern "C" void lrsdp_options_default(lrsdp_options *o) {
     o->refresh_every = 0;
     o->profile = 0;
     o->verbose = 0;
+    o->phase2 = 0;
+    o->switch_err1 = 1e-3;
+    o->admm_check = 10;
+    o->max_admm = 5000;
 }
 
 namespace {
@@ -247,6 +252,24 @@ int write_state(lrsdp_ctx *c, const SolverState &h) {
     LRSDP_HIP_TRY(hipMemcpyAsync(d, c->pinned, sizeof(SolverState), hipMemcpyHostToDevice, c->stream));
     LRSDP_HIP_TRY(hipStreamSynchronize(c->stream));
     return LRSDP_OK;
+}
+
+// One splitting iteration for MaxCut (Section 2.2): U-step from V, V-step from
+// U with the multiplier step fused into its epilogue.
+int admm_iter(hipStream_t s, const DevCsr &P, int prec, void *U, void *V, int64_t ld, double *y, double sigma) {
+    int np = 0, rc;
+    SpmmArgs a;
+    a.epi = kEpiSplit;
+    a.V = V;
+    a.Y = U;
+    a.y = y;
+    a.sigma = sigma;
+    a.ld = ld;
+    if ((rc = spmm_maxcut(s, P, prec, a, &np))) return rc;
+    a.V = U;
+    a.Y = V;
+    a.R = U;
+    return spmm_maxcut(s, P, prec, a, &np);
 }
 
 int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws, void *R, double *y,
@@ -350,6 +373,7 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
     if ((rc = alm_refresh(0.0, 0))) return rc;
 
     int status = LRSDP_NOT_CONVERGED;
+    int64_t admm_iters = 0;
     int64_t outer = 0;
     int64_t total_inner = 0;
     double sigma_host = sigma0;
@@ -489,6 +513,49 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
             status = LRSDP_OK;
             break;
         }
+        if (mc && o->phase2 && hs.err1 <= o->switch_err1) {
+            // splitting phase from U = V = R with the current y and sigma; measures
+            // at R = (U + V)/2 every admm_check iterations (R holds V, the first G
+            // slot holds U)
+            void *U = gring[0];
+            const int64_t bytes = n * ld * (prec == LRSDP_F64 ? 8 : 4);
+            LRSDP_HIP_TRY(hipMemcpyAsync(U, R, bytes, hipMemcpyDeviceToDevice, s));
+            const int chk = std::max(1, o->admm_check);
+            int64_t it2 = 0;
+            while (it2 < o->max_admm) {
+                for (int b = 0; b < chk && rc == 0; ++b, ++it2) rc = admm_iter(s, p->csr, prec, U, R, ld, y, sigma_host);
+                if (rc) break;
+                if ((rc = launch_avg(s, prec, U, R, gring[1], n * ld))) break;
+                SpmmArgs ref;
+                ref.epi = kEpiRefresh;
+                ref.V = gring[1];
+                ref.Y = CD;
+                ref.y = y;
+                ref.rn = rn;
+                ref.sigma = 0.0;
+                ref.ld = ld;
+                ref.partials = part_misc;
+                int np = 0;
+                if ((rc = spmm_maxcut(s, p->csr, prec, ref, &np))) break;
+                if ((rc = launch_alm_finalize(s, st, part_misc, np, 0))) break;
+                if ((rc = read_state(c, &hs))) break;
+                if (o->verbose)
+                    fprintf(stderr, "[lrsdp] admm %6lld obj % .10e err1 %.3e err3 % .3e t %.3fs\n", (long long)it2,
+                            hs.obj, hs.err1, hs.err3, elapsed());
+                if (!std::isfinite(hs.obj) || !std::isfinite(hs.err1)) {
+                    rc = set_error(LRSDP_ENUMERIC, "NaN/Inf in the splitting phase");
+                    break;
+                }
+                if (hs.err1 <= o->tol && std::fabs(hs.err3) <= o->tol) {
+                    status = LRSDP_OK;
+                    break;
+                }
+                if (elapsed() > o->time_limit_s) break;
+            }
+            admm_iters = it2;
+            if (rc == 0) LRSDP_HIP_TRY(hipMemcpyAsync(R, gring[1], bytes, hipMemcpyDeviceToDevice, s));
+            break;
+        }
         if (hs.inner_total >= o->max_iter_total || elapsed() > o->time_limit_s) break;
     }
     free_events();
@@ -509,6 +576,7 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
     res->spmm_launches = spmm_n;
     res->spmm_ms = spmm_ms;
     res->spmm_bytes = mc ? maxcut_spmm_bytes(p, prec, o->rank) : completion_grad_bytes(p, prec, o->rank, T);
+    res->admm_iters = admm_iters;
     return status;
 }
 
@@ -791,5 +859,18 @@ extern "C" int lrsdp_warmstart(lrsdp_ctx *c, const lrsdp_problem *p, const float
     const double mean = n > 0 ? hsum / (double)n : 0.0;
     if (!std::isfinite(mean)) return set_error(LRSDP_ENUMERIC, "warm-start penalty prediction is not finite");
     *sigma0 = base * std::exp(std::max(-10.0, std::min(10.0, mean)));
+    return LRSDP_OK;
+}
+
+extern "C" int lrsdp_k_admm(lrsdp_ctx *c, const lrsdp_problem *p, int prec, void *U, void *V, int64_t ld, double *y,
+                            double sigma, int iters) {
+    clear_error();
+    if (!c || !U || !V || !y || iters < 0 || !(sigma > 0)) return set_error(LRSDP_EINVAL, "bad argument");
+    int rc;
+    if ((rc = check_problem(p)) || (rc = check_prec(prec)) || (rc = check_ld(prec, ld))) return rc;
+    if (p->info.kind != LRSDP_MAXCUT) return set_error(LRSDP_EUNSUPPORTED, "splitting step is for MaxCut problems");
+    const int pr = prec == LRSDP_F64 ? LRSDP_F64 : LRSDP_F32;
+    for (int k = 0; k < iters; ++k)
+        if ((rc = admm_iter(c->stream, p->csr, pr, U, V, ld, y, sigma))) return rc;
     return LRSDP_OK;
 }

@@ -566,6 +566,13 @@ __global__ __launch_bounds__(kBlock) void k_grad_init_maxcut(GradInitArgs<S> a) 
     block_sums_store<1>(s, a.partials + (size_t)blockIdx.x * kMaxSums);
 }
 
+// out = (a + b) / 2 elementwise
+template <typename S>
+__global__ __launch_bounds__(kBlock) void k_avg(const S *a, const S *b, S *out, int64_t count) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += (int64_t)gridDim.x * kBlock)
+        out[i] = (S)(0.5 * ((double)a[i] + (double)b[i]));
+}
+
 template <typename S>
 __global__ __launch_bounds__(kBlock) void k_fill(S *p, int64_t count, S v) {
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += (int64_t)gridDim.x * kBlock) p[i] = v;
@@ -718,6 +725,18 @@ int launch_fill(hipStream_t s, int prec, void *p, int64_t count) {
     int nb = grid_for(count, kBlock);
     if (prec == LRSDP_F64) hipLaunchKernelGGL(k_fill<double>, dim3(nb), dim3(kBlock), 0, s, (double *)p, count, 0.0);
     else hipLaunchKernelGGL(k_fill<float>, dim3(nb), dim3(kBlock), 0, s, (float *)p, count, 0.0f);
+    LRSDP_CHECK_LAUNCH();
+    return LRSDP_OK;
+}
+
+int launch_avg(hipStream_t s, int prec, const void *a, const void *b, void *out, int64_t count) {
+    int nb = grid_for(count, kBlock);
+    if (prec == LRSDP_F64)
+        hipLaunchKernelGGL(k_avg<double>, dim3(nb), dim3(kBlock), 0, s, (const double *)a, (const double *)b,
+                           (double *)out, count);
+    else
+        hipLaunchKernelGGL(k_avg<float>, dim3(nb), dim3(kBlock), 0, s, (const float *)a, (const float *)b,
+                           (float *)out, count);
     LRSDP_CHECK_LAUNCH();
     return LRSDP_OK;
 }

@@ -24,6 +24,12 @@
 //      kEpiRefresh  CR_i = (C R)_i, obj_i = R_i.CR_i, res_i = ||R_i||^2 - 1,
 //                   optional multiplier step y_i <- y_i - sigma res_i; sums
 //                   obj, b^T y, ||res||^2
+//      kEpiSplit    splitting half-step (Section 2.2, eq. 2.2 for A = diag): with
+//                   b_i = -(C V)_i + (y_i + 2 sigma) V_i the block of the operator
+//                   for row i is sigma (V_i V_i^T + I), so the exact solve is
+//                   U_i = (b_i - (V_i . b_i) / (1 + ||V_i||^2) V_i) / sigma (written
+//                   to Y); when R is given (the V-step, R = U) the multiplier step
+//                   y_i <- y_i + sigma (1 - R_i . Y_i) follows
 //  * Per-block sums go to a fixed-grid partials array (deterministic).
 //  * BF16 input (float32 path only): the gathered operand is a bfloat16 copy
 //    (row stride ldb = ld rounded up to 8); a lane then covers 8 columns, i.e.
@@ -180,6 +186,33 @@ __device__ __forceinline__ void epilogue(const DevCsr &P, const SpmmArgs &a, int
             if (a.q2) a.q2[row] = q2;
             if (a.rn) a.rn[row] = rr;
         }
+    } else if constexpr (EPI == kEpiSplit) {  // NC = 1
+        const CV v = act[0] ? *reinterpret_cast<const CV *>((const S *)a.V + off[0]) : zero;
+        vfma(acc[0], dg, v);                                   // (C V)_i
+        const double coef = a.y[row] + 2.0 * a.sigma;
+        D4 vv4 = widen(v), cv4 = widen(acc[0]), b4;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) b4.v[c] = fma(coef, vv4.v[c], -cv4.v[c]);
+        double vb = 0.0, vv = 0.0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            vb = fma(vv4.v[c], b4.v[c], vb);
+            vv = fma(vv4.v[c], vv4.v[c], vv);
+        }
+        vb = group_sum<GS>(vb);
+        vv = group_sum<GS>(vv);
+        const double f = vb / (1.0 + vv), is = 1.0 / a.sigma;
+        D4 u4;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) u4.v[c] = (b4.v[c] - f * vv4.v[c]) * is;
+        CV us;
+        narrow(u4, us);
+        if (act[0]) *reinterpret_cast<CV *>((S *)a.Y + off[0]) = us;
+        if (a.R) {
+            const CV r = act[0] ? *reinterpret_cast<const CV *>((const S *)a.R + off[0]) : zero;
+            const double ru = group_sum<GS>(vdot(r, us));
+            if (lane == 0) a.y[row] += a.sigma * (1.0 - ru);
+        }
     } else {  // kEpiRefresh: V = R (storage type, NC = 1)
         double obj = 0.0, rn = 0.0;
 #pragma unroll
@@ -231,7 +264,8 @@ __global__ __launch_bounds__(kBlock) void k_spmm_light(DevCsr P, SpmmArgs a) {
         gather<S, W, NC>(P, a.V, a.ldv, beg, end, lane, active, acc);
         epilogue<S, GS, EPI, NC>(P, a, row, lane, active, acc, s);
     }
-    if constexpr (EPI != kEpiPlain) block_sums_store<kLsSums>(s, a.partials + (size_t)blockIdx.x * kMaxSums);
+    if constexpr (EPI == kEpiLS || EPI == kEpiRefresh)
+        block_sums_store<kLsSums>(s, a.partials + (size_t)blockIdx.x * kMaxSums);
 }
 
 // Segments of heavy rows: partial sums to seg_buf (16 chunks = 256 bytes per segment).
@@ -297,7 +331,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_fixup(DevCsr P, SpmmArgs a, int
         }
         __syncthreads();
     }
-    if constexpr (EPI != kEpiPlain)
+    if constexpr (EPI == kEpiLS || EPI == kEpiRefresh)
         block_sums_store<kLsSums>(s, a.partials + (size_t)(part_base + blockIdx.x) * kMaxSums);
 }
 
@@ -347,6 +381,7 @@ int launch_epi(hipStream_t st, const DevCsr &P, const SpmmArgs &a, int *nparts) 
     switch (a.epi) {
         case kEpiPlain: return launch_gs<S, kEpiPlain, NC>(st, P, a, nparts);
         case kEpiLS: return launch_gs<S, kEpiLS, NC>(st, P, a, nparts);
+        case kEpiSplit: return launch_gs<S, kEpiSplit, 1>(st, P, a, nparts);
         default: return launch_gs<S, kEpiRefresh, 1>(st, P, a, nparts);
     }
 }
@@ -359,7 +394,7 @@ int spmm_maxcut(hipStream_t st, const DevCsr &P, int prec, const SpmmArgs &a_in,
     if (a.ld <= 0 || (a.ld * esz) % 16 != 0 || a.ld * esz > 256)
         return set_error(LRSDP_EINVAL, "ld = %lld: row bytes must be a positive multiple of 16, at most 256",
                          (long long)a.ld);
-    const bool bf = prec == LRSDP_F32_BF16IN && a.epi != kEpiRefresh;
+    const bool bf = prec == LRSDP_F32_BF16IN && a.epi != kEpiRefresh && a.epi != kEpiSplit;
     if (bf && a.epi == kEpiLS && !a.Vown)
         return set_error(LRSDP_EINVAL, "bfloat16 line-search SpMM needs the float32 operand");
     a.ldv = bf ? bf16_ld(a.ld) : a.ld;

@@ -40,14 +40,14 @@ template <int W>
 __global__ __launch_bounds__(kBlock) void k_node_stats(DevCsr P, float4 *stats) {
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < P.n; i += (int64_t)gridDim.x * kBlock) {
         const int b = P.row_ptr[i], e = P.row_ptr[i + 1];
-        float s = 0.f, a = 0.f;
+        double s = 0.0, a = 0.0;
         for (int k = b; k < e; ++k) {
-            const float w = edge_w<W>(P, k, P.col[k]);
+            const double w = edge_w<W>(P, k, P.col[k]);
             s += w;
-            a += fabsf(w);
+            a += fabs(w);
         }
         const float d = (float)(e - b);
-        stats[i] = make_float4(d, s, a, log1pf(d));
+        stats[i] = make_float4(d, (float)s, (float)a, (float)log1p((double)(e - b)));
     }
 }
 
@@ -60,18 +60,23 @@ __global__ __launch_bounds__(kBlock) void k_features(DevCsr P, const float4 *sta
         const float d = si.x, a = si.z, l = si.w;
         const float bal = si.y / fmaxf(a, 1.f);
         const int b = P.row_ptr[i], e = P.row_ptr[i + 1];
-        float sl = 0.f, sl2 = 0.f, swb = 0.f, sinv = 0.f, sw = 0.f, lmax = -1e30f, sdd = 0.f;
+        // Neighbour sums in double: the spread feature (std of l over the
+        // neighbours) cancels badly in float for hubs whose neighbours have
+        // near-equal degrees.  This pass runs once per graph.
+        double sl = 0.0, sl2 = 0.0, swb = 0.0, sinv = 0.0, sw = 0.0, sdd = 0.0;
+        float lmax = -1e30f;
         for (int k = b; k < e; ++k) {
             const int32_t c = P.col[k];
-            const float w = edge_w<W>(P, k, c);
+            const double w = edge_w<W>(P, k, c);
             const float4 sj = stats[c & 0x7fffffff];
-            sl += sj.w;
-            sl2 += sj.w * sj.w;
-            swb += w * (sj.y / fmaxf(sj.z, 1.f));
-            sinv += 1.f / (1.f + sj.x);
+            const double lj = (double)sj.w - (double)l;
+            sl += lj;
+            sl2 += lj * lj;
+            swb += w * (double)(sj.y / fmaxf(sj.z, 1.f));
+            sinv += 1.0 / (1.0 + (double)sj.x);
             sw += w;
             lmax = fmaxf(lmax, sj.w);
-            sdd += sj.x / (d + sj.x);
+            sdd += (double)sj.x / ((double)d + (double)sj.x);
         }
         float f[kNF];
         f[0] = l;
@@ -84,15 +89,15 @@ __global__ __launch_bounds__(kBlock) void k_features(DevCsr P, const float4 *sta
         f[12] = log1pf(dbar);
         f[15] = 1.f;
         if (e > b) {
-            const float inv = 1.f / (float)(e - b);
-            const float ml = sl * inv;
-            f[3] = ml;
-            f[4] = sqrtf(fmaxf(sl2 * inv - ml * ml, 0.f));
-            f[5] = swb * inv;
-            f[6] = sinv * inv;
-            f[10] = sw * inv;
+            const double inv = 1.0 / (double)(e - b);
+            const double ml = sl * inv;  // mean of l_j - l_i
+            f[3] = (float)((double)l + ml);
+            f[4] = (float)sqrt(fmax(sl2 * inv - ml * ml, 0.0));
+            f[5] = (float)(swb * inv);
+            f[6] = (float)(sinv * inv);
+            f[10] = (float)(sw * inv);
             f[13] = lmax - l;
-            f[14] = sdd * inv;
+            f[14] = (float)(sdd * inv);
         } else {
             f[3] = f[4] = f[5] = f[6] = f[10] = f[13] = f[14] = 0.f;
         }

@@ -42,7 +42,8 @@ class Options(C.Structure):
         ("sigma0", C.c_double), ("sigma_factor", C.c_double), ("sigma_max_ratio", C.c_double),
         ("feas_decrease", C.c_double), ("eta0", C.c_double), ("eta_factor", C.c_double),
         ("eta_min", C.c_double), ("check_every", C.c_int), ("refresh_every", C.c_int),
-        ("profile", C.c_int), ("verbose", C.c_int),
+        ("profile", C.c_int), ("verbose", C.c_int), ("phase2", C.c_int), ("switch_err1", C.c_double),
+        ("admm_check", C.c_int), ("max_admm", C.c_int),
     ]
 
 
@@ -52,6 +53,7 @@ class Result(C.Structure):
         ("err3", C.c_double), ("sigma", C.c_double), ("seconds", C.c_double),
         ("outer", C.c_int64), ("inner", C.c_int64), ("status", C.c_int),
         ("spmm_launches", C.c_int), ("spmm_ms", C.c_double), ("spmm_bytes", C.c_double),
+        ("admm_iters", C.c_int64),
     ]
 
     def as_dict(self):
@@ -88,6 +90,7 @@ _SIGS = {
     "lrsdp_k_cubic": (C.c_int, [_P, _P, _P]),
     "lrsdp_k_alm": (C.c_int, [_P, _P, C.c_int, _P, _I64, _P, C.c_double, _P, _P]),
     "lrsdp_k_lbfgs_dir": (C.c_int, [_P, C.c_int, _I64, _I64, _P, _P, _P, C.c_int, _P]),
+    "lrsdp_k_admm": (C.c_int, [_P, _P, C.c_int, _P, _P, _I64, _P, C.c_double, C.c_int]),
     "lrsdp_mlp_param_count": (C.c_int, []),
     "lrsdp_ws_features": (C.c_int, [_P, _P, _P, _P]),
     "lrsdp_mlp_forward": (C.c_int, [_P, _P, _P, _I64, _P]),
@@ -328,3 +331,8 @@ def warmstart(ctx, prob, params, work, y0):
 def ws_targets(ctx, prob, stats, y, log_sigma_ratio, target):
     _check(load().lrsdp_ws_targets(ctx.handle, prob.handle, _ptr(stats), _ptr(y), float(log_sigma_ratio),
                                    _ptr(target)))
+
+
+def k_admm(ctx, prob, prec, U, V, y, sigma, iters):
+    _check(load().lrsdp_k_admm(ctx.handle, prob.handle, prec, _ptr(U), _ptr(V), U.shape[1], _ptr(y),
+                               float(sigma), int(iters)))

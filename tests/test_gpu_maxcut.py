@@ -371,3 +371,54 @@ def test_solve_refresh_every_matches(ctx):
     ores = alm_solve(maxcut_problem(n, u, v, w), R0, opts=OOptions())
     assert rc == L.OK
     assert abs(res.obj - ores.obj) <= 1e-5 * abs(ores.obj)
+
+
+@pytest.mark.parametrize("case", ["er_1k", "pm1_ragged", "cl_heavy", "isolated"])
+def test_admm_step_parity(ctx, case):
+    # splitting iterations: per-row exact solves on the GPU vs CG (Algorithm 2) in the oracle
+    import torch
+    from oracle.alm import admm_step
+    n, r, prob, op = setup(ctx, case)
+    r = min(r, 16)
+    print_case(test="admm", case=case)
+    rng = np.random.default_rng(18)
+    U = init_factor(n, r, 19) + 0.01 * rng.standard_normal((n, r))
+    V = U + 0.01 * rng.standard_normal((n, r))
+    y = -np.abs(rng.standard_normal(n))
+    # A penalty above the default initial one (4 sum|C_ij| / m = 20 on the
+    # Chung-Lu graph): at sigma = 3 the iteration diverges on its hub rows and
+    # rounding differences grow ~100x per step.
+    sigma = 30.0
+    Ud, Vd, yd = dev_factor(U, L.F64), dev_factor(V, L.F64), dev_vec(y)
+    L.k_admm(ctx, prob, L.F64, Ud, Vd, yd, sigma, 3)
+    torch.cuda.synchronize()
+    Uo, Vo, yo = U, V, y
+    for _ in range(3):
+        Uo, Vo, yo = admm_step(op, Uo, Vo, yo, sigma)
+    scale = 1.0 + np.abs(Uo).max()
+    assert np.max(np.abs(host(Ud, r) - Uo)) <= 1e-9 * scale
+    assert np.max(np.abs(host(Vd, r) - Vo)) <= 1e-9 * scale
+    assert np.max(np.abs(yd.cpu().numpy() - yo)) <= 1e-9 * (1 + np.abs(yo).max())
+    # several iterations in one call equal the same number of single calls
+    U2, V2, y2 = dev_factor(U, L.F64), dev_factor(V, L.F64), dev_vec(y)
+    L.k_admm(ctx, prob, L.F64, U2, V2, y2, sigma, 3)
+    torch.cuda.synchronize()
+    U1, V1, y1 = dev_factor(U, L.F64), dev_factor(V, L.F64), dev_vec(y)
+    for _ in range(3):
+        L.k_admm(ctx, prob, L.F64, U1, V1, y1, sigma, 1)
+    torch.cuda.synchronize()
+    assert torch.equal(U1, U2) and torch.equal(V1, V2) and torch.equal(y1, y2)
+
+
+def test_solve_phase2_matches_oracle(ctx):
+    n, u, v, w, r = graph("er_1k")
+    R0 = init_factor(n, 16, 15051)
+    print_case(test="solve_phase2", case="er_1k")
+    rc, res, R, y = gpu_solve(ctx, n, u, v, w, R0, L.F64, phase2=1, switch_err1=1e-3)
+    ores = alm_solve(maxcut_problem(n, u, v, w), R0, opts=OOptions(phase2=True, switch_err1=1e-3))
+    rc0, res0, _, _ = gpu_solve(ctx, n, u, v, w, R0, L.F64)
+    print("phase2", res.as_dict(), "oracle", ores.obj, ores.inner, ores.history[-1], "alm only", res0.as_dict())
+    assert rc == L.OK and ores.converged and res.admm_iters > 0
+    assert abs(res.obj - ores.obj) <= 1e-5 * abs(ores.obj)
+    m = K.alm_measures(maxcut_problem(n, u, v, w), R, y)
+    assert m["err1"] <= 1e-5 and abs(m["err3"]) <= 1e-5
