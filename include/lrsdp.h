@@ -300,7 +300,10 @@ int lrsdp_mlp_grad(lrsdp_ctx *ctx, const float *params, const float *feat, const
 int lrsdp_mlp_adam(lrsdp_ctx *ctx, float *params, float *m, float *v, const float *grad, int step, float lr);
 
 /* Warm start for the problem: y0 (device m float64) and *sigma0 (host).
- * work: device float32 scratch of 22 n.  Synchronises the stream. */
+ * work: device float32 scratch of 22 n.  Synchronises the stream.
+ * Returns LRSDP_ENUMERIC (y0 contents then undefined, *sigma0 untouched) when
+ * any predicted multiplier or the penalty is not finite; the caller then
+ * solves from the cold start. */
 int lrsdp_warmstart(lrsdp_ctx *ctx, const lrsdp_problem *prob, const float *params, float *work, double *y0,
                     double *sigma0);
 

@@ -851,13 +851,14 @@ extern "C" int lrsdp_warmstart(lrsdp_ctx *c, const lrsdp_problem *p, const float
     if ((rc = ws_features(s, p->csr, feat, stats))) return rc;
     if ((rc = mlp_forward(s, params, feat, n, out))) return rc;
     if ((rc = warm_y0(s, out, stats, n, y0, part, sum))) return rc;
-    double hsum = 0.0;
-    LRSDP_HIP_TRY(hipMemcpyAsync(c->pinned, sum, sizeof(double), hipMemcpyDeviceToHost, s));
+    double hsum[2] = {0.0, 0.0};
+    LRSDP_HIP_TRY(hipMemcpyAsync(c->pinned, sum, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
     LRSDP_HIP_TRY(hipStreamSynchronize(s));
-    std::memcpy(&hsum, c->pinned, sizeof(double));
+    std::memcpy(hsum, c->pinned, 2 * sizeof(double));
     const double base = std::max(4.0 * p->info.c_l1 / (double)p->info.m, 1e-8);
-    const double mean = n > 0 ? hsum / (double)n : 0.0;
-    if (!std::isfinite(mean)) return set_error(LRSDP_ENUMERIC, "warm-start penalty prediction is not finite");
+    const double mean = n > 0 ? hsum[0] / (double)n : 0.0;
+    if (!std::isfinite(mean) || !std::isfinite(hsum[1]))
+        return set_error(LRSDP_ENUMERIC, "warm-start prediction is not finite");
     *sigma0 = base * std::exp(std::max(-10.0, std::min(10.0, mean)));
     return LRSDP_OK;
 }

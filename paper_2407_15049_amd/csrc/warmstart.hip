@@ -306,12 +306,14 @@ __global__ __launch_bounds__(kBlock) void k_adam(float *theta, float *m, float *
 // y0_i = -out_i0 * a_i / 4; s = sum_i out_i1 (per-block partials)
 __global__ __launch_bounds__(kBlock) void k_warm_y0(const float *out, const float4 *stats, int64_t n, double *y0,
                                                     double *partials) {
-    double s[1] = {0.0};
+    double s[2] = {0.0, 0.0};
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
-        y0[i] = -0.25 * (double)out[2 * i] * (double)stats[i].z;
+        const double yi = -0.25 * (double)out[2 * i] * (double)stats[i].z;
+        y0[i] = yi;
         s[0] += (double)out[2 * i + 1];
+        s[1] += yi;  // only read for finiteness: a NaN or Inf anywhere shows here
     }
-    block_sums_store<1>(s, partials + (size_t)blockIdx.x * kMaxSums);
+    block_sums_store<2>(s, partials + (size_t)blockIdx.x * kMaxSums);
 }
 
 // training targets: t_i = -4 y_i / a_i (0 for isolated nodes), s_i = s
@@ -392,7 +394,7 @@ int warm_y0(hipStream_t s, const float *out, const float4 *stats, int64_t n, dou
     const int nb = blocks_for(n);
     hipLaunchKernelGGL(k_warm_y0, dim3(nb), dim3(kBlock), 0, s, out, stats, n, y0, partials);
     LRSDP_CHECK_LAUNCH();
-    return launch_reduce(s, partials, nb, 1, mean_out1);
+    return launch_reduce(s, partials, nb, 2, mean_out1);
 }
 
 int mlp_param_count() { return kNParam; }

@@ -104,10 +104,19 @@ def train(ctx, data, steps=400, lr=3e-3, seed=0, log=None):
 
 
 def warm_start(ctx, prob, params):
-    """Predicted (y0 device float64, sigma0) for a MaxCut problem."""
+    """Predicted (y0 device float64, sigma0) for a MaxCut problem.
+
+    Fallback: when the prediction is not finite the cold start is returned,
+    y0 = 0 and sigma0 = 0.0 (0 selects the default initial penalty)."""
     import torch
     n = prob.info.n
     work = torch.empty(22 * n, dtype=torch.float32, device=ctx.torch_device)
     y0 = torch.empty(n, dtype=torch.float64, device=ctx.torch_device)
-    sigma0 = L.warmstart(ctx, prob, params, work, y0)
+    try:
+        sigma0 = L.warmstart(ctx, prob, params, work, y0)
+    except L.LrsdpError as e:
+        if e.code != L.ENUMERIC:
+            raise
+        y0.zero_()
+        sigma0 = 0.0
     return y0, sigma0

@@ -190,7 +190,11 @@ def test_solve_fully_observed_nuclear_norm(ctx):
 # Solve cases use the planted rank as the factor rank: with more columns than the
 # planted rank the Burer-Monteiro iteration converges sublinearly (the extra
 # columns decay slowly), which the oracle cannot follow in seconds.
-SOLVE_CASES = {"tiny": (40, 31, 2, 7, 2), "medium": (300, 250, 4, 20, 4)}
+# (n1, n2, planted rank, samples per row, factor rank).  At 7 samples per row the
+# rank-2 tiny case ends at a spurious stationary point of the factorization
+# under the default penalty schedule (oracle and GPU alike); 10 per row
+# converges and recovers the planted matrix.
+SOLVE_CASES = {"tiny": (40, 31, 2, 10, 2), "medium": (300, 250, 4, 20, 4)}
 
 
 @pytest.mark.parametrize("case", list(SOLVE_CASES))

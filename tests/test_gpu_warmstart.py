@@ -149,3 +149,18 @@ def test_trained_warm_start_gains(ctx):
         print(mode, r.as_dict())
         assert rc == L.OK
     assert res["warm"].inner < res["cold"].inner
+
+
+def test_warmstart_non_finite_falls_back_to_cold(ctx):
+    import torch
+    n, u, v, w = graph("pm1")
+    prob = L.Problem.maxcut(n, u, v, w).upload(ctx)
+    theta = mlp.init_params(9).astype(np.float32)
+    theta[mlp.NPARAM - 2] = np.nan          # b3[0]: every t_i becomes NaN, log-penalty stays finite
+    y0, sigma0 = W.warm_start(ctx, prob, dev(theta))
+    torch.cuda.synchronize()
+    assert sigma0 == 0.0 and torch.count_nonzero(y0).item() == 0
+    with pytest.raises(L.LrsdpError) as e:
+        L.warmstart(ctx, prob, dev(theta), torch.empty(22 * n, dtype=torch.float32, device="cuda"),
+                    torch.empty(n, dtype=torch.float64, device="cuda"))
+    assert e.value.code == L.ENUMERIC
