@@ -55,6 +55,30 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "spmm_maxcut_traffic_pair_1m_f64.md")
+SPMM_SOURCES = [os.path.join(ROOT, "paper_2407_15049_amd", "csrc", f)
+                for f in ("spmm_maxcut.hip", "device.h", "kernels.h")]
+
+
+def measured_traffic():
+    """HBM bytes per SpMM launch from the committed counter summary, or None when
+    the SpMM sources changed since the counters were taken."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    fields = dict(line.split(": ", 1) for line in text.splitlines()
+                  if line.startswith(("source_sha256: ", "traffic_bytes_per_launch: ")))
+    h = hashlib.sha256()
+    for f in SPMM_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    if fields.get("source_sha256") != h.hexdigest():
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -129,6 +153,7 @@ def main():
     spmm_n = sum(res.spmm_launches for v in recs.values() for _, res in v)
     spmm_bytes = sum(res.spmm_bytes * res.spmm_launches for v in recs.values() for _, res in v)
     achieved = (spmm_bytes / 1e9) / (spmm_ms / 1e3) if spmm_ms > 0 else None
+    traffic = measured_traffic()
 
     paths = {"f64": {}}
     for run in runs:
@@ -220,7 +245,8 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
-            "traffic": None,
+            "traffic": traffic,
+            "traffic_gbs": round(traffic / 1e9 / (spmm_ms / 1e3 / spmm_n), 1) if traffic and spmm_n else None,
             "launches": spmm_n,
             "avg_us": round(1e3 * spmm_ms / max(spmm_n, 1), 2),
             "alg_bytes_per_launch": {run["name"]: recs[run["name"]][-1][1].spmm_bytes for run in runs},
