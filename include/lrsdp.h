@@ -299,6 +299,46 @@ int lrsdp_mlp_grad(lrsdp_ctx *ctx, const float *params, const float *feat, const
  * device arrays of nparam float32. */
 int lrsdp_mlp_adam(lrsdp_ctx *ctx, float *params, float *m, float *v, const float *grad, int step, float lr);
 
+/* ---- dual certificate --------------------------------------------------------
+ * Smallest eigenvalue of S = C - A*(y) (the dual slack of the error measures,
+ * Section 4.2) by block Lanczos on the problem's own SpMM, blocks of 8
+ * float64 vectors, no stored basis.  For any y it yields a lower bound on the
+ * optimum: MaxCut (diag(X) = 1, so trace X = n): b^T y + n min(0, lambda_lb);
+ * completion (C = I): b^T y / max(1, 1 - lambda_lb), since 1 - lambda_min is the
+ * spectral norm of the n1 x n2 matrix of the y_k.
+ */
+typedef struct {
+    double  lambda_min;  /* smallest Ritz value of S (>= the true lambda_min)     */
+    double  resid;       /* residual norm of that Ritz pair                       */
+    double  lambda_lb;   /* lambda_min - resid: the value the bound uses          */
+    double  dual_bound;  /* lower bound on the optimum from y and lambda_lb       */
+    double  err2;        /* max(0, -lambda_min) / (1 + ||vec(C)||_1)              */
+    double  by;          /* b^T y                                                 */
+    int64_t iters;       /* block Lanczos steps taken                             */
+    int     status;      /* 0: resid <= tol; 1: max_iter reached; 2: the Krylov
+                            space became invariant (resid = 0, lambda exact up to
+                            rounding)                                             */
+    int     block;       /* block size (8)                                        */
+} lrsdp_cert;
+
+/* Device workspace for lrsdp_certify with at most max_iter steps:
+ * 4 n x 8 float64 blocks plus max_iter KB and 0.3 MB of partial sums. */
+int lrsdp_certify_workspace_bytes(const lrsdp_problem *prob, int max_iter,
+                                  size_t *bytes);
+
+/* Run block Lanczos on S = C - A*(y) (y: device float64, m entries) from a
+ * seeded random start block until the residual of the smallest Ritz pair is
+ * <= tol (absolute) or max_iter steps; checks every 10 steps.  work: caller
+ * device memory, 256-byte aligned, of lrsdp_certify_workspace_bytes.
+ * Synchronises the context stream.  Errors: EINVAL (arguments, not uploaded),
+ * EUNSUPPORTED (n < 16), ENOMEM (workspace short), ENUMERIC (rank-deficient
+ * start block or non-finite values).  The bound is exact up to the loss of
+ * orthogonality of the Lanczos basis (no re-orthogonalisation).
+ */
+int lrsdp_certify(lrsdp_ctx *ctx, const lrsdp_problem *prob, const double *y,
+                  int max_iter, double tol, uint64_t seed, void *work,
+                  size_t work_bytes, lrsdp_cert *out);
+
 /* Warm start for the problem: y0 (device m float64) and *sigma0 (host).
  * work: device float32 scratch of 22 n.  Synchronises the stream.
  * Returns LRSDP_ENUMERIC (y0 contents then undefined, *sigma0 untouched) when

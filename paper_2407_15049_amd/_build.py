@@ -18,6 +18,7 @@ LIB = os.path.join(LIBDIR, "liblrsdp.so")
 SOURCES = [
     "problem.hip",
     "spmm_maxcut.hip",
+    "certify.hip",
     "solver_kernels.hip",
     "entry_kernels.hip",
     "completion.hip",

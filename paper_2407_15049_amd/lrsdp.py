@@ -68,6 +68,17 @@ class ProblemInfo(C.Structure):
     ]
 
 
+class Cert(C.Structure):
+    _fields_ = [
+        ("lambda_min", C.c_double), ("resid", C.c_double), ("lambda_lb", C.c_double),
+        ("dual_bound", C.c_double), ("err2", C.c_double), ("by", C.c_double),
+        ("iters", C.c_int64), ("status", C.c_int), ("block", C.c_int),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 _P = C.c_void_p
 _I64 = C.c_int64
 _SIGS = {
@@ -98,6 +109,8 @@ _SIGS = {
     "lrsdp_mlp_adam": (C.c_int, [_P, _P, _P, _P, _P, C.c_int, C.c_float]),
     "lrsdp_warmstart": (C.c_int, [_P, _P, _P, _P, _P, C.POINTER(C.c_double)]),
     "lrsdp_ws_targets": (C.c_int, [_P, _P, _P, _P, C.c_double, _P]),
+    "lrsdp_certify_workspace_bytes": (C.c_int, [_P, C.c_int, C.POINTER(C.c_size_t)]),
+    "lrsdp_certify": (C.c_int, [_P, _P, _P, C.c_int, C.c_double, C.c_uint64, _P, C.c_size_t, C.POINTER(Cert)]),
 }
 
 _lib = None
@@ -336,3 +349,21 @@ def ws_targets(ctx, prob, stats, y, log_sigma_ratio, target):
 def k_admm(ctx, prob, prec, U, V, y, sigma, iters):
     _check(load().lrsdp_k_admm(ctx.handle, prob.handle, prec, _ptr(U), _ptr(V), U.shape[1], _ptr(y),
                                float(sigma), int(iters)))
+
+
+def certify_workspace_bytes(prob, max_iter):
+    b = C.c_size_t()
+    _check(load().lrsdp_certify_workspace_bytes(prob.handle, max_iter, C.byref(b)))
+    return b.value
+
+
+def certify(ctx, prob, y, max_iter=300, tol=1e-6, seed=15049, work=None):
+    """Smallest eigenvalue of C - A*(y) (y: device float64) and the dual bound it
+    gives; returns a Cert.  `work` is a device uint8 tensor (allocated here if None)."""
+    import torch
+    if work is None:
+        work = torch.empty(certify_workspace_bytes(prob, max_iter), dtype=torch.uint8, device=ctx.torch_device)
+    out = Cert()
+    _check(load().lrsdp_certify(ctx.handle, prob.handle, _ptr(y), max_iter, tol, seed, _ptr(work),
+                                work.numel() * work.element_size(), C.byref(out)))
+    return out
