@@ -131,6 +131,22 @@ def main():
             raise RuntimeError(f"{run['name']} prec {prec} did not converge: {res.as_dict()}")
         return dt, res
 
+    cert_ws = {}
+
+    def cert_of(run, y, obj):
+        """Dual certificate of the multipliers y (outside every timed region)."""
+        if run["name"] not in cert_ws:
+            cert_ws[run["name"]] = torch.empty(L.certify_workspace_bytes(run["prob"], 600), dtype=torch.uint8,
+                                               device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c = L.certify(ctx, run["prob"], y, max_iter=600, tol=1e-8 * abs(obj) / run["n"],
+                      work=cert_ws[run["name"]])
+        dt = time.perf_counter() - t0
+        gap = (obj - c.dual_bound) / (1.0 + abs(obj) + abs(c.dual_bound))
+        return dict(lambda_min=c.lambda_min, cert_resid=c.resid, dual_bound=c.dual_bound, cert_gap=gap,
+                    err2=c.err2, cert_iters=c.iters, cert_s=round(dt, 4))
+
     for w in range(args.warmup):
         for run in runs:
             dt, res = solve(run, L.F64)
@@ -158,22 +174,30 @@ def main():
     paths = {"f64": {}}
     for run in runs:
         dt, res = recs[run["name"]][-1]
-        paths["f64"][run["name"]] = dict(
-            seconds=round(dt, 4), outer=res.outer, inner=res.inner, obj=res.obj, err1=res.err1,
-            err3=res.err3, spmm_us=round(1e3 * res.spmm_ms / max(res.spmm_launches, 1), 2))
-    def record(path, run, dt, res, extra=None):
+        rec = dict(seconds=round(dt, 4), outer=res.outer, inner=res.inner, obj=res.obj, err1=res.err1,
+                   err3=res.err3, spmm_us=round(1e3 * res.spmm_ms / max(res.spmm_launches, 1), 2))
+        if not args.short:
+            rec.update(cert_of(run, run["per"][L.F64]["y"], res.obj))
+            log(f"f64 {run['name']} certificate: lambda_min {rec['lambda_min']:.3e} gap {rec['cert_gap']:.2e} "
+                f"({rec['cert_iters']} steps, {rec['cert_s']}s)")
+        paths["f64"][run["name"]] = rec
+
+    def record(path, run, dt, res, extra=None, y=None):
         o64 = paths["f64"][run["name"]]["obj"]
         rec = dict(seconds=round(dt, 4), outer=res.outer, inner=res.inner, obj=res.obj, err1=res.err1,
                    err3=res.err3, obj_rel_vs_f64=abs(res.obj - o64) / abs(o64),
                    spmm_us=round(1e3 * res.spmm_ms / max(res.spmm_launches, 1), 2))
         rec.update(extra or {})
+        if y is not None and not args.short:
+            rec.update(cert_of(run, y, res.obj))
         paths.setdefault(path, {})[run["name"]] = rec
-        log(f"{path} {run['name']} {dt:.3f}s outer {res.outer} inner {res.inner} obj {res.obj:.8e}")
+        log(f"{path} {run['name']} {dt:.3f}s outer {res.outer} inner {res.inner} obj {res.obj:.8e}"
+            + (f" cert gap {rec['cert_gap']:.2e}" if "cert_gap" in rec else ""))
 
     if not args.no_f32:
         for run in runs:
             dt, res = solve(run, L.F32)
-            record("f32", run, dt, res)
+            record("f32", run, dt, res, y=run["per"][L.F32]["y"])
         # bfloat16 gathered operand (float32 iterate, exact gradient every 25 iterations)
         for run in runs:
             p = run["per"][L.F32]
@@ -185,7 +209,7 @@ def main():
             t0 = time.perf_counter()
             rc, res = L.solve(ctx, run["prob"], p["R"], p["y"], o, workspace=ws)
             torch.cuda.synchronize()
-            record("f32_bf16in", run, time.perf_counter() - t0, res, dict(converged=rc == L.OK))
+            record("f32_bf16in", run, time.perf_counter() - t0, res, dict(converged=rc == L.OK), y=p["y"])
             del ws
         if not args.no_warm:
             from paper_2407_15049_amd import warmstart as W
@@ -208,7 +232,8 @@ def main():
                 o = L.default_options(prec=L.F32, rank=run["r"], ld=p["opts"].ld, profile=1, sigma0=sigma0)
                 rc, res = L.solve(ctx, run["prob"], p["R"], p["y"], o, workspace=p["ws"])
                 torch.cuda.synchronize()
-                record("f32_warm", run, time.perf_counter() - t0, res, dict(sigma0=sigma0, converged=rc == L.OK))
+                record("f32_warm", run, time.perf_counter() - t0, res, dict(sigma0=sigma0, converged=rc == L.OK),
+                       y=p["y"])
             paths["f32_warm"]["model"] = warm_info
 
     if args.copy_calibration:

@@ -13,13 +13,20 @@
 // float64 (a 64-byte row: one 4-lane group of the SpMM).  Per step:
 //   W = S Q_j                                   (the problem's own SpMM)
 //   A_j = Q_j^T W                               (Gram kernel + reduction)
-//   W <- W - Q_j A_j - Q_{j-1} B_{j-1}^T        (fused with the Gram W^T W)
-//   W = Q_{j+1} B_j                             (Cholesky QR: B_j upper triangular)
+//   W <- W - Q_j A_j - Q_{j-1} B_{j-1}^T        (fused with Q_j^T W, Q_{j-1}^T W)
+//   W <- W - Q_j (Q_j^T W) - Q_{j-1} (Q_{j-1}^T W)   (one local re-orthogonalisation,
+//                                                  fused with the Gram W^T W)
+//   W = Q_{j+1} B_j                             (Cholesky QR applied twice, so that
+//                                                Q_{j+1} stays orthonormal when W is
+//                                                ill conditioned; B_j upper triangular)
 // S Q_j = Q_{j-1} B_{j-1}^T + Q_j A_j + Q_{j+1} B_j, so T_k, the block
 // tridiagonal matrix of the A_j and B_j, is S projected on the Krylov space.
 // No basis is kept (memory: four n x 8 blocks) and there is no global
 // re-orthogonalisation: the extreme Ritz values converge regardless (copies of
-// converged ones may appear; they do not lower the smallest).  The smallest
+// converged ones may appear; they do not lower the smallest).  Within a step
+// orthonormality is kept: a single Cholesky QR of an ill-conditioned W (common
+// once the large eigenvalues of hub rows have converged) loses it and then the
+// Ritz values leave the spectrum.  The smallest
 // eigenvalue theta of T_k is found on the host by bisection on the inertia of
 // the band LDL^T of T_k - sigma I, its eigenvector s by inverse iteration, and
 // the residual of the Ritz pair is ||B_k s_last|| (s_last = last block of s).
@@ -27,6 +34,7 @@
 // up to the loss of orthogonality of the basis.
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstring>
 #include <vector>
 
@@ -62,11 +70,14 @@ __global__ __launch_bounds__(kBlock) void k_cert_random(double *Q, int64_t count
     }
 }
 
-// Sum the per-lane accumulators acc[k] (column c = lane & 7 of X, column k of
-// Y) over the wave and the workgroup, and store the 64 entries (X^T Y)[c][k]
-// of this workgroup to part[blockIdx.x * 64 + c * 8 + k].  Fixed order.
-__device__ __forceinline__ void gram_store(double (&acc)[kCB], double *part) {
-    __shared__ double sh[kBlock / 64][kCS];
+// Partial sums of a Gram kernel: per workgroup, kCP doubles (two 8 x 8
+// matrices; single-matrix kernels fill the first kCS).
+constexpr int kCP = 2 * kCS;
+
+// Sum the per-lane accumulators acc[k] (column c = lane & 7 of the left
+// operand, column k of the right one) over the wave and the workgroup and
+// store (X^T Y)[c][k] at part[blockIdx.x * kCP + off + c * 8 + k].  Fixed order.
+__device__ __forceinline__ void gram_store(double (&acc)[kCB], double *part, int off, double (*sh)[kCP]) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, c = threadIdx.x & 7;
 #pragma unroll
     for (int k = 0; k < kCB; ++k) {
@@ -74,98 +85,146 @@ __device__ __forceinline__ void gram_store(double (&acc)[kCB], double *part) {
         v += __shfl_xor(v, 8, 64);
         v += __shfl_xor(v, 16, 64);
         v += __shfl_xor(v, 32, 64);
-        if (lane < kCB) sh[wave][c * kCB + k] = v;
+        if (lane < kCB) sh[wave][off + c * kCB + k] = v;
     }
+}
+
+__device__ __forceinline__ void part_store(double *part, int count, double (*sh)[kCP]) {
     __syncthreads();
-    if (threadIdx.x < kCS) {
+    if (threadIdx.x < count) {
         double t = 0.0;
 #pragma unroll
         for (int w = 0; w < kBlock / 64; ++w) t += sh[w][threadIdx.x];
-        part[(size_t)blockIdx.x * kCS + threadIdx.x] = t;
+        part[(size_t)blockIdx.x * kCP + threadIdx.x] = t;
     }
 }
 
-// part <- per-workgroup partials of X^T Y (n x 8 row-major blocks).  Eight
-// lanes own a row, lane c its entry c; the other entries of the row come by
-// shuffles inside the 8-lane group (all eight share the row, so all are active).
-__global__ __launch_bounds__(kBlock) void k_cert_gram(const double *__restrict__ X, const double *__restrict__ Y,
-                                                      int64_t n, double *part) {
+// Row i of an n x 8 block is owned by eight consecutive lanes, lane c holding
+// entry c; other entries of the row come by shuffles inside the 8-lane group
+// (the eight lanes share the row, so all of them are active together).
+#define CERT_ROWS(i)                                                                           \
+    for (int64_t i = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kCB; i < n;                \
+         i += (int64_t)gridDim.x * (kBlock / kCB))
+
+// part <- partials of Q1^T Y (entries 0..63) and, if Q2 is given, Q2^T Y (64..127).
+__global__ __launch_bounds__(kBlock) void k_cert_proj(const double *__restrict__ Q1, const double *__restrict__ Q2,
+                                                      const double *__restrict__ Y, int64_t n, double *part) {
+    __shared__ double sh[kBlock / 64][kCP];
     const int lane = threadIdx.x & 63, c = threadIdx.x & 7, base = lane & ~7;
-    double acc[kCB] = {0, 0, 0, 0, 0, 0, 0, 0};
-    const int64_t stride = (int64_t)gridDim.x * (kBlock / kCB);
-    for (int64_t i = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kCB; i < n; i += stride) {
-        const double x = X[i * kCB + c];
+    double a1[kCB] = {0, 0, 0, 0, 0, 0, 0, 0}, a2[kCB] = {0, 0, 0, 0, 0, 0, 0, 0};
+    CERT_ROWS(i) {
         const double y = Y[i * kCB + c];
+        const double x1 = Q1[i * kCB + c];
+        const double x2 = Q2 ? Q2[i * kCB + c] : 0.0;
 #pragma unroll
-        for (int k = 0; k < kCB; ++k) acc[k] = fma(x, __shfl(y, base | k, 64), acc[k]);
+        for (int k = 0; k < kCB; ++k) {
+            const double yk = __shfl(y, base | k, 64);
+            a1[k] = fma(x1, yk, a1[k]);
+            a2[k] = fma(x2, yk, a2[k]);
+        }
     }
-    gram_store(acc, part);
+    gram_store(a1, part, 0, sh);
+    gram_store(a2, part, kCS, sh);
+    part_store(part, kCP, sh);
 }
 
-// Sum the 64-entry partial rows into LDS g[64] with all kBlock threads: four
-// threads per entry over interleaved rows, combined in a fixed order.
-__device__ __forceinline__ void reduce_gram(const double *part, int np, double *g) {
-    __shared__ double sh[4][kCS];
-    const int e = threadIdx.x & (kCS - 1), q = threadIdx.x >> 6;
+// Sum the partial rows into LDS g[0..K) with all kBlock threads (kBlock / K
+// threads per entry over interleaved rows, combined in a fixed order).
+template <int K>
+__device__ __forceinline__ void reduce_part(const double *part, int np, double *g) {
+    constexpr int P = kBlock / K;
+    __shared__ double sh[P][K];
+    const int e = threadIdx.x % K, q = threadIdx.x / K;
     double t = 0.0;
-    for (int b = q; b < np; b += 4) t += part[(size_t)b * kCS + e];
+    for (int b = q; b < np; b += P) t += part[(size_t)b * kCP + e];
     sh[q][e] = t;
     __syncthreads();
-    if (threadIdx.x < kCS) g[threadIdx.x] = (sh[0][e] + sh[1][e]) + (sh[2][e] + sh[3][e]);
+    if (threadIdx.x < K) {
+        double v = 0.0;
+#pragma unroll
+        for (int r = 0; r < P; ++r) v += sh[r][threadIdx.x];
+        g[threadIdx.x] = v;
+    }
     __syncthreads();
 }
 
 __global__ __launch_bounds__(kBlock) void k_cert_fin_a(const double *part, int np, CertStep *steps, int j) {
     __shared__ double g[kCS];
-    reduce_gram(part, np, g);
+    reduce_part<kCS>(part, np, g);
     if (threadIdx.x < kCS) {
         const int r = threadIdx.x / kCB, c = threadIdx.x % kCB;
         steps[j].A[threadIdx.x] = 0.5 * (g[r * kCB + c] + g[c * kCB + r]);
     }
 }
 
-// W <- W - Q A_j - Qp B_{j-1}^T (Qp may be null), and the partials of W^T W.
-__global__ __launch_bounds__(kBlock) void k_cert_update(double *__restrict__ W, const double *__restrict__ Q,
-                                                        const double *__restrict__ Qp, const CertStep *steps, int j,
-                                                        int64_t n, double *part) {
-    __shared__ double A[kCS], Bp[kCS];
+// out[0..128) <- the reduced pair of projections (no symmetrisation)
+__global__ __launch_bounds__(kBlock) void k_cert_fin_c(const double *part, int np, double *out) {
+    __shared__ double g[kCP];
+    reduce_part<kCP>(part, np, g);
+    if (threadIdx.x < kCP) out[threadIdx.x] = g[threadIdx.x];
+}
+
+// W <- W - Q1 M1 - Q2 M2' with M2' = M2^T if trans2 else M2 (row times 8 x 8
+// matrix; Q2 may be null).  Then mode 0: partials of Q1^T W and Q2^T W;
+// mode 1: partials of W^T W.
+__global__ __launch_bounds__(kBlock) void k_cert_sub(double *__restrict__ W, const double *__restrict__ Q1,
+                                                     const double *M1, const double *__restrict__ Q2,
+                                                     const double *M2, int trans2, int mode, int64_t n,
+                                                     double *part) {
+    __shared__ double sh[kBlock / 64][kCP];
+    __shared__ double m1[kCS], m2[kCS];
     if (threadIdx.x < kCS) {
-        A[threadIdx.x] = steps[j].A[threadIdx.x];
-        Bp[threadIdx.x] = (Qp && j > 0) ? steps[j - 1].B[threadIdx.x] : 0.0;
+        const int r = threadIdx.x / kCB, c = threadIdx.x % kCB;
+        m1[threadIdx.x] = M1[threadIdx.x];
+        m2[threadIdx.x] = Q2 ? (trans2 ? M2[c * kCB + r] : M2[threadIdx.x]) : 0.0;
     }
     __syncthreads();
     const int lane = threadIdx.x & 63, c = threadIdx.x & 7, base = lane & ~7;
-    double acc[kCB] = {0, 0, 0, 0, 0, 0, 0, 0};
-    const int64_t stride = (int64_t)gridDim.x * (kBlock / kCB);
-    for (int64_t i = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kCB; i < n; i += stride) {
-        const double q = Q[i * kCB + c];
-        const double qp = Qp ? Qp[i * kCB + c] : 0.0;
+    double a1[kCB] = {0, 0, 0, 0, 0, 0, 0, 0}, a2[kCB] = {0, 0, 0, 0, 0, 0, 0, 0};
+    CERT_ROWS(i) {
+        const double q1 = Q1[i * kCB + c];
+        const double q2 = Q2 ? Q2[i * kCB + c] : 0.0;
         double w = W[i * kCB + c];
 #pragma unroll
         for (int k = 0; k < kCB; ++k) {
-            w = fma(-__shfl(q, base | k, 64), A[k * kCB + c], w);
-            w = fma(-__shfl(qp, base | k, 64), Bp[c * kCB + k], w);
+            w = fma(-__shfl(q1, base | k, 64), m1[k * kCB + c], w);
+            w = fma(-__shfl(q2, base | k, 64), m2[k * kCB + c], w);
         }
         W[i * kCB + c] = w;
+        if (mode == 0) {
 #pragma unroll
-        for (int k = 0; k < kCB; ++k) acc[k] = fma(w, __shfl(w, base | k, 64), acc[k]);
+            for (int k = 0; k < kCB; ++k) {
+                const double wk = __shfl(w, base | k, 64);
+                a1[k] = fma(q1, wk, a1[k]);
+                a2[k] = fma(q2, wk, a2[k]);
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < kCB; ++k) a1[k] = fma(w, __shfl(w, base | k, 64), a1[k]);
+        }
     }
-    gram_store(acc, part);
+    gram_store(a1, part, 0, sh);
+    if (mode == 0) gram_store(a2, part, kCS, sh);
+    part_store(part, mode == 0 ? kCP : kCS, sh);
 }
 
-// Cholesky QR factor of the reduced Gram matrix G = W^T W = B^T B (B upper
-// triangular) and B^{-1}.  Breakdown (a pivot at or below 1e-24 of the squared
-// scale of the step, or not finite) means the Krylov space is invariant:
-// *flag records the first such step as j + 2 (1: the start block) and
-// B, B^{-1} are zeroed so later steps stay finite.
+// Cholesky factor R (upper, G = R^T R) of the reduced Gram matrix and R^{-1}.
+// `scale2` bounds the squared size of the step (for the breakdown test):
+// steps[j].A and steps[j-1].B when j >= 0 and first_pass, else the Gram
+// diagonal.  Breakdown (a pivot at or below 1e-24 scale2, or not finite): the
+// Krylov space is invariant; *flag records the first such step as j + 2 (1:
+// the start block) and R, R^{-1} are zeroed so later steps stay finite.  If
+// Rprev is given, B_j = R Rprev is stored in steps[j].B (the second pass of
+// Cholesky QR).
 __global__ __launch_bounds__(kBlock) void k_cert_chol(const double *part, int np, CertStep *steps, int j,
-                                                      double *Rinv, int *flag) {
+                                                      int first_pass, double *Rout, double *Rinv,
+                                                      const double *Rprev, int *flag) {
     __shared__ double g[kCS];
-    reduce_gram(part, np, g);
+    reduce_part<kCS>(part, np, g);
     if (threadIdx.x != 0) return;
     double scale = 0.0;
     for (int k = 0; k < kCB; ++k) scale = fmax(scale, g[k * kCB + k]);
-    if (j >= 0) {
+    if (j >= 0 && first_pass) {
         double s = 0.0;
         for (int e = 0; e < kCS; ++e) {
             s = fmax(s, fabs(steps[j].A[e]));
@@ -192,7 +251,7 @@ __global__ __launch_bounds__(kBlock) void k_cert_chol(const double *part, int np
         }
     }
     if (ok) {
-        // inverse of the upper-triangular R, column by column (back substitution)
+        // inverse of the upper-triangular R by back substitution, column by column
         for (int c = 0; c < kCB; ++c) {
             for (int r = c; r >= 0; --r) {
                 double v = (r == c) ? 1.0 : 0.0;
@@ -204,25 +263,44 @@ __global__ __launch_bounds__(kBlock) void k_cert_chol(const double *part, int np
         for (int e = 0; e < kCS; ++e) R[e] = Ri[e] = 0.0;
         if (*flag == 0) *flag = j + 2;
     }
-    if (j >= 0)
-        for (int e = 0; e < kCS; ++e) steps[j].B[e] = R[e];
-    for (int e = 0; e < kCS; ++e) Rinv[e] = Ri[e];
+    for (int e = 0; e < kCS; ++e) {
+        Rout[e] = R[e];
+        Rinv[e] = Ri[e];
+    }
+    if (Rprev && j >= 0) {
+        for (int r = 0; r < kCB; ++r)
+            for (int c = 0; c < kCB; ++c) {
+                double v = 0.0;
+                for (int k = r; k <= c; ++k) v += R[r * kCB + k] * Rprev[k * kCB + c];
+                steps[j].B[r * kCB + c] = v;
+            }
+    }
 }
 
-// Qn_i = W_i B^{-1} (row times upper-triangular inverse)
-__global__ __launch_bounds__(kBlock) void k_cert_scale(const double *__restrict__ W, const double *Rinv,
-                                                       double *__restrict__ Qn, int64_t n) {
+// Qo_i = W_i Rinv (row times upper-triangular inverse; Qo may equal W), and if
+// part is given the partials of Qo^T Qo.
+__global__ __launch_bounds__(kBlock) void k_cert_scale(const double *W, const double *Rinv, double *Qo, int64_t n,
+                                                       double *part) {
+    __shared__ double sh[kBlock / 64][kCP];
     __shared__ double Ri[kCS];
     if (threadIdx.x < kCS) Ri[threadIdx.x] = Rinv[threadIdx.x];
     __syncthreads();
     const int lane = threadIdx.x & 63, c = threadIdx.x & 7, base = lane & ~7;
-    const int64_t stride = (int64_t)gridDim.x * (kBlock / kCB);
-    for (int64_t i = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kCB; i < n; i += stride) {
+    double acc[kCB] = {0, 0, 0, 0, 0, 0, 0, 0};
+    CERT_ROWS(i) {
         const double w = W[i * kCB + c];
         double v = 0.0;
 #pragma unroll
         for (int k = 0; k < kCB; ++k) v = fma(__shfl(w, base | k, 64), Ri[k * kCB + c], v);
-        Qn[i * kCB + c] = v;
+        Qo[i * kCB + c] = v;
+        if (part) {
+#pragma unroll
+            for (int k = 0; k < kCB; ++k) acc[k] = fma(v, __shfl(v, base | k, 64), acc[k]);
+        }
+    }
+    if (part) {
+        gram_store(acc, part, 0, sh);
+        part_store(part, kCS, sh);
     }
 }
 
@@ -361,7 +439,7 @@ void ritz_min(const std::vector<CertStep> &st, int k, bool has_next, double *the
 }
 
 struct CertLayout {
-    size_t q[3], w, part, steps, rinv, flag, by, total;
+    size_t q[3], w, part, steps, small, flag, by, total;
 };
 
 CertLayout cert_layout(int64_t n, int max_iter) {
@@ -371,13 +449,23 @@ CertLayout cert_layout(int64_t n, int max_iter) {
     size_t o = 0;
     for (int i = 0; i < 3; ++i) { L.q[i] = o; o += al(blk); }
     L.w = o; o += al(blk);
-    L.part = o; o += al((size_t)kCertGrid * kCS * sizeof(double));
+    L.part = o; o += al((size_t)kCertGrid * kCP * sizeof(double));
     L.steps = o; o += al((size_t)max_iter * sizeof(CertStep));
-    L.rinv = o; o += al(kCS * sizeof(double));
+    L.small = o; o += al(6 * kCS * sizeof(double));   // C (2 blocks), R1, R1^{-1}, R2, R2^{-1}
     L.flag = o; o += 256;
     L.by = o; o += 256;
     L.total = o;
     return L;
+}
+
+// Device addresses of the A and B blocks of step j (address arithmetic only).
+const double *step_a(const CertStep *steps, int j) {
+    return reinterpret_cast<const double *>(reinterpret_cast<const char *>(steps) + (size_t)j * sizeof(CertStep) +
+                                            offsetof(CertStep, A));
+}
+const double *step_b(const CertStep *steps, int j) {
+    return reinterpret_cast<const double *>(reinterpret_cast<const char *>(steps) + (size_t)j * sizeof(CertStep) +
+                                            offsetof(CertStep, B));
 }
 
 int apply_s(hipStream_t s, const lrsdp_problem *p, const double *V, const double *y, double *Y) {
@@ -424,7 +512,8 @@ extern "C" int lrsdp_certify(lrsdp_ctx *c, const lrsdp_problem *p, const double 
     double *Wb = reinterpret_cast<double *>(ws + L.w);
     double *part = reinterpret_cast<double *>(ws + L.part);
     CertStep *steps = reinterpret_cast<CertStep *>(ws + L.steps);
-    double *rinv = reinterpret_cast<double *>(ws + L.rinv);
+    double *small = reinterpret_cast<double *>(ws + L.small);
+    double *Cm = small, *R1 = small + 2 * kCS, *R1i = small + 3 * kCS, *R2 = small + 4 * kCS, *R2i = small + 5 * kCS;
     int *flag = reinterpret_cast<int *>(ws + L.flag);
     double *by = reinterpret_cast<double *>(ws + L.by);
     hipStream_t s = c->stream;
@@ -435,11 +524,13 @@ extern "C" int lrsdp_certify(lrsdp_ctx *c, const lrsdp_problem *p, const double 
     const bool mc = p->info.kind == LRSDP_MAXCUT;
     hipLaunchKernelGGL(k_cert_by, dim3(1), dim3(kBlock), 0, s, mc ? nullptr : p->cmp.b, y, p->info.m, by);
     LRSDP_CHECK_LAUNCH();
-    // start block: random, orthonormalised by one Cholesky QR
+    // start block: random, orthonormalised by Cholesky QR applied twice
     hipLaunchKernelGGL(k_cert_random, dim3(g), dim3(kBlock), 0, s, Wb, n * kCB, seed);
-    hipLaunchKernelGGL(k_cert_gram, dim3(g), dim3(kBlock), 0, s, Wb, Wb, n, part);
-    hipLaunchKernelGGL(k_cert_chol, dim3(1), dim3(kBlock), 0, s, part, g, steps, -1, rinv, flag);
-    hipLaunchKernelGGL(k_cert_scale, dim3(g), dim3(kBlock), 0, s, Wb, rinv, Q[0], n);
+    hipLaunchKernelGGL(k_cert_proj, dim3(g), dim3(kBlock), 0, s, Wb, nullptr, Wb, n, part);
+    hipLaunchKernelGGL(k_cert_chol, dim3(1), dim3(kBlock), 0, s, part, g, steps, -1, 1, R1, R1i, nullptr, flag);
+    hipLaunchKernelGGL(k_cert_scale, dim3(g), dim3(kBlock), 0, s, Wb, R1i, Wb, n, part);
+    hipLaunchKernelGGL(k_cert_chol, dim3(1), dim3(kBlock), 0, s, part, g, steps, -1, 0, R2, R2i, nullptr, flag);
+    hipLaunchKernelGGL(k_cert_scale, dim3(g), dim3(kBlock), 0, s, Wb, R2i, Q[0], n, nullptr);
     LRSDP_CHECK_LAUNCH();
 
     std::vector<CertStep> host;
@@ -449,13 +540,22 @@ extern "C" int lrsdp_certify(lrsdp_ctx *c, const lrsdp_problem *p, const double 
     int status = 1;
     for (int j = 0; j < max_iter; ++j) {
         if ((rc = apply_s(s, p, Q[cur], y, Wb))) return rc;
-        hipLaunchKernelGGL(k_cert_gram, dim3(g), dim3(kBlock), 0, s, Q[cur], Wb, n, part);
+        const double *Qp = prev >= 0 ? Q[prev] : nullptr;
+        const double *Aj = step_a(steps, j);
+        const double *Bp = j > 0 ? step_b(steps, j - 1) : nullptr;
+        // A_j = Q_j^T S Q_j
+        hipLaunchKernelGGL(k_cert_proj, dim3(g), dim3(kBlock), 0, s, Q[cur], nullptr, Wb, n, part);
         hipLaunchKernelGGL(k_cert_fin_a, dim3(1), dim3(kBlock), 0, s, part, g, steps, j);
-        hipLaunchKernelGGL(k_cert_update, dim3(g), dim3(kBlock), 0, s, Wb, Q[cur], prev >= 0 ? Q[prev] : nullptr,
-                           steps, j, n, part);
-        hipLaunchKernelGGL(k_cert_chol, dim3(1), dim3(kBlock), 0, s, part, g, steps, j, rinv, flag);
+        // three-term recurrence, then one re-orthogonalisation against Q_j, Q_{j-1}
+        hipLaunchKernelGGL(k_cert_sub, dim3(g), dim3(kBlock), 0, s, Wb, Q[cur], Aj, Qp, Bp, 1, 0, n, part);
+        hipLaunchKernelGGL(k_cert_fin_c, dim3(1), dim3(kBlock), 0, s, part, g, Cm);
+        hipLaunchKernelGGL(k_cert_sub, dim3(g), dim3(kBlock), 0, s, Wb, Q[cur], Cm, Qp, Cm + kCS, 0, 1, n, part);
+        // Cholesky QR twice: W = Q_{j+1} R2 R1, B_j = R2 R1
+        hipLaunchKernelGGL(k_cert_chol, dim3(1), dim3(kBlock), 0, s, part, g, steps, j, 1, R1, R1i, nullptr, flag);
+        hipLaunchKernelGGL(k_cert_scale, dim3(g), dim3(kBlock), 0, s, Wb, R1i, Wb, n, part);
+        hipLaunchKernelGGL(k_cert_chol, dim3(1), dim3(kBlock), 0, s, part, g, steps, j, 0, R2, R2i, R1, flag);
         const int nxt = prev < 0 ? (cur + 1) % 3 : 3 - cur - prev;  // the buffer holding neither Q_j nor Q_{j-1}
-        hipLaunchKernelGGL(k_cert_scale, dim3(g), dim3(kBlock), 0, s, Wb, rinv, Q[nxt], n);
+        hipLaunchKernelGGL(k_cert_scale, dim3(g), dim3(kBlock), 0, s, Wb, R2i, Q[nxt], n, nullptr);
         LRSDP_CHECK_LAUNCH();
         prev = cur;
         cur = nxt;

@@ -51,10 +51,17 @@ def maxcut_case(case):
     if case == "general":
         u, v = erdos_renyi_edges(900, 4000, 35)
         return 900, u, v, np.random.default_rng(36).uniform(-2, 3, 4000)
+    if case == "hub":                              # one row of 3000: eigenvalues far apart, ill-conditioned blocks
+        u, v = erdos_renyi_edges(6000, 24000, 37)
+        pairs = {(min(a, b), max(a, b)) for a, b in zip(u.tolist(), v.tolist())}
+        for k in range(1, 3001):
+            pairs.add((0, k))
+        uv = np.array(sorted(pairs), dtype=np.int32)
+        return 6000, uv[:, 0], uv[:, 1], pm1_weights(len(uv), 38)
     raise KeyError(case)
 
 
-@pytest.mark.parametrize("case", ["er", "pm1", "cl_heavy", "general"])
+@pytest.mark.parametrize("case", ["er", "pm1", "cl_heavy", "general", "hub"])
 def test_maxcut_lambda_min_parity(ctx, case):
     n, u, v, w = maxcut_case(case)
     print_case(test="certify", case=case, n=n)
