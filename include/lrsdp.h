@@ -186,6 +186,10 @@ typedef struct {
     double  spmm_ms;      /* summed duration of those launches (HIP events)    */
     double  spmm_bytes;   /* algorithmic bytes of one SpMM launch              */
     int64_t admm_iters;   /* splitting-phase iterations (phase2 = 1)           */
+    int64_t admm_fallbacks; /* splitting phases abandoned (diverged: not finite
+                               or err1 above 10x its value at the switch; or
+                               max_admm reached): R, y and the ALM state of the
+                               switch were restored and the ALM went on alone */
 } lrsdp_result;
 
 /* Device workspace the solve needs for this problem and these options. */

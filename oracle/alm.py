@@ -69,6 +69,8 @@ class SolveResult:
     converged: bool
     seconds: float
     history: list = field(default_factory=list)
+    admm_iters: int = 0
+    admm_fallbacks: int = 0
 
 
 def default_sigma0(prob: SDPProblem) -> float:
@@ -125,6 +127,8 @@ def alm_solve(prob: SDPProblem, R0: np.ndarray, y0=None, opts: Options | None = 
     converged = False
     meas = K.alm_measures(prob, R, y)
     outer = 0
+    phase2_on = opts.phase2
+    admm_total = fallbacks = 0
     for outer in range(1, opts.max_outer + 1):
         R, it, gnorm = lbfgs_minimize(prob, R, y, sigma, eta, opts, opts.max_iter_total - total)
         total += it
@@ -137,12 +141,22 @@ def alm_solve(prob: SDPProblem, R0: np.ndarray, y0=None, opts: Options | None = 
         if meas["err1"] <= opts.tol and abs(meas["err3"]) <= opts.tol:
             converged = True
             break
-        if opts.phase2 and meas["err1"] <= opts.switch_err1:
-            R, _, _, y, meas, it2 = admm_phase(prob, R, y, sigma, tol=opts.tol, max_iter=opts.max_admm,
-                                               check_every=opts.admm_check)
-            hist.append(dict(outer=outer, admm=it2, sigma=sigma, **meas))
-            converged = meas["err1"] <= opts.tol and abs(meas["err3"]) <= opts.tol
-            break
+        if phase2_on and meas["err1"] <= opts.switch_err1:
+            # Splitting phase with the penalty of the subproblem just solved.  If it
+            # diverges or stops at max_admm unconverged, the ALM goes on from the
+            # point of the switch with the splitting phase off (the paper leaves
+            # this case open).
+            Rm, _, _, y2, meas2, it2, diverged = admm_phase(
+                prob, R, y, sigma, tol=opts.tol, max_iter=opts.max_admm, check_every=opts.admm_check,
+                diverge_factor=10.0)
+            admm_total += it2
+            hist.append(dict(outer=outer, admm=it2, sigma=sigma, diverged=diverged, **meas2))
+            if not diverged and meas2["err1"] <= opts.tol and abs(meas2["err3"]) <= opts.tol:
+                R, y, meas = Rm, y2, meas2
+                converged = True
+                break
+            phase2_on = False
+            fallbacks += 1
         if total >= opts.max_iter_total or time.perf_counter() - t0 > opts.time_limit:
             break
         if meas["err1"] > opts.feas_decrease * err1_prev:
@@ -152,7 +166,8 @@ def alm_solve(prob: SDPProblem, R0: np.ndarray, y0=None, opts: Options | None = 
     return SolveResult(R=R, y=y, sigma=sigma, obj=meas["obj"], dual=meas["dual"],
                        err1=meas["err1"], err1_inf=meas["err1_inf"], err3=meas["err3"],
                        outer=outer, inner=total, converged=converged,
-                       seconds=time.perf_counter() - t0, history=hist)
+                       seconds=time.perf_counter() - t0, history=hist,
+                       admm_iters=admm_total, admm_fallbacks=fallbacks)
 
 
 # ---------------------------------------------------------------------------
@@ -206,19 +221,31 @@ def admm_step(prob: SDPProblem, U, V, y, sigma, cg_tol=1e-12, cg_iters=1000):
     return U, V, y
 
 
-def admm_phase(prob: SDPProblem, R, y, sigma, tol=1e-5, max_iter=2000, check_every=10, log=None):
+def admm_phase(prob: SDPProblem, R, y, sigma, tol=1e-5, max_iter=2000, check_every=10, log=None,
+               diverge_factor=None):
     """Run splitting iterations from U = V = R until err1 and |err3| at
-    R = (U + V)/2 are below tol (checked every `check_every` iterations)."""
+    R = (U + V)/2 are below tol (checked every `check_every` iterations).
+    With diverge_factor, stop early (diverged = True) when a check finds a
+    non-finite value or err1 above diverge_factor times its value at R."""
     U, V = R.copy(), R.copy()
     meas = K.alm_measures(prob, R, y)
+    err1_0 = meas["err1"]
     it = 0
-    for it in range(1, max_iter + 1):
-        U, V, y = admm_step(prob, U, V, y, sigma)
-        if it % check_every == 0 or it == max_iter:
-            Rm = 0.5 * (U + V)
-            meas = K.alm_measures(prob, Rm, y)
-            if log is not None:
-                log(dict(it=it, **meas))
-            if meas["err1"] <= tol and abs(meas["err3"]) <= tol:
-                break
-    return 0.5 * (U + V), U, V, y, meas, it
+    diverged = False
+    with np.errstate(all="ignore"):
+        for it in range(1, max_iter + 1):
+            U, V, y = admm_step(prob, U, V, y, sigma)
+            if it % check_every == 0 or it == max_iter:
+                Rm = 0.5 * (U + V)
+                meas = K.alm_measures(prob, Rm, y)
+                if log is not None:
+                    log(dict(it=it, **meas))
+                if diverge_factor is not None and (not np.isfinite(meas["obj"]) or not np.isfinite(meas["err1"])
+                                                   or meas["err1"] > diverge_factor * err1_0):
+                    diverged = True
+                    break
+                if meas["err1"] <= tol and abs(meas["err3"]) <= tol:
+                    break
+    if diverge_factor is None:
+        return 0.5 * (U + V), U, V, y, meas, it
+    return 0.5 * (U + V), U, V, y, meas, it, diverged

@@ -373,7 +373,8 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
     if ((rc = alm_refresh(0.0, 0))) return rc;
 
     int status = LRSDP_NOT_CONVERGED;
-    int64_t admm_iters = 0;
+    int64_t admm_iters = 0, admm_fallbacks = 0;
+    bool phase2_on = o->phase2 != 0;
     int64_t outer = 0;
     int64_t total_inner = 0;
     double sigma_host = sigma0;
@@ -504,6 +505,7 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
             fprintf(stderr, "[lrsdp] outer %3lld inner %6lld sigma %.3e obj % .10e err1 %.3e err3 % .3e gnorm %.3e t %.3fs\n",
                     (long long)outer, (long long)hs.inner_total, sigma_host, hs.obj, hs.err1, hs.err3, hs.gnorm,
                     elapsed());
+        const double sigma_sub = sigma_host;  // penalty of the subproblem just solved
         sigma_host = hs.sigma;
         if (hs.numeric) {
             rc = set_error(LRSDP_ENUMERIC, "NaN/Inf in the ALM measures (outer %lld)", (long long)outer);
@@ -513,17 +515,23 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
             status = LRSDP_OK;
             break;
         }
-        if (mc && o->phase2 && hs.err1 <= o->switch_err1) {
-            // splitting phase from U = V = R with the current y and sigma; measures
+        if (mc && phase2_on && hs.err1 <= o->switch_err1) {
+            // splitting phase from U = V = R with the current y and the penalty of the
+            // subproblem just solved; measures
             // at R = (U + V)/2 every admm_check iterations (R holds V, the first G
-            // slot holds U)
+            // slot holds U).  R, y and the solver state are kept (first D slot,
+            // second ytil buffer, host copy) for the fallback below.
             void *U = gring[0];
             const int64_t bytes = n * ld * (prec == LRSDP_F64 ? 8 : 4);
+            const SolverState snap = hs;
+            LRSDP_HIP_TRY(hipMemcpyAsync(dring[0], R, bytes, hipMemcpyDeviceToDevice, s));
+            LRSDP_HIP_TRY(hipMemcpyAsync(ytil[1], y, n * sizeof(double), hipMemcpyDeviceToDevice, s));
             LRSDP_HIP_TRY(hipMemcpyAsync(U, R, bytes, hipMemcpyDeviceToDevice, s));
             const int chk = std::max(1, o->admm_check);
             int64_t it2 = 0;
+            bool done2 = false, diverged = false;
             while (it2 < o->max_admm) {
-                for (int b = 0; b < chk && rc == 0; ++b, ++it2) rc = admm_iter(s, p->csr, prec, U, R, ld, y, sigma_host);
+                for (int b = 0; b < chk && rc == 0; ++b, ++it2) rc = admm_iter(s, p->csr, prec, U, R, ld, y, sigma_sub);
                 if (rc) break;
                 if ((rc = launch_avg(s, prec, U, R, gring[1], n * ld))) break;
                 SpmmArgs ref;
@@ -542,19 +550,40 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
                 if (o->verbose)
                     fprintf(stderr, "[lrsdp] admm %6lld obj % .10e err1 %.3e err3 % .3e t %.3fs\n", (long long)it2,
                             hs.obj, hs.err1, hs.err3, elapsed());
-                if (!std::isfinite(hs.obj) || !std::isfinite(hs.err1)) {
-                    rc = set_error(LRSDP_ENUMERIC, "NaN/Inf in the splitting phase");
+                if (!std::isfinite(hs.obj) || !std::isfinite(hs.err1) || hs.err1 > 10.0 * snap.err1) {
+                    diverged = true;
                     break;
                 }
                 if (hs.err1 <= o->tol && std::fabs(hs.err3) <= o->tol) {
-                    status = LRSDP_OK;
+                    done2 = true;
                     break;
                 }
                 if (elapsed() > o->time_limit_s) break;
             }
-            admm_iters = it2;
-            if (rc == 0) LRSDP_HIP_TRY(hipMemcpyAsync(R, gring[1], bytes, hipMemcpyDeviceToDevice, s));
-            break;
+            admm_iters += it2;
+            if (rc) break;
+            if (done2) {
+                LRSDP_HIP_TRY(hipMemcpyAsync(R, gring[1], bytes, hipMemcpyDeviceToDevice, s));
+                status = LRSDP_OK;
+                break;
+            }
+            if (elapsed() > o->time_limit_s && !diverged) {
+                LRSDP_HIP_TRY(hipMemcpyAsync(R, gring[1], bytes, hipMemcpyDeviceToDevice, s));
+                break;
+            }
+            // Fallback (diverged, or max_admm without convergence): restore R, y and
+            // the ALM state of the switch, recompute C R, and go on with the ALM
+            // alone.
+            ++admm_fallbacks;
+            phase2_on = false;
+            LRSDP_HIP_TRY(hipMemcpyAsync(R, dring[0], bytes, hipMemcpyDeviceToDevice, s));
+            LRSDP_HIP_TRY(hipMemcpyAsync(y, ytil[1], n * sizeof(double), hipMemcpyDeviceToDevice, s));
+            if ((rc = write_state(c, snap))) break;
+            if ((rc = alm_refresh(0.0, 0))) break;
+            if ((rc = read_state(c, &hs))) break;
+            if (o->verbose)
+                fprintf(stderr, "[lrsdp] splitting phase %s after %lld iterations: back to the ALM\n",
+                        diverged ? "diverged" : "did not converge", (long long)it2);
         }
         if (hs.inner_total >= o->max_iter_total || elapsed() > o->time_limit_s) break;
     }
@@ -577,6 +606,7 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
     res->spmm_ms = spmm_ms;
     res->spmm_bytes = mc ? maxcut_spmm_bytes(p, prec, o->rank) : completion_grad_bytes(p, prec, o->rank, T);
     res->admm_iters = admm_iters;
+    res->admm_fallbacks = admm_fallbacks;
     return status;
 }
 

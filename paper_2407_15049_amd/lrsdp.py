@@ -53,7 +53,7 @@ class Result(C.Structure):
         ("err3", C.c_double), ("sigma", C.c_double), ("seconds", C.c_double),
         ("outer", C.c_int64), ("inner", C.c_int64), ("status", C.c_int),
         ("spmm_launches", C.c_int), ("spmm_ms", C.c_double), ("spmm_bytes", C.c_double),
-        ("admm_iters", C.c_int64),
+        ("admm_iters", C.c_int64), ("admm_fallbacks", C.c_int64),
     ]
 
     def as_dict(self):

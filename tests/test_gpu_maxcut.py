@@ -422,3 +422,39 @@ def test_solve_phase2_matches_oracle(ctx):
     assert abs(res.obj - ores.obj) <= 1e-5 * abs(ores.obj)
     m = K.alm_measures(maxcut_problem(n, u, v, w), R, y)
     assert m["err1"] <= 1e-5 and abs(m["err3"]) <= 1e-5
+
+
+def test_phase2_forced_fallback_equals_alm_only(ctx):
+    # a splitting phase that cannot finish (max_admm = 10 from an early switch) is
+    # abandoned; the solve then equals the ALM alone bit for bit, and the oracle's
+    # solve with the same options
+    n, u, v, w, r = graph("er_1k")
+    R0 = init_factor(n, 16, 15051)
+    print_case(test="phase2_fallback", case="er_1k")
+    rc0, res0, R0g, y0g = gpu_solve(ctx, n, u, v, w, R0, L.F64)
+    rc, res, R, y = gpu_solve(ctx, n, u, v, w, R0, L.F64, phase2=1, switch_err1=1e-1, max_admm=10, admm_check=10)
+    print(res.as_dict())
+    assert rc == L.OK and rc0 == L.OK
+    assert res.admm_fallbacks == 1 and res.admm_iters == 10
+    assert res.obj == res0.obj and res.inner == res0.inner and res.outer == res0.outer
+    assert np.array_equal(R, R0g) and np.array_equal(y, y0g)
+    ores = alm_solve(maxcut_problem(n, u, v, w), R0,
+                     opts=OOptions(phase2=True, switch_err1=1e-1, max_admm=10, admm_check=10))
+    assert ores.admm_fallbacks == 1
+    assert abs(res.obj - ores.obj) <= 1e-5 * abs(ores.obj)
+
+
+def test_phase2_hub_graph_never_fails(ctx):
+    # on hub rows the splitting iteration at the switch penalty can diverge; the
+    # solve must fall back to the ALM and still converge
+    n, u, v, w, r = graph("cl_heavy")
+    R0 = init_factor(n, 16, 17)
+    print_case(test="phase2_hub", case="cl_heavy")
+    rc, res, R, y = gpu_solve(ctx, n, u, v, w, R0, L.F64, phase2=1, switch_err1=1e-3)
+    print(res.as_dict())
+    assert rc == L.OK, res.as_dict()
+    m = K.alm_measures(maxcut_problem(n, u, v, w), R, y)
+    assert m["err1"] <= 1e-5 and abs(m["err3"]) <= 1e-5
+    if res.admm_fallbacks:
+        rc0, res0, _, _ = gpu_solve(ctx, n, u, v, w, R0, L.F64)
+        assert res.obj == res0.obj

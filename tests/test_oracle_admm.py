@@ -63,3 +63,20 @@ def test_splitting_converges_on_odd_cycle():
     assert meas["err1"] <= 1e-8 and abs(meas["err3"]) <= 1e-8
     assert np.isclose(meas["obj"], -(n / 2) * (1 + np.cos(np.pi / n)), rtol=1e-6)
     assert np.linalg.norm(U - V) <= 1e-5 * np.linalg.norm(U)
+
+
+def test_phase2_fallback_reproduces_alm_only():
+    # a splitting phase that cannot finish (max_admm = 10 from an early switch)
+    # is abandoned: the solve then equals the ALM alone, iterate for iterate
+    from oracle.alm import Options, alm_solve
+    from oracle.problem import maxcut_problem
+    from synth import erdos_renyi_edges, init_factor
+    n = 120
+    u, v = erdos_renyi_edges(n, 500, 7)
+    prob = maxcut_problem(n, u, v)
+    R0 = init_factor(n, 8, 9)
+    a = alm_solve(prob, R0, opts=Options())
+    b = alm_solve(prob, R0, opts=Options(phase2=True, switch_err1=1e-1, max_admm=10, admm_check=10))
+    assert b.admm_fallbacks == 1 and b.admm_iters == 10
+    assert np.array_equal(a.R, b.R) and np.array_equal(a.y, b.y)
+    assert a.obj == b.obj and a.outer == b.outer and a.inner == b.inner
