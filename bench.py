@@ -30,6 +30,10 @@ HBM_PEAK_GBS = 8000.0
 WORKLOAD = ("maxcut n=1e6 pair: Erdos-Renyi 5e6 edges + Chung-Lu beta=2.5 mean degree 10 (5e6 edges), "
             "weights uniform in {-1,+1}, C=-L/4, diag(X)=1, rank 20")
 INSTANCES = ["er_1m_pm1", "cl_1m_pm1"]
+OTHER_WORKLOADS = {
+    "cl_10m": "maxcut n=1e7 Chung-Lu beta=2.5 mean degree 8 (4e7 edges), unit weights, C=-L/4, diag(X)=1, rank 24",
+    "er_1k": "maxcut n=1e3 Erdos-Renyi 5e3 edges, unit weights, C=-L/4, diag(X)=1, rank 10",
+}
 
 
 def parse():
@@ -40,12 +44,16 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-f32", action="store_true", help="skip the float32 / warm-start / bf16 paths")
     ap.add_argument("--no-warm", action="store_true", help="skip the learned warm start")
+    ap.add_argument("--no-bf16", action="store_true", help="skip the bfloat16-input path")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample")
     ap.add_argument("--instances", default=",".join(INSTANCES))
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--short", type=int, default=0,
                     help="profiling aid: cap each solve at this many L-BFGS iterations (first ALM step only)")
+    ap.add_argument("--completion", action="store_true",
+                    help="instead of the MaxCut step: time the matrix-completion kernels (SDDMM constraint map, "
+                         "gradient SpMM) and 300 L-BFGS iterations at n1 = n2 = 5e5, m = 1e7, rank 16")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device-to-device copy three times (counter calibration)")
     return ap.parse_args()
@@ -93,6 +101,8 @@ def main():
 
     dev = torch.device("cuda", 0)
     ctx = L.Context(0)
+    if args.completion:
+        return completion_bench(args, ctx, dev)
     names = args.instances.split(",")
     runs = []
     for name in names:
@@ -199,7 +209,7 @@ def main():
             dt, res = solve(run, L.F32)
             record("f32", run, dt, res, y=run["per"][L.F32]["y"])
         # bfloat16 gathered operand (float32 iterate, exact gradient every 25 iterations)
-        for run in runs:
+        for run in ([] if args.no_bf16 else runs):
             p = run["per"][L.F32]
             o = L.default_options(prec=L.F32_BF16IN, rank=run["r"], ld=p["opts"].ld, profile=1, refresh_every=25)
             ws = torch.empty(L.workspace_bytes(run["prob"], o), dtype=torch.uint8, device=dev)
@@ -261,7 +271,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD, "instances": names, "tol": 1e-5, "path": "plain FP64 ALM + L-BFGS",
+        "config": {"workload": WORKLOAD if names == INSTANCES else
+                   "; ".join(OTHER_WORKLOADS.get(nm, nm) for nm in names), "instances": names, "tol": 1e-5, "path": "plain FP64 ALM + L-BFGS",
                    "lbfgs_mem": runs[0]["per"][L.F64]["opts"].lbfgs_mem},
         "roofline": {
             "kernel": "spmm (MaxCut, line-search epilogue)",
@@ -280,6 +291,78 @@ def main():
         "paths": paths,
     }
     print(json.dumps(out), flush=True)
+
+
+COMPLETION = dict(n1=500_000, n2=500_000, k=5, per_row=20, rank=16, seed=15051)
+
+
+def completion_bench(args, ctx, dev):
+    """Kernel bandwidth of the completion hot path (SDDMM constraint map, gradient
+    SpMM) with HIP events on the library's stream, and the time of 300 L-BFGS
+    iterations of the solve, in float64 and float32."""
+    import numpy as np
+    import torch
+
+    from paper_2407_15049_amd import lrsdp as L
+    from synth.graphs import completion_instance, gaussian_factor
+
+    cfg = COMPLETION
+    t0 = time.perf_counter()
+    i, j, M, _, _ = completion_instance(cfg["n1"], cfg["n2"], cfg["k"], cfg["per_row"], cfg["seed"])
+    prob = L.Problem.completion(cfg["n1"], cfg["n2"], i, j, M).upload(ctx)
+    n, m, r = prob.info.n, prob.info.m, cfg["rank"]
+    log(f"completion n={n} m={m} setup {time.perf_counter() - t0:.1f}s")
+    stream = torch.cuda.current_stream(dev)
+    out = {}
+    reps = 20
+    for prec, name in [(L.F64, "f64"), (L.F32, "f32")]:
+        ld = L.padded_ld(r, prec)
+        w = 8 if prec == L.F64 else 4
+        R = torch.zeros((n, ld), dtype=L.elem_dtype(prec), device=dev)
+        R[:, :r] = torch.from_numpy(gaussian_factor(n, r, 1.0 / math.sqrt(r), cfg["seed"] + 1)).to(dev, R.dtype)
+        y = torch.from_numpy(np.random.default_rng(cfg["seed"] + 2).standard_normal(m) * 0.1).to(dev)
+        acon = torch.empty(m, dtype=torch.float64, device=dev)
+        Y = torch.empty_like(R)
+
+        def timed(fn):
+            for _ in range(3):
+                fn()
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            ev[0].record(stream)
+            for _ in range(reps):
+                fn()
+            ev[1].record(stream)
+            torch.cuda.synchronize()
+            return ev[0].elapsed_time(ev[1]) * 1e3 / reps      # us per launch
+
+        t_sdd = timed(lambda: L.k_constraint(ctx, prob, prec, R, R, acon))
+        t_spmm = timed(lambda: L.k_spmm(ctx, prob, prec, R, y, Y))
+        b_sdd = 4.0 * (cfg["n1"] + 1) + 4.0 * m + n * ld * w + 8.0 * m
+        b_spmm = 4.0 * (n + 2) + 4.0 * m + 8.0 * m + 16.0 * m + 2.0 * n * ld * w
+        opts = L.default_options(prec=prec, rank=r, ld=ld, max_iter_total=300, max_inner=300, max_outer=1,
+                                 eta0=1e-12)          # no early inner stop: 300 full iterations
+        R0 = R.clone()
+        y0 = torch.zeros(m, dtype=torch.float64, device=dev)
+        ws = torch.empty(L.workspace_bytes(prob, opts), dtype=torch.uint8, device=dev)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        rc, res = L.solve(ctx, prob, R0, y0, opts, workspace=ws)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        out[name] = dict(
+            sddmm_us=round(t_sdd, 2), sddmm_alg_bytes=b_sdd, sddmm_gbs=round(b_sdd / t_sdd / 1e3, 1),
+            sddmm_frac=round(b_sdd / t_sdd / 1e3 / HBM_PEAK_GBS, 4),
+            spmm_us=round(t_spmm, 2), spmm_alg_bytes=b_spmm, spmm_gbs=round(b_spmm / t_spmm / 1e3, 1),
+            spmm_frac=round(b_spmm / t_spmm / 1e3 / HBM_PEAK_GBS, 4),
+            iters=res.inner, ms_per_iter=round(1e3 * dt / max(res.inner, 1), 3), err1=res.err1)
+        log(f"completion {name}: {out[name]}")
+        del R, Y, R0, ws
+    print(json.dumps({
+        "metric": "completion kernels: SDDMM / SpMM algorithmic GB/s and L-BFGS ms per iteration",
+        "unit": "GB/s", "n_gpus": 1, "dtype": "f64,f32", "data": "synthetic",
+        "config": {"workload": "matrix completion n1=n2=5e5 (X of order 1e6), m=1e7 samples (20 per row), "
+                               "planted rank 5, factor rank 16", **cfg},
+        "kernels": out}), flush=True)
 
 
 def cpu_baseline(runs, recs, target_s):

@@ -46,14 +46,21 @@ __device__ __forceinline__ void cmp_gather(const int32_t *__restrict__ ptr, cons
     constexpr int NV = Chunk<S>::N;
     const int b = ptr[row], e = ptr[row + 1];
     int k = b;
-    for (; k + 2 <= e; k += 2) {
-        const int64_t j0 = base + nbr[k], j1 = base + nbr[k + 1];
-        const S w0 = (S)ytil[eid[k]], w1 = (S)ytil[eid[k + 1]];
+    // four samples per step: indices and weights first, then four row loads in flight
+    for (; k + 4 <= e; k += 4) {
+        int64_t j[4];
+        S w[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            j[q] = base + nbr[k + q];
+            w[q] = (S)ytil[eid[k + q]];
+        }
         if (active) {
-            const CV v0 = *reinterpret_cast<const CV *>(V + j0 * ld + lane * NV);
-            const CV v1 = *reinterpret_cast<const CV *>(V + j1 * ld + lane * NV);
-            vfma(acc, w0, v0);
-            vfma(acc, w1, v1);
+            CV v[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[q] = *reinterpret_cast<const CV *>(V + j[q] * ld + lane * NV);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) vfma(acc, w[q], v[q]);
         }
     }
     for (; k < e; ++k) {
@@ -156,43 +163,60 @@ __global__ __launch_bounds__(kBlock) void k_cmp_sddmm(DevCompletion P, SddArgs<S
         const CV ui = active ? *reinterpret_cast<const CV *>(a.U + off) : zero;
         const CV vi = (MODE != kSddRefresh && active) ? *reinterpret_cast<const CV *>(a.V + off) : zero;
         const int b = P.top_ptr[i], e = P.top_ptr[i + 1];
-        for (int t = b; t < e; ++t) {
-            const int64_t pj = (P.n1 + P.top_col[t]) * a.ld + lane * NV;
-            const int k = P.top_eid[t];
-            if constexpr (MODE == kSddA) {
-                // <A_k, U V^T> = U_i . V_{n1+j} + U_{n1+j} . V_i
-                const CV vj = active ? *reinterpret_cast<const CV *>(a.V + pj) : zero;
-                const CV uj = active ? *reinterpret_cast<const CV *>(a.U + pj) : zero;
-                const double d = group_sum<GS>(vdot(ui, vj) + vdot(uj, vi));
-                if (lane == 0) a.out[k] = d;
-            } else if constexpr (MODE == kSddLS) {
-                const CV rj = active ? *reinterpret_cast<const CV *>(a.U + pj) : zero;
-                const CV dj = active ? *reinterpret_cast<const CV *>(a.V + pj) : zero;
-                const double q1 = 2.0 * group_sum<GS>(vdot(ui, dj) + vdot(vi, rj));
-                const double q2 = 2.0 * group_sum<GS>(vdot(vi, dj));
-                if (lane == 0) {
-                    const double yt = a.ytil[k];
-                    if (a.q1) a.q1[k] = q1;
-                    if (a.q2) a.q2[k] = q2;
-                    s[1] += yt * q2;
-                    s[2] += yt * q1;
-                    s[3] += q2 * q2;
-                    s[4] += q1 * q2;
-                    s[5] += q1 * q1;
-                }
-            } else {
-                const CV rj = active ? *reinterpret_cast<const CV *>(a.U + pj) : zero;
-                const double ak = 2.0 * group_sum<GS>(vdot(ui, rj));
-                if (lane == 0) {
-                    const double res = ak - P.b[k];
-                    double yk = a.y[k];
-                    if (a.sigma > 0.0) {
-                        yk -= a.sigma * res;
-                        a.y[k] = yk;
+        // four samples per step (the tail repeats the last sample's loads and
+        // skips its outputs): all eight partner-row loads are in flight before
+        // the first reduction
+        for (int t = b; t < e; t += 4) {
+            const int cnt = min(4, e - t);
+            int64_t pj[4];
+            int kk[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int tq = t + min(q, cnt - 1);
+                pj[q] = (P.n1 + P.top_col[tq]) * a.ld + lane * NV;
+                kk[q] = P.top_eid[tq];
+            }
+            CV xu[4], xv[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                xu[q] = active ? *reinterpret_cast<const CV *>(a.U + pj[q]) : zero;
+                xv[q] = (MODE != kSddRefresh && active) ? *reinterpret_cast<const CV *>(a.V + pj[q]) : zero;
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int k = kk[q];
+                const bool live = q < cnt;
+                if constexpr (MODE == kSddA) {
+                    // <A_k, U V^T> = U_i . V_{n1+j} + U_{n1+j} . V_i
+                    const double d = group_sum<GS>(vdot(ui, xv[q]) + vdot(xu[q], vi));
+                    if (lane == 0 && live) a.out[k] = d;
+                } else if constexpr (MODE == kSddLS) {
+                    // R rows in xu, D rows in xv
+                    const double q1 = 2.0 * group_sum<GS>(vdot(ui, xv[q]) + vdot(vi, xu[q]));
+                    const double q2 = 2.0 * group_sum<GS>(vdot(vi, xv[q]));
+                    if (lane == 0 && live) {
+                        const double yt = a.ytil[k];
+                        if (a.q1) a.q1[k] = q1;
+                        if (a.q2) a.q2[k] = q2;
+                        s[1] += yt * q2;
+                        s[2] += yt * q1;
+                        s[3] += q2 * q2;
+                        s[4] += q1 * q2;
+                        s[5] += q1 * q1;
                     }
-                    if (a.out) a.out[k] = ak;
-                    s[1] += P.b[k] * yk;
-                    s[2] += res * res;
+                } else {
+                    const double ak = 2.0 * group_sum<GS>(vdot(ui, xu[q]));
+                    if (lane == 0 && live) {
+                        const double res = ak - P.b[k];
+                        double yk = a.y[k];
+                        if (a.sigma > 0.0) {
+                            yk -= a.sigma * res;
+                            a.y[k] = yk;
+                        }
+                        if (a.out) a.out[k] = ak;
+                        s[1] += P.b[k] * yk;
+                        s[2] += res * res;
+                    }
                 }
             }
         }

@@ -21,6 +21,8 @@ available here; these synthetic families stand in for them):
 
 from __future__ import annotations
 
+import sys
+
 import numpy as np
 
 
@@ -33,7 +35,11 @@ def _distinct_pairs(draw, n: int, m: int, rng: np.random.Generator):
     loop-free pairs exist; keep them in order of first appearance (so the result
     is a uniform sample without replacement when ``draw`` is uniform)."""
     keys = np.empty(0, dtype=np.int64)
+    rounds = 0
     while keys.size < m:
+        if m >= 10_000_000:                      # large draws take minutes: show progress
+            print(f"[synth] distinct pairs: {keys.size}/{m} after {rounds} rounds", file=sys.stderr, flush=True)
+        rounds += 1
         need = m - keys.size
         k = max(2 * need, 1024)
         u, v = draw(rng, k)
