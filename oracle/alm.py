@@ -49,6 +49,7 @@ class Options:
     eta_min: float = 1e-9
     time_limit: float = 1e30
     phase2: bool = False           # switch to the splitting phase (Section 2.2)
+    precond: bool = False          # MaxCut: row-block H0 for the L-BFGS direction (not in the paper)
     switch_err1: float = 1e-3      # ... once err1 <= switch_err1 after an ALM step
     admm_check: int = 10
     max_admm: int = 5000
@@ -77,6 +78,25 @@ def default_sigma0(prob: SDPProblem) -> float:
     return max(4.0 * prob.c_l1 / prob.m, 1e-8)
 
 
+def row_block_h0(prob: SDPProblem, R: np.ndarray, sigma: float):
+    """H0 = P^{-1} with P block diagonal over rows, P_i = h_i I + 4 sigma R_i R_i^T,
+    h_i = 2 max(sum_j |C_ij|, 1e-3 ||vec(C)||_1 / n).
+
+    An extension, not in the paper (Algorithm 1 uses H0 = I).  For MaxCut the
+    Hessian of the Lagrangian in row i has the penalty block 4 sigma R_i R_i^T
+    (constraint i involves row i only) next to a part of the size of row i of
+    C; P models both.  Applied per row by Sherman-Morrison:
+    P_i^{-1} q = (q - kappa_i (R_i . q) R_i) / h_i, kappa_i = 4 sigma / (h_i + 4 sigma ||R_i||^2).
+    """
+    rowabs = np.asarray(abs(prob.C).sum(axis=1)).ravel()
+    h = 2.0 * np.maximum(rowabs, 1e-3 * prob.c_l1 / prob.n)
+    kappa = 4.0 * sigma / (h + 4.0 * sigma * np.sum(R * R, axis=1))
+
+    def apply(Q):
+        return (Q - (kappa * np.sum(R * Q, axis=1))[:, None] * R) / h[:, None]
+    return apply
+
+
 def lbfgs_minimize(prob: SDPProblem, R, y, sigma, eta, opts: Options, budget: int):
     """Minimise L(.; y, sigma) from R with Algorithm 1 and the exact step."""
     G = K.gradient(prob, R, y, sigma)
@@ -87,11 +107,12 @@ def lbfgs_minimize(prob: SDPProblem, R, y, sigma, eta, opts: Options, budget: in
     while it < min(opts.max_inner, budget):
         if gnorm <= target:
             break
-        D = two_loop(G, pairs)
+        h0 = row_block_h0(prob, R, sigma) if opts.precond else None
+        D = two_loop(G, pairs, h0)
         c = K.linesearch_coeffs(prob, R, D, y, sigma)
         if not c["a4"] < 0.0:
             pairs = []
-            D = -G
+            D = -G if h0 is None else -h0(G)
             c = K.linesearch_coeffs(prob, R, D, y, sigma)
         tau = K.exact_step(c["a1"], c["a2"], c["a3"], c["a4"])
         it += 1

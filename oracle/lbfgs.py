@@ -1,4 +1,4 @@
-"""L-BFGS search direction (paper Algorithm 1, H0 = I).
+"""L-BFGS search direction (paper Algorithm 1; H0 = I, or a given H0).
 
 Test infrastructure only (see the package docstring).
 """
@@ -12,12 +12,14 @@ def _dot(a, b):
     return float(np.sum(a * b))
 
 
-def two_loop(G: np.ndarray, pairs) -> np.ndarray:
+def two_loop(G: np.ndarray, pairs, h0=None) -> np.ndarray:
     """Direction from the gradient G and the stored pairs (s_t, y_t), oldest first.
 
     Starts from D = -G; the first loop runs from the newest pair to the oldest,
-    alpha_t = beta_t <s_t, D>, D -= alpha_t y_t; the second runs from the oldest
-    to the newest, D += (alpha_t - beta_t <y_t, D>) s_t, with beta_t = 1/<y_t, s_t>.
+    alpha_t = beta_t <s_t, D>, D -= alpha_t y_t; then D <- H0 D (Algorithm 1 has
+    H0 = I; `h0` is a callable applying another H0); the second loop runs from
+    the oldest to the newest, D += (alpha_t - beta_t <y_t, D>) s_t, with
+    beta_t = 1/<y_t, s_t>.
     """
     D = -G.copy()
     alpha = [0.0] * len(pairs)
@@ -26,6 +28,8 @@ def two_loop(G: np.ndarray, pairs) -> np.ndarray:
         st, yt = pairs[t]
         alpha[t] = beta[t] * _dot(st, D)
         D = D - alpha[t] * yt
+    if h0 is not None:
+        D = h0(D)
     for t in range(len(pairs)):
         st, yt = pairs[t]
         D = D + (alpha[t] - beta[t] * _dot(yt, D)) * st
