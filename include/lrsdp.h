@@ -138,7 +138,7 @@ int lrsdp_problem_upload(lrsdp_ctx *ctx, lrsdp_problem *prob, void *dev,
  * 1e8, feas_decrease = 0.25, eta0 = 0.1, eta_factor = 0.25, eta_min = 1e-9,
  * max_outer = 300, max_inner = 2000, max_iter_total = 200000,
  * check_every = 8, time_limit_s = 1e30, refresh_every = 0 (off), phase2 = 0,
- * switch_err1 = 1e-3, admm_check = 10, max_admm = 5000.
+ * switch_err1 = 1e-3, admm_check = 10, max_admm = 5000, precond = 0.
  */
 typedef struct {
     int     prec;             /* LRSDP_F64 / LRSDP_F32 / LRSDP_F32_BF16IN      */
@@ -167,6 +167,11 @@ typedef struct {
     double  switch_err1;      /* ALM -> splitting threshold on err1            */
     int     admm_check;       /* splitting iterations between measure checks   */
     int     max_admm;         /* splitting iterations at most                  */
+    int     precond;          /* 1: MaxCut L-BFGS with the row-block H0
+                                 P^{-1}, P_i = h_i I + 4 sigma R_i R_i^T and
+                                 h_i = 2 max(sum_j |C_ij|, 1e-3 ||vec(C)||_1 / n),
+                                 in place of Algorithm 1's H0 = I (an extension;
+                                 lbfgs_mem <= 4; EUNSUPPORTED for completion)  */
 } lrsdp_options;
 
 void lrsdp_options_default(lrsdp_options *opts);
@@ -202,7 +207,8 @@ int lrsdp_workspace_bytes(const lrsdp_problem *prob, const lrsdp_options *opts,
  * least lrsdp_workspace_bytes.  Blocking.  Returns LRSDP_OK when converged,
  * LRSDP_NOT_CONVERGED at a limit (res still filled), or an error code.
  * The algorithm: ALM (Section 2.1) whose subproblem is minimised by L-BFGS
- * (Algorithm 1, H0 = I) with the exact quartic line search of appendix A.2.
+ * (Algorithm 1, H0 = I; the row-block H0 with precond = 1) with the exact
+ * quartic line search of appendix A.2.
  */
 int lrsdp_solve(lrsdp_ctx *ctx, lrsdp_problem *prob, const lrsdp_options *opts,
                 void *ws, size_t ws_bytes, void *R, double *y,
@@ -337,7 +343,8 @@ int lrsdp_certify_workspace_bytes(const lrsdp_problem *prob, int max_iter,
  * Synchronises the context stream.  Errors: EINVAL (arguments, not uploaded),
  * EUNSUPPORTED (n < 16), ENOMEM (workspace short), ENUMERIC (rank-deficient
  * start block or non-finite values).  The bound is exact up to the loss of
- * orthogonality of the Lanczos basis (no re-orthogonalisation).
+ * orthogonality of the Lanczos basis (re-orthogonalised only against the two
+ * previous blocks).
  */
 int lrsdp_certify(lrsdp_ctx *ctx, const lrsdp_problem *prob, const double *y,
                   int max_iter, double tol, uint64_t seed, void *work,

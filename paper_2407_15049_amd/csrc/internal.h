@@ -54,6 +54,7 @@ struct DevCsr {
     const int32_t *col = nullptr;       // nnz; bit 31 = negative weight (kWSign)
     const double *val = nullptr;        // nnz (kWGeneral only)
     const double *diag = nullptr;       // n   (C_ii)
+    const double *hrow = nullptr;       // n   2 max(sum_j |C_ij|, 1e-3 ||vec(C)||_1 / n) (row-block H0)
     // Work lists.  Light rows (<= kSegLen nonzeros) sorted by decreasing length
     // inside windows of consecutive rows; heavy rows split into segments.
     const int32_t *light = nullptr;     // n_light row ids
@@ -86,7 +87,7 @@ struct lrsdp_problem {
     // host data
     std::vector<int32_t> row_ptr, col, light, heavy, heavy_seg;
     std::vector<int4> seg;
-    std::vector<double> val, diag;
+    std::vector<double> val, diag, hrow;
     std::vector<int32_t> top_ptr, top_col, top_eid, bot_ptr, bot_row, bot_eid, samp_i, samp_j;
     std::vector<double> b;
     // device views (valid after upload)

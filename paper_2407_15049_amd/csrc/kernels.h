@@ -18,7 +18,9 @@ struct SolverState {
     double a[4];                         // quartic coefficients a1..a4
     double taus[kMaxMem];                // step of the direction in each D slot
     double gram[kMaxBasis * kMaxBasis];  // Gram matrix of the G/D ring slots
-    double coef[kMaxBasis];              // next direction = sum coef_j basis_j
+    double coef[kMaxBasis];              // next direction = sum coef_j basis_j (precond: the
+                                         // G-slot part is multiplied by P^{-1} row by row)
+    double wgram[(kMaxMem + 1) * (kMaxMem + 1)];  // precond: G slots' Gram in the P^{-1} metric
     // ALM measures after the last multiplier step
     double obj, dual, res_norm, err1, err1_inf, err3, err1_prev;
     // options copied at solve start
@@ -34,7 +36,27 @@ struct SolverState {
     int converged;  // ALM stop test met
     int numeric;    // NaN/Inf met
     int refreshes;  // exact C R recomputations
+    int precond;    // 1: row-block H0 = P^{-1} in the two-loop (MaxCut)
 };
+
+// Row-block H0 of the L-BFGS direction (solve option precond, MaxCut):
+// P_i = h_i I + 4 sigma R_i R_i^T, applied as
+// P_i^{-1} q = (q - kap_i (R_i . q) R_i) / h_i with kap_i = 4 sigma / (h_i + 4 sigma ||R_i||^2).
+// rho[g * n + i] = R_i . G_{g,i} (row dots of the current R with G ring slot g).
+constexpr int kPcMem = 2;              // largest L-BFGS memory with precond
+constexpr int kPcPairs = (kPcMem + 1) * (kPcMem + 2) / 2;
+constexpr int kPcOff = 17;             // partial-sum index of the first weighted Gram pair
+struct PcBufs {
+    double *rho;         // (T + 1) x n
+    double *kap;         // n
+    const double *hrow;  // n
+    int64_t n;
+};
+
+// index of the unordered G-slot pair (j, l), j <= l <= kPcMem
+__host__ __device__ inline int pc_pair(int j, int l) {
+    return j * (kPcMem + 1) - j * (j - 1) / 2 + (l - j);
+}
 
 // Pointers of the L-BFGS rings: G slots 0..T, D slots 0..T-1.  Basis index of
 // G slot g is g, of D slot d is T + 1 + d.

@@ -135,6 +135,7 @@ extern "C" int lrsdp_problem_maxcut(int64_t n, int64_t n_edges, const int32_t *u
     std::vector<int32_t> ctmp;
     std::vector<double> wtmp;
     p->diag.assign(n, 0.0);
+    p->hrow.assign(n, 0.0);
     double c_l1 = 0.0;
     int64_t max_row = 0;
     for (int64_t i = 0; i < n; ++i) {
@@ -150,7 +151,7 @@ extern "C" int lrsdp_problem_maxcut(int64_t n, int64_t n_edges, const int32_t *u
             ctmp[k] = p->col[b0 + idx[k]];
             wtmp[k] = wv[b0 + idx[k]];
         }
-        double wsum = 0.0;
+        double wsum = 0.0, wabs = 0.0;
         for (int64_t k = 0; k < len; ++k) {
             if (k > 0 && ctmp[k] == ctmp[k - 1]) {
                 int32_t c = ctmp[k];
@@ -160,11 +161,16 @@ extern "C" int lrsdp_problem_maxcut(int64_t n, int64_t n_edges, const int32_t *u
             p->col[b0 + k] = ctmp[k];
             wv[b0 + k] = wtmp[k];
             wsum += wtmp[k];
+            wabs += std::fabs(wtmp[k]);
             c_l1 += std::fabs(wtmp[k]) * 0.25;
         }
         p->diag[i] = -0.25 * wsum;
         c_l1 += std::fabs(p->diag[i]);
+        p->hrow[i] = 0.25 * wabs + std::fabs(p->diag[i]);   // sum_j |C_ij|, finished below
     }
+    // h_i of the row-block H0 of the L-BFGS direction (solve option precond)
+    const double hfloor = n > 0 ? 1e-3 * c_l1 / (double)n : 0.0;
+    for (int64_t i = 0; i < n; ++i) p->hrow[i] = 2.0 * std::max(p->hrow[i], hfloor);
     if (mode == kWSign) {
         for (int64_t k = 0; k < nnz; ++k)
             if (wv[k] < 0) p->col[k] = (int32_t)((uint32_t)p->col[k] | 0x80000000u);
@@ -298,6 +304,7 @@ size_t plan_device(const lrsdp_problem *p, size_t *offs) {
         add(p->heavy.size() * 4);
         add(p->heavy_seg.size() * 4);
         add(p->seg.size() * 256);      // segment partial sums (<= 256 B per row)
+        add(p->hrow.size() * 8);
     } else {
         add(p->top_ptr.size() * 4);
         add(p->top_col.size() * 4);
@@ -344,6 +351,7 @@ extern "C" int lrsdp_problem_upload(lrsdp_ctx *ctx, lrsdp_problem *p, void *dev,
         LRSDP_HIP_TRY(put(offs[5], p->seg.data(), p->seg.size() * sizeof(int4)));
         LRSDP_HIP_TRY(put(offs[6], p->heavy.data(), p->heavy.size() * 4));
         LRSDP_HIP_TRY(put(offs[7], p->heavy_seg.data(), p->heavy_seg.size() * 4));
+        LRSDP_HIP_TRY(put(offs[9], p->hrow.data(), p->hrow.size() * 8));
         DevCsr &c = p->csr;
         c.row_ptr = (const int32_t *)(base + offs[0]);
         c.col = (const int32_t *)(base + offs[1]);
@@ -354,6 +362,7 @@ extern "C" int lrsdp_problem_upload(lrsdp_ctx *ctx, lrsdp_problem *p, void *dev,
         c.heavy = (const int32_t *)(base + offs[6]);
         c.heavy_seg = (const int32_t *)(base + offs[7]);
         c.seg_buf = base + offs[8];
+        c.hrow = (const double *)(base + offs[9]);
         c.n = p->info.n;
         c.nnz = p->info.nnz;
         c.n_light = (int64_t)p->light.size();

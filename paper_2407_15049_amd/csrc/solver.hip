@@ -23,11 +23,12 @@ int launch_reduce(hipStream_t, const double *, int, int, double *);
 int launch_cubic(hipStream_t, const double *, double *);
 int launch_update_maxcut(hipStream_t, int, SolverState *, void *, const void *, const double *, const double *,
                          const double *, const double *, const double *, double *, void *const *, void *const *,
-                         int, int64_t, int64_t, double *, int *);
+                         int, int64_t, int64_t, double *, int *, const PcBufs * = nullptr);
 int launch_combine(hipStream_t, int, SolverState *, const double *, const void *const *, int, void *, int64_t,
-                   int64_t, double *, int *, uint16_t *);
+                   int64_t, double *, int *, uint16_t *, const void * = nullptr, const PcBufs * = nullptr);
 int launch_grad_init_maxcut(hipStream_t, int, SolverState *, const void *, const void *, const double *,
-                            const double *, double *, void *, int64_t, int64_t, double *, int *);
+                            const double *, double *, void *, int64_t, int64_t, double *, int *,
+                            const PcBufs * = nullptr);
 int launch_fill(hipStream_t, int, void *, int64_t);
 int launch_avg(hipStream_t, int, const void *, const void *, void *, int64_t);
 int launch_dots(hipStream_t, int, const void *, const void *const *, int, int64_t, int64_t, double *, int *);
@@ -183,12 +184,13 @@ extern "C" void lrsdp_options_default(lrsdp_options *o) {
     o->switch_err1 = 1e-3;
     o->admm_check = 10;
     o->max_admm = 5000;
+    o->precond = 0;
 }
 
 namespace {
 
 struct WsPlan {
-    size_t cd, gring[kMaxMem + 1], dring[kMaxMem], ytil[2], rn, q1, q2, acon, shadow, total;
+    size_t cd, gring[kMaxMem + 1], dring[kMaxMem], ytil[2], rn, q1, q2, acon, shadow, rho, kap, total;
 };
 
 int plan_workspace(const lrsdp_problem *p, const lrsdp_options *o, WsPlan *w) {
@@ -200,6 +202,12 @@ int plan_workspace(const lrsdp_problem *p, const lrsdp_options *o, WsPlan *w) {
     if (o->rank < 1 || o->ld < o->rank) return set_error(LRSDP_EINVAL, "need 1 <= rank <= ld");
     rc = check_ld(o->prec, o->ld);
     if (rc) return rc;
+    if (o->precond) {
+        if (p->info.kind != LRSDP_MAXCUT)
+            return set_error(LRSDP_EUNSUPPORTED, "precond (row-block H0) is for MaxCut problems");
+        if (o->lbfgs_mem > kPcMem)
+            return set_error(LRSDP_EINVAL, "precond needs lbfgs_mem <= %d (got %d)", kPcMem, o->lbfgs_mem);
+    }
     const size_t arr = (size_t)p->info.n * o->ld * elem_size(o->prec);
     size_t off = 0;
     auto take = [&](size_t b) {
@@ -217,6 +225,8 @@ int plan_workspace(const lrsdp_problem *p, const lrsdp_options *o, WsPlan *w) {
     w->q2 = take((size_t)p->info.m * 8);
     w->acon = take((size_t)p->info.m * 8);
     w->shadow = take(o->prec == LRSDP_F32_BF16IN ? (size_t)p->info.n * bf16_ld(o->ld) * 2 : 0);
+    w->rho = take(o->precond ? (size_t)(o->lbfgs_mem + 1) * p->info.n * 8 : 0);
+    w->kap = take(o->precond ? (size_t)p->info.n * 8 : 0);
     w->total = off + 256;
     return LRSDP_OK;
 }
@@ -296,6 +306,8 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
     double *acon = reinterpret_cast<double *>(ws + w.acon);
     const bool bf = o->prec == LRSDP_F32_BF16IN && mc;
     uint16_t *shadow = bf ? reinterpret_cast<uint16_t *>(ws + w.shadow) : nullptr;
+    PcBufs pcb{reinterpret_cast<double *>(ws + w.rho), reinterpret_cast<double *>(ws + w.kap), p->csr.hrow, n};
+    const PcBufs *pc = (mc && o->precond) ? &pcb : nullptr;
     SolverState *st = at<SolverState>(c->scratch, kStateOff);
     double *part_ls = at<double>(c->scratch, kPartLsOff);
     double *part_cb = at<double>(c->scratch, kPartCbOff);
@@ -317,6 +329,7 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
     h.eta_factor = o->eta_factor;
     h.eta_min = o->eta_min;
     h.b_l1 = p->info.b_l1;
+    h.precond = (mc && o->precond) ? 1 : 0;
     h.b_inf = p->info.b_inf;
     h.max_inner = o->max_inner;
     h.T = T;
@@ -382,7 +395,8 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
         // subproblem start: ytil, G_0, D_0 = -G_0
         int nb = 0, ncb = 0;
         if (mc) {
-            if ((rc = launch_grad_init_maxcut(s, prec, st, R, CD, y, rn, ytil[0], gring[0], n, ld, part_misc, &nb)))
+            if ((rc = launch_grad_init_maxcut(s, prec, st, R, CD, y, rn, ytil[0], gring[0], n, ld, part_misc, &nb,
+                                              pc)))
                 break;
         } else {
             if ((rc = cmp_ytil(s, p->cmp, st, 0.0, acon, y, ytil[0]))) break;
@@ -391,7 +405,8 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
         int64_t left = o->max_iter_total - total_inner;
         int k_limit = (int)std::min<int64_t>(o->max_inner, std::max<int64_t>(left, 0));
         if ((rc = launch_init_finalize(s, st, part_misc, nb, k_limit))) break;
-        if ((rc = launch_combine(s, prec, st, nullptr, basis, 2 * T + 1, nullptr, n, ld, part_cb, &ncb, shadow))) break;
+        if ((rc = launch_combine(s, prec, st, nullptr, basis, 2 * T + 1, nullptr, n, ld, part_cb, &ncb, shadow, R, pc)))
+            break;
         // L-BFGS iterations in batches of B.  `it` indexes the ring slots (reset
         // by a gradient refresh); `done_it` counts every enqueued iteration.
         int64_t it = 0, done_it = 0, since_refresh = 0;
@@ -416,7 +431,7 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
                     int np2 = 0;
                     if ((rc = spmm_maxcut(s, p->csr, prec, ref, &np2))) break;
                     if ((rc = launch_grad_init_maxcut(s, prec, st, R, CD, y, rn, ytil[0], gring[0], n, ld, part_misc,
-                                                      &nb2)))
+                                                      &nb2, pc)))
                         break;
                 } else {
                     if ((rc = cmp_sddmm(s, p->cmp, prec, 2, R, nullptr, ld, acon, nullptr, nullptr, nullptr, y, 0.0,
@@ -428,7 +443,7 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
                 }
                 if ((rc = launch_init_finalize(s, st, part_misc, nb2, -1))) break;
                 if ((rc = launch_combine(s, prec, st, nullptr, basis, 2 * T + 1, nullptr, n, ld, part_cb, &ncb,
-                                         shadow)))
+                                         shadow, R, pc)))
                     break;
             }
             for (int b = 0; b < B && !mc; ++b, ++it, ++done_it, ++since_refresh) {
@@ -467,10 +482,11 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
                 if ((rc = launch_ls_finalize(s, st, part_ls, nls, part_cb, ncb, LRSDP_MAXCUT))) break;
                 int nup = 0;
                 if ((rc = launch_update_maxcut(s, prec, st, R, CD, y, rn, q1, q2, ytil[it % 2], ytil[(it + 1) % 2],
-                                               gring, dring, T, n, ld, part_up, &nup)))
+                                               gring, dring, T, n, ld, part_up, &nup, pc)))
                     break;
                 if ((rc = launch_lbfgs_finalize(s, st, part_up, nup))) break;
-                if ((rc = launch_combine(s, prec, st, nullptr, basis, 2 * T + 1, nullptr, n, ld, part_cb, &ncb, shadow)))
+                if ((rc = launch_combine(s, prec, st, nullptr, basis, 2 * T + 1, nullptr, n, ld, part_cb, &ncb, shadow,
+                                         R, pc)))
                     break;
             }
             if (rc) break;

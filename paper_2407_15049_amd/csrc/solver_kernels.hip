@@ -167,6 +167,61 @@ __device__ void two_loop_coef(SolverState &st) {
     for (int j = 0; j < kMaxBasis; ++j) st.coef[j] = j < NB ? q[j] : 0.0;
 }
 
+// The same recursion with H0 = P^{-1} (row-block H0, see PcBufs).  The first
+// loop keeps q in the span of the G slots (coefficients qa); the middle step
+// r = P^{-1} q is kept symbolic; the second loop needs y_t^T P^{-1} q, which
+// is a combination of entries of the P^{-1}-weighted Gram matrix of the G
+// slots (wgram, recomputed every iteration because P moves with R), and
+// y_t^T s_t', entries of the plain Gram matrix.  Output: coefficients qa on the
+// G slots (the combine pass applies P^{-1} to that part) and on the D slots.
+__device__ void two_loop_coef_pc(SolverState &st) {
+    const int T = st.T, NB = 2 * T + 1, nmem = st.nmem, gk = st.gk, dk = st.dk;
+    const double *M = st.gram;
+    const double *W = st.wgram;
+    constexpr int WS = kMaxMem + 1;
+    double qa[kMaxMem + 1], alpha[kMaxMem], beta[kMaxMem], fd[kMaxMem], tau[kMaxMem];
+    int ds[kMaxMem], g0[kMaxMem], g1[kMaxMem];
+    for (int j = 0; j <= T; ++j) qa[j] = 0.0;
+    qa[gk] = -1.0;
+    for (int t = 0; t < nmem; ++t) {  // t = 0 oldest
+        const int back = nmem - t;
+        ds[t] = T + 1 + ((dk - back) % T + T) % T;
+        g0[t] = ((gk - back) % (T + 1) + (T + 1)) % (T + 1);
+        g1[t] = (g0[t] + 1) % (T + 1);
+        tau[t] = st.taus[ds[t] - T - 1];
+        beta[t] = 1.0 / (tau[t] * (M[g1[t] * kMaxBasis + ds[t]] - M[g0[t] * kMaxBasis + ds[t]]));
+        fd[t] = 0.0;
+    }
+    for (int t = nmem - 1; t >= 0; --t) {
+        double sq = 0.0;
+        for (int j = 0; j <= T; ++j) sq += M[ds[t] * kMaxBasis + j] * qa[j];
+        alpha[t] = beta[t] * tau[t] * sq;
+        qa[g1[t]] -= alpha[t];
+        qa[g0[t]] += alpha[t];
+    }
+    for (int t = 0; t < nmem; ++t) {
+        double yr = 0.0;
+        for (int j = 0; j <= T; ++j) yr += (W[g1[t] * WS + j] - W[g0[t] * WS + j]) * qa[j];
+        for (int u = 0; u < t; ++u) yr += (M[g1[t] * kMaxBasis + ds[u]] - M[g0[t] * kMaxBasis + ds[u]]) * fd[u];
+        fd[t] = (alpha[t] - beta[t] * yr) * tau[t];
+    }
+    // descent safeguard: <G_k, D> < 0, else D = -P^{-1} G_k (always a descent direction)
+    double gd = 0.0;
+    for (int j = 0; j <= T; ++j) gd += W[gk * WS + j] * qa[j];
+    for (int t = 0; t < nmem; ++t) gd += M[gk * kMaxBasis + ds[t]] * fd[t];
+    if (!(gd < 0.0)) {
+        st.nmem = 0;
+        for (int j = 0; j <= T; ++j) qa[j] = 0.0;
+        qa[gk] = -1.0;
+        for (int t = 0; t < nmem; ++t) fd[t] = 0.0;
+    }
+    for (int j = 0; j < kMaxBasis; ++j) st.coef[j] = 0.0;
+    for (int j = 0; j <= T; ++j) st.coef[j] = qa[j];
+    if (st.nmem > 0)
+        for (int t = 0; t < nmem; ++t) st.coef[ds[t]] = fd[t];
+    (void)NB;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -228,11 +283,12 @@ __global__ __launch_bounds__(kBlock) void k_ls_finalize(SolverState *gst, const 
 // compute the next direction's coefficients.
 __global__ __launch_bounds__(kBlock) void k_lbfgs_finalize(SolverState *gst, const double *up_part, int n_up) {
     __shared__ SolverState st;
-    __shared__ double raw[kMaxBasis];
+    __shared__ double raw[kMaxSums];
     block_copy(&st, gst);
     __syncthreads();
     if (st.done) return;
-    reduce_rows<kMaxBasis>(up_part, n_up, raw);
+    if (st.precond) reduce_rows<kMaxSums>(up_part, n_up, raw);
+    else reduce_rows<kMaxBasis>(up_part, n_up, raw);
     if (threadIdx.x == 0) {
         const int T = st.T, NB = 2 * T + 1;
         const int gk = st.gk, gk1 = (gk + 1) % (T + 1), ds = T + 1 + st.dk;
@@ -241,6 +297,14 @@ __global__ __launch_bounds__(kBlock) void k_lbfgs_finalize(SolverState *gst, con
             const double v = j <= T ? raw[j] : raw[kMaxMem + 1 + (j - T - 1)];
             M[gk1 * kMaxBasis + j] = v;
             M[j * kMaxBasis + gk1] = v;
+        }
+        if (st.precond) {
+            for (int j = 0; j <= T; ++j)
+                for (int l = j; l <= T; ++l) {
+                    const double v = raw[kPcOff + pc_pair(j, l)];
+                    st.wgram[j * (kMaxMem + 1) + l] = v;
+                    st.wgram[l * (kMaxMem + 1) + j] = v;
+                }
         }
         const double tau = st.tau;
         const double ys = tau * (M[gk1 * kMaxBasis + ds] - M[gk * kMaxBasis + ds]);
@@ -261,6 +325,8 @@ __global__ __launch_bounds__(kBlock) void k_lbfgs_finalize(SolverState *gst, con
             st.done = 1;
         } else if (st.k >= st.max_inner) {
             st.done = 2;
+        } else if (st.precond) {
+            two_loop_coef_pc(st);
         } else {
             two_loop_coef(st);
         }
@@ -447,6 +513,127 @@ __global__ __launch_bounds__(kBlock) void k_update_maxcut(UpdateArgs<S> a) {
     block_sums_store<kMaxBasis>(s, a.partials + (size_t)blockIdx.x * kMaxSums);
 }
 
+// The update sweep with the row-block H0 (solve option precond): one lane
+// group of GS lanes per row (row dots need the whole row).  Besides everything
+// k_update_maxcut computes it stores, for the new R, rho_g = R_i . G_{g,i} for
+// every G slot and kap_i, and sums the P^{-1}-weighted Gram matrix of the G
+// slots, sum_i [G_j,i . G_l,i - kap_i rho_j rho_l] / h_i, at partial indices
+// kPcOff + pc_pair(j, l).  T <= kPcMem.
+template <typename S, int GS>
+__global__ __launch_bounds__(kBlock) void k_update_maxcut_pc(UpdateArgs<S> a, PcBufs pc, int ld) {
+    using CV = typename Chunk<S>::V;
+    constexpr int NV = Chunk<S>::N;
+    constexpr int GPB = kBlock / GS;
+    SolverState *st = a.st;
+    if (st->done) return;
+    const double tau = st->tau, sigma = st->sigma;
+    const int T = st->T, gk = st->gk, gk1 = (gk + 1) % (T + 1), dk = st->dk;
+    const int lane = threadIdx.x % GS, grp = threadIdx.x / GS;
+    const bool active = lane * NV < ld;
+    const int cpr = ld / NV;
+    const CV zero = vzero(CV{});
+    // sums: G slots [0, kPcMem], D slots [kPcMem + 1, 2 kPcMem], weighted pairs after
+    constexpr int NS = 2 * kPcMem + 1 + kPcPairs;
+    double s[NS];
+#pragma unroll
+    for (int j = 0; j < NS; ++j) s[j] = 0.0;
+    const CV *D = nullptr;
+    const CV *Go = nullptr;
+    CV *Gn = nullptr;
+#pragma unroll
+    for (int g = 0; g <= kPcMem; ++g) {
+        if (g == gk) Go = reinterpret_cast<const CV *>(a.rings.g[g]);
+        if (g == gk1) Gn = reinterpret_cast<CV *>(a.rings.g[g]);
+    }
+#pragma unroll
+    for (int d = 0; d < kPcMem; ++d)
+        if (d == dk) D = reinterpret_cast<const CV *>(a.rings.d[d]);
+    CV *R = reinterpret_cast<CV *>(a.R);
+    const CV *CD = reinterpret_cast<const CV *>(a.CD);
+    for (int64_t row = (int64_t)blockIdx.x * GPB + grp; row < pc.n; row += (int64_t)gridDim.x * GPB) {
+        const int64_t c = row * cpr + lane;
+        const CV r = active ? R[c] : zero, d = active ? D[c] : zero;
+        const CV cd = active ? CD[c] : zero, go = active ? Go[c] : zero;
+        const double yold = a.ytil_in[row];
+        const double rnn = a.rn[row] + tau * (a.q1[row] + tau * a.q2[row]);
+        const double ynew = a.y[row] + sigma * (1.0 - rnn);
+        const D4 R0 = widen(r), Dd = widen(d), CDd = widen(cd), G0 = widen(go);
+        D4 Rn;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) Rn.v[e] = fma(tau, Dd.v[e], R0.v[e]);
+        CV rn_s;
+        narrow(Rn, rn_s);
+        Rn = widen(rn_s);
+        D4 Gv;
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            Gv.v[e] = G0.v[e] + 2.0 * tau * CDd.v[e] + 2.0 * yold * R0.v[e] - 2.0 * ynew * Rn.v[e];
+        CV gn_s;
+        narrow(Gv, gn_s);
+        if (active) {
+            R[c] = rn_s;
+            Gn[c] = gn_s;
+        }
+        // the G slots of this chunk (new gradient in slot gk1), held as named
+        // values: kPcMem = 2, so three slots and six pairs, written out
+        static_assert(kPcMem == 2, "the preconditioned sweep is written for three G slots");
+        const CV *gp0 = reinterpret_cast<const CV *>(a.rings.g[0]);
+        const CV *gp1 = reinterpret_cast<const CV *>(a.rings.g[1]);
+        const CV *gp2 = reinterpret_cast<const CV *>(a.rings.g[2]);
+        const CV b0 = gk1 == 0 ? gn_s : (gk == 0 ? go : (active && T >= 0 ? gp0[c] : zero));
+        const CV b1 = gk1 == 1 ? gn_s : (gk == 1 ? go : (active && T >= 1 ? gp1[c] : zero));
+        const CV b2 = gk1 == 2 ? gn_s : (gk == 2 ? go : (active && T >= 2 ? gp2[c] : zero));
+        s[0] += vdot(gn_s, b0);
+        s[1] += vdot(gn_s, b1);
+        if (T >= 2) s[2] += vdot(gn_s, b2);
+        {
+            const CV *dp0 = reinterpret_cast<const CV *>(a.rings.d[0]);
+            const CV *dp1 = reinterpret_cast<const CV *>(a.rings.d[1]);
+            const CV bd0 = dk == 0 ? d : (active ? dp0[c] : zero);
+            s[kPcMem + 1] += vdot(gn_s, bd0);
+            if (T >= 2) {
+                const CV bd1 = dk == 1 ? d : (active ? dp1[c] : zero);
+                s[kPcMem + 2] += vdot(gn_s, bd1);
+            }
+        }
+        const double rho0 = group_sum<GS>(vdot(rn_s, b0));
+        const double rho1 = group_sum<GS>(vdot(rn_s, b1));
+        const double rho2 = T >= 2 ? group_sum<GS>(vdot(rn_s, b2)) : 0.0;
+        const double h = pc.hrow[row];
+        const double w = 1.0 / h;
+        const double kap = 4.0 * sigma / (h + 4.0 * sigma * rnn);
+        const double wk = lane == 0 ? w * kap : 0.0;
+        constexpr int P0 = 2 * kPcMem + 1;
+        s[P0 + pc_pair(0, 0)] += w * vdot(b0, b0) - wk * rho0 * rho0;
+        s[P0 + pc_pair(0, 1)] += w * vdot(b0, b1) - wk * rho0 * rho1;
+        s[P0 + pc_pair(1, 1)] += w * vdot(b1, b1) - wk * rho1 * rho1;
+        if (T >= 2) {
+            s[P0 + pc_pair(0, 2)] += w * vdot(b0, b2) - wk * rho0 * rho2;
+            s[P0 + pc_pair(1, 2)] += w * vdot(b1, b2) - wk * rho1 * rho2;
+            s[P0 + pc_pair(2, 2)] += w * vdot(b2, b2) - wk * rho2 * rho2;
+        }
+        if (lane == 0) {
+            a.ytil_out[row] = ynew;
+            pc.kap[row] = kap;
+            pc.rho[row] = rho0;
+            pc.rho[pc.n + row] = rho1;
+            if (T >= 2) pc.rho[2 * pc.n + row] = rho2;
+        }
+    }
+    // partial row in the layout of the flat sweep (G slot g at g, D slot d at
+    // kMaxMem + 1 + d) plus the weighted pairs at kPcOff
+    double out[kMaxSums];
+#pragma unroll
+    for (int j = 0; j < kMaxSums; ++j) out[j] = 0.0;
+#pragma unroll
+    for (int g = 0; g <= kPcMem; ++g) out[g] = s[g];
+#pragma unroll
+    for (int d = 0; d < kPcMem; ++d) out[kMaxMem + 1 + d] = s[kPcMem + 1 + d];
+#pragma unroll
+    for (int q = 0; q < kPcPairs; ++q) out[kPcOff + q] = s[2 * kPcMem + 1 + q];
+    block_sums_store<kMaxSums>(out, a.partials + (size_t)blockIdx.x * kMaxSums);
+}
+
 template <typename S>
 struct CombineArgs {
     SolverState *st;        // coefficients (solver) or nullptr
@@ -458,6 +645,8 @@ struct CombineArgs {
     double *partials;       // dots of out with each basis entry, then ||out||^2
     uint16_t *shadow;       // float32 only: bfloat16 copy of out (row stride ldb), or nullptr
     int64_t ld, ldb;
+    const S *R;             // precond: current R
+    PcBufs pc;              // precond: rho, kap, h
 };
 
 // float32 -> bfloat16, round to nearest, ties to even (NaN kept quiet)
@@ -491,16 +680,45 @@ __global__ __launch_bounds__(kBlock) void k_combine(CombineArgs<S> a) {
     double s[kMaxBasis + 1];
 #pragma unroll
     for (int j = 0; j <= kMaxBasis; ++j) s[j] = 0.0;
+    const bool pcon = st && st->precond;
+    const int TG = st ? st->T : -1;               // G slots 0..TG (precond only)
+    const int64_t cpr = a.nchunks / (a.pc.n > 0 ? a.pc.n : 1);
     for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < a.nchunks; c += (int64_t)gridDim.x * kBlock) {
         CV b[kMaxBasis];
         D4 acc{{0.0, 0.0, 0.0, 0.0}};
+        if (pcon) {
+            // D = P^{-1} (sum over G slots) + sum over D slots, row by row
+            D4 accg{{0.0, 0.0, 0.0, 0.0}};
+            const int64_t row = c / cpr;
+            double ra = 0.0;
 #pragma unroll
-        for (int j = 0; j < kMaxBasis; ++j) {
-            if (j < NB) {
-                b[j] = reinterpret_cast<const CV *>(a.basis[j])[c];
-                D4 w = widen(b[j]);
+            for (int j = 0; j < kMaxBasis; ++j) {
+                if (j < NB) {
+                    b[j] = reinterpret_cast<const CV *>(a.basis[j])[c];
+                    D4 w = widen(b[j]);
+                    if (j <= TG) {
 #pragma unroll
-                for (int e = 0; e < 4; ++e) acc.v[e] = fma(cf[j], w.v[e], acc.v[e]);
+                        for (int e = 0; e < 4; ++e) accg.v[e] = fma(cf[j], w.v[e], accg.v[e]);
+                        ra = fma(cf[j], a.pc.rho[j * a.pc.n + row], ra);
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) acc.v[e] = fma(cf[j], w.v[e], acc.v[e]);
+                    }
+                }
+            }
+            const D4 r = widen(reinterpret_cast<const CV *>(a.R)[c]);
+            const double hi = 1.0 / a.pc.hrow[row], kr = a.pc.kap[row] * ra;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc.v[e] = fma(hi, accg.v[e] - kr * r.v[e], acc.v[e]);
+        } else {
+#pragma unroll
+            for (int j = 0; j < kMaxBasis; ++j) {
+                if (j < NB) {
+                    b[j] = reinterpret_cast<const CV *>(a.basis[j])[c];
+                    D4 w = widen(b[j]);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) acc.v[e] = fma(cf[j], w.v[e], acc.v[e]);
+                }
             }
         }
         CV o;
@@ -535,6 +753,7 @@ struct GradInitArgs {
     S *G;
     int64_t n, ld;
     double *partials;
+    PcBufs pc;          // precond: rho of G slot 0 and kap (rho == nullptr: off)
 };
 
 // Start of a subproblem (MaxCut): ytil = y + sigma (1 - ||R_i||^2),
@@ -552,16 +771,26 @@ __global__ __launch_bounds__(kBlock) void k_grad_init_maxcut(GradInitArgs<S> a) 
         const int64_t off = row * a.ld + lane * NV;
         const double yt = a.y[row] + sigma * (1.0 - a.rn[row]);
         if (lane == 0) a.ytil[row] = yt;
-        if (!active) continue;
-        D4 r = widen(*reinterpret_cast<const CV *>(a.R + off));
-        D4 cr = widen(*reinterpret_cast<const CV *>(a.CR + off));
+        const CV zero = vzero(CV{});
+        const CV rs = active ? *reinterpret_cast<const CV *>(a.R + off) : zero;
+        D4 r = widen(rs);
+        D4 cr = widen(active ? *reinterpret_cast<const CV *>(a.CR + off) : zero);
         D4 g;
 #pragma unroll
         for (int c = 0; c < 4; ++c) g.v[c] = 2.0 * (cr.v[c] - yt * r.v[c]);
         CV gs;
         narrow(g, gs);
-        *reinterpret_cast<CV *>(a.G + off) = gs;
+        if (active) *reinterpret_cast<CV *>(a.G + off) = gs;
         s[0] += vdot(gs, gs);
+        if (a.pc.rho) {
+            // row-block H0: R_i . G_i for G slot 0 and kap_i at the current R
+            const double rho = group_sum<GS>(vdot(rs, gs));
+            if (lane == 0) {
+                const double h = a.pc.hrow[row];
+                a.pc.rho[row] = rho;
+                a.pc.kap[row] = 4.0 * sigma / (h + 4.0 * sigma * a.rn[row]);
+            }
+        }
     }
     block_sums_store<1>(s, a.partials + (size_t)blockIdx.x * kMaxSums);
 }
@@ -658,10 +887,20 @@ int launch_cubic(hipStream_t s, const double *a, double *tau) {
     return LRSDP_OK;
 }
 
+template <typename S>
+static int update_pc(hipStream_t s, const UpdateArgs<S> &a, const PcBufs &pc, int64_t ld, int cpr, int *nb) {
+    const int gs = cpr <= 4 ? 4 : (cpr <= 8 ? 8 : 16);
+    *nb = grid_for(pc.n, kBlock / gs);
+    if (gs == 4) hipLaunchKernelGGL((k_update_maxcut_pc<S, 4>), dim3(*nb), dim3(kBlock), 0, s, a, pc, (int)ld);
+    else if (gs == 8) hipLaunchKernelGGL((k_update_maxcut_pc<S, 8>), dim3(*nb), dim3(kBlock), 0, s, a, pc, (int)ld);
+    else hipLaunchKernelGGL((k_update_maxcut_pc<S, 16>), dim3(*nb), dim3(kBlock), 0, s, a, pc, (int)ld);
+    return LRSDP_OK;
+}
+
 int launch_update_maxcut(hipStream_t s, int prec, SolverState *st, void *R, const void *CD, const double *y,
                          const double *rn, const double *q1, const double *q2, const double *ytil_in,
                          double *ytil_out, void *const *gring, void *const *dring, int T, int64_t n, int64_t ld,
-                         double *partials, int *nb) {
+                         double *partials, int *nb, const PcBufs *pc) {
     const int cpr = chunks_per_row(prec, ld);
     const int64_t nch = n * cpr;
     *nb = grid_for(nch, kBlock);
@@ -670,13 +909,15 @@ int launch_update_maxcut(hipStream_t s, int prec, SolverState *st, void *R, cons
                              partials};
         for (int g = 0; g <= T; ++g) a.rings.g[g] = (double *)gring[g];
         for (int d = 0; d < T; ++d) a.rings.d[d] = (double *)dring[d];
-        hipLaunchKernelGGL(k_update_maxcut<double>, dim3(*nb), dim3(kBlock), 0, s, a);
+        if (pc) update_pc<double>(s, a, *pc, ld, cpr, nb);
+        else hipLaunchKernelGGL(k_update_maxcut<double>, dim3(*nb), dim3(kBlock), 0, s, a);
     } else {
         UpdateArgs<float> a{st, (float *)R, (const float *)CD, y, rn, q1, q2, ytil_in, ytil_out, {}, nch, cpr,
                             partials};
         for (int g = 0; g <= T; ++g) a.rings.g[g] = (float *)gring[g];
         for (int d = 0; d < T; ++d) a.rings.d[d] = (float *)dring[d];
-        hipLaunchKernelGGL(k_update_maxcut<float>, dim3(*nb), dim3(kBlock), 0, s, a);
+        if (pc) update_pc<float>(s, a, *pc, ld, cpr, nb);
+        else hipLaunchKernelGGL(k_update_maxcut<float>, dim3(*nb), dim3(kBlock), 0, s, a);
     }
     LRSDP_CHECK_LAUNCH();
     return LRSDP_OK;
@@ -684,15 +925,18 @@ int launch_update_maxcut(hipStream_t s, int prec, SolverState *st, void *R, cons
 
 // basis: nb device arrays of n*ld elements; out = sum coef_j basis_j.
 int launch_combine(hipStream_t s, int prec, SolverState *st, const double *coef, const void *const *basis, int nb,
-                   void *out, int64_t n, int64_t ld, double *partials, int *nblk, uint16_t *shadow) {
+                   void *out, int64_t n, int64_t ld, double *partials, int *nblk, uint16_t *shadow, const void *R,
+                   const PcBufs *pc) {
     const int64_t nch = n * ld * (prec == LRSDP_F64 ? 8 : 4) / 16;
     *nblk = grid_for(nch, kBlock);
+    const PcBufs p = pc ? *pc : PcBufs{nullptr, nullptr, nullptr, n};
     if (prec == LRSDP_F64) {
-        CombineArgs<double> a{st, coef, {}, nb, (double *)out, nch, partials, nullptr, ld, ld};
+        CombineArgs<double> a{st, coef, {}, nb, (double *)out, nch, partials, nullptr, ld, ld, (const double *)R, p};
         for (int j = 0; j < nb; ++j) a.basis[j] = (const double *)basis[j];
         hipLaunchKernelGGL(k_combine<double>, dim3(*nblk), dim3(kBlock), 0, s, a);
     } else {
-        CombineArgs<float> a{st, coef, {}, nb, (float *)out, nch, partials, shadow, ld, bf16_ld(ld)};
+        CombineArgs<float> a{st, coef, {}, nb, (float *)out, nch, partials, shadow, ld, bf16_ld(ld), (const float *)R,
+                             p};
         for (int j = 0; j < nb; ++j) a.basis[j] = (const float *)basis[j];
         hipLaunchKernelGGL(k_combine<float>, dim3(*nblk), dim3(kBlock), 0, s, a);
     }
@@ -702,17 +946,19 @@ int launch_combine(hipStream_t s, int prec, SolverState *st, const double *coef,
 
 int launch_grad_init_maxcut(hipStream_t s, int prec, SolverState *st, const void *R, const void *CR,
                             const double *y, const double *rn, double *ytil, void *G, int64_t n, int64_t ld,
-                            double *partials, int *nblk) {
+                            double *partials, int *nblk, const PcBufs *pc) {
     const int cpr = chunks_per_row(prec, ld);
     const int gs = cpr <= 4 ? 4 : (cpr <= 8 ? 8 : 16);
     *nblk = grid_for(n, kBlock / gs);
+    const PcBufs p = pc ? *pc : PcBufs{nullptr, nullptr, nullptr, n};
     if (prec == LRSDP_F64) {
-        GradInitArgs<double> a{st, (const double *)R, (const double *)CR, y, rn, ytil, (double *)G, n, ld, partials};
+        GradInitArgs<double> a{st, (const double *)R, (const double *)CR, y, rn, ytil, (double *)G, n, ld, partials,
+                               p};
         if (gs == 4) hipLaunchKernelGGL((k_grad_init_maxcut<double, 4>), dim3(*nblk), dim3(kBlock), 0, s, a);
         else if (gs == 8) hipLaunchKernelGGL((k_grad_init_maxcut<double, 8>), dim3(*nblk), dim3(kBlock), 0, s, a);
         else hipLaunchKernelGGL((k_grad_init_maxcut<double, 16>), dim3(*nblk), dim3(kBlock), 0, s, a);
     } else {
-        GradInitArgs<float> a{st, (const float *)R, (const float *)CR, y, rn, ytil, (float *)G, n, ld, partials};
+        GradInitArgs<float> a{st, (const float *)R, (const float *)CR, y, rn, ytil, (float *)G, n, ld, partials, p};
         if (gs == 4) hipLaunchKernelGGL((k_grad_init_maxcut<float, 4>), dim3(*nblk), dim3(kBlock), 0, s, a);
         else if (gs == 8) hipLaunchKernelGGL((k_grad_init_maxcut<float, 8>), dim3(*nblk), dim3(kBlock), 0, s, a);
         else hipLaunchKernelGGL((k_grad_init_maxcut<float, 16>), dim3(*nblk), dim3(kBlock), 0, s, a);

@@ -43,7 +43,7 @@ class Options(C.Structure):
         ("feas_decrease", C.c_double), ("eta0", C.c_double), ("eta_factor", C.c_double),
         ("eta_min", C.c_double), ("check_every", C.c_int), ("refresh_every", C.c_int),
         ("profile", C.c_int), ("verbose", C.c_int), ("phase2", C.c_int), ("switch_err1", C.c_double),
-        ("admm_check", C.c_int), ("max_admm", C.c_int),
+        ("admm_check", C.c_int), ("max_admm", C.c_int), ("precond", C.c_int),
     ]
 
 

@@ -127,3 +127,20 @@ def test_workspace_validation():
 
 def test_padded_ld():
     assert L.padded_ld(20, L.F64) == 20 and L.padded_ld(26, L.F32) == 28 and L.padded_ld(10, L.F32) == 12
+
+
+def test_precond_option_validation():
+    u, v = erdos_renyi_edges(50, 120, 1)
+    p = L.Problem.maxcut(50, u, v)
+    o = L.default_options(prec=L.F64, rank=4, ld=4, precond=1, lbfgs_mem=3)
+    with pytest.raises(L.LrsdpError) as e:
+        L.workspace_bytes(p, o)
+    assert e.value.code == L.EINVAL and "lbfgs_mem" in str(e.value)
+    o.lbfgs_mem = 2
+    base = L.workspace_bytes(p, L.default_options(prec=L.F64, rank=4, ld=4))
+    assert L.workspace_bytes(p, o) >= base + 4 * 50 * 8      # (T + 1) rho rows and kap
+    i, j, M, _, _ = completion_instance(10, 8, 2, 3, seed=1)
+    c = L.Problem.completion(10, 8, i, j, M)
+    with pytest.raises(L.LrsdpError) as e:
+        L.workspace_bytes(c, L.default_options(prec=L.F64, rank=4, ld=4, precond=1))
+    assert e.value.code == L.EUNSUPPORTED

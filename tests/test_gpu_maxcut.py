@@ -458,3 +458,51 @@ def test_phase2_hub_graph_never_fails(ctx):
     if res.admm_fallbacks:
         rc0, res0, _, _ = gpu_solve(ctx, n, u, v, w, R0, L.F64)
         assert res.obj == res0.obj
+
+
+@pytest.mark.parametrize("case", ["er_1k", "cl_heavy", "isolated", "general"])
+def test_precond_iterates_match_oracle(ctx, case):
+    # row-block H0: after a few L-BFGS iterations of the first subproblem the
+    # GPU iterate equals the oracle's (same directions, steps and pairs)
+    import torch
+    n, u, v, w, r = graph(case)
+    r = min(r, 16)
+    print_case(test="precond_iterates", case=case)
+    R0 = init_factor(n, r, 23)
+    op = maxcut_problem(n, u, v, w)
+    kw = dict(precond=1, max_outer=1, max_inner=6, eta0=1e-14)
+    rc, res, R, y = gpu_solve(ctx, n, u, v, w, R0, L.F64, **kw)
+    ores = alm_solve(op, R0, opts=OOptions(precond=True, max_outer=1, max_inner=6, eta0=1e-14))
+    print(res.as_dict(), ores.inner)
+    assert res.inner == ores.inner == 6
+    scale = 1.0 + np.abs(ores.R).max()
+    assert np.max(np.abs(R - ores.R)) <= 1e-9 * scale
+    assert np.max(np.abs(y - ores.y)) <= 1e-9 * (1.0 + np.abs(ores.y).max())
+
+
+def test_precond_solve_matches_oracle(ctx):
+    n, u, v, w, _ = graph("er_1k")
+    R0 = init_factor(n, 16, 15051)
+    print_case(test="precond_solve", case="er_1k")
+    rc, res, R, y = gpu_solve(ctx, n, u, v, w, R0, L.F64, precond=1)
+    ores = alm_solve(maxcut_problem(n, u, v, w), R0, opts=OOptions(precond=True))
+    rc0, res0, _, _ = gpu_solve(ctx, n, u, v, w, R0, L.F64)
+    print("precond", res.as_dict(), "oracle", ores.obj, ores.inner, "plain", res0.as_dict())
+    assert rc == L.OK and ores.converged
+    assert abs(res.obj - ores.obj) <= 1e-5 * abs(ores.obj)
+    assert abs(res.obj - res0.obj) <= 2e-5 * abs(res0.obj)       # same certified optimum
+    assert res.inner < res0.inner
+
+
+@pytest.mark.parametrize("prec", [L.F64, L.F32])
+def test_precond_hub_graph_converges_faster(ctx, prec):
+    n, u, v, w, _ = graph("cl_heavy")
+    R0 = init_factor(n, 16, 29)
+    print_case(test="precond_hub", prec=prec)
+    rc, res, R, y = gpu_solve(ctx, n, u, v, w, R0, prec, precond=1)
+    rc0, res0, _, _ = gpu_solve(ctx, n, u, v, w, R0, prec)
+    print("precond", res.as_dict(), "plain", res0.as_dict())
+    assert rc == L.OK and rc0 == L.OK
+    m = K.alm_measures(maxcut_problem(n, u, v, w), R, y)
+    assert m["err1"] <= 1e-5 and abs(m["err3"]) <= 1e-5
+    assert res.inner < res0.inner
