@@ -45,6 +45,7 @@ def parse():
     ap.add_argument("--no-f32", action="store_true", help="skip the float32 / warm-start / bf16 paths")
     ap.add_argument("--no-warm", action="store_true", help="skip the learned warm start")
     ap.add_argument("--no-bf16", action="store_true", help="skip the bfloat16-input path")
+    ap.add_argument("--no-precond", action="store_true", help="skip the row-block H0 paths")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample")
     ap.add_argument("--instances", default=",".join(INSTANCES))
@@ -204,10 +205,34 @@ def main():
         log(f"{path} {run['name']} {dt:.3f}s outer {res.outer} inner {res.inner} obj {res.obj:.8e}"
             + (f" cert gap {rec['cert_gap']:.2e}" if "cert_gap" in rec else ""))
 
+    def solve_with(run, prec, **kw):
+        """One untimed-by-the-step solve of `run` in `prec` with extra options."""
+        p = run["per"][prec]
+        o = L.default_options(prec=prec, rank=run["r"], ld=p["opts"].ld, profile=1, **kw)
+        ws = torch.empty(L.workspace_bytes(run["prob"], o), dtype=torch.uint8, device=dev)
+        p["R"].copy_(p["R0"])
+        p["y"].zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, res = L.solve(ctx, run["prob"], p["R"], p["y"], o, workspace=ws)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        del ws
+        return dt, rc, res
+
+    if not args.no_precond:
+        # row-block H0 for Algorithm 1 (an extension; the timed step keeps H0 = I)
+        for run in runs:
+            dt, rc, res = solve_with(run, L.F64, precond=1)
+            record("f64_precond", run, dt, res, dict(converged=rc == L.OK), y=run["per"][L.F64]["y"])
     if not args.no_f32:
         for run in runs:
             dt, res = solve(run, L.F32)
             record("f32", run, dt, res, y=run["per"][L.F32]["y"])
+        if not args.no_precond:
+            for run in runs:
+                dt, rc, res = solve_with(run, L.F32, precond=1)
+                record("f32_precond", run, dt, res, dict(converged=rc == L.OK), y=run["per"][L.F32]["y"])
         # bfloat16 gathered operand (float32 iterate, exact gradient every 25 iterations)
         for run in ([] if args.no_bf16 else runs):
             p = run["per"][L.F32]

@@ -171,7 +171,9 @@ typedef struct {
                                  P^{-1}, P_i = h_i I + 4 sigma R_i R_i^T and
                                  h_i = 2 max(sum_j |C_ij|, 1e-3 ||vec(C)||_1 / n),
                                  in place of Algorithm 1's H0 = I (an extension;
-                                 lbfgs_mem <= 4; EUNSUPPORTED for completion)  */
+                                 lbfgs_mem <= 2; EUNSUPPORTED for completion);
+                                 2: the same with h_i = 2 max(C_ii - ytil_i,
+                                 0.005 h_i of mode 1) at the current iterate    */
 } lrsdp_options;
 
 void lrsdp_options_default(lrsdp_options *opts);

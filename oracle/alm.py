@@ -49,7 +49,8 @@ class Options:
     eta_min: float = 1e-9
     time_limit: float = 1e30
     phase2: bool = False           # switch to the splitting phase (Section 2.2)
-    precond: bool = False          # MaxCut: row-block H0 for the L-BFGS direction (not in the paper)
+    precond: int = 0               # MaxCut: row-block H0 for the L-BFGS direction (not in the paper):
+                                   # 1 static h, 2 h from the diagonal of C - Diag(ytil)
     switch_err1: float = 1e-3      # ... once err1 <= switch_err1 after an ALM step
     admm_check: int = 10
     max_admm: int = 5000
@@ -78,9 +79,11 @@ def default_sigma0(prob: SDPProblem) -> float:
     return max(4.0 * prob.c_l1 / prob.m, 1e-8)
 
 
-def row_block_h0(prob: SDPProblem, R: np.ndarray, sigma: float):
+def row_block_h0(prob: SDPProblem, R: np.ndarray, sigma: float, y=None, mode: int = 1):
     """H0 = P^{-1} with P block diagonal over rows, P_i = h_i I + 4 sigma R_i R_i^T,
-    h_i = 2 max(sum_j |C_ij|, 1e-3 ||vec(C)||_1 / n).
+    h_i = 2 max(sum_j |C_ij|, 1e-3 ||vec(C)||_1 / n) (mode 1), or (mode 2, with
+    the multipliers y) h_i = 2 max(C_ii - ytil_i, 0.005 h_i of mode 1) where
+    ytil = y + sigma (1 - ||R_i||^2) is the multiplier estimate at R.
 
     An extension, not in the paper (Algorithm 1 uses H0 = I).  For MaxCut the
     Hessian of the Lagrangian in row i has the penalty block 4 sigma R_i R_i^T
@@ -90,7 +93,11 @@ def row_block_h0(prob: SDPProblem, R: np.ndarray, sigma: float):
     """
     rowabs = np.asarray(abs(prob.C).sum(axis=1)).ravel()
     h = 2.0 * np.maximum(rowabs, 1e-3 * prob.c_l1 / prob.n)
-    kappa = 4.0 * sigma / (h + 4.0 * sigma * np.sum(R * R, axis=1))
+    rr = np.sum(R * R, axis=1)
+    if mode == 2:
+        ytil = y + sigma * (1.0 - rr)
+        h = 2.0 * np.maximum(np.asarray(prob.C.diagonal()).ravel() - ytil, 0.005 * h)
+    kappa = 4.0 * sigma / (h + 4.0 * sigma * rr)
 
     def apply(Q):
         return (Q - (kappa * np.sum(R * Q, axis=1))[:, None] * R) / h[:, None]
@@ -107,7 +114,7 @@ def lbfgs_minimize(prob: SDPProblem, R, y, sigma, eta, opts: Options, budget: in
     while it < min(opts.max_inner, budget):
         if gnorm <= target:
             break
-        h0 = row_block_h0(prob, R, sigma) if opts.precond else None
+        h0 = row_block_h0(prob, R, sigma, y, int(opts.precond)) if opts.precond else None
         D = two_loop(G, pairs, h0)
         c = K.linesearch_coeffs(prob, R, D, y, sigma)
         if not c["a4"] < 0.0:

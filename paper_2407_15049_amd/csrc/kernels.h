@@ -40,7 +40,8 @@ struct SolverState {
 };
 
 // Row-block H0 of the L-BFGS direction (solve option precond, MaxCut):
-// P_i = h_i I + 4 sigma R_i R_i^T, applied as
+// P_i = h_i I + 4 sigma R_i R_i^T (h_i static, or from the diagonal of
+// C - Diag(ytil) at the current iterate), applied as
 // P_i^{-1} q = (q - kap_i (R_i . q) R_i) / h_i with kap_i = 4 sigma / (h_i + 4 sigma ||R_i||^2).
 // rho[g * n + i] = R_i . G_{g,i} (row dots of the current R with G ring slot g).
 constexpr int kPcMem = 2;              // largest L-BFGS memory with precond
@@ -49,8 +50,11 @@ constexpr int kPcOff = 17;             // partial-sum index of the first weighte
 struct PcBufs {
     double *rho;         // (T + 1) x n
     double *kap;         // n
-    const double *hrow;  // n
+    const double *hrow;  // n: static h_i = 2 max(sum_j |C_ij|, 1e-3 ||vec(C)||_1 / n)
     int64_t n;
+    int mode;            // 1: h = hrow; 2: h_i = 2 max(C_ii - ytil_i, 0.01 hrow_i), moves with ytil
+    const double *diag;  // mode 2: C_ii
+    double *hdyn;        // mode 2: h of the current iterate (n)
 };
 
 // index of the unordered G-slot pair (j, l), j <= l <= kPcMem

@@ -190,7 +190,7 @@ extern "C" void lrsdp_options_default(lrsdp_options *o) {
 namespace {
 
 struct WsPlan {
-    size_t cd, gring[kMaxMem + 1], dring[kMaxMem], ytil[2], rn, q1, q2, acon, shadow, rho, kap, total;
+    size_t cd, gring[kMaxMem + 1], dring[kMaxMem], ytil[2], rn, q1, q2, acon, shadow, rho, kap, hdyn, total;
 };
 
 int plan_workspace(const lrsdp_problem *p, const lrsdp_options *o, WsPlan *w) {
@@ -202,6 +202,7 @@ int plan_workspace(const lrsdp_problem *p, const lrsdp_options *o, WsPlan *w) {
     if (o->rank < 1 || o->ld < o->rank) return set_error(LRSDP_EINVAL, "need 1 <= rank <= ld");
     rc = check_ld(o->prec, o->ld);
     if (rc) return rc;
+    if (o->precond < 0 || o->precond > 2) return set_error(LRSDP_EINVAL, "precond = %d not in {0, 1, 2}", o->precond);
     if (o->precond) {
         if (p->info.kind != LRSDP_MAXCUT)
             return set_error(LRSDP_EUNSUPPORTED, "precond (row-block H0) is for MaxCut problems");
@@ -227,6 +228,7 @@ int plan_workspace(const lrsdp_problem *p, const lrsdp_options *o, WsPlan *w) {
     w->shadow = take(o->prec == LRSDP_F32_BF16IN ? (size_t)p->info.n * bf16_ld(o->ld) * 2 : 0);
     w->rho = take(o->precond ? (size_t)(o->lbfgs_mem + 1) * p->info.n * 8 : 0);
     w->kap = take(o->precond ? (size_t)p->info.n * 8 : 0);
+    w->hdyn = take(o->precond == 2 ? (size_t)p->info.n * 8 : 0);
     w->total = off + 256;
     return LRSDP_OK;
 }
@@ -306,7 +308,8 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
     double *acon = reinterpret_cast<double *>(ws + w.acon);
     const bool bf = o->prec == LRSDP_F32_BF16IN && mc;
     uint16_t *shadow = bf ? reinterpret_cast<uint16_t *>(ws + w.shadow) : nullptr;
-    PcBufs pcb{reinterpret_cast<double *>(ws + w.rho), reinterpret_cast<double *>(ws + w.kap), p->csr.hrow, n};
+    PcBufs pcb{reinterpret_cast<double *>(ws + w.rho), reinterpret_cast<double *>(ws + w.kap), p->csr.hrow, n,
+               o->precond, p->csr.diag, reinterpret_cast<double *>(ws + w.hdyn)};
     const PcBufs *pc = (mc && o->precond) ? &pcb : nullptr;
     SolverState *st = at<SolverState>(c->scratch, kStateOff);
     double *part_ls = at<double>(c->scratch, kPartLsOff);

@@ -599,7 +599,7 @@ __global__ __launch_bounds__(kBlock) void k_update_maxcut_pc(UpdateArgs<S> a, Pc
         const double rho0 = group_sum<GS>(vdot(rn_s, b0));
         const double rho1 = group_sum<GS>(vdot(rn_s, b1));
         const double rho2 = T >= 2 ? group_sum<GS>(vdot(rn_s, b2)) : 0.0;
-        const double h = pc.hrow[row];
+        const double h = pc.mode == 2 ? 2.0 * fmax(pc.diag[row] - ynew, 0.005 * pc.hrow[row]) : pc.hrow[row];
         const double w = 1.0 / h;
         const double kap = 4.0 * sigma / (h + 4.0 * sigma * rnn);
         const double wk = lane == 0 ? w * kap : 0.0;
@@ -615,6 +615,7 @@ __global__ __launch_bounds__(kBlock) void k_update_maxcut_pc(UpdateArgs<S> a, Pc
         if (lane == 0) {
             a.ytil_out[row] = ynew;
             pc.kap[row] = kap;
+            if (pc.mode == 2) pc.hdyn[row] = h;
             pc.rho[row] = rho0;
             pc.rho[pc.n + row] = rho1;
             if (T >= 2) pc.rho[2 * pc.n + row] = rho2;
@@ -707,7 +708,7 @@ __global__ __launch_bounds__(kBlock) void k_combine(CombineArgs<S> a) {
                 }
             }
             const D4 r = widen(reinterpret_cast<const CV *>(a.R)[c]);
-            const double hi = 1.0 / a.pc.hrow[row], kr = a.pc.kap[row] * ra;
+            const double hi = 1.0 / (a.pc.mode == 2 ? a.pc.hdyn[row] : a.pc.hrow[row]), kr = a.pc.kap[row] * ra;
 #pragma unroll
             for (int e = 0; e < 4; ++e) acc.v[e] = fma(hi, accg.v[e] - kr * r.v[e], acc.v[e]);
         } else {
@@ -786,7 +787,9 @@ __global__ __launch_bounds__(kBlock) void k_grad_init_maxcut(GradInitArgs<S> a) 
             // row-block H0: R_i . G_i for G slot 0 and kap_i at the current R
             const double rho = group_sum<GS>(vdot(rs, gs));
             if (lane == 0) {
-                const double h = a.pc.hrow[row];
+                const double h = a.pc.mode == 2 ? 2.0 * fmax(a.pc.diag[row] - yt, 0.005 * a.pc.hrow[row])
+                                                 : a.pc.hrow[row];
+                if (a.pc.mode == 2) a.pc.hdyn[row] = h;
                 a.pc.rho[row] = rho;
                 a.pc.kap[row] = 4.0 * sigma / (h + 4.0 * sigma * a.rn[row]);
             }
@@ -929,7 +932,7 @@ int launch_combine(hipStream_t s, int prec, SolverState *st, const double *coef,
                    const PcBufs *pc) {
     const int64_t nch = n * ld * (prec == LRSDP_F64 ? 8 : 4) / 16;
     *nblk = grid_for(nch, kBlock);
-    const PcBufs p = pc ? *pc : PcBufs{nullptr, nullptr, nullptr, n};
+    const PcBufs p = pc ? *pc : PcBufs{nullptr, nullptr, nullptr, n, 0, nullptr, nullptr};
     if (prec == LRSDP_F64) {
         CombineArgs<double> a{st, coef, {}, nb, (double *)out, nch, partials, nullptr, ld, ld, (const double *)R, p};
         for (int j = 0; j < nb; ++j) a.basis[j] = (const double *)basis[j];
@@ -950,7 +953,7 @@ int launch_grad_init_maxcut(hipStream_t s, int prec, SolverState *st, const void
     const int cpr = chunks_per_row(prec, ld);
     const int gs = cpr <= 4 ? 4 : (cpr <= 8 ? 8 : 16);
     *nblk = grid_for(n, kBlock / gs);
-    const PcBufs p = pc ? *pc : PcBufs{nullptr, nullptr, nullptr, n};
+    const PcBufs p = pc ? *pc : PcBufs{nullptr, nullptr, nullptr, n, 0, nullptr, nullptr};
     if (prec == LRSDP_F64) {
         GradInitArgs<double> a{st, (const double *)R, (const double *)CR, y, rn, ytil, (double *)G, n, ld, partials,
                                p};

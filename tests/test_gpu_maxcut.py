@@ -460,8 +460,9 @@ def test_phase2_hub_graph_never_fails(ctx):
         assert res.obj == res0.obj
 
 
+@pytest.mark.parametrize("mode", [1, 2])
 @pytest.mark.parametrize("case", ["er_1k", "cl_heavy", "isolated", "general"])
-def test_precond_iterates_match_oracle(ctx, case):
+def test_precond_iterates_match_oracle(ctx, case, mode):
     # row-block H0: after a few L-BFGS iterations of the first subproblem the
     # GPU iterate equals the oracle's (same directions, steps and pairs)
     import torch
@@ -470,9 +471,9 @@ def test_precond_iterates_match_oracle(ctx, case):
     print_case(test="precond_iterates", case=case)
     R0 = init_factor(n, r, 23)
     op = maxcut_problem(n, u, v, w)
-    kw = dict(precond=1, max_outer=1, max_inner=6, eta0=1e-14)
+    kw = dict(precond=mode, max_outer=1, max_inner=6, eta0=1e-14)
     rc, res, R, y = gpu_solve(ctx, n, u, v, w, R0, L.F64, **kw)
-    ores = alm_solve(op, R0, opts=OOptions(precond=True, max_outer=1, max_inner=6, eta0=1e-14))
+    ores = alm_solve(op, R0, opts=OOptions(precond=mode, max_outer=1, max_inner=6, eta0=1e-14))
     print(res.as_dict(), ores.inner)
     assert res.inner == ores.inner == 6
     scale = 1.0 + np.abs(ores.R).max()
