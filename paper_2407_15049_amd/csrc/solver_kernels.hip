@@ -661,7 +661,7 @@ __device__ __forceinline__ uint16_t bf16_rne(float f) {
 // out = sum_j coef_j basis_j, and <out, basis_j> (pre-update values) for all j
 // plus <out, out>.  In the solver the output is D slot dk, itself basis entry
 // T+1+dk (read before written by the same thread).
-template <typename S>
+template <typename S, bool PC>
 __global__ __launch_bounds__(kBlock) void k_combine(CombineArgs<S> a) {
     using CV = typename Chunk<S>::V;
     const SolverState *st = a.st;
@@ -681,13 +681,13 @@ __global__ __launch_bounds__(kBlock) void k_combine(CombineArgs<S> a) {
     double s[kMaxBasis + 1];
 #pragma unroll
     for (int j = 0; j <= kMaxBasis; ++j) s[j] = 0.0;
-    const bool pcon = st && st->precond;
-    const int TG = st ? st->T : -1;               // G slots 0..TG (precond only)
-    const int64_t cpr = a.nchunks / (a.pc.n > 0 ? a.pc.n : 1);
+    constexpr bool pcon = PC;   // row-block H0: the solver's state has precond set
+    const int TG = PC ? st->T : -1;                              // G slots 0..TG
+    const int64_t cpr = PC ? a.nchunks / (a.pc.n > 0 ? a.pc.n : 1) : 1;  // chunks per row
     for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < a.nchunks; c += (int64_t)gridDim.x * kBlock) {
         CV b[kMaxBasis];
         D4 acc{{0.0, 0.0, 0.0, 0.0}};
-        if (pcon) {
+        if constexpr (pcon) {
             // D = P^{-1} (sum over G slots) + sum over D slots, row by row
             D4 accg{{0.0, 0.0, 0.0, 0.0}};
             const int64_t row = c / cpr;
@@ -936,12 +936,14 @@ int launch_combine(hipStream_t s, int prec, SolverState *st, const double *coef,
     if (prec == LRSDP_F64) {
         CombineArgs<double> a{st, coef, {}, nb, (double *)out, nch, partials, nullptr, ld, ld, (const double *)R, p};
         for (int j = 0; j < nb; ++j) a.basis[j] = (const double *)basis[j];
-        hipLaunchKernelGGL(k_combine<double>, dim3(*nblk), dim3(kBlock), 0, s, a);
+        if (pc) hipLaunchKernelGGL((k_combine<double, true>), dim3(*nblk), dim3(kBlock), 0, s, a);
+        else hipLaunchKernelGGL((k_combine<double, false>), dim3(*nblk), dim3(kBlock), 0, s, a);
     } else {
         CombineArgs<float> a{st, coef, {}, nb, (float *)out, nch, partials, shadow, ld, bf16_ld(ld), (const float *)R,
                              p};
         for (int j = 0; j < nb; ++j) a.basis[j] = (const float *)basis[j];
-        hipLaunchKernelGGL(k_combine<float>, dim3(*nblk), dim3(kBlock), 0, s, a);
+        if (pc) hipLaunchKernelGGL((k_combine<float, true>), dim3(*nblk), dim3(kBlock), 0, s, a);
+        else hipLaunchKernelGGL((k_combine<float, false>), dim3(*nblk), dim3(kBlock), 0, s, a);
     }
     LRSDP_CHECK_LAUNCH();
     return LRSDP_OK;
