@@ -30,6 +30,7 @@ HBM_PEAK_GBS = 8000.0
 WORKLOAD = ("maxcut n=1e6 pair: Erdos-Renyi 5e6 edges + Chung-Lu beta=2.5 mean degree 10 (5e6 edges), "
             "weights uniform in {-1,+1}, C=-L/4, diag(X)=1, rank 20")
 INSTANCES = ["er_1m_pm1", "cl_1m_pm1"]
+ALL_PATHS = ["f64_precond", "f32", "f32_precond", "f32_bf16in", "f32_warm", "f32_precond_warm"]
 OTHER_WORKLOADS = {
     "cl_10m": "maxcut n=1e7 Chung-Lu beta=2.5 mean degree 8 (4e7 edges), unit weights, C=-L/4, diag(X)=1, rank 24",
     "er_1k": "maxcut n=1e3 Erdos-Renyi 5e3 edges, unit weights, C=-L/4, diag(X)=1, rank 10",
@@ -46,6 +47,8 @@ def parse():
     ap.add_argument("--no-warm", action="store_true", help="skip the learned warm start")
     ap.add_argument("--no-bf16", action="store_true", help="skip the bfloat16-input path")
     ap.add_argument("--no-precond", action="store_true", help="skip the row-block H0 paths")
+    ap.add_argument("--paths", default=",".join(ALL_PATHS),
+                    help="untimed comparison paths to run after the timed step (comma list)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample")
     ap.add_argument("--instances", default=",".join(INSTANCES))
@@ -173,7 +176,7 @@ def main():
         torch.cuda.synchronize()
         step_times.append(time.perf_counter() - t0)
         log(f"step {s}: {step_times[-1]:.3f}s")
-    ms_per_step = 1000.0 * sum(step_times) / len(step_times)
+    ms_per_step = 1000.0 * sum(step_times) / len(step_times) if step_times else None
 
     # SpMM roofline from the HIP events of the timed solves
     spmm_ms = sum(res.spmm_ms for v in recs.values() for _, res in v)
@@ -182,8 +185,19 @@ def main():
     achieved = (spmm_bytes / 1e9) / (spmm_ms / 1e3) if spmm_ms > 0 else None
     traffic = measured_traffic()
 
+    enabled = [p for p in args.paths.split(",") if p] if args.paths else []
+    drop = set()
+    if args.no_precond:
+        drop |= {"f64_precond", "f32_precond", "f32_precond_warm"}
+    if args.no_f32:
+        drop |= {p for p in ALL_PATHS if p.startswith("f32")}
+    if args.no_bf16:
+        drop.add("f32_bf16in")
+    if args.no_warm:
+        drop |= {"f32_warm", "f32_precond_warm"}
+    enabled = [p for p in enabled if p not in drop]
     paths = {"f64": {}}
-    for run in runs:
+    for run in ([] if not step_times else runs):
         dt, res = recs[run["name"]][-1]
         rec = dict(seconds=round(dt, 4), outer=res.outer, inner=res.inner, obj=res.obj, err1=res.err1,
                    err3=res.err3, spmm_us=round(1e3 * res.spmm_ms / max(res.spmm_launches, 1), 2))
@@ -194,9 +208,9 @@ def main():
         paths["f64"][run["name"]] = rec
 
     def record(path, run, dt, res, extra=None, y=None):
-        o64 = paths["f64"][run["name"]]["obj"]
+        o64 = paths["f64"].get(run["name"], {}).get("obj")
         rec = dict(seconds=round(dt, 4), outer=res.outer, inner=res.inner, obj=res.obj, err1=res.err1,
-                   err3=res.err3, obj_rel_vs_f64=abs(res.obj - o64) / abs(o64),
+                   err3=res.err3, obj_rel_vs_f64=abs(res.obj - o64) / abs(o64) if o64 else None,
                    spmm_us=round(1e3 * res.spmm_ms / max(res.spmm_launches, 1), 2))
         rec.update(extra or {})
         if y is not None and not args.short:
@@ -208,7 +222,7 @@ def main():
     def solve_with(run, prec, **kw):
         """One untimed-by-the-step solve of `run` in `prec` with extra options."""
         p = run["per"][prec]
-        o = L.default_options(prec=prec, rank=run["r"], ld=p["opts"].ld, profile=1, **kw)
+        o = L.default_options(prec=prec, rank=run["r"], ld=p["opts"].ld, profile=1, verbose=int(args.verbose), **kw)
         ws = torch.empty(L.workspace_bytes(run["prob"], o), dtype=torch.uint8, device=dev)
         p["R"].copy_(p["R0"])
         p["y"].zero_()
@@ -220,21 +234,22 @@ def main():
         del ws
         return dt, rc, res
 
-    if not args.no_precond:
+    if "f64_precond" in enabled:
         # row-block H0 for Algorithm 1 (an extension; the timed step keeps H0 = I)
         for run in runs:
             dt, rc, res = solve_with(run, L.F64, precond=1)
             record("f64_precond", run, dt, res, dict(converged=rc == L.OK), y=run["per"][L.F64]["y"])
-    if not args.no_f32:
+    if "f32" in enabled:
         for run in runs:
             dt, res = solve(run, L.F32)
             record("f32", run, dt, res, y=run["per"][L.F32]["y"])
-        if not args.no_precond:
-            for run in runs:
-                dt, rc, res = solve_with(run, L.F32, precond=1)
-                record("f32_precond", run, dt, res, dict(converged=rc == L.OK), y=run["per"][L.F32]["y"])
+    if "f32_precond" in enabled:
+        for run in runs:
+            dt, rc, res = solve_with(run, L.F32, precond=1)
+            record("f32_precond", run, dt, res, dict(converged=rc == L.OK), y=run["per"][L.F32]["y"])
+    if "f32_bf16in" in enabled:
         # bfloat16 gathered operand (float32 iterate, exact gradient every 25 iterations)
-        for run in ([] if args.no_bf16 else runs):
+        for run in runs:
             p = run["per"][L.F32]
             o = L.default_options(prec=L.F32_BF16IN, rank=run["r"], ld=p["opts"].ld, profile=1, refresh_every=25)
             ws = torch.empty(L.workspace_bytes(run["prob"], o), dtype=torch.uint8, device=dev)
@@ -246,30 +261,36 @@ def main():
             torch.cuda.synchronize()
             record("f32_bf16in", run, time.perf_counter() - t0, res, dict(converged=rc == L.OK), y=p["y"])
             del ws
-        if not args.no_warm:
-            from paper_2407_15049_amd import warmstart as W
-            t0 = time.perf_counter()
-            data = W.make_training_set(ctx, log=log)
-            t1 = time.perf_counter()
-            params, hist = W.train(ctx, data, steps=400, lr=3e-3, log=log)
-            torch.cuda.synchronize()
-            t2 = time.perf_counter()
-            del data
-            warm_info = dict(train_graphs=len(W.TRAIN_SPECS), label_solves_s=round(t1 - t0, 2),
-                             train_s=round(t2 - t1, 2), loss_first=hist[0][1], loss_last=hist[-1][1])
+    warm_paths = [w for w in ("f32_warm", "f32_precond_warm") if w in enabled]
+    if warm_paths:
+        from paper_2407_15049_amd import warmstart as W
+        t0 = time.perf_counter()
+        data = W.make_training_set(ctx, log=log)
+        t1 = time.perf_counter()
+        params, hist = W.train(ctx, data, steps=400, lr=3e-3, log=log)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        del data
+        warm_info = dict(train_graphs=len(W.TRAIN_SPECS), label_solves_s=round(t1 - t0, 2),
+                         train_s=round(t2 - t1, 2), loss_first=hist[0][1], loss_last=hist[-1][1])
+        for wp in warm_paths:
             for run in runs:
                 p = run["per"][L.F32]
+                o = L.default_options(prec=L.F32, rank=run["r"], ld=p["opts"].ld, profile=1,
+                                      precond=1 if wp == "f32_precond_warm" else 0,
+                                      verbose=int(args.verbose))
+                ws = torch.empty(L.workspace_bytes(run["prob"], o), dtype=torch.uint8, device=dev)
                 p["R"].copy_(p["R0"])
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()           # features + inference count toward the solve
                 y0, sigma0 = W.warm_start(ctx, run["prob"], params)
                 p["y"].copy_(y0)
-                o = L.default_options(prec=L.F32, rank=run["r"], ld=p["opts"].ld, profile=1, sigma0=sigma0)
-                rc, res = L.solve(ctx, run["prob"], p["R"], p["y"], o, workspace=p["ws"])
+                o.sigma0 = sigma0
+                rc, res = L.solve(ctx, run["prob"], p["R"], p["y"], o, workspace=ws)
                 torch.cuda.synchronize()
-                record("f32_warm", run, time.perf_counter() - t0, res, dict(sigma0=sigma0, converged=rc == L.OK),
-                       y=p["y"])
-            paths["f32_warm"]["model"] = warm_info
+                record(wp, run, time.perf_counter() - t0, res, dict(sigma0=sigma0, converged=rc == L.OK), y=p["y"])
+                del ws
+            paths[wp]["model"] = warm_info
 
     if args.copy_calibration:
         a = torch.ones(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
@@ -280,17 +301,17 @@ def main():
         log("copy calibration: 3 x 1 GiB device-to-device copies")
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and step_times:
         cpu = cpu_baseline(runs, recs, args.cpu_seconds)
 
     out = {
         "metric": METRIC,
-        "value": round(ms_per_step / 1000.0, 4),
+        "value": round(ms_per_step / 1000.0, 4) if ms_per_step else None,
         "unit": "s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 2),
+        "ms_per_step": round(ms_per_step, 2) if ms_per_step else None,
         "higher_is_better": False,
         "scaling": "strong",
         "vs_baseline": None,
@@ -310,7 +331,8 @@ def main():
             "traffic_gbs": round(traffic / 1e9 / (spmm_ms / 1e3 / spmm_n), 1) if traffic and spmm_n else None,
             "launches": spmm_n,
             "avg_us": round(1e3 * spmm_ms / max(spmm_n, 1), 2),
-            "alg_bytes_per_launch": {run["name"]: recs[run["name"]][-1][1].spmm_bytes for run in runs},
+            "alg_bytes_per_launch": {run["name"]: recs[run["name"]][-1][1].spmm_bytes for run in runs
+                                     if recs[run["name"]]},
         },
         "cpu_baseline": cpu,
         "paths": paths,
