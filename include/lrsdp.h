@@ -138,7 +138,8 @@ int lrsdp_problem_upload(lrsdp_ctx *ctx, lrsdp_problem *prob, void *dev,
  * 1e8, feas_decrease = 0.25, eta0 = 0.1, eta_factor = 0.25, eta_min = 1e-9,
  * max_outer = 300, max_inner = 2000, max_iter_total = 200000,
  * check_every = 8, time_limit_s = 1e30, refresh_every = 0 (off), phase2 = 0,
- * switch_err1 = 1e-3, admm_check = 10, max_admm = 5000, precond = 0.
+ * switch_err1 = 1e-3, admm_check = 10, max_admm = 5000, precond = 0,
+ * rank_max = 0 (off), rank_trigger = 2000, rank_scale = 1e-2, rank_seed = 15049.
  */
 typedef struct {
     int     prec;             /* LRSDP_F64 / LRSDP_F32 / LRSDP_F32_BF16IN      */
@@ -174,6 +175,20 @@ typedef struct {
                                  lbfgs_mem <= 2; EUNSUPPORTED for completion);
                                  2: the same with h_i = 2 max(C_ii - ytil_i,
                                  0.005 h_i of mode 1) at the current iterate    */
+    int     rank_max;         /* dynamic rank (appendix A.1): after an ALM step
+                                 whose L-BFGS run took >= rank_trigger
+                                 iterations, rank <- min(ceil(1.5 rank),
+                                 rank_max, ld, floor(sqrt(2m))); the new columns
+                                 of R get rank_scale * N(0, 1) values; 0 or
+                                 <= rank: off                                  */
+    int     rank_trigger;     /* L-BFGS iterations of one subproblem that
+                                 trigger a rank increase                       */
+    double  rank_scale;       /* standard deviation of the new entries         */
+    int64_t rank_seed;        /* seed of the new entries: entry (i, c) takes
+                                 outputs 2k and 2k+1 (k = 65536 i + c) of the
+                                 SplitMix64 sequence seeded with rank_seed, as
+                                 uniforms u = ((x >> 11) + 0.5) 2^-53, through
+                                 Box-Muller: sqrt(-2 ln u0) cos(2 pi u1)        */
 } lrsdp_options;
 
 void lrsdp_options_default(lrsdp_options *opts);
@@ -197,6 +212,8 @@ typedef struct {
                                or err1 above 10x its value at the switch; or
                                max_admm reached): R, y and the ALM state of the
                                switch were restored and the ALM went on alone */
+    int64_t rank_final;   /* rank at the end (differs from opts->rank when the
+                             dynamic rank grew it)                             */
 } lrsdp_result;
 
 /* Device workspace the solve needs for this problem and these options. */

@@ -49,6 +49,10 @@ class Options:
     eta_min: float = 1e-9
     time_limit: float = 1e30
     phase2: bool = False           # switch to the splitting phase (Section 2.2)
+    rank_max: int = 0              # dynamic rank (appendix A.1); 0 or <= rank: off
+    rank_trigger: int = 2000       # L-BFGS iterations of a subproblem that trigger growth
+    rank_scale: float = 1e-2       # standard deviation of the new entries
+    rank_seed: int = 15049
     precond: int = 0               # MaxCut: row-block H0 for the L-BFGS direction (not in the paper):
                                    # 1 static h, 2 h from the diagonal of C - Diag(ytil)
     switch_err1: float = 1e-3      # ... once err1 <= switch_err1 after an ALM step
@@ -73,10 +77,36 @@ class SolveResult:
     history: list = field(default_factory=list)
     admm_iters: int = 0
     admm_fallbacks: int = 0
+    rank_final: int = 0
 
 
 def default_sigma0(prob: SDPProblem) -> float:
     return max(4.0 * prob.c_l1 / prob.m, 1e-8)
+
+
+_GAMMA = np.uint64(0x9E3779B97F4A7C15)
+
+
+def splitmix64_at(seed: int, j: np.ndarray) -> np.ndarray:
+    """Output j (from 0) of the SplitMix64 sequence seeded with `seed` (Steele,
+    Lea and Flood, 2014): mix(seed + (j+1) gamma), arithmetic modulo 2^64."""
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed) + (np.asarray(j, dtype=np.uint64) + np.uint64(1)) * _GAMMA
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        return z ^ (z >> np.uint64(31))
+
+
+def new_columns(n: int, c0: int, c1: int, seed: int) -> np.ndarray:
+    """N(0, 1) entries for columns c0..c1-1 of an n-row factor: entry (i, c) takes
+    outputs 2k and 2k+1, k = 65536 i + c, as uniforms ((x >> 11) + 0.5) 2^-53,
+    then Box-Muller sqrt(-2 ln u0) cos(2 pi u1)."""
+    i = np.arange(n, dtype=np.uint64)[:, None]
+    c = np.arange(c0, c1, dtype=np.uint64)[None, :]
+    k = i * np.uint64(65536) + c
+    u0 = ((splitmix64_at(seed, np.uint64(2) * k) >> np.uint64(11)).astype(np.float64) + 0.5) * 2.0 ** -53
+    u1 = ((splitmix64_at(seed, np.uint64(2) * k + np.uint64(1)) >> np.uint64(11)).astype(np.float64) + 0.5) * 2.0 ** -53
+    return np.sqrt(-2.0 * np.log(u0)) * np.cos(2.0 * np.pi * u1)
 
 
 def row_block_h0(prob: SDPProblem, R: np.ndarray, sigma: float, y=None, mode: int = 1):
@@ -157,6 +187,8 @@ def alm_solve(prob: SDPProblem, R0: np.ndarray, y0=None, opts: Options | None = 
     outer = 0
     phase2_on = opts.phase2
     admm_total = fallbacks = 0
+    rank_cur = R.shape[1]
+    rank_cap = min(max(opts.rank_max, rank_cur), int(np.floor(np.sqrt(2.0 * prob.m))))
     for outer in range(1, opts.max_outer + 1):
         R, it, gnorm = lbfgs_minimize(prob, R, y, sigma, eta, opts, opts.max_iter_total - total)
         total += it
@@ -169,6 +201,14 @@ def alm_solve(prob: SDPProblem, R0: np.ndarray, y0=None, opts: Options | None = 
         if meas["err1"] <= opts.tol and abs(meas["err3"]) <= opts.tol:
             converged = True
             break
+        if rank_cur < rank_cap and it >= opts.rank_trigger:
+            # dynamic rank (appendix A.1): rank <- min(ceil(1.5 rank), cap), new
+            # columns rank_scale * N(0, 1) from the seeded generator
+            r_new = min(rank_cap, (3 * rank_cur + 1) // 2)
+            R = np.hstack([R, opts.rank_scale * new_columns(prob.n, rank_cur, r_new, opts.rank_seed)])
+            rank_cur = r_new
+            meas = K.alm_measures(prob, R, y)
+            hist.append(dict(outer=outer, rank=rank_cur, **meas))
         if phase2_on and meas["err1"] <= opts.switch_err1:
             # Splitting phase with the penalty of the subproblem just solved.  If it
             # diverges or stops at max_admm unconverged, the ALM goes on from the
@@ -195,7 +235,7 @@ def alm_solve(prob: SDPProblem, R0: np.ndarray, y0=None, opts: Options | None = 
                        err1=meas["err1"], err1_inf=meas["err1_inf"], err3=meas["err3"],
                        outer=outer, inner=total, converged=converged,
                        seconds=time.perf_counter() - t0, history=hist,
-                       admm_iters=admm_total, admm_fallbacks=fallbacks)
+                       admm_iters=admm_total, admm_fallbacks=fallbacks, rank_final=R.shape[1])
 
 
 # ---------------------------------------------------------------------------

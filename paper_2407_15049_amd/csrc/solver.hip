@@ -30,6 +30,7 @@ int launch_grad_init_maxcut(hipStream_t, int, SolverState *, const void *, const
                             const double *, double *, void *, int64_t, int64_t, double *, int *,
                             const PcBufs * = nullptr);
 int launch_fill(hipStream_t, int, void *, int64_t);
+int launch_rank_grow(hipStream_t, int, void *, int64_t, int64_t, int, int, uint64_t, double);
 int launch_avg(hipStream_t, int, const void *, const void *, void *, int64_t);
 int launch_dots(hipStream_t, int, const void *, const void *const *, int, int64_t, int64_t, double *, int *);
 int launch_rowdot(hipStream_t, int, const void *, const void *, int64_t, int64_t, double *);
@@ -185,6 +186,10 @@ extern "C" void lrsdp_options_default(lrsdp_options *o) {
     o->admm_check = 10;
     o->max_admm = 5000;
     o->precond = 0;
+    o->rank_max = 0;
+    o->rank_trigger = 2000;
+    o->rank_scale = 1e-2;
+    o->rank_seed = 15049;
 }
 
 namespace {
@@ -391,6 +396,9 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
     int status = LRSDP_NOT_CONVERGED;
     int64_t admm_iters = 0, admm_fallbacks = 0;
     bool phase2_on = o->phase2 != 0;
+    int rank_cur = o->rank;
+    const int rank_cap = (int)std::min<int64_t>(
+        {(int64_t)std::max(o->rank_max, o->rank), ld, (int64_t)std::floor(std::sqrt(2.0 * (double)p->info.m))});
     int64_t outer = 0;
     int64_t total_inner = 0;
     double sigma_host = sigma0;
@@ -534,6 +542,18 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
             status = LRSDP_OK;
             break;
         }
+        if (rank_cur < rank_cap && hs.k >= o->rank_trigger) {
+            // dynamic rank: the subproblem just solved took rank_trigger L-BFGS
+            // iterations or more; grow R in place (new columns from the seeded
+            // generator), then exact C R and measures for the new R
+            const int r_new = std::min<int64_t>(rank_cap, (3 * (int64_t)rank_cur + 1) / 2);
+            if ((rc = launch_rank_grow(s, prec, R, n, ld, rank_cur, r_new, (uint64_t)o->rank_seed, o->rank_scale)))
+                break;
+            if (o->verbose) fprintf(stderr, "[lrsdp] rank %d -> %d\n", rank_cur, r_new);
+            rank_cur = r_new;
+            if ((rc = alm_refresh(0.0, 0))) break;
+            if ((rc = read_state(c, &hs))) break;
+        }
         if (mc && phase2_on && hs.err1 <= o->switch_err1) {
             // splitting phase from U = V = R with the current y and the penalty of the
             // subproblem just solved; measures
@@ -626,6 +646,7 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
     res->spmm_bytes = mc ? maxcut_spmm_bytes(p, prec, o->rank) : completion_grad_bytes(p, prec, o->rank, T);
     res->admm_iters = admm_iters;
     res->admm_fallbacks = admm_fallbacks;
+    res->rank_final = rank_cur;
     return status;
 }
 

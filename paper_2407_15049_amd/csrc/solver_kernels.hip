@@ -798,6 +798,35 @@ __global__ __launch_bounds__(kBlock) void k_grad_init_maxcut(GradInitArgs<S> a) 
     block_sums_store<1>(s, a.partials + (size_t)blockIdx.x * kMaxSums);
 }
 
+// Dynamic rank (appendix A.1): new columns [c0, c1) of R get scale * N(0, 1)
+// values from a counter-based generator.  Entry (i, c) takes outputs 2k and
+// 2k+1, k = 65536 i + c, of the SplitMix64 sequence seeded with `seed` (output
+// j is mix(seed + (j+1) gamma), Steele, Lea and Flood 2014) as uniforms
+// u = ((x >> 11) + 0.5) 2^-53 in (0, 1), then Box-Muller:
+// z = sqrt(-2 ln u0) cos(2 pi u1).
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t j) {
+    uint64_t z = seed + (j + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+template <typename S>
+__global__ __launch_bounds__(kBlock) void k_rank_grow(S *R, int64_t n, int64_t ld, int c0, int c1, uint64_t seed,
+                                                      double scale) {
+    const int w = c1 - c0;
+    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < n * w; e += (int64_t)gridDim.x * kBlock) {
+        const int64_t i = e / w;
+        const int c = c0 + (int)(e - i * w);
+        const uint64_t k = (uint64_t)i * 65536ull + (uint64_t)c;
+        const uint64_t x0 = splitmix64_at(seed, 2 * k), x1 = splitmix64_at(seed, 2 * k + 1);
+        const double u0 = ((double)(x0 >> 11) + 0.5) * 0x1.0p-53;
+        const double u1 = ((double)(x1 >> 11) + 0.5) * 0x1.0p-53;
+        const double z = sqrt(-2.0 * log(u0)) * cos(6.283185307179586 * u1);
+        R[i * ld + c] = (S)(scale * z);
+    }
+}
+
 // out = (a + b) / 2 elementwise
 template <typename S>
 __global__ __launch_bounds__(kBlock) void k_avg(const S *a, const S *b, S *out, int64_t count) {
@@ -968,6 +997,18 @@ int launch_grad_init_maxcut(hipStream_t s, int prec, SolverState *st, const void
         else if (gs == 8) hipLaunchKernelGGL((k_grad_init_maxcut<float, 8>), dim3(*nblk), dim3(kBlock), 0, s, a);
         else hipLaunchKernelGGL((k_grad_init_maxcut<float, 16>), dim3(*nblk), dim3(kBlock), 0, s, a);
     }
+    LRSDP_CHECK_LAUNCH();
+    return LRSDP_OK;
+}
+
+int launch_rank_grow(hipStream_t s, int prec, void *R, int64_t n, int64_t ld, int c0, int c1, uint64_t seed,
+                     double scale) {
+    if (c1 <= c0) return LRSDP_OK;
+    const int nb = grid_for(n * (c1 - c0), kBlock);
+    if (prec == LRSDP_F64)
+        hipLaunchKernelGGL(k_rank_grow<double>, dim3(nb), dim3(kBlock), 0, s, (double *)R, n, ld, c0, c1, seed, scale);
+    else
+        hipLaunchKernelGGL(k_rank_grow<float>, dim3(nb), dim3(kBlock), 0, s, (float *)R, n, ld, c0, c1, seed, scale);
     LRSDP_CHECK_LAUNCH();
     return LRSDP_OK;
 }

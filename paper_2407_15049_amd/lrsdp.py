@@ -44,6 +44,7 @@ class Options(C.Structure):
         ("eta_min", C.c_double), ("check_every", C.c_int), ("refresh_every", C.c_int),
         ("profile", C.c_int), ("verbose", C.c_int), ("phase2", C.c_int), ("switch_err1", C.c_double),
         ("admm_check", C.c_int), ("max_admm", C.c_int), ("precond", C.c_int),
+        ("rank_max", C.c_int), ("rank_trigger", C.c_int), ("rank_scale", C.c_double), ("rank_seed", C.c_int64),
     ]
 
 
@@ -53,7 +54,7 @@ class Result(C.Structure):
         ("err3", C.c_double), ("sigma", C.c_double), ("seconds", C.c_double),
         ("outer", C.c_int64), ("inner", C.c_int64), ("status", C.c_int),
         ("spmm_launches", C.c_int), ("spmm_ms", C.c_double), ("spmm_bytes", C.c_double),
-        ("admm_iters", C.c_int64), ("admm_fallbacks", C.c_int64),
+        ("admm_iters", C.c_int64), ("admm_fallbacks", C.c_int64), ("rank_final", C.c_int64),
     ]
 
     def as_dict(self):

@@ -255,7 +255,8 @@ def gpu_solve(ctx, n, u, v, w, R0, prec, **kw):
     import torch
     r = R0.shape[1]
     prob = L.Problem.maxcut(n, u, v, w).upload(ctx)
-    opts = L.default_options(prec=prec, rank=r, ld=L.padded_ld(r, L.F64 if prec == L.F64 else L.F32), **kw)
+    rank = kw.pop("rank", r)          # R0 may carry zero columns beyond the rank (dynamic rank)
+    opts = L.default_options(prec=prec, rank=rank, ld=L.padded_ld(r, L.F64 if prec == L.F64 else L.F32), **kw)
     Rd = dev_factor(R0, prec)
     yd = torch.zeros(n, dtype=torch.float64, device="cuda")
     rc, res = L.solve(ctx, prob, Rd, yd, opts)
@@ -507,3 +508,33 @@ def test_precond_hub_graph_converges_faster(ctx, prec):
     m = K.alm_measures(maxcut_problem(n, u, v, w), R, y)
     assert m["err1"] <= 1e-5 and abs(m["err3"]) <= 1e-5
     assert res.inner < res0.inner
+
+
+def test_rank_growth_columns_match_the_oracle_generator(ctx):
+    # growth after the first ALM step: the new columns are the generator's values
+    n, u, v, w, _ = graph("pm1_ragged")
+    R0 = init_factor(n, 10, 31)
+    print_case(test="rank_growth_columns", case="pm1_ragged")
+    kw = dict(max_outer=1, max_inner=50, rank_max=16, rank_trigger=5, rank_scale=0.03, rank_seed=777)
+    rc, res, R, y = gpu_solve(ctx, n, u, v, w, np.hstack([R0, np.zeros((n, 6))]), L.F64, rank=10, **kw)
+    ores = alm_solve(maxcut_problem(n, u, v, w), R0, opts=OOptions(**kw))
+    print(res.as_dict(), ores.rank_final)
+    assert res.rank_final == ores.rank_final == 15
+    assert np.max(np.abs(R[:, 10:15] - ores.R[:, 10:15])) <= 1e-14
+    assert np.all(R[:, 15:] == 0.0)
+    assert np.max(np.abs(R[:, :10] - ores.R[:, :10])) <= 1e-9 * (1 + np.abs(ores.R).max())
+
+
+def test_rank_growth_solve_matches_oracle(ctx):
+    # rank 10 start on the 1k-node graph (non-global stationary point at rank 10)
+    n, u, v, w, _ = graph("er_1k")
+    R0 = init_factor(n, 10, 15050)
+    print_case(test="rank_growth_solve", case="er_1k")
+    kw = dict(rank_max=16, rank_trigger=100)
+    rc, res, R, y = gpu_solve(ctx, n, u, v, w, np.hstack([R0, np.zeros((n, 6))]), L.F64, rank=10, **kw)
+    ores = alm_solve(maxcut_problem(n, u, v, w), R0, opts=OOptions(**kw))
+    print(res.as_dict(), "oracle", ores.obj, ores.rank_final)
+    assert rc == L.OK and ores.converged
+    assert res.rank_final == ores.rank_final
+    assert abs(res.obj - ores.obj) <= 1e-5 * abs(ores.obj)
+    assert res.obj < -3906.0                    # below the rank-10 stationary value -3905.98
