@@ -30,7 +30,9 @@ HBM_PEAK_GBS = 8000.0
 WORKLOAD = ("maxcut n=1e6 pair: Erdos-Renyi 5e6 edges + Chung-Lu beta=2.5 mean degree 10 (5e6 edges), "
             "weights uniform in {-1,+1}, C=-L/4, diag(X)=1, rank 20")
 INSTANCES = ["er_1m_pm1", "cl_1m_pm1"]
-ALL_PATHS = ["f64_precond", "f32", "f32_precond", "f32_bf16in", "f32_warm", "f32_precond_warm"]
+ALL_PATHS = ["f64_precond", "f64_dynrank", "f32", "f32_precond", "f32_bf16in", "f32_warm", "f32_precond_warm",
+             "f32_dynrank_precond"]
+DYNRANK_LD = {0: 30, 1: 32}       # row stride with room for the grown rank (FP64, FP32)
 OTHER_WORKLOADS = {
     "cl_10m": "maxcut n=1e7 Chung-Lu beta=2.5 mean degree 8 (4e7 edges), unit weights, C=-L/4, diag(X)=1, rank 24",
     "er_1k": "maxcut n=1e3 Erdos-Renyi 5e3 edges, unit weights, C=-L/4, diag(X)=1, rank 10",
@@ -239,6 +241,29 @@ def main():
         for run in runs:
             dt, rc, res = solve_with(run, L.F64, precond=1)
             record("f64_precond", run, dt, res, dict(converged=rc == L.OK), y=run["per"][L.F64]["y"])
+    def solve_dynrank(run, prec, **kw):
+        """Dynamic rank (appendix A.1): start at the workload's rank, grow in place
+        up to the stride DYNRANK_LD."""
+        ld = DYNRANK_LD[0 if prec == L.F64 else 1]
+        o = L.default_options(prec=prec, rank=run["r"], ld=ld, profile=1, rank_max=ld,
+                              verbose=int(args.verbose), **kw)
+        ws = torch.empty(L.workspace_bytes(run["prob"], o), dtype=torch.uint8, device=dev)
+        R = torch.zeros((run["n"], ld), dtype=L.elem_dtype(prec), device=dev)
+        R[:, :run["r"]] = run["per"][prec]["R0"][:, :run["r"]]
+        y = run["per"][prec]["y"]
+        y.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, res = L.solve(ctx, run["prob"], R, y, o, workspace=ws)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        del ws, R
+        return dt, rc, res, y
+
+    if "f64_dynrank" in enabled:
+        for run in runs:
+            dt, rc, res, y = solve_dynrank(run, L.F64)
+            record("f64_dynrank", run, dt, res, dict(converged=rc == L.OK, rank_final=res.rank_final), y=y)
     if "f32" in enabled:
         for run in runs:
             dt, res = solve(run, L.F32)
@@ -261,6 +286,10 @@ def main():
             torch.cuda.synchronize()
             record("f32_bf16in", run, time.perf_counter() - t0, res, dict(converged=rc == L.OK), y=p["y"])
             del ws
+    if "f32_dynrank_precond" in enabled:
+        for run in runs:
+            dt, rc, res, y = solve_dynrank(run, L.F32, precond=1)
+            record("f32_dynrank_precond", run, dt, res, dict(converged=rc == L.OK, rank_final=res.rank_final), y=y)
     warm_paths = [w for w in ("f32_warm", "f32_precond_warm") if w in enabled]
     if warm_paths:
         from paper_2407_15049_amd import warmstart as W

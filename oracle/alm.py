@@ -201,24 +201,33 @@ def alm_solve(prob: SDPProblem, R0: np.ndarray, y0=None, opts: Options | None = 
         if meas["err1"] <= opts.tol and abs(meas["err3"]) <= opts.tol:
             converged = True
             break
+        # penalty and inner-tolerance schedule, from the measures after the
+        # multiplier step
+        sigma_sub = sigma
+        if meas["err1"] > opts.feas_decrease * err1_prev:
+            sigma = min(sigma * opts.sigma_factor, sigma_cap)
+        err1_prev = meas["err1"]
+        eta = max(eta * opts.eta_factor, opts.eta_min)
         if rank_cur < rank_cap and it >= opts.rank_trigger:
             # dynamic rank (appendix A.1): rank <- min(ceil(1.5 rank), cap), new
-            # columns rank_scale * N(0, 1) from the seeded generator
+            # columns rank_scale * N(0, 1) from the seeded generator; the new
+            # columns move err1, so the penalty rule restarts its reference
             r_new = min(rank_cap, (3 * rank_cur + 1) // 2)
             R = np.hstack([R, opts.rank_scale * new_columns(prob.n, rank_cur, r_new, opts.rank_seed)])
             rank_cur = r_new
             meas = K.alm_measures(prob, R, y)
             hist.append(dict(outer=outer, rank=rank_cur, **meas))
+            err1_prev = np.inf
         if phase2_on and meas["err1"] <= opts.switch_err1:
             # Splitting phase with the penalty of the subproblem just solved.  If it
             # diverges or stops at max_admm unconverged, the ALM goes on from the
             # point of the switch with the splitting phase off (the paper leaves
             # this case open).
             Rm, _, _, y2, meas2, it2, diverged = admm_phase(
-                prob, R, y, sigma, tol=opts.tol, max_iter=opts.max_admm, check_every=opts.admm_check,
+                prob, R, y, sigma_sub, tol=opts.tol, max_iter=opts.max_admm, check_every=opts.admm_check,
                 diverge_factor=10.0)
             admm_total += it2
-            hist.append(dict(outer=outer, admm=it2, sigma=sigma, diverged=diverged, **meas2))
+            hist.append(dict(outer=outer, admm=it2, sigma=sigma_sub, diverged=diverged, **meas2))
             if not diverged and meas2["err1"] <= opts.tol and abs(meas2["err3"]) <= opts.tol:
                 R, y, meas = Rm, y2, meas2
                 converged = True
@@ -227,10 +236,6 @@ def alm_solve(prob: SDPProblem, R0: np.ndarray, y0=None, opts: Options | None = 
             fallbacks += 1
         if total >= opts.max_iter_total or time.perf_counter() - t0 > opts.time_limit:
             break
-        if meas["err1"] > opts.feas_decrease * err1_prev:
-            sigma = min(sigma * opts.sigma_factor, sigma_cap)
-        err1_prev = meas["err1"]
-        eta = max(eta * opts.eta_factor, opts.eta_min)
     return SolveResult(R=R, y=y, sigma=sigma, obj=meas["obj"], dual=meas["dual"],
                        err1=meas["err1"], err1_inf=meas["err1_inf"], err3=meas["err3"],
                        outer=outer, inner=total, converged=converged,

@@ -553,6 +553,10 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
             rank_cur = r_new;
             if ((rc = alm_refresh(0.0, 0))) break;
             if ((rc = read_state(c, &hs))) break;
+            // the new columns move err1; the penalty rule restarts its reference
+            // so that the jump is not read as a stall
+            hs.err1_prev = INFINITY;
+            if ((rc = write_state(c, hs))) break;
         }
         if (mc && phase2_on && hs.err1 <= o->switch_err1) {
             // splitting phase from U = V = R with the current y and the penalty of the
