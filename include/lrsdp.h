@@ -276,12 +276,23 @@ int lrsdp_k_alm(lrsdp_ctx *ctx, const lrsdp_problem *prob, int prec,
                 const void *R, int64_t ld, double *y, double sigma, void *work,
                 double *out);
 
-/* `iters` splitting iterations (Section 2.2, eqs. 2.2-2.3; MaxCut only) in
- * place: U <- argmin_U L(U, V, y), V <- argmin_V L(U, V, y), each solved
- * exactly per row, then y <- y + sigma (b - A(U V^T)).  U, V device n x ld,
- * y device m float64. */
+/* `iters` splitting iterations (Section 2.2, eqs. 2.2-2.3) in place:
+ * U <- argmin_U L(U, V, y), V <- argmin_V L(U, V, y), then
+ * y <- y + sigma (b - A(U V^T)).  U, V device n x ld, y device m float64.
+ * MaxCut: each half-step solved exactly per row (work unused, may be NULL).
+ * Completion: each half-step solved by conjugate gradients (Algorithm 2)
+ * from the current iterate until ||r||_F <= cg_tol max(1, ||rhs||_F) or cg_max
+ * steps; work: caller device memory, 256-byte aligned, of
+ * lrsdp_admm_workspace_bytes; synchronises the stream (the CG scalars are
+ * formed on the host).  ENUMERIC if CG meets non-positive curvature. */
 int lrsdp_k_admm(lrsdp_ctx *ctx, const lrsdp_problem *prob, int prec, void *U, void *V, int64_t ld,
-                 double *y, double sigma, int iters);
+                 double *y, double sigma, int iters, double cg_tol, int cg_max,
+                 void *work, size_t work_bytes);
+
+/* Device workspace of lrsdp_k_admm: 0 for MaxCut; five n x ld arrays and
+ * three m float64 vectors for completion. */
+int lrsdp_admm_workspace_bytes(const lrsdp_problem *prob, int prec, int64_t ld,
+                               size_t *bytes);
 
 /* Compact-form L-BFGS direction (Algorithm 1, H0 = I) for gradient G and k
  * pairs s_t = S[t], y_t = Y[t] (oldest first; S, Y: host arrays of k device

@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <initializer_list>
 
 #include "kernels.h"
 
@@ -195,7 +196,8 @@ extern "C" void lrsdp_options_default(lrsdp_options *o) {
 namespace {
 
 struct WsPlan {
-    size_t cd, gring[kMaxMem + 1], dring[kMaxMem], ytil[2], rn, q1, q2, acon, shadow, rho, kap, hdyn, total;
+    size_t cd, gring[kMaxMem + 1], dring[kMaxMem], ytil[2], rn, q1, q2, acon, shadow, rho, kap, hdyn, cadmm, csnap,
+        total;
 };
 
 int plan_workspace(const lrsdp_problem *p, const lrsdp_options *o, WsPlan *w) {
@@ -234,6 +236,12 @@ int plan_workspace(const lrsdp_problem *p, const lrsdp_options *o, WsPlan *w) {
     w->rho = take(o->precond ? (size_t)(o->lbfgs_mem + 1) * p->info.n * 8 : 0);
     w->kap = take(o->precond ? (size_t)p->info.n * 8 : 0);
     w->hdyn = take(o->precond == 2 ? (size_t)p->info.n * 8 : 0);
+    // completion splitting phase: CG scratch (five n x ld arrays, three m-vectors)
+    // and the copy of R kept for the fallback
+    const bool cph2 = o->phase2 && p->info.kind == LRSDP_COMPLETION;
+    const size_t arr256 = (arr + 255) / 256 * 256, vec256 = ((size_t)p->info.m * 8 + 255) / 256 * 256;
+    w->cadmm = take(cph2 ? 5 * arr256 + 3 * vec256 : 0);
+    w->csnap = take(cph2 ? arr : 0);
     w->total = off + 256;
     return LRSDP_OK;
 }
@@ -287,6 +295,121 @@ int admm_iter(hipStream_t s, const DevCsr &P, int prec, void *U, void *V, int64_
     a.Y = V;
     a.R = U;
     return spmm_maxcut(s, P, prec, a, &np);
+}
+
+// ---------------------------------------------------------------------------
+// Splitting iteration for matrix completion (Section 2.2, eqs. 2.2-2.3): each
+// half-step solves the positive definite system of eq. 2.2,
+//   A_V(U) = sigma A*(A(U V^T)) V + sigma U = B_V = -C V + A*(y) V + sigma A*(b) V + sigma V,
+// by conjugate gradients (Algorithm 2) warm-started at the current U, until
+// ||r||_F <= cg_tol max(1, ||B_V||_F).  With C = I and S(V, z) = (I - A*(z)) V
+// (the completion SpMM): B_V = sigma V - S(V, y + sigma b) and
+// A_V(X) = sigma (V - S(V, A(X V^T))) + sigma X.  The vector updates are combine
+// passes (coefficients from the host, dots back to the host).
+// ---------------------------------------------------------------------------
+struct CmpAdmmBufs {
+    void *B, *r, *p, *q, *S;   // n x ld
+    double *z, *w, *zero;       // m
+};
+
+size_t cmp_admm_bytes(const lrsdp_problem *p, int prec, int64_t ld) {
+    const size_t arr = ((size_t)p->info.n * ld * elem_size(prec) + 255) / 256 * 256;
+    const size_t vec = ((size_t)p->info.m * 8 + 255) / 256 * 256;
+    return 5 * arr + 3 * vec;
+}
+
+CmpAdmmBufs cmp_admm_layout(const lrsdp_problem *p, int prec, int64_t ld, char *work) {
+    const size_t arr = ((size_t)p->info.n * ld * elem_size(prec) + 255) / 256 * 256;
+    const size_t vec = ((size_t)p->info.m * 8 + 255) / 256 * 256;
+    CmpAdmmBufs b;
+    b.B = work;
+    b.r = work + arr;
+    b.p = work + 2 * arr;
+    b.q = work + 3 * arr;
+    b.S = work + 4 * arr;
+    b.z = reinterpret_cast<double *>(work + 5 * arr);
+    b.w = reinterpret_cast<double *>(work + 5 * arr + vec);
+    b.zero = reinterpret_cast<double *>(work + 5 * arr + 2 * vec);
+    return b;
+}
+
+// out = sum_j coef_j basis_j; sums[j] = <out, basis_j>, sums[kMaxBasis] = ||out||^2 (host).
+// Synchronises the stream.
+int cmp_lincomb(lrsdp_ctx *c, int prec, std::initializer_list<const void *> basis, std::initializer_list<double> coef,
+                void *out, int64_t n, int64_t ld, double *sums) {
+    const void *bs[kMaxBasis];
+    double *dcoef = at<double>(c->scratch, kSmallOff);
+    double *dred = at<double>(c->scratch, kSmallOff) + 64;
+    double *part = at<double>(c->scratch, kPartMiscOff);
+    double *hc = reinterpret_cast<double *>(static_cast<char *>(c->pinned) + 6144);
+    int nb = 0;
+    for (const void *b : basis) bs[nb++] = b;
+    int k = 0;
+    for (double v : coef) hc[k++] = v;
+    LRSDP_HIP_TRY(hipMemcpyAsync(dcoef, hc, nb * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    int nblk = 0, rc;
+    if ((rc = launch_combine(c->stream, prec, nullptr, dcoef, bs, nb, out, n, ld, part, &nblk, nullptr))) return rc;
+    if ((rc = launch_reduce(c->stream, part, nblk, kMaxBasis + 1, dred))) return rc;
+    double *hr = reinterpret_cast<double *>(static_cast<char *>(c->pinned) + 6656);
+    LRSDP_HIP_TRY(hipMemcpyAsync(hr, dred, (kMaxBasis + 1) * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    LRSDP_HIP_TRY(hipStreamSynchronize(c->stream));
+    std::memcpy(sums, hr, (kMaxBasis + 1) * sizeof(double));
+    return LRSDP_OK;
+}
+
+// out = A_V(X) (sums as cmp_lincomb; sums[2] = <out, X>)
+int cmp_split_apply(lrsdp_ctx *c, const lrsdp_problem *p, int prec, const void *X, const void *V, int64_t ld,
+                    double sigma, const CmpAdmmBufs &b, void *out, double *sums) {
+    int nb = 0, rc;
+    if ((rc = cmp_sddmm(c->stream, p->cmp, prec, 0, X, V, ld, b.z, nullptr, nullptr, nullptr, nullptr, 0.0, nullptr,
+                        nullptr, &nb)))
+        return rc;
+    if ((rc = spmm_completion(c->stream, p->cmp, prec, V, ld, b.z, b.S))) return rc;
+    return cmp_lincomb(c, prec, {V, b.S, X}, {sigma, -sigma, sigma}, out, p->info.n, ld, sums);
+}
+
+// U <- argmin of the half-step (CG from the current U); returns CG iterations in *its
+int cmp_split_half(lrsdp_ctx *c, const lrsdp_problem *p, int prec, void *U, const void *V, int64_t ld,
+                   const double *y, double sigma, double cg_tol, int cg_max, const CmpAdmmBufs &b, int *its) {
+    const int64_t n = p->info.n;
+    double sums[kMaxBasis + 1];
+    int rc;
+    if ((rc = cmp_ytil(c->stream, p->cmp, nullptr, sigma, b.zero, y, b.w))) return rc;     // w = y + sigma b
+    if ((rc = spmm_completion(c->stream, p->cmp, prec, V, ld, b.w, b.S))) return rc;
+    if ((rc = cmp_lincomb(c, prec, {V, b.S}, {sigma, -1.0}, b.B, n, ld, sums))) return rc;
+    const double eps = cg_tol * std::max(1.0, std::sqrt(std::max(sums[kMaxBasis], 0.0)));
+    if ((rc = cmp_split_apply(c, p, prec, U, V, ld, sigma, b, b.q, sums))) return rc;
+    if ((rc = cmp_lincomb(c, prec, {b.B, b.q}, {1.0, -1.0}, b.r, n, ld, sums))) return rc;
+    double rr = sums[kMaxBasis];
+    if ((rc = cmp_lincomb(c, prec, {b.r}, {1.0}, b.p, n, ld, sums))) return rc;
+    int k = 0;
+    for (; k < cg_max; ++k) {
+        if (!(std::sqrt(std::max(rr, 0.0)) > eps)) break;
+        if ((rc = cmp_split_apply(c, p, prec, b.p, V, ld, sigma, b, b.q, sums))) return rc;
+        const double pq = sums[2];
+        if (!(pq > 0.0) || !std::isfinite(pq)) return set_error(LRSDP_ENUMERIC, "splitting CG lost positive curvature");
+        const double alpha = rr / pq;
+        if ((rc = cmp_lincomb(c, prec, {U, b.p}, {1.0, alpha}, U, n, ld, sums))) return rc;
+        if ((rc = cmp_lincomb(c, prec, {b.r, b.q}, {1.0, -alpha}, b.r, n, ld, sums))) return rc;
+        const double rr_new = sums[kMaxBasis];
+        const double beta = rr_new / rr;
+        rr = rr_new;
+        if ((rc = cmp_lincomb(c, prec, {b.r, b.p}, {1.0, beta}, b.p, n, ld, sums))) return rc;
+    }
+    *its = k;
+    return LRSDP_OK;
+}
+
+// One completion splitting iteration: U-step, V-step, y <- y + sigma (b - A(U V^T)).
+int cmp_admm_iter(lrsdp_ctx *c, const lrsdp_problem *p, int prec, void *U, void *V, int64_t ld, double *y,
+                  double sigma, double cg_tol, int cg_max, const CmpAdmmBufs &b) {
+    int its = 0, rc, nb = 0;
+    if ((rc = cmp_split_half(c, p, prec, U, V, ld, y, sigma, cg_tol, cg_max, b, &its))) return rc;
+    if ((rc = cmp_split_half(c, p, prec, V, U, ld, y, sigma, cg_tol, cg_max, b, &its))) return rc;
+    if ((rc = cmp_sddmm(c->stream, p->cmp, prec, 0, U, V, ld, b.z, nullptr, nullptr, nullptr, nullptr, 0.0, nullptr,
+                        nullptr, &nb)))
+        return rc;
+    return cmp_ytil(c->stream, p->cmp, nullptr, sigma, b.z, y, y);
 }
 
 int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws, void *R, double *y,
@@ -557,6 +680,75 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
             // so that the jump is not read as a stall
             hs.err1_prev = INFINITY;
             if ((rc = write_state(c, hs))) break;
+        }
+        if (!mc && phase2_on && hs.err1 <= o->switch_err1) {
+            // completion splitting phase: CG half-steps (Algorithm 2), same measures,
+            // stop test and fallback as the MaxCut phase below
+            void *U = gring[0];
+            void *Ravg = gring[1];
+            const int64_t bytes = n * ld * (prec == LRSDP_F64 ? 8 : 4);
+            const SolverState snap = hs;
+            const CmpAdmmBufs cb = cmp_admm_layout(p, prec, ld, ws + w.cadmm);
+            LRSDP_HIP_TRY(hipMemcpyAsync(ws + w.csnap, R, bytes, hipMemcpyDeviceToDevice, s));
+            LRSDP_HIP_TRY(hipMemcpyAsync(ytil[1], y, p->info.m * sizeof(double), hipMemcpyDeviceToDevice, s));
+            LRSDP_HIP_TRY(hipMemcpyAsync(U, R, bytes, hipMemcpyDeviceToDevice, s));
+            if ((rc = launch_fill(s, LRSDP_F64, cb.zero, p->info.m))) break;
+            const int chk = std::max(1, o->admm_check);
+            int64_t it2 = 0;
+            bool done2 = false, diverged = false;
+            while (it2 < o->max_admm) {
+                for (int b = 0; b < chk && rc == 0; ++b, ++it2)
+                    rc = cmp_admm_iter(c, p, prec, U, R, ld, y, sigma_sub, 1e-10, 200, cb);
+                if (rc) break;
+                if ((rc = launch_avg(s, prec, U, R, Ravg, n * ld))) break;
+                int nb1 = 0, nb2 = 0;
+                if ((rc = cmp_sddmm(s, p->cmp, prec, 2, Ravg, nullptr, ld, acon, nullptr, nullptr, nullptr, y, 0.0,
+                                    part_misc, nullptr, &nb1)))
+                    break;
+                const void *rb[1] = {Ravg};
+                if ((rc = launch_dots(s, prec, Ravg, rb, 1, n, ld, part_misc + (size_t)nb1 * kMaxSums, &nb2))) break;
+                if ((rc = launch_alm_finalize(s, st, part_misc, nb1 + nb2, 0))) break;
+                if ((rc = read_state(c, &hs))) break;
+                if (o->verbose)
+                    fprintf(stderr, "[lrsdp] admm %6lld obj % .10e err1 %.3e err3 % .3e t %.3fs\n", (long long)it2,
+                            hs.obj, hs.err1, hs.err3, elapsed());
+                if (!std::isfinite(hs.obj) || !std::isfinite(hs.err1) || hs.err1 > 10.0 * snap.err1) {
+                    diverged = true;
+                    break;
+                }
+                if (hs.err1 <= o->tol && std::fabs(hs.err3) <= o->tol) {
+                    done2 = true;
+                    break;
+                }
+                if (elapsed() > o->time_limit_s) break;
+            }
+            admm_iters += it2;
+            if (rc == LRSDP_ENUMERIC) {
+                // CG lost positive curvature: treat as a diverged splitting phase
+                rc = 0;
+                diverged = true;
+                clear_error();
+            }
+            if (rc) break;
+            if (done2) {
+                LRSDP_HIP_TRY(hipMemcpyAsync(R, Ravg, bytes, hipMemcpyDeviceToDevice, s));
+                status = LRSDP_OK;
+                break;
+            }
+            if (elapsed() > o->time_limit_s && !diverged) {
+                LRSDP_HIP_TRY(hipMemcpyAsync(R, Ravg, bytes, hipMemcpyDeviceToDevice, s));
+                break;
+            }
+            ++admm_fallbacks;
+            phase2_on = false;
+            LRSDP_HIP_TRY(hipMemcpyAsync(R, ws + w.csnap, bytes, hipMemcpyDeviceToDevice, s));
+            LRSDP_HIP_TRY(hipMemcpyAsync(y, ytil[1], p->info.m * sizeof(double), hipMemcpyDeviceToDevice, s));
+            if ((rc = write_state(c, snap))) break;
+            if ((rc = alm_refresh(0.0, 0))) break;
+            if ((rc = read_state(c, &hs))) break;
+            if (o->verbose)
+                fprintf(stderr, "[lrsdp] splitting phase %s after %lld iterations: back to the ALM\n",
+                        diverged ? "diverged" : "did not converge", (long long)it2);
         }
         if (mc && phase2_on && hs.err1 <= o->switch_err1) {
             // splitting phase from U = V = R with the current y and the penalty of the
@@ -937,15 +1129,35 @@ extern "C" int lrsdp_warmstart(lrsdp_ctx *c, const lrsdp_problem *p, const float
     return LRSDP_OK;
 }
 
+extern "C" int lrsdp_admm_workspace_bytes(const lrsdp_problem *p, int prec, int64_t ld, size_t *bytes) {
+    clear_error();
+    if (!p || !bytes) return set_error(LRSDP_EINVAL, "NULL argument");
+    int rc;
+    if ((rc = check_prec(prec)) || (rc = check_ld(prec, ld))) return rc;
+    *bytes = p->info.kind == LRSDP_MAXCUT ? 0 : cmp_admm_bytes(p, prec == LRSDP_F64 ? LRSDP_F64 : LRSDP_F32, ld);
+    return LRSDP_OK;
+}
+
 extern "C" int lrsdp_k_admm(lrsdp_ctx *c, const lrsdp_problem *p, int prec, void *U, void *V, int64_t ld, double *y,
-                            double sigma, int iters) {
+                            double sigma, int iters, double cg_tol, int cg_max, void *work, size_t work_bytes) {
     clear_error();
     if (!c || !U || !V || !y || iters < 0 || !(sigma > 0)) return set_error(LRSDP_EINVAL, "bad argument");
     int rc;
     if ((rc = check_problem(p)) || (rc = check_prec(prec)) || (rc = check_ld(prec, ld))) return rc;
-    if (p->info.kind != LRSDP_MAXCUT) return set_error(LRSDP_EUNSUPPORTED, "splitting step is for MaxCut problems");
     const int pr = prec == LRSDP_F64 ? LRSDP_F64 : LRSDP_F32;
+    if (p->info.kind == LRSDP_MAXCUT) {
+        for (int k = 0; k < iters; ++k)
+            if ((rc = admm_iter(c->stream, p->csr, pr, U, V, ld, y, sigma))) return rc;
+        return LRSDP_OK;
+    }
+    if (!(cg_tol > 0.0) || cg_max < 1) return set_error(LRSDP_EINVAL, "need cg_tol > 0 and cg_max >= 1");
+    const size_t need = cmp_admm_bytes(p, pr, ld);
+    if (!work || work_bytes < need)
+        return set_error(LRSDP_ENOMEM, "splitting workspace needs %zu bytes, got %zu", need, work_bytes);
+    if ((uintptr_t)work % 256) return set_error(LRSDP_EINVAL, "workspace must be 256-byte aligned");
+    const CmpAdmmBufs b = cmp_admm_layout(p, pr, ld, static_cast<char *>(work));
+    if ((rc = launch_fill(c->stream, LRSDP_F64, b.zero, p->info.m))) return rc;
     for (int k = 0; k < iters; ++k)
-        if ((rc = admm_iter(c->stream, p->csr, pr, U, V, ld, y, sigma))) return rc;
+        if ((rc = cmp_admm_iter(c, p, pr, U, V, ld, y, sigma, cg_tol, cg_max, b))) return rc;
     return LRSDP_OK;
 }

@@ -102,7 +102,9 @@ _SIGS = {
     "lrsdp_k_cubic": (C.c_int, [_P, _P, _P]),
     "lrsdp_k_alm": (C.c_int, [_P, _P, C.c_int, _P, _I64, _P, C.c_double, _P, _P]),
     "lrsdp_k_lbfgs_dir": (C.c_int, [_P, C.c_int, _I64, _I64, _P, _P, _P, C.c_int, _P]),
-    "lrsdp_k_admm": (C.c_int, [_P, _P, C.c_int, _P, _P, _I64, _P, C.c_double, C.c_int]),
+    "lrsdp_k_admm": (C.c_int, [_P, _P, C.c_int, _P, _P, _I64, _P, C.c_double, C.c_int, C.c_double, C.c_int, _P,
+                                C.c_size_t]),
+    "lrsdp_admm_workspace_bytes": (C.c_int, [_P, C.c_int, _I64, C.POINTER(C.c_size_t)]),
     "lrsdp_mlp_param_count": (C.c_int, []),
     "lrsdp_ws_features": (C.c_int, [_P, _P, _P, _P]),
     "lrsdp_mlp_forward": (C.c_int, [_P, _P, _P, _I64, _P]),
@@ -347,9 +349,22 @@ def ws_targets(ctx, prob, stats, y, log_sigma_ratio, target):
                                    _ptr(target)))
 
 
-def k_admm(ctx, prob, prec, U, V, y, sigma, iters):
+def admm_workspace_bytes(prob, prec, ld):
+    b = C.c_size_t()
+    _check(load().lrsdp_admm_workspace_bytes(prob.handle, prec, ld, C.byref(b)))
+    return b.value
+
+
+def k_admm(ctx, prob, prec, U, V, y, sigma, iters, cg_tol=1e-12, cg_max=1000, work=None):
+    """Splitting iterations in place (completion: CG half-steps; `work` is
+    allocated here when None)."""
+    import torch
+    nb = admm_workspace_bytes(prob, prec, U.shape[1])
+    if work is None and nb:
+        work = torch.empty(nb, dtype=torch.uint8, device=U.device)
+    wb = 0 if work is None else work.numel() * work.element_size()
     _check(load().lrsdp_k_admm(ctx.handle, prob.handle, prec, _ptr(U), _ptr(V), U.shape[1], _ptr(y),
-                               float(sigma), int(iters)))
+                               float(sigma), int(iters), float(cg_tol), int(cg_max), _ptr(work), wb))
 
 
 def certify_workspace_bytes(prob, max_iter):

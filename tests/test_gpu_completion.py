@@ -229,3 +229,51 @@ def test_solve_f32_medium(ctx):
     assert rc == L.OK and rc64 == L.OK
     assert m["err1"] <= 1e-5 and abs(m["err3"]) <= 1e-5
     assert abs(res.obj - res64.obj) <= 1e-5 * abs(res64.obj)
+
+
+@pytest.mark.parametrize("case", ["small", "medium"])
+def test_admm_step_parity(ctx, case):
+    # completion splitting iterations: CG half-steps (Algorithm 2) on the GPU vs
+    # the oracle's CG, both to 1e-12 of the right-hand side
+    import torch
+    from oracle.alm import admm_step
+    n1, n2, k, per = {"small": (40, 31, 2, 7), "medium": (300, 250, 4, 20)}[case]
+    r = 4
+    i, j, M, _, _ = completion_instance(n1, n2, k, per, seed=33)
+    prob = L.Problem.completion(n1, n2, i, j, M).upload(ctx)
+    op = completion_problem(n1, n2, i, j, M)
+    print("CASE", dict(test="cmp_admm", case=case), flush=True)
+    rng = np.random.default_rng(34)
+    U = 0.5 * rng.standard_normal((op.n, r))
+    V = U + 0.05 * rng.standard_normal((op.n, r))
+    y = 0.1 * rng.standard_normal(op.m)
+    sigma = 2.0
+    Ud, Vd = dev_factor(U, L.F64), dev_factor(V, L.F64)
+    yd = torch.from_numpy(y.copy()).cuda()
+    L.k_admm(ctx, prob, L.F64, Ud, Vd, yd, sigma, 2, cg_tol=1e-12, cg_max=2000)
+    torch.cuda.synchronize()
+    Uo, Vo, yo = U, V, y
+    for _ in range(2):
+        Uo, Vo, yo = admm_step(op, Uo, Vo, yo, sigma, cg_tol=1e-12, cg_iters=2000)
+    scale = 1.0 + np.abs(Uo).max()
+    assert np.max(np.abs(host(Ud, r) - Uo)) <= 1e-9 * scale
+    assert np.max(np.abs(host(Vd, r) - Vo)) <= 1e-9 * scale
+    assert np.max(np.abs(yd.cpu().numpy() - yo)) <= 1e-9 * (1.0 + np.abs(yo).max()) * scale
+    assert np.all(host(Ud)[:, r:] == 0.0)
+
+
+def test_solve_phase2_matches_oracle(ctx):
+    n1, n2, k, per, r = SOLVE_CASES["medium"]
+    i, j, Mij, U, V = completion_instance(n1, n2, k, per, seed=21)
+    prob = L.Problem.completion(n1, n2, i, j, Mij).upload(ctx)
+    op = completion_problem(n1, n2, i, j, Mij)
+    print("CASE", dict(test="cmp_solve_phase2"), flush=True)
+    R0 = init_factor(op.n, r, 7)
+    rc, res, R, y = gpu_solve(ctx, prob, R0, L.F64, op.m, tol=1e-7, phase2=1, switch_err1=1e-3)
+    ores = alm_solve(op, R0, opts=OOptions(tol=1e-7, phase2=True, switch_err1=1e-3))
+    print(res.as_dict(), "oracle", ores.obj, ores.converged, ores.admm_iters, ores.admm_fallbacks)
+    assert rc == L.OK and ores.converged
+    assert res.admm_iters > 0 and res.admm_fallbacks == ores.admm_fallbacks
+    assert abs(res.obj - ores.obj) <= 1e-5 * abs(ores.obj)
+    m = K.alm_measures(op, R, y)
+    assert m["err1"] <= 1e-7 and abs(m["err3"]) <= 1e-7
