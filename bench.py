@@ -30,8 +30,8 @@ HBM_PEAK_GBS = 8000.0
 WORKLOAD = ("maxcut n=1e6 pair: Erdos-Renyi 5e6 edges + Chung-Lu beta=2.5 mean degree 10 (5e6 edges), "
             "weights uniform in {-1,+1}, C=-L/4, diag(X)=1, rank 20")
 INSTANCES = ["er_1m_pm1", "cl_1m_pm1"]
-ALL_PATHS = ["f64_precond", "f64_dynrank", "f32", "f32_precond", "f32_bf16in", "f32_warm", "f32_precond_warm",
-             "f32_dynrank_precond"]
+ALL_PATHS = ["f64_precond", "f64_dynrank", "f64_reopt", "f64_reopt2", "f32", "f32_precond", "f32_bf16in",
+             "f32_warm", "f32_precond_warm", "f32_dynrank_precond"]
 DYNRANK_LD = {0: 30, 1: 32}       # row stride with room for the grown rank (FP64, FP32)
 OTHER_WORKLOADS = {
     "cl_10m": "maxcut n=1e7 Chung-Lu beta=2.5 mean degree 8 (4e7 edges), unit weights, C=-L/4, diag(X)=1, rank 24",
@@ -264,6 +264,16 @@ def main():
         for run in runs:
             dt, rc, res, y = solve_dynrank(run, L.F64)
             record("f64_dynrank", run, dt, res, dict(converged=rc == L.OK, rank_final=res.rank_final), y=y)
+    for path, level in (("f64_reopt", 1), ("f64_reopt2", 2)):
+        # re-optimisation (Section 4.1): rounds stop at err1 <= tol; C scaled by
+        # 0.1 per extra round until |err3| <= tol (and err2 <= tol at level 2)
+        if path in enabled:
+            for run in runs:
+                dt, rc, res = solve_with(run, L.F64, reopt=level)
+                extra = dict(converged=rc == L.OK, reopt_rounds=res.reopt_rounds)
+                if level == 2:
+                    extra["reopt_err2"] = res.err2
+                record(path, run, dt, res, extra, y=run["per"][L.F64]["y"])
     if "f32" in enabled:
         for run in runs:
             dt, res = solve(run, L.F32)

@@ -139,7 +139,10 @@ int lrsdp_problem_upload(lrsdp_ctx *ctx, lrsdp_problem *prob, void *dev,
  * max_outer = 300, max_inner = 2000, max_iter_total = 200000,
  * check_every = 8, time_limit_s = 1e30, refresh_every = 0 (off), phase2 = 0,
  * switch_err1 = 1e-3, admm_check = 10, max_admm = 5000, precond = 0,
- * rank_max = 0 (off), rank_trigger = 2000, rank_scale = 1e-2, rank_seed = 15049.
+ * rank_max = 0 (off), rank_trigger = 2000, rank_scale = 1e-2, rank_seed = 15049,
+ * reopt = 0, reopt_factor = 0.1, max_reopt = 10, cert_iters = 300.
+ * With re-optimisation the results (obj, dual, err3, sigma, y) are those of
+ * the original problem: the last round's divided by its objective scale.
  */
 typedef struct {
     int     prec;             /* LRSDP_F64 / LRSDP_F32 / LRSDP_F32_BF16IN      */
@@ -189,6 +192,24 @@ typedef struct {
                                  SplitMix64 sequence seeded with rank_seed, as
                                  uniforms u = ((x >> 11) + 0.5) 2^-53, through
                                  Box-Muller: sqrt(-2 ln u0) cos(2 pi u1)        */
+    int     reopt;            /* re-optimisation level (Section 4.1).  0: off,
+                                 the ALM runs until err1 <= tol and
+                                 |err3| <= tol.  1 (mild): each round stops
+                                 when err1 <= tol; if |err3| > tol on the
+                                 original problem, a new round solves the
+                                 problem with reopt_factor times the previous
+                                 round's C, warm from its R, its y times
+                                 reopt_factor and its penalty (inner tolerance
+                                 restarted, no splitting phase after the first
+                                 round).  2 (strict): as 1, and the final test
+                                 also needs err2 <= tol, err2 from the
+                                 certified lower bound lambda_min - resid of a
+                                 block Lanczos run (lrsdp_certify, at most
+                                 cert_iters steps, residual target
+                                 0.1 tol (1 + ||vec(C)||_1)) on C - A*(y)    */
+    double  reopt_factor;     /* objective scale per round, 0 < f < 1          */
+    int     max_reopt;        /* rounds after the first at most                */
+    int     cert_iters;       /* reopt = 2: Lanczos steps per certificate      */
 } lrsdp_options;
 
 void lrsdp_options_default(lrsdp_options *opts);
@@ -214,6 +235,9 @@ typedef struct {
                                switch were restored and the ALM went on alone */
     int64_t rank_final;   /* rank at the end (differs from opts->rank when the
                              dynamic rank grew it)                             */
+    int64_t reopt_rounds; /* re-optimisation rounds after the first (reopt >= 1)*/
+    double  err2;         /* reopt = 2: err2 of the last certificate (from
+                             lambda_lb); NaN when none was run                 */
 } lrsdp_result;
 
 /* Device workspace the solve needs for this problem and these options. */

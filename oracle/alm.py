@@ -18,17 +18,21 @@ options struct (the two share numbers, not code):
 * L-BFGS memory T = lbfgs_mem (default 2) pairs from consecutive iterations; a pair failing
   the curvature guard, or a direction that is not a descent direction, clears
   the memory (the next direction is -grad);
-* stop when err1 <= tol and |err3| <= tol (the paper's mild re-opt criterion).
+* stop when err1 <= tol and |err3| <= tol (the paper's mild re-opt criterion);
+  with ``reopt`` >= 1 the paper's re-optimisation instead (Section 4.1, see
+  ``reopt_solve``).
 """
 
 from __future__ import annotations
 
+import dataclasses
 import time
 from dataclasses import dataclass, field
 
 import numpy as np
 
 from . import kernels as K
+from .certify import lambda_min
 from .lbfgs import accept_pair, two_loop
 from .problem import SDPProblem
 
@@ -58,6 +62,9 @@ class Options:
     switch_err1: float = 1e-3      # ... once err1 <= switch_err1 after an ALM step
     admm_check: int = 10
     max_admm: int = 5000
+    reopt: int = 0                 # re-optimisation (Section 4.1): 0 off, 1 mild, 2 strict
+    reopt_factor: float = 0.1      # objective scale applied per round
+    max_reopt: int = 10            # rounds after the first at most
 
 
 @dataclass
@@ -78,6 +85,9 @@ class SolveResult:
     admm_iters: int = 0
     admm_fallbacks: int = 0
     rank_final: int = 0
+    reopt_rounds: int = 0
+    err2: float = float("nan")
+    eta: float = 0.0               # inner tolerance factor of the last subproblem
 
 
 def default_sigma0(prob: SDPProblem) -> float:
@@ -134,11 +144,12 @@ def row_block_h0(prob: SDPProblem, R: np.ndarray, sigma: float, y=None, mode: in
     return apply
 
 
-def lbfgs_minimize(prob: SDPProblem, R, y, sigma, eta, opts: Options, budget: int):
-    """Minimise L(.; y, sigma) from R with Algorithm 1 and the exact step."""
+def lbfgs_minimize(prob: SDPProblem, R, y, sigma, eta, opts: Options, budget: int, floor: float = 1.0):
+    """Minimise L(.; y, sigma) from R with Algorithm 1 and the exact step, until
+    ||grad||_F <= eta max(floor, ||grad at R||_F) (floor: the objective's scale)."""
     G = K.gradient(prob, R, y, sigma)
     gnorm = float(np.sqrt(np.sum(G * G)))
-    target = eta * max(1.0, gnorm)
+    target = eta * max(floor, gnorm)
     pairs = []
     it = 0
     while it < min(opts.max_inner, budget):
@@ -173,12 +184,25 @@ def lbfgs_minimize(prob: SDPProblem, R, y, sigma, eta, opts: Options, budget: in
 def alm_solve(prob: SDPProblem, R0: np.ndarray, y0=None, opts: Options | None = None,
               log=None) -> SolveResult:
     opts = opts or Options()
+    if opts.reopt:
+        return reopt_solve(prob, R0, y0, opts, log)
+    return _alm_run(prob, R0, y0, opts, log)
+
+
+def _alm_run(prob: SDPProblem, R0: np.ndarray, y0, opts: Options, log=None, sigma=None, sigma_cap=None,
+             err1_only=False, floor=1.0, eta=None) -> SolveResult:
+    """One ALM run.  sigma / sigma_cap / eta: starting penalty, its cap and the
+    starting inner tolerance factor (defaults from the options); floor: the
+    inner stop's floor; err1_only: stop as soon as err1 <= tol (a
+    re-optimisation round), otherwise when err1 <= tol and |err3| <= tol."""
     t0 = time.perf_counter()
     R = np.array(R0, dtype=np.float64, copy=True)
     y = np.zeros(prob.m) if y0 is None else np.array(y0, dtype=np.float64, copy=True)
-    sigma = opts.sigma0 if opts.sigma0 > 0 else default_sigma0(prob)
-    sigma_cap = sigma * opts.sigma_max_ratio
-    eta = opts.eta0
+    if sigma is None:
+        sigma = opts.sigma0 if opts.sigma0 > 0 else default_sigma0(prob)
+    if sigma_cap is None:
+        sigma_cap = sigma * opts.sigma_max_ratio
+    eta = opts.eta0 if eta is None else eta
     err1_prev = np.inf
     total = 0
     hist = []
@@ -190,7 +214,7 @@ def alm_solve(prob: SDPProblem, R0: np.ndarray, y0=None, opts: Options | None = 
     rank_cur = R.shape[1]
     rank_cap = min(max(opts.rank_max, rank_cur), int(np.floor(np.sqrt(2.0 * prob.m))))
     for outer in range(1, opts.max_outer + 1):
-        R, it, gnorm = lbfgs_minimize(prob, R, y, sigma, eta, opts, opts.max_iter_total - total)
+        R, it, gnorm = lbfgs_minimize(prob, R, y, sigma, eta, opts, opts.max_iter_total - total, floor)
         total += it
         y = K.multiplier_estimate(prob, R, y, sigma)
         meas = K.alm_measures(prob, R, y)
@@ -198,7 +222,7 @@ def alm_solve(prob: SDPProblem, R0: np.ndarray, y0=None, opts: Options | None = 
         hist.append(rec)
         if log is not None:
             log(rec)
-        if meas["err1"] <= opts.tol and abs(meas["err3"]) <= opts.tol:
+        if meas["err1"] <= opts.tol and (err1_only or abs(meas["err3"]) <= opts.tol):
             converged = True
             break
         # penalty and inner-tolerance schedule, from the measures after the
@@ -225,10 +249,10 @@ def alm_solve(prob: SDPProblem, R0: np.ndarray, y0=None, opts: Options | None = 
             # this case open).
             Rm, _, _, y2, meas2, it2, diverged = admm_phase(
                 prob, R, y, sigma_sub, tol=opts.tol, max_iter=opts.max_admm, check_every=opts.admm_check,
-                diverge_factor=10.0)
+                diverge_factor=10.0, err1_only=err1_only)
             admm_total += it2
             hist.append(dict(outer=outer, admm=it2, sigma=sigma_sub, diverged=diverged, **meas2))
-            if not diverged and meas2["err1"] <= opts.tol and abs(meas2["err3"]) <= opts.tol:
+            if not diverged and meas2["err1"] <= opts.tol and (err1_only or abs(meas2["err3"]) <= opts.tol):
                 R, y, meas = Rm, y2, meas2
                 converged = True
                 break
@@ -240,7 +264,80 @@ def alm_solve(prob: SDPProblem, R0: np.ndarray, y0=None, opts: Options | None = 
                        err1=meas["err1"], err1_inf=meas["err1_inf"], err3=meas["err3"],
                        outer=outer, inner=total, converged=converged,
                        seconds=time.perf_counter() - t0, history=hist,
-                       admm_iters=admm_total, admm_fallbacks=fallbacks, rank_final=R.shape[1])
+                       admm_iters=admm_total, admm_fallbacks=fallbacks, rank_final=R.shape[1], eta=eta)
+
+
+def scaled_objective(prob: SDPProblem, alpha: float) -> SDPProblem:
+    """The same constraints with the objective matrix alpha C."""
+    return dataclasses.replace(prob, C=(alpha * prob.C).tocsr())
+
+
+def reopt_solve(prob: SDPProblem, R0: np.ndarray, y0=None, opts: Options | None = None,
+                log=None) -> SolveResult:
+    """Re-optimisation (Section 4.1).  A round stops once the primal
+    infeasibility tolerance holds (err1 <= tol).  The final criteria are then
+    evaluated on the original problem: |err3| <= tol (level 1), and also
+    err2 <= tol (level 2).  While they fail, the next round solves the problem
+    with the objective matrix scaled down by reopt_factor once more (factor^k C
+    in round k), warm from the previous round's output: its R, its multipliers
+    times reopt_factor (the multipliers of the scaled problem), its penalty, and
+    its inner tolerance factor taken one schedule step further.  The floor of
+    the inner stop is in the objective's units, so it scales with C (alpha in
+    round k); the penalty rule's err1 reference restarts each round; the
+    penalty cap stays that of the first round; only the first round may enter
+    the splitting phase.  max_outer and max_iter_total bound all rounds
+    together.  The result is stated for the original problem: objective,
+    multipliers and penalty of the last round divided by its scale (the
+    Lagrangian of alpha C with y and sigma is alpha times that of C with y/alpha
+    and sigma/alpha)."""
+    opts = opts or Options()
+    t0 = time.perf_counter()
+    sigma0 = opts.sigma0 if opts.sigma0 > 0 else default_sigma0(prob)
+    sigma_cap = sigma0 * opts.sigma_max_ratio
+    alpha = 1.0
+    rounds = 0
+    outer = inner = admm = fallbacks = 0
+    hist = []
+    err2 = float("nan")
+    R, y, sigma, eta = R0, y0, sigma0, opts.eta0
+    converged = False
+    while True:
+        ro = dataclasses.replace(opts, reopt=0, max_outer=opts.max_outer - outer,
+                                 max_iter_total=opts.max_iter_total - inner,
+                                 phase2=opts.phase2 and rounds == 0)
+        res = _alm_run(scaled_objective(prob, alpha), R, y, ro, log, sigma=sigma, sigma_cap=sigma_cap,
+                       err1_only=True, floor=alpha, eta=eta)
+        outer += res.outer
+        inner += res.inner
+        admm += res.admm_iters
+        fallbacks += res.admm_fallbacks
+        hist.extend(dict(round=rounds, alpha=alpha, **h) for h in res.history)
+        R, y, sigma = res.R, res.y, res.sigma
+        eta = max(res.eta * opts.eta_factor, opts.eta_min)
+        if not res.converged:
+            break
+        obj, dual = res.obj / alpha, res.dual / alpha
+        err3 = (obj - dual) / (1.0 + abs(obj) + abs(dual))
+        ok = abs(err3) <= opts.tol
+        if ok and opts.reopt == 2:
+            err2 = max(0.0, -lambda_min(prob, y / alpha)) / (1.0 + prob.c_l1)
+            ok = err2 <= opts.tol
+        hist.append(dict(round=rounds, alpha=alpha, err3_original=err3, err2=err2, met=ok))
+        if ok:
+            converged = True
+            break
+        if rounds >= opts.max_reopt or inner >= opts.max_iter_total or outer >= opts.max_outer:
+            break
+        rounds += 1
+        alpha *= opts.reopt_factor
+        y = opts.reopt_factor * y
+    meas = K.alm_measures(prob, R, y / alpha)
+    return SolveResult(R=R, y=y / alpha, sigma=sigma / alpha, obj=meas["obj"], dual=meas["dual"],
+                       err1=meas["err1"], err1_inf=meas["err1_inf"], err3=meas["err3"],
+                       outer=outer, inner=inner, converged=converged,
+                       seconds=time.perf_counter() - t0, history=hist,
+                       admm_iters=admm, admm_fallbacks=fallbacks, rank_final=R.shape[1],
+                       reopt_rounds=rounds, err2=err2, eta=eta)
 
 
 # ---------------------------------------------------------------------------
@@ -295,9 +392,10 @@ def admm_step(prob: SDPProblem, U, V, y, sigma, cg_tol=1e-12, cg_iters=1000):
 
 
 def admm_phase(prob: SDPProblem, R, y, sigma, tol=1e-5, max_iter=2000, check_every=10, log=None,
-               diverge_factor=None):
+               diverge_factor=None, err1_only=False):
     """Run splitting iterations from U = V = R until err1 and |err3| at
-    R = (U + V)/2 are below tol (checked every `check_every` iterations).
+    R = (U + V)/2 are below tol (checked every `check_every` iterations; err1
+    alone with err1_only).
     With diverge_factor, stop early (diverged = True) when a check finds a
     non-finite value or err1 above diverge_factor times its value at R."""
     U, V = R.copy(), R.copy()
@@ -317,7 +415,7 @@ def admm_phase(prob: SDPProblem, R, y, sigma, tol=1e-5, max_iter=2000, check_eve
                                                    or meas["err1"] > diverge_factor * err1_0):
                     diverged = True
                     break
-                if meas["err1"] <= tol and abs(meas["err3"]) <= tol:
+                if meas["err1"] <= tol and (err1_only or abs(meas["err3"]) <= tol):
                     break
     if diverge_factor is None:
         return 0.5 * (U + V), U, V, y, meas, it

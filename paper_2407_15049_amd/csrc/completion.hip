@@ -34,6 +34,7 @@ struct CmpSpmmArgs {
     int force_slot;       // >= 0: write G into this slot and ignore st->done (subproblem start)
     Rings<S> rings;       // G slots 0..T, D slots 0..T-1
     double *partials;
+    double cs;            // objective scale: C = cs I
 };
 
 // acc += sum over the row's samples of ytil_k * V_partner  (this lane's chunk)
@@ -70,7 +71,7 @@ __device__ __forceinline__ void cmp_gather(const int32_t *__restrict__ ptr, cons
     }
 }
 
-// GRAD = false: Y = V - A*(ytil) V.  GRAD = true: G_{k+1} = 2 (R - A*(ytil) R)
+// GRAD = false: Y = cs V - A*(ytil) V.  GRAD = true: G_{k+1} = 2 (cs R - A*(ytil) R)
 // into G slot (gk+1) mod (T+1), plus its dots with every ring slot.
 template <typename S, int GS, bool GRAD>
 __global__ __launch_bounds__(kBlock) void k_cmp_spmm(DevCompletion P, CmpSpmmArgs<S> a) {
@@ -108,7 +109,10 @@ __global__ __launch_bounds__(kBlock) void k_cmp_spmm(DevCompletion P, CmpSpmmArg
         const CV v = active ? *reinterpret_cast<const CV *>(a.V + off) : zero;
         D4 vv = widen(v), aa = widen(acc), o;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) o.v[c] = GRAD ? 2.0 * (vv.v[c] - aa.v[c]) : vv.v[c] - aa.v[c];
+        for (int c = 0; c < 4; ++c) {
+            const double cv = a.cs * vv.v[c];
+            o.v[c] = GRAD ? 2.0 * (cv - aa.v[c]) : cv - aa.v[c];
+        }
         CV os;
         narrow(o, os);
         if constexpr (!GRAD) {
@@ -301,23 +305,23 @@ int spmm_completion(hipStream_t s, const DevCompletion &P, int prec, const void 
                     void *Y) {
     int nb = 0;
     if (prec == LRSDP_F64) {
-        CmpSpmmArgs<double> a{(const double *)V, (double *)Y, ytil, ld, nullptr, -1, {}, nullptr};
+        CmpSpmmArgs<double> a{(const double *)V, (double *)Y, ytil, ld, nullptr, -1, {}, nullptr, 1.0};
         return cmp_spmm_t<double, false>(s, P, a, &nb);
     }
-    CmpSpmmArgs<float> a{(const float *)V, (float *)Y, ytil, ld, nullptr, -1, {}, nullptr};
+    CmpSpmmArgs<float> a{(const float *)V, (float *)Y, ytil, ld, nullptr, -1, {}, nullptr, 1.0};
     return cmp_spmm_t<float, false>(s, P, a, &nb);
 }
 
 int cmp_grad(hipStream_t s, const DevCompletion &P, int prec, const SolverState *st, const void *R,
              const double *ytil, void *const *gring, void *const *dring, int T, int64_t ld, double *partials,
-             int force_slot, int *nb) {
+             int force_slot, int *nb, double cs) {
     if (prec == LRSDP_F64) {
-        CmpSpmmArgs<double> a{(const double *)R, nullptr, ytil, ld, st, force_slot, {}, partials};
+        CmpSpmmArgs<double> a{(const double *)R, nullptr, ytil, ld, st, force_slot, {}, partials, cs};
         for (int g = 0; g <= T; ++g) a.rings.g[g] = (double *)gring[g];
         for (int d = 0; d < T; ++d) a.rings.d[d] = (double *)dring[d];
         return cmp_spmm_t<double, true>(s, P, a, nb);
     }
-    CmpSpmmArgs<float> a{(const float *)R, nullptr, ytil, ld, st, force_slot, {}, partials};
+    CmpSpmmArgs<float> a{(const float *)R, nullptr, ytil, ld, st, force_slot, {}, partials, cs};
     for (int g = 0; g <= T; ++g) a.rings.g[g] = (float *)gring[g];
     for (int d = 0; d < T; ++d) a.rings.d[d] = (float *)dring[d];
     return cmp_spmm_t<float, true>(s, P, a, nb);

@@ -33,6 +33,16 @@ __device__ __forceinline__ void vfma(float4 &a, float w, const float4 &b) {
 }
 
 // float64 dot product of two chunks (float inputs promoted before the products)
+__device__ __forceinline__ void vscale(double2 &a, double w) {
+    a.x *= w;
+    a.y *= w;
+}
+__device__ __forceinline__ void vscale(float4 &a, float w) {
+    a.x *= w;
+    a.y *= w;
+    a.z *= w;
+    a.w *= w;
+}
 __device__ __forceinline__ double vdot(const double2 &a, const double2 &b) {
     return fma(a.x, b.x, a.y * b.y);
 }

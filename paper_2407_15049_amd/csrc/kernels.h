@@ -14,6 +14,7 @@ struct SolverState {
     double sigma_cap;                    // sigma_max_ratio * sigma0
     double eta;                          // inner tolerance factor
     double target;                       // inner stop: ||G||_F <= target
+    double gfloor;                       // target = eta max(gfloor, ||G_0||_F); gfloor = objective scale
     double gnorm;                        // ||G_k||_F
     double a[4];                         // quartic coefficients a1..a4
     double taus[kMaxMem];                // step of the direction in each D slot
@@ -37,6 +38,7 @@ struct SolverState {
     int numeric;    // NaN/Inf met
     int refreshes;  // exact C R recomputations
     int precond;    // 1: row-block H0 = P^{-1} in the two-loop (MaxCut)
+    int stop_rule;  // 0: err1 <= tol and |err3| <= tol; 1: err1 <= tol (a re-optimisation round)
 };
 
 // Row-block H0 of the L-BFGS direction (solve option precond, MaxCut):
@@ -55,6 +57,7 @@ struct PcBufs {
     int mode;            // 1: h = hrow; 2: h_i = 2 max(C_ii - ytil_i, 0.01 hrow_i), moves with ytil
     const double *diag;  // mode 2: C_ii
     double *hdyn;        // mode 2: h of the current iterate (n)
+    double cs;           // objective scale: h from cs C
 };
 
 // index of the unordered G-slot pair (j, l), j <= l <= kPcMem
@@ -85,6 +88,7 @@ struct SpmmArgs {
     double *y = nullptr;            // kEpiRefresh: multipliers
     double *rn = nullptr;           // kEpiRefresh / kEpiLS: ||R_i||^2 out (nullable)
     double sigma = 0.0;             // kEpiRefresh: y <- y - sigma (rn - 1) if > 0; kEpiSplit: penalty
+    double cs = 1.0;                // objective scale: the operator is cs C (re-optimisation)
     double *q1 = nullptr;           // kEpiLS: optional per-constraint outputs
     double *q2 = nullptr;
     int64_t ld = 0;

@@ -16,10 +16,11 @@
 
 namespace lrsdp {
 
-int launch_ls_finalize(hipStream_t, SolverState *, const double *, int, const double *, int, int);
+int launch_ls_finalize(hipStream_t, SolverState *, const double *, int, const double *, int, int, double);
 int launch_lbfgs_finalize(hipStream_t, SolverState *, const double *, int);
 int launch_init_finalize(hipStream_t, SolverState *, const double *, int, int);
-int launch_alm_finalize(hipStream_t, SolverState *, const double *, int, int);
+int launch_alm_finalize(hipStream_t, SolverState *, const double *, int, int, double);
+int launch_dscale(hipStream_t, double *, double, int64_t);
 int launch_reduce(hipStream_t, const double *, int, int, double *);
 int launch_cubic(hipStream_t, const double *, double *);
 int launch_update_maxcut(hipStream_t, int, SolverState *, void *, const void *, const double *, const double *,
@@ -42,7 +43,7 @@ int launch_two_loop_pairs(hipStream_t, const double *, int, double *, int *);
 int launch_gather_gram(hipStream_t, const double *, int, int, double *);
 int launch_ls_out_cmp(hipStream_t, const double *, const double *, double, double *);
 int cmp_grad(hipStream_t, const DevCompletion &, int, const SolverState *, const void *, const double *,
-             void *const *, void *const *, int, int64_t, double *, int, int *);
+             void *const *, void *const *, int, int64_t, double *, int, int *, double);
 int cmp_sddmm(hipStream_t, const DevCompletion &, int, int, const void *, const void *, int64_t, double *, double *,
               double *, const double *, double *, double, double *, const SolverState *, int *);
 int cmp_samples(hipStream_t, const DevCompletion &, const SolverState *, double *, const double *, const double *,
@@ -191,13 +192,17 @@ extern "C" void lrsdp_options_default(lrsdp_options *o) {
     o->rank_trigger = 2000;
     o->rank_scale = 1e-2;
     o->rank_seed = 15049;
+    o->reopt = 0;
+    o->reopt_factor = 0.1;
+    o->max_reopt = 10;
+    o->cert_iters = 300;
 }
 
 namespace {
 
 struct WsPlan {
     size_t cd, gring[kMaxMem + 1], dring[kMaxMem], ytil[2], rn, q1, q2, acon, shadow, rho, kap, hdyn, cadmm, csnap,
-        total;
+        yorig, cert, cert_bytes, total;
 };
 
 int plan_workspace(const lrsdp_problem *p, const lrsdp_options *o, WsPlan *w) {
@@ -210,6 +215,10 @@ int plan_workspace(const lrsdp_problem *p, const lrsdp_options *o, WsPlan *w) {
     rc = check_ld(o->prec, o->ld);
     if (rc) return rc;
     if (o->precond < 0 || o->precond > 2) return set_error(LRSDP_EINVAL, "precond = %d not in {0, 1, 2}", o->precond);
+    if (o->reopt < 0 || o->reopt > 2) return set_error(LRSDP_EINVAL, "reopt = %d not in {0, 1, 2}", o->reopt);
+    if (o->reopt && (!(o->reopt_factor > 0.0) || !(o->reopt_factor < 1.0) || o->max_reopt < 0))
+        return set_error(LRSDP_EINVAL, "re-optimisation needs 0 < reopt_factor < 1 and max_reopt >= 0");
+    if (o->reopt == 2 && o->cert_iters < 1) return set_error(LRSDP_EINVAL, "reopt = 2 needs cert_iters >= 1");
     if (o->precond) {
         if (p->info.kind != LRSDP_MAXCUT)
             return set_error(LRSDP_EUNSUPPORTED, "precond (row-block H0) is for MaxCut problems");
@@ -242,6 +251,12 @@ int plan_workspace(const lrsdp_problem *p, const lrsdp_options *o, WsPlan *w) {
     const size_t arr256 = (arr + 255) / 256 * 256, vec256 = ((size_t)p->info.m * 8 + 255) / 256 * 256;
     w->cadmm = take(cph2 ? 5 * arr256 + 3 * vec256 : 0);
     w->csnap = take(cph2 ? arr : 0);
+    // strict re-optimisation: multipliers of the original problem and the
+    // certificate's workspace
+    w->cert_bytes = 0;
+    if (o->reopt == 2 && (rc = lrsdp_certify_workspace_bytes(p, o->cert_iters, &w->cert_bytes))) return rc;
+    w->yorig = take(o->reopt == 2 ? (size_t)p->info.m * 8 : 0);
+    w->cert = take(w->cert_bytes);
     w->total = off + 256;
     return LRSDP_OK;
 }
@@ -437,7 +452,7 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
     const bool bf = o->prec == LRSDP_F32_BF16IN && mc;
     uint16_t *shadow = bf ? reinterpret_cast<uint16_t *>(ws + w.shadow) : nullptr;
     PcBufs pcb{reinterpret_cast<double *>(ws + w.rho), reinterpret_cast<double *>(ws + w.kap), p->csr.hrow, n,
-               o->precond, p->csr.diag, reinterpret_cast<double *>(ws + w.hdyn)};
+               o->precond, p->csr.diag, reinterpret_cast<double *>(ws + w.hdyn), 1.0};
     const PcBufs *pc = (mc && o->precond) ? &pcb : nullptr;
     SolverState *st = at<SolverState>(c->scratch, kStateOff);
     double *part_ls = at<double>(c->scratch, kPartLsOff);
@@ -453,6 +468,7 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
     h.sigma = sigma0;
     h.sigma_cap = sigma0 * o->sigma_max_ratio;
     h.eta = o->eta0;
+    h.gfloor = 1.0;
     h.err1_prev = INFINITY;
     h.tol = o->tol;
     h.sigma_factor = o->sigma_factor;
@@ -464,6 +480,7 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
     h.b_inf = p->info.b_inf;
     h.max_inner = o->max_inner;
     h.T = T;
+    h.stop_rule = o->reopt ? 1 : 0;
     rc = write_state(c, h);
     if (rc) return rc;
     // zero the rings so stale slots hold finite values
@@ -486,6 +503,9 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
     };
     double spmm_ms = 0.0;
     int spmm_n = 0;
+    // objective scale of the current re-optimisation round: the round solves
+    // the problem with cs C in place of C
+    double cs = 1.0;
 
     // ALM measures at R, with the multiplier step y <- y + sigma (b - A(RR^T))
     // when sigma > 0.  MaxCut: exact C R (into CD), ||R_i||^2; completion:
@@ -500,6 +520,7 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
             ref.y = y;
             ref.rn = rn;
             ref.sigma = sigma;
+            ref.cs = cs;
             ref.ld = ld;
             ref.partials = part_misc;
             if ((r2 = spmm_maxcut(s, p->csr, prec, ref, &np))) return r2;
@@ -512,7 +533,7 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
             if ((r2 = launch_dots(s, prec, R, rb, 1, n, ld, part_misc + (size_t)nb1 * kMaxSums, &nb2))) return r2;
             np = nb1 + nb2;
         }
-        return launch_alm_finalize(s, st, part_misc, np, mode);
+        return launch_alm_finalize(s, st, part_misc, np, mode, mc ? 1.0 : cs);
     };
     if ((rc = alm_refresh(0.0, 0))) return rc;
 
@@ -525,6 +546,55 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
     int64_t outer = 0;
     int64_t total_inner = 0;
     double sigma_host = sigma0;
+    int reopt_rounds = 0;
+    double err2 = NAN;
+    // Re-optimisation (Section 4.1), after a round met err1 <= tol: test the
+    // final criteria on the original problem, whose objective and multipliers
+    // are those of the round divided by cs.  Returns 0 when they hold, 1 when a
+    // limit stops the solve, 2 when a new round has been set up (C <- factor C
+    // and y <- factor y, the multipliers of the scaled problem; R, the penalty
+    // and the rank carry over; the inner tolerance factor takes one more
+    // schedule step and the inner stop's floor moves to the objective scale;
+    // the penalty rule's err1 reference restarts; no splitting phase), or an
+    // error code.
+    auto reopt_check = [&](SolverState &hs) -> int {
+        const double err3o = (hs.obj - hs.dual) / (cs + std::fabs(hs.obj) + std::fabs(hs.dual));
+        bool ok = std::fabs(err3o) <= o->tol;
+        int r2 = 0;
+        if (ok && o->reopt == 2) {
+            // dual infeasibility from the certified lower bound on
+            // lambda_min(C - A*(y / cs))
+            double *yo = reinterpret_cast<double *>(ws + w.yorig);
+            LRSDP_HIP_TRY(hipMemcpyAsync(yo, y, p->info.m * sizeof(double), hipMemcpyDeviceToDevice, s));
+            if (cs != 1.0 && (r2 = launch_dscale(s, yo, 1.0 / cs, p->info.m))) return r2;
+            lrsdp_cert ct{};
+            if ((r2 = lrsdp_certify(c, p, yo, o->cert_iters, 0.1 * o->tol * (1.0 + p->info.c_l1), 15049, ws + w.cert,
+                                    w.cert_bytes, &ct)))
+                return r2;
+            err2 = std::max(0.0, -ct.lambda_lb) / (1.0 + p->info.c_l1);
+            ok = err2 <= o->tol;
+        }
+        if (o->verbose)
+            fprintf(stderr, "[lrsdp] re-opt round %d (scale %.3e): err1 %.3e err3 % .3e err2 %.3e %s\n", reopt_rounds,
+                    cs, hs.err1, err3o, err2, ok ? "met" : "not met");
+        if (ok) return 0;
+        if (reopt_rounds >= o->max_reopt || hs.inner_total >= o->max_iter_total || outer >= o->max_outer ||
+            elapsed() > o->time_limit_s)
+            return 1;
+        ++reopt_rounds;
+        cs *= o->reopt_factor;
+        pcb.cs = cs;
+        phase2_on = false;
+        if ((r2 = launch_dscale(s, y, o->reopt_factor, p->info.m))) return r2;
+        if ((r2 = alm_refresh(0.0, 0))) return r2;
+        if ((r2 = read_state(c, &hs))) return r2;
+        hs.eta = std::max(hs.eta * o->eta_factor, o->eta_min);
+        hs.gfloor = cs;
+        hs.err1_prev = INFINITY;
+        hs.converged = 0;
+        if ((r2 = write_state(c, hs))) return r2;
+        return 2;
+    };
     for (outer = 1; outer <= o->max_outer; ++outer) {
         // subproblem start: ytil, G_0, D_0 = -G_0
         int nb = 0, ncb = 0;
@@ -534,7 +604,7 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
                 break;
         } else {
             if ((rc = cmp_ytil(s, p->cmp, st, 0.0, acon, y, ytil[0]))) break;
-            if ((rc = cmp_grad(s, p->cmp, prec, st, R, ytil[0], gring, dring, T, ld, part_misc, 0, &nb))) break;
+            if ((rc = cmp_grad(s, p->cmp, prec, st, R, ytil[0], gring, dring, T, ld, part_misc, 0, &nb, cs))) break;
         }
         int64_t left = o->max_iter_total - total_inner;
         int k_limit = (int)std::min<int64_t>(o->max_inner, std::max<int64_t>(left, 0));
@@ -560,6 +630,7 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
                     ref.y = y;
                     ref.rn = rn;
                     ref.sigma = 0.0;
+                    ref.cs = cs;
                     ref.ld = ld;
                     ref.partials = part_misc;
                     int np2 = 0;
@@ -572,7 +643,7 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
                                         part_misc, nullptr, &nb2)))
                         break;
                     if ((rc = cmp_ytil(s, p->cmp, st, 0.0, acon, y, ytil[0]))) break;
-                    if ((rc = cmp_grad(s, p->cmp, prec, st, R, ytil[0], gring, dring, T, ld, part_misc, 0, &nb2)))
+                    if ((rc = cmp_grad(s, p->cmp, prec, st, R, ytil[0], gring, dring, T, ld, part_misc, 0, &nb2, cs)))
                         break;
                 }
                 if ((rc = launch_init_finalize(s, st, part_misc, nb2, -1))) break;
@@ -585,11 +656,12 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
                 if ((rc = cmp_sddmm(s, p->cmp, prec, 1, R, dring[it % T], ld, nullptr, q1, q2, ytil[0], nullptr, 0.0,
                                     part_ls, st, &nls)))
                     break;
-                if ((rc = launch_ls_finalize(s, st, part_ls, nls, part_cb, ncb, LRSDP_COMPLETION))) break;
+                if ((rc = launch_ls_finalize(s, st, part_ls, nls, part_cb, ncb, LRSDP_COMPLETION, cs))) break;
                 if ((rc = cmp_samples(s, p->cmp, st, acon, q1, q2, y, ytil[0]))) break;
                 if ((rc = axpy_state(s, prec, st, R, dring[it % T], n, ld))) break;
                 if (o->profile) LRSDP_HIP_TRY(hipEventRecord(evs[2 * b], s));
-                if ((rc = cmp_grad(s, p->cmp, prec, st, R, ytil[0], gring, dring, T, ld, part_up, -1, &nup))) break;
+                if ((rc = cmp_grad(s, p->cmp, prec, st, R, ytil[0], gring, dring, T, ld, part_up, -1, &nup, cs)))
+                    break;
                 if (o->profile) LRSDP_HIP_TRY(hipEventRecord(evs[2 * b + 1], s));
                 if ((rc = launch_lbfgs_finalize(s, st, part_up, nup))) break;
                 if ((rc = launch_combine(s, prec, st, nullptr, basis, 2 * T + 1, nullptr, n, ld, part_cb, &ncb, shadow)))
@@ -607,13 +679,14 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
                 ls.q2 = q2;
                 ls.rn = rn;
                 ls.ld = ld;
+                ls.cs = cs;
                 ls.partials = part_ls;
                 ls.st = st;
                 int nls = 0;
                 if (o->profile) LRSDP_HIP_TRY(hipEventRecord(evs[2 * b], s));
                 if ((rc = spmm_maxcut(s, p->csr, bf ? LRSDP_F32_BF16IN : prec, ls, &nls))) break;
                 if (o->profile) LRSDP_HIP_TRY(hipEventRecord(evs[2 * b + 1], s));
-                if ((rc = launch_ls_finalize(s, st, part_ls, nls, part_cb, ncb, LRSDP_MAXCUT))) break;
+                if ((rc = launch_ls_finalize(s, st, part_ls, nls, part_cb, ncb, LRSDP_MAXCUT, 1.0))) break;
                 int nup = 0;
                 if ((rc = launch_update_maxcut(s, prec, st, R, CD, y, rn, q1, q2, ytil[it % 2], ytil[(it + 1) % 2],
                                                gring, dring, T, n, ld, part_up, &nup, pc)))
@@ -662,8 +735,14 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
             break;
         }
         if (hs.converged) {
-            status = LRSDP_OK;
-            break;
+            const int d = o->reopt ? reopt_check(hs) : 0;
+            if (d < 0) {
+                rc = d;
+                break;
+            }
+            if (d == 0) status = LRSDP_OK;
+            if (d != 2) break;
+            continue;
         }
         if (rank_cur < rank_cap && hs.k >= o->rank_trigger) {
             // dynamic rank: the subproblem just solved took rank_trigger L-BFGS
@@ -707,7 +786,7 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
                     break;
                 const void *rb[1] = {Ravg};
                 if ((rc = launch_dots(s, prec, Ravg, rb, 1, n, ld, part_misc + (size_t)nb1 * kMaxSums, &nb2))) break;
-                if ((rc = launch_alm_finalize(s, st, part_misc, nb1 + nb2, 0))) break;
+                if ((rc = launch_alm_finalize(s, st, part_misc, nb1 + nb2, 0, 1.0))) break;
                 if ((rc = read_state(c, &hs))) break;
                 if (o->verbose)
                     fprintf(stderr, "[lrsdp] admm %6lld obj % .10e err1 %.3e err3 % .3e t %.3fs\n", (long long)it2,
@@ -716,7 +795,7 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
                     diverged = true;
                     break;
                 }
-                if (hs.err1 <= o->tol && std::fabs(hs.err3) <= o->tol) {
+                if (hs.err1 <= o->tol && (o->reopt || std::fabs(hs.err3) <= o->tol)) {
                     done2 = true;
                     break;
                 }
@@ -732,8 +811,14 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
             if (rc) break;
             if (done2) {
                 LRSDP_HIP_TRY(hipMemcpyAsync(R, Ravg, bytes, hipMemcpyDeviceToDevice, s));
-                status = LRSDP_OK;
-                break;
+                const int d = o->reopt ? reopt_check(hs) : 0;
+                if (d < 0) {
+                    rc = d;
+                    break;
+                }
+                if (d == 0) status = LRSDP_OK;
+                if (d != 2) break;
+                continue;
             }
             if (elapsed() > o->time_limit_s && !diverged) {
                 LRSDP_HIP_TRY(hipMemcpyAsync(R, Ravg, bytes, hipMemcpyDeviceToDevice, s));
@@ -780,7 +865,7 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
                 ref.partials = part_misc;
                 int np = 0;
                 if ((rc = spmm_maxcut(s, p->csr, prec, ref, &np))) break;
-                if ((rc = launch_alm_finalize(s, st, part_misc, np, 0))) break;
+                if ((rc = launch_alm_finalize(s, st, part_misc, np, 0, 1.0))) break;
                 if ((rc = read_state(c, &hs))) break;
                 if (o->verbose)
                     fprintf(stderr, "[lrsdp] admm %6lld obj % .10e err1 %.3e err3 % .3e t %.3fs\n", (long long)it2,
@@ -789,7 +874,7 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
                     diverged = true;
                     break;
                 }
-                if (hs.err1 <= o->tol && std::fabs(hs.err3) <= o->tol) {
+                if (hs.err1 <= o->tol && (o->reopt || std::fabs(hs.err3) <= o->tol)) {
                     done2 = true;
                     break;
                 }
@@ -799,8 +884,14 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
             if (rc) break;
             if (done2) {
                 LRSDP_HIP_TRY(hipMemcpyAsync(R, gring[1], bytes, hipMemcpyDeviceToDevice, s));
-                status = LRSDP_OK;
-                break;
+                const int d = o->reopt ? reopt_check(hs) : 0;
+                if (d < 0) {
+                    rc = d;
+                    break;
+                }
+                if (d == 0) status = LRSDP_OK;
+                if (d != 2) break;
+                continue;
             }
             if (elapsed() > o->time_limit_s && !diverged) {
                 LRSDP_HIP_TRY(hipMemcpyAsync(R, gring[1], bytes, hipMemcpyDeviceToDevice, s));
@@ -826,13 +917,18 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
     if (rc < 0) return rc;
     SolverState hs{};
     if ((rc = read_state(c, &hs))) return rc;
+    // back to the original problem after re-optimisation rounds: objective,
+    // multipliers and penalty divided by cs (L for cs C equals cs times L for C
+    // with y / cs and sigma / cs)
+    if (cs != 1.0 && (rc = launch_dscale(s, y, 1.0 / cs, p->info.m))) return rc;
+    LRSDP_HIP_TRY(hipStreamSynchronize(s));
     std::memset(res, 0, sizeof(*res));
-    res->obj = hs.obj;
-    res->dual = hs.dual;
+    res->obj = hs.obj / cs;
+    res->dual = hs.dual / cs;
     res->err1 = hs.err1;
     res->err1_inf = hs.err1_inf;
-    res->err3 = hs.err3;
-    res->sigma = hs.sigma;
+    res->err3 = (hs.obj - hs.dual) / (cs + std::fabs(hs.obj) + std::fabs(hs.dual));
+    res->sigma = hs.sigma / cs;
     res->seconds = elapsed();
     res->outer = std::min<int64_t>(outer, o->max_outer);
     res->inner = hs.inner_total;
@@ -843,6 +939,8 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
     res->admm_iters = admm_iters;
     res->admm_fallbacks = admm_fallbacks;
     res->rank_final = rank_cur;
+    res->reopt_rounds = reopt_rounds;
+    res->err2 = err2;
     return status;
 }
 

@@ -233,9 +233,9 @@ __device__ void two_loop_coef_pc(SolverState &st) {
 // Line-search stage: fold the previous combine pass's dots into the Gram
 // matrix, form a1..a4 and take the exact step.
 // kind: LRSDP_MAXCUT (p2 summed by the SpMM epilogue) or LRSDP_COMPLETION
-// (C = I, so p2 = <C, D D^T> = ||D||_F^2, a Gram entry).
+// (C = cs I, so p2 = <C, D D^T> = cs ||D||_F^2, from a Gram entry).
 __global__ __launch_bounds__(kBlock) void k_ls_finalize(SolverState *gst, const double *ls_part, int n_ls,
-                                                        const double *cb_part, int n_cb, int kind) {
+                                                        const double *cb_part, int n_cb, int kind, double cs) {
     __shared__ SolverState st;
     __shared__ double ls[kLsSums];
     __shared__ double cb[kMaxBasis + 1];
@@ -256,7 +256,7 @@ __global__ __launch_bounds__(kBlock) void k_ls_finalize(SolverState *gst, const 
         const double sigma = st.sigma;
         const double a1 = 0.5 * sigma * ls[3];
         const double a2 = sigma * ls[4];
-        const double p2 = kind == LRSDP_COMPLETION ? M[dcol * kMaxBasis + dcol] : ls[0];
+        const double p2 = kind == LRSDP_COMPLETION ? cs * M[dcol * kMaxBasis + dcol] : ls[0];
         const double a3 = p2 - ls[1] + 0.5 * sigma * ls[5];
         const double a4 = M[st.gk * kMaxBasis + dcol];
         st.a[0] = a1;
@@ -355,7 +355,7 @@ __global__ __launch_bounds__(kBlock) void k_init_finalize(SolverState *gst, cons
         if (!restart) {
             st.k = 0;
             st.max_inner = k_limit;
-            st.target = st.eta * fmax(1.0, st.gnorm);
+            st.target = st.eta * fmax(st.gfloor, st.gnorm);
         }
         k_limit = st.max_inner - st.k;
         for (int j = 0; j < kMaxBasis; ++j) st.coef[j] = 0.0;
@@ -376,14 +376,16 @@ __global__ __launch_bounds__(kBlock) void k_init_finalize(SolverState *gst, cons
 
 // ALM step: measures after the multiplier update, stop test, penalty and
 // inner-tolerance schedules.  mode 0: initial point (no schedule update).
+// obj_scale multiplies the first sum: the objective of a completion problem
+// with C = cs I arrives as ||R||_F^2 (MaxCut's SpMM already applies cs).
 __global__ __launch_bounds__(kBlock) void k_alm_finalize(SolverState *gst, const double *part, int n_part,
-                                                         int mode) {
+                                                         int mode, double obj_scale) {
     __shared__ SolverState st;
     __shared__ double rs[3];
     block_copy(&st, gst);
     reduce_rows<3>(part, n_part, rs);
     if (threadIdx.x == 0) {
-        const double obj = rs[0], dual = rs[1];
+        const double obj = obj_scale * rs[0], dual = rs[1];
         const double res_norm = sqrt(fmax(rs[2], 0.0));
         st.obj = obj;
         st.dual = dual;
@@ -394,7 +396,7 @@ __global__ __launch_bounds__(kBlock) void k_alm_finalize(SolverState *gst, const
         if (!isfinite(obj) || !isfinite(dual) || !isfinite(res_norm)) st.numeric = 1;
         st.refreshes += 1;
         if (mode != 0) {
-            st.converged = (st.err1 <= st.tol && fabs(st.err3) <= st.tol) ? 1 : 0;
+            st.converged = (st.err1 <= st.tol && (st.stop_rule == 1 || fabs(st.err3) <= st.tol)) ? 1 : 0;
             if (!st.converged) {
                 if (st.err1 > st.feas_decrease * st.err1_prev)
                     st.sigma = fmin(st.sigma * st.sigma_factor, st.sigma_cap);
@@ -599,7 +601,8 @@ __global__ __launch_bounds__(kBlock) void k_update_maxcut_pc(UpdateArgs<S> a, Pc
         const double rho0 = group_sum<GS>(vdot(rn_s, b0));
         const double rho1 = group_sum<GS>(vdot(rn_s, b1));
         const double rho2 = T >= 2 ? group_sum<GS>(vdot(rn_s, b2)) : 0.0;
-        const double h = pc.mode == 2 ? 2.0 * fmax(pc.diag[row] - ynew, 0.005 * pc.hrow[row]) : pc.hrow[row];
+        const double hs = pc.cs * pc.hrow[row];
+        const double h = pc.mode == 2 ? 2.0 * fmax(pc.cs * pc.diag[row] - ynew, 0.005 * hs) : hs;
         const double w = 1.0 / h;
         const double kap = 4.0 * sigma / (h + 4.0 * sigma * rnn);
         const double wk = lane == 0 ? w * kap : 0.0;
@@ -708,7 +711,7 @@ __global__ __launch_bounds__(kBlock) void k_combine(CombineArgs<S> a) {
                 }
             }
             const D4 r = widen(reinterpret_cast<const CV *>(a.R)[c]);
-            const double hi = 1.0 / (a.pc.mode == 2 ? a.pc.hdyn[row] : a.pc.hrow[row]), kr = a.pc.kap[row] * ra;
+            const double hi = 1.0 / (a.pc.mode == 2 ? a.pc.hdyn[row] : a.pc.cs * a.pc.hrow[row]), kr = a.pc.kap[row] * ra;
 #pragma unroll
             for (int e = 0; e < 4; ++e) acc.v[e] = fma(hi, accg.v[e] - kr * r.v[e], acc.v[e]);
         } else {
@@ -787,8 +790,8 @@ __global__ __launch_bounds__(kBlock) void k_grad_init_maxcut(GradInitArgs<S> a) 
             // row-block H0: R_i . G_i for G slot 0 and kap_i at the current R
             const double rho = group_sum<GS>(vdot(rs, gs));
             if (lane == 0) {
-                const double h = a.pc.mode == 2 ? 2.0 * fmax(a.pc.diag[row] - yt, 0.005 * a.pc.hrow[row])
-                                                 : a.pc.hrow[row];
+                const double hs = a.pc.cs * a.pc.hrow[row];
+                const double h = a.pc.mode == 2 ? 2.0 * fmax(a.pc.cs * a.pc.diag[row] - yt, 0.005 * hs) : hs;
                 if (a.pc.mode == 2) a.pc.hdyn[row] = h;
                 a.pc.rho[row] = rho;
                 a.pc.kap[row] = 4.0 * sigma / (h + 4.0 * sigma * a.rn[row]);
@@ -825,6 +828,12 @@ __global__ __launch_bounds__(kBlock) void k_rank_grow(S *R, int64_t n, int64_t l
         const double z = sqrt(-2.0 * log(u0)) * cos(6.283185307179586 * u1);
         R[i * ld + c] = (S)(scale * z);
     }
+}
+
+// x <- a x elementwise (float64 vectors)
+__global__ __launch_bounds__(kBlock) void k_dscale(double *x, double a, int64_t count) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += (int64_t)gridDim.x * kBlock)
+        x[i] *= a;
 }
 
 // out = (a + b) / 2 elementwise
@@ -875,8 +884,8 @@ static int grid_for(int64_t work_items, int per_block) {
 static int chunks_per_row(int prec, int64_t ld) { return (int)(ld * (prec == LRSDP_F64 ? 8 : 4) / 16); }
 
 int launch_ls_finalize(hipStream_t s, SolverState *st, const double *ls, int nls, const double *cb, int ncb,
-                       int kind) {
-    hipLaunchKernelGGL(k_ls_finalize, dim3(1), dim3(kBlock), 0, s, st, ls, nls, cb, ncb, kind);
+                       int kind, double cs) {
+    hipLaunchKernelGGL(k_ls_finalize, dim3(1), dim3(kBlock), 0, s, st, ls, nls, cb, ncb, kind, cs);
     LRSDP_CHECK_LAUNCH();
     return LRSDP_OK;
 }
@@ -893,8 +902,8 @@ int launch_init_finalize(hipStream_t s, SolverState *st, const double *part, int
     return LRSDP_OK;
 }
 
-int launch_alm_finalize(hipStream_t s, SolverState *st, const double *part, int np, int mode) {
-    hipLaunchKernelGGL(k_alm_finalize, dim3(1), dim3(kBlock), 0, s, st, part, np, mode);
+int launch_alm_finalize(hipStream_t s, SolverState *st, const double *part, int np, int mode, double obj_scale) {
+    hipLaunchKernelGGL(k_alm_finalize, dim3(1), dim3(kBlock), 0, s, st, part, np, mode, obj_scale);
     LRSDP_CHECK_LAUNCH();
     return LRSDP_OK;
 }
@@ -961,7 +970,7 @@ int launch_combine(hipStream_t s, int prec, SolverState *st, const double *coef,
                    const PcBufs *pc) {
     const int64_t nch = n * ld * (prec == LRSDP_F64 ? 8 : 4) / 16;
     *nblk = grid_for(nch, kBlock);
-    const PcBufs p = pc ? *pc : PcBufs{nullptr, nullptr, nullptr, n, 0, nullptr, nullptr};
+    const PcBufs p = pc ? *pc : PcBufs{nullptr, nullptr, nullptr, n, 0, nullptr, nullptr, 1.0};
     if (prec == LRSDP_F64) {
         CombineArgs<double> a{st, coef, {}, nb, (double *)out, nch, partials, nullptr, ld, ld, (const double *)R, p};
         for (int j = 0; j < nb; ++j) a.basis[j] = (const double *)basis[j];
@@ -984,7 +993,7 @@ int launch_grad_init_maxcut(hipStream_t s, int prec, SolverState *st, const void
     const int cpr = chunks_per_row(prec, ld);
     const int gs = cpr <= 4 ? 4 : (cpr <= 8 ? 8 : 16);
     *nblk = grid_for(n, kBlock / gs);
-    const PcBufs p = pc ? *pc : PcBufs{nullptr, nullptr, nullptr, n, 0, nullptr, nullptr};
+    const PcBufs p = pc ? *pc : PcBufs{nullptr, nullptr, nullptr, n, 0, nullptr, nullptr, 1.0};
     if (prec == LRSDP_F64) {
         GradInitArgs<double> a{st, (const double *)R, (const double *)CR, y, rn, ytil, (double *)G, n, ld, partials,
                                p};
@@ -1009,6 +1018,13 @@ int launch_rank_grow(hipStream_t s, int prec, void *R, int64_t n, int64_t ld, in
         hipLaunchKernelGGL(k_rank_grow<double>, dim3(nb), dim3(kBlock), 0, s, (double *)R, n, ld, c0, c1, seed, scale);
     else
         hipLaunchKernelGGL(k_rank_grow<float>, dim3(nb), dim3(kBlock), 0, s, (float *)R, n, ld, c0, c1, seed, scale);
+    LRSDP_CHECK_LAUNCH();
+    return LRSDP_OK;
+}
+
+int launch_dscale(hipStream_t s, double *x, double a, int64_t count) {
+    if (count <= 0) return LRSDP_OK;
+    hipLaunchKernelGGL(k_dscale, dim3(grid_for(count, kBlock)), dim3(kBlock), 0, s, x, a, count);
     LRSDP_CHECK_LAUNCH();
     return LRSDP_OK;
 }

@@ -123,7 +123,12 @@ __device__ __forceinline__ void epilogue(const DevCsr &P, const SpmmArgs &a, int
                                          typename Chunk<S>::V (&acc)[NC], double (&s)[kLsSums]) {
     using CV = typename Chunk<S>::V;
     constexpr int NV = Chunk<S>::N;
-    const S dg = (S)P.diag[row];
+    // operator cs C: the gathered off-diagonal sum and the diagonal both take the
+    // objective scale (cs = 1 leaves every value unchanged)
+    const S cs = (S)a.cs;
+#pragma unroll
+    for (int q = 0; q < NC; ++q) vscale(acc[q], cs);
+    const S dg = (S)(a.cs * P.diag[row]);
     const CV zero = vzero(CV{});
     int64_t off[NC];
     bool act[NC];
@@ -144,7 +149,7 @@ __device__ __forceinline__ void epilogue(const DevCsr &P, const SpmmArgs &a, int
             if (active) load_nbr<S, NC>(a.V, row, a.ldv, lane, v);
         }
         S shift = dg;
-        if (a.ytil) shift = (S)((double)P.diag[row] - a.ytil[row]);
+        if (a.ytil) shift = (S)(a.cs * P.diag[row] - a.ytil[row]);
 #pragma unroll
         for (int q = 0; q < NC; ++q) {
             vfma(acc[q], shift, v[q]);

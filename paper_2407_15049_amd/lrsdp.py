@@ -45,6 +45,7 @@ class Options(C.Structure):
         ("profile", C.c_int), ("verbose", C.c_int), ("phase2", C.c_int), ("switch_err1", C.c_double),
         ("admm_check", C.c_int), ("max_admm", C.c_int), ("precond", C.c_int),
         ("rank_max", C.c_int), ("rank_trigger", C.c_int), ("rank_scale", C.c_double), ("rank_seed", C.c_int64),
+        ("reopt", C.c_int), ("reopt_factor", C.c_double), ("max_reopt", C.c_int), ("cert_iters", C.c_int),
     ]
 
 
@@ -55,6 +56,7 @@ class Result(C.Structure):
         ("outer", C.c_int64), ("inner", C.c_int64), ("status", C.c_int),
         ("spmm_launches", C.c_int), ("spmm_ms", C.c_double), ("spmm_bytes", C.c_double),
         ("admm_iters", C.c_int64), ("admm_fallbacks", C.c_int64), ("rank_final", C.c_int64),
+        ("reopt_rounds", C.c_int64), ("err2", C.c_double),
     ]
 
     def as_dict(self):

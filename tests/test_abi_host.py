@@ -144,3 +144,18 @@ def test_precond_option_validation():
     with pytest.raises(L.LrsdpError) as e:
         L.workspace_bytes(c, L.default_options(prec=L.F64, rank=4, ld=4, precond=1))
     assert e.value.code == L.EUNSUPPORTED
+
+
+def test_reopt_option_validation():
+    u, v = erdos_renyi_edges(50, 120, 1)
+    p = L.Problem.maxcut(50, u, v)
+    for bad in (dict(reopt=3), dict(reopt=1, reopt_factor=1.0), dict(reopt=1, reopt_factor=0.0),
+                dict(reopt=1, max_reopt=-1), dict(reopt=2, cert_iters=0)):
+        with pytest.raises(L.LrsdpError) as e:
+            L.workspace_bytes(p, L.default_options(prec=L.F64, rank=4, ld=4, **bad))
+        assert e.value.code == L.EINVAL, bad
+    base = L.workspace_bytes(p, L.default_options(prec=L.F64, rank=4, ld=4))
+    assert L.workspace_bytes(p, L.default_options(prec=L.F64, rank=4, ld=4, reopt=1)) == base
+    # strict level: the multipliers of the original problem and the certificate's workspace
+    cert = L.certify_workspace_bytes(p, 300)
+    assert L.workspace_bytes(p, L.default_options(prec=L.F64, rank=4, ld=4, reopt=2)) >= base + cert + 50 * 8

@@ -1,0 +1,176 @@
+"""GPU re-optimisation (Section 4.1) against the oracle.
+
+Each case runs the library's solve with reopt = 1 or 2 and the oracle's
+reopt_solve on the same seeded inputs.  Both must take the same number of
+rounds and ALM steps.  The objectives must agree to 1e-6 relative: both sides
+follow the same path, and the L-BFGS counts differ only through rounding.  The
+library's reported measures must equal the oracle's recomputation from the
+returned R and y on the original problem.  The strict level's err2 comes from
+the GPU certificate's lower bound lambda_min - resid on one side and a dense
+eigensolver on the other; the two agree to within the certificate's residual
+target of 0.1 tol.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import kernels as K
+from oracle.alm import Options as OOptions
+from oracle.alm import alm_solve
+from oracle.problem import completion_problem, maxcut_problem
+from synth import chung_lu_edges, completion_instance, erdos_renyi_edges, init_factor, pm1_weights
+
+from paper_2407_15049_amd import lrsdp as L
+from gpu_util import dev_factor, host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return L.Context(0)
+
+
+def print_case(**kw):
+    print("CASE", kw, flush=True)
+
+
+def maxcut_case(case):
+    if case == "cl2k":                 # round 0 ends with |err3| = 1.4e-4: one more round
+        u, v = chung_lu_edges(2000, 8000, 2.5, 77)
+        return 2000, u, v, pm1_weights(8000, 3), init_factor(2000, 8, 5)
+    if case == "er200_rank2":          # rank-2 stationary point, lambda_min < -0.1
+        u, v = erdos_renyi_edges(200, 800, 5)
+        return 200, u, v, None, init_factor(200, 2, 8)
+    if case == "er_1k":                # round 0 already meets |err3| <= tol
+        u, v = erdos_renyi_edges(1000, 5000, 15049)
+        return 1000, u, v, None, init_factor(1000, 10, 15050)
+    raise KeyError(case)
+
+
+def solve(ctx, prob, R0, prec, m, **kw):
+    import torch
+    r = R0.shape[1]
+    opts = L.default_options(prec=prec, rank=r, ld=L.padded_ld(r, L.F64 if prec == L.F64 else L.F32), **kw)
+    Rd = dev_factor(R0, prec)
+    yd = torch.zeros(m, dtype=torch.float64, device="cuda")
+    rc, res = L.solve(ctx, prob, Rd, yd, opts)
+    torch.cuda.synchronize()
+    return rc, res, host(Rd, r), yd.cpu().numpy()
+
+
+def check_reported(op, res, R, y):
+    m = K.alm_measures(op, R, y)
+    assert abs(m["obj"] - res.obj) <= 1e-10 * abs(res.obj)
+    assert abs(m["dual"] - res.dual) <= 1e-10 * abs(res.dual)
+    assert abs(m["err3"] - res.err3) <= 1e-9 * (1 + abs(res.obj))
+    assert abs(m["err1"] - res.err1) <= 1e-10 + 1e-8 * res.err1
+    return m
+
+
+@pytest.mark.parametrize("case,level", [("cl2k", 1), ("cl2k", 2), ("er_1k", 1)])
+def test_maxcut_reopt_matches_oracle(ctx, case, level):
+    n, u, v, w, R0 = maxcut_case(case)
+    print_case(test="reopt", case=case, level=level)
+    prob = L.Problem.maxcut(n, u, v, w).upload(ctx)
+    op = maxcut_problem(n, u, v, w)
+    rc, res, R, y = solve(ctx, prob, R0, L.F64, n, reopt=level)
+    ores = alm_solve(op, R0, opts=OOptions(reopt=level))
+    print(res.as_dict(), "oracle", ores.obj, ores.outer, ores.inner, ores.reopt_rounds, ores.err2)
+    assert rc == L.OK and ores.converged
+    assert res.reopt_rounds == ores.reopt_rounds and res.outer == ores.outer
+    assert abs(res.obj - ores.obj) <= 1e-6 * abs(ores.obj)
+    m = check_reported(op, res, R, y)
+    assert m["err1"] <= 1e-5 and abs(m["err3"]) <= 1e-5
+    if level == 2:
+        assert abs(res.err2 - ores.err2) <= 0.1e-5 + 1e-9
+        assert res.err2 >= ores.err2 - 1e-12          # from a lower bound on lambda_min
+    else:
+        assert np.isnan(res.err2)
+    if case == "cl2k":
+        assert res.reopt_rounds >= 1
+
+
+def test_strict_reopt_reports_not_converged(ctx):
+    n, u, v, w, R0 = maxcut_case("er200_rank2")
+    print_case(test="reopt_strict", case="er200_rank2")
+    prob = L.Problem.maxcut(n, u, v, w).upload(ctx)
+    op = maxcut_problem(n, u, v, w)
+    rc, res, R, y = solve(ctx, prob, R0, L.F64, n, reopt=2, max_reopt=3)
+    ores = alm_solve(op, R0, opts=OOptions(reopt=2, max_reopt=3))
+    print(res.as_dict(), "oracle", ores.err2, ores.reopt_rounds)
+    assert rc == L.NOT_CONVERGED and not ores.converged
+    assert res.reopt_rounds == ores.reopt_rounds == 3
+    assert res.err2 > 1e-5
+    assert abs(res.err2 - ores.err2) <= 0.1e-5 + 1e-6 * ores.err2
+    check_reported(op, res, R, y)
+    # the mild level accepts the same point at once
+    rc1, res1, _, _ = solve(ctx, prob, R0, L.F64, n, reopt=1)
+    assert rc1 == L.OK and res1.reopt_rounds == 0
+
+
+def test_completion_reopt_matches_oracle(ctx):
+    # round 0 ends with |err3| = 1.9e-5, round 1 with 1.1e-6; no subproblem
+    # reaches max_inner (where the two sides' rounding would decide the count)
+    i, j, M, _, _ = completion_instance(60, 50, 3, 14, seed=8)
+    print_case(test="reopt", case="completion 60x50")
+    prob = L.Problem.completion(60, 50, i, j, M).upload(ctx)
+    op = completion_problem(60, 50, i, j, M)
+    R0 = init_factor(110, 5, 9)
+    rc, res, R, y = solve(ctx, prob, R0, L.F64, op.m, reopt=1)
+    ores = alm_solve(op, R0, opts=OOptions(reopt=1))
+    print(res.as_dict(), "oracle", ores.obj, ores.outer, ores.inner, ores.reopt_rounds)
+    assert rc == L.OK and ores.converged and ores.reopt_rounds == 1
+    assert res.reopt_rounds == ores.reopt_rounds and res.outer == ores.outer
+    assert abs(res.obj - ores.obj) <= 1e-6 * abs(ores.obj)
+    m = check_reported(op, res, R, y)
+    assert m["err1"] <= 1e-5 and abs(m["err3"]) <= 1e-5
+
+
+def test_reopt_with_row_block_h0_matches_oracle(ctx):
+    n, u, v, w, R0 = maxcut_case("cl2k")
+    print_case(test="reopt_precond", case="cl2k")
+    prob = L.Problem.maxcut(n, u, v, w).upload(ctx)
+    op = maxcut_problem(n, u, v, w)
+    rc, res, R, y = solve(ctx, prob, R0, L.F64, n, reopt=1, precond=1)
+    ores = alm_solve(op, R0, opts=OOptions(reopt=1, precond=1))
+    print(res.as_dict(), "oracle", ores.obj, ores.outer, ores.inner, ores.reopt_rounds)
+    assert rc == L.OK and ores.converged
+    assert res.reopt_rounds == ores.reopt_rounds and res.outer == ores.outer
+    assert abs(res.obj - ores.obj) <= 1e-6 * abs(ores.obj)
+    check_reported(op, res, R, y)
+
+
+def test_reopt_after_the_splitting_phase_matches_oracle(ctx):
+    # the splitting phase reaches err1 <= tol in 10 iterations with |err3| =
+    # 1.3e-5; a re-optimisation round follows
+    n, u, v, w, _ = maxcut_case("er_1k")
+    R0 = init_factor(n, 16, 15051)
+    print_case(test="reopt_phase2", case="er_1k rank 16")
+    prob = L.Problem.maxcut(n, u, v, w).upload(ctx)
+    op = maxcut_problem(n, u, v, w)
+    rc, res, R, y = solve(ctx, prob, R0, L.F64, n, reopt=1, phase2=1, switch_err1=1e-3)
+    ores = alm_solve(op, R0, opts=OOptions(reopt=1, phase2=True, switch_err1=1e-3))
+    print(res.as_dict(), "oracle", ores.obj, ores.outer, ores.inner, ores.reopt_rounds, ores.admm_iters)
+    assert rc == L.OK and ores.converged and ores.reopt_rounds == 1 and ores.admm_fallbacks == 0
+    assert res.reopt_rounds == ores.reopt_rounds and res.admm_iters == ores.admm_iters
+    assert res.admm_fallbacks == 0
+    assert abs(res.obj - ores.obj) <= 1e-6 * abs(ores.obj)
+    m = check_reported(op, res, R, y)
+    assert m["err1"] <= 1e-5 and abs(m["err3"]) <= 1e-5
+
+
+def test_reopt_f32(ctx):
+    n, u, v, w, R0 = maxcut_case("cl2k")
+    print_case(test="reopt_f32", case="cl2k")
+    prob = L.Problem.maxcut(n, u, v, w).upload(ctx)
+    op = maxcut_problem(n, u, v, w)
+    rc, res, R, y = solve(ctx, prob, R0, L.F32, n, reopt=1)
+    ores = alm_solve(op, R0, opts=OOptions(reopt=1))
+    print(res.as_dict(), "oracle", ores.obj)
+    assert rc == L.OK
+    m = K.alm_measures(op, R, y)
+    assert m["err1"] <= 1e-5 and abs(m["err3"]) <= 1e-5
+    assert abs(m["obj"] - ores.obj) <= 1e-4 * abs(ores.obj)
