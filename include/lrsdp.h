@@ -65,6 +65,7 @@ extern "C" {
 /* ---- problem kinds --------------------------------------------------------- */
 #define LRSDP_MAXCUT       1
 #define LRSDP_COMPLETION   2
+#define LRSDP_GENERAL      3
 
 typedef struct lrsdp_ctx lrsdp_ctx;
 typedef struct lrsdp_problem lrsdp_problem;
@@ -104,10 +105,30 @@ int lrsdp_problem_completion(int64_t n1, int64_t n2, int64_t m,
                              const int32_t *i, const int32_t *j,
                              const double *Mij, lrsdp_problem **out);
 
+/* General single-block problem: min <C, X> s.t. <A_k, X> = b_k (k < m), X psd
+ * of order n, with sparse symmetric C and A_k given as triplets (host arrays).
+ * C: c_nnz entries (c_row[t], c_col[t], c_val[t]); A: a_nnz entries
+ * (a_con[t], a_row[t], a_col[t], a_val[t]) of constraint a_con[t].  Each
+ * off-diagonal entry is given once, in either triangle, and stands for both
+ * (r, c) and (c, r); repeated positions are summed.  The build compresses the
+ * stacked constraint matrix to its nonzero columns (positions of the upper
+ * triangle) and keeps the union Omega of those positions with the nonzeros of
+ * C (Section 3.4): <A_k, X> = sum over a < b of A_k,ab (X_ab + X_ba) plus
+ * sum_a A_k,aa X_aa, and the solve applies C - A*(y) as one sparse matrix on
+ * Omega.  Rejects (EINVAL) indices out of range, non-finite values, and
+ * n or |Omega| beyond int32.  The row-block H0, the splitting phase, the
+ * warm start and the certificate are not available for this kind
+ * (EUNSUPPORTED).
+ */
+int lrsdp_problem_general(int64_t n, int64_t c_nnz, const int32_t *c_row, const int32_t *c_col,
+                          const double *c_val, int64_t m, int64_t a_nnz, const int32_t *a_con,
+                          const int32_t *a_row, const int32_t *a_col, const double *a_val,
+                          const double *b, lrsdp_problem **out);
+
 void lrsdp_problem_destroy(lrsdp_problem *prob);
 
 typedef struct {
-    int     kind;        /* LRSDP_MAXCUT or LRSDP_COMPLETION                     */
+    int     kind;        /* LRSDP_MAXCUT, LRSDP_COMPLETION or LRSDP_GENERAL      */
     int64_t n;           /* order of X                                           */
     int64_t m;           /* number of constraints                                */
     int64_t nnz;         /* stored off-diagonal nonzeros of the SpMM operator    */
@@ -269,8 +290,10 @@ int lrsdp_k_spmm(lrsdp_ctx *ctx, const lrsdp_problem *prob, int prec,
                  const void *V, int64_t ld, const double *ytil, void *Y);
 
 /* out[k] = <A_k, U V^T> (m float64): the compressed outer product of Section
- * 3.4 (MaxCut: row dot U_i.V_i; completion: 2 U_i . V_{n1+j}).  V may be NULL
- * (then V = U). */
+ * 3.4 (MaxCut: row dot U_i.V_i; completion: 2 U_i . V_{n1+j}; general: the
+ * stacked constraint matrix times the outer products at the positions of
+ * Omega).  V may be NULL (then V = U).  General problems use scratch inside
+ * the problem's device memory: calls on one problem must not overlap. */
 int lrsdp_k_constraint(lrsdp_ctx *ctx, const lrsdp_problem *prob, int prec,
                        const void *U, const void *V, int64_t ld, double *out);
 

@@ -108,3 +108,29 @@ def completion_problem(n1: int, n2: int, i, j, Mij) -> SDPProblem:
     C = sp.identity(n, format="csr")
     return SDPProblem(n=n, m=m, C=C, col_a=col_a, col_b=col_b, Abar=Abar,
                       b=2.0 * np.asarray(Mij, dtype=np.float64), kind="completion")
+
+
+def general_problem(n: int, c_row, c_col, c_val, m: int, a_con, a_row, a_col, a_val, b) -> SDPProblem:
+    """min <C, X> s.t. <A_k, X> = b_k (k < m), X psd of order n (the paper's
+    problem, eq. prob:sdp, with one block), from triplets of symmetric C and A_k:
+    an off-diagonal triplet (r, c, v), r != c, is the pair of entries (r, c)
+    and (c, r), both v; repeated triplets add up.  The constraint map is the
+    plain inner product <A_k, X> = sum_ab A_k[a, b] X[a, b] over the full
+    matrix (both triangles), stacked as in Section 3.3."""
+    c_row = np.asarray(c_row, dtype=np.int64)
+    c_col = np.asarray(c_col, dtype=np.int64)
+    c_val = np.asarray(c_val, dtype=np.float64)
+    off = c_row != c_col
+    C = sp.csr_matrix((np.concatenate([c_val, c_val[off]]),
+                       (np.concatenate([c_row, c_col[off]]), np.concatenate([c_col, c_row[off]]))), shape=(n, n))
+    C.sum_duplicates()
+    a_con = np.asarray(a_con, dtype=np.int64)
+    a_row = np.asarray(a_row, dtype=np.int64)
+    a_col = np.asarray(a_col, dtype=np.int64)
+    a_val = np.asarray(a_val, dtype=np.float64)
+    off = a_row != a_col
+    col_a, col_b, Abar = _stack_constraints(
+        n, m, np.concatenate([a_con, a_con[off]]), np.concatenate([a_row, a_col[off]]),
+        np.concatenate([a_col, a_row[off]]), np.concatenate([a_val, a_val[off]]))
+    return SDPProblem(n=n, m=m, C=C, col_a=col_a, col_b=col_b, Abar=Abar,
+                      b=np.asarray(b, dtype=np.float64), kind="general")

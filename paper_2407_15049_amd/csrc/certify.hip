@@ -479,6 +479,7 @@ int apply_s(hipStream_t s, const lrsdp_problem *p, const double *V, const double
         int np = 0;
         return spmm_maxcut(s, p->csr, LRSDP_F64, a, &np);
     }
+    if (p->info.kind == LRSDP_GENERAL) return spmm_general(s, p->gen, LRSDP_F64, V, kCB, y, Y);
     return spmm_completion(s, p->cmp, LRSDP_F64, V, kCB, y, Y);
 }
 
@@ -522,7 +523,8 @@ extern "C" int lrsdp_certify(lrsdp_ctx *c, const lrsdp_problem *p, const double 
 
     LRSDP_HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int), s));
     const bool mc = p->info.kind == LRSDP_MAXCUT;
-    hipLaunchKernelGGL(k_cert_by, dim3(1), dim3(kBlock), 0, s, mc ? nullptr : p->cmp.b, y, p->info.m, by);
+    const double *bvec = mc ? nullptr : (p->info.kind == LRSDP_GENERAL ? p->gen.b : p->cmp.b);
+    hipLaunchKernelGGL(k_cert_by, dim3(1), dim3(kBlock), 0, s, bvec, y, p->info.m, by);
     LRSDP_CHECK_LAUNCH();
     // start block: random, orthonormalised by Cholesky QR applied twice
     hipLaunchKernelGGL(k_cert_random, dim3(g), dim3(kBlock), 0, s, Wb, n * kCB, seed);
@@ -591,7 +593,8 @@ extern "C" int lrsdp_certify(lrsdp_ctx *c, const lrsdp_problem *p, const double 
     out->by = hby;
     out->err2 = std::max(0.0, -theta) / (1.0 + p->info.c_l1);
     if (mc) out->dual_bound = hby + (double)n * std::min(0.0, out->lambda_lb);
-    else out->dual_bound = hby / std::max(1.0, 1.0 - out->lambda_lb);
+    else if (p->info.kind == LRSDP_COMPLETION) out->dual_bound = hby / std::max(1.0, 1.0 - out->lambda_lb);
+    else out->dual_bound = NAN;   // needs a bound on trace X, which a general problem does not state
     out->iters = done;
     out->status = status;
     out->block = kCB;

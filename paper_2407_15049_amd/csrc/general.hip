@@ -1,0 +1,338 @@
+// General problems: the compressed linear map of Section 3.4 on the GPU.
+//
+// Omega holds the positions (a, b), a <= b, that are nonzero in C or in some
+// A_k.  The constraint map runs in two passes:
+//   k_gen_xbar  one lane group per position: the compressed outer product
+//               xbar_o = X_ab + X_ba (a < b) or X_aa for X = U V^T (the
+//               paper's CompressedOuterProduct, over every position of Omega
+//               so that the C-weighted sums of the objective and the line
+//               search come out of the same pass);
+//   k_gen_cons  one thread per constraint: its row of the stacked matrix
+//               (nonzero columns only) times xbar, plus the line-search or
+//               ALM row terms.
+// The operator C - A*(y) is applied by k_gen_spmm on the symmetric pattern of
+// Omega; the value of each stored entry, cs C_o - sum_k A_k,o y_k, is formed
+// on the fly from the transposed stacked matrix (eq. At with the index set
+// Omega), so no n x n or |Omega| buffer is written per call.
+#include <algorithm>
+
+#include "device.h"
+#include "kernels.h"
+
+namespace lrsdp {
+namespace {
+
+int gen_grid(int64_t items, int per_block) {
+    const int64_t need = (items + per_block - 1) / per_block;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(need, kMaxBlocks));
+}
+
+enum { kGenA = 0, kGenLS = 1, kGenRefresh = 2 };
+
+template <typename S>
+struct XbarArgs {
+    const S *U;
+    const S *V;         // kGenA: V; kGenLS: D (U = R); kGenRefresh: unused (U = R)
+    int64_t ld;
+    double *x1, *x2;    // per position: A: xbar(U V^T); LS: xbar(RD^T + DR^T), xbar(DD^T); refresh: xbar(RR^T)
+    double cs;          // objective scale
+    double *partials;   // LS: s[0] = <C, DD^T>, s[6] = <C, RD^T + DR^T>; refresh: s[0] = <C, RR^T>
+    const SolverState *st;
+};
+
+template <typename S, int GS, int MODE>
+__global__ __launch_bounds__(kBlock) void k_gen_xbar(DevGeneral P, XbarArgs<S> a) {
+    using CV = typename Chunk<S>::V;
+    constexpr int NV = Chunk<S>::N;
+    constexpr int GPB = kBlock / GS;
+    if (a.st && a.st->done) return;
+    const int lane = threadIdx.x % GS, grp = threadIdx.x / GS;
+    const bool active = lane * NV < a.ld;
+    const CV zero = vzero(CV{});
+    double s[kLsSums] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int64_t o = (int64_t)blockIdx.x * GPB + grp; o < P.nom; o += (int64_t)gridDim.x * GPB) {
+        const int32_t ia = P.om_a[o], ib = P.om_b[o];
+        // a diagonal position counts X_aa once: half of the symmetric formula
+        const double w = ia == ib ? 0.5 : 1.0;
+        const int64_t ra = (int64_t)ia * a.ld + lane * NV, rb = (int64_t)ib * a.ld + lane * NV;
+        const CV ua = active ? *reinterpret_cast<const CV *>(a.U + ra) : zero;
+        const CV ub = active ? *reinterpret_cast<const CV *>(a.U + rb) : zero;
+        if constexpr (MODE == kGenRefresh) {
+            const double x = w * 2.0 * group_sum<GS>(vdot(ua, ub));
+            if (lane == 0) {
+                a.x1[o] = x;
+                s[0] += a.cs * P.cval[o] * x;
+            }
+        } else {
+            const CV va = active ? *reinterpret_cast<const CV *>(a.V + ra) : zero;
+            const CV vb = active ? *reinterpret_cast<const CV *>(a.V + rb) : zero;
+            if constexpr (MODE == kGenA) {
+                const double x = w * group_sum<GS>(vdot(ua, vb) + vdot(ub, va));
+                if (lane == 0) a.x1[o] = x;
+            } else {
+                const double q1 = w * 2.0 * group_sum<GS>(vdot(ua, vb) + vdot(ub, va));
+                const double q2 = w * 2.0 * group_sum<GS>(vdot(va, vb));
+                if (lane == 0) {
+                    a.x1[o] = q1;
+                    a.x2[o] = q2;
+                    const double c = a.cs * P.cval[o];
+                    s[0] += c * q2;
+                    s[6] += c * q1;
+                }
+            }
+        }
+    }
+    if constexpr (MODE != kGenA) block_sums_store<kLsSums>(s, a.partials + (size_t)blockIdx.x * kMaxSums);
+}
+
+struct ConsArgs {
+    const double *x1, *x2;
+    double *out;          // A: A(U V^T); refresh: constraint values (nullable)
+    double *q1, *q2;      // LS outputs (nullable)
+    const double *ytil;   // LS
+    double *y;            // refresh: multipliers
+    double sigma;         // refresh: y <- y + sigma (b - a) when > 0
+    double *partials;
+    const SolverState *st;
+};
+
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_gen_cons(DevGeneral P, ConsArgs a) {
+    if (a.st && a.st->done) return;
+    double s[kLsSums] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < P.m; k += (int64_t)gridDim.x * kBlock) {
+        double t1 = 0.0, t2 = 0.0;
+        for (int t = P.a_ptr[k]; t < P.a_ptr[k + 1]; ++t) {
+            const double v = P.a_val[t];
+            const int32_t o = P.a_idx[t];
+            t1 = fma(v, a.x1[o], t1);
+            if constexpr (MODE == kGenLS) t2 = fma(v, a.x2[o], t2);
+        }
+        if constexpr (MODE == kGenA) {
+            a.out[k] = t1;
+        } else if constexpr (MODE == kGenLS) {
+            if (a.q1) a.q1[k] = t1;
+            if (a.q2) a.q2[k] = t2;
+            const double yt = a.ytil[k];
+            s[1] += yt * t2;
+            s[2] += yt * t1;
+            s[3] += t2 * t2;
+            s[4] += t1 * t2;
+            s[5] += t1 * t1;
+        } else {
+            const double res = t1 - P.b[k];
+            double yk = a.y[k];
+            if (a.sigma > 0.0) {
+                yk -= a.sigma * res;
+                a.y[k] = yk;
+            }
+            if (a.out) a.out[k] = t1;
+            s[1] += P.b[k] * yk;
+            s[2] += res * res;
+        }
+    }
+    if constexpr (MODE != kGenA) block_sums_store<kLsSums>(s, a.partials + (size_t)blockIdx.x * kMaxSums);
+}
+
+template <typename S>
+struct GenSpmmArgs {
+    const S *V;
+    S *Y;
+    const double *ytil;   // nullable: then the operator is cs C
+    double cs;
+    int64_t ld;
+    const SolverState *st;
+    int force_slot;       // >= 0: write G into this slot and ignore st->done (subproblem start)
+    Rings<S> rings;
+    double *partials;
+};
+
+// value of C - A*(ytil) at position o (objective scale cs)
+__device__ __forceinline__ double gen_value(const DevGeneral &P, int32_t o, const double *ytil, double cs) {
+    double v = cs * P.cval[o];
+    if (ytil)
+        for (int t = P.at_ptr[o]; t < P.at_ptr[o + 1]; ++t) v = fma(-P.at_val[t], ytil[P.at_idx[t]], v);
+    return v;
+}
+
+// GRAD = false: Y = (cs C - A*(ytil)) V.  GRAD = true: G_{k+1} = 2 (cs C - A*(ytil)) R
+// into G slot (gk+1) mod (T+1), plus its dots with every ring slot.
+template <typename S, int GS, bool GRAD>
+__global__ __launch_bounds__(kBlock) void k_gen_spmm(DevGeneral P, GenSpmmArgs<S> a) {
+    using CV = typename Chunk<S>::V;
+    constexpr int NV = Chunk<S>::N;
+    constexpr int GPB = kBlock / GS;
+    int T = 0, gk1 = 0;
+    S *Gn = nullptr;
+    if constexpr (GRAD) {
+        if (a.force_slot < 0 && a.st->done) return;
+        T = a.st->T;
+        gk1 = a.force_slot >= 0 ? a.force_slot : (a.st->gk + 1) % (T + 1);
+#pragma unroll
+        for (int g = 0; g <= kMaxMem; ++g)
+            if (g == gk1) Gn = a.rings.g[g];
+    }
+    const int lane = threadIdx.x % GS, grp = threadIdx.x / GS;
+    const bool active = lane * NV < a.ld;
+    const CV zero = vzero(CV{});
+    double s[kMaxBasis];
+#pragma unroll
+    for (int j = 0; j < kMaxBasis; ++j) s[j] = 0.0;
+    for (int64_t row = (int64_t)blockIdx.x * GPB + grp; row < P.n; row += (int64_t)gridDim.x * GPB) {
+        D4 acc{{0.0, 0.0, 0.0, 0.0}};
+        const int e0 = P.s_ptr[row], e1 = P.s_ptr[row + 1];
+        int e = e0;
+        for (; e + 4 <= e1; e += 4) {
+            CV v[4];
+            double w[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                v[q] = active ? *reinterpret_cast<const CV *>(a.V + (int64_t)P.s_col[e + q] * a.ld + lane * NV)
+                              : zero;
+                w[q] = gen_value(P, P.s_om[e + q], a.ytil, a.cs);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const D4 vq = widen(v[q]);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc.v[c] = fma(w[q], vq.v[c], acc.v[c]);
+            }
+        }
+        for (; e < e1; ++e) {
+            const CV v0 = active ? *reinterpret_cast<const CV *>(a.V + (int64_t)P.s_col[e] * a.ld + lane * NV)
+                                 : zero;
+            const double w0 = gen_value(P, P.s_om[e], a.ytil, a.cs);
+            const D4 vq = widen(v0);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc.v[c] = fma(w0, vq.v[c], acc.v[c]);
+        }
+        D4 o;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) o.v[c] = GRAD ? 2.0 * acc.v[c] : acc.v[c];
+        CV os;
+        narrow(o, os);
+        const int64_t off = row * a.ld + lane * NV;
+        if constexpr (!GRAD) {
+            if (active) *reinterpret_cast<CV *>(a.Y + off) = os;
+        } else {
+            if (active) *reinterpret_cast<CV *>(Gn + off) = os;
+#pragma unroll
+            for (int g = 0; g <= kMaxMem; ++g) {
+                if (g <= T) {
+                    CV bsl = (g == gk1) ? os : (active ? *reinterpret_cast<const CV *>(a.rings.g[g] + off) : zero);
+                    s[g] += vdot(os, bsl);
+                }
+            }
+#pragma unroll
+            for (int d = 0; d < kMaxMem; ++d) {
+                if (d < T) {
+                    CV bsl = active ? *reinterpret_cast<const CV *>(a.rings.d[d] + off) : zero;
+                    s[kMaxMem + 1 + d] += vdot(os, bsl);
+                }
+            }
+        }
+    }
+    if constexpr (GRAD) block_sums_store<kMaxBasis>(s, a.partials + (size_t)blockIdx.x * kMaxSums);
+}
+
+template <typename S>
+int gs_of_gen(int64_t ld) {
+    const int ch = (int)(ld * (int64_t)sizeof(S) / 16);
+    return ch <= 4 ? 4 : (ch <= 8 ? 8 : 16);
+}
+
+template <typename S, int MODE>
+int xbar_t(hipStream_t s, const DevGeneral &P, const XbarArgs<S> &a, int *nb) {
+    const int gs = gs_of_gen<S>(a.ld);
+    *nb = gen_grid(P.nom, kBlock / gs);
+    if (gs == 4) hipLaunchKernelGGL((k_gen_xbar<S, 4, MODE>), dim3(*nb), dim3(kBlock), 0, s, P, a);
+    else if (gs == 8) hipLaunchKernelGGL((k_gen_xbar<S, 8, MODE>), dim3(*nb), dim3(kBlock), 0, s, P, a);
+    else hipLaunchKernelGGL((k_gen_xbar<S, 16, MODE>), dim3(*nb), dim3(kBlock), 0, s, P, a);
+    LRSDP_CHECK_LAUNCH();
+    return LRSDP_OK;
+}
+
+template <int MODE>
+int cons_t(hipStream_t s, const DevGeneral &P, const ConsArgs &a, int *nb) {
+    *nb = gen_grid(P.m, kBlock);
+    hipLaunchKernelGGL((k_gen_cons<MODE>), dim3(*nb), dim3(kBlock), 0, s, P, a);
+    LRSDP_CHECK_LAUNCH();
+    return LRSDP_OK;
+}
+
+template <typename S, int MODE>
+int sddmm_t(hipStream_t s, const DevGeneral &P, const void *U, const void *V, int64_t ld, double *out, double *q1,
+            double *q2, const double *ytil, double *y, double sigma, double cs, double *partials,
+            const SolverState *st, int *nb) {
+    XbarArgs<S> xa{(const S *)U, (const S *)V, ld, P.x1, P.x2, cs, partials, st};
+    int nb1 = 0, nb2 = 0, rc;
+    if ((rc = xbar_t<S, MODE>(s, P, xa, &nb1))) return rc;
+    if (MODE == kGenA) nb1 = 0;   // no partial sums from the first pass
+    ConsArgs ca{P.x1, P.x2, out, q1, q2, ytil, y, sigma, partials ? partials + (size_t)nb1 * kMaxSums : nullptr,
+                st};
+    if ((rc = cons_t<MODE>(s, P, ca, &nb2))) return rc;
+    *nb = MODE == kGenA ? 0 : nb1 + nb2;
+    return LRSDP_OK;
+}
+
+template <typename S, bool GRAD>
+int gen_spmm_t(hipStream_t s, const DevGeneral &P, const GenSpmmArgs<S> &a, int *nb) {
+    const int gs = gs_of_gen<S>(a.ld);
+    *nb = gen_grid(P.n, kBlock / gs);
+    if (gs == 4) hipLaunchKernelGGL((k_gen_spmm<S, 4, GRAD>), dim3(*nb), dim3(kBlock), 0, s, P, a);
+    else if (gs == 8) hipLaunchKernelGGL((k_gen_spmm<S, 8, GRAD>), dim3(*nb), dim3(kBlock), 0, s, P, a);
+    else hipLaunchKernelGGL((k_gen_spmm<S, 16, GRAD>), dim3(*nb), dim3(kBlock), 0, s, P, a);
+    LRSDP_CHECK_LAUNCH();
+    return LRSDP_OK;
+}
+
+}  // namespace
+
+// mode 0: out = A(U V^T); mode 1: line-search terms of direction V at U with
+// ytil (partials: {<C,DD^T>, ytil.q2, ytil.q1, q2.q2, q1.q2, q1.q1, <C,RD^T+DR^T>});
+// mode 2: constraint values (into out when given) and the multiplier step,
+// partials {<C,RR^T>, b.y, ||A(RR^T) - b||^2}.  *nb = partial rows written.
+int gen_sddmm(hipStream_t s, const DevGeneral &P, int prec, int mode, const void *U, const void *V, int64_t ld,
+              double *out, double *q1, double *q2, const double *ytil, double *y, double sigma, double cs,
+              double *partials, const SolverState *st, int *nb) {
+    if (prec == LRSDP_F64) {
+        if (mode == kGenA)
+            return sddmm_t<double, kGenA>(s, P, U, V, ld, out, q1, q2, ytil, y, sigma, cs, partials, st, nb);
+        if (mode == kGenLS)
+            return sddmm_t<double, kGenLS>(s, P, U, V, ld, out, q1, q2, ytil, y, sigma, cs, partials, st, nb);
+        return sddmm_t<double, kGenRefresh>(s, P, U, V, ld, out, q1, q2, ytil, y, sigma, cs, partials, st, nb);
+    }
+    if (mode == kGenA)
+        return sddmm_t<float, kGenA>(s, P, U, V, ld, out, q1, q2, ytil, y, sigma, cs, partials, st, nb);
+    if (mode == kGenLS)
+        return sddmm_t<float, kGenLS>(s, P, U, V, ld, out, q1, q2, ytil, y, sigma, cs, partials, st, nb);
+    return sddmm_t<float, kGenRefresh>(s, P, U, V, ld, out, q1, q2, ytil, y, sigma, cs, partials, st, nb);
+}
+
+int spmm_general(hipStream_t s, const DevGeneral &P, int prec, const void *V, int64_t ld, const double *ytil,
+                 void *Y) {
+    int nb = 0;
+    if (prec == LRSDP_F64) {
+        GenSpmmArgs<double> a{(const double *)V, (double *)Y, ytil, 1.0, ld, nullptr, -1, {}, nullptr};
+        return gen_spmm_t<double, false>(s, P, a, &nb);
+    }
+    GenSpmmArgs<float> a{(const float *)V, (float *)Y, ytil, 1.0, ld, nullptr, -1, {}, nullptr};
+    return gen_spmm_t<float, false>(s, P, a, &nb);
+}
+
+int gen_grad(hipStream_t s, const DevGeneral &P, int prec, const SolverState *st, const void *R,
+             const double *ytil, void *const *gring, void *const *dring, int T, int64_t ld, double *partials,
+             int force_slot, int *nb, double cs) {
+    if (prec == LRSDP_F64) {
+        GenSpmmArgs<double> a{(const double *)R, nullptr, ytil, cs, ld, st, force_slot, {}, partials};
+        for (int g = 0; g <= T; ++g) a.rings.g[g] = (double *)gring[g];
+        for (int d = 0; d < T; ++d) a.rings.d[d] = (double *)dring[d];
+        return gen_spmm_t<double, true>(s, P, a, nb);
+    }
+    GenSpmmArgs<float> a{(const float *)R, nullptr, ytil, cs, ld, st, force_slot, {}, partials};
+    for (int g = 0; g <= T; ++g) a.rings.g[g] = (float *)gring[g];
+    for (int d = 0; d < T; ++d) a.rings.d[d] = (float *)dring[d];
+    return gen_spmm_t<float, true>(s, P, a, nb);
+}
+
+}  // namespace lrsdp

@@ -80,6 +80,28 @@ struct DevCompletion {
     int64_t n1 = 0, n2 = 0, m = 0;
 };
 
+// General problem (Section 3.4 compression).  Omega: positions (a, b), a <= b,
+// that are nonzero in C or in some A_k; the stacked constraint matrix keeps
+// only its nonzero columns, indexed by position in Omega.
+struct DevGeneral {
+    const int32_t *om_a = nullptr;      // |Omega| row of each position
+    const int32_t *om_b = nullptr;      // |Omega| column (>= row)
+    const double *cval = nullptr;       // |Omega| C_ab (0 where only constraints touch)
+    const int32_t *a_ptr = nullptr;     // m + 1: constraint rows of the stacked matrix
+    const int32_t *a_idx = nullptr;     // nnz_a: Omega index
+    const double *a_val = nullptr;      // nnz_a: A_k,ab
+    const int32_t *at_ptr = nullptr;    // |Omega| + 1: the transpose, rows = positions
+    const int32_t *at_idx = nullptr;    // nnz_a: constraint index
+    const double *at_val = nullptr;     // nnz_a
+    const int32_t *s_ptr = nullptr;     // n + 1: symmetric pattern of Omega by rows
+    const int32_t *s_col = nullptr;     // nnz_s: column
+    const int32_t *s_om = nullptr;      // nnz_s: Omega index of the entry
+    const double *b = nullptr;          // m
+    double *x1 = nullptr;               // |Omega| compressed outer products (problem-owned scratch:
+    double *x2 = nullptr;               // calls on one problem must not overlap)
+    int64_t n = 0, m = 0, nom = 0, nnz_a = 0, nnz_s = 0;
+};
+
 }  // namespace lrsdp
 
 struct lrsdp_problem {
@@ -90,9 +112,12 @@ struct lrsdp_problem {
     std::vector<double> val, diag, hrow;
     std::vector<int32_t> top_ptr, top_col, top_eid, bot_ptr, bot_row, bot_eid, samp_i, samp_j;
     std::vector<double> b;
+    std::vector<int32_t> om_a, om_b, a_ptr, a_idx, at_ptr, at_idx, s_ptr, s_col, s_om;
+    std::vector<double> cval, a_val, at_val;
     // device views (valid after upload)
     lrsdp::DevCsr csr;
     lrsdp::DevCompletion cmp;
+    lrsdp::DevGeneral gen;
     void *dev = nullptr;
     size_t dev_bytes = 0;
     bool uploaded = false;

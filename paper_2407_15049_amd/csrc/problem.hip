@@ -278,6 +278,155 @@ extern "C" int lrsdp_problem_get_info(const lrsdp_problem *prob, lrsdp_problem_i
     return LRSDP_OK;
 }
 
+extern "C" int lrsdp_problem_general(int64_t n, int64_t c_nnz, const int32_t *c_row, const int32_t *c_col,
+                                     const double *c_val, int64_t m, int64_t a_nnz, const int32_t *a_con,
+                                     const int32_t *a_row, const int32_t *a_col, const double *a_val,
+                                     const double *b, lrsdp_problem **out) {
+    clear_error();
+    if (!out) return set_error(LRSDP_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || n > INT32_MAX - 1) return set_error(LRSDP_EINVAL, "n = %lld out of range", (long long)n);
+    if (m < 1 || m > INT32_MAX - 1) return set_error(LRSDP_EINVAL, "m = %lld out of range", (long long)m);
+    if (c_nnz < 0 || a_nnz < 0 || a_nnz > INT32_MAX) return set_error(LRSDP_EINVAL, "bad entry counts");
+    if ((c_nnz > 0 && (!c_row || !c_col || !c_val)) || (a_nnz > 0 && (!a_con || !a_row || !a_col || !a_val)) || !b)
+        return set_error(LRSDP_EINVAL, "input arrays are NULL");
+    for (int64_t t = 0; t < c_nnz; ++t) {
+        if (c_row[t] < 0 || c_row[t] >= n || c_col[t] < 0 || c_col[t] >= n)
+            return set_error(LRSDP_EINVAL, "C entry %lld = (%d, %d) out of range", (long long)t, c_row[t], c_col[t]);
+        if (!std::isfinite(c_val[t])) return set_error(LRSDP_EINVAL, "C value %lld is not finite", (long long)t);
+    }
+    for (int64_t t = 0; t < a_nnz; ++t) {
+        if (a_con[t] < 0 || a_con[t] >= m)
+            return set_error(LRSDP_EINVAL, "A entry %lld names constraint %d", (long long)t, a_con[t]);
+        if (a_row[t] < 0 || a_row[t] >= n || a_col[t] < 0 || a_col[t] >= n)
+            return set_error(LRSDP_EINVAL, "A entry %lld = (%d, %d) out of range", (long long)t, a_row[t], a_col[t]);
+        if (!std::isfinite(a_val[t])) return set_error(LRSDP_EINVAL, "A value %lld is not finite", (long long)t);
+    }
+    for (int64_t k = 0; k < m; ++k)
+        if (!std::isfinite(b[k])) return set_error(LRSDP_EINVAL, "b[%lld] is not finite", (long long)k);
+    auto key = [n](int32_t r, int32_t c) {
+        const int64_t a = std::min(r, c), bb = std::max(r, c);
+        return a * n + bb;
+    };
+    // C: positions of the upper triangle, repeated positions summed
+    std::vector<std::pair<int64_t, double>> ce(c_nnz);
+    for (int64_t t = 0; t < c_nnz; ++t) ce[t] = {key(c_row[t], c_col[t]), c_val[t]};
+    std::sort(ce.begin(), ce.end(), [](const auto &x, const auto &y) { return x.first < y.first; });
+    std::vector<std::pair<int64_t, double>> cs;
+    for (const auto &e : ce) {
+        if (!cs.empty() && cs.back().first == e.first) cs.back().second += e.second;
+        else cs.push_back(e);
+    }
+    // A: (constraint, position) pairs, repeated ones summed
+    struct AE {
+        int32_t k;
+        int64_t pos;
+        double v;
+    };
+    std::vector<AE> ae(a_nnz);
+    for (int64_t t = 0; t < a_nnz; ++t) ae[t] = {a_con[t], key(a_row[t], a_col[t]), a_val[t]};
+    std::sort(ae.begin(), ae.end(), [](const AE &x, const AE &y) { return x.k != y.k ? x.k < y.k : x.pos < y.pos; });
+    std::vector<AE> as;
+    for (const auto &e : ae) {
+        if (!as.empty() && as.back().k == e.k && as.back().pos == e.pos) as.back().v += e.v;
+        else as.push_back(e);
+    }
+    // Omega = positions of C and of the nonzero columns of the stacked matrix
+    std::vector<int64_t> om;
+    om.reserve(cs.size() + as.size());
+    for (const auto &e : cs) om.push_back(e.first);
+    for (const auto &e : as) om.push_back(e.pos);
+    std::sort(om.begin(), om.end());
+    om.erase(std::unique(om.begin(), om.end()), om.end());
+    if ((int64_t)om.size() > INT32_MAX / 2) return set_error(LRSDP_EINVAL, "|Omega| = %zu too large", om.size());
+    auto idx = [&](int64_t pos) { return (int32_t)(std::lower_bound(om.begin(), om.end(), pos) - om.begin()); };
+    const int64_t nom = (int64_t)om.size();
+    auto *p = new lrsdp_problem();
+    p->om_a.resize(nom);
+    p->om_b.resize(nom);
+    p->cval.assign(nom, 0.0);
+    for (int64_t o = 0; o < nom; ++o) {
+        p->om_a[o] = (int32_t)(om[o] / n);
+        p->om_b[o] = (int32_t)(om[o] % n);
+    }
+    double c_l1 = 0.0;
+    for (const auto &e : cs) {
+        const int32_t o = idx(e.first);
+        p->cval[o] = e.second;
+        c_l1 += (p->om_a[o] == p->om_b[o] ? 1.0 : 2.0) * std::fabs(e.second);
+    }
+    // stacked constraint matrix by constraint rows (sorted by Omega index)
+    p->a_ptr.assign(m + 1, 0);
+    p->a_idx.resize(as.size());
+    p->a_val.resize(as.size());
+    for (size_t t = 0; t < as.size(); ++t) {
+        p->a_ptr[as[t].k + 1]++;
+        p->a_idx[t] = idx(as[t].pos);
+        p->a_val[t] = as[t].v;
+    }
+    for (int64_t k = 0; k < m; ++k) p->a_ptr[k + 1] += p->a_ptr[k];
+    // its transpose by positions (sorted by constraint)
+    p->at_ptr.assign(nom + 1, 0);
+    for (size_t t = 0; t < as.size(); ++t) p->at_ptr[p->a_idx[t] + 1]++;
+    for (int64_t o = 0; o < nom; ++o) p->at_ptr[o + 1] += p->at_ptr[o];
+    p->at_idx.resize(as.size());
+    p->at_val.resize(as.size());
+    {
+        std::vector<int32_t> fill(p->at_ptr.begin(), p->at_ptr.end() - 1);
+        for (size_t t = 0; t < as.size(); ++t) {
+            const int32_t o = p->a_idx[t];
+            p->at_idx[fill[o]] = as[t].k;
+            p->at_val[fill[o]] = as[t].v;
+            fill[o]++;
+        }
+    }
+    // symmetric pattern of Omega by rows: (a, b) in row a and, off the diagonal,
+    // (b, a) in row b, each with its Omega index; columns ascending
+    std::vector<std::pair<int64_t, int32_t>> se;   // (row * n + col, omega)
+    se.reserve(2 * nom);
+    for (int64_t o = 0; o < nom; ++o) {
+        const int64_t a = p->om_a[o], bb = p->om_b[o];
+        se.push_back({a * n + bb, (int32_t)o});
+        if (a != bb) se.push_back({bb * n + a, (int32_t)o});
+    }
+    std::sort(se.begin(), se.end(), [](const auto &x, const auto &y) { return x.first < y.first; });
+    if ((int64_t)se.size() > INT32_MAX) {
+        delete p;
+        return set_error(LRSDP_EINVAL, "symmetric pattern too large");
+    }
+    p->s_ptr.assign(n + 1, 0);
+    p->s_col.resize(se.size());
+    p->s_om.resize(se.size());
+    for (size_t t = 0; t < se.size(); ++t) {
+        p->s_ptr[se[t].first / n + 1]++;
+        p->s_col[t] = (int32_t)(se[t].first % n);
+        p->s_om[t] = se[t].second;
+    }
+    int64_t max_row = 0;
+    for (int64_t r = 0; r < n; ++r) {
+        max_row = std::max<int64_t>(max_row, p->s_ptr[r + 1]);
+        p->s_ptr[r + 1] += p->s_ptr[r];
+    }
+    p->b.assign(b, b + m);
+    double b_l1 = 0.0, b_inf = 0.0;
+    for (int64_t k = 0; k < m; ++k) {
+        b_l1 += std::fabs(b[k]);
+        b_inf = std::max(b_inf, std::fabs(b[k]));
+    }
+    auto &I = p->info;
+    I.kind = LRSDP_GENERAL;
+    I.n = n;
+    I.m = m;
+    I.nnz = (int64_t)se.size();
+    I.weights = kWGeneral;
+    I.max_row_nnz = max_row;
+    I.c_l1 = c_l1;
+    I.b_l1 = b_l1;
+    I.b_inf = b_inf;
+    *out = p;
+    return LRSDP_OK;
+}
+
 namespace {
 
 struct Layout {
@@ -305,6 +454,22 @@ size_t plan_device(const lrsdp_problem *p, size_t *offs) {
         add(p->heavy_seg.size() * 4);
         add(p->seg.size() * 256);      // segment partial sums (<= 256 B per row)
         add(p->hrow.size() * 8);
+    } else if (p->info.kind == LRSDP_GENERAL) {
+        add(p->om_a.size() * 4);
+        add(p->om_b.size() * 4);
+        add(p->cval.size() * 8);
+        add(p->a_ptr.size() * 4);
+        add(p->a_idx.size() * 4);
+        add(p->a_val.size() * 8);
+        add(p->at_ptr.size() * 4);
+        add(p->at_idx.size() * 4);
+        add(p->at_val.size() * 8);
+        add(p->s_ptr.size() * 4);
+        add(p->s_col.size() * 4);
+        add(p->s_om.size() * 4);
+        add(p->b.size() * 8);
+        add(p->om_a.size() * 8);       // compressed outer products (two per position)
+        add(p->om_a.size() * 8);
     } else {
         add(p->top_ptr.size() * 4);
         add(p->top_col.size() * 4);
@@ -369,6 +534,41 @@ extern "C" int lrsdp_problem_upload(lrsdp_ctx *ctx, lrsdp_problem *p, void *dev,
         c.n_seg = (int64_t)p->seg.size();
         c.n_heavy = (int64_t)p->heavy.size();
         c.wmode = p->info.weights;
+    } else if (p->info.kind == LRSDP_GENERAL) {
+        LRSDP_HIP_TRY(put(offs[0], p->om_a.data(), p->om_a.size() * 4));
+        LRSDP_HIP_TRY(put(offs[1], p->om_b.data(), p->om_b.size() * 4));
+        LRSDP_HIP_TRY(put(offs[2], p->cval.data(), p->cval.size() * 8));
+        LRSDP_HIP_TRY(put(offs[3], p->a_ptr.data(), p->a_ptr.size() * 4));
+        LRSDP_HIP_TRY(put(offs[4], p->a_idx.data(), p->a_idx.size() * 4));
+        LRSDP_HIP_TRY(put(offs[5], p->a_val.data(), p->a_val.size() * 8));
+        LRSDP_HIP_TRY(put(offs[6], p->at_ptr.data(), p->at_ptr.size() * 4));
+        LRSDP_HIP_TRY(put(offs[7], p->at_idx.data(), p->at_idx.size() * 4));
+        LRSDP_HIP_TRY(put(offs[8], p->at_val.data(), p->at_val.size() * 8));
+        LRSDP_HIP_TRY(put(offs[9], p->s_ptr.data(), p->s_ptr.size() * 4));
+        LRSDP_HIP_TRY(put(offs[10], p->s_col.data(), p->s_col.size() * 4));
+        LRSDP_HIP_TRY(put(offs[11], p->s_om.data(), p->s_om.size() * 4));
+        LRSDP_HIP_TRY(put(offs[12], p->b.data(), p->b.size() * 8));
+        DevGeneral &g = p->gen;
+        g.om_a = (const int32_t *)(base + offs[0]);
+        g.om_b = (const int32_t *)(base + offs[1]);
+        g.cval = (const double *)(base + offs[2]);
+        g.a_ptr = (const int32_t *)(base + offs[3]);
+        g.a_idx = (const int32_t *)(base + offs[4]);
+        g.a_val = (const double *)(base + offs[5]);
+        g.at_ptr = (const int32_t *)(base + offs[6]);
+        g.at_idx = (const int32_t *)(base + offs[7]);
+        g.at_val = (const double *)(base + offs[8]);
+        g.s_ptr = (const int32_t *)(base + offs[9]);
+        g.s_col = (const int32_t *)(base + offs[10]);
+        g.s_om = (const int32_t *)(base + offs[11]);
+        g.b = (const double *)(base + offs[12]);
+        g.x1 = (double *)(base + offs[13]);
+        g.x2 = (double *)(base + offs[14]);
+        g.n = p->info.n;
+        g.m = p->info.m;
+        g.nom = (int64_t)p->om_a.size();
+        g.nnz_a = (int64_t)p->a_idx.size();
+        g.nnz_s = (int64_t)p->s_col.size();
     } else {
         LRSDP_HIP_TRY(put(offs[0], p->top_ptr.data(), p->top_ptr.size() * 4));
         LRSDP_HIP_TRY(put(offs[1], p->top_col.data(), p->top_col.size() * 4));

@@ -51,6 +51,10 @@ int cmp_samples(hipStream_t, const DevCompletion &, const SolverState *, double 
 int cmp_ytil(hipStream_t, const DevCompletion &, const SolverState *, double, const double *, const double *,
              double *);
 int axpy_state(hipStream_t, int, const SolverState *, void *, const void *, int64_t, int64_t);
+int gen_sddmm(hipStream_t, const DevGeneral &, int, int, const void *, const void *, int64_t, double *, double *,
+              double *, const double *, double *, double, double, double *, const SolverState *, int *);
+int gen_grad(hipStream_t, const DevGeneral &, int, const SolverState *, const void *, const double *, void *const *,
+             void *const *, int, int64_t, double *, int, int *, double);
 
 namespace {
 
@@ -108,6 +112,15 @@ double maxcut_spmm_bytes(const lrsdp_problem *p, int prec, int r) {
 double completion_grad_bytes(const lrsdp_problem *p, int prec, int r, int T) {
     const double n = (double)p->info.n, m = (double)p->info.m, w = elem_size(prec);
     return 4.0 * (n + 2) + 2.0 * m * 16.0 + (2.0 + 2.0 * T) * n * r * w;
+}
+
+// Algorithmic bytes of one general-problem gradient SpMM launch: row pointers,
+// per stored entry its column, position and C value, the transposed stacked
+// matrix and ytil once, R read, G written, the 2T ring slots read.
+double general_grad_bytes(const lrsdp_problem *p, int prec, int r, int T) {
+    const double n = (double)p->info.n, nnz = (double)p->info.nnz, w = elem_size(prec);
+    const double nom = (double)p->gen.nom, na = (double)p->gen.nnz_a, m = (double)p->info.m;
+    return 4.0 * (n + 1) + 8.0 * nnz + 12.0 * nom + 12.0 * na + 8.0 * m + (2.0 + 2.0 * T) * n * r * w;
 }
 
 }  // namespace
@@ -216,6 +229,8 @@ int plan_workspace(const lrsdp_problem *p, const lrsdp_options *o, WsPlan *w) {
     if (rc) return rc;
     if (o->precond < 0 || o->precond > 2) return set_error(LRSDP_EINVAL, "precond = %d not in {0, 1, 2}", o->precond);
     if (o->reopt < 0 || o->reopt > 2) return set_error(LRSDP_EINVAL, "reopt = %d not in {0, 1, 2}", o->reopt);
+    if (o->phase2 && p->info.kind == LRSDP_GENERAL)
+        return set_error(LRSDP_EUNSUPPORTED, "the splitting phase is implemented for MaxCut and completion problems");
     if (o->reopt && (!(o->reopt_factor > 0.0) || !(o->reopt_factor < 1.0) || o->max_reopt < 0))
         return set_error(LRSDP_EINVAL, "re-optimisation needs 0 < reopt_factor < 1 and max_reopt >= 0");
     if (o->reopt == 2 && o->cert_iters < 1) return set_error(LRSDP_EINVAL, "reopt = 2 needs cert_iters >= 1");
@@ -430,6 +445,14 @@ int cmp_admm_iter(lrsdp_ctx *c, const lrsdp_problem *p, int prec, void *U, void 
 int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws, void *R, double *y,
                lrsdp_result *res) {
     const bool mc = p->info.kind == LRSDP_MAXCUT;
+    const bool gen = p->info.kind == LRSDP_GENERAL;
+    const bool cmp = p->info.kind == LRSDP_COMPLETION;
+    // per-constraint kernels (acon, ytil updates) of the sample families see
+    // only m and b: a general problem passes them through a completion view
+    DevCompletion gview{};
+    gview.m = p->info.m;
+    gview.b = p->gen.b;
+    const DevCompletion &cv = gen ? gview : p->cmp;
     const auto t0 = std::chrono::steady_clock::now();
     auto elapsed = [&]() { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); };
     const int prec = o->prec == LRSDP_F64 ? LRSDP_F64 : LRSDP_F32;
@@ -524,6 +547,10 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
             ref.ld = ld;
             ref.partials = part_misc;
             if ((r2 = spmm_maxcut(s, p->csr, prec, ref, &np))) return r2;
+        } else if (gen) {
+            if ((r2 = gen_sddmm(s, p->gen, prec, 2, R, nullptr, ld, acon, nullptr, nullptr, nullptr, y, sigma, cs,
+                                part_misc, nullptr, &np)))
+                return r2;
         } else {
             int nb1 = 0, nb2 = 0;
             if ((r2 = cmp_sddmm(s, p->cmp, prec, 2, R, nullptr, ld, acon, nullptr, nullptr, nullptr, y, sigma,
@@ -533,7 +560,7 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
             if ((r2 = launch_dots(s, prec, R, rb, 1, n, ld, part_misc + (size_t)nb1 * kMaxSums, &nb2))) return r2;
             np = nb1 + nb2;
         }
-        return launch_alm_finalize(s, st, part_misc, np, mode, mc ? 1.0 : cs);
+        return launch_alm_finalize(s, st, part_misc, np, mode, cmp ? cs : 1.0);
     };
     if ((rc = alm_refresh(0.0, 0))) return rc;
 
@@ -603,8 +630,10 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
                                               pc)))
                 break;
         } else {
-            if ((rc = cmp_ytil(s, p->cmp, st, 0.0, acon, y, ytil[0]))) break;
-            if ((rc = cmp_grad(s, p->cmp, prec, st, R, ytil[0], gring, dring, T, ld, part_misc, 0, &nb, cs))) break;
+            if ((rc = cmp_ytil(s, cv, st, 0.0, acon, y, ytil[0]))) break;
+            if (gen) rc = gen_grad(s, p->gen, prec, st, R, ytil[0], gring, dring, T, ld, part_misc, 0, &nb, cs);
+            else rc = cmp_grad(s, p->cmp, prec, st, R, ytil[0], gring, dring, T, ld, part_misc, 0, &nb, cs);
+            if (rc) break;
         }
         int64_t left = o->max_iter_total - total_inner;
         int k_limit = (int)std::min<int64_t>(o->max_inner, std::max<int64_t>(left, 0));
@@ -639,12 +668,19 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
                                                       &nb2, pc)))
                         break;
                 } else {
-                    if ((rc = cmp_sddmm(s, p->cmp, prec, 2, R, nullptr, ld, acon, nullptr, nullptr, nullptr, y, 0.0,
-                                        part_misc, nullptr, &nb2)))
-                        break;
-                    if ((rc = cmp_ytil(s, p->cmp, st, 0.0, acon, y, ytil[0]))) break;
-                    if ((rc = cmp_grad(s, p->cmp, prec, st, R, ytil[0], gring, dring, T, ld, part_misc, 0, &nb2, cs)))
-                        break;
+                    if (gen)
+                        rc = gen_sddmm(s, p->gen, prec, 2, R, nullptr, ld, acon, nullptr, nullptr, nullptr, y, 0.0, cs,
+                                       part_misc, nullptr, &nb2);
+                    else
+                        rc = cmp_sddmm(s, p->cmp, prec, 2, R, nullptr, ld, acon, nullptr, nullptr, nullptr, y, 0.0,
+                                       part_misc, nullptr, &nb2);
+                    if (rc) break;
+                    if ((rc = cmp_ytil(s, cv, st, 0.0, acon, y, ytil[0]))) break;
+                    if (gen)
+                        rc = gen_grad(s, p->gen, prec, st, R, ytil[0], gring, dring, T, ld, part_misc, 0, &nb2, cs);
+                    else
+                        rc = cmp_grad(s, p->cmp, prec, st, R, ytil[0], gring, dring, T, ld, part_misc, 0, &nb2, cs);
+                    if (rc) break;
                 }
                 if ((rc = launch_init_finalize(s, st, part_misc, nb2, -1))) break;
                 if ((rc = launch_combine(s, prec, st, nullptr, basis, 2 * T + 1, nullptr, n, ld, part_cb, &ncb,
@@ -653,15 +689,35 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
             }
             for (int b = 0; b < B && !mc; ++b, ++it, ++done_it, ++since_refresh) {
                 int nls = 0, nup = 0;
-                if ((rc = cmp_sddmm(s, p->cmp, prec, 1, R, dring[it % T], ld, nullptr, q1, q2, ytil[0], nullptr, 0.0,
-                                    part_ls, st, &nls)))
-                    break;
-                if ((rc = launch_ls_finalize(s, st, part_ls, nls, part_cb, ncb, LRSDP_COMPLETION, cs))) break;
-                if ((rc = cmp_samples(s, p->cmp, st, acon, q1, q2, y, ytil[0]))) break;
-                if ((rc = axpy_state(s, prec, st, R, dring[it % T], n, ld))) break;
+                if (gen)
+                    rc = gen_sddmm(s, p->gen, prec, 1, R, dring[it % T], ld, nullptr, q1, q2, ytil[0], nullptr, 0.0,
+                                   cs, part_ls, st, &nls);
+                else
+                    rc = cmp_sddmm(s, p->cmp, prec, 1, R, dring[it % T], ld, nullptr, q1, q2, ytil[0], nullptr, 0.0,
+                                   part_ls, st, &nls);
+                if (rc) break;
+                if ((rc = launch_ls_finalize(s, st, part_ls, nls, part_cb, ncb, p->info.kind, cs))) break;
+                if (gen) {
+                    // general problems recompute A(RR^T) at the new R (one more
+                    // compressed pass) instead of the recurrence a += tau (q1 +
+                    // tau q2): with float32 storage of R the recurrence drifts
+                    // from the constraint values of the rounded R
+                    int nrf = 0;
+                    if ((rc = axpy_state(s, prec, st, R, dring[it % T], n, ld))) break;
+                    if ((rc = gen_sddmm(s, p->gen, prec, 2, R, nullptr, ld, acon, nullptr, nullptr, nullptr, y, 0.0,
+                                        cs, part_misc, st, &nrf)))
+                        break;
+                    if ((rc = cmp_ytil(s, cv, st, 0.0, acon, y, ytil[0]))) break;
+                } else {
+                    if ((rc = cmp_samples(s, cv, st, acon, q1, q2, y, ytil[0]))) break;
+                    if ((rc = axpy_state(s, prec, st, R, dring[it % T], n, ld))) break;
+                }
                 if (o->profile) LRSDP_HIP_TRY(hipEventRecord(evs[2 * b], s));
-                if ((rc = cmp_grad(s, p->cmp, prec, st, R, ytil[0], gring, dring, T, ld, part_up, -1, &nup, cs)))
-                    break;
+                if (gen)
+                    rc = gen_grad(s, p->gen, prec, st, R, ytil[0], gring, dring, T, ld, part_up, -1, &nup, cs);
+                else
+                    rc = cmp_grad(s, p->cmp, prec, st, R, ytil[0], gring, dring, T, ld, part_up, -1, &nup, cs);
+                if (rc) break;
                 if (o->profile) LRSDP_HIP_TRY(hipEventRecord(evs[2 * b + 1], s));
                 if ((rc = launch_lbfgs_finalize(s, st, part_up, nup))) break;
                 if ((rc = launch_combine(s, prec, st, nullptr, basis, 2 * T + 1, nullptr, n, ld, part_cb, &ncb, shadow)))
@@ -760,7 +816,7 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
             hs.err1_prev = INFINITY;
             if ((rc = write_state(c, hs))) break;
         }
-        if (!mc && phase2_on && hs.err1 <= o->switch_err1) {
+        if (cmp && phase2_on && hs.err1 <= o->switch_err1) {
             // completion splitting phase: CG half-steps (Algorithm 2), same measures,
             // stop test and fallback as the MaxCut phase below
             void *U = gring[0];
@@ -935,7 +991,9 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
     res->status = status;
     res->spmm_launches = spmm_n;
     res->spmm_ms = spmm_ms;
-    res->spmm_bytes = mc ? maxcut_spmm_bytes(p, prec, o->rank) : completion_grad_bytes(p, prec, o->rank, T);
+    res->spmm_bytes = mc    ? maxcut_spmm_bytes(p, prec, o->rank)
+                      : gen ? general_grad_bytes(p, prec, o->rank, T)
+                            : completion_grad_bytes(p, prec, o->rank, T);
     res->admm_iters = admm_iters;
     res->admm_fallbacks = admm_fallbacks;
     res->rank_final = rank_cur;
@@ -982,6 +1040,7 @@ extern "C" int lrsdp_k_spmm(lrsdp_ctx *c, const lrsdp_problem *p, int prec, cons
     }
     if (prec == LRSDP_F32_BF16IN)
         return set_error(LRSDP_EUNSUPPORTED, "bfloat16 input is implemented for the MaxCut SpMM only");
+    if (p->info.kind == LRSDP_GENERAL) return spmm_general(c->stream, p->gen, pr, V, ld, ytil, Y);
     return spmm_completion(c->stream, p->cmp, pr, V, ld, ytil, Y);
 }
 
@@ -995,6 +1054,9 @@ extern "C" int lrsdp_k_constraint(lrsdp_ctx *c, const lrsdp_problem *p, int prec
     if (!V) V = U;
     if (p->info.kind == LRSDP_MAXCUT) return launch_rowdot(c->stream, pr, U, V, p->info.n, ld, out);
     int nb = 0;
+    if (p->info.kind == LRSDP_GENERAL)
+        return gen_sddmm(c->stream, p->gen, pr, 0, U, V, ld, out, nullptr, nullptr, nullptr, nullptr, 0.0, 1.0,
+                         nullptr, nullptr, &nb);
     return cmp_sddmm(c->stream, p->cmp, pr, 0, U, V, ld, out, nullptr, nullptr, nullptr, nullptr, 0.0, nullptr,
                      nullptr, &nb);
 }
@@ -1010,6 +1072,28 @@ extern "C" int lrsdp_k_ls_coeffs(lrsdp_ctx *c, const lrsdp_problem *p, int prec,
     const int64_t n = p->info.n;
     const size_t arr = (size_t)n * ld * elem_size(pr);
     char *wk = static_cast<char *>(work);
+    if (p->info.kind == LRSDP_GENERAL) {
+        // a = A(RR^T), ytil = y + sigma (b - a), then the C-weighted and
+        // per-constraint line-search terms in one compressed pass
+        const int64_t m = p->info.m;
+        double *acon = reinterpret_cast<double *>(wk);
+        double *yt = acon + m;
+        double *part = at<double>(c->scratch, kPartLsOff);
+        double *sums = at<double>(c->scratch, kSmallOff);
+        hipStream_t s = c->stream;
+        DevCompletion v{};
+        v.m = m;
+        v.b = p->gen.b;
+        int nb = 0;
+        if ((rc = gen_sddmm(s, p->gen, pr, 0, R, R, ld, acon, nullptr, nullptr, nullptr, nullptr, 0.0, 1.0, nullptr,
+                            nullptr, &nb)))
+            return rc;
+        if ((rc = cmp_ytil(s, v, nullptr, sigma, acon, y, yt))) return rc;
+        if ((rc = gen_sddmm(s, p->gen, pr, 1, R, D, ld, nullptr, q1, q2, yt, nullptr, 0.0, 1.0, part, nullptr, &nb)))
+            return rc;
+        if ((rc = launch_reduce(s, part, nb, kLsSums, sums))) return rc;
+        return launch_ls_out(s, sums, sigma, out);
+    }
     if (p->info.kind == LRSDP_COMPLETION) {
         // a = A(RR^T), ytil = y + sigma (b - a), sample terms, then p1 = 2<R,D>, p2 = ||D||^2
         const int64_t m = p->info.m;
@@ -1079,6 +1163,14 @@ extern "C" int lrsdp_k_alm(lrsdp_ctx *c, const lrsdp_problem *p, int prec, const
     const int pr = prec == LRSDP_F64 ? LRSDP_F64 : LRSDP_F32;
     double *part = at<double>(c->scratch, kPartMiscOff);
     double *sums = at<double>(c->scratch, kSmallOff);
+    if (p->info.kind == LRSDP_GENERAL) {
+        int nb = 0;
+        if ((rc = gen_sddmm(c->stream, p->gen, pr, 2, R, nullptr, ld, static_cast<double *>(work), nullptr, nullptr,
+                            nullptr, y, sigma, 1.0, part, nullptr, &nb)))
+            return rc;
+        if ((rc = launch_reduce(c->stream, part, nb, 3, sums))) return rc;
+        return launch_alm_out(c->stream, sums, p->info.b_l1, p->info.b_inf, out);
+    }
     if (p->info.kind == LRSDP_COMPLETION) {
         int nb1 = 0, nb2 = 0;
         if ((rc = cmp_sddmm(c->stream, p->cmp, pr, 2, R, nullptr, ld, static_cast<double *>(work), nullptr, nullptr,
@@ -1232,6 +1324,8 @@ extern "C" int lrsdp_admm_workspace_bytes(const lrsdp_problem *p, int prec, int6
     if (!p || !bytes) return set_error(LRSDP_EINVAL, "NULL argument");
     int rc;
     if ((rc = check_prec(prec)) || (rc = check_ld(prec, ld))) return rc;
+    if (p->info.kind == LRSDP_GENERAL)
+        return set_error(LRSDP_EUNSUPPORTED, "the splitting phase is implemented for MaxCut and completion problems");
     *bytes = p->info.kind == LRSDP_MAXCUT ? 0 : cmp_admm_bytes(p, prec == LRSDP_F64 ? LRSDP_F64 : LRSDP_F32, ld);
     return LRSDP_OK;
 }
@@ -1243,6 +1337,8 @@ extern "C" int lrsdp_k_admm(lrsdp_ctx *c, const lrsdp_problem *p, int prec, void
     int rc;
     if ((rc = check_problem(p)) || (rc = check_prec(prec)) || (rc = check_ld(prec, ld))) return rc;
     const int pr = prec == LRSDP_F64 ? LRSDP_F64 : LRSDP_F32;
+    if (p->info.kind == LRSDP_GENERAL)
+        return set_error(LRSDP_EUNSUPPORTED, "the splitting phase is implemented for MaxCut and completion problems");
     if (p->info.kind == LRSDP_MAXCUT) {
         for (int k = 0; k < iters; ++k)
             if ((rc = admm_iter(c->stream, p->csr, pr, U, V, ld, y, sigma))) return rc;

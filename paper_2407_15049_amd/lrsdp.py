@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(_HERE, "_lib", "liblrsdp.so")
 OK, NOT_CONVERGED = 0, 1
 EINVAL, ENOMEM, EHIP, ENUMERIC, EUNSUPPORTED = -1, -2, -3, -4, -5
 F64, F32, F32_BF16IN = 0, 1, 2
-MAXCUT, COMPLETION = 1, 2
+MAXCUT, COMPLETION, GENERAL = 1, 2, 3
 
 
 class LrsdpUnavailable(ImportError):
@@ -91,6 +91,7 @@ _SIGS = {
     "lrsdp_ctx_destroy": (None, [_P]),
     "lrsdp_problem_maxcut": (C.c_int, [_I64, _I64, _P, _P, _P, C.POINTER(_P)]),
     "lrsdp_problem_completion": (C.c_int, [_I64, _I64, _I64, _P, _P, _P, C.POINTER(_P)]),
+    "lrsdp_problem_general": (C.c_int, [_I64, _I64, _P, _P, _P, _I64, _I64, _P, _P, _P, _P, _P, C.POINTER(_P)]),
     "lrsdp_problem_destroy": (None, [_P]),
     "lrsdp_problem_get_info": (C.c_int, [_P, C.POINTER(ProblemInfo)]),
     "lrsdp_problem_device_bytes": (C.c_int, [_P, C.POINTER(C.c_size_t)]),
@@ -232,6 +233,26 @@ class Problem:
         ma, mp = _host(Mij, np.float64)
         h = C.c_void_p()
         _check(lib.lrsdp_problem_completion(int(n1), int(n2), len(ia), ip, jp, mp, C.byref(h)))
+        return cls(h)
+
+    @classmethod
+    def general(cls, n, c_row, c_col, c_val, m, a_con, a_row, a_col, a_val, b):
+        """min <C, X> s.t. <A_k, X> = b_k: C and the A_k as triplets, each
+        off-diagonal entry given once (it stands for both (r, c) and (c, r))."""
+        lib = load()
+        cr, crp = _host(c_row, np.int32)
+        cc, ccp = _host(c_col, np.int32)
+        cv, cvp = _host(c_val, np.float64)
+        ak, akp = _host(a_con, np.int32)
+        ar, arp = _host(a_row, np.int32)
+        ac, acp = _host(a_col, np.int32)
+        av, avp = _host(a_val, np.float64)
+        bb, bp = _host(b, np.float64)
+        if not (len(cr) == len(cc) == len(cv)) or not (len(ak) == len(ar) == len(ac) == len(av)) or len(bb) != m:
+            raise ValueError("triplet arrays of different lengths, or len(b) != m")
+        h = C.c_void_p()
+        _check(lib.lrsdp_problem_general(int(n), len(cr), crp, ccp, cvp, int(m), len(ak), akp, arp, acp, avp, bp,
+                                         C.byref(h)))
         return cls(h)
 
     @property

@@ -14,3 +14,5 @@ from .graphs import (  # noqa: F401
     maxcut_instance,
     MAXCUT_CONFIGS,
 )
+from .general import (cycle_edges, petersen_edges, random_box_triplets, random_general_triplets,  # noqa: F401
+                      theta_triplets)

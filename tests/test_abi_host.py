@@ -159,3 +159,40 @@ def test_reopt_option_validation():
     # strict level: the multipliers of the original problem and the certificate's workspace
     cert = L.certify_workspace_bytes(p, 300)
     assert L.workspace_bytes(p, L.default_options(prec=L.F64, rank=4, ld=4, reopt=2)) >= base + cert + 50 * 8
+
+
+def test_general_problem_build_and_validation():
+    from oracle.problem import general_problem
+    from synth import random_general_triplets
+    cr, cc, cv, m, ak, ar, ac, av, W = random_general_triplets(40, 25, 3, 60, 2, 9)
+    b = np.arange(m, dtype=np.float64) - 3.0
+    p = L.Problem.general(40, cr, cc, cv, m, ak, ar, ac, av, b)
+    op = general_problem(40, cr, cc, cv, m, ak, ar, ac, av, b)
+    info = p.info
+    assert info.kind == L.GENERAL and info.n == 40 and info.m == m
+    # symmetric pattern of Omega: the positions of C's and the constraints' triplets
+    pos = {(min(a, c), max(a, c)) for a, c in zip(list(cr) + list(ar), list(cc) + list(ac))}
+    assert info.nnz == sum(1 if a == c else 2 for a, c in pos)
+    assert info.c_l1 == pytest.approx(op.c_l1, rel=1e-14)
+    assert info.b_l1 == pytest.approx(np.abs(b).sum()) and info.b_inf == pytest.approx(np.abs(b).max())
+    bad = [
+        dict(c_row=[40]), dict(a_row=[-1]), dict(a_con=[m]), dict(c_val=[np.nan]), dict(b=np.full(m, np.inf)),
+    ]
+    for kw in bad:
+        args = dict(c_row=cr, c_col=cc, c_val=cv, a_con=ak, a_row=ar, a_col=ac, a_val=av, b=b)
+        for k, v in kw.items():
+            if k == "b":
+                args[k] = v
+            else:
+                a = np.array(args[k], copy=True)
+                a[0] = v[0]
+                args[k] = a
+        with pytest.raises(L.LrsdpError) as e:
+            L.Problem.general(40, args["c_row"], args["c_col"], args["c_val"], m, args["a_con"], args["a_row"],
+                              args["a_col"], args["a_val"], args["b"])
+        assert e.value.code == L.EINVAL, kw
+    for kw in (dict(phase2=1), dict(precond=1)):
+        with pytest.raises(L.LrsdpError) as e:
+            L.workspace_bytes(p, L.default_options(prec=L.F64, rank=4, ld=4, **kw))
+        assert e.value.code == L.EUNSUPPORTED, kw
+    assert L.workspace_bytes(p, L.default_options(prec=L.F64, rank=4, ld=4, reopt=2)) > 0

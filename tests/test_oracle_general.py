@@ -1,0 +1,114 @@
+"""Oracle general problems (one block, sparse C and A_k from triplets) against
+independent references.
+
+* The MaxCut and completion SDPs written as general triplets give the same
+  constraint map, adjoint and objective as their dedicated constructors.
+* Triplet convention: an off-diagonal entry may be given in either triangle,
+  and repeated entries add up.
+* Closed forms of the Lovasz theta number (Lovasz 1979): the theta SDP's
+  optimum is -theta, with theta(C_n) = n cos(pi/n) / (1 + cos(pi/n)) for odd n
+  (sqrt 5 for the pentagon), theta(Petersen) = 4, theta(K_n) = 1 and
+  theta of the edgeless graph = n.
+* A random feasible instance solves to a point whose dual slack
+  C - A*(y) is psd up to the tolerance (a certified optimum).
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+from oracle import certify
+from oracle.alm import Options, alm_solve
+from oracle.problem import completion_problem, general_problem, maxcut_problem
+from synth import (completion_instance, cycle_edges, erdos_renyi_edges, init_factor, petersen_edges,
+                   random_general_triplets, theta_triplets)
+
+
+def maxcut_triplets(n, u, v, w):
+    deg = np.zeros(n)
+    np.add.at(deg, u, w)
+    np.add.at(deg, v, w)
+    c_row = np.concatenate([u, np.arange(n)])
+    c_col = np.concatenate([v, np.arange(n)])
+    c_val = np.concatenate([0.25 * w, -0.25 * deg])     # C = -L/4
+    k = np.arange(n)
+    return c_row, c_col, c_val, n, k, k, k, np.ones(n), np.ones(n)
+
+
+def same_problem(p, q, rng):
+    U = rng.standard_normal((p.n, 4))
+    V = rng.standard_normal((p.n, 4))
+    y = rng.standard_normal(p.m)
+    assert np.allclose(p.A_of(U, V), q.A_of(U, V), rtol=1e-13, atol=1e-12)
+    assert np.allclose((p.A_adj(y) @ V), (q.A_adj(y) @ V), rtol=1e-13, atol=1e-12)
+    assert p.objective(U, V) == pytest.approx(q.objective(U, V), rel=1e-13)
+    assert p.c_l1 == pytest.approx(q.c_l1, rel=1e-14)
+    assert np.array_equal(p.b, q.b)
+
+
+def test_maxcut_as_general():
+    u, v = erdos_renyi_edges(70, 300, 3)
+    w = np.random.default_rng(4).uniform(-1, 2, 300)
+    same_problem(general_problem(70, *maxcut_triplets(70, u, v, w)), maxcut_problem(70, u, v, w),
+                 np.random.default_rng(5))
+
+
+def test_completion_as_general():
+    n1, n2 = 20, 15
+    i, j, M, _, _ = completion_instance(n1, n2, 2, 5, seed=6)
+    n = n1 + n2
+    m = len(i)
+    c_row = c_col = np.arange(n)
+    g = general_problem(n, c_row, c_col, np.ones(n), m, np.arange(m), i, n1 + j, np.ones(m), 2 * M)
+    same_problem(g, completion_problem(n1, n2, i, j, M), np.random.default_rng(7))
+
+
+def test_triplet_convention():
+    rng = np.random.default_rng(8)
+    n, m = 12, 3
+    a_con = np.array([0, 1, 1, 2])
+    a_row = np.array([3, 0, 5, 7])
+    a_col = np.array([9, 0, 2, 7])
+    a_val = np.array([1.5, 2.0, -1.0, 0.5])
+    b = np.array([1.0, 2.0, 3.0])
+    p = general_problem(n, [1, 4], [4, 4], [2.0, -1.0], m, a_con, a_row, a_col, a_val, b)
+    # the other triangle, and an entry split into two triplets that add up
+    q = general_problem(n, [4, 4, 4], [1, 1, 4], [0.5, 1.5, -1.0], m, a_con, a_col, a_row, a_val, b)
+    same_problem(p, q, rng)
+    # <A_0, X> = 1.5 (X_39 + X_93) for X = U V^T
+    U, V = rng.standard_normal((n, 3)), rng.standard_normal((n, 3))
+    X = U @ V.T
+    assert p.A_of(U, V)[0] == pytest.approx(1.5 * (X[3, 9] + X[9, 3]), rel=1e-14)
+    assert p.A_of(U, V)[1] == pytest.approx(2.0 * X[0, 0] - (X[5, 2] + X[2, 5]), rel=1e-13)
+
+
+def theta(n, u, v, rank, tol=1e-8):
+    op = general_problem(n, *theta_triplets(n, u, v))
+    res = alm_solve(op, init_factor(n, rank, 3), opts=Options(tol=tol))
+    assert res.converged
+    return -res.obj
+
+
+@pytest.mark.parametrize("n", [5, 7, 9])
+def test_theta_odd_cycle(n):
+    u, v = cycle_edges(n)
+    c = math.cos(math.pi / n)
+    assert theta(n, u, v, 6) == pytest.approx(n * c / (1 + c), rel=1e-6)
+
+
+def test_theta_petersen_complete_and_empty():
+    u, v = petersen_edges()
+    assert theta(10, u, v, 6) == pytest.approx(4.0, rel=1e-6)
+    iu = np.triu_indices(6, 1)
+    assert theta(6, iu[0], iu[1], 6) == pytest.approx(1.0, rel=1e-6)
+    assert theta(8, np.zeros(0, np.int32), np.zeros(0, np.int32), 3) == pytest.approx(8.0, rel=1e-6)
+
+
+def test_random_general_reaches_a_certified_optimum():
+    cr, cc, cv, m, ak, ar, ac, av, W = random_general_triplets(60, 40, 4, 120, 3, 5)
+    op = general_problem(60, cr, cc, cv, m, ak, ar, ac, av, np.zeros(m))
+    op = general_problem(60, cr, cc, cv, m, ak, ar, ac, av, op.A_of(W))
+    res = alm_solve(op, init_factor(60, 10, 4), opts=Options())
+    assert res.converged and res.err1 <= 1e-5 and abs(res.err3) <= 1e-5
+    assert certify.lambda_min(op, res.y) >= -1e-5 * (1 + op.c_l1)
