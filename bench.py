@@ -60,6 +60,10 @@ def parse():
     ap.add_argument("--completion", action="store_true",
                     help="instead of the MaxCut step: time the matrix-completion kernels (SDDMM constraint map, "
                          "gradient SpMM) and 300 L-BFGS iterations at n1 = n2 = 5e5, m = 1e7, rank 16")
+    ap.add_argument("--general", action="store_true",
+                    help="instead of the MaxCut step: time the general-problem kernels (compressed constraint map, "
+                         "C - A*(y) SpMM) and a full solve of a general SDP with n = 1e6 (diag(X) = 1 plus 1000 "
+                         "side constraints, 5e6 random objective entries, rank 16)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device-to-device copy three times (counter calibration)")
     return ap.parse_args()
@@ -109,6 +113,8 @@ def main():
     ctx = L.Context(0)
     if args.completion:
         return completion_bench(args, ctx, dev)
+    if args.general:
+        return general_bench(args, ctx, dev)
     names = args.instances.split(",")
     runs = []
     for name in names:
@@ -448,6 +454,106 @@ def completion_bench(args, ctx, dev):
         "unit": "GB/s", "n_gpus": 1, "dtype": "f64,f32", "data": "synthetic",
         "config": {"workload": "matrix completion n1=n2=5e5 (X of order 1e6), m=1e7 samples (20 per row), "
                                "planted rank 5, factor rank 16", **cfg},
+        "kernels": out}), flush=True)
+
+
+GENERAL = dict(n=1_000_000, c_nnz=5_000_000, extra=1000, per_con=5, rank=16, seed=15052)
+
+
+def general_instance(cfg):
+    """Triplets of the general benchmark SDP: a symmetric objective with c_nnz
+    N(0, 1) entries at uniform positions, diag(X) = 1, and `extra` side
+    constraints on `per_con` off-diagonal positions each with N(0, 1)
+    coefficients and right-hand side 0 (X = I is feasible)."""
+    import numpy as np
+    g = np.random.Generator(np.random.PCG64(cfg["seed"]))
+    n = cfg["n"]
+    c_row = g.integers(0, n, cfg["c_nnz"]).astype(np.int32)
+    c_col = g.integers(0, n, cfg["c_nnz"]).astype(np.int32)
+    c_val = g.standard_normal(cfg["c_nnz"])
+    k = np.repeat(np.arange(n, n + cfg["extra"], dtype=np.int32), cfg["per_con"])
+    rr = g.integers(0, n, k.size).astype(np.int32)
+    cc = ((rr + 1 + g.integers(0, n - 1, k.size)) % n).astype(np.int32)     # off the diagonal
+    diag = np.arange(n, dtype=np.int32)
+    a_con = np.concatenate([diag, k])
+    a_row = np.concatenate([diag, rr])
+    a_col = np.concatenate([diag, cc])
+    a_val = np.concatenate([np.ones(n), g.standard_normal(k.size)])
+    m = n + cfg["extra"]
+    b = np.concatenate([np.ones(n), np.zeros(cfg["extra"])])
+    return c_row, c_col, c_val, m, a_con, a_row, a_col, a_val, b
+
+
+def general_bench(args, ctx, dev):
+    """Kernel bandwidth of the general-problem path (compressed outer product +
+    constraint rows, C - A*(y) SpMM on Omega) with HIP events on the library's
+    stream, and a full solve to 1e-5, in float64 and float32."""
+    import numpy as np
+    import torch
+
+    from paper_2407_15049_amd import lrsdp as L
+    from synth import init_factor
+
+    cfg = GENERAL
+    t0 = time.perf_counter()
+    prob = L.Problem.general(cfg["n"], *general_instance(cfg)).upload(ctx)
+    inf = prob.info
+    n, m, r, nnz_s = inf.n, inf.m, cfg["rank"], inf.nnz
+    nom = (nnz_s + n) // 2                  # positions: each off-diagonal one is stored twice, all n diagonals once
+    nnz_a = n + cfg["extra"] * cfg["per_con"]
+    log(f"general n={n} m={m} |Omega|={nom} symmetric nnz={nnz_s} setup {time.perf_counter() - t0:.1f}s")
+    stream = torch.cuda.current_stream(dev)
+    out = {}
+    reps = 20
+    for prec, name in [(L.F64, "f64"), (L.F32, "f32")]:
+        ld = L.padded_ld(r, prec)
+        w = 8 if prec == L.F64 else 4
+        R = torch.zeros((n, ld), dtype=L.elem_dtype(prec), device=dev)
+        R[:, :r] = torch.from_numpy(init_factor(n, r, cfg["seed"] + 1)).to(dev, R.dtype)
+        y = torch.from_numpy(np.random.default_rng(cfg["seed"] + 2).standard_normal(m) * 0.1).to(dev)
+        acon = torch.empty(m, dtype=torch.float64, device=dev)
+        Y = torch.empty_like(R)
+
+        def timed(fn):
+            for _ in range(3):
+                fn()
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            ev[0].record(stream)
+            for _ in range(reps):
+                fn()
+            ev[1].record(stream)
+            torch.cuda.synchronize()
+            return ev[0].elapsed_time(ev[1]) * 1e3 / reps      # us per launch
+
+        t_map = timed(lambda: L.k_constraint(ctx, prob, prec, R, R, acon))
+        t_spmm = timed(lambda: L.k_spmm(ctx, prob, prec, R, y, Y))
+        # algorithmic bytes: every array once, R read once
+        b_map = 8.0 * nom + 8.0 * nom + n * ld * w + 4.0 * (m + 1) + 12.0 * nnz_a + 8.0 * nom + 8.0 * m
+        b_spmm = (4.0 * (n + 1) + 8.0 * nnz_s + 8.0 * nom + 4.0 * (nom + 1) + 12.0 * nnz_a + 8.0 * m
+                  + 2.0 * n * ld * w)
+        opts = L.default_options(prec=prec, rank=r, ld=ld, time_limit_s=120.0)
+        R0 = R.clone()
+        y0 = torch.zeros(m, dtype=torch.float64, device=dev)
+        ws = torch.empty(L.workspace_bytes(prob, opts), dtype=torch.uint8, device=dev)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        rc, res = L.solve(ctx, prob, R0, y0, opts, workspace=ws)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        out[name] = dict(
+            map_us=round(t_map, 2), map_alg_bytes=b_map, map_gbs=round(b_map / t_map / 1e3, 1),
+            map_frac=round(b_map / t_map / 1e3 / HBM_PEAK_GBS, 4),
+            spmm_us=round(t_spmm, 2), spmm_alg_bytes=b_spmm, spmm_gbs=round(b_spmm / t_spmm / 1e3, 1),
+            spmm_frac=round(b_spmm / t_spmm / 1e3 / HBM_PEAK_GBS, 4),
+            solve_s=round(dt, 3), converged=rc == L.OK, outer=res.outer, iters=res.inner,
+            ms_per_iter=round(1e3 * dt / max(res.inner, 1), 3), obj=res.obj, err1=res.err1, err3=res.err3)
+        log(f"general {name}: {out[name]}")
+        del R, Y, R0, ws
+    print(json.dumps({
+        "metric": "general SDP: compressed constraint map / C - A*(y) SpMM algorithmic GB/s and time to 1e-5",
+        "unit": "GB/s", "n_gpus": 1, "dtype": "f64,f32", "data": "synthetic",
+        "config": {"workload": "general SDP n=1e6: 5e6 random N(0,1) objective entries, diag(X)=1 plus 1000 "
+                               "side constraints on 5 off-diagonal positions each (b = 0), rank 16", **cfg},
         "kernels": out}), flush=True)
 
 

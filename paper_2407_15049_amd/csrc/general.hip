@@ -10,10 +10,11 @@
 //   k_gen_cons  one thread per constraint: its row of the stacked matrix
 //               (nonzero columns only) times xbar, plus the line-search or
 //               ALM row terms.
-// The operator C - A*(y) is applied by k_gen_spmm on the symmetric pattern of
-// Omega; the value of each stored entry, cs C_o - sum_k A_k,o y_k, is formed
-// on the fly from the transposed stacked matrix (eq. At with the index set
-// Omega), so no n x n or |Omega| buffer is written per call.
+// The operator C - A*(y) is applied on the symmetric pattern of Omega in two
+// passes: k_gen_sv streams over the positions and forms their values
+// cs C_o - sum_k A_k,o y_k from the transposed stacked matrix (eq. At with the
+// index set Omega) into the problem's second compressed buffer, then
+// k_gen_spmm gathers one value and one row of V per stored entry.
 #include <algorithm>
 
 #include "device.h"
@@ -147,17 +148,24 @@ struct GenSpmmArgs {
     double *partials;
 };
 
-// value of C - A*(ytil) at position o (objective scale cs)
-__device__ __forceinline__ double gen_value(const DevGeneral &P, int32_t o, const double *ytil, double cs) {
-    double v = cs * P.cval[o];
-    if (ytil)
-        for (int t = P.at_ptr[o]; t < P.at_ptr[o + 1]; ++t) v = fma(-P.at_val[t], ytil[P.at_idx[t]], v);
-    return v;
+// x2[o] = value of cs C - A*(ytil) at position o (skipped when st says the
+// subproblem is finished)
+__global__ __launch_bounds__(kBlock) void k_gen_sv(DevGeneral P, const double *ytil, double cs,
+                                                   const SolverState *st) {
+    if (st && st->done) return;
+    for (int64_t o = (int64_t)blockIdx.x * kBlock + threadIdx.x; o < P.nom; o += (int64_t)gridDim.x * kBlock) {
+        double v = cs * P.cval[o];
+        if (ytil)
+            for (int t = P.at_ptr[o]; t < P.at_ptr[o + 1]; ++t) v = fma(-P.at_val[t], ytil[P.at_idx[t]], v);
+        P.x2[o] = v;
+    }
 }
 
 // GRAD = false: Y = (cs C - A*(ytil)) V.  GRAD = true: G_{k+1} = 2 (cs C - A*(ytil)) R
-// into G slot (gk+1) mod (T+1), plus its dots with every ring slot.
-template <typename S, int GS, bool GRAD>
+// into G slot (gk+1) mod (T+1), plus its dots with every ring slot.  TM: the
+// largest memory the instance handles (T <= TM); the ring loops run to TM, so
+// the common T <= 2 build keeps its ring pointers in registers.
+template <typename S, int GS, bool GRAD, int TM>
 __global__ __launch_bounds__(kBlock) void k_gen_spmm(DevGeneral P, GenSpmmArgs<S> a) {
     using CV = typename Chunk<S>::V;
     constexpr int NV = Chunk<S>::N;
@@ -169,7 +177,7 @@ __global__ __launch_bounds__(kBlock) void k_gen_spmm(DevGeneral P, GenSpmmArgs<S
         T = a.st->T;
         gk1 = a.force_slot >= 0 ? a.force_slot : (a.st->gk + 1) % (T + 1);
 #pragma unroll
-        for (int g = 0; g <= kMaxMem; ++g)
+        for (int g = 0; g <= TM; ++g)
             if (g == gk1) Gn = a.rings.g[g];
     }
     const int lane = threadIdx.x % GS, grp = threadIdx.x / GS;
@@ -189,7 +197,7 @@ __global__ __launch_bounds__(kBlock) void k_gen_spmm(DevGeneral P, GenSpmmArgs<S
             for (int q = 0; q < 4; ++q) {
                 v[q] = active ? *reinterpret_cast<const CV *>(a.V + (int64_t)P.s_col[e + q] * a.ld + lane * NV)
                               : zero;
-                w[q] = gen_value(P, P.s_om[e + q], a.ytil, a.cs);
+                w[q] = P.x2[P.s_om[e + q]];
             }
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -201,7 +209,7 @@ __global__ __launch_bounds__(kBlock) void k_gen_spmm(DevGeneral P, GenSpmmArgs<S
         for (; e < e1; ++e) {
             const CV v0 = active ? *reinterpret_cast<const CV *>(a.V + (int64_t)P.s_col[e] * a.ld + lane * NV)
                                  : zero;
-            const double w0 = gen_value(P, P.s_om[e], a.ytil, a.cs);
+            const double w0 = P.x2[P.s_om[e]];
             const D4 vq = widen(v0);
 #pragma unroll
             for (int c = 0; c < 4; ++c) acc.v[c] = fma(w0, vq.v[c], acc.v[c]);
@@ -217,14 +225,14 @@ __global__ __launch_bounds__(kBlock) void k_gen_spmm(DevGeneral P, GenSpmmArgs<S
         } else {
             if (active) *reinterpret_cast<CV *>(Gn + off) = os;
 #pragma unroll
-            for (int g = 0; g <= kMaxMem; ++g) {
+            for (int g = 0; g <= TM; ++g) {
                 if (g <= T) {
                     CV bsl = (g == gk1) ? os : (active ? *reinterpret_cast<const CV *>(a.rings.g[g] + off) : zero);
                     s[g] += vdot(os, bsl);
                 }
             }
 #pragma unroll
-            for (int d = 0; d < kMaxMem; ++d) {
+            for (int d = 0; d < TM; ++d) {
                 if (d < T) {
                     CV bsl = active ? *reinterpret_cast<const CV *>(a.rings.d[d] + off) : zero;
                     s[kMaxMem + 1 + d] += vdot(os, bsl);
@@ -275,15 +283,26 @@ int sddmm_t(hipStream_t s, const DevGeneral &P, const void *U, const void *V, in
     return LRSDP_OK;
 }
 
-template <typename S, bool GRAD>
-int gen_spmm_t(hipStream_t s, const DevGeneral &P, const GenSpmmArgs<S> &a, int *nb) {
+template <typename S, bool GRAD, int TM>
+int gen_spmm_tm(hipStream_t s, const DevGeneral &P, const GenSpmmArgs<S> &a, int *nb) {
+    // values first (the gradient call of a finished subproblem skips both)
+    const SolverState *skip = (GRAD && a.force_slot < 0) ? a.st : nullptr;
+    hipLaunchKernelGGL(k_gen_sv, dim3(gen_grid(P.nom, kBlock)), dim3(kBlock), 0, s, P, a.ytil, a.cs, skip);
     const int gs = gs_of_gen<S>(a.ld);
     *nb = gen_grid(P.n, kBlock / gs);
-    if (gs == 4) hipLaunchKernelGGL((k_gen_spmm<S, 4, GRAD>), dim3(*nb), dim3(kBlock), 0, s, P, a);
-    else if (gs == 8) hipLaunchKernelGGL((k_gen_spmm<S, 8, GRAD>), dim3(*nb), dim3(kBlock), 0, s, P, a);
-    else hipLaunchKernelGGL((k_gen_spmm<S, 16, GRAD>), dim3(*nb), dim3(kBlock), 0, s, P, a);
+    if (gs == 4) hipLaunchKernelGGL((k_gen_spmm<S, 4, GRAD, TM>), dim3(*nb), dim3(kBlock), 0, s, P, a);
+    else if (gs == 8) hipLaunchKernelGGL((k_gen_spmm<S, 8, GRAD, TM>), dim3(*nb), dim3(kBlock), 0, s, P, a);
+    else hipLaunchKernelGGL((k_gen_spmm<S, 16, GRAD, TM>), dim3(*nb), dim3(kBlock), 0, s, P, a);
     LRSDP_CHECK_LAUNCH();
     return LRSDP_OK;
+}
+
+// T: L-BFGS memory of the gradient call (0 for the plain SpMM)
+template <typename S, bool GRAD>
+int gen_spmm_t(hipStream_t s, const DevGeneral &P, const GenSpmmArgs<S> &a, int *nb, int T = 0) {
+    if (!GRAD) return gen_spmm_tm<S, false, 0>(s, P, a, nb);
+    if (T <= 2) return gen_spmm_tm<S, GRAD, 2>(s, P, a, nb);
+    return gen_spmm_tm<S, GRAD, kMaxMem>(s, P, a, nb);
 }
 
 }  // namespace
@@ -327,12 +346,12 @@ int gen_grad(hipStream_t s, const DevGeneral &P, int prec, const SolverState *st
         GenSpmmArgs<double> a{(const double *)R, nullptr, ytil, cs, ld, st, force_slot, {}, partials};
         for (int g = 0; g <= T; ++g) a.rings.g[g] = (double *)gring[g];
         for (int d = 0; d < T; ++d) a.rings.d[d] = (double *)dring[d];
-        return gen_spmm_t<double, true>(s, P, a, nb);
+        return gen_spmm_t<double, true>(s, P, a, nb, T);
     }
     GenSpmmArgs<float> a{(const float *)R, nullptr, ytil, cs, ld, st, force_slot, {}, partials};
     for (int g = 0; g <= T; ++g) a.rings.g[g] = (float *)gring[g];
     for (int d = 0; d < T; ++d) a.rings.d[d] = (float *)dring[d];
-    return gen_spmm_t<float, true>(s, P, a, nb);
+    return gen_spmm_t<float, true>(s, P, a, nb, T);
 }
 
 }  // namespace lrsdp

@@ -97,8 +97,9 @@ struct DevGeneral {
     const int32_t *s_col = nullptr;     // nnz_s: column
     const int32_t *s_om = nullptr;      // nnz_s: Omega index of the entry
     const double *b = nullptr;          // m
-    double *x1 = nullptr;               // |Omega| compressed outer products (problem-owned scratch:
-    double *x2 = nullptr;               // calls on one problem must not overlap)
+    double *x1 = nullptr;               // |Omega| compressed outer products, and (x2) the values of
+    double *x2 = nullptr;               // C - A*(y) for the SpMM (problem-owned scratch: calls on one
+                                        // problem must not overlap)
     int64_t n = 0, m = 0, nom = 0, nnz_a = 0, nnz_s = 0;
 };
 
