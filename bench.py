@@ -30,8 +30,8 @@ HBM_PEAK_GBS = 8000.0
 WORKLOAD = ("maxcut n=1e6 pair: Erdos-Renyi 5e6 edges + Chung-Lu beta=2.5 mean degree 10 (5e6 edges), "
             "weights uniform in {-1,+1}, C=-L/4, diag(X)=1, rank 20")
 INSTANCES = ["er_1m_pm1", "cl_1m_pm1"]
-ALL_PATHS = ["f64_precond", "f64_dynrank", "f64_reopt", "f64_reopt2", "f32", "f32_precond", "f32_bf16in",
-             "f32_warm", "f32_precond_warm", "f32_dynrank_precond"]
+ALL_PATHS = ["f64_degsort", "f64_precond", "f64_dynrank", "f64_reopt", "f64_reopt2", "f32", "f32_precond",
+             "f32_bf16in", "f32_warm", "f32_precond_warm", "f32_dynrank_precond"]
 DYNRANK_LD = {0: 30, 1: 32}       # row stride with room for the grown rank (FP64, FP32)
 OTHER_WORKLOADS = {
     "cl_10m": "maxcut n=1e7 Chung-Lu beta=2.5 mean degree 8 (4e7 edges), unit weights, C=-L/4, diag(X)=1, rank 24",
@@ -242,6 +242,32 @@ def main():
         del ws
         return dt, rc, res
 
+    if "f64_degsort" in enabled:
+        # the same graphs with nodes relabelled by decreasing degree (hubs first):
+        # the locality counterpart of the random labels of the timed step; the
+        # starting factor is permuted with the nodes, so the solve is the same
+        # problem up to the order of summation
+        import numpy as np
+        for run in runs:
+            inst, n = run["inst"], run["n"]
+            deg = np.bincount(inst["u"], minlength=n) + np.bincount(inst["v"], minlength=n)
+            order = np.argsort(-deg, kind="stable")            # new node k is old node order[k]
+            new_id = np.empty(n, dtype=np.int64)
+            new_id[order] = np.arange(n)
+            prob2 = L.Problem.maxcut(n, new_id[inst["u"]], new_id[inst["v"]], inst["w"]).upload(ctx)
+            p = run["per"][L.F64]
+            o = L.default_options(prec=L.F64, rank=run["r"], ld=p["opts"].ld, profile=1, verbose=int(args.verbose))
+            ws = torch.empty(L.workspace_bytes(prob2, o), dtype=torch.uint8, device=dev)
+            R = p["R0"][torch.from_numpy(order).to(dev)].contiguous()
+            y = torch.zeros(n, dtype=torch.float64, device=dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rc, res = L.solve(ctx, prob2, R, y, o, workspace=ws)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            y_orig = y[torch.from_numpy(new_id).to(dev)].contiguous()     # back to the original labels
+            record("f64_degsort", run, dt, res, dict(converged=rc == L.OK), y=y_orig)
+            del prob2, ws, R, y, y_orig
     if "f64_precond" in enabled:
         # row-block H0 for Algorithm 1 (an extension; the timed step keeps H0 = I)
         for run in runs:
@@ -344,6 +370,28 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         log("copy calibration: 3 x 1 GiB device-to-device copies")
+        del a, b
+
+    # copy ceiling of the box: a 1 GiB device-to-device copy, read + write bytes
+    # over its HIP-event time (median of 10)
+    copy_gbs = None
+    if step_times:
+        a = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        stream = torch.cuda.current_stream(dev)
+        for _ in range(3):
+            b.copy_(a)
+        times = []
+        for _ in range(10):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            b.copy_(a)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1) / 1e3)
+        copy_gbs = round(2.0 * (1 << 30) / 1e9 / sorted(times)[len(times) // 2], 1)
+        log(f"copy ceiling: {copy_gbs} GB/s")
+        del a, b
 
     cpu = None
     if not args.no_cpu_baseline and step_times:
@@ -378,6 +426,7 @@ def main():
             "avg_us": round(1e3 * spmm_ms / max(spmm_n, 1), 2),
             "alg_bytes_per_launch": {run["name"]: recs[run["name"]][-1][1].spmm_bytes for run in runs
                                      if recs[run["name"]]},
+            "copy_ceiling_gbs": copy_gbs,
         },
         "cpu_baseline": cpu,
         "paths": paths,
