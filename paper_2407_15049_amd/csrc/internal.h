@@ -103,6 +103,10 @@ struct DevGeneral {
     int64_t n = 0, m = 0, nom = 0, nnz_a = 0, nnz_s = 0;
 };
 
+// General problem: Y = (C - A*(ytil)) V on the symmetric pattern of Omega.
+int spmm_general(hipStream_t s, const DevGeneral &P, int prec, const void *V, int64_t ld, const double *ytil,
+                 void *Y);
+
 }  // namespace lrsdp
 
 struct lrsdp_problem {

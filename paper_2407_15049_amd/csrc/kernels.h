@@ -103,10 +103,6 @@ int spmm_maxcut(hipStream_t s, const DevCsr &P, int prec, const SpmmArgs &a, int
 int spmm_completion(hipStream_t s, const DevCompletion &P, int prec, const void *V, int64_t ld,
                     const double *ytil, void *Y);
 
-// General problem: Y = (C - A*(ytil)) V on the symmetric pattern of Omega.
-int spmm_general(hipStream_t s, const DevGeneral &P, int prec, const void *V, int64_t ld, const double *ytil,
-                 void *Y);
-
 // Row stride (elements) of the bfloat16 copy of an n x ld float32 array:
 // ld rounded up to a multiple of 8 (16-byte rows).
 inline int64_t bf16_ld(int64_t ld) { return (ld + 7) / 8 * 8; }
