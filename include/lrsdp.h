@@ -125,6 +125,22 @@ int lrsdp_problem_general(int64_t n, int64_t c_nnz, const int32_t *c_row, const 
                           const int32_t *a_row, const int32_t *a_col, const double *a_val,
                           const double *b, lrsdp_problem **out);
 
+/* Several PSD blocks: min sum_j <C_j, X_j> s.t. sum_j <A_kj, X_j> = b_k, every
+ * X_j psd of order block_n[j] (a block of order 1 is a nonnegative scalar).
+ * Triplets as in lrsdp_problem_general with block-local indices and a block id
+ * per triplet (c_blk, a_blk).  The blocks are laid out one after another in a
+ * single factor R of order sum_j block_n[j] and one rank: the data touches no
+ * position between two blocks, so the entries of RR^T outside the diagonal
+ * blocks enter neither the objective nor the constraints, and RR^T psd makes
+ * every block psd.  Row offset of block j = sum_{i<j} block_n[i].  EINVAL for
+ * a bad block id or a local index outside its block.
+ */
+int lrsdp_problem_general_blocks(int64_t nblocks, const int64_t *block_n, int64_t c_nnz, const int32_t *c_blk,
+                                 const int32_t *c_row, const int32_t *c_col, const double *c_val, int64_t m,
+                                 int64_t a_nnz, const int32_t *a_con, const int32_t *a_blk, const int32_t *a_row,
+                                 const int32_t *a_col, const double *a_val, const double *b,
+                                 lrsdp_problem **out);
+
 void lrsdp_problem_destroy(lrsdp_problem *prob);
 
 typedef struct {

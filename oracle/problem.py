@@ -134,3 +134,39 @@ def general_problem(n: int, c_row, c_col, c_val, m: int, a_con, a_row, a_col, a_
         np.concatenate([a_col, a_row[off]]), np.concatenate([a_val, a_val[off]]))
     return SDPProblem(n=n, m=m, C=C, col_a=col_a, col_b=col_b, Abar=Abar,
                       b=np.asarray(b, dtype=np.float64), kind="general")
+
+
+def general_blocks_problem(block_n, c_blk, c_row, c_col, c_val, m, a_con, a_blk, a_row, a_col, a_val,
+                           b) -> SDPProblem:
+    """Several PSD blocks: min sum_j <C_j, X_j> s.t. sum_j <A_kj, X_j> = b_k, read
+    as one problem in X = diag(X_1, ..., X_p) with C = diag(C_j) and
+    A_k = diag(A_kj) (block_diag of the per-block matrices; the triplet
+    convention of general_problem inside each block)."""
+    block_n = [int(x) for x in block_n]
+    c_blk, c_row, c_col, c_val = (np.asarray(x) for x in (c_blk, c_row, c_col, c_val))
+    a_con, a_blk, a_row, a_col, a_val = (np.asarray(x) for x in (a_con, a_blk, a_row, a_col, a_val))
+
+    def sym(r, c, v, nj):
+        off = r != c
+        M = sp.csr_matrix((np.concatenate([v, v[off]]), (np.concatenate([r, c[off]]), np.concatenate([c, r[off]]))),
+                          shape=(nj, nj))
+        M.sum_duplicates()
+        return M
+
+    C = sp.block_diag([sym(c_row[c_blk == j], c_col[c_blk == j], c_val[c_blk == j].astype(np.float64), nj)
+                       for j, nj in enumerate(block_n)], format="csr")
+    n = sum(block_n)
+    k_idx, a_idx, b_idx, vals = [], [], [], []
+    for k in range(m):
+        sel = a_con == k
+        Ak = sp.block_diag([sym(a_row[sel & (a_blk == j)], a_col[sel & (a_blk == j)],
+                                a_val[sel & (a_blk == j)].astype(np.float64), nj)
+                            for j, nj in enumerate(block_n)], format="coo")
+        k_idx.append(np.full(Ak.nnz, k))
+        a_idx.append(Ak.row)
+        b_idx.append(Ak.col)
+        vals.append(Ak.data)
+    col_a, col_b, Abar = _stack_constraints(n, m, np.concatenate(k_idx), np.concatenate(a_idx),
+                                            np.concatenate(b_idx), np.concatenate(vals))
+    return SDPProblem(n=n, m=m, C=C, col_a=col_a, col_b=col_b, Abar=Abar,
+                      b=np.asarray(b, dtype=np.float64), kind="general")

@@ -427,6 +427,49 @@ extern "C" int lrsdp_problem_general(int64_t n, int64_t c_nnz, const int32_t *c_
     return LRSDP_OK;
 }
 
+extern "C" int lrsdp_problem_general_blocks(int64_t nblocks, const int64_t *block_n, int64_t c_nnz,
+                                            const int32_t *c_blk, const int32_t *c_row, const int32_t *c_col,
+                                            const double *c_val, int64_t m, int64_t a_nnz, const int32_t *a_con,
+                                            const int32_t *a_blk, const int32_t *a_row, const int32_t *a_col,
+                                            const double *a_val, const double *b, lrsdp_problem **out) {
+    clear_error();
+    if (!out) return set_error(LRSDP_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (nblocks < 1 || !block_n) return set_error(LRSDP_EINVAL, "need at least one block");
+    if (c_nnz < 0 || a_nnz < 0) return set_error(LRSDP_EINVAL, "bad entry counts");
+    if ((c_nnz > 0 && (!c_blk || !c_row || !c_col)) || (a_nnz > 0 && (!a_blk || !a_row || !a_col)))
+        return set_error(LRSDP_EINVAL, "input arrays are NULL");
+    std::vector<int64_t> off(nblocks + 1, 0);
+    for (int64_t j = 0; j < nblocks; ++j) {
+        if (block_n[j] < 1) return set_error(LRSDP_EINVAL, "block %lld has order %lld", (long long)j,
+                                             (long long)block_n[j]);
+        off[j + 1] = off[j] + block_n[j];
+        if (off[j + 1] > INT32_MAX - 1) return set_error(LRSDP_EINVAL, "total order too large");
+    }
+    auto place = [&](int64_t cnt, const int32_t *blk, const int32_t *r, const int32_t *c, std::vector<int32_t> &gr,
+                     std::vector<int32_t> &gc, const char *what) -> int {
+        gr.resize(cnt);
+        gc.resize(cnt);
+        for (int64_t t = 0; t < cnt; ++t) {
+            const int32_t j = blk[t];
+            if (j < 0 || j >= nblocks)
+                return set_error(LRSDP_EINVAL, "%s entry %lld names block %d", what, (long long)t, j);
+            if (r[t] < 0 || r[t] >= block_n[j] || c[t] < 0 || c[t] >= block_n[j])
+                return set_error(LRSDP_EINVAL, "%s entry %lld = (%d, %d) outside block %d", what, (long long)t, r[t],
+                                 c[t], j);
+            gr[t] = (int32_t)(off[j] + r[t]);
+            gc[t] = (int32_t)(off[j] + c[t]);
+        }
+        return LRSDP_OK;
+    };
+    std::vector<int32_t> cr, cc, ar, ac;
+    int rc;
+    if ((rc = place(c_nnz, c_blk, c_row, c_col, cr, cc, "C"))) return rc;
+    if ((rc = place(a_nnz, a_blk, a_row, a_col, ar, ac, "A"))) return rc;
+    return lrsdp_problem_general(off[nblocks], c_nnz, cr.data(), cc.data(), c_val, m, a_nnz, a_con, ar.data(),
+                                 ac.data(), a_val, b, out);
+}
+
 namespace {
 
 struct Layout {

@@ -92,6 +92,8 @@ _SIGS = {
     "lrsdp_problem_maxcut": (C.c_int, [_I64, _I64, _P, _P, _P, C.POINTER(_P)]),
     "lrsdp_problem_completion": (C.c_int, [_I64, _I64, _I64, _P, _P, _P, C.POINTER(_P)]),
     "lrsdp_problem_general": (C.c_int, [_I64, _I64, _P, _P, _P, _I64, _I64, _P, _P, _P, _P, _P, C.POINTER(_P)]),
+    "lrsdp_problem_general_blocks": (C.c_int, [_I64, _P, _I64, _P, _P, _P, _P, _I64, _I64, _P, _P, _P, _P, _P, _P,
+                                               C.POINTER(_P)]),
     "lrsdp_problem_destroy": (None, [_P]),
     "lrsdp_problem_get_info": (C.c_int, [_P, C.POINTER(ProblemInfo)]),
     "lrsdp_problem_device_bytes": (C.c_int, [_P, C.POINTER(C.c_size_t)]),
@@ -253,6 +255,24 @@ class Problem:
         h = C.c_void_p()
         _check(lib.lrsdp_problem_general(int(n), len(cr), crp, ccp, cvp, int(m), len(ak), akp, arp, acp, avp, bp,
                                          C.byref(h)))
+        return cls(h)
+
+    @classmethod
+    def general_blocks(cls, block_n, c_blk, c_row, c_col, c_val, m, a_con, a_blk, a_row, a_col, a_val, b):
+        """Several PSD blocks laid out one after another in one factor; triplets
+        carry a block id and block-local indices."""
+        lib = load()
+        bn, bnp = _host(block_n, np.int64)
+        arrs = [_host(x, t) for x, t in ((c_blk, np.int32), (c_row, np.int32), (c_col, np.int32), (c_val, np.float64),
+                                         (a_con, np.int32), (a_blk, np.int32), (a_row, np.int32), (a_col, np.int32),
+                                         (a_val, np.float64), (b, np.float64))]
+        (cb, cbp), (cr, crp), (cc, ccp), (cv, cvp), (ak, akp), (ab, abp), (ar, arp), (ac, acp), (av, avp), (bb, bp) = arrs
+        if not (len(cb) == len(cr) == len(cc) == len(cv)) or not (len(ak) == len(ab) == len(ar) == len(ac) == len(av)) \
+                or len(bb) != m:
+            raise ValueError("triplet arrays of different lengths, or len(b) != m")
+        h = C.c_void_p()
+        _check(lib.lrsdp_problem_general_blocks(len(bn), bnp, len(cb), cbp, crp, ccp, cvp, int(m), len(ak), akp, abp,
+                                                arp, acp, avp, bp, C.byref(h)))
         return cls(h)
 
     @property

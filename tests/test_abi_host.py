@@ -196,3 +196,24 @@ def test_general_problem_build_and_validation():
             L.workspace_bytes(p, L.default_options(prec=L.F64, rank=4, ld=4, **kw))
         assert e.value.code == L.EUNSUPPORTED, kw
     assert L.workspace_bytes(p, L.default_options(prec=L.F64, rank=4, ld=4, reopt=2)) > 0
+
+
+def test_general_blocks_build_and_validation():
+    from oracle.problem import general_blocks_problem
+    from test_oracle_general import two_theta_blocks
+    args = two_theta_blocks()
+    p = L.Problem.general_blocks(*args)
+    op = general_blocks_problem(*args)
+    assert p.info.n == 15 and p.info.m == op.m
+    assert p.info.c_l1 == pytest.approx(op.c_l1, rel=1e-14)
+    block_n, c_blk, c_row, c_col, c_val, m, a_con, a_blk, a_row, a_col, a_val, b = args
+    bad_blk = np.array(c_blk, copy=True)
+    bad_blk[0] = 2
+    with pytest.raises(L.LrsdpError) as e:
+        L.Problem.general_blocks(block_n, bad_blk, c_row, c_col, c_val, m, a_con, a_blk, a_row, a_col, a_val, b)
+    assert e.value.code == L.EINVAL
+    bad_row = np.array(a_row, copy=True)
+    bad_row[0] = 5                                  # block 0 has order 5
+    with pytest.raises(L.LrsdpError) as e:
+        L.Problem.general_blocks(block_n, c_blk, c_row, c_col, c_val, m, a_con, a_blk, bad_row, a_col, a_val, b)
+    assert e.value.code == L.EINVAL

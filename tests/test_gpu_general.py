@@ -310,3 +310,23 @@ def test_general_strict_reopt(ctx):
     assert m["err1"] <= 1e-5 and abs(m["err3"]) <= 1e-5
     e2 = certify.err2(op, y)
     assert res.err2 <= 1e-5 and abs(res.err2 - e2) <= 1e-6
+
+
+@pytest.mark.parametrize("case", ["two_theta", "slack"])
+def test_blocks_closed_forms(ctx, case):
+    from oracle.problem import general_blocks_problem
+    from test_oracle_general import theta_with_slack_block, two_theta_blocks
+    args = two_theta_blocks() if case == "two_theta" else theta_with_slack_block()
+    want = math.sqrt(5) + 4.0 if case == "two_theta" else math.sqrt(5)
+    print_case(test="blocks", case=case)
+    prob = L.Problem.general_blocks(*args).upload(ctx)
+    op = general_blocks_problem(*args)
+    R0 = init_factor(op.n, 6 if case == "two_theta" else 4, 3)
+    rc, res, R, y = gpu_solve(ctx, prob, R0, L.F64, op.m, tol=1e-8)
+    ores = alm_solve(op, R0, opts=OOptions(tol=1e-8))
+    print(res.as_dict(), "oracle", ores.obj, "closed form", -want)
+    assert rc == L.OK and ores.converged
+    assert -res.obj == pytest.approx(want, rel=1e-6)
+    assert abs(res.obj - ores.obj) <= 1e-7 * want
+    m = K.alm_measures(op, R, y)
+    assert abs(m["obj"] - res.obj) <= 1e-10 * want

@@ -112,3 +112,62 @@ def test_random_general_reaches_a_certified_optimum():
     res = alm_solve(op, init_factor(60, 10, 4), opts=Options())
     assert res.converged and res.err1 <= 1e-5 and abs(res.err3) <= 1e-5
     assert certify.lambda_min(op, res.y) >= -1e-5 * (1 + op.c_l1)
+
+
+def two_theta_blocks():
+    """Blocks: theta SDP of C5 (order 5) and of the Petersen graph (order 10),
+    each with its own trace constraint; optimum -(sqrt 5 + 4)."""
+    t1 = theta_triplets(5, *cycle_edges(5))
+    t2 = theta_triplets(10, *petersen_edges())
+    c_blk = np.concatenate([np.zeros(len(t1[0]), np.int32), np.ones(len(t2[0]), np.int32)])
+    c_row = np.concatenate([t1[0], t2[0]])
+    c_col = np.concatenate([t1[1], t2[1]])
+    c_val = np.concatenate([t1[2], t2[2]])
+    m1 = t1[3]
+    a_con = np.concatenate([t1[4], m1 + t2[4]])
+    a_blk = np.concatenate([np.zeros(len(t1[4]), np.int32), np.ones(len(t2[4]), np.int32)])
+    a_row = np.concatenate([t1[5], t2[5]])
+    a_col = np.concatenate([t1[6], t2[6]])
+    a_val = np.concatenate([t1[7], t2[7]])
+    b = np.concatenate([t1[8], t2[8]])
+    return [5, 10], c_blk, c_row, c_col, c_val, m1 + t2[3], a_con, a_blk, a_row, a_col, a_val, b
+
+
+def theta_with_slack_block():
+    """Blocks: X (order 5, theta of C5) and a scalar s >= 0 (order 1):
+    tr X + s = 1 and the edge constraints; optimum -sqrt 5 with s = 0."""
+    c_row, c_col, c_val, m, a_con, a_row, a_col, a_val, b = theta_triplets(5, *cycle_edges(5))
+    a_con = np.concatenate([a_con, [0]])
+    a_blk = np.concatenate([np.zeros(len(a_row), np.int32), [1]])
+    a_row = np.concatenate([a_row, [0]])
+    a_col = np.concatenate([a_col, [0]])
+    a_val = np.concatenate([a_val, [1.0]])
+    return [5, 1], np.zeros(len(c_row), np.int32), c_row, c_col, c_val, m, a_con, a_blk, a_row, a_col, a_val, b
+
+
+def test_blocks_equal_offset_indices():
+    from oracle.problem import general_blocks_problem
+    args = two_theta_blocks()
+    p = general_blocks_problem(*args)
+    block_n, c_blk, c_row, c_col, c_val, m, a_con, a_blk, a_row, a_col, a_val, b = args
+    off = np.array([0, 5])
+    q = general_problem(15, off[c_blk] + c_row, off[c_blk] + c_col, c_val, m, a_con, off[a_blk] + a_row,
+                        off[a_blk] + a_col, a_val, b)
+    same_problem(p, q, np.random.default_rng(11))
+
+
+def test_two_theta_blocks_closed_form():
+    from oracle.problem import general_blocks_problem
+    op = general_blocks_problem(*two_theta_blocks())
+    res = alm_solve(op, init_factor(15, 6, 3), opts=Options(tol=1e-8))
+    assert res.converged
+    assert -res.obj == pytest.approx(math.sqrt(5) + 4.0, rel=1e-6)
+
+
+def test_scalar_slack_block():
+    from oracle.problem import general_blocks_problem
+    op = general_blocks_problem(*theta_with_slack_block())
+    res = alm_solve(op, init_factor(6, 4, 3), opts=Options(tol=1e-8))
+    assert res.converged
+    assert -res.obj == pytest.approx(math.sqrt(5), rel=1e-6)
+    assert np.sum(res.R[5] ** 2) <= 1e-6          # the slack ends at 0
