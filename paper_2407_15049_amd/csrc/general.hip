@@ -9,7 +9,8 @@
 //               search come out of the same pass);
 //   k_gen_cons  one thread per constraint: its row of the stacked matrix
 //               (nonzero columns only) times xbar, plus the line-search or
-//               ALM row terms.
+//               ALM row terms; rows longer than kLongRow (a trace
+//               constraint) go to k_gen_cons_long, a workgroup per row.
 // The operator C - A*(y) is applied on the symmetric pattern of Omega in two
 // passes: k_gen_sv streams over the positions and forms their values
 // cs C_o - sum_k A_k,o y_k from the transposed stacked matrix (eq. At with the
@@ -97,11 +98,40 @@ struct ConsArgs {
     const SolverState *st;
 };
 
+// the terms of constraint k once its row sums t1 (and t2) are known
+template <int MODE>
+__device__ __forceinline__ void cons_epilogue(const DevGeneral &P, const ConsArgs &a, int64_t k, double t1,
+                                              double t2, double (&s)[kLsSums]) {
+    if constexpr (MODE == kGenA) {
+        a.out[k] = t1;
+    } else if constexpr (MODE == kGenLS) {
+        if (a.q1) a.q1[k] = t1;
+        if (a.q2) a.q2[k] = t2;
+        const double yt = a.ytil[k];
+        s[1] += yt * t2;
+        s[2] += yt * t1;
+        s[3] += t2 * t2;
+        s[4] += t1 * t2;
+        s[5] += t1 * t1;
+    } else {
+        const double res = t1 - P.b[k];
+        double yk = a.y[k];
+        if (a.sigma > 0.0) {
+            yk -= a.sigma * res;
+            a.y[k] = yk;
+        }
+        if (a.out) a.out[k] = t1;
+        s[1] += P.b[k] * yk;
+        s[2] += res * res;
+    }
+}
+
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_gen_cons(DevGeneral P, ConsArgs a) {
     if (a.st && a.st->done) return;
     double s[kLsSums] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < P.m; k += (int64_t)gridDim.x * kBlock) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < P.n_short; i += (int64_t)gridDim.x * kBlock) {
+        const int64_t k = P.con_short[i];
         double t1 = 0.0, t2 = 0.0;
         for (int t = P.a_ptr[k]; t < P.a_ptr[k + 1]; ++t) {
             const double v = P.a_val[t];
@@ -109,27 +139,45 @@ __global__ __launch_bounds__(kBlock) void k_gen_cons(DevGeneral P, ConsArgs a) {
             t1 = fma(v, a.x1[o], t1);
             if constexpr (MODE == kGenLS) t2 = fma(v, a.x2[o], t2);
         }
-        if constexpr (MODE == kGenA) {
-            a.out[k] = t1;
-        } else if constexpr (MODE == kGenLS) {
-            if (a.q1) a.q1[k] = t1;
-            if (a.q2) a.q2[k] = t2;
-            const double yt = a.ytil[k];
-            s[1] += yt * t2;
-            s[2] += yt * t1;
-            s[3] += t2 * t2;
-            s[4] += t1 * t2;
-            s[5] += t1 * t1;
-        } else {
-            const double res = t1 - P.b[k];
-            double yk = a.y[k];
-            if (a.sigma > 0.0) {
-                yk -= a.sigma * res;
-                a.y[k] = yk;
+        cons_epilogue<MODE>(P, a, k, t1, t2, s);
+    }
+    if constexpr (MODE != kGenA) block_sums_store<kLsSums>(s, a.partials + (size_t)blockIdx.x * kMaxSums);
+}
+
+// One workgroup per long constraint row: the threads stride over the row, a
+// fixed wavefront/LDS tree adds their sums (deterministic), thread 0 takes the
+// epilogue.
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_gen_cons_long(DevGeneral P, ConsArgs a) {
+    if (a.st && a.st->done) return;
+    __shared__ double sh[kBlock / 64][2];
+    double s[kLsSums] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int64_t i = blockIdx.x; i < P.n_long; i += gridDim.x) {
+        const int64_t k = P.con_long[i];
+        double t1 = 0.0, t2 = 0.0;
+        for (int t = P.a_ptr[k] + threadIdx.x; t < P.a_ptr[k + 1]; t += kBlock) {
+            const double v = P.a_val[t];
+            const int32_t o = P.a_idx[t];
+            t1 = fma(v, a.x1[o], t1);
+            if constexpr (MODE == kGenLS) t2 = fma(v, a.x2[o], t2);
+        }
+        t1 = wave_sum(t1);
+        t2 = wave_sum(t2);
+        __syncthreads();                      // sh of the previous row has been read
+        if (lane == 0) {
+            sh[wave][0] = t1;
+            sh[wave][1] = t2;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double r1 = 0.0, r2 = 0.0;
+#pragma unroll
+            for (int w = 0; w < kBlock / 64; ++w) {
+                r1 += sh[w][0];
+                r2 += sh[w][1];
             }
-            if (a.out) a.out[k] = t1;
-            s[1] += P.b[k] * yk;
-            s[2] += res * res;
+            cons_epilogue<MODE>(P, a, k, r1, r2, s);
         }
     }
     if constexpr (MODE != kGenA) block_sums_store<kLsSums>(s, a.partials + (size_t)blockIdx.x * kMaxSums);
@@ -260,10 +308,20 @@ int xbar_t(hipStream_t s, const DevGeneral &P, const XbarArgs<S> &a, int *nb) {
     return LRSDP_OK;
 }
 
+// The constraint kernels use at most kMaxBlocks / 2 workgroups each, so that
+// with the positions pass the partial rows stay within 2 kMaxBlocks.
 template <int MODE>
 int cons_t(hipStream_t s, const DevGeneral &P, const ConsArgs &a, int *nb) {
-    *nb = gen_grid(P.m, kBlock);
-    hipLaunchKernelGGL((k_gen_cons<MODE>), dim3(*nb), dim3(kBlock), 0, s, P, a);
+    const int nb_short = std::min(gen_grid(P.n_short, kBlock), kMaxBlocks / 2);
+    hipLaunchKernelGGL((k_gen_cons<MODE>), dim3(nb_short), dim3(kBlock), 0, s, P, a);
+    *nb = nb_short;
+    if (P.n_long > 0) {
+        ConsArgs b = a;
+        if (b.partials) b.partials += (size_t)nb_short * kMaxSums;
+        const int nb_long = (int)std::min<int64_t>(P.n_long, kMaxBlocks / 2);
+        hipLaunchKernelGGL((k_gen_cons_long<MODE>), dim3(nb_long), dim3(kBlock), 0, s, P, b);
+        *nb += nb_long;
+    }
     LRSDP_CHECK_LAUNCH();
     return LRSDP_OK;
 }

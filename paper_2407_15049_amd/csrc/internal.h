@@ -80,6 +80,10 @@ struct DevCompletion {
     int64_t n1 = 0, n2 = 0, m = 0;
 };
 
+// Constraint rows of a general problem longer than this are reduced by a
+// whole workgroup (a trace constraint spans n positions).
+constexpr int kLongRow = 512;
+
 // General problem (Section 3.4 compression).  Omega: positions (a, b), a <= b,
 // that are nonzero in C or in some A_k; the stacked constraint matrix keeps
 // only its nonzero columns, indexed by position in Omega.
@@ -97,6 +101,9 @@ struct DevGeneral {
     const int32_t *s_col = nullptr;     // nnz_s: column
     const int32_t *s_om = nullptr;      // nnz_s: Omega index of the entry
     const double *b = nullptr;          // m
+    const int32_t *con_short = nullptr; // constraints whose row has <= kLongRow entries (a thread each)
+    const int32_t *con_long = nullptr;  // the longer ones (a workgroup each)
+    int64_t n_short = 0, n_long = 0;
     double *x1 = nullptr;               // |Omega| compressed outer products, and (x2) the values of
     double *x2 = nullptr;               // C - A*(y) for the SpMM (problem-owned scratch: calls on one
                                         // problem must not overlap)
@@ -117,7 +124,7 @@ struct lrsdp_problem {
     std::vector<double> val, diag, hrow;
     std::vector<int32_t> top_ptr, top_col, top_eid, bot_ptr, bot_row, bot_eid, samp_i, samp_j;
     std::vector<double> b;
-    std::vector<int32_t> om_a, om_b, a_ptr, a_idx, at_ptr, at_idx, s_ptr, s_col, s_om;
+    std::vector<int32_t> om_a, om_b, a_ptr, a_idx, at_ptr, at_idx, s_ptr, s_col, s_om, con_short, con_long;
     std::vector<double> cval, a_val, at_val;
     // device views (valid after upload)
     lrsdp::DevCsr csr;

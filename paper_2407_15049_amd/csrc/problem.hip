@@ -365,6 +365,8 @@ extern "C" int lrsdp_problem_general(int64_t n, int64_t c_nnz, const int32_t *c_
         p->a_val[t] = as[t].v;
     }
     for (int64_t k = 0; k < m; ++k) p->a_ptr[k + 1] += p->a_ptr[k];
+    for (int64_t k = 0; k < m; ++k)
+        (p->a_ptr[k + 1] - p->a_ptr[k] > kLongRow ? p->con_long : p->con_short).push_back((int32_t)k);
     // its transpose by positions (sorted by constraint)
     p->at_ptr.assign(nom + 1, 0);
     for (size_t t = 0; t < as.size(); ++t) p->at_ptr[p->a_idx[t] + 1]++;
@@ -513,6 +515,8 @@ size_t plan_device(const lrsdp_problem *p, size_t *offs) {
         add(p->b.size() * 8);
         add(p->om_a.size() * 8);       // compressed outer products (two per position)
         add(p->om_a.size() * 8);
+        add(p->con_short.size() * 4);
+        add(p->con_long.size() * 4);
     } else {
         add(p->top_ptr.size() * 4);
         add(p->top_col.size() * 4);
@@ -532,7 +536,7 @@ size_t plan_device(const lrsdp_problem *p, size_t *offs) {
 extern "C" int lrsdp_problem_device_bytes(const lrsdp_problem *prob, size_t *bytes) {
     clear_error();
     if (!prob || !bytes) return set_error(LRSDP_EINVAL, "NULL argument");
-    size_t offs[16];
+    size_t offs[24];
     *bytes = plan_device(prob, offs);
     return LRSDP_OK;
 }
@@ -540,7 +544,7 @@ extern "C" int lrsdp_problem_device_bytes(const lrsdp_problem *prob, size_t *byt
 extern "C" int lrsdp_problem_upload(lrsdp_ctx *ctx, lrsdp_problem *p, void *dev, size_t bytes) {
     clear_error();
     if (!ctx || !p || !dev) return set_error(LRSDP_EINVAL, "NULL argument");
-    size_t offs[16];
+    size_t offs[24];
     size_t need = plan_device(p, offs);
     if (bytes < need)
         return set_error(LRSDP_ENOMEM, "problem needs %zu device bytes, %zu given", need, bytes);
@@ -607,6 +611,12 @@ extern "C" int lrsdp_problem_upload(lrsdp_ctx *ctx, lrsdp_problem *p, void *dev,
         g.b = (const double *)(base + offs[12]);
         g.x1 = (double *)(base + offs[13]);
         g.x2 = (double *)(base + offs[14]);
+        LRSDP_HIP_TRY(put(offs[15], p->con_short.data(), p->con_short.size() * 4));
+        LRSDP_HIP_TRY(put(offs[16], p->con_long.data(), p->con_long.size() * 4));
+        g.con_short = (const int32_t *)(base + offs[15]);
+        g.con_long = (const int32_t *)(base + offs[16]);
+        g.n_short = (int64_t)p->con_short.size();
+        g.n_long = (int64_t)p->con_long.size();
         g.n = p->info.n;
         g.m = p->info.m;
         g.nom = (int64_t)p->om_a.size();

@@ -234,6 +234,8 @@ int plan_workspace(const lrsdp_problem *p, const lrsdp_options *o, WsPlan *w) {
     if (o->reopt && (!(o->reopt_factor > 0.0) || !(o->reopt_factor < 1.0) || o->max_reopt < 0))
         return set_error(LRSDP_EINVAL, "re-optimisation needs 0 < reopt_factor < 1 and max_reopt >= 0");
     if (o->reopt == 2 && o->cert_iters < 1) return set_error(LRSDP_EINVAL, "reopt = 2 needs cert_iters >= 1");
+    if (o->reopt == 2 && p->info.n < 16)
+        return set_error(LRSDP_EUNSUPPORTED, "reopt = 2 needs the certificate, which needs n >= 16");
     if (o->precond) {
         if (p->info.kind != LRSDP_MAXCUT)
             return set_error(LRSDP_EUNSUPPORTED, "precond (row-block H0) is for MaxCut problems");

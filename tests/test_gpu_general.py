@@ -59,13 +59,16 @@ def case_data(case):
     if case == "random_small":
         n, t = random_case(60, 40, 4, 120, 5)
         return n, t, 10
-    if case == "random_ragged":         # many blocks and a ragged tail
+    if case == "random_ragged":         # many blocks and a ragged tail; the trace row is a long row
         n, t = random_case(2003, 1501, 5, 6000, 6)
         return n, t, 12
+    if case == "long_rows":             # every constraint row longer than 512: a workgroup per row,
+        n, t = random_case(700, 1200, 600, 2000, 8)      # more rows than workgroups
+        return n, t, 8
     raise KeyError(case)
 
 
-CASES = ["theta_petersen", "theta_dense", "random_small", "random_ragged"]
+CASES = ["theta_petersen", "theta_dense", "random_small", "random_ragged", "long_rows"]
 
 
 def setup(ctx, case):
