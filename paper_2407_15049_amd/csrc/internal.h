@@ -57,7 +57,7 @@ struct DevCsr {
     const double *hrow = nullptr;       // n   2 max(sum_j |C_ij|, 1e-3 ||vec(C)||_1 / n) (row-block H0)
     // Work lists.  Light rows (<= kSegLen nonzeros) sorted by decreasing length
     // inside windows of consecutive rows; heavy rows split into segments.
-    const int32_t *light = nullptr;     // n_light row ids
+    const int4 *light = nullptr;        // n_light {row, begin, end, 0}
     const int4 *seg = nullptr;          // n_seg {row, begin, end, slot}
     const int32_t *heavy = nullptr;     // n_heavy row ids
     const int32_t *heavy_seg = nullptr; // n_heavy + 1 offsets into seg
@@ -119,7 +119,8 @@ int spmm_general(hipStream_t s, const DevGeneral &P, int prec, const void *V, in
 struct lrsdp_problem {
     lrsdp_problem_info info{};
     // host data
-    std::vector<int32_t> row_ptr, col, light, heavy, heavy_seg;
+    std::vector<int32_t> row_ptr, col, heavy, heavy_seg;
+    std::vector<int4> light;
     std::vector<int4> seg;
     std::vector<double> val, diag, hrow;
     std::vector<int32_t> top_ptr, top_col, top_eid, bot_ptr, bot_row, bot_eid, samp_i, samp_j;

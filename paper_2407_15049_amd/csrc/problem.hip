@@ -78,7 +78,7 @@ void build_work_lists(lrsdp_problem *p, int64_t n) {
         std::stable_sort(win.begin(), win.end(), [&](int32_t a, int32_t b) {
             return (rp[a + 1] - rp[a]) > (rp[b + 1] - rp[b]);
         });
-        p->light.insert(p->light.end(), win.begin(), win.end());
+        for (int32_t i : win) p->light.push_back(make_int4(i, rp[i], rp[i + 1], 0));
     }
 }
 
@@ -493,7 +493,7 @@ size_t plan_device(const lrsdp_problem *p, size_t *offs) {
         add(p->col.size() * 4);
         add(p->val.size() * 8);
         add(p->diag.size() * 8);
-        add(p->light.size() * 4);
+        add(p->light.size() * sizeof(int4));
         add(p->seg.size() * sizeof(int4));
         add(p->heavy.size() * 4);
         add(p->heavy_seg.size() * 4);
@@ -559,7 +559,7 @@ extern "C" int lrsdp_problem_upload(lrsdp_ctx *ctx, lrsdp_problem *p, void *dev,
         LRSDP_HIP_TRY(put(offs[1], p->col.data(), p->col.size() * 4));
         LRSDP_HIP_TRY(put(offs[2], p->val.data(), p->val.size() * 8));
         LRSDP_HIP_TRY(put(offs[3], p->diag.data(), p->diag.size() * 8));
-        LRSDP_HIP_TRY(put(offs[4], p->light.data(), p->light.size() * 4));
+        LRSDP_HIP_TRY(put(offs[4], p->light.data(), p->light.size() * sizeof(int4)));
         LRSDP_HIP_TRY(put(offs[5], p->seg.data(), p->seg.size() * sizeof(int4)));
         LRSDP_HIP_TRY(put(offs[6], p->heavy.data(), p->heavy.size() * 4));
         LRSDP_HIP_TRY(put(offs[7], p->heavy_seg.data(), p->heavy_seg.size() * 4));
@@ -569,7 +569,7 @@ extern "C" int lrsdp_problem_upload(lrsdp_ctx *ctx, lrsdp_problem *p, void *dev,
         c.col = (const int32_t *)(base + offs[1]);
         c.val = p->val.empty() ? nullptr : (const double *)(base + offs[2]);
         c.diag = (const double *)(base + offs[3]);
-        c.light = (const int32_t *)(base + offs[4]);
+        c.light = (const int4 *)(base + offs[4]);
         c.seg = (const int4 *)(base + offs[5]);
         c.heavy = (const int32_t *)(base + offs[6]);
         c.heavy_seg = (const int32_t *)(base + offs[7]);

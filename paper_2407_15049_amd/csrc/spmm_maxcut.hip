@@ -77,41 +77,80 @@ __device__ __forceinline__ void load_nbr(const void *V, int64_t j, int64_t ldv, 
     }
 }
 
-// acc += sum_{e in [beg, end)} C_{row, col[e]} V_{col[e]}  (this lane's chunks)
-template <typename S, int W, int NC>
+// acc += sum_{e in [beg, end)} C_{row, col[e]} V_{col[e]}  (this lane's chunks).
+// The GS lanes of the group fetch up to GS column indices of the row with one
+// coalesced load and hand them round by lane shuffles, so a batch of up to
+// eight neighbour-row loads per lane is issued back to back instead of each
+// waiting behind its own index load.  The products are added in edge order,
+// which rounds exactly as a sequential walk over the row does.
+template <typename S, int GS, int W, int NC>
 __device__ __forceinline__ void gather(const DevCsr &P, const void *__restrict__ V, int64_t ldv, int beg, int end,
                                        int lane, bool active, typename Chunk<S>::V (&acc)[NC]) {
     using CV = typename Chunk<S>::V;
-    const int32_t *__restrict__ col = P.col;
-    int e = beg;
-    for (; e + 4 <= end; e += 4) {
-        int32_t c0 = col[e], c1 = col[e + 1], c2 = col[e + 2], c3 = col[e + 3];
-        S w0 = edge_weight<S, W>(P, e, c0), w1 = edge_weight<S, W>(P, e + 1, c1);
-        S w2 = edge_weight<S, W>(P, e + 2, c2), w3 = edge_weight<S, W>(P, e + 3, c3);
-        if (active) {
-            CV v0[NC], v1[NC], v2[NC], v3[NC];
-            load_nbr<S, NC>(V, c0 & 0x7fffffff, ldv, lane, v0);
-            load_nbr<S, NC>(V, c1 & 0x7fffffff, ldv, lane, v1);
-            load_nbr<S, NC>(V, c2 & 0x7fffffff, ldv, lane, v2);
-            load_nbr<S, NC>(V, c3 & 0x7fffffff, ldv, lane, v3);
+    constexpr int KB = GS < 8 ? GS : 8;   // neighbour rows in flight per lane
+    for (int e0 = beg; e0 < end; e0 += GS) {
+        const int cnt = min(GS, end - e0);   // the same for every lane of the group
+        int32_t mc = 0;
+        S mw = (S)0;
+        if (lane < cnt) {
+            mc = P.col[e0 + lane];
+            if constexpr (W == kWGeneral) mw = edge_weight<S, W>(P, e0 + lane, mc);
+        }
 #pragma unroll
-            for (int q = 0; q < NC; ++q) {
-                vfma(acc[q], w0, v0[q]);
-                vfma(acc[q], w1, v1[q]);
-                vfma(acc[q], w2, v2[q]);
-                vfma(acc[q], w3, v3[q]);
+        for (int k0 = 0; k0 < GS; k0 += KB) {
+            if (k0 >= cnt) break;
+            int32_t c[KB];
+            S w[KB];
+#pragma unroll
+            for (int k = 0; k < KB; ++k) {
+                c[k] = __shfl(mc, k0 + k, GS);
+                if constexpr (W == kWGeneral) w[k] = __shfl(mw, k0 + k, GS);
+                else w[k] = edge_weight<S, W>(P, 0, c[k]);
+            }
+            if (active) {
+                CV v[KB][NC];
+#pragma unroll
+                for (int k = 0; k < KB; ++k)
+                    if (k0 + k < cnt) load_nbr<S, NC>(V, c[k] & 0x7fffffff, ldv, lane, v[k]);
+#pragma unroll
+                for (int k = 0; k < KB; ++k) {
+                    if (k0 + k < cnt) {
+#pragma unroll
+                        for (int q = 0; q < NC; ++q) vfma(acc[q], w[k], v[k][q]);
+                    }
+                }
             }
         }
     }
-    for (; e < end; ++e) {
-        int32_t c0 = col[e];
-        S w0 = edge_weight<S, W>(P, e, c0);
-        if (active) {
-            CV v0[NC];
-            load_nbr<S, NC>(V, c0 & 0x7fffffff, ldv, lane, v0);
+}
+
+// Operands of the line-search epilogue that do not depend on the gather (the
+// row's own D and R chunks, C_ii, ytil_i), loaded before it so that their
+// latency overlaps the neighbour loads.  The other epilogues load in place.
+template <typename S, int NC>
+struct OwnRow {
+    typename Chunk<S>::V d[NC], r[NC];
+    double diag = 0.0, ytil = 0.0;
+};
+
+template <typename S, int EPI, int NC>
+__device__ __forceinline__ void load_own(const DevCsr &P, const SpmmArgs &a, int row, int lane, bool active,
+                                         OwnRow<S, NC> &o) {
+    if constexpr (EPI == kEpiLS) {
+        using CV = typename Chunk<S>::V;
+        constexpr int NV = Chunk<S>::N;
+        const S *Dn = (const S *)(NC == 1 ? a.V : a.Vown);   // own row of D in the storage type
+        const CV zero = vzero(CV{});
 #pragma unroll
-            for (int q = 0; q < NC; ++q) vfma(acc[q], w0, v0[q]);
+        for (int q = 0; q < NC; ++q) {
+            const int ci = lane * NC + q;
+            const bool act = active && ci * NV < a.ld;
+            const int64_t off = (int64_t)row * a.ld + ci * NV;
+            o.d[q] = act ? *reinterpret_cast<const CV *>(Dn + off) : zero;
+            o.r[q] = act ? *reinterpret_cast<const CV *>((const S *)a.R + off) : zero;
         }
+        o.diag = P.diag[row];
+        o.ytil = a.ytil[row];
     }
 }
 
@@ -120,7 +159,8 @@ __device__ __forceinline__ void gather(const DevCsr &P, const void *__restrict__
 // output chunks lane*NC + q, q < NC.
 template <typename S, int GS, int EPI, int NC>
 __device__ __forceinline__ void epilogue(const DevCsr &P, const SpmmArgs &a, int row, int lane, bool active,
-                                         typename Chunk<S>::V (&acc)[NC], double (&s)[kLsSums]) {
+                                         const OwnRow<S, NC> &own, typename Chunk<S>::V (&acc)[NC],
+                                         double (&s)[kLsSums]) {
     using CV = typename Chunk<S>::V;
     constexpr int NV = Chunk<S>::N;
     // operator cs C: the gathered off-diagonal sum and the diagonal both take the
@@ -128,7 +168,7 @@ __device__ __forceinline__ void epilogue(const DevCsr &P, const SpmmArgs &a, int
     const S cs = (S)a.cs;
 #pragma unroll
     for (int q = 0; q < NC; ++q) vscale(acc[q], cs);
-    const S dg = (S)(a.cs * P.diag[row]);
+    const S dg = (S)(a.cs * (EPI == kEpiLS ? own.diag : P.diag[row]));
     const CV zero = vzero(CV{});
     int64_t off[NC];
     bool act[NC];
@@ -156,12 +196,11 @@ __device__ __forceinline__ void epilogue(const DevCsr &P, const SpmmArgs &a, int
             if (act[q]) *reinterpret_cast<CV *>((S *)a.Y + off[q]) = acc[q];
         }
     } else if constexpr (EPI == kEpiLS) {
-        const S *Dn = (const S *)(NC == 1 ? a.V : a.Vown);   // own row of D in the storage type
         double p2 = 0.0, q1 = 0.0, q2 = 0.0, rr = 0.0, p1 = 0.0;
 #pragma unroll
         for (int q = 0; q < NC; ++q) {
-            const CV d = act[q] ? *reinterpret_cast<const CV *>(Dn + off[q]) : zero;
-            const CV r = act[q] ? *reinterpret_cast<const CV *>((const S *)a.R + off[q]) : zero;
+            const CV d = own.d[q];
+            const CV r = own.r[q];
             vfma(acc[q], dg, d);
             if (act[q]) *reinterpret_cast<CV *>((S *)a.Y + off[q]) = acc[q];
             p2 += vdot(acc[q], d);
@@ -179,7 +218,7 @@ __device__ __forceinline__ void epilogue(const DevCsr &P, const SpmmArgs &a, int
         if (a.rn) rr = group_sum<GS>(rr);
         if (a.aux) p1 = 2.0 * group_sum<GS>(p1);
         if (lane == 0) {
-            const double yt = a.ytil[row];
+            const double yt = own.ytil;
             s[0] += p2;
             s[1] += yt * q2;
             s[2] += yt * q1;
@@ -261,13 +300,15 @@ __global__ __launch_bounds__(kBlock) void k_spmm_light(DevCsr P, SpmmArgs a) {
     const bool active = lane_active<S, NC>(a, lane);
     double s[kLsSums] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int64_t it = (int64_t)blockIdx.x * GPB + grp; it < P.n_light; it += (int64_t)gridDim.x * GPB) {
-        const int row = P.light[it];
-        const int beg = P.row_ptr[row], end = P.row_ptr[row + 1];
+        const int4 wl = P.light[it];   // {row, begin, end}: no dependent row_ptr load
+        const int row = wl.x, beg = wl.y, end = wl.z;
         CV acc[NC];
 #pragma unroll
         for (int q = 0; q < NC; ++q) acc[q] = vzero(CV{});
-        gather<S, W, NC>(P, a.V, a.ldv, beg, end, lane, active, acc);
-        epilogue<S, GS, EPI, NC>(P, a, row, lane, active, acc, s);
+        OwnRow<S, NC> own;
+        load_own<S, EPI, NC>(P, a, row, lane, active, own);
+        gather<S, GS, W, NC>(P, a.V, a.ldv, beg, end, lane, active, acc);
+        epilogue<S, GS, EPI, NC>(P, a, row, lane, active, own, acc, s);
     }
     if constexpr (EPI == kEpiLS || EPI == kEpiRefresh)
         block_sums_store<kLsSums>(s, a.partials + (size_t)blockIdx.x * kMaxSums);
@@ -288,7 +329,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_segments(DevCsr P, SpmmArgs a) 
         CV acc[NC];
 #pragma unroll
         for (int q = 0; q < NC; ++q) acc[q] = vzero(CV{});
-        gather<S, W, NC>(P, a.V, a.ldv, sg.y, sg.z, lane, active, acc);
+        gather<S, GS, W, NC>(P, a.V, a.ldv, sg.y, sg.z, lane, active, acc);
         if (active) {
 #pragma unroll
             for (int q = 0; q < NC; ++q) buf[(int64_t)sg.w * 16 + lane * NC + q] = acc[q];
@@ -332,7 +373,9 @@ __global__ __launch_bounds__(kBlock) void k_spmm_fixup(DevCsr P, SpmmArgs a, int
 #pragma unroll 4
                 for (int g = 0; g < GPB; ++g) vfma(t[q], (S)1, sh[g][lane * NC + q]);
             }
-            epilogue<S, GS, EPI, NC>(P, a, row, lane, active, t, s);
+            OwnRow<S, NC> own;
+            load_own<S, EPI, NC>(P, a, row, lane, active, own);
+            epilogue<S, GS, EPI, NC>(P, a, row, lane, active, own, t, s);
         }
         __syncthreads();
     }
