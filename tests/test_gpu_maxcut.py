@@ -56,10 +56,35 @@ def graph(case):
     if case == "wide32":
         u, v = erdos_renyi_edges(333, 1500, 9)
         return 333, u, v, None, 32
+    if case == "degree_ladder":
+        return degree_ladder(general=False)
+    if case == "ladder_general":
+        return degree_ladder(general=True)
     raise KeyError(case)
 
 
-CASES = ["er_1k", "pm1_ragged", "general", "cl_heavy", "isolated", "empty", "wide32"]
+def degree_ladder(general):
+    """Hub rows of every degree around the gather's batch and lane-group sizes
+    (0-40, 63-65, 127-130 around the 128-entry segment length, 255-257) joined
+    to distinct leaves drawn from a pool of other nodes; +-1 weights (or real
+    weights in [-2, 3) when `general`), rank 20."""
+    rng = np.random.default_rng(20)
+    degrees = list(range(0, 41)) + [63, 64, 65, 127, 128, 129, 130, 255, 256, 257]
+    hubs = len(degrees)
+    n = hubs + 2000
+    us, vs = [], []
+    for h, d in enumerate(degrees):
+        leaves = hubs + rng.choice(n - hubs, size=d, replace=False)
+        us.append(np.full(d, h))
+        vs.append(leaves)
+    u = np.concatenate(us).astype(np.int32)
+    v = np.concatenate(vs).astype(np.int32)
+    perm = rng.permutation(n).astype(np.int32)      # spread the hubs over the work-list windows
+    w = rng.uniform(-2, 3, len(u)) if general else pm1_weights(len(u), 21)
+    return n, perm[u], perm[v], w, 20
+
+
+CASES = ["er_1k", "pm1_ragged", "general", "cl_heavy", "isolated", "empty", "wide32", "degree_ladder", "ladder_general"]
 
 
 def setup(ctx, case):
@@ -128,7 +153,7 @@ def test_constraint_map_parity(ctx, case, prec):
 
 
 @pytest.mark.parametrize("prec", [L.F64, L.F32])
-@pytest.mark.parametrize("case", ["er_1k", "pm1_ragged", "general", "cl_heavy", "isolated"])
+@pytest.mark.parametrize("case", ["er_1k", "pm1_ragged", "general", "cl_heavy", "isolated", "degree_ladder", "ladder_general"])
 def test_linesearch_coeffs_parity(ctx, case, prec):
     import torch
     n, r, prob, op = setup(ctx, case)
@@ -326,7 +351,7 @@ def test_solve_reports_limits(ctx):
     assert rc == L.NOT_CONVERGED and res.outer == 1 and res.err1 > 0
 
 
-@pytest.mark.parametrize("case", ["er_1k", "pm1_ragged", "general", "cl_heavy", "isolated"])
+@pytest.mark.parametrize("case", ["er_1k", "pm1_ragged", "general", "cl_heavy", "isolated", "degree_ladder", "ladder_general"])
 def test_spmm_bf16_input_parity(ctx, case):
     # bfloat16 gathered operand, float32 accumulation and output
     import torch
