@@ -37,37 +37,54 @@ struct CmpSpmmArgs {
     double cs;            // objective scale: C = cs I
 };
 
-// acc += sum over the row's samples of ytil_k * V_partner  (this lane's chunk)
-template <typename S>
+// acc += sum over the row's samples of ytil_k * V_partner  (this lane's chunk).
+// The GS lanes of the group take the row's samples PW at a time: each lane
+// loads the partner index and the weight ytil_k of PW / GS samples (coalesced
+// index loads, the ytil gathers of all of them in flight at once), then the
+// partner rows are fetched eight at a time with the indices and weights handed
+// round by lane shuffles.  The products are added in sample order, which
+// rounds exactly as a sequential walk over the row does.
+template <typename S, int GS>
 __device__ __forceinline__ void cmp_gather(const int32_t *__restrict__ ptr, const int32_t *__restrict__ nbr,
                                            const int32_t *__restrict__ eid, int row, int64_t base,
                                            const double *__restrict__ ytil, const S *__restrict__ V, int64_t ld,
                                            int lane, bool active, typename Chunk<S>::V &acc) {
     using CV = typename Chunk<S>::V;
     constexpr int NV = Chunk<S>::N;
+    constexpr int PW = GS < 16 ? 16 : GS;   // samples per pass
+    constexpr int NT = PW / GS;             // samples per lane and pass
+    constexpr int KB = 8;                   // partner rows in flight per lane
     const int b = ptr[row], e = ptr[row + 1];
-    int k = b;
-    // four samples per step: indices and weights first, then four row loads in flight
-    for (; k + 4 <= e; k += 4) {
-        int64_t j[4];
-        S w[4];
+    for (int k0 = b; k0 < e; k0 += PW) {
+        const int cnt = min(PW, e - k0);     // the same for every lane of the group
+        int32_t jj[NT];
+        S ww[NT];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            j[q] = base + nbr[k + q];
-            w[q] = (S)ytil[eid[k + q]];
+        for (int t = 0; t < NT; ++t) {
+            const int q = lane + t * GS;
+            jj[t] = q < cnt ? nbr[k0 + q] : 0;
+            ww[t] = q < cnt ? (S)ytil[eid[k0 + q]] : (S)0;
         }
-        if (active) {
-            CV v[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) v[q] = *reinterpret_cast<const CV *>(V + j[q] * ld + lane * NV);
+        for (int q0 = 0; q0 < PW; q0 += KB) {
+            if (q0 >= cnt) break;
+            int64_t j[KB];
+            S w[KB];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) vfma(acc, w[q], v[q]);
+            for (int q = 0; q < KB; ++q) {
+                j[q] = base + __shfl(jj[(q0 + q) / GS], (q0 + q) % GS, GS);
+                w[q] = __shfl(ww[(q0 + q) / GS], (q0 + q) % GS, GS);
+            }
+            if (active) {
+                CV v[KB];
+#pragma unroll
+                for (int q = 0; q < KB; ++q)
+                    if (q0 + q < cnt) v[q] = *reinterpret_cast<const CV *>(V + j[q] * ld + lane * NV);
+#pragma unroll
+                for (int q = 0; q < KB; ++q)
+                    if (q0 + q < cnt) vfma(acc, w[q], v[q]);
+            }
         }
-    }
-    for (; k < e; ++k) {
-        const int64_t j0 = base + nbr[k];
-        const S w0 = (S)ytil[eid[k]];
-        if (active) vfma(acc, w0, *reinterpret_cast<const CV *>(V + j0 * ld + lane * NV));
     }
 }
 
@@ -101,9 +118,9 @@ __global__ __launch_bounds__(kBlock) void k_cmp_spmm(DevCompletion P, CmpSpmmArg
         CV acc = zero;
         if (a.ytil) {
             if (row < P.n1)
-                cmp_gather<S>(P.top_ptr, P.top_col, P.top_eid, (int)row, P.n1, a.ytil, a.V, a.ld, lane, active, acc);
+                cmp_gather<S, GS>(P.top_ptr, P.top_col, P.top_eid, (int)row, P.n1, a.ytil, a.V, a.ld, lane, active, acc);
             else
-                cmp_gather<S>(P.bot_ptr, P.bot_row, P.bot_eid, (int)(row - P.n1), 0, a.ytil, a.V, a.ld, lane, active,
+                cmp_gather<S, GS>(P.bot_ptr, P.bot_row, P.bot_eid, (int)(row - P.n1), 0, a.ytil, a.V, a.ld, lane, active,
                               acc);
         }
         const int64_t off = row * a.ld + lane * NV;
@@ -168,18 +185,36 @@ __global__ __launch_bounds__(kBlock) void k_cmp_sddmm(DevCompletion P, SddArgs<S
         const CV ui = active ? *reinterpret_cast<const CV *>(a.U + off) : zero;
         const CV vi = (MODE != kSddRefresh && active) ? *reinterpret_cast<const CV *>(a.V + off) : zero;
         const int b = P.top_ptr[i], e = P.top_ptr[i + 1];
-        // four samples per step (the tail repeats the last sample's loads and
-        // skips its outputs): all eight partner-row loads are in flight before
-        // the first reduction
-        for (int t = b; t < e; t += 4) {
-            const int cnt = min(4, e - t);
+        // The row's samples PW at a time: each lane loads the partner index and
+        // sample id of NT of them (coalesced; past the row's end it repeats the
+        // last sample), then four samples per step take them by lane shuffles,
+        // with all eight partner-row loads in flight before the first reduction
+        // (a step past the end repeats the last sample's loads and skips its
+        // outputs).  NT = 2 for float64 rows; float32 rows keep one, since the
+        // extra index registers cost the float32 line-search build a wave per
+        // SIMD (measured slower at n = 1e6, m = 1e7).
+        constexpr int NT = sizeof(S) == 8 ? 2 : 1;
+        constexpr int PW = NT * GS;
+        for (int t0 = b; t0 < e; t0 += PW) {
+          const int cnt0 = min(PW, e - t0);
+          int32_t cc[NT], ee[NT];
+#pragma unroll
+          for (int u = 0; u < NT; ++u) {
+              const int tq = t0 + min(lane + u * GS, cnt0 - 1);
+              cc[u] = P.top_col[tq];
+              ee[u] = P.top_eid[tq];
+          }
+#pragma unroll
+          for (int s0 = 0; s0 < PW; s0 += 4) {
+            if (s0 >= cnt0) break;
+            const int cnt = min(4, cnt0 - s0);
             int64_t pj[4];
             int kk[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int tq = t + min(q, cnt - 1);
-                pj[q] = (P.n1 + P.top_col[tq]) * a.ld + lane * NV;
-                kk[q] = P.top_eid[tq];
+                const int src = s0 + q;   // compile-time register and lane
+                pj[q] = (P.n1 + __shfl(cc[src / GS], src % GS, GS)) * a.ld + lane * NV;
+                kk[q] = __shfl(ee[src / GS], src % GS, GS);
             }
             CV xu[4], xv[4];
 #pragma unroll
@@ -224,6 +259,7 @@ __global__ __launch_bounds__(kBlock) void k_cmp_sddmm(DevCompletion P, SddArgs<S
                     }
                 }
             }
+          }
         }
     }
     if constexpr (MODE != kSddA) block_sums_store<kLsSums>(s, a.partials + (size_t)blockIdx.x * kMaxSums);

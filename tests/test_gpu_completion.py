@@ -36,10 +36,31 @@ CASES = {
     "small": (40, 31, 2, 7, 4),
     "ragged": (1003, 777, 5, 20, 16),
     "wide": (500, 400, 3, 11, 24),
+    "ladder": None,
 }
 
 
+def sample_ladder():
+    """Top rows with every sample count around the gather's pass sizes (0-40,
+    63-65, 127-129), columns drawn without replacement from 300; the planted
+    values come from a rank-3 product.  Returns the setup tuple."""
+    rng = np.random.default_rng(22)
+    counts = list(range(0, 41)) + [63, 64, 65, 127, 128, 129]
+    n1, n2, k = len(counts), 300, 3
+    U = rng.standard_normal((n1, k)) / np.sqrt(k)
+    V = rng.standard_normal((n2, k)) / np.sqrt(k)
+    i = np.repeat(np.arange(n1, dtype=np.int32), counts)
+    j = np.concatenate([np.sort(rng.choice(n2, c, replace=False)) for c in counts]).astype(np.int32)
+    Mij = np.einsum("ak,ak->a", U[i], V[j])
+    return n1, n2, i, j, Mij, U, V, 16
+
+
 def setup(ctx, case):
+    if case == "ladder":
+        n1, n2, i, j, Mij, U, V, r = sample_ladder()
+        prob = L.Problem.completion(n1, n2, i, j, Mij).upload(ctx)
+        op = completion_problem(n1, n2, i, j, Mij)
+        return prob, op, r, (n1, n2, i, j, Mij, U, V)
     n1, n2, k, per, r = CASES[case]
     i, j, Mij, U, V = completion_instance(n1, n2, k, per, seed=21)
     prob = L.Problem.completion(n1, n2, i, j, Mij).upload(ctx)
