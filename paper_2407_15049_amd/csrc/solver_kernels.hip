@@ -136,9 +136,11 @@ __device__ double grow(const double *M, int i, int NB, const double *q) {
 __device__ void two_loop_coef(SolverState &st) {
     const int T = st.T, NB = 2 * T + 1, nmem = st.nmem, gk = st.gk, dk = st.dk;
     const double *M = st.gram;
-    double q[kMaxBasis], alpha[kMaxMem], beta[kMaxMem];
-    int ds[kMaxMem], g0[kMaxMem], g1[kMaxMem];
-    double tau[kMaxMem];
+    // work arrays in LDS: indexed at run time, they would otherwise live in
+    // scratch memory (one thread of the workgroup runs this)
+    __shared__ double q[kMaxBasis], alpha[kMaxMem], beta[kMaxMem];
+    __shared__ int ds[kMaxMem], g0[kMaxMem], g1[kMaxMem];
+    __shared__ double tau[kMaxMem];
     for (int j = 0; j < NB; ++j) q[j] = 0.0;
     q[gk] = -1.0;
     for (int t = 0; t < nmem; ++t) {  // t = 0 oldest
@@ -179,8 +181,9 @@ __device__ void two_loop_coef_pc(SolverState &st) {
     const double *M = st.gram;
     const double *W = st.wgram;
     constexpr int WS = kMaxMem + 1;
-    double qa[kMaxMem + 1], alpha[kMaxMem], beta[kMaxMem], fd[kMaxMem], tau[kMaxMem];
-    int ds[kMaxMem], g0[kMaxMem], g1[kMaxMem];
+    // work arrays in LDS (see two_loop_coef)
+    __shared__ double qa[kMaxMem + 1], alpha[kMaxMem], beta[kMaxMem], fd[kMaxMem], tau[kMaxMem];
+    __shared__ int ds[kMaxMem], g0[kMaxMem], g1[kMaxMem];
     for (int j = 0; j <= T; ++j) qa[j] = 0.0;
     qa[gk] = -1.0;
     for (int t = 0; t < nmem; ++t) {  // t = 0 oldest
