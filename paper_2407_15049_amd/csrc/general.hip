@@ -308,11 +308,12 @@ int xbar_t(hipStream_t s, const DevGeneral &P, const XbarArgs<S> &a, int *nb) {
     return LRSDP_OK;
 }
 
-// The constraint kernels use at most kMaxBlocks / 2 workgroups each, so that
-// with the positions pass the partial rows stay within 2 kMaxBlocks.
+// With long rows present the two constraint kernels use at most kMaxBlocks / 2
+// workgroups each, so that with the positions pass the partial rows stay
+// within 2 kMaxBlocks; without them the short-row kernel keeps the full grid.
 template <int MODE>
 int cons_t(hipStream_t s, const DevGeneral &P, const ConsArgs &a, int *nb) {
-    const int nb_short = std::min(gen_grid(P.n_short, kBlock), kMaxBlocks / 2);
+    const int nb_short = std::min(gen_grid(P.n_short, kBlock), P.n_long > 0 ? kMaxBlocks / 2 : kMaxBlocks);
     hipLaunchKernelGGL((k_gen_cons<MODE>), dim3(nb_short), dim3(kBlock), 0, s, P, a);
     *nb = nb_short;
     if (P.n_long > 0) {
