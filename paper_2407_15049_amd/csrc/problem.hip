@@ -15,6 +15,7 @@
 #include <cstdio>
 #include <cstring>
 #include <numeric>
+#include <thread>
 
 #include "internal.h"
 
@@ -43,6 +44,13 @@ extern "C" const char *lrsdp_last_error(void) { return g_last_error.c_str(); }
 extern "C" const char *lrsdp_version(void) { return "lrsdp 0.1 (gfx950)"; }
 
 namespace {
+
+// Host threads for a build pass over `work` entries: one per 2^20 entries, at
+// most 16 and at most the hardware's count.
+int host_threads(int64_t work) {
+    int64_t hw = std::max<int64_t>(1, (int64_t)std::thread::hardware_concurrency());
+    return (int)std::max<int64_t>(1, std::min<int64_t>({16, hw, work >> 20}));
+}
 
 // Light rows sorted by decreasing length inside windows of consecutive rows, so
 // a wavefront's groups walk rows of similar length while touching nearby rows.
@@ -130,43 +138,67 @@ extern "C" int lrsdp_problem_maxcut(int64_t n, int64_t n_edges, const int32_t *u
         wv[pa] = we;
         wv[pb] = we;
     }
-    // sort each row by column (deterministic layout, duplicate detection)
-    std::vector<int32_t> idx;
-    std::vector<int32_t> ctmp;
-    std::vector<double> wtmp;
+    // sort each row by column (deterministic layout, duplicate detection); rows
+    // are independent, so blocks of rows go to host threads, and the per-row
+    // terms of ||vec(C)||_1 are added in row order afterwards (the same sum
+    // whatever the thread count)
     p->diag.assign(n, 0.0);
     p->hrow.assign(n, 0.0);
+    std::vector<double> row_l1(n, 0.0);
+    std::vector<int64_t> dup_row(1, -1);
+    auto sort_rows = [&](int64_t r0, int64_t r1, int64_t *first_dup) {
+        std::vector<std::pair<int32_t, double>> ent;
+        for (int64_t i = r0; i < r1; ++i) {
+            int64_t b0 = p->row_ptr[i], b1 = p->row_ptr[i + 1];
+            int64_t len = b1 - b0;
+            ent.resize(len);
+            for (int64_t k = 0; k < len; ++k) ent[k] = {p->col[b0 + k], wv[b0 + k]};
+            std::sort(ent.begin(), ent.end(),
+                      [](const std::pair<int32_t, double> &x, const std::pair<int32_t, double> &y) {
+                          return x.first < y.first;
+                      });
+            double wsum = 0.0, wabs = 0.0, l1 = 0.0;
+            for (int64_t k = 0; k < len; ++k) {
+                if (k > 0 && ent[k].first == ent[k - 1].first) {
+                    *first_dup = i;
+                    return;
+                }
+                p->col[b0 + k] = ent[k].first;
+                wv[b0 + k] = ent[k].second;
+                wsum += ent[k].second;
+                wabs += std::fabs(ent[k].second);
+                l1 += std::fabs(ent[k].second) * 0.25;
+            }
+            p->diag[i] = -0.25 * wsum;
+            row_l1[i] = l1 + std::fabs(p->diag[i]);
+            p->hrow[i] = 0.25 * wabs + std::fabs(p->diag[i]);   // sum_j |C_ij|, finished below
+        }
+    };
+    {
+        const int nt = host_threads(nnz);
+        std::vector<int64_t> first_dup(nt, -1);
+        std::vector<std::thread> pool;
+        const int64_t chunk = (n + nt - 1) / nt;
+        for (int t = 0; t < nt; ++t) {
+            int64_t r0 = std::min<int64_t>(n, t * chunk), r1 = std::min<int64_t>(n, r0 + chunk);
+            pool.emplace_back(sort_rows, r0, r1, &first_dup[t]);
+        }
+        for (auto &th : pool) th.join();
+        for (int t = 0; t < nt; ++t)
+            if (first_dup[t] >= 0) {
+                int64_t i = first_dup[t];
+                std::vector<int32_t> c(p->col.begin() + p->row_ptr[i], p->col.begin() + p->row_ptr[i + 1]);
+                std::sort(c.begin(), c.end());
+                int32_t d = c[std::adjacent_find(c.begin(), c.end()) - c.begin()];
+                delete p;
+                return set_error(LRSDP_EINVAL, "edge (%lld, %d) appears more than once", (long long)i, d);
+            }
+    }
     double c_l1 = 0.0;
     int64_t max_row = 0;
     for (int64_t i = 0; i < n; ++i) {
-        int64_t b0 = p->row_ptr[i], b1 = p->row_ptr[i + 1];
-        int64_t len = b1 - b0;
-        max_row = std::max(max_row, len);
-        idx.resize(len);
-        std::iota(idx.begin(), idx.end(), 0);
-        std::sort(idx.begin(), idx.end(), [&](int32_t x, int32_t y) { return p->col[b0 + x] < p->col[b0 + y]; });
-        ctmp.resize(len);
-        wtmp.resize(len);
-        for (int64_t k = 0; k < len; ++k) {
-            ctmp[k] = p->col[b0 + idx[k]];
-            wtmp[k] = wv[b0 + idx[k]];
-        }
-        double wsum = 0.0, wabs = 0.0;
-        for (int64_t k = 0; k < len; ++k) {
-            if (k > 0 && ctmp[k] == ctmp[k - 1]) {
-                int32_t c = ctmp[k];
-                delete p;
-                return set_error(LRSDP_EINVAL, "edge (%lld, %d) appears more than once", (long long)i, c);
-            }
-            p->col[b0 + k] = ctmp[k];
-            wv[b0 + k] = wtmp[k];
-            wsum += wtmp[k];
-            wabs += std::fabs(wtmp[k]);
-            c_l1 += std::fabs(wtmp[k]) * 0.25;
-        }
-        p->diag[i] = -0.25 * wsum;
-        c_l1 += std::fabs(p->diag[i]);
-        p->hrow[i] = 0.25 * wabs + std::fabs(p->diag[i]);   // sum_j |C_ij|, finished below
+        c_l1 += row_l1[i];
+        max_row = std::max<int64_t>(max_row, p->row_ptr[i + 1] - p->row_ptr[i]);
     }
     // h_i of the row-block H0 of the L-BFGS direction (solve option precond)
     const double hfloor = n > 0 ? 1e-3 * c_l1 / (double)n : 0.0;

@@ -12,9 +12,10 @@ available here; these synthetic families stand in for them):
 * ``erdos_renyi_edges``: ``m`` distinct unordered pairs drawn uniformly without
   replacement from the ``n(n-1)/2`` possible pairs.
 * ``chung_lu_edges``: power-law expected degrees, weight of node ``i`` proportional
-  to ``(i+1)^(-1/(beta-1))``; both endpoints drawn proportionally to the weight,
-  self-loops and repeats rejected until ``m`` distinct edges exist; node ids then
-  relabelled by a uniform random permutation.
+  to ``(i+1)^(-1/(beta-1))``; both endpoints drawn proportionally to the weight
+  (multinomial counts per node, shuffled), self-loops and repeats rejected until
+  ``m`` distinct edges exist; node ids then relabelled by a uniform random
+  permutation.
 * ``completion_instance``: planted ``M = U V^T`` with ``U, V`` i.i.d. N(0, 1/k) and a
   fixed number of distinct observed columns per row.
 """
@@ -30,26 +31,50 @@ def _rng(seed: int) -> np.random.Generator:
     return np.random.Generator(np.random.PCG64(int(seed)))
 
 
-def _distinct_pairs(draw, n: int, m: int, rng: np.random.Generator):
+def _first_occurrences(keys: np.ndarray) -> np.ndarray:
+    """Positions of the first occurrence of every distinct value of ``keys``, in
+    increasing order (what ``np.unique(..., return_index=True)`` gives once
+    sorted, without its stable argsort of the whole array: repeats are rare, so
+    only the positions holding a repeated value are sorted by position)."""
+    s = np.sort(keys)
+    rep = s[1:][s[1:] == s[:-1]]
+    if rep.size == 0:
+        return np.arange(keys.size)
+    rep = np.unique(rep)
+    slot = np.searchsorted(rep, keys)
+    slot[slot == rep.size] = 0
+    pos = np.flatnonzero(rep[slot] == keys)          # every position holding a repeated value
+    kp = keys[pos]
+    order = np.argsort(kp, kind="stable")            # by value, then by position
+    ks = kp[order]
+    later = np.zeros(ks.size, dtype=bool)
+    later[1:] = ks[1:] == ks[:-1]
+    keep = np.ones(keys.size, dtype=bool)
+    keep[pos[order[later]]] = False
+    return np.flatnonzero(keep)
+
+
+def _distinct_pairs(draw, n: int, m: int, rng: np.random.Generator, overdraw=None):
     """Draw endpoint pairs with ``draw(rng, k)`` until ``m`` distinct unordered,
     loop-free pairs exist; keep them in order of first appearance (so the result
-    is a uniform sample without replacement when ``draw`` is uniform)."""
+    is a uniform sample without replacement when ``draw`` is uniform).
+    ``overdraw(need)`` is the number of pairs drawn in a round (default twice
+    the number still missing)."""
     keys = np.empty(0, dtype=np.int64)
     rounds = 0
     while keys.size < m:
-        if m >= 10_000_000:                      # large draws take minutes: show progress
+        if m >= 10_000_000:
             print(f"[synth] distinct pairs: {keys.size}/{m} after {rounds} rounds", file=sys.stderr, flush=True)
         rounds += 1
         need = m - keys.size
-        k = max(2 * need, 1024)
+        k = overdraw(need) if overdraw else max(2 * need, 1024)
         u, v = draw(rng, k)
         keep = u != v
         a = np.minimum(u, v)[keep].astype(np.int64)
         b = np.maximum(u, v)[keep].astype(np.int64)
         cand = np.concatenate([keys, a * n + b])
-        _, first = np.unique(cand, return_index=True)
-        first.sort()
-        keys = cand[first]
+        del u, v, a, b, keep
+        keys = cand[_first_occurrences(cand)]
     keys = keys[:m]
     return (keys // n).astype(np.int32), (keys % n).astype(np.int32)
 
@@ -67,20 +92,26 @@ def erdos_renyi_edges(n: int, m: int, seed: int):
 
 
 def chung_lu_edges(n: int, m: int, beta: float, seed: int, relabel: bool = True):
-    """Chung-Lu power-law graph with degree exponent ``beta`` and ``m`` edges."""
+    """Chung-Lu power-law graph with degree exponent ``beta`` and ``m`` edges.
+
+    Endpoints are i.i.d. draws with probability proportional to
+    ``(i+1)^(-1/(beta-1))``.  A round of ``k`` pairs takes its ``2k`` endpoints
+    as multinomial counts per node laid out in node order and shuffled by a
+    uniform permutation, which is the law of ``2k`` i.i.d. draws (and avoids a
+    binary search per draw); consecutive endpoints form the pairs."""
     if m > n * (n - 1) // 2:
         raise ValueError("more edges than node pairs")
     rng = _rng(seed)
     theta = np.arange(1, n + 1, dtype=np.float64) ** (-1.0 / (beta - 1.0))
-    cdf = np.cumsum(theta)
-    cdf /= cdf[-1]
+    prob = theta / theta.sum()
+    ids = np.arange(n, dtype=np.int32)
 
     def draw(g, k):
-        u = np.searchsorted(cdf, g.random(k), side="right")
-        v = np.searchsorted(cdf, g.random(k), side="right")
-        return np.minimum(u, n - 1), np.minimum(v, n - 1)
+        ends = np.repeat(ids, g.multinomial(2 * k, prob))
+        g.shuffle(ends)
+        return ends[0::2], ends[1::2]
 
-    u, v = _distinct_pairs(draw, n, m, rng)
+    u, v = _distinct_pairs(draw, n, m, rng, overdraw=lambda need: need + need // 16 + 1024)
     if relabel:
         perm = rng.permutation(n).astype(np.int32)
         u, v = perm[u], perm[v]

@@ -204,3 +204,42 @@ def test_exact_step_special_cases():
     # two local minima: picks the deeper one (f(t)=t^4-4t^3+4t^2-0.1t has minima near 0 and 2)
     t = K.exact_step(1.0, -4.0, 4.0, -0.1)
     assert t > 1.5
+
+
+# --------------------------------------------------------------------------- measures by hand
+def test_alm_measures_by_hand_maxcut():
+    # Path 0-1-2 with unit weights: C = -L/4 = [[-1/4, 1/4, 0], [1/4, -1/2, 1/4], [0, 1/4, -1/4]].
+    # R = [[1, 0], [0, 1], [1, 1]] gives X = RR^T = [[1, 0, 1], [0, 1, 1], [1, 1, 2]], so
+    # <C, X> = (-1/4 - 1/2 - 2/4) + 2 (1/4 * 0 + 1/4 * 1 + 0 * 1) = -3/4 and
+    # A(X) - b = diag(X) - 1 = (0, 0, 1).  With y = (1/2, -1, 2), b^T y = 3/2.
+    # Error measures of the experimental setting: err1 = ||res|| / (1 + ||b||_1) = 1/4,
+    # the infinity-norm variant 1 / (1 + 1) = 1/2, err3 = (-3/4 - 3/2) / (1 + 3/4 + 3/2) = -9/13.
+    prob = maxcut_problem(3, [0, 1], [1, 2])
+    R = np.array([[1.0, 0.0], [0.0, 1.0], [1.0, 1.0]])
+    y = np.array([0.5, -1.0, 2.0])
+    m = K.alm_measures(prob, R, y)
+    assert m["obj"] == -0.75
+    assert m["res_norm"] == 1.0
+    assert m["dual"] == 1.5
+    assert m["err1"] == 0.25
+    assert m["err1_inf"] == 0.5
+    assert np.isclose(m["err3"], -9.0 / 13.0, rtol=1e-15)
+
+
+def test_alm_measures_by_hand_completion():
+    # n1 = n2 = 2, samples (0,0) M = 1.5, (1,1) M = -0.5, (0,1) M = 2, so b = (3, -1, 4).
+    # Rows of R: top block R0 = (1, 2), R1 = (0, 1); bottom block R2 = (1, -1), R3 = (2, 0).
+    # <I, RR^T> = ||R||_F^2 = 5 + 1 + 2 + 4 = 12; A(RR^T)_k = 2 R_i . R_{n1+j} = (-2, 0, 4);
+    # res = (-5, 1, 0), ||res|| = sqrt(26), ||b||_1 = 8, ||b||_inf = 4.
+    # y = (1, -2, 1/2): b^T y = 3 + 2 + 2 = 7, err3 = (12 - 7) / (1 + 12 + 7) = 1/4.
+    prob = completion_problem(2, 2, [0, 1, 0], [0, 1, 1], [1.5, -0.5, 2.0])
+    R = np.array([[1.0, 2.0], [0.0, 1.0], [1.0, -1.0], [2.0, 0.0]])
+    y = np.array([1.0, -2.0, 0.5])
+    m = K.alm_measures(prob, R, y)
+    assert m["obj"] == 12.0
+    assert np.allclose(K.constraint_map(prob, R), [-2.0, 0.0, 4.0], rtol=0, atol=0)
+    assert np.isclose(m["res_norm"], np.sqrt(26.0), rtol=1e-15)
+    assert m["dual"] == 7.0
+    assert np.isclose(m["err1"], np.sqrt(26.0) / 9.0, rtol=1e-15)
+    assert np.isclose(m["err1_inf"], np.sqrt(26.0) / 5.0, rtol=1e-15)
+    assert m["err3"] == 0.25

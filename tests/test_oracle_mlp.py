@@ -32,6 +32,12 @@ def test_features_small_graph_by_hand():
     assert np.isclose(F[0, 13], np.log(4) - np.log(2))
     assert np.all(F[4, [3, 4, 5, 6, 10, 13, 14]] == 0) and F[4, 15] == 1
     assert np.allclose(F[:, 11], np.log(5) / 20)
+    # dbar = 2|E|/n = 6/5: column 7 is log(1 + d_i/dbar), 8 is 1/(1 + d_i), 9 is a_i/max(d_i, 1)
+    # (a_i = sum_j |w_ij| = 2, 6, 1, 3, 0), 12 is log(1 + dbar)
+    assert np.allclose(F[:, 7], np.log([1 + 1 / 1.2, 1 + 3 / 1.2, 1 + 1 / 1.2, 1 + 1 / 1.2, 1.0]), rtol=1e-15)
+    assert np.allclose(F[:, 8], [0.5, 0.25, 0.5, 0.5, 1.0], rtol=0, atol=0)
+    assert np.allclose(F[:, 9], [2.0, 2.0, 1.0, 3.0, 0.0], rtol=0, atol=0)
+    assert np.allclose(F[:, 12], np.log(2.2), rtol=1e-15)
 
 
 def test_mlp_gradient_central_differences():
