@@ -1,18 +1,25 @@
 #!/usr/bin/env python3
 """Time to 1e-5 tolerance of the MaxCut SDP hot path on one MI355X.
 
-Workload (one "step"): the 1e6-node MaxCut SDP pair -- an Erdos-Renyi graph
-and a Chung-Lu power-law graph (exponent 2.5, mean degree 10), 5e6 edges
-each, weights uniform in {-1, +1}, C = -L/4, diag(X) = 1, rank 20 -- each
-solved from a seeded unit-row starting factor until err1 <= 1e-5 and
-|err3| <= 1e-5 with the plain float64 method.  Problems, starting factors and
-workspaces are resident in HBM before the timed region; the timed region is
-the solves themselves.  The float32 path is run after the timed region and
-reported beside it.
+Workload (one "step"): the plain float64 method (ALM + L-BFGS with H0 = I and
+the exact line search) solving the 1e7-node Chung-Lu MaxCut SDP (exponent 2.5,
+mean degree 8, 4e7 edges, unit weights, C = -L/4, diag(X) = 1, rank 24) from a
+seeded unit-row starting factor until err1 <= 1e-5 and |err3| <= 1e-5.  The
+problem, the starting factor and the workspace are resident in HBM before the
+timed region; the timed region is the solve.  Beside it, untimed by the step but
+timed on its own: float32 + learned warm start on the same graph (features and
+MLP inference counted in its time), with the model committed beside the
+library.
+
+The whole run keeps to a wall-clock budget (--budget, counted from the start of
+the process, generation and upload included): warm-ups are short capped solves,
+as many timed solves run as fit (at least one; `steps` reports the executed
+count), every solve carries a time limit, and the comparison path and the CPU
+baseline run only in the time left.
 
 The JSON line carries the SpMM roofline (algorithmic bytes per launch over the
 launch duration measured with HIP events on the solve's stream) and the CPU
-oracle's time on a bounded sample of the same workload.
+oracle's time on a bounded sample of the same workload family.
 """
 
 import argparse
@@ -22,38 +29,43 @@ import os
 import sys
 import time
 
+T_START = time.perf_counter()
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "time to 1e-5 tol: plain FP64 vs FP32+learned warm start; SpMM/SDDMM HBM GB/s"
 HBM_PEAK_GBS = 8000.0
-WORKLOAD = ("maxcut n=1e6 pair: Erdos-Renyi 5e6 edges + Chung-Lu beta=2.5 mean degree 10 (5e6 edges), "
-            "weights uniform in {-1,+1}, C=-L/4, diag(X)=1, rank 20")
-INSTANCES = ["er_1m_pm1", "cl_1m_pm1"]
-ALL_PATHS = ["f64_degsort", "f64_precond", "f64_dynrank", "f64_reopt", "f64_reopt2", "f32", "f32_precond",
-             "f32_bf16in", "f32_warm", "f32_precond_warm", "f32_dynrank_precond"]
-DYNRANK_LD = {0: 30, 1: 32}       # row stride with room for the grown rank (FP64, FP32)
-OTHER_WORKLOADS = {
-    "cl_10m": "maxcut n=1e7 Chung-Lu beta=2.5 mean degree 8 (4e7 edges), unit weights, C=-L/4, diag(X)=1, rank 24",
-    "er_1k": "maxcut n=1e3 Erdos-Renyi 5e3 edges, unit weights, C=-L/4, diag(X)=1, rank 10",
+WORKLOADS = {
+    "cl_10m": (["cl_10m"], "maxcut n=1e7 Chung-Lu beta=2.5 mean degree 8 (4e7 edges), unit weights, C=-L/4, "
+                           "diag(X)=1, rank 24"),
+    "pair_1m": (["er_1m_pm1", "cl_1m_pm1"],
+                "maxcut n=1e6 pair: Erdos-Renyi 5e6 edges + Chung-Lu beta=2.5 mean degree 10 (5e6 edges), "
+                "weights uniform in {-1,+1}, C=-L/4, diag(X)=1, rank 20"),
+    "er_1k": (["er_1k"], "maxcut n=1e3 Erdos-Renyi 5e3 edges, unit weights, C=-L/4, diag(X)=1, rank 10"),
 }
+DEFAULT_PATHS = "f32_warm"
+ALL_PATHS = ["f32_warm", "f32_precond_warm", "f32", "f32_precond", "f32_bf16in", "f64_precond", "f64_degsort",
+             "f64_dynrank", "f64_reopt", "f64_reopt2", "f32_dynrank_precond"]
+DYNRANK_LD = {0: 30, 1: 32}       # row stride with room for the grown rank (FP64, FP32)
 
 
 def parse():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2, help="timed solves at most (as many as fit the budget run)")
+    ap.add_argument("--warmup", type=int, default=1, help="warm-up solves, each capped at --warmup-iters")
+    ap.add_argument("--warmup-iters", type=int, default=20)
+    ap.add_argument("--budget", type=float, default=540.0,
+                    help="wall-clock budget of the whole run in seconds, from process start")
+    ap.add_argument("--workload", default="cl_10m", choices=sorted(WORKLOADS))
+    ap.add_argument("--instances", default=None, help="comma list of named instances (overrides --workload)")
+    ap.add_argument("--paths", default=DEFAULT_PATHS,
+                    help="comparison paths run after the timed steps in the time left (comma list of: "
+                         + ", ".join(ALL_PATHS) + ")")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-f32", action="store_true", help="skip the float32 / warm-start / bf16 paths")
-    ap.add_argument("--no-warm", action="store_true", help="skip the learned warm start")
-    ap.add_argument("--no-bf16", action="store_true", help="skip the bfloat16-input path")
-    ap.add_argument("--no-precond", action="store_true", help="skip the row-block H0 paths")
-    ap.add_argument("--paths", default=",".join(ALL_PATHS),
-                    help="untimed comparison paths to run after the timed step (comma list)")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0,
-                    help="target CPU time of the oracle sample")
-    ap.add_argument("--instances", default=",".join(INSTANCES))
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--cert", action="store_true", help="dual certificate of every result (untimed)")
+    ap.add_argument("--cert-iters", type=int, default=600)
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--short", type=int, default=0,
                     help="profiling aid: cap each solve at this many L-BFGS iterations (first ALM step only)")
@@ -70,38 +82,14 @@ def parse():
 
 
 def log(*a):
-    print("[bench]", *a, file=sys.stderr, flush=True)
-
-
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "spmm_maxcut_traffic_pair_1m_f64.md")
-SPMM_SOURCES = [os.path.join(ROOT, "paper_2407_15049_amd", "csrc", f)
-                for f in ("spmm_maxcut.hip", "device.h", "kernels.h")]
-
-
-def measured_traffic():
-    """HBM bytes per SpMM launch from the committed counter summary, or None when
-    the SpMM sources changed since the counters were taken."""
-    import hashlib
-    try:
-        text = open(TRAFFIC_PROFILE).read()
-    except OSError:
-        return None
-    fields = dict(line.split(": ", 1) for line in text.splitlines()
-                  if line.startswith(("source_sha256: ", "traffic_bytes_per_launch: ")))
-    h = hashlib.sha256()
-    for f in SPMM_SOURCES:
-        with open(f, "rb") as fh:
-            h.update(fh.read())
-    if fields.get("source_sha256") != h.hexdigest():
-        return None
-    return float(fields["traffic_bytes_per_launch"])
+    print(f"[bench {time.perf_counter() - T_START:7.1f}s]", *a, file=sys.stderr, flush=True)
 
 
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); "
-              "run with --gpus 1", file=sys.stderr)
+        print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); nothing here uses a "
+              "second GPU, so run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
@@ -115,283 +103,123 @@ def main():
         return completion_bench(args, ctx, dev)
     if args.general:
         return general_bench(args, ctx, dev)
-    names = args.instances.split(",")
+
+    def left():
+        return args.budget - (time.perf_counter() - T_START)
+
+    if args.instances:
+        names = args.instances.split(",")
+        known = {tuple(v[0]): (k, v[1]) for k, v in WORKLOADS.items()}
+        wl_name, wl_desc = known.get(tuple(names), (",".join(names), ",".join(names)))
+    else:
+        names, wl_desc = WORKLOADS[args.workload]
+        wl_name = args.workload
     runs = []
     for name in names:
         t0 = time.perf_counter()
         inst = maxcut_instance(name)
+        t1 = time.perf_counter()
         n, r = inst["n"], inst["rank"]
-        prob = L.Problem.maxcut(n, inst["u"], inst["v"], inst["w"]).upload(ctx)
+        prob = L.Problem.maxcut(n, inst["u"], inst["v"], inst["w"])
+        t2 = time.perf_counter()
+        prob.upload(ctx)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
         R0 = init_factor(n, r, inst["seed"] + 1)
-        per = {}
-        for prec in ([L.F64] if args.no_f32 else [L.F64, L.F32]):
-            ld = L.padded_ld(r, prec)
-            opts = L.default_options(prec=prec, rank=r, ld=ld, profile=1, verbose=int(args.verbose))
-            if args.short:
-                opts.max_outer, opts.max_inner = 1, args.short
-            R0d = torch.zeros((n, ld), dtype=L.elem_dtype(prec), device=dev)
-            R0d[:, :r] = torch.from_numpy(R0).to(dev, R0d.dtype)
-            per[prec] = dict(
-                opts=opts, R0=R0d, R=torch.empty_like(R0d),
-                y=torch.zeros(n, dtype=torch.float64, device=dev),
-                ws=torch.empty(L.workspace_bytes(prob, opts), dtype=torch.uint8, device=dev))
+        ld = L.padded_ld(r, L.F64)
+        R0d = torch.zeros((n, ld), dtype=torch.float64, device=dev)
+        R0d[:, :r] = torch.from_numpy(R0).to(dev)
+        del R0
+        opts = L.default_options(prec=L.F64, rank=r, ld=ld, profile=1, verbose=int(args.verbose))
+        if args.short:
+            opts.max_outer, opts.max_inner = 1, args.short
+        per = {L.F64: dict(opts=opts, R0=R0d, R=torch.empty_like(R0d),
+                           y=torch.zeros(n, dtype=torch.float64, device=dev),
+                           ws=torch.empty(L.workspace_bytes(prob, opts), dtype=torch.uint8, device=dev))}
         info = prob.info
-        runs.append(dict(name=name, inst=inst, prob=prob, per=per, n=n, r=r, nnz=info.nnz))
-        log(f"{name}: n={n} nnz={info.nnz} max_row={info.max_row_nnz} setup {time.perf_counter() - t0:.1f}s")
+        runs.append(dict(name=name, inst=inst, prob=prob, per=per, n=n, r=r, nnz=info.nnz,
+                         setup=dict(generate_s=round(t1 - t0, 2), build_s=round(t2 - t1, 2),
+                                    upload_s=round(t3 - t2, 2))))
+        log(f"{name}: n={n} nnz={info.nnz} max_row={info.max_row_nnz} generate {t1 - t0:.1f}s "
+            f"build {t2 - t1:.1f}s upload {t3 - t2:.1f}s")
     torch.cuda.synchronize()
 
-    def solve(run, prec):
+    def solve(run, prec, opts=None, limit=None, R_init=None, y_init=None, ws=None):
+        """One solve of `run` in `prec` from its starting factor (or R_init / y_init),
+        stopped by the solver's own time limit when `limit` is given."""
         p = run["per"][prec]
-        p["R"].copy_(p["R0"])
-        p["y"].zero_()
+        o = opts if opts is not None else p["opts"]
+        if limit is not None:
+            o.time_limit_s = max(1.0, limit)
+        p["R"].copy_(p["R0"] if R_init is None else R_init)
+        if y_init is None:
+            p["y"].zero_()
+        else:
+            p["y"].copy_(y_init)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        rc, res = L.solve(ctx, run["prob"], p["R"], p["y"], p["opts"], workspace=p["ws"])
+        rc, res = L.solve(ctx, run["prob"], p["R"], p["y"], o, workspace=p["ws"] if ws is None else ws)
         torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        if rc != L.OK and not args.short:
-            raise RuntimeError(f"{run['name']} prec {prec} did not converge: {res.as_dict()}")
-        return dt, res
+        return time.perf_counter() - t0, rc, res
 
-    cert_ws = {}
-
-    def cert_of(run, y, obj):
-        """Dual certificate of the multipliers y (outside every timed region)."""
-        if run["name"] not in cert_ws:
-            cert_ws[run["name"]] = torch.empty(L.certify_workspace_bytes(run["prob"], 600), dtype=torch.uint8,
-                                               device=dev)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        c = L.certify(ctx, run["prob"], y, max_iter=600, tol=1e-8 * abs(obj) / run["n"],
-                      work=cert_ws[run["name"]])
-        dt = time.perf_counter() - t0
-        gap = (obj - c.dual_bound) / (1.0 + abs(obj) + abs(c.dual_bound))
-        return dict(lambda_min=c.lambda_min, cert_resid=c.resid, dual_bound=c.dual_bound, cert_gap=gap,
-                    err2=c.err2, cert_iters=c.iters, cert_s=round(dt, 4))
-
+    # ---- warm-up: short capped solves (kernels loaded, clocks up)
+    warm_opts = {}
     for w in range(args.warmup):
         for run in runs:
-            dt, res = solve(run, L.F64)
-            log(f"warmup {w} {run['name']} f64 {dt:.3f}s outer {res.outer} inner {res.inner}")
+            p = run["per"][L.F64]
+            o = L.default_options(prec=L.F64, rank=run["r"], ld=p["opts"].ld, max_outer=1,
+                                  max_inner=args.warmup_iters)
+            warm_opts[run["name"]] = o
+            dt, rc, res = solve(run, L.F64, opts=o)
+            log(f"warm-up {w} {run['name']}: {res.inner} iterations {dt:.2f}s")
 
+    # ---- timed steps: full float64 solves, as many as fit
+    reserve_cpu = 0.0 if args.no_cpu_baseline else args.cpu_seconds + 15.0
+    enabled = [q for q in args.paths.split(",") if q] if args.paths else []
     step_times, recs = [], {run["name"]: [] for run in runs}
     for s in range(args.steps):
+        if step_times:
+            # keep room for the comparison path (about half a float64 solve) and the CPU sample
+            need = step_times[-1] + (0.5 * step_times[0] if enabled else 0.0) + reserve_cpu + 10.0
+            if need > left():
+                log(f"budget: {left():.0f}s left, a further step needs about {need:.0f}s; {s} step(s) timed")
+                break
+        limit = left() - reserve_cpu - 10.0
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for run in runs:
-            dt, res = solve(run, L.F64)
-            recs[run["name"]].append((dt, res))
+            dt, rc, res = solve(run, L.F64, limit=limit / len(runs))
+            recs[run["name"]].append((dt, rc, res))
+            log(f"step {s} {run['name']}: {dt:.2f}s rc {rc} outer {res.outer} inner {res.inner} "
+                f"obj {res.obj:.10e} err1 {res.err1:.2e} err3 {res.err3:.2e}")
         torch.cuda.synchronize()
         step_times.append(time.perf_counter() - t0)
-        log(f"step {s}: {step_times[-1]:.3f}s")
     ms_per_step = 1000.0 * sum(step_times) / len(step_times) if step_times else None
+    converged = all(rc == L.OK for v in recs.values() for _, rc, _ in v)
 
-    # SpMM roofline from the HIP events of the timed solves
-    spmm_ms = sum(res.spmm_ms for v in recs.values() for _, res in v)
-    spmm_n = sum(res.spmm_launches for v in recs.values() for _, res in v)
-    spmm_bytes = sum(res.spmm_bytes * res.spmm_launches for v in recs.values() for _, res in v)
+    # ---- SpMM roofline from the HIP events of the timed solves
+    allres = [res for v in recs.values() for _, _, res in v]
+    spmm_ms = sum(res.spmm_ms for res in allres)
+    spmm_n = sum(res.spmm_launches for res in allres)
+    spmm_bytes = sum(res.spmm_bytes * res.spmm_launches for res in allres)
     achieved = (spmm_bytes / 1e9) / (spmm_ms / 1e3) if spmm_ms > 0 else None
-    traffic = measured_traffic()
+    traffic = measured_traffic(wl_name)
 
-    enabled = [p for p in args.paths.split(",") if p] if args.paths else []
-    drop = set()
-    if args.no_precond:
-        drop |= {"f64_precond", "f32_precond", "f32_precond_warm"}
-    if args.no_f32:
-        drop |= {p for p in ALL_PATHS if p.startswith("f32")}
-    if args.no_bf16:
-        drop.add("f32_bf16in")
-    if args.no_warm:
-        drop |= {"f32_warm", "f32_precond_warm"}
-    enabled = [p for p in enabled if p not in drop]
     paths = {"f64": {}}
-    for run in ([] if not step_times else runs):
-        dt, res = recs[run["name"]][-1]
-        rec = dict(seconds=round(dt, 4), outer=res.outer, inner=res.inner, obj=res.obj, err1=res.err1,
-                   err3=res.err3, spmm_us=round(1e3 * res.spmm_ms / max(res.spmm_launches, 1), 2))
-        if not args.short:
-            rec.update(cert_of(run, run["per"][L.F64]["y"], res.obj))
-            log(f"f64 {run['name']} certificate: lambda_min {rec['lambda_min']:.3e} gap {rec['cert_gap']:.2e} "
-                f"({rec['cert_iters']} steps, {rec['cert_s']}s)")
+    for run in runs:
+        if not recs[run["name"]]:
+            continue
+        dt, rc, res = recs[run["name"]][-1]
+        rec = dict(seconds=round(dt, 3), converged=rc == L.OK, outer=res.outer, inner=res.inner, obj=res.obj,
+                   err1=res.err1, err1_inf=res.err1_inf, err3=res.err3,
+                   ms_per_iter=round(1e3 * dt / max(res.inner, 1), 3),
+                   spmm_us=round(1e3 * res.spmm_ms / max(res.spmm_launches, 1), 2),
+                   all_seconds=[round(d, 3) for d, _, _ in recs[run["name"]]])
         paths["f64"][run["name"]] = rec
 
-    def record(path, run, dt, res, extra=None, y=None):
-        o64 = paths["f64"].get(run["name"], {}).get("obj")
-        rec = dict(seconds=round(dt, 4), outer=res.outer, inner=res.inner, obj=res.obj, err1=res.err1,
-                   err3=res.err3, obj_rel_vs_f64=abs(res.obj - o64) / abs(o64) if o64 else None,
-                   spmm_us=round(1e3 * res.spmm_ms / max(res.spmm_launches, 1), 2))
-        rec.update(extra or {})
-        if y is not None and not args.short:
-            rec.update(cert_of(run, y, res.obj))
-        paths.setdefault(path, {})[run["name"]] = rec
-        log(f"{path} {run['name']} {dt:.3f}s outer {res.outer} inner {res.inner} obj {res.obj:.8e}"
-            + (f" cert gap {rec['cert_gap']:.2e}" if "cert_gap" in rec else ""))
+    copy_gbs = copy_ceiling(torch, dev, args.copy_calibration) if step_times else None
 
-    def solve_with(run, prec, **kw):
-        """One untimed-by-the-step solve of `run` in `prec` with extra options."""
-        p = run["per"][prec]
-        o = L.default_options(prec=prec, rank=run["r"], ld=p["opts"].ld, profile=1, verbose=int(args.verbose), **kw)
-        ws = torch.empty(L.workspace_bytes(run["prob"], o), dtype=torch.uint8, device=dev)
-        p["R"].copy_(p["R0"])
-        p["y"].zero_()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        rc, res = L.solve(ctx, run["prob"], p["R"], p["y"], o, workspace=ws)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        del ws
-        return dt, rc, res
-
-    if "f64_degsort" in enabled:
-        # the same graphs with nodes relabelled by decreasing degree (hubs first):
-        # the locality counterpart of the random labels of the timed step; the
-        # starting factor is permuted with the nodes, so the solve is the same
-        # problem up to the order of summation
-        import numpy as np
-        for run in runs:
-            inst, n = run["inst"], run["n"]
-            deg = np.bincount(inst["u"], minlength=n) + np.bincount(inst["v"], minlength=n)
-            order = np.argsort(-deg, kind="stable")            # new node k is old node order[k]
-            new_id = np.empty(n, dtype=np.int64)
-            new_id[order] = np.arange(n)
-            prob2 = L.Problem.maxcut(n, new_id[inst["u"]], new_id[inst["v"]], inst["w"]).upload(ctx)
-            p = run["per"][L.F64]
-            o = L.default_options(prec=L.F64, rank=run["r"], ld=p["opts"].ld, profile=1, verbose=int(args.verbose))
-            ws = torch.empty(L.workspace_bytes(prob2, o), dtype=torch.uint8, device=dev)
-            R = p["R0"][torch.from_numpy(order).to(dev)].contiguous()
-            y = torch.zeros(n, dtype=torch.float64, device=dev)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            rc, res = L.solve(ctx, prob2, R, y, o, workspace=ws)
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - t0
-            y_orig = y[torch.from_numpy(new_id).to(dev)].contiguous()     # back to the original labels
-            record("f64_degsort", run, dt, res, dict(converged=rc == L.OK), y=y_orig)
-            del prob2, ws, R, y, y_orig
-    if "f64_precond" in enabled:
-        # row-block H0 for Algorithm 1 (an extension; the timed step keeps H0 = I)
-        for run in runs:
-            dt, rc, res = solve_with(run, L.F64, precond=1)
-            record("f64_precond", run, dt, res, dict(converged=rc == L.OK), y=run["per"][L.F64]["y"])
-    def solve_dynrank(run, prec, **kw):
-        """Dynamic rank (appendix A.1): start at the workload's rank, grow in place
-        up to the stride DYNRANK_LD."""
-        ld = DYNRANK_LD[0 if prec == L.F64 else 1]
-        o = L.default_options(prec=prec, rank=run["r"], ld=ld, profile=1, rank_max=ld,
-                              verbose=int(args.verbose), **kw)
-        ws = torch.empty(L.workspace_bytes(run["prob"], o), dtype=torch.uint8, device=dev)
-        R = torch.zeros((run["n"], ld), dtype=L.elem_dtype(prec), device=dev)
-        R[:, :run["r"]] = run["per"][prec]["R0"][:, :run["r"]]
-        y = run["per"][prec]["y"]
-        y.zero_()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        rc, res = L.solve(ctx, run["prob"], R, y, o, workspace=ws)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        del ws, R
-        return dt, rc, res, y
-
-    if "f64_dynrank" in enabled:
-        for run in runs:
-            dt, rc, res, y = solve_dynrank(run, L.F64)
-            record("f64_dynrank", run, dt, res, dict(converged=rc == L.OK, rank_final=res.rank_final), y=y)
-    for path, level in (("f64_reopt", 1), ("f64_reopt2", 2)):
-        # re-optimisation (Section 4.1): rounds stop at err1 <= tol; C scaled by
-        # 0.1 per extra round until |err3| <= tol (and err2 <= tol at level 2)
-        if path in enabled:
-            for run in runs:
-                dt, rc, res = solve_with(run, L.F64, reopt=level)
-                extra = dict(converged=rc == L.OK, reopt_rounds=res.reopt_rounds)
-                if level == 2:
-                    extra["reopt_err2"] = res.err2
-                record(path, run, dt, res, extra, y=run["per"][L.F64]["y"])
-    if "f32" in enabled:
-        for run in runs:
-            dt, res = solve(run, L.F32)
-            record("f32", run, dt, res, y=run["per"][L.F32]["y"])
-    if "f32_precond" in enabled:
-        for run in runs:
-            dt, rc, res = solve_with(run, L.F32, precond=1)
-            record("f32_precond", run, dt, res, dict(converged=rc == L.OK), y=run["per"][L.F32]["y"])
-    if "f32_bf16in" in enabled:
-        # bfloat16 gathered operand (float32 iterate, exact gradient every 25 iterations)
-        for run in runs:
-            p = run["per"][L.F32]
-            o = L.default_options(prec=L.F32_BF16IN, rank=run["r"], ld=p["opts"].ld, profile=1, refresh_every=25)
-            ws = torch.empty(L.workspace_bytes(run["prob"], o), dtype=torch.uint8, device=dev)
-            p["R"].copy_(p["R0"])
-            p["y"].zero_()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            rc, res = L.solve(ctx, run["prob"], p["R"], p["y"], o, workspace=ws)
-            torch.cuda.synchronize()
-            record("f32_bf16in", run, time.perf_counter() - t0, res, dict(converged=rc == L.OK), y=p["y"])
-            del ws
-    if "f32_dynrank_precond" in enabled:
-        for run in runs:
-            dt, rc, res, y = solve_dynrank(run, L.F32, precond=1)
-            record("f32_dynrank_precond", run, dt, res, dict(converged=rc == L.OK, rank_final=res.rank_final), y=y)
-    warm_paths = [w for w in ("f32_warm", "f32_precond_warm") if w in enabled]
-    if warm_paths:
-        from paper_2407_15049_amd import warmstart as W
-        t0 = time.perf_counter()
-        data = W.make_training_set(ctx, log=log)
-        t1 = time.perf_counter()
-        params, hist = W.train(ctx, data, steps=400, lr=3e-3, log=log)
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        del data
-        warm_info = dict(train_graphs=len(W.TRAIN_SPECS), label_solves_s=round(t1 - t0, 2),
-                         train_s=round(t2 - t1, 2), loss_first=hist[0][1], loss_last=hist[-1][1])
-        for wp in warm_paths:
-            for run in runs:
-                p = run["per"][L.F32]
-                o = L.default_options(prec=L.F32, rank=run["r"], ld=p["opts"].ld, profile=1,
-                                      precond=1 if wp == "f32_precond_warm" else 0,
-                                      verbose=int(args.verbose))
-                ws = torch.empty(L.workspace_bytes(run["prob"], o), dtype=torch.uint8, device=dev)
-                p["R"].copy_(p["R0"])
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()           # features + inference count toward the solve
-                y0, sigma0 = W.warm_start(ctx, run["prob"], params)
-                p["y"].copy_(y0)
-                o.sigma0 = sigma0
-                rc, res = L.solve(ctx, run["prob"], p["R"], p["y"], o, workspace=ws)
-                torch.cuda.synchronize()
-                record(wp, run, time.perf_counter() - t0, res, dict(sigma0=sigma0, converged=rc == L.OK), y=p["y"])
-                del ws
-            paths[wp]["model"] = warm_info
-
-    if args.copy_calibration:
-        a = torch.ones(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        log("copy calibration: 3 x 1 GiB device-to-device copies")
-        del a, b
-
-    # copy ceiling of the box: a 1 GiB device-to-device copy, read + write bytes
-    # over its HIP-event time (median of 10)
-    copy_gbs = None
-    if step_times:
-        a = torch.ones(1 << 27, dtype=torch.float64, device=dev)
-        b = torch.empty_like(a)
-        stream = torch.cuda.current_stream(dev)
-        for _ in range(3):
-            b.copy_(a)
-        times = []
-        for _ in range(10):
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            b.copy_(a)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            times.append(e0.elapsed_time(e1) / 1e3)
-        copy_gbs = round(2.0 * (1 << 30) / 1e9 / sorted(times)[len(times) // 2], 1)
-        log(f"copy ceiling: {copy_gbs} GB/s")
-        del a, b
+    comparison_paths(args, ctx, dev, L, runs, paths, enabled, left, reserve_cpu, solve, log)
 
     cpu = None
     if not args.no_cpu_baseline and step_times:
@@ -399,20 +227,23 @@ def main():
 
     out = {
         "metric": METRIC,
-        "value": round(ms_per_step / 1000.0, 4) if ms_per_step else None,
+        "value": round(ms_per_step / 1000.0, 3) if ms_per_step else None,
         "unit": "s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": len(step_times),
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 2) if ms_per_step else None,
+        "ms_per_step": round(ms_per_step, 1) if ms_per_step else None,
         "higher_is_better": False,
         "scaling": "strong",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD if names == INSTANCES else
-                   "; ".join(OTHER_WORKLOADS.get(nm, nm) for nm in names), "instances": names, "tol": 1e-5, "path": "plain FP64 ALM + L-BFGS",
-                   "lbfgs_mem": runs[0]["per"][L.F64]["opts"].lbfgs_mem},
+        "config": {"workload": wl_desc, "name": wl_name, "instances": names, "tol": 1e-5,
+                   "path": "plain FP64 ALM + L-BFGS (H0 = I), exact line search",
+                   "lbfgs_mem": runs[0]["per"][L.F64]["opts"].lbfgs_mem, "converged": converged,
+                   "steps_requested": args.steps, "warmup_iters": args.warmup_iters, "budget_s": args.budget,
+                   "setup": {run["name"]: run["setup"] for run in runs}},
+        "step_seconds": [round(t, 3) for t in step_times],
         "roofline": {
             "kernel": "spmm (MaxCut, line-search epilogue)",
             "bound": "hbm",
@@ -421,17 +252,221 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
             "traffic": traffic,
-            "traffic_gbs": round(traffic / 1e9 / (spmm_ms / 1e3 / spmm_n), 1) if traffic and spmm_n else None,
+            "traffic_note": ("HBM-side bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated) from the stored "
+                             "counter summary of this workload; it counts L2 misses, MALL hits included"
+                             if traffic else "no counter summary matching the current SpMM sources"),
             "launches": spmm_n,
             "avg_us": round(1e3 * spmm_ms / max(spmm_n, 1), 2),
-            "alg_bytes_per_launch": {run["name"]: recs[run["name"]][-1][1].spmm_bytes for run in runs
+            "alg_bytes_per_launch": {run["name"]: recs[run["name"]][-1][2].spmm_bytes for run in runs
                                      if recs[run["name"]]},
             "copy_ceiling_gbs": copy_gbs,
         },
         "cpu_baseline": cpu,
         "paths": paths,
+        "wall_s": round(time.perf_counter() - T_START, 1),
     }
     print(json.dumps(out), flush=True)
+
+
+def copy_ceiling(torch, dev, calibration_copies):
+    """Read + write bytes of a 1 GiB device-to-device copy over its HIP-event time
+    (median of 10): the box's copy ceiling.  With calibration_copies, three more
+    untimed copies for the counter calibration of a profiled run."""
+    a = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    stream = torch.cuda.current_stream(dev)
+    for _ in range(3 if calibration_copies else 1):
+        b.copy_(a)
+    times = []
+    for _ in range(10):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        b.copy_(a)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1) / 1e3)
+    del a, b
+    gbs = round(2.0 * (1 << 30) / 1e9 / sorted(times)[len(times) // 2], 1)
+    log(f"copy ceiling: {gbs} GB/s")
+    return gbs
+
+
+def comparison_paths(args, ctx, dev, L, runs, paths, enabled, left, reserve_cpu, solve, log):
+    """Untimed-by-the-step paths on the same graphs, each one solve with a time
+    limit from what is left of the budget."""
+    import torch
+    if not enabled:
+        return
+
+    def budget_for_path():
+        return left() - reserve_cpu - 10.0
+
+    def record(path, run, dt, rc, res, extra=None, y=None):
+        o64 = paths["f64"].get(run["name"], {}).get("obj")
+        rec = dict(seconds=round(dt, 3), converged=rc == L.OK, outer=res.outer, inner=res.inner, obj=res.obj,
+                   err1=res.err1, err3=res.err3, obj_rel_vs_f64=abs(res.obj - o64) / abs(o64) if o64 else None,
+                   ms_per_iter=round(1e3 * dt / max(res.inner, 1), 3),
+                   spmm_us=round(1e3 * res.spmm_ms / max(res.spmm_launches, 1), 2))
+        rec.update(extra or {})
+        if args.cert and y is not None and not args.short:
+            rec.update(cert_of(args, ctx, dev, L, run, y, res.obj))
+        paths.setdefault(path, {})[run["name"]] = rec
+        log(f"{path} {run['name']} {dt:.2f}s rc {rc} outer {res.outer} inner {res.inner} obj {res.obj:.10e}")
+
+    def ensure_f32(run):
+        if L.F32 in run["per"]:
+            return run["per"][L.F32]
+        n, r = run["n"], run["r"]
+        ld = L.padded_ld(r, L.F32)
+        o = L.default_options(prec=L.F32, rank=r, ld=ld, profile=1, verbose=int(args.verbose))
+        R0 = torch.zeros((n, ld), dtype=torch.float32, device=dev)
+        R0[:, :r] = run["per"][L.F64]["R0"][:, :r].to(torch.float32)
+        run["per"][L.F32] = dict(opts=o, R0=R0, R=torch.empty_like(R0),
+                                 y=torch.zeros(n, dtype=torch.float64, device=dev),
+                                 ws=torch.empty(L.workspace_bytes(run["prob"], o), dtype=torch.uint8, device=dev))
+        return run["per"][L.F32]
+
+    def opts_for(run, prec, **kw):
+        p = run["per"][prec]
+        return L.default_options(prec=prec, rank=run["r"], ld=p["opts"].ld, profile=1,
+                                 verbose=int(args.verbose), **kw)
+
+    model = None
+    for path in enabled:
+        if path not in ALL_PATHS:
+            raise SystemExit(f"unknown path {path}")
+        for run in runs:
+            if budget_for_path() < 20.0:
+                paths.setdefault(path, {})[run["name"]] = dict(skipped=f"budget: {left():.0f}s left")
+                log(f"{path} {run['name']}: skipped, {left():.0f}s left")
+                continue
+            lim = budget_for_path()
+            if path in ("f32_warm", "f32_precond_warm"):
+                from paper_2407_15049_amd import warmstart as W
+                if model is None:
+                    model = W.load_model(dev)
+                if model is None:
+                    paths.setdefault(path, {})[run["name"]] = dict(skipped="no trained warm-start model in the tree")
+                    continue
+                p = ensure_f32(run)
+                o = opts_for(run, L.F32, precond=1 if path == "f32_precond_warm" else 0)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()                 # features + inference count toward the solve
+                y0, sigma0 = W.warm_start(ctx, run["prob"], model)
+                o.sigma0 = sigma0
+                dt, rc, res = solve(run, L.F32, opts=o, limit=lim - (time.perf_counter() - t0), y_init=y0)
+                dt = time.perf_counter() - t0
+                record(path, run, dt, rc, res, dict(sigma0=sigma0, model=model.meta.get("name")), y=p["y"])
+            elif path in ("f32", "f32_precond", "f32_bf16in"):
+                p = ensure_f32(run)
+                kw = dict(precond=1) if path == "f32_precond" else {}
+                if path == "f32_bf16in":
+                    o = L.default_options(prec=L.F32_BF16IN, rank=run["r"], ld=p["opts"].ld, profile=1,
+                                          refresh_every=25)
+                    ws = torch.empty(L.workspace_bytes(run["prob"], o), dtype=torch.uint8, device=dev)
+                    dt, rc, res = solve(run, L.F32, opts=o, limit=lim, ws=ws)
+                    del ws
+                else:
+                    dt, rc, res = solve(run, L.F32, opts=opts_for(run, L.F32, **kw), limit=lim)
+                record(path, run, dt, rc, res, y=p["y"])
+            elif path in ("f64_precond", "f64_reopt", "f64_reopt2"):
+                kw = {"f64_precond": dict(precond=1), "f64_reopt": dict(reopt=1), "f64_reopt2": dict(reopt=2)}[path]
+                o = opts_for(run, L.F64, **kw)
+                ws = torch.empty(L.workspace_bytes(run["prob"], o), dtype=torch.uint8, device=dev)
+                dt, rc, res = solve(run, L.F64, opts=o, limit=lim, ws=ws)
+                del ws
+                extra = dict(reopt_rounds=res.reopt_rounds) if "reopt" in path else None
+                record(path, run, dt, rc, res, extra, y=run["per"][L.F64]["y"])
+            elif path in ("f64_dynrank", "f32_dynrank_precond"):
+                prec = L.F64 if path == "f64_dynrank" else L.F32
+                if prec == L.F32:
+                    ensure_f32(run)
+                ld = DYNRANK_LD[0 if prec == L.F64 else 1]
+                o = L.default_options(prec=prec, rank=run["r"], ld=ld, profile=1, rank_max=ld,
+                                      verbose=int(args.verbose), precond=1 if prec == L.F32 else 0)
+                o.time_limit_s = max(1.0, lim)
+                ws = torch.empty(L.workspace_bytes(run["prob"], o), dtype=torch.uint8, device=dev)
+                R = torch.zeros((run["n"], ld), dtype=L.elem_dtype(prec), device=dev)
+                R[:, :run["r"]] = run["per"][prec]["R0"][:, :run["r"]]
+                y = torch.zeros(run["n"], dtype=torch.float64, device=dev)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                rc, res = L.solve(ctx, run["prob"], R, y, o, workspace=ws)
+                torch.cuda.synchronize()
+                record(path, run, time.perf_counter() - t0, rc, res, dict(rank_final=res.rank_final), y=y)
+                del ws, R
+            elif path == "f64_degsort":
+                # the same graph with nodes relabelled by decreasing degree (hubs first), the
+                # starting factor permuted alike: the same problem up to the order of summation
+                import numpy as np
+                inst, n = run["inst"], run["n"]
+                deg = np.bincount(inst["u"], minlength=n) + np.bincount(inst["v"], minlength=n)
+                order = np.argsort(-deg, kind="stable")
+                new_id = np.empty(n, dtype=np.int64)
+                new_id[order] = np.arange(n)
+                prob2 = L.Problem.maxcut(n, new_id[inst["u"]], new_id[inst["v"]], inst["w"]).upload(ctx)
+                o = opts_for(run, L.F64)
+                o.time_limit_s = max(1.0, lim)
+                ws = torch.empty(L.workspace_bytes(prob2, o), dtype=torch.uint8, device=dev)
+                R = run["per"][L.F64]["R0"][torch.from_numpy(order).to(dev)].contiguous()
+                y = torch.zeros(n, dtype=torch.float64, device=dev)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                rc, res = L.solve(ctx, prob2, R, y, o, workspace=ws)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                y_orig = y[torch.from_numpy(new_id).to(dev)].contiguous()
+                record(path, run, dt, rc, res, y=y_orig)
+                del prob2, ws, R, y
+    if args.cert:
+        for run in runs:
+            rec = paths["f64"].get(run["name"])
+            if rec and left() > reserve_cpu + 20:
+                rec.update(cert_of(args, ctx, dev, L, run, run["per"][L.F64]["y"], rec["obj"]))
+
+
+def cert_of(args, ctx, dev, L, run, y, obj):
+    """Dual estimate of the multipliers y by block Lanczos (outside every timed
+    region): lambda_min is a Ritz value, the bound subtracts its residual."""
+    import torch
+    torch.cuda.synchronize()
+    work = torch.empty(L.certify_workspace_bytes(run["prob"], args.cert_iters), dtype=torch.uint8, device=dev)
+    t0 = time.perf_counter()
+    c = L.certify(ctx, run["prob"], y, max_iter=args.cert_iters, tol=1e-8 * abs(obj) / run["n"], work=work)
+    dt = time.perf_counter() - t0
+    gap = (obj - c.dual_bound) / (1.0 + abs(obj) + abs(c.dual_bound))
+    return dict(lambda_min=c.lambda_min, cert_resid=c.resid, dual_bound_est=c.dual_bound, gap_est=gap,
+                err2=c.err2, cert_iters=c.iters, cert_s=round(dt, 3))
+
+
+TRAFFIC_PROFILES = {
+    "pair_1m": "spmm_maxcut_traffic_pair_1m_f64.md",
+    "cl_10m": "spmm_maxcut_traffic_cl_10m_f64.md",
+}
+SPMM_SOURCES = [os.path.join(ROOT, "paper_2407_15049_amd", "csrc", f)
+                for f in ("spmm_maxcut.hip", "device.h", "kernels.h")]
+
+
+def measured_traffic(workload):
+    """HBM bytes per SpMM launch from the committed counter summary of this
+    workload, or None when there is none or the SpMM sources changed since the
+    counters were taken."""
+    import hashlib
+    if workload not in TRAFFIC_PROFILES:
+        return None
+    try:
+        text = open(os.path.join(ROOT, "profiles", TRAFFIC_PROFILES[workload])).read()
+    except OSError:
+        return None
+    fields = dict(line.split(": ", 1) for line in text.splitlines()
+                  if line.startswith(("source_sha256: ", "traffic_bytes_per_launch: ")))
+    h = hashlib.sha256()
+    for f in SPMM_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    if fields.get("source_sha256") != h.hexdigest():
+        return None
+    return float(fields["traffic_bytes_per_launch"])
 
 
 COMPLETION = dict(n1=500_000, n2=500_000, k=5, per_row=20, rank=16, seed=15051)
@@ -607,47 +642,65 @@ def general_bench(args, ctx, dev):
 
 
 def cpu_baseline(runs, recs, target_s):
-    """Oracle (numpy/scipy FP64, one thread) L-BFGS iterations on every instance
-    for about target_s seconds in total; time per iteration times the
-    iterations the GPU FP64 solve of that instance took, summed over the
-    instances (the same unit as the step)."""
+    """The oracle (numpy/scipy, float64) timed on the host on a bounded sample of
+    the workload: per instance, L-BFGS iterations of its first ALM subproblem
+    for about target_s seconds in total, on the instance itself when it has at
+    most 2e7 stored entries, else on a graph of the same family with a tenth of
+    the nodes and edges (time per iteration scaled by the ratio of stored
+    entries).  Time per iteration times the iterations of the GPU float64
+    solve, summed over the instances: the unit of the step."""
     from threadpoolctl import threadpool_limits
 
     from oracle.alm import Options, alm_solve
     from oracle.problem import maxcut_problem
-    from synth import init_factor
+    from synth import MAXCUT_CONFIGS, chung_lu_edges, erdos_renyi_edges, init_factor, pm1_weights
 
-    total, parts = 0.0, []
-    with threadpool_limits(limits=1):
+    threads = max(1, min(os.cpu_count() or 1, 16))
+    total, parts, util = 0.0, [], []
+    with threadpool_limits(limits=threads):
         for run in runs:
             inst = run["inst"]
+            n, u, v, w, scale, what = inst["n"], inst["u"], inst["v"], inst["w"], 1.0, "the instance itself"
+            if run["nnz"] > 20_000_000:
+                kind, n0, m0, beta, wk, rank, seed = MAXCUT_CONFIGS[run["name"]]
+                n, m = n0 // 10, m0 // 10
+                u, v = chung_lu_edges(n, m, beta, seed + 1) if kind == "cl" else erdos_renyi_edges(n, m, seed + 1)
+                w = None if wk == "unit" else pm1_weights(m, seed + 7920)
+                what = f"a graph of the same family with n={n}, {m} edges"
             t0 = time.perf_counter()
-            op = maxcut_problem(inst["n"], inst["u"], inst["v"], inst["w"])
-            R0 = init_factor(inst["n"], inst["rank"], inst["seed"] + 1)
+            op = maxcut_problem(n, u, v, w)
+            R0 = init_factor(n, inst["rank"], inst["seed"] + 1)
+            if n != inst["n"]:
+                scale = run["nnz"] / float(op.C.nnz)
             build = time.perf_counter() - t0
-            t1 = time.perf_counter()                       # calibrate on 2 iterations
-            alm_solve(op, R0, opts=Options(max_outer=1, max_inner=2))
-            per_iter = (time.perf_counter() - t1) / 2
-            k = max(2, int(target_s / len(runs) / max(per_iter, 1e-6)))
-            t2 = time.perf_counter()
-            res = alm_solve(op, R0, opts=Options(max_outer=1, max_inner=k))
-            sample_s = time.perf_counter() - t2
-            per_iter = sample_s / max(res.inner, 1)
-            gres = recs[run["name"]][-1][1]
+            t1 = time.perf_counter()
+            alm_solve(op, R0, opts=Options(max_outer=1, max_inner=1))
+            one = time.perf_counter() - t1
+            k = max(2, int(target_s / len(runs) / max(one, 1e-6)))
+            t2, c2 = time.perf_counter(), time.process_time()
+            res = alm_solve(op, R0, opts=Options(max_outer=1, max_inner=1 + k))
+            wall = time.perf_counter() - t2
+            util.append((time.process_time() - c2) / max(wall, 1e-9))
+            per_iter = max(wall - one, 1e-9) / max(res.inner - 1, 1) * scale
+            gres = recs[run["name"]][-1][2]
             est = per_iter * gres.inner
             total += est
-            log(f"cpu oracle {run['name']}: {res.inner} iterations in {sample_s:.1f}s ({per_iter:.3f}s/iter), "
-                f"estimate for {gres.inner} iterations: {est:.0f}s (problem build {build:.1f}s)")
-            parts.append(f"{run['name']}: {res.inner} iterations in {sample_s:.1f}s, scaled to the GPU FP64 "
-                         f"solve's {gres.inner} iterations / {gres.outer} ALM steps")
+            log(f"cpu oracle {run['name']}: {res.inner} iterations in {wall:.1f}s on {what} "
+                f"({per_iter:.3f}s per iteration at full size), estimate for {gres.inner} iterations: {est:.0f}s "
+                f"(problem build {build:.1f}s)")
+            parts.append(f"{run['name']}: {res.inner - 1} iterations after the first ({wall - one:.1f}s) on {what}"
+                         + (f", scaled by the stored-entry ratio {scale:.2f}" if scale != 1.0 else "")
+                         + f", times the GPU FP64 solve's {gres.inner} iterations")
             del op
     return {
         "value": round(total, 1),
         "unit": "s",
-        "cores": 1,
+        "cores": threads,
+        "cpu_util": round(sum(util) / len(util), 2),
         "kind": "oracle",
-        "sample": ("oracle L-BFGS iterations of the first ALM subproblem (numpy/scipy, one thread), per "
-                   "instance: " + "; ".join(parts) + "; oracle problem builds not included"),
+        "sample": ("oracle L-BFGS iterations of the first ALM subproblem (numpy/scipy float64; BLAS pool of "
+                   f"{threads} threads, scipy's sparse products on one; cpu_util = process CPU seconds per wall "
+                   "second), per instance: " + "; ".join(parts) + "; problem builds not included"),
     }
 
 

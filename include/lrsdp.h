@@ -177,7 +177,8 @@ int lrsdp_problem_upload(lrsdp_ctx *ctx, lrsdp_problem *prob, void *dev,
  * check_every = 8, time_limit_s = 1e30, refresh_every = 0 (off), phase2 = 0,
  * switch_err1 = 1e-3, admm_check = 10, max_admm = 5000, precond = 0,
  * rank_max = 0 (off), rank_trigger = 2000, rank_scale = 1e-2, rank_seed = 15049,
- * reopt = 0, reopt_factor = 0.1, max_reopt = 10, cert_iters = 300.
+ * reopt = 0, reopt_factor = 0.1, max_reopt = 10, cert_iters = 300,
+ * sigma_hold = 0.
  * With re-optimisation the results (obj, dual, err3, sigma, y) are those of
  * the original problem: the last round's divided by its objective scale.
  */
@@ -240,13 +241,15 @@ typedef struct {
                                  restarted, no splitting phase after the first
                                  round).  2 (strict): as 1, and the final test
                                  also needs err2 <= tol, err2 from the
-                                 certified lower bound lambda_min - resid of a
+                                 estimated lower bound lambda_min - resid of a
                                  block Lanczos run (lrsdp_certify, at most
                                  cert_iters steps, residual target
                                  0.1 tol (1 + ||vec(C)||_1)) on C - A*(y)    */
     double  reopt_factor;     /* objective scale per round, 0 < f < 1          */
     int     max_reopt;        /* rounds after the first at most                */
     int     cert_iters;       /* reopt = 2: Lanczos steps per certificate      */
+    double  sigma_hold;       /* the penalty is not raised after an ALM step
+                                 whose err1 <= sigma_hold (0: always eligible) */
 } lrsdp_options;
 
 void lrsdp_options_default(lrsdp_options *opts);
@@ -369,14 +372,22 @@ int lrsdp_k_lbfgs_dir(lrsdp_ctx *ctx, int prec, int64_t n, int64_t ld,
 
 /* ---- learned warm start (MaxCut) -------------------------------------------
  * The paper has no warm start; this is the project's extension: a per-node MLP
- * 16 -> 64 -> 64 -> 2 (tanh hidden layers, float32 parameters laid out as
- * W1[64][16], b1[64], W2[64][64], b2[64], W3[2][64], b3[2]) maps 16 local graph
- * features of node i to (t_i, s_i); the warm start is y0_i = -t_i a_i / 4 with
- * a_i = sum_j |w_ij|, and sigma0 = (default sigma0) * exp(mean_i s_i).  Only
- * MaxCut problems are accepted (others: EUNSUPPORTED).
+ * 16 -> 64 -> 64 -> 2 (tanh hidden layers; parameters laid out as W1[64][16],
+ * b1[64], W2[64][64], b2[64], W3[2][64], b3[2]) maps 16 local graph features
+ * of node i to (t_i, s_i); the warm start is y0_i = -t_i a_i / 4 with
+ * a_i = sum_j |w_ij| and t_i limited to [-2, 2] (at an optimum y*_i =
+ * -sum_j w_ij (1 - X*_ij) / 4 with |X*_ij| <= 1), and sigma0 = (default
+ * sigma0) * exp(mean_i s_i) with the mean limited to a caller-given range (the
+ * range of the training labels).  The default sigma0 is 4 ||vec(C)||_1 / m.
+ * Parameters are float32 (LRSDP_PARAM_F32) or bfloat16 storage
+ * (LRSDP_PARAM_BF16, widened exactly to float32 in the kernels; training keeps
+ * a float32 master copy).  Activations and sums are float32.  Only MaxCut
+ * problems are accepted (others: EUNSUPPORTED).
  */
+#define LRSDP_PARAM_F32  0
+#define LRSDP_PARAM_BF16 1
 
-/* Number of float32 parameters (5378). */
+/* Number of parameters (5378). */
 int lrsdp_mlp_param_count(void);
 
 /* feat (device n x 16 float32, row-major) = node features of the problem's
@@ -384,37 +395,62 @@ int lrsdp_mlp_param_count(void);
 int lrsdp_ws_features(lrsdp_ctx *ctx, const lrsdp_problem *prob, float *feat, float *stats);
 
 /* Training targets from a solved problem: target (device n x 2 float32) =
- * (-4 y_i / a_i, log_sigma_ratio) (first entry 0 for isolated nodes); stats as
- * filled by lrsdp_ws_features, y the solution multipliers (device float64). */
+ * (-4 y_i / a_i, log(sigma_final / default sigma0)) (first entry 0 for
+ * isolated nodes); stats as filled by lrsdp_ws_features, y the solution
+ * multipliers (device float64), sigma_final the penalty the cold solve ended
+ * with (lrsdp_result.sigma; EINVAL unless positive and finite). */
 int lrsdp_ws_targets(lrsdp_ctx *ctx, const lrsdp_problem *prob, const float *stats, const double *y,
-                     double log_sigma_ratio, float *target);
+                     double sigma_final, float *target);
 
-/* out (device n x 2 float32) = MLP(feat). */
-int lrsdp_mlp_forward(lrsdp_ctx *ctx, const float *params, const float *feat, int64_t n, float *out);
+/* out (device n x 2 float32) = MLP(feat); params of param_dtype. */
+int lrsdp_mlp_forward(lrsdp_ctx *ctx, const void *params, int param_dtype, const float *feat, int64_t n,
+                      float *out);
 
-/* grad (device nparam float32) and *loss (device float64) of
- * L = (1/n) sum_i ||MLP(feat_i) - target_i||^2, target device n x 2 float32.
- * work: device float32 scratch of 256 * (nparam + 1).  Deterministic. */
-int lrsdp_mlp_grad(lrsdp_ctx *ctx, const float *params, const float *feat, const float *target, int64_t n,
-                   float *grad, double *loss, float *work);
+/* grad (device nparam float32) and *loss (device float64, may be NULL) of
+ * L = (1/n) sum_i ||MLP(feat_i) - target_i||^2, target device n x 2 float32,
+ * params of param_dtype.  work: device float32 scratch of 256 * (nparam + 1).
+ * Deterministic (fixed-order sums, no atomics). */
+int lrsdp_mlp_grad(lrsdp_ctx *ctx, const void *params, int param_dtype, const float *feat, const float *target,
+                   int64_t n, float *grad, double *loss, float *work);
 
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8; step counts from 1) on
  * device arrays of nparam float32. */
 int lrsdp_mlp_adam(lrsdp_ctx *ctx, float *params, float *m, float *v, const float *grad, int step, float lr);
 
-/* ---- dual certificate --------------------------------------------------------
+/* Full-batch training: `steps` Adam steps numbered first_step, first_step + 1,
+ * ...  Each step takes the gradient at the bfloat16 parameters params_bf16
+ * (device nparam uint16), updates the float32 master copy `master` with the
+ * moments m, v (device nparam float32 each, zero before step 1), and rounds
+ * the master to params_bf16 (round to nearest even); params_bf16 is first set
+ * from master.  feat / target: device n x 16 and n x 2 float32 (nodes of all
+ * training graphs stacked).  work: device float32 scratch of
+ * lrsdp_mlp_train_work_floats().  loss_hist: NULL or device float64 of
+ * `steps` entries, the loss before each step.  Enqueued on the context
+ * stream, no synchronisation. */
+int lrsdp_mlp_train(lrsdp_ctx *ctx, float *master, uint16_t *params_bf16, float *m, float *v, const float *feat,
+                    const float *target, int64_t n, int first_step, int steps, float lr, float *work,
+                    double *loss_hist);
+int lrsdp_mlp_train_work_floats(void);
+
+/* ---- dual estimate (certificate) --------------------------------------------
  * Smallest eigenvalue of S = C - A*(y) (the dual slack of the error measures,
  * Section 4.2) by block Lanczos on the problem's own SpMM, blocks of 8
- * float64 vectors, no stored basis.  For any y it yields a lower bound on the
- * optimum: MaxCut (diag(X) = 1, so trace X = n): b^T y + n min(0, lambda_lb);
- * completion (C = I): b^T y / max(1, 1 - lambda_lb), since 1 - lambda_min is the
- * spectral norm of the n1 x n2 matrix of the y_k.
+ * float64 vectors, no stored basis.  For any y, a lower bound lb on
+ * lambda_min(S) gives a lower bound on the optimum: MaxCut (diag(X) = 1, so
+ * trace X = n): b^T y + n min(0, lb); completion (C = I): b^T y / max(1, 1 - lb),
+ * since 1 - lambda_min is the spectral norm of the n1 x n2 matrix of the y_k.
+ * The library uses lb = (smallest Ritz value) - (its residual norm).  That is a
+ * bound on the eigenvalue of S nearest the Ritz value; it bounds lambda_min
+ * only if Lanczos has not missed a lower eigenvalue, which a Krylov method
+ * cannot exclude.  The bound and the gap computed from it are therefore
+ * estimates, not proofs.
  */
 typedef struct {
     double  lambda_min;  /* smallest Ritz value of S (>= the true lambda_min)     */
     double  resid;       /* residual norm of that Ritz pair                       */
     double  lambda_lb;   /* lambda_min - resid: the value the bound uses          */
-    double  dual_bound;  /* lower bound on the optimum from y and lambda_lb       */
+    double  dual_bound;  /* estimated lower bound on the optimum from y and
+                            lambda_lb (see above)                                 */
     double  err2;        /* max(0, -lambda_min) / (1 + ||vec(C)||_1)              */
     double  by;          /* b^T y                                                 */
     int64_t iters;       /* block Lanczos steps taken                             */
@@ -443,13 +479,14 @@ int lrsdp_certify(lrsdp_ctx *ctx, const lrsdp_problem *prob, const double *y,
                   int max_iter, double tol, uint64_t seed, void *work,
                   size_t work_bytes, lrsdp_cert *out);
 
-/* Warm start for the problem: y0 (device m float64) and *sigma0 (host).
- * work: device float32 scratch of 22 n.  Synchronises the stream.
- * Returns LRSDP_ENUMERIC (y0 contents then undefined, *sigma0 untouched) when
- * any predicted multiplier or the penalty is not finite; the caller then
- * solves from the cold start. */
-int lrsdp_warmstart(lrsdp_ctx *ctx, const lrsdp_problem *prob, const float *params, float *work, double *y0,
-                    double *sigma0);
+/* Warm start for the problem: y0 (device m float64) and *sigma0 (host), with
+ * the mean penalty output limited to [log_ratio_lo, log_ratio_hi] (EINVAL if
+ * empty or not finite).  params of param_dtype.  work: device float32 scratch
+ * of 22 n.  Synchronises the stream.  Returns LRSDP_ENUMERIC (y0 contents then
+ * undefined, *sigma0 untouched) when any predicted multiplier or the penalty
+ * is not finite; the caller then solves from the cold start. */
+int lrsdp_warmstart(lrsdp_ctx *ctx, const lrsdp_problem *prob, const void *params, int param_dtype,
+                    double log_ratio_lo, double log_ratio_hi, float *work, double *y0, double *sigma0);
 
 #ifdef __cplusplus
 }

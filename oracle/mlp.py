@@ -134,8 +134,30 @@ def adam(theta, m, v, g, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
 
 
 def multipliers_from_output(out: np.ndarray, absdeg: np.ndarray) -> np.ndarray:
-    """y0_i = -t_i sum_j |w_ij| / 4 from the first output t_i."""
-    return -0.25 * out[:, 0] * absdeg
+    """y0_i = -t_i sum_j |w_ij| / 4 from the first output, t_i = out_i0 limited to
+    [-2, 2]: at an optimum y*_i = -sum_j w_ij (1 - X*_ij) / 4 with |X*_ij| <= 1, so
+    |t_i| <= 2 for every exact label."""
+    return -0.25 * np.clip(out[:, 0], -2.0, 2.0) * absdeg
+
+
+def initial_penalty(out: np.ndarray, sigma_default: float, log_lo: float, log_hi: float) -> float:
+    """sigma0 = sigma_default exp(s) with s the mean second output limited to
+    [log_lo, log_hi] (the range of the training labels)."""
+    return sigma_default * float(np.exp(np.clip(out[:, 1].mean(), log_lo, log_hi)))
+
+
+def sigma_label(sigma_final: float, sigma_default: float) -> float:
+    """Penalty label of a cold solve: log(sigma_final / sigma_default)."""
+    return float(np.log(sigma_final / sigma_default))
+
+
+def to_bfloat16(x: np.ndarray) -> np.ndarray:
+    """Round float32 values to bfloat16 (round to nearest, ties to even) and
+    return them widened back to float64: keep the top 16 bits of the float32
+    pattern after adding 0x7fff plus the lowest kept bit."""
+    u = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
 def targets_from_solution(y: np.ndarray, absdeg: np.ndarray) -> np.ndarray:

@@ -30,8 +30,9 @@
 // eigenvalue theta of T_k is found on the host by bisection on the inertia of
 // the band LDL^T of T_k - sigma I, its eigenvector s by inverse iteration, and
 // the residual of the Ritz pair is ||B_k s_last|| (s_last = last block of s).
-// lambda_lb = theta - residual is the bound used for the certificate: exact
-// up to the loss of orthogonality of the basis.
+// lambda_lb = theta - residual bounds the eigenvalue of S nearest theta from
+// below; it bounds lambda_min(S) only if no lower eigenvalue was missed, which
+// Lanczos cannot rule out, so the dual bound built on it is an estimate.
 #include <algorithm>
 #include <cmath>
 #include <cstddef>

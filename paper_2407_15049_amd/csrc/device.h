@@ -152,4 +152,15 @@ __device__ __forceinline__ void block_copy(T *dst, const T *src) {
     for (int i = threadIdx.x; i < (int)(sizeof(T) / 8); i += blockDim.x) d[i] = s[i];
 }
 
+// float32 -> bfloat16, round to nearest, ties to even (NaN kept quiet)
+__device__ __forceinline__ uint16_t bf16_rne(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// bfloat16 bits -> float32 (exact)
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
 }  // namespace lrsdp

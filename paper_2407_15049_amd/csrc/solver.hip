@@ -96,6 +96,11 @@ int check_problem(const lrsdp_problem *p) {
     return LRSDP_OK;
 }
 
+// Default initial penalty: 4 ||vec(C)||_1 / m (floored at 1e-8).
+double default_sigma0(const lrsdp_problem *p) {
+    return std::max(4.0 * p->info.c_l1 / (double)p->info.m, 1e-8);
+}
+
 // Algorithmic bytes of one MaxCut line-search SpMM launch (each array once):
 // work list + row pointers + column indices (+ values) + gathered D + own rows
 // of R and D read once + C D written + ytil + diagonal.
@@ -209,6 +214,7 @@ extern "C" void lrsdp_options_default(lrsdp_options *o) {
     o->reopt_factor = 0.1;
     o->max_reopt = 10;
     o->cert_iters = 300;
+    o->sigma_hold = 0.0;
 }
 
 namespace {
@@ -488,7 +494,7 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
     for (int g = 0; g <= T; ++g) basis[g] = gring[g];
     for (int d = 0; d < T; ++d) basis[T + 1 + d] = dring[d];
 
-    const double sigma0 = o->sigma0 > 0 ? o->sigma0 : std::max(4.0 * p->info.c_l1 / (double)p->info.m, 1e-8);
+    const double sigma0 = o->sigma0 > 0 ? o->sigma0 : default_sigma0(p);
     SolverState h{};
     h.sigma = sigma0;
     h.sigma_cap = sigma0 * o->sigma_max_ratio;
@@ -498,6 +504,7 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
     h.tol = o->tol;
     h.sigma_factor = o->sigma_factor;
     h.feas_decrease = o->feas_decrease;
+    h.sigma_hold = o->sigma_hold;
     h.eta_factor = o->eta_factor;
     h.eta_min = o->eta_min;
     h.b_l1 = p->info.b_l1;
@@ -1241,22 +1248,26 @@ extern "C" int lrsdp_k_lbfgs_dir(lrsdp_ctx *c, int prec, int64_t n, int64_t ld, 
 // ---------------------------------------------------------------------------
 namespace lrsdp {
 int ws_features(hipStream_t, const DevCsr &, float *, float4 *);
-int mlp_forward(hipStream_t, const float *, const float *, int64_t, float *);
-int mlp_grad(hipStream_t, const float *, const float *, const float *, int64_t, float *, double *, float *);
-int mlp_adam(hipStream_t, float *, float *, float *, const float *, int, float);
+int mlp_forward(hipStream_t, const void *, int, const float *, int64_t, float *);
+int mlp_grad(hipStream_t, const void *, int, const float *, const float *, int64_t, float *, double *, float *);
+int mlp_adam(hipStream_t, float *, float *, float *, const float *, int, float, uint16_t *);
+int to_bf16(hipStream_t, const float *, int64_t, uint16_t *);
 int warm_y0(hipStream_t, const float *, const float4 *, int64_t, double *, double *, double *);
 int mlp_param_count();
 int ws_targets(hipStream_t, const float4 *, const double *, int64_t, double, float *);
 }  // namespace lrsdp
 
 extern "C" int lrsdp_ws_targets(lrsdp_ctx *c, const lrsdp_problem *p, const float *stats, const double *y,
-                                double log_sigma_ratio, float *target) {
+                                double sigma_final, float *target) {
     clear_error();
     if (!c || !stats || !y || !target) return set_error(LRSDP_EINVAL, "NULL argument");
     int rc;
     if ((rc = check_problem(p))) return rc;
     if (p->info.kind != LRSDP_MAXCUT) return set_error(LRSDP_EUNSUPPORTED, "warm start is for MaxCut problems");
-    return ws_targets(c->stream, reinterpret_cast<const float4 *>(stats), y, p->info.n, log_sigma_ratio, target);
+    if (!(sigma_final > 0.0) || !std::isfinite(sigma_final))
+        return set_error(LRSDP_EINVAL, "sigma_final must be positive and finite");
+    return ws_targets(c->stream, reinterpret_cast<const float4 *>(stats), y, p->info.n,
+                      std::log(sigma_final / default_sigma0(p)), target);
 }
 
 extern "C" int lrsdp_mlp_param_count(void) { return mlp_param_count(); }
@@ -1271,34 +1282,75 @@ extern "C" int lrsdp_ws_features(lrsdp_ctx *c, const lrsdp_problem *p, float *fe
     return ws_features(c->stream, p->csr, feat, reinterpret_cast<float4 *>(stats));
 }
 
-extern "C" int lrsdp_mlp_forward(lrsdp_ctx *c, const float *params, const float *feat, int64_t n, float *out) {
-    clear_error();
-    if (!c || !params || !feat || !out || n < 0) return set_error(LRSDP_EINVAL, "bad argument");
-    if (n == 0) return LRSDP_OK;
-    return mlp_forward(c->stream, params, feat, n, out);
+static int check_param_dtype(int dtype) {
+    if (dtype != LRSDP_PARAM_F32 && dtype != LRSDP_PARAM_BF16)
+        return set_error(LRSDP_EINVAL, "parameter dtype %d is neither LRSDP_PARAM_F32 nor LRSDP_PARAM_BF16", dtype);
+    return LRSDP_OK;
 }
 
-extern "C" int lrsdp_mlp_grad(lrsdp_ctx *c, const float *params, const float *feat, const float *target, int64_t n,
-                              float *grad, double *loss, float *work) {
+extern "C" int lrsdp_mlp_forward(lrsdp_ctx *c, const void *params, int param_dtype, const float *feat, int64_t n,
+                                 float *out) {
+    clear_error();
+    if (!c || !params || !feat || !out || n < 0) return set_error(LRSDP_EINVAL, "bad argument");
+    int rc;
+    if ((rc = check_param_dtype(param_dtype))) return rc;
+    if (n == 0) return LRSDP_OK;
+    return mlp_forward(c->stream, params, param_dtype == LRSDP_PARAM_BF16, feat, n, out);
+}
+
+extern "C" int lrsdp_mlp_grad(lrsdp_ctx *c, const void *params, int param_dtype, const float *feat,
+                              const float *target, int64_t n, float *grad, double *loss, float *work) {
     clear_error();
     if (!c || !params || !feat || !target || !grad || !work || n <= 0) return set_error(LRSDP_EINVAL, "bad argument");
-    return mlp_grad(c->stream, params, feat, target, n, grad, loss, work);
+    int rc;
+    if ((rc = check_param_dtype(param_dtype))) return rc;
+    return mlp_grad(c->stream, params, param_dtype == LRSDP_PARAM_BF16, feat, target, n, grad, loss, work);
 }
 
 extern "C" int lrsdp_mlp_adam(lrsdp_ctx *c, float *params, float *m, float *v, const float *grad, int step, float lr) {
     clear_error();
     if (!c || !params || !m || !v || !grad || step < 1) return set_error(LRSDP_EINVAL, "bad argument");
-    return mlp_adam(c->stream, params, m, v, grad, step, lr);
+    return mlp_adam(c->stream, params, m, v, grad, step, lr, nullptr);
 }
 
-extern "C" int lrsdp_warmstart(lrsdp_ctx *c, const lrsdp_problem *p, const float *params, float *work, double *y0,
-                               double *sigma0) {
+extern "C" int lrsdp_mlp_train(lrsdp_ctx *c, float *master, uint16_t *params_bf16, float *m, float *v,
+                               const float *feat, const float *target, int64_t n, int first_step, int steps,
+                               float lr, float *work, double *loss_hist) {
+    clear_error();
+    if (!c || !master || !params_bf16 || !m || !v || !feat || !target || !work || n <= 0 || first_step < 1 ||
+        steps < 0 || !(lr > 0.0f))
+        return set_error(LRSDP_EINVAL, "bad argument");
+    const int P = mlp_param_count();
+    float *grad = work;                            // P floats, then the gradient partials
+    float *partials = work + ((P + 63) / 64) * 64;
+    hipStream_t s = c->stream;
+    int rc;
+    if ((rc = to_bf16(s, master, P, params_bf16))) return rc;
+    for (int k = 0; k < steps; ++k) {
+        if ((rc = mlp_grad(s, params_bf16, 1, feat, target, n, grad, loss_hist ? loss_hist + k : nullptr, partials)))
+            return rc;
+        if ((rc = mlp_adam(s, master, m, v, grad, first_step + k, lr, params_bf16))) return rc;
+    }
+    return LRSDP_OK;
+}
+
+extern "C" int lrsdp_mlp_train_work_floats(void) {
+    const int P = mlp_param_count();
+    return ((P + 63) / 64) * 64 + 256 * (P + 1);
+}
+
+extern "C" int lrsdp_warmstart(lrsdp_ctx *c, const lrsdp_problem *p, const void *params, int param_dtype,
+                               double log_ratio_lo, double log_ratio_hi, float *work, double *y0, double *sigma0) {
     clear_error();
     if (!c || !params || !work || !y0 || !sigma0) return set_error(LRSDP_EINVAL, "NULL argument");
     int rc;
+    if ((rc = check_param_dtype(param_dtype))) return rc;
     if ((rc = check_problem(p))) return rc;
     if (p->info.kind != LRSDP_MAXCUT) return set_error(LRSDP_EUNSUPPORTED, "warm start is for MaxCut problems");
     if ((uintptr_t)work % 16) return set_error(LRSDP_EINVAL, "work must be 16-byte aligned");
+    if (!(log_ratio_lo <= log_ratio_hi) || !std::isfinite(log_ratio_lo) || !std::isfinite(log_ratio_hi))
+        return set_error(LRSDP_EINVAL, "the penalty range [%g, %g] is empty or not finite", log_ratio_lo,
+                         log_ratio_hi);
     const int64_t n = p->info.n;
     float *feat = work;
     float4 *stats = reinterpret_cast<float4 *>(work + 16 * n);
@@ -1307,17 +1359,16 @@ extern "C" int lrsdp_warmstart(lrsdp_ctx *c, const lrsdp_problem *p, const float
     double *sum = at<double>(c->scratch, kSmallOff);
     hipStream_t s = c->stream;
     if ((rc = ws_features(s, p->csr, feat, stats))) return rc;
-    if ((rc = mlp_forward(s, params, feat, n, out))) return rc;
+    if ((rc = mlp_forward(s, params, param_dtype == LRSDP_PARAM_BF16, feat, n, out))) return rc;
     if ((rc = warm_y0(s, out, stats, n, y0, part, sum))) return rc;
     double hsum[2] = {0.0, 0.0};
     LRSDP_HIP_TRY(hipMemcpyAsync(c->pinned, sum, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
     LRSDP_HIP_TRY(hipStreamSynchronize(s));
     std::memcpy(hsum, c->pinned, 2 * sizeof(double));
-    const double base = std::max(4.0 * p->info.c_l1 / (double)p->info.m, 1e-8);
     const double mean = n > 0 ? hsum[0] / (double)n : 0.0;
     if (!std::isfinite(mean) || !std::isfinite(hsum[1]))
         return set_error(LRSDP_ENUMERIC, "warm-start prediction is not finite");
-    *sigma0 = base * std::exp(std::max(-10.0, std::min(10.0, mean)));
+    *sigma0 = default_sigma0(p) * std::exp(std::max(log_ratio_lo, std::min(log_ratio_hi, mean)));
     return LRSDP_OK;
 }
 

@@ -401,7 +401,7 @@ __global__ __launch_bounds__(kBlock) void k_alm_finalize(SolverState *gst, const
         if (mode != 0) {
             st.converged = (st.err1 <= st.tol && (st.stop_rule == 1 || fabs(st.err3) <= st.tol)) ? 1 : 0;
             if (!st.converged) {
-                if (st.err1 > st.feas_decrease * st.err1_prev)
+                if (st.err1 > st.feas_decrease * st.err1_prev && st.err1 > st.sigma_hold)
                     st.sigma = fmin(st.sigma * st.sigma_factor, st.sigma_cap);
                 st.err1_prev = st.err1;
                 st.eta = fmax(st.eta * st.eta_factor, st.eta_min);
@@ -655,14 +655,6 @@ struct CombineArgs {
     const S *R;             // precond: current R
     PcBufs pc;              // precond: rho, kap, h
 };
-
-// float32 -> bfloat16, round to nearest, ties to even (NaN kept quiet)
-__device__ __forceinline__ uint16_t bf16_rne(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
 
 // out = sum_j coef_j basis_j, and <out, basis_j> (pre-update values) for all j
 // plus <out, out>.  In the solver the output is D slot dk, itself basis entry

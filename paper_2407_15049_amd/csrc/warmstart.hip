@@ -107,8 +107,13 @@ __global__ __launch_bounds__(kBlock) void k_features(DevCsr P, const float4 *sta
     }
 }
 
-__device__ __forceinline__ void load_params(const float *g, float *sh) {
-    for (int k = threadIdx.x; k < kNParam; k += blockDim.x) sh[k] = g[k];
+__device__ __forceinline__ float param_at(const float *g, int k) { return g[k]; }
+__device__ __forceinline__ float param_at(const uint16_t *g, int k) { return bf16_to_f32(g[k]); }
+
+// parameters (float32, or bfloat16 storage widened exactly) into LDS as float32
+template <typename PT>
+__device__ __forceinline__ void load_params(const PT *g, float *sh) {
+    for (int k = threadIdx.x; k < kNParam; k += blockDim.x) sh[k] = param_at(g, k);
 }
 
 // One node: h1 = tanh(W1 x + b1) kept in registers (fully unrolled, static
@@ -137,7 +142,8 @@ __device__ __forceinline__ void mlp_node(const float *P, const float (&x)[kNF], 
     out[1] = o1;
 }
 
-__global__ __launch_bounds__(kBlock) void k_mlp_forward(const float *params, const float *F, int64_t n, float *out) {
+template <typename PT>
+__global__ __launch_bounds__(kBlock) void k_mlp_forward(const PT *params, const float *F, int64_t n, float *out) {
     __shared__ float P[kNParam];
     load_params(params, P);
     __syncthreads();
@@ -156,7 +162,8 @@ __global__ __launch_bounds__(kBlock) void k_mlp_forward(const float *params, con
 // blockDim = kTile = 128.  Thread t owns dW3[t/64][t%64], db3[t] (t < 2),
 // dW2[t/2][(t%2)*32 + q] (q < 32), db2[t] and db1[t] (t < 64),
 // dW1[t/2][(t%2)*8 + q] (q < 8).
-__global__ __launch_bounds__(kTile) void k_mlp_grad(const float *params, const float *F, const float *T, int64_t n,
+template <typename PT>
+__global__ __launch_bounds__(kTile) void k_mlp_grad(const PT *params, const float *F, const float *T, int64_t n,
                                                     float *partials /* gridDim x (kNParam + 1) */) {
     constexpr int SX = kNF + 1, SH = kH + 1;   // padded LDS rows (no bank conflicts)
     __shared__ float P[kNParam];
@@ -289,8 +296,9 @@ __global__ __launch_bounds__(kBlock) void k_grad_reduce(const float *partials, i
 
 // Adam (Kingma & Ba): m <- b1 m + (1-b1) g, v <- b2 v + (1-b2) g^2,
 // theta <- theta - lr mhat / (sqrt(vhat) + eps) with bias-corrected mhat, vhat.
+// With `store`, the updated float32 master is also rounded to bfloat16 there.
 __global__ __launch_bounds__(kBlock) void k_adam(float *theta, float *m, float *v, const float *g, int step, float lr,
-                                                 float b1, float b2, float eps) {
+                                                 float b1, float b2, float eps, uint16_t *store) {
     const int p = blockIdx.x * kBlock + threadIdx.x;
     if (p >= kNParam) return;
     const float gp = g[p];
@@ -300,15 +308,27 @@ __global__ __launch_bounds__(kBlock) void k_adam(float *theta, float *m, float *
     v[p] = vp;
     const float mh = mp / (1.f - powf(b1, (float)step));
     const float vh = vp / (1.f - powf(b2, (float)step));
-    theta[p] -= lr * mh / (sqrtf(vh) + eps);
+    const float th = theta[p] - lr * mh / (sqrtf(vh) + eps);
+    theta[p] = th;
+    if (store) store[p] = bf16_rne(th);
 }
 
-// y0_i = -out_i0 * a_i / 4; s = sum_i out_i1 (per-block partials)
+__global__ __launch_bounds__(kBlock) void k_to_bf16(const float *x, int64_t n, uint16_t *out) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        out[i] = bf16_rne(x[i]);
+}
+
+// y0_i = -t_i * a_i / 4 with t_i = out_i0 limited to [-2, 2] (the range of
+// -4 y*_i / a_i at an optimum, where y*_i = -sum_j w_ij (1 - X*_ij) / 4 and
+// |X*_ij| <= 1); s = sum_i out_i1 (per-block partials).  A NaN output stays
+// NaN (fmin/fmax would drop it), so the finiteness test below still sees it.
 __global__ __launch_bounds__(kBlock) void k_warm_y0(const float *out, const float4 *stats, int64_t n, double *y0,
                                                     double *partials) {
     double s[2] = {0.0, 0.0};
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
-        const double yi = -0.25 * (double)out[2 * i] * (double)stats[i].z;
+        const double o = (double)out[2 * i];
+        const double t = o != o ? o : (o > 2.0 ? 2.0 : (o < -2.0 ? -2.0 : o));
+        const double yi = -0.25 * t * (double)stats[i].z;
         y0[i] = yi;
         s[0] += (double)out[2 * i + 1];
         s[1] += yi;  // only read for finiteness: a NaN or Inf anywhere shows here
@@ -364,17 +384,26 @@ int ws_features(hipStream_t s, const DevCsr &P, float *F, float4 *stats) {
     return LRSDP_OK;
 }
 
-int mlp_forward(hipStream_t s, const float *params, const float *F, int64_t n, float *out) {
-    hipLaunchKernelGGL(k_mlp_forward, dim3(blocks_for(n)), dim3(kBlock), 0, s, params, F, n, out);
+int mlp_forward(hipStream_t s, const void *params, int bf16, const float *F, int64_t n, float *out) {
+    if (bf16)
+        hipLaunchKernelGGL(k_mlp_forward<uint16_t>, dim3(blocks_for(n)), dim3(kBlock), 0, s,
+                           (const uint16_t *)params, F, n, out);
+    else
+        hipLaunchKernelGGL(k_mlp_forward<float>, dim3(blocks_for(n)), dim3(kBlock), 0, s, (const float *)params, F,
+                           n, out);
     LRSDP_CHECK_LAUNCH();
     return LRSDP_OK;
 }
 
-int mlp_grad(hipStream_t s, const float *params, const float *F, const float *T, int64_t n, float *grad,
+int mlp_grad(hipStream_t s, const void *params, int bf16, const float *F, const float *T, int64_t n, float *grad,
              double *loss, float *partials) {
     int64_t tiles = (n + kTile - 1) / kTile;
     const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(tiles, kGradBlocks));
-    hipLaunchKernelGGL(k_mlp_grad, dim3(nb), dim3(kTile), 0, s, params, F, T, n, partials);
+    if (bf16)
+        hipLaunchKernelGGL(k_mlp_grad<uint16_t>, dim3(nb), dim3(kTile), 0, s, (const uint16_t *)params, F, T, n,
+                           partials);
+    else
+        hipLaunchKernelGGL(k_mlp_grad<float>, dim3(nb), dim3(kTile), 0, s, (const float *)params, F, T, n, partials);
     LRSDP_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_grad_reduce, dim3((kNParam + 1 + kBlock - 1) / kBlock), dim3(kBlock), 0, s, partials, nb,
                        grad, loss);
@@ -382,9 +411,15 @@ int mlp_grad(hipStream_t s, const float *params, const float *F, const float *T,
     return LRSDP_OK;
 }
 
-int mlp_adam(hipStream_t s, float *theta, float *m, float *v, const float *g, int step, float lr) {
+int mlp_adam(hipStream_t s, float *theta, float *m, float *v, const float *g, int step, float lr, uint16_t *store) {
     hipLaunchKernelGGL(k_adam, dim3((kNParam + kBlock - 1) / kBlock), dim3(kBlock), 0, s, theta, m, v, g, step, lr,
-                       0.9f, 0.999f, 1e-8f);
+                       0.9f, 0.999f, 1e-8f, store);
+    LRSDP_CHECK_LAUNCH();
+    return LRSDP_OK;
+}
+
+int to_bf16(hipStream_t s, const float *x, int64_t n, uint16_t *out) {
+    hipLaunchKernelGGL(k_to_bf16, dim3(blocks_for(n)), dim3(kBlock), 0, s, x, n, out);
     LRSDP_CHECK_LAUNCH();
     return LRSDP_OK;
 }

@@ -46,6 +46,7 @@ class Options(C.Structure):
         ("admm_check", C.c_int), ("max_admm", C.c_int), ("precond", C.c_int),
         ("rank_max", C.c_int), ("rank_trigger", C.c_int), ("rank_scale", C.c_double), ("rank_seed", C.c_int64),
         ("reopt", C.c_int), ("reopt_factor", C.c_double), ("max_reopt", C.c_int), ("cert_iters", C.c_int),
+        ("sigma_hold", C.c_double),
     ]
 
 
@@ -112,10 +113,12 @@ _SIGS = {
     "lrsdp_admm_workspace_bytes": (C.c_int, [_P, C.c_int, _I64, C.POINTER(C.c_size_t)]),
     "lrsdp_mlp_param_count": (C.c_int, []),
     "lrsdp_ws_features": (C.c_int, [_P, _P, _P, _P]),
-    "lrsdp_mlp_forward": (C.c_int, [_P, _P, _P, _I64, _P]),
-    "lrsdp_mlp_grad": (C.c_int, [_P, _P, _P, _P, _I64, _P, _P, _P]),
+    "lrsdp_mlp_forward": (C.c_int, [_P, _P, C.c_int, _P, _I64, _P]),
+    "lrsdp_mlp_grad": (C.c_int, [_P, _P, C.c_int, _P, _P, _I64, _P, _P, _P]),
     "lrsdp_mlp_adam": (C.c_int, [_P, _P, _P, _P, _P, C.c_int, C.c_float]),
-    "lrsdp_warmstart": (C.c_int, [_P, _P, _P, _P, _P, C.POINTER(C.c_double)]),
+    "lrsdp_mlp_train": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, _I64, C.c_int, C.c_int, C.c_float, _P, _P]),
+    "lrsdp_mlp_train_work_floats": (C.c_int, []),
+    "lrsdp_warmstart": (C.c_int, [_P, _P, _P, C.c_int, C.c_double, C.c_double, _P, _P, C.POINTER(C.c_double)]),
     "lrsdp_ws_targets": (C.c_int, [_P, _P, _P, _P, C.c_double, _P]),
     "lrsdp_certify_workspace_bytes": (C.c_int, [_P, C.c_int, C.POINTER(C.c_size_t)]),
     "lrsdp_certify": (C.c_int, [_P, _P, _P, C.c_int, C.c_double, C.c_uint64, _P, C.c_size_t, C.POINTER(Cert)]),
@@ -367,28 +370,53 @@ def ws_features(ctx, prob, feat, stats):
     _check(load().lrsdp_ws_features(ctx.handle, prob.handle, _ptr(feat), _ptr(stats)))
 
 
+PARAM_F32, PARAM_BF16 = 0, 1
+
+
+def _param_dtype(params):
+    import torch
+    if params.dtype == torch.float32:
+        return PARAM_F32
+    if params.dtype in (torch.bfloat16, torch.int16, torch.uint16):
+        return PARAM_BF16
+    raise TypeError(f"MLP parameters must be float32 or bfloat16, not {params.dtype}")
+
+
 def mlp_forward(ctx, params, feat, out):
-    _check(load().lrsdp_mlp_forward(ctx.handle, _ptr(params), _ptr(feat), feat.shape[0], _ptr(out)))
+    _check(load().lrsdp_mlp_forward(ctx.handle, _ptr(params), _param_dtype(params), _ptr(feat), feat.shape[0],
+                                    _ptr(out)))
 
 
 def mlp_grad(ctx, params, feat, target, grad, loss, work):
-    _check(load().lrsdp_mlp_grad(ctx.handle, _ptr(params), _ptr(feat), _ptr(target), feat.shape[0],
-                                 _ptr(grad), _ptr(loss), _ptr(work)))
+    _check(load().lrsdp_mlp_grad(ctx.handle, _ptr(params), _param_dtype(params), _ptr(feat), _ptr(target),
+                                 feat.shape[0], _ptr(grad), _ptr(loss) if loss is not None else None, _ptr(work)))
 
 
 def mlp_adam(ctx, params, m, v, grad, step, lr):
     _check(load().lrsdp_mlp_adam(ctx.handle, _ptr(params), _ptr(m), _ptr(v), _ptr(grad), int(step), float(lr)))
 
 
-def warmstart(ctx, prob, params, work, y0):
+def mlp_train_work_floats() -> int:
+    return load().lrsdp_mlp_train_work_floats()
+
+
+def mlp_train(ctx, master, params_bf16, m, v, feat, target, first_step, steps, lr, work, loss_hist=None):
+    _check(load().lrsdp_mlp_train(ctx.handle, _ptr(master), _ptr(params_bf16), _ptr(m), _ptr(v), _ptr(feat),
+                                  _ptr(target), feat.shape[0], int(first_step), int(steps), float(lr), _ptr(work),
+                                  _ptr(loss_hist) if loss_hist is not None else None))
+
+
+def warmstart(ctx, prob, params, work, y0, log_ratio_range=(-10.0, 10.0)):
     """Fill y0 (device float64) and return the predicted sigma0."""
     s = C.c_double()
-    _check(load().lrsdp_warmstart(ctx.handle, prob.handle, _ptr(params), _ptr(work), _ptr(y0), C.byref(s)))
+    lo, hi = log_ratio_range
+    _check(load().lrsdp_warmstart(ctx.handle, prob.handle, _ptr(params), _param_dtype(params), float(lo), float(hi),
+                                  _ptr(work), _ptr(y0), C.byref(s)))
     return s.value
 
 
-def ws_targets(ctx, prob, stats, y, log_sigma_ratio, target):
-    _check(load().lrsdp_ws_targets(ctx.handle, prob.handle, _ptr(stats), _ptr(y), float(log_sigma_ratio),
+def ws_targets(ctx, prob, stats, y, sigma_final, target):
+    _check(load().lrsdp_ws_targets(ctx.handle, prob.handle, _ptr(stats), _ptr(y), float(sigma_final),
                                    _ptr(target)))
 
 

@@ -1,0 +1,279 @@
+"""GPU parity past one pass of the kernels' grid.
+
+Every streaming and SpMM kernel caps its grid at 2048 workgroups of 256 lanes
+and walks the rest of its rows in grid-stride loops, so at the workloads' sizes
+each lane group handles many rows and carries its partial sums across them.
+These cases are large enough for that: a 200,000-node Chung-Lu graph (about
+6-12 grid passes for the 4-, 8- and 16-lane groups of float64 rank 8, 20 and
+24 and float32 rank 24; hub rows split into segments) and a completion problem
+with 480,000 samples.  Same bars as the small cases: float64 outputs within
+1e-10 of the sum of absolute values of their terms, float32 storage checked
+on the rounded inputs within 1e-4 of that sum.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import kernels as K
+from oracle.alm import Options as OOptions
+from oracle.alm import alm_solve
+from oracle.lbfgs import two_loop
+from oracle.problem import completion_problem, maxcut_problem
+from synth import chung_lu_edges, completion_instance, init_factor, pm1_weights
+
+from paper_2407_15049_amd import lrsdp as L
+from gpu_util import dev_factor, dev_vec, host, rounded
+
+pytestmark = pytest.mark.gpu
+
+TOL = {L.F64: 1e-10, L.F32: 1e-4}
+N_BIG, M_BIG = 200_000, 1_000_000
+_CACHE = {}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return L.Context(0)
+
+
+def big_graph(weights):
+    if weights not in _CACHE:
+        u, v = chung_lu_edges(N_BIG, M_BIG, 2.5, 31)
+        w = pm1_weights(M_BIG, 32) if weights == "pm1" else np.random.default_rng(33).uniform(-2, 3, M_BIG)
+        _CACHE[weights] = (u, v, w, maxcut_problem(N_BIG, u, v, w))
+    return _CACHE[weights]
+
+
+def setup(ctx, weights):
+    u, v, w, op = big_graph(weights)
+    key = ("prob", weights)
+    if key not in _CACHE:
+        _CACHE[key] = L.Problem.maxcut(N_BIG, u, v, w).upload(ctx)
+    return _CACHE[key], op
+
+
+CASES = [("pm1", L.F64, 8), ("pm1", L.F64, 20), ("pm1", L.F64, 24), ("pm1", L.F32, 24), ("real", L.F64, 20),
+         ("real", L.F32, 24)]
+
+
+def test_graph_spans_grid_passes(ctx):
+    prob, op = setup(ctx, "pm1")
+    info = prob.info
+    # 2048 x 256 lanes; 16-lane groups (float64 rank 24) cover 32,768 rows per pass
+    assert info.n > 6 * 2048 * 256 // 16
+    assert info.max_row_nnz > 128          # hub rows go through the segment kernels
+
+
+@pytest.mark.parametrize("weights,prec,r", CASES)
+def test_spmm_parity_fullgrid(ctx, weights, prec, r):
+    import torch
+    prob, op = setup(ctx, weights)
+    print("CASE", dict(test="spmm_fullgrid", weights=weights, prec=prec, r=r), flush=True)
+    rng = np.random.default_rng(41)
+    V = rounded(rng.standard_normal((N_BIG, r)), prec)
+    ytil = rng.standard_normal(N_BIG)
+    Vd = dev_factor(V, prec)
+    Yd = torch.full_like(Vd, np.nan)
+    L.k_spmm(ctx, prob, prec, Vd, dev_vec(ytil), Yd)
+    torch.cuda.synchronize()
+    Y = host(Yd)
+    assert np.all(Y[:, r:] == 0.0)
+    Yo = K.spmm(op, ytil, V)
+    bound = abs(op.C) @ np.abs(V) + np.abs(ytil)[:, None] * np.abs(V)
+    err = np.abs(Y[:, :r] - Yo)
+    assert np.all(err <= TOL[prec] * bound + 1e-300), f"max ratio {np.max(err / (bound + 1e-300))}"
+
+
+@pytest.mark.parametrize("weights,prec,r", CASES)
+def test_constraint_map_parity_fullgrid(ctx, weights, prec, r):
+    import torch
+    prob, op = setup(ctx, weights)
+    print("CASE", dict(test="constraint_fullgrid", weights=weights, prec=prec, r=r), flush=True)
+    rng = np.random.default_rng(42)
+    U = rounded(rng.standard_normal((N_BIG, r)), prec)
+    V = rounded(rng.standard_normal((N_BIG, r)), prec)
+    out = torch.empty(N_BIG, dtype=torch.float64, device="cuda")
+    L.k_constraint(ctx, prob, prec, dev_factor(U, prec), dev_factor(V, prec), out)
+    torch.cuda.synchronize()
+    bound = np.sum(np.abs(U) * np.abs(V), axis=1)
+    assert np.all(np.abs(out.cpu().numpy() - K.constraint_map(op, U, V)) <= 1e-12 * bound + 1e-300)
+
+
+@pytest.mark.parametrize("weights,prec,r", CASES)
+def test_linesearch_coeffs_parity_fullgrid(ctx, weights, prec, r):
+    import torch
+    prob, op = setup(ctx, weights)
+    print("CASE", dict(test="ls_fullgrid", weights=weights, prec=prec, r=r), flush=True)
+    rng = np.random.default_rng(43)
+    R = rounded(rng.standard_normal((N_BIG, r)) / np.sqrt(r), prec)
+    D = rounded(rng.standard_normal((N_BIG, r)) * 0.1, prec)
+    y = rng.standard_normal(N_BIG)
+    sigma = 2.7
+    Rd, Dd = dev_factor(R, prec), dev_factor(D, prec)
+    esz = 8 if prec == L.F64 else 4
+    work = torch.empty(2 * N_BIG * Rd.shape[1] * esz + 8 * N_BIG, dtype=torch.uint8, device="cuda")
+    out = torch.zeros(8, dtype=torch.float64, device="cuda")
+    q1 = torch.zeros(N_BIG, dtype=torch.float64, device="cuda")
+    q2 = torch.zeros(N_BIG, dtype=torch.float64, device="cuda")
+    L.k_ls_coeffs(ctx, prob, prec, Rd, Dd, dev_vec(y), sigma, work, out, q1, q2)
+    torch.cuda.synchronize()
+    g = out.cpu().numpy()
+    c = K.linesearch_coeffs(op, R, D, y, sigma)
+    ytil = y + sigma * c["q0"]
+    absC = abs(op.C)
+    aR, aD = np.abs(R), np.abs(D)
+    bq1 = 2 * np.sum(aR * aD, axis=1)
+    bq2 = np.sum(aD * aD, axis=1)
+    bp1 = 2 * np.sum((absC @ aR) * aD)
+    bp2 = np.sum((absC @ aD) * aD)
+    assert np.all(np.abs(q1.cpu().numpy() - c["q1"]) <= 1e-12 * bq1 + 1e-300)
+    assert np.all(np.abs(q2.cpu().numpy() - c["q2"]) <= 1e-12 * bq2 + 1e-300)
+    bounds = {
+        "a1": 0.5 * sigma * np.sum(bq2 * bq2), "a2": sigma * np.sum(bq1 * bq2),
+        "a3": bp2 + np.sum(np.abs(ytil) * bq2) + 0.5 * sigma * np.sum(bq1 * bq1),
+        "a4": bp1 + np.sum(np.abs(ytil) * bq1), "p1": bp1, "p2": bp2,
+    }
+    for idx, name in enumerate(["a1", "a2", "a3", "a4", "p1", "p2"]):
+        assert abs(g[idx] - c[name]) <= TOL[prec] * bounds[name], (name, g[idx], c[name])
+
+
+@pytest.mark.parametrize("weights,prec,r", CASES)
+def test_alm_step_parity_fullgrid(ctx, weights, prec, r):
+    import torch
+    prob, op = setup(ctx, weights)
+    print("CASE", dict(test="alm_fullgrid", weights=weights, prec=prec, r=r), flush=True)
+    rng = np.random.default_rng(44)
+    R = rounded(init_factor(N_BIG, r, 45) * (1 + 0.05 * rng.standard_normal((N_BIG, 1))), prec)
+    y = rng.standard_normal(N_BIG)
+    sigma = 1.3
+    Rd = dev_factor(R, prec)
+    yd = dev_vec(y)
+    work = torch.empty_like(Rd)
+    out = torch.zeros(8, dtype=torch.float64, device="cuda")
+    L.k_alm(ctx, prob, prec, Rd, yd, sigma, work, out)
+    torch.cuda.synchronize()
+    ynew = K.multiplier_estimate(op, R, y, sigma)
+    m = K.alm_measures(op, R, ynew)
+    assert np.allclose(yd.cpu().numpy(), ynew, rtol=0, atol=1e-13 * (1 + np.abs(y).max() + sigma))
+    g = out.cpu().numpy()
+    bobj = np.sum((abs(op.C) @ np.abs(R)) * np.abs(R))
+    assert abs(g[0] - m["obj"]) <= TOL[prec] * bobj
+    assert abs(g[1] - m["dual"]) <= 1e-12 * np.abs(ynew).sum()
+    assert abs(g[2] - m["res_norm"]) <= 1e-9 * (1 + m["res_norm"])
+    assert abs(g[5] - m["err3"]) <= 1e-9
+
+
+@pytest.mark.parametrize("prec,r,k", [(L.F64, 24, 2), (L.F32, 24, 2), (L.F64, 8, 4)])
+def test_lbfgs_direction_parity_fullgrid(ctx, prec, r, k):
+    import torch
+    print("CASE", dict(test="lbfgs_fullgrid", prec=prec, r=r, k=k), flush=True)
+    rng = np.random.default_rng(46 + k)
+    h = rng.uniform(0.5, 5.0, (N_BIG, r))
+    S = [rounded(rng.standard_normal((N_BIG, r)), prec) for _ in range(k)]
+    Y = [rounded(h * s, prec) for s in S]
+    G = rounded(rng.standard_normal((N_BIG, r)), prec)
+    Dd = dev_factor(np.zeros((N_BIG, r)), prec)
+    L.k_lbfgs_dir(ctx, prec, dev_factor(G, prec), [dev_factor(s, prec) for s in S],
+                  [dev_factor(y, prec) for y in Y], Dd)
+    torch.cuda.synchronize()
+    Do = two_loop(G, list(zip(S, Y)))
+    tol = 1e-10 if prec == L.F64 else 2e-6
+    assert np.linalg.norm(host(Dd, r) - Do) <= tol * np.linalg.norm(Do)
+
+
+@pytest.mark.parametrize("weights,precond", [("pm1", 0), ("real", 0), ("pm1", 1)])
+def test_iterates_match_oracle_fullgrid(ctx, weights, precond):
+    """Six L-BFGS iterations of the first subproblem at n = 2e5: the GPU iterate
+    and multipliers equal the oracle's (same directions, steps and pairs)."""
+    import torch
+    prob, op = setup(ctx, weights)
+    r = 20
+    print("CASE", dict(test="iterates_fullgrid", weights=weights, precond=precond), flush=True)
+    R0 = init_factor(N_BIG, r, 47)
+    opts = L.default_options(prec=L.F64, rank=r, ld=r, precond=precond, max_outer=1, max_inner=6, eta0=1e-14)
+    Rd = dev_factor(R0, L.F64)
+    yd = torch.zeros(N_BIG, dtype=torch.float64, device="cuda")
+    rc, res = L.solve(ctx, prob, Rd, yd, opts)
+    torch.cuda.synchronize()
+    ores = alm_solve(op, R0, opts=OOptions(precond=precond, max_outer=1, max_inner=6, eta0=1e-14))
+    assert res.inner == ores.inner == 6
+    scale = 1.0 + np.abs(ores.R).max()
+    assert np.max(np.abs(host(Rd, r) - ores.R)) <= 1e-9 * scale
+    assert np.max(np.abs(yd.cpu().numpy() - ores.y)) <= 1e-9 * (1.0 + np.abs(ores.y).max())
+
+
+# ---------------------------------------------------------------- completion, m = 480,000
+CMP = dict(n1=60_000, n2=50_000, k=5, per=8, r=16)
+
+
+def cmp_setup(ctx):
+    if "cmp" not in _CACHE:
+        i, j, Mij, _, _ = completion_instance(CMP["n1"], CMP["n2"], CMP["k"], CMP["per"], seed=48)
+        _CACHE["cmp"] = (L.Problem.completion(CMP["n1"], CMP["n2"], i, j, Mij).upload(ctx),
+                         completion_problem(CMP["n1"], CMP["n2"], i, j, Mij))
+    return _CACHE["cmp"]
+
+
+@pytest.mark.parametrize("prec", [L.F64, L.F32])
+def test_completion_kernels_fullgrid(ctx, prec):
+    import torch
+    prob, op = cmp_setup(ctx)
+    assert op.m > 262_144
+    r = CMP["r"]
+    print("CASE", dict(test="cmp_fullgrid", prec=prec, m=op.m), flush=True)
+    rng = np.random.default_rng(49)
+    # SpMM (I - A*(ytil)) V
+    V = rounded(rng.standard_normal((op.n, r)), prec)
+    ytil = rng.standard_normal(op.m)
+    Vd = dev_factor(V, prec)
+    Yd = torch.full_like(Vd, np.nan)
+    L.k_spmm(ctx, prob, prec, Vd, dev_vec(ytil), Yd)
+    torch.cuda.synchronize()
+    bound = np.abs(V) + abs(op.A_adj(np.abs(ytil))) @ np.abs(V)
+    assert np.all(np.abs(host(Yd, r) - K.spmm(op, ytil, V)) <= TOL[prec] * bound + 1e-300)
+    # SDDMM A(U V^T)
+    U = rounded(rng.standard_normal((op.n, r)), prec)
+    out = torch.empty(op.m, dtype=torch.float64, device="cuda")
+    L.k_constraint(ctx, prob, prec, dev_factor(U, prec), Vd, out)
+    torch.cuda.synchronize()
+    bq = op.Abar @ np.einsum("pc,pc->p", np.abs(U[op.col_a]), np.abs(V[op.col_b]))
+    assert np.all(np.abs(out.cpu().numpy() - K.constraint_map(op, U, V)) <= 1e-12 * bq + 1e-300)
+    # line-search coefficients
+    R = rounded(rng.standard_normal((op.n, r)) / np.sqrt(r), prec)
+    D = rounded(rng.standard_normal((op.n, r)) * 0.1, prec)
+    y = rng.standard_normal(op.m)
+    sigma = 1.9
+    Rd, Dd = dev_factor(R, prec), dev_factor(D, prec)
+    esz = 8 if prec == L.F64 else 4
+    work = torch.empty(2 * op.n * Rd.shape[1] * esz + 16 * op.m, dtype=torch.uint8, device="cuda")
+    o8 = torch.zeros(8, dtype=torch.float64, device="cuda")
+    L.k_ls_coeffs(ctx, prob, prec, Rd, Dd, dev_vec(y), sigma, work, o8)
+    torch.cuda.synchronize()
+    g = o8.cpu().numpy()
+    c = K.linesearch_coeffs(op, R, D, y, sigma)
+    yt = y + sigma * c["q0"]
+    aR, aD = np.abs(R), np.abs(D)
+    pair = lambda X, Y: op.Abar @ np.einsum("pc,pc->p", X[op.col_a], Y[op.col_b])
+    bq1 = pair(aR, aD) + pair(aD, aR)
+    bq2 = pair(aD, aD)
+    bp1, bp2 = 2 * np.sum(aR * aD), np.sum(aD * aD)
+    bounds = {"a1": 0.5 * sigma * np.sum(bq2 * bq2), "a2": sigma * np.sum(bq1 * bq2),
+              "a3": bp2 + np.sum(np.abs(yt) * bq2) + 0.5 * sigma * np.sum(bq1 * bq1),
+              "a4": bp1 + np.sum(np.abs(yt) * bq1)}
+    for idx, name in enumerate(["a1", "a2", "a3", "a4"]):
+        assert abs(g[idx] - c[name]) <= TOL[prec] * bounds[name], (name, g[idx], c[name])
+    # multiplier step and measures
+    yd = dev_vec(y)
+    w2 = torch.empty(8 * max(op.m, op.n * Rd.shape[1]), dtype=torch.uint8, device="cuda")
+    L.k_alm(ctx, prob, prec, Rd, yd, 0.7, w2, o8)
+    torch.cuda.synchronize()
+    ynew = K.multiplier_estimate(op, R, y, 0.7)
+    m = K.alm_measures(op, R, ynew)
+    bA = op.Abar @ np.einsum("pc,pc->p", aR[op.col_a], aR[op.col_b])
+    assert np.all(np.abs(yd.cpu().numpy() - ynew) <= 1e-12 * (np.abs(y) + 0.7 * (np.abs(op.b) + bA)))
+    g = o8.cpu().numpy()
+    assert abs(g[0] - m["obj"]) <= 1e-12 * m["obj"]
+    assert abs(g[2] - m["res_norm"]) <= 1e-9 * (1 + m["res_norm"])
+    assert abs(g[5] - m["err3"]) <= 1e-9

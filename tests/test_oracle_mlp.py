@@ -84,3 +84,25 @@ def test_features_power_law_sane():
     deg = np.bincount(np.concatenate([u, v]), minlength=500)
     assert np.all(F[deg > 0, 1] == 1.0)           # unit weights: balance 1
     assert np.all(F[deg == 0, 1] == 0.0)
+
+
+def test_bfloat16_rounding_by_hand():
+    # bfloat16 keeps 8 significand bits: around 1 the spacing is 2^-7
+    x = np.array([1.0, 1 + 2 ** -8, 1 + 3 * 2 ** -8, 1 + 2 ** -8 + 2 ** -20, 1 + 2 ** -9, -2.5,
+                  2.0 ** 100 * (1 + 2 ** -8), -(2.0 ** -100) * (1 + 3 * 2 ** -8)], dtype=np.float32)
+    got = mlp.to_bfloat16(x)
+    # 1 + 2^-8 is a tie: to even (1); 1 + 3 2^-8 is a tie between 1 + 2^-7 (odd last bit) and
+    # 1 + 2^-6 (even); just above the tie rounds up; below it rounds down; ties at other scales alike
+    want = [1.0, 1.0, 1 + 2 ** -6, 1 + 2 ** -7, 1.0, -2.5, 2.0 ** 100, -(2.0 ** -100) * (1 + 2 ** -6)]
+    assert np.array_equal(got, want)
+
+
+def test_warm_start_limits():
+    out = np.array([[3.0, 0.5], [-2.5, 4.0], [1.0, -9.0]])
+    absdeg = np.array([4.0, 8.0, 2.0])
+    # t limited to [-2, 2]: (2, -2, 1) -> y0 = -t a / 4 = (-2, 4, -0.5)
+    assert np.array_equal(mlp.multipliers_from_output(out, absdeg), [-2.0, 4.0, -0.5])
+    # mean second output = -1.5: inside [-2, 1] it stays, [-1, 1] lifts it to -1
+    assert np.isclose(mlp.initial_penalty(out, 10.0, -2.0, 1.0), 10.0 * np.exp(-1.5))
+    assert np.isclose(mlp.initial_penalty(out, 10.0, -1.0, 1.0), 10.0 * np.exp(-1.0))
+    assert np.isclose(mlp.sigma_label(40.0, 10.0), np.log(4.0))
