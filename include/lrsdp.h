@@ -177,8 +177,7 @@ int lrsdp_problem_upload(lrsdp_ctx *ctx, lrsdp_problem *prob, void *dev,
  * check_every = 8, time_limit_s = 1e30, refresh_every = 0 (off), phase2 = 0,
  * switch_err1 = 1e-3, admm_check = 10, max_admm = 5000, precond = 0,
  * rank_max = 0 (off), rank_trigger = 2000, rank_scale = 1e-2, rank_seed = 15049,
- * reopt = 0, reopt_factor = 0.1, max_reopt = 10, cert_iters = 300,
- * sigma_hold = 0.
+ * reopt = 0, reopt_factor = 0.1, max_reopt = 10, cert_iters = 300.
  * With re-optimisation the results (obj, dual, err3, sigma, y) are those of
  * the original problem: the last round's divided by its objective scale.
  */
@@ -248,8 +247,6 @@ typedef struct {
     double  reopt_factor;     /* objective scale per round, 0 < f < 1          */
     int     max_reopt;        /* rounds after the first at most                */
     int     cert_iters;       /* reopt = 2: Lanczos steps per certificate      */
-    double  sigma_hold;       /* the penalty is not raised after an ALM step
-                                 whose err1 <= sigma_hold (0: always eligible) */
 } lrsdp_options;
 
 void lrsdp_options_default(lrsdp_options *opts);

@@ -48,7 +48,6 @@ class Options:
     sigma_factor: float = 2.0
     sigma_max_ratio: float = 1e8
     feas_decrease: float = 0.25
-    sigma_hold: float = 0.0         # no penalty increase after a step with err1 <= sigma_hold
     eta0: float = 1e-1
     eta_factor: float = 0.25
     eta_min: float = 1e-9
@@ -229,7 +228,7 @@ def _alm_run(prob: SDPProblem, R0: np.ndarray, y0, opts: Options, log=None, sigm
         # penalty and inner-tolerance schedule, from the measures after the
         # multiplier step
         sigma_sub = sigma
-        if meas["err1"] > opts.feas_decrease * err1_prev and meas["err1"] > opts.sigma_hold:
+        if meas["err1"] > opts.feas_decrease * err1_prev:
             sigma = min(sigma * opts.sigma_factor, sigma_cap)
         err1_prev = meas["err1"]
         eta = max(eta * opts.eta_factor, opts.eta_min)

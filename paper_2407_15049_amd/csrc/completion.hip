@@ -55,15 +55,30 @@ __device__ __forceinline__ void cmp_gather(const int32_t *__restrict__ ptr, cons
     constexpr int NT = PW / GS;             // samples per lane and pass
     constexpr int KB = 8;                   // partner rows in flight per lane
     const int b = ptr[row], e = ptr[row + 1];
+    // indices and weights of the first pass; each pass loads the next one's
+    // before its own partner rows, so their latency overlaps the gather
+    int32_t jj[NT];
+    S ww[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int q = lane + t * GS;
+        const bool in = q < min(PW, e - b);
+        jj[t] = in ? nbr[b + q] : 0;
+        ww[t] = in ? (S)ytil[eid[b + q]] : (S)0;
+    }
     for (int k0 = b; k0 < e; k0 += PW) {
         const int cnt = min(PW, e - k0);     // the same for every lane of the group
-        int32_t jj[NT];
-        S ww[NT];
+        int32_t jn[NT] = {};
+        S wn[NT] = {};
+        const int k1 = k0 + PW;
+        if (k1 < e) {
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            const int q = lane + t * GS;
-            jj[t] = q < cnt ? nbr[k0 + q] : 0;
-            ww[t] = q < cnt ? (S)ytil[eid[k0 + q]] : (S)0;
+            for (int t = 0; t < NT; ++t) {
+                const int q = lane + t * GS;
+                const bool in = q < min(PW, e - k1);
+                jn[t] = in ? nbr[k1 + q] : 0;
+                wn[t] = in ? (S)ytil[eid[k1 + q]] : (S)0;
+            }
         }
 #pragma unroll
         for (int q0 = 0; q0 < PW; q0 += KB) {
@@ -84,6 +99,11 @@ __device__ __forceinline__ void cmp_gather(const int32_t *__restrict__ ptr, cons
                 for (int q = 0; q < KB; ++q)
                     if (q0 + q < cnt) vfma(acc, w[q], v[q]);
             }
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            jj[t] = jn[t];
+            ww[t] = wn[t];
         }
     }
 }
@@ -193,16 +213,30 @@ __global__ __launch_bounds__(kBlock) void k_cmp_sddmm(DevCompletion P, SddArgs<S
         // outputs).  NT = 2 for float64 rows; float32 rows keep one, since the
         // extra index registers cost the float32 line-search build a wave per
         // SIMD (measured slower at n = 1e6, m = 1e7).
+        // The next pass's indices are loaded before this pass's partner rows, so
+        // their latency overlaps the gather instead of adding to it.
         constexpr int NT = sizeof(S) == 8 ? 2 : 1;
         constexpr int PW = NT * GS;
+        int32_t cc[NT], ee[NT];
+        if (b < e) {
+#pragma unroll
+            for (int u = 0; u < NT; ++u) {
+                const int tq = b + min(lane + u * GS, min(PW, e - b) - 1);
+                cc[u] = P.top_col[tq];
+                ee[u] = P.top_eid[tq];
+            }
+        }
         for (int t0 = b; t0 < e; t0 += PW) {
           const int cnt0 = min(PW, e - t0);
-          int32_t cc[NT], ee[NT];
+          int32_t cn[NT] = {}, en[NT] = {};
+          const int t1 = t0 + PW;
+          if (t1 < e) {
 #pragma unroll
-          for (int u = 0; u < NT; ++u) {
-              const int tq = t0 + min(lane + u * GS, cnt0 - 1);
-              cc[u] = P.top_col[tq];
-              ee[u] = P.top_eid[tq];
+              for (int u = 0; u < NT; ++u) {
+                  const int tq = t1 + min(lane + u * GS, min(PW, e - t1) - 1);
+                  cn[u] = P.top_col[tq];
+                  en[u] = P.top_eid[tq];
+              }
           }
 #pragma unroll
           for (int s0 = 0; s0 < PW; s0 += 4) {
@@ -260,72 +294,11 @@ __global__ __launch_bounds__(kBlock) void k_cmp_sddmm(DevCompletion P, SddArgs<S
                 }
             }
           }
-        }
-    }
-    if constexpr (MODE != kSddA) block_sums_store<kLsSums>(s, a.partials + (size_t)blockIdx.x * kMaxSums);
-}
-
-// float32 rows of at most 16 values (64 bytes): one lane per sample, samples in
-// id order (i and j from the sample arrays, coalesced), the four 16-byte chunks
-// of each of its rows loaded by the lane itself.  No index broadcast and no
-// cross-lane reduction, and every lane has its whole row fetches in flight at
-// once; with samples sorted by row the rows i of neighbouring lanes coincide
-// and hit in cache.  Products are promoted to float64 as in the group kernel.
-template <int MODE>
-__global__ __launch_bounds__(kBlock) void k_cmp_sddmm_lane(DevCompletion P, SddArgs<float> a) {
-    if (a.st && a.st->done) return;
-    const int nch = (int)(a.ld / 4);          // 16-byte chunks per row, <= 4
-    const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
-    double s[kLsSums] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < P.m; k += (int64_t)gridDim.x * kBlock) {
-        const int64_t ri = (int64_t)P.samp_i[k] * a.ld, rj = (P.n1 + (int64_t)P.samp_j[k]) * a.ld;
-        float4 ui[4], uj[4], vi[4], vj[4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const bool act = c < nch;
-            ui[c] = act ? *reinterpret_cast<const float4 *>(a.U + ri + 4 * c) : zero;
-            uj[c] = act ? *reinterpret_cast<const float4 *>(a.U + rj + 4 * c) : zero;
-            if constexpr (MODE != kSddRefresh) {
-                vi[c] = act ? *reinterpret_cast<const float4 *>(a.V + ri + 4 * c) : zero;
-                vj[c] = act ? *reinterpret_cast<const float4 *>(a.V + rj + 4 * c) : zero;
-            }
-        }
-        if constexpr (MODE == kSddA) {
-            double d = 0.0;
-#pragma unroll
-            for (int c = 0; c < 4; ++c) d += vdot(ui[c], vj[c]) + vdot(uj[c], vi[c]);
-            a.out[k] = d;
-        } else if constexpr (MODE == kSddLS) {
-            // R rows in u, D rows in v
-            double t1 = 0.0, t2 = 0.0;
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                t1 += vdot(ui[c], vj[c]) + vdot(vi[c], uj[c]);
-                t2 += vdot(vi[c], vj[c]);
-            }
-            const double q1 = 2.0 * t1, q2 = 2.0 * t2;
-            const double yt = a.ytil[k];
-            if (a.q1) a.q1[k] = q1;
-            if (a.q2) a.q2[k] = q2;
-            s[1] += yt * q2;
-            s[2] += yt * q1;
-            s[3] += q2 * q2;
-            s[4] += q1 * q2;
-            s[5] += q1 * q1;
-        } else {
-            double t = 0.0;
-#pragma unroll
-            for (int c = 0; c < 4; ++c) t += vdot(ui[c], uj[c]);
-            const double ak = 2.0 * t;
-            const double res = ak - P.b[k];
-            double yk = a.y[k];
-            if (a.sigma > 0.0) {
-                yk -= a.sigma * res;
-                a.y[k] = yk;
-            }
-            if (a.out) a.out[k] = ak;
-            s[1] += P.b[k] * yk;
-            s[2] += res * res;
+          for (int u = 0; u < NT; ++u) {
+              cc[u] = cn[u];
+              ee[u] = en[u];
+          }
         }
     }
     if constexpr (MODE != kSddA) block_sums_store<kLsSums>(s, a.partials + (size_t)blockIdx.x * kMaxSums);
@@ -402,14 +375,6 @@ int cmp_spmm_t(hipStream_t s, const DevCompletion &P, const CmpSpmmArgs<S> &a, i
 
 template <typename S, int MODE>
 int cmp_sddmm_t(hipStream_t s, const DevCompletion &P, const SddArgs<S> &a, int *nb) {
-    if constexpr (sizeof(S) == 4) {
-        if (a.ld <= 16) {
-            *nb = grid(P.m, kBlock);
-            hipLaunchKernelGGL((k_cmp_sddmm_lane<MODE>), dim3(*nb), dim3(kBlock), 0, s, P, a);
-            LRSDP_CHECK_LAUNCH();
-            return LRSDP_OK;
-        }
-    }
     const int gs = gs_of<S>(a.ld);
     *nb = grid(P.n1, kBlock / gs);
     if (gs == 4) hipLaunchKernelGGL((k_cmp_sddmm<S, 4, MODE>), dim3(*nb), dim3(kBlock), 0, s, P, a);

@@ -25,7 +25,7 @@ struct SolverState {
     // ALM measures after the last multiplier step
     double obj, dual, res_norm, err1, err1_inf, err3, err1_prev;
     // options copied at solve start
-    double tol, sigma_factor, feas_decrease, eta_factor, eta_min, b_l1, b_inf, sigma_hold;
+    double tol, sigma_factor, feas_decrease, eta_factor, eta_min, b_l1, b_inf;
     int64_t inner_total;
     int max_inner;
     int T;          // L-BFGS memory

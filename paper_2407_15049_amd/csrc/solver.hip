@@ -214,7 +214,6 @@ extern "C" void lrsdp_options_default(lrsdp_options *o) {
     o->reopt_factor = 0.1;
     o->max_reopt = 10;
     o->cert_iters = 300;
-    o->sigma_hold = 0.0;
 }
 
 namespace {
@@ -504,7 +503,6 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
     h.tol = o->tol;
     h.sigma_factor = o->sigma_factor;
     h.feas_decrease = o->feas_decrease;
-    h.sigma_hold = o->sigma_hold;
     h.eta_factor = o->eta_factor;
     h.eta_min = o->eta_min;
     h.b_l1 = p->info.b_l1;

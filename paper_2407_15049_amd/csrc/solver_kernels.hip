@@ -401,7 +401,7 @@ __global__ __launch_bounds__(kBlock) void k_alm_finalize(SolverState *gst, const
         if (mode != 0) {
             st.converged = (st.err1 <= st.tol && (st.stop_rule == 1 || fabs(st.err3) <= st.tol)) ? 1 : 0;
             if (!st.converged) {
-                if (st.err1 > st.feas_decrease * st.err1_prev && st.err1 > st.sigma_hold)
+                if (st.err1 > st.feas_decrease * st.err1_prev)
                     st.sigma = fmin(st.sigma * st.sigma_factor, st.sigma_cap);
                 st.err1_prev = st.err1;
                 st.eta = fmax(st.eta * st.eta_factor, st.eta_min);

@@ -299,8 +299,13 @@ __global__ __launch_bounds__(kBlock) void k_spmm_light(DevCsr P, SpmmArgs a) {
     const int grp = threadIdx.x / GS;
     const bool active = lane_active<S, NC>(a, lane);
     double s[kLsSums] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int64_t it = (int64_t)blockIdx.x * GPB + grp; it < P.n_light; it += (int64_t)gridDim.x * GPB) {
-        const int4 wl = P.light[it];   // {row, begin, end}: no dependent row_ptr load
+    const int64_t stride = (int64_t)gridDim.x * GPB;
+    int64_t it = (int64_t)blockIdx.x * GPB + grp;
+    // work-list entries {row, begin, end} (no dependent row_ptr load); the next
+    // row's entry is loaded before this row's gather, off the critical path
+    int4 wl = it < P.n_light ? P.light[it] : make_int4(0, 0, 0, 0);
+    for (; it < P.n_light; it += stride) {
+        const int4 wn = it + stride < P.n_light ? P.light[it + stride] : make_int4(0, 0, 0, 0);
         const int row = wl.x, beg = wl.y, end = wl.z;
         CV acc[NC];
 #pragma unroll
@@ -309,6 +314,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_light(DevCsr P, SpmmArgs a) {
         load_own<S, EPI, NC>(P, a, row, lane, active, own);
         gather<S, GS, W, NC>(P, a.V, a.ldv, beg, end, lane, active, acc);
         epilogue<S, GS, EPI, NC>(P, a, row, lane, active, own, acc, s);
+        wl = wn;
     }
     if constexpr (EPI == kEpiLS || EPI == kEpiRefresh)
         block_sums_store<kLsSums>(s, a.partials + (size_t)blockIdx.x * kMaxSums);

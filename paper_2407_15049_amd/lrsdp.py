@@ -46,7 +46,6 @@ class Options(C.Structure):
         ("admm_check", C.c_int), ("max_admm", C.c_int), ("precond", C.c_int),
         ("rank_max", C.c_int), ("rank_trigger", C.c_int), ("rank_scale", C.c_double), ("rank_seed", C.c_int64),
         ("reopt", C.c_int), ("reopt_factor", C.c_double), ("max_reopt", C.c_int), ("cert_iters", C.c_int),
-        ("sigma_hold", C.c_double),
     ]
 
 

@@ -162,7 +162,9 @@ def test_alm_step_parity_fullgrid(ctx, weights, prec, r):
     assert abs(g[0] - m["obj"]) <= TOL[prec] * bobj
     assert abs(g[1] - m["dual"]) <= 1e-12 * np.abs(ynew).sum()
     assert abs(g[2] - m["res_norm"]) <= 1e-9 * (1 + m["res_norm"])
-    assert abs(g[5] - m["err3"]) <= 1e-9
+    # err3 moves by at most 2 |d obj| / (1 + |obj| + |dual|) when obj moves by d obj
+    den = 1.0 + abs(m["obj"]) + abs(m["dual"])
+    assert abs(g[5] - m["err3"]) <= 2.0 * TOL[prec] * bobj / den + 1e-12
 
 
 @pytest.mark.parametrize("prec,r,k", [(L.F64, 24, 2), (L.F32, 24, 2), (L.F64, 8, 4)])

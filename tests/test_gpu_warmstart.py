@@ -192,10 +192,14 @@ def test_warmstart_prediction_formula(ctx):
     n, u, v, w = graph("pm1")
     prob = L.Problem.maxcut(n, u, v, w).upload(ctx)
     theta = (mlp.init_params(9) + 0.1).astype(np.float32).astype(np.float64)
-    theta[mlp.NPARAM - 2] = 1.7        # b3[0]: pushes some t_i past 2, so the limit acts
     F = mlp.features(n, u, v, w).astype(np.float32).astype(np.float64)
+    # b3[0] (second-to-last parameter) shifts every t_i: put the median at 2, so
+    # the limit acts on about half of the nodes
+    theta[mlp.NPARAM - 2] = 0.0
+    out0, _ = mlp.forward(theta, F)
+    theta[mlp.NPARAM - 2] = float(np.float32(2.0 - np.median(out0[:, 0])))
     out, _ = mlp.forward(theta, F)
-    assert (np.abs(out[:, 0]) > 2).any() and (np.abs(out[:, 0]) < 2).any()
+    assert (out[:, 0] > 2).any() and (out[:, 0] < 2).any()
     absdeg = np.bincount(np.concatenate([u, v]), weights=np.abs(np.concatenate([w, w])), minlength=n)
     base = 4.0 * maxcut_problem(n, u, v, w).c_l1 / n
     s = out[:, 1].mean()
