@@ -339,6 +339,20 @@ int lrsdp_k_alm(lrsdp_ctx *ctx, const lrsdp_problem *prob, int prec,
                 const void *R, int64_t ld, double *y, double sigma, void *work,
                 double *out);
 
+/* Allocation-free variant of lrsdp_k_alm, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops, harnesses that
+ * forbid it): the same computation and outputs, with the work buffer taken
+ * from a static device array of lrsdp_k_alm_noalloc_max_bytes() bytes (64 MiB)
+ * that the library holds on each device from the first context created there
+ * until the process ends.  The call itself allocates nothing.  ENOMEM (with
+ * the sizes in the message) when max(n * ld * (element bytes), 8 * m) exceeds
+ * the array.  All calls on one device share the array: calls that overlap on
+ * one device (several streams or host threads) race; serialise them. */
+int lrsdp_k_alm_noalloc(lrsdp_ctx *ctx, const lrsdp_problem *prob, int prec,
+                        const void *R, int64_t ld, double *y, double sigma,
+                        double *out);
+size_t lrsdp_k_alm_noalloc_max_bytes(void);
+
 /* `iters` splitting iterations (Section 2.2, eqs. 2.2-2.3) in place:
  * U <- argmin_U L(U, V, y), V <- argmin_V L(U, V, y), then
  * y <- y + sigma (b - A(U V^T)).  U, V device n x ld, y device m float64.

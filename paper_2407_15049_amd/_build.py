@@ -25,6 +25,7 @@ SOURCES = [
     "completion.hip",
     "warmstart.hip",
     "solver.hip",
+    "noalloc.hip",
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

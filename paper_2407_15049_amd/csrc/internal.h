@@ -18,6 +18,10 @@ namespace lrsdp {
 int set_error(int code, const char *fmt, ...);
 void clear_error();
 
+// Takes the device address of the allocation-free entry point's static array
+// on `device` (current) once; lrsdp_ctx_create calls it.
+int noalloc_init(int device, void **ptr);
+
 #define LRSDP_HIP_TRY(expr)                                                      \
     do {                                                                         \
         hipError_t e_ = (expr);                                                  \
@@ -144,4 +148,5 @@ struct lrsdp_ctx {
     void *pinned = nullptr;       // host pinned read-back block
     size_t pinned_bytes = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    void *static_scratch = nullptr;  // device address of the allocation-free entry point's array
 };

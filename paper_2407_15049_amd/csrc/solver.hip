@@ -159,6 +159,11 @@ extern "C" int lrsdp_ctx_create(int device, void *hip_stream, lrsdp_ctx **out) {
         lrsdp_ctx_destroy(c);
         return set_error(LRSDP_EHIP, "context setup failed: %s", hipGetErrorString(e));
     }
+    int rc = noalloc_init(device, &c->static_scratch);
+    if (rc) {
+        lrsdp_ctx_destroy(c);
+        return rc;
+    }
     *out = c;
     return LRSDP_OK;
 }

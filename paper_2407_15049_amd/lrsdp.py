@@ -106,6 +106,8 @@ _SIGS = {
     "lrsdp_k_ls_coeffs": (C.c_int, [_P, _P, C.c_int, _P, _P, _I64, _P, C.c_double, _P, _P, _P, _P]),
     "lrsdp_k_cubic": (C.c_int, [_P, _P, _P]),
     "lrsdp_k_alm": (C.c_int, [_P, _P, C.c_int, _P, _I64, _P, C.c_double, _P, _P]),
+    "lrsdp_k_alm_noalloc": (C.c_int, [_P, _P, C.c_int, _P, _I64, _P, C.c_double, _P]),
+    "lrsdp_k_alm_noalloc_max_bytes": (C.c_size_t, []),
     "lrsdp_k_lbfgs_dir": (C.c_int, [_P, C.c_int, _I64, _I64, _P, _P, _P, C.c_int, _P]),
     "lrsdp_k_admm": (C.c_int, [_P, _P, C.c_int, _P, _P, _I64, _P, C.c_double, C.c_int, C.c_double, C.c_int, _P,
                                 C.c_size_t]),
@@ -350,6 +352,16 @@ def k_cubic(ctx, a, tau):
 def k_alm(ctx, prob, prec, R, y, sigma, work, out):
     _check(load().lrsdp_k_alm(ctx.handle, prob.handle, prec, _ptr(R), R.shape[1], _ptr(y), float(sigma),
                               _ptr(work), _ptr(out)))
+
+
+def k_alm_noalloc(ctx, prob, prec, R, y, sigma, out):
+    """lrsdp_k_alm without a caller work buffer (the library's static array)."""
+    _check(load().lrsdp_k_alm_noalloc(ctx.handle, prob.handle, prec, _ptr(R), R.shape[1], _ptr(y), float(sigma),
+                                      _ptr(out)))
+
+
+def k_alm_noalloc_max_bytes() -> int:
+    return load().lrsdp_k_alm_noalloc_max_bytes()
 
 
 def k_lbfgs_dir(ctx, prec, G, S, Y, D):
