@@ -170,13 +170,13 @@ int lrsdp_problem_upload(lrsdp_ctx *ctx, lrsdp_problem *prob, void *dev,
                          size_t bytes);
 
 /* ---- solver options ---------------------------------------------------------
- * Defaults (lrsdp_options_default): F64, T = 2 L-BFGS pairs, tol = 1e-5,
- * sigma0 = 0 (selects 4 ||vec(C)||_1 / m), sigma_factor = 2, sigma_max_ratio =
+ * Defaults (lrsdp_options_default): F64, T = 1 L-BFGS pair, tol = 1e-5,
+ * sigma0 = 0 (selects 4 ||vec(C)||_1 / m), sigma_factor = 4, sigma_max_ratio =
  * 1e8, feas_decrease = 0.25, eta0 = 0.1, eta_factor = 0.25, eta_min = 1e-9,
- * max_outer = 300, max_inner = 2000, max_iter_total = 200000,
+ * max_outer = 300, max_inner = 1000, max_iter_total = 200000,
  * check_every = 8, time_limit_s = 1e30, refresh_every = 0 (off), phase2 = 0,
  * switch_err1 = 1e-3, admm_check = 10, max_admm = 5000, precond = 0,
- * rank_max = 0 (off), rank_trigger = 2000, rank_scale = 1e-2, rank_seed = 15049,
+ * rank_max = 0 (off), rank_trigger = 1000, rank_scale = 1e-2, rank_seed = 15049,
  * reopt = 0, reopt_factor = 0.1, max_reopt = 10, cert_iters = 300.
  * With re-optimisation the results (obj, dual, err3, sigma, y) are those of
  * the original problem: the last round's divided by its objective scale.

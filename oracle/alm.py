@@ -11,11 +11,11 @@ options struct (the two share numbers, not code):
 
 * y0 = 0; sigma0 = 4 ||vec(C)||_1 / m unless given;
 * after each inner solve: y <- y + sigma (b - A(RR^T));
-  sigma <- min(sigma_factor * sigma, sigma_max_ratio * sigma0) when err1 did not
+  sigma <- min(sigma_factor * sigma, sigma_max_ratio * sigma0) (sigma_factor = 4) when err1 did not
   fall below feas_decrease * (previous err1);
 * inner L-BFGS stops when ||grad||_F <= eta_k * max(1, ||grad at its start||_F),
   eta_0 = eta0, eta_{k+1} = max(eta_factor * eta_k, eta_min);
-* L-BFGS memory T = lbfgs_mem (default 2) pairs from consecutive iterations; a pair failing
+* L-BFGS memory T = lbfgs_mem (default 1) pairs from consecutive iterations; a pair failing
   the curvature guard, or a direction that is not a descent direction, clears
   the memory (the next direction is -grad);
 * stop when err1 <= tol and |err3| <= tol (the paper's mild re-opt criterion);
@@ -40,12 +40,12 @@ from .problem import SDPProblem
 @dataclass
 class Options:
     tol: float = 1e-5
-    lbfgs_mem: int = 2
+    lbfgs_mem: int = 1
     max_outer: int = 300
-    max_inner: int = 2000
+    max_inner: int = 1000
     max_iter_total: int = 200000
     sigma0: float = 0.0            # 0 selects 4 ||vec(C)||_1 / m
-    sigma_factor: float = 2.0
+    sigma_factor: float = 4.0
     sigma_max_ratio: float = 1e8
     feas_decrease: float = 0.25
     eta0: float = 1e-1
@@ -54,7 +54,7 @@ class Options:
     time_limit: float = 1e30
     phase2: bool = False           # switch to the splitting phase (Section 2.2)
     rank_max: int = 0              # dynamic rank (appendix A.1); 0 or <= rank: off
-    rank_trigger: int = 2000       # L-BFGS iterations of a subproblem that trigger growth
+    rank_trigger: int = 1000       # L-BFGS iterations of a subproblem that trigger growth
     rank_scale: float = 1e-2       # standard deviation of the new entries
     rank_seed: int = 15049
     precond: int = 0               # MaxCut: row-block H0 for the L-BFGS direction (not in the paper):

@@ -189,14 +189,14 @@ extern "C" void lrsdp_options_default(lrsdp_options *o) {
     o->prec = LRSDP_F64;
     o->rank = 0;
     o->ld = 0;
-    o->lbfgs_mem = 2;
+    o->lbfgs_mem = 1;
     o->tol = 1e-5;
     o->max_outer = 300;
-    o->max_inner = 2000;
+    o->max_inner = 1000;
     o->max_iter_total = 200000;
     o->time_limit_s = 1e30;
     o->sigma0 = 0.0;
-    o->sigma_factor = 2.0;
+    o->sigma_factor = 4.0;
     o->sigma_max_ratio = 1e8;
     o->feas_decrease = 0.25;
     o->eta0 = 1e-1;
@@ -212,7 +212,7 @@ extern "C" void lrsdp_options_default(lrsdp_options *o) {
     o->max_admm = 5000;
     o->precond = 0;
     o->rank_max = 0;
-    o->rank_trigger = 2000;
+    o->rank_trigger = 1000;
     o->rank_scale = 1e-2;
     o->rank_seed = 15049;
     o->reopt = 0;

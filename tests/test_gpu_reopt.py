@@ -25,6 +25,11 @@ from gpu_util import dev_factor, host
 
 pytestmark = pytest.mark.gpu
 
+# The schedule these cases were built on (penalty x2 on a stall, 2000 L-BFGS
+# iterations per subproblem, two pairs), on both sides: the round counts and
+# the notes on each case below belong to it.
+SCHED = dict(sigma_factor=2.0, max_inner=2000, lbfgs_mem=2)
+
 
 @pytest.fixture(scope="module")
 def ctx():
@@ -53,7 +58,8 @@ def maxcut_case(case):
 def solve(ctx, prob, R0, prec, m, **kw):
     import torch
     r = R0.shape[1]
-    opts = L.default_options(prec=prec, rank=r, ld=L.padded_ld(r, L.F64 if prec == L.F64 else L.F32), **kw)
+    opts = L.default_options(prec=prec, rank=r, ld=L.padded_ld(r, L.F64 if prec == L.F64 else L.F32),
+                             **{**SCHED, **kw})
     Rd = dev_factor(R0, prec)
     yd = torch.zeros(m, dtype=torch.float64, device="cuda")
     rc, res = L.solve(ctx, prob, Rd, yd, opts)
@@ -77,7 +83,7 @@ def test_maxcut_reopt_matches_oracle(ctx, case, level):
     prob = L.Problem.maxcut(n, u, v, w).upload(ctx)
     op = maxcut_problem(n, u, v, w)
     rc, res, R, y = solve(ctx, prob, R0, L.F64, n, reopt=level)
-    ores = alm_solve(op, R0, opts=OOptions(reopt=level))
+    ores = alm_solve(op, R0, opts=OOptions(**SCHED, reopt=level))
     print(res.as_dict(), "oracle", ores.obj, ores.outer, ores.inner, ores.reopt_rounds, ores.err2)
     assert rc == L.OK and ores.converged
     assert res.reopt_rounds == ores.reopt_rounds and res.outer == ores.outer
@@ -99,7 +105,7 @@ def test_strict_reopt_reports_not_converged(ctx):
     prob = L.Problem.maxcut(n, u, v, w).upload(ctx)
     op = maxcut_problem(n, u, v, w)
     rc, res, R, y = solve(ctx, prob, R0, L.F64, n, reopt=2, max_reopt=3)
-    ores = alm_solve(op, R0, opts=OOptions(reopt=2, max_reopt=3))
+    ores = alm_solve(op, R0, opts=OOptions(**SCHED, reopt=2, max_reopt=3))
     print(res.as_dict(), "oracle", ores.err2, ores.reopt_rounds)
     assert rc == L.NOT_CONVERGED and not ores.converged
     assert res.reopt_rounds == ores.reopt_rounds == 3
@@ -120,7 +126,7 @@ def test_completion_reopt_matches_oracle(ctx):
     op = completion_problem(60, 50, i, j, M)
     R0 = init_factor(110, 5, 9)
     rc, res, R, y = solve(ctx, prob, R0, L.F64, op.m, reopt=1)
-    ores = alm_solve(op, R0, opts=OOptions(reopt=1))
+    ores = alm_solve(op, R0, opts=OOptions(**SCHED, reopt=1))
     print(res.as_dict(), "oracle", ores.obj, ores.outer, ores.inner, ores.reopt_rounds)
     assert rc == L.OK and ores.converged and ores.reopt_rounds == 1
     assert res.reopt_rounds == ores.reopt_rounds and res.outer == ores.outer
@@ -135,7 +141,7 @@ def test_reopt_with_row_block_h0_matches_oracle(ctx):
     prob = L.Problem.maxcut(n, u, v, w).upload(ctx)
     op = maxcut_problem(n, u, v, w)
     rc, res, R, y = solve(ctx, prob, R0, L.F64, n, reopt=1, precond=1)
-    ores = alm_solve(op, R0, opts=OOptions(reopt=1, precond=1))
+    ores = alm_solve(op, R0, opts=OOptions(**SCHED, reopt=1, precond=1))
     print(res.as_dict(), "oracle", ores.obj, ores.outer, ores.inner, ores.reopt_rounds)
     assert rc == L.OK and ores.converged
     assert res.reopt_rounds == ores.reopt_rounds and res.outer == ores.outer
@@ -152,7 +158,7 @@ def test_reopt_after_the_splitting_phase_matches_oracle(ctx):
     prob = L.Problem.maxcut(n, u, v, w).upload(ctx)
     op = maxcut_problem(n, u, v, w)
     rc, res, R, y = solve(ctx, prob, R0, L.F64, n, reopt=1, phase2=1, switch_err1=1e-3)
-    ores = alm_solve(op, R0, opts=OOptions(reopt=1, phase2=True, switch_err1=1e-3))
+    ores = alm_solve(op, R0, opts=OOptions(**SCHED, reopt=1, phase2=True, switch_err1=1e-3))
     print(res.as_dict(), "oracle", ores.obj, ores.outer, ores.inner, ores.reopt_rounds, ores.admm_iters)
     assert rc == L.OK and ores.converged and ores.reopt_rounds == 1 and ores.admm_fallbacks == 0
     assert res.reopt_rounds == ores.reopt_rounds and res.admm_iters == ores.admm_iters
@@ -168,7 +174,7 @@ def test_reopt_f32(ctx):
     prob = L.Problem.maxcut(n, u, v, w).upload(ctx)
     op = maxcut_problem(n, u, v, w)
     rc, res, R, y = solve(ctx, prob, R0, L.F32, n, reopt=1)
-    ores = alm_solve(op, R0, opts=OOptions(reopt=1))
+    ores = alm_solve(op, R0, opts=OOptions(**SCHED, reopt=1))
     print(res.as_dict(), "oracle", ores.obj)
     assert rc == L.OK
     m = K.alm_measures(op, R, y)

@@ -21,6 +21,11 @@ from oracle.alm import Options, _alm_run, alm_solve, scaled_objective
 from oracle.problem import completion_problem, maxcut_problem
 from synth import chung_lu_edges, completion_instance, erdos_renyi_edges, init_factor, pm1_weights
 
+# The schedule these cases were built on (penalty x2 on a stall, 2000 L-BFGS
+# iterations per subproblem, two pairs): which round first meets err3 depends
+# on it, and the properties pinned here are those of the re-optimisation logic.
+SCHED = dict(sigma_factor=2.0, max_inner=2000, lbfgs_mem=2)
+
 
 def cl2k():
     u, v = chung_lu_edges(2000, 8000, 2.5, 77)
@@ -53,10 +58,10 @@ def test_scaled_lagrangian_identity(kind):
 
 def test_mild_reopt_meets_err3_on_the_original_problem():
     op, R0 = cl2k()
-    first = _alm_run(op, R0, None, Options(), err1_only=True)
+    first = _alm_run(op, R0, None, Options(**SCHED), err1_only=True)
     m0 = K.alm_measures(op, first.R, first.y)
     assert first.converged and m0["err1"] <= 1e-5 and abs(m0["err3"]) > 1e-5   # round 0 alone is not enough
-    res = alm_solve(op, R0, opts=Options(reopt=1))
+    res = alm_solve(op, R0, opts=Options(**SCHED, reopt=1))
     assert res.converged and res.reopt_rounds >= 1
     m = K.alm_measures(op, res.R, res.y)
     assert m["err1"] <= 1e-5 and abs(m["err3"]) <= 1e-5
@@ -72,8 +77,8 @@ def test_reopt_without_extra_rounds_is_the_err1_only_run():
     u, v = erdos_renyi_edges(1000, 5000, 15049)
     op = maxcut_problem(1000, u, v)
     R0 = init_factor(1000, 10, 15050)
-    first = _alm_run(op, R0, None, Options(), err1_only=True)
-    res = alm_solve(op, R0, opts=Options(reopt=1))
+    first = _alm_run(op, R0, None, Options(**SCHED), err1_only=True)
+    res = alm_solve(op, R0, opts=Options(**SCHED, reopt=1))
     assert res.reopt_rounds == 0 and res.converged
     assert np.array_equal(res.R, first.R) and np.array_equal(res.y, first.y)
     assert res.outer == first.outer and res.inner == first.inner
@@ -83,8 +88,8 @@ def test_strict_reopt_rejects_a_rank_deficient_stationary_point():
     u, v = erdos_renyi_edges(200, 800, 5)
     op = maxcut_problem(200, u, v)
     R0 = init_factor(200, 2, 8)
-    mild = alm_solve(op, R0, opts=Options(reopt=1))
-    strict = alm_solve(op, R0, opts=Options(reopt=2, max_reopt=3))
+    mild = alm_solve(op, R0, opts=Options(**SCHED, reopt=1))
+    strict = alm_solve(op, R0, opts=Options(**SCHED, reopt=2, max_reopt=3))
     assert mild.converged and mild.reopt_rounds == 0
     assert not strict.converged and strict.reopt_rounds == 3
     lam = certify.lambda_min(op, strict.y)
@@ -98,7 +103,7 @@ def test_strict_reopt_rejects_a_rank_deficient_stationary_point():
 
 def test_strict_reopt_accepts_when_lambda_min_is_small():
     op, R0 = cl2k()
-    res = alm_solve(op, R0, opts=Options(reopt=2))
+    res = alm_solve(op, R0, opts=Options(**SCHED, reopt=2))
     assert res.converged
     assert res.err2 == pytest.approx(certify.err2(op, res.y), rel=1e-9)
     assert res.err2 <= 1e-5
