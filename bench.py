@@ -133,9 +133,8 @@ def main():
         opts = L.default_options(prec=L.F64, rank=r, ld=ld, profile=1, verbose=int(args.verbose))
         if args.short:
             opts.max_outer, opts.max_inner = 1, args.short
-        per = {L.F64: dict(opts=opts, R0=R0d, R=torch.empty_like(R0d),
-                           y=torch.zeros(n, dtype=torch.float64, device=dev),
-                           ws=torch.empty(L.workspace_bytes(prob, opts), dtype=torch.uint8, device=dev))}
+        # R, y and the workspace of the float64 path are allocated at its first solve
+        per = {L.F64: dict(opts=opts, R0=R0d, R=None, y=None, ws=None)}
         info = prob.info
         runs.append(dict(name=name, inst=inst, prob=prob, per=per, n=n, r=r, nnz=info.nnz,
                          setup=dict(generate_s=round(t1 - t0, 2), build_s=round(t2 - t1, 2),
@@ -148,6 +147,10 @@ def main():
         """One solve of `run` in `prec` from its starting factor (or R_init / y_init),
         stopped by the solver's own time limit when `limit` is given."""
         p = run["per"][prec]
+        if p["R"] is None:
+            p["R"] = torch.empty_like(p["R0"])
+            p["y"] = torch.zeros(run["n"], dtype=torch.float64, device=dev)
+            p["ws"] = torch.empty(L.workspace_bytes(run["prob"], p["opts"]), dtype=torch.uint8, device=dev)
         o = opts if opts is not None else p["opts"]
         if limit is not None:
             o.time_limit_s = max(1.0, limit)

@@ -205,18 +205,18 @@ __global__ __launch_bounds__(kBlock) void k_cmp_sddmm(DevCompletion P, SddArgs<S
         const CV ui = active ? *reinterpret_cast<const CV *>(a.U + off) : zero;
         const CV vi = (MODE != kSddRefresh && active) ? *reinterpret_cast<const CV *>(a.V + off) : zero;
         const int b = P.top_ptr[i], e = P.top_ptr[i + 1];
-        // The row's samples PW at a time: each lane loads the partner index and
-        // sample id of NT of them (coalesced; past the row's end it repeats the
-        // last sample), then four samples per step take them by lane shuffles,
-        // with all eight partner-row loads in flight before the first reduction
-        // (a step past the end repeats the last sample's loads and skips its
-        // outputs).  NT = 2 for float64 rows; float32 rows keep one, since the
-        // extra index registers cost the float32 line-search build a wave per
-        // SIMD (measured slower at n = 1e6, m = 1e7).
-        // The next pass's indices are loaded before this pass's partner rows, so
-        // their latency overlaps the gather instead of adding to it.
-        constexpr int NT = sizeof(S) == 8 ? 2 : 1;
+        // The row's samples PW = 2 GS at a time: each lane loads the partner
+        // index and sample id of two of them (coalesced; past the row's end it
+        // repeats the last sample), then SS samples per step take them by lane
+        // shuffles, with all 2 SS partner-row loads in flight before the first
+        // reduction (a step past the end repeats the last sample's loads and
+        // skips its outputs).  The next pass's indices are loaded before this
+        // pass's partner rows, so their latency overlaps the gather.  Float32
+        // rows of 4-lane groups take eight samples per step (one step per
+        // pass); float64 rows four.
+        constexpr int NT = 2;
         constexpr int PW = NT * GS;
+        constexpr int SS = sizeof(S) == 8 ? 4 : 8;   // samples per step
         int32_t cc[NT], ee[NT];
         if (b < e) {
 #pragma unroll
@@ -239,25 +239,25 @@ __global__ __launch_bounds__(kBlock) void k_cmp_sddmm(DevCompletion P, SddArgs<S
               }
           }
 #pragma unroll
-          for (int s0 = 0; s0 < PW; s0 += 4) {
+          for (int s0 = 0; s0 < PW; s0 += SS) {
             if (s0 >= cnt0) break;
-            const int cnt = min(4, cnt0 - s0);
-            int64_t pj[4];
-            int kk[4];
+            const int cnt = min(SS, cnt0 - s0);
+            int64_t pj[SS];
+            int kk[SS];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
+            for (int q = 0; q < SS; ++q) {
                 const int src = s0 + q;   // compile-time register and lane
                 pj[q] = (P.n1 + __shfl(cc[src / GS], src % GS, GS)) * a.ld + lane * NV;
                 kk[q] = __shfl(ee[src / GS], src % GS, GS);
             }
-            CV xu[4], xv[4];
+            CV xu[SS], xv[SS];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
+            for (int q = 0; q < SS; ++q) {
                 xu[q] = active ? *reinterpret_cast<const CV *>(a.U + pj[q]) : zero;
                 xv[q] = (MODE != kSddRefresh && active) ? *reinterpret_cast<const CV *>(a.V + pj[q]) : zero;
             }
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
+            for (int q = 0; q < SS; ++q) {
                 const int k = kk[q];
                 const bool live = q < cnt;
                 if constexpr (MODE == kSddA) {

@@ -555,7 +555,9 @@ def test_rank_growth_solve_matches_oracle(ctx):
     n, u, v, w, _ = graph("er_1k")
     R0 = init_factor(n, 10, 15050)
     print_case(test="rank_growth_solve", case="er_1k")
-    kw = dict(rank_max=16, rank_trigger=100)
+    # the schedule this case was built on (penalty x2, 2000 iterations, two pairs),
+    # on both sides: whether a subproblem reaches rank_trigger decides the growth
+    kw = dict(rank_max=16, rank_trigger=100, sigma_factor=2.0, max_inner=2000, lbfgs_mem=2)
     rc, res, R, y = gpu_solve(ctx, n, u, v, w, np.hstack([R0, np.zeros((n, 6))]), L.F64, rank=10, **kw)
     ores = alm_solve(maxcut_problem(n, u, v, w), R0, opts=OOptions(**kw))
     print(res.as_dict(), "oracle", ores.obj, ores.rank_final)
