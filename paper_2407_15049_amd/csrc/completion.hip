@@ -205,18 +205,20 @@ __global__ __launch_bounds__(kBlock) void k_cmp_sddmm(DevCompletion P, SddArgs<S
         const CV ui = active ? *reinterpret_cast<const CV *>(a.U + off) : zero;
         const CV vi = (MODE != kSddRefresh && active) ? *reinterpret_cast<const CV *>(a.V + off) : zero;
         const int b = P.top_ptr[i], e = P.top_ptr[i + 1];
-        // The row's samples PW = 2 GS at a time: each lane loads the partner
-        // index and sample id of two of them (coalesced; past the row's end it
-        // repeats the last sample), then SS samples per step take them by lane
-        // shuffles, with all 2 SS partner-row loads in flight before the first
-        // reduction (a step past the end repeats the last sample's loads and
-        // skips its outputs).  The next pass's indices are loaded before this
-        // pass's partner rows, so their latency overlaps the gather.  Float32
-        // rows of 4-lane groups take eight samples per step (one step per
-        // pass); float64 rows four.
-        constexpr int NT = 2;
+        // The row's samples PW at a time: each lane loads the partner index and
+        // sample id of NT of them (coalesced; past the row's end it repeats the
+        // last sample), then SS = 4 samples per step take them by lane shuffles,
+        // with all eight partner-row loads in flight before the first reduction
+        // (a step past the end repeats the last sample's loads and skips its
+        // outputs).  NT = 2 for float64 rows; float32 rows keep one: the extra
+        // index registers cost the float32 line-search build a wave per SIMD,
+        // and eight samples per step with two index registers measured 682 us
+        // against 500 us (mode A, n = 1e6, m = 1e7).  The next pass's indices
+        // are loaded before this pass's partner rows, so their latency overlaps
+        // the gather.
+        constexpr int NT = sizeof(S) == 8 ? 2 : 1;
         constexpr int PW = NT * GS;
-        constexpr int SS = sizeof(S) == 8 ? 4 : 8;   // samples per step
+        constexpr int SS = 4;   // samples per step
         int32_t cc[NT], ee[NT];
         if (b < e) {
 #pragma unroll
