@@ -42,6 +42,8 @@ WORKLOADS = {
                 "maxcut n=1e6 pair: Erdos-Renyi 5e6 edges + Chung-Lu beta=2.5 mean degree 10 (5e6 edges), "
                 "weights uniform in {-1,+1}, C=-L/4, diag(X)=1, rank 20"),
     "er_1k": (["er_1k"], "maxcut n=1e3 Erdos-Renyi 5e3 edges, unit weights, C=-L/4, diag(X)=1, rank 10"),
+    "cl_50m": (["cl_50m"], "maxcut n=5e7 Chung-Lu beta=2.5 mean degree 4 (1e8 edges), unit weights, C=-L/4, "
+                           "diag(X)=1, rank 26 (held out from the warm-start training graphs)"),
 }
 DEFAULT_PATHS = "f32_warm"
 ALL_PATHS = ["f32_warm", "f32_precond_warm", "f32", "f32_precond", "f32_bf16in", "f64_precond", "f64_degsort",
@@ -62,6 +64,8 @@ def parse():
     ap.add_argument("--paths", default=DEFAULT_PATHS,
                     help="comparison paths run after the timed steps in the time left (comma list of: "
                          + ", ".join(ALL_PATHS) + ")")
+    ap.add_argument("--path-limit", type=float, default=None,
+                    help="time limit of each comparison-path solve in seconds (default: the budget left)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--cert", action="store_true", help="dual certificate of every result (untimed)")
@@ -302,7 +306,8 @@ def comparison_paths(args, ctx, dev, L, runs, paths, enabled, left, reserve_cpu,
         return
 
     def budget_for_path():
-        return left() - reserve_cpu - 10.0
+        b = left() - reserve_cpu - 10.0
+        return min(b, args.path_limit) if args.path_limit else b
 
     def record(path, run, dt, rc, res, extra=None, y=None):
         o64 = paths["f64"].get(run["name"], {}).get("obj")
@@ -536,12 +541,13 @@ def completion_bench(args, ctx, dev):
             iters=res.inner, ms_per_iter=round(1e3 * dt / max(res.inner, 1), 3), err1=res.err1)
         log(f"completion {name}: {out[name]}")
         del R, Y, R0, ws
+    copy_gbs = copy_ceiling(torch, dev, args.copy_calibration)
     print(json.dumps({
         "metric": "completion kernels: SDDMM / SpMM algorithmic GB/s and L-BFGS ms per iteration",
         "unit": "GB/s", "n_gpus": 1, "dtype": "f64,f32", "data": "synthetic",
         "config": {"workload": "matrix completion n1=n2=5e5 (X of order 1e6), m=1e7 samples (20 per row), "
                                "planted rank 5, factor rank 16", **cfg},
-        "kernels": out}), flush=True)
+        "kernels": out, "copy_ceiling_gbs": copy_gbs}), flush=True)
 
 
 GENERAL = dict(n=1_000_000, c_nnz=5_000_000, extra=1000, per_con=5, rank=16, seed=15052)

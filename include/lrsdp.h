@@ -125,6 +125,23 @@ int lrsdp_problem_general(int64_t n, int64_t c_nnz, const int32_t *c_row, const 
                           const int32_t *a_row, const int32_t *a_col, const double *a_val,
                           const double *b, lrsdp_problem **out);
 
+/* Storage of C for general problems (Section 3.5, last paragraph: a small C
+ * with many nonzeros is stored densely and applied with dense operators).
+ * LRSDP_C_DENSE keeps C as an n x n float64 matrix (n <= 16384; n^2 * 8 bytes
+ * of device memory): C V is a dense product (float64 matrix cores), Omega
+ * holds only the nonzero columns of the stacked constraint matrix, and the
+ * objective and line-search terms <C, U V^T> come from the rows of C V.
+ * LRSDP_C_SPARSE keeps C on Omega.  LRSDP_C_AUTO (lrsdp_problem_general)
+ * takes dense storage when n <= 8192 and at least 10% of the upper-triangle
+ * positions of C are nonzero.  lrsdp_problem_info.c_dense reports the choice. */
+#define LRSDP_C_AUTO   0
+#define LRSDP_C_SPARSE 1
+#define LRSDP_C_DENSE  2
+int lrsdp_problem_general_ex(int64_t n, int64_t c_nnz, const int32_t *c_row, const int32_t *c_col,
+                             const double *c_val, int64_t m, int64_t a_nnz, const int32_t *a_con,
+                             const int32_t *a_row, const int32_t *a_col, const double *a_val,
+                             const double *b, int c_storage, lrsdp_problem **out);
+
 /* Several PSD blocks: min sum_j <C_j, X_j> s.t. sum_j <A_kj, X_j> = b_k, every
  * X_j psd of order block_n[j] (a block of order 1 is a nonnegative scalar).
  * Triplets as in lrsdp_problem_general with block-local indices and a block id
@@ -154,6 +171,7 @@ typedef struct {
     double  c_l1;        /* ||vec(C)||_1                                         */
     double  b_l1;        /* ||b||_1                                              */
     double  b_inf;       /* ||b||_inf                                            */
+    int     c_dense;     /* general problems: 1 when C is stored densely         */
 } lrsdp_problem_info;
 
 int lrsdp_problem_get_info(const lrsdp_problem *prob, lrsdp_problem_info *out);
@@ -388,8 +406,10 @@ int lrsdp_k_lbfgs_dir(lrsdp_ctx *ctx, int prec, int64_t n, int64_t ld,
  * of node i to (t_i, s_i); the warm start is y0_i = -t_i a_i / 4 with
  * a_i = sum_j |w_ij| and t_i limited to [-2, 2] (at an optimum y*_i =
  * -sum_j w_ij (1 - X*_ij) / 4 with |X*_ij| <= 1), and sigma0 = (default
- * sigma0) * exp(mean_i s_i) with the mean limited to a caller-given range (the
- * range of the training labels).  The default sigma0 is 4 ||vec(C)||_1 / m.
+ * sigma0) * exp(m / 2), m the mean of s_i limited to a caller-given range (the
+ * range of the training labels): s predicts log(final penalty / default) of a
+ * cold solve, and the warm start begins at the geometric mean of the default
+ * and that penalty.  The default sigma0 is 4 ||vec(C)||_1 / m.
  * Parameters are float32 (LRSDP_PARAM_F32) or bfloat16 storage
  * (LRSDP_PARAM_BF16, widened exactly to float32 in the kernels; training keeps
  * a float32 master copy).  Activations and sums are float32.  Only MaxCut

@@ -141,9 +141,11 @@ def multipliers_from_output(out: np.ndarray, absdeg: np.ndarray) -> np.ndarray:
 
 
 def initial_penalty(out: np.ndarray, sigma_default: float, log_lo: float, log_hi: float) -> float:
-    """sigma0 = sigma_default exp(s) with s the mean second output limited to
-    [log_lo, log_hi] (the range of the training labels)."""
-    return sigma_default * float(np.exp(np.clip(out[:, 1].mean(), log_lo, log_hi)))
+    """sigma0 = sigma_default exp(s / 2) with s the mean second output limited to
+    [log_lo, log_hi] (the range of the training labels): the output predicts
+    log(final penalty / default) of a cold solve, and the warm start begins at
+    the geometric mean of the default and that final penalty."""
+    return sigma_default * float(np.exp(0.5 * np.clip(out[:, 1].mean(), log_lo, log_hi)))
 
 
 def sigma_label(sigma_final: float, sigma_default: float) -> float:

@@ -16,6 +16,13 @@
 // cs C_o - sum_k A_k,o y_k from the transposed stacked matrix (eq. At with the
 // index set Omega) into the problem's second compressed buffer, then
 // k_gen_spmm gathers one value and one row of V per stored entry.
+//
+// Dense storage of C (Section 3.5, last paragraph): Omega then holds the
+// constraint positions only (C's entries there are zero) and C enters through
+// the dense product W = cs C V (k_dense_mfma, float64 matrix cores, split over
+// k, then k_dense_finish adds the splits in a fixed order).  The SpMM adds W
+// to the sparse part row by row; the objective and line-search sums
+// <C, U V^T> = sum_i U_i . (C V)_i come from the rows of the product.
 #include <algorithm>
 
 #include "device.h"
@@ -194,6 +201,7 @@ struct GenSpmmArgs {
     int force_slot;       // >= 0: write G into this slot and ignore st->done (subproblem start)
     Rings<S> rings;
     double *partials;
+    const S *addw;        // dense C: the rows of cs C V, added to the sparse part (nullable)
 };
 
 // x2[o] = value of cs C - A*(ytil) at position o (skipped when st says the
@@ -262,12 +270,17 @@ __global__ __launch_bounds__(kBlock) void k_gen_spmm(DevGeneral P, GenSpmmArgs<S
 #pragma unroll
             for (int c = 0; c < 4; ++c) acc.v[c] = fma(w0, vq.v[c], acc.v[c]);
         }
+        const int64_t off = row * a.ld + lane * NV;
+        if (a.addw) {
+            const D4 wv = widen(active ? *reinterpret_cast<const CV *>(a.addw + off) : zero);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc.v[c] += wv.v[c];
+        }
         D4 o;
 #pragma unroll
         for (int c = 0; c < 4; ++c) o.v[c] = GRAD ? 2.0 * acc.v[c] : acc.v[c];
         CV os;
         narrow(o, os);
-        const int64_t off = row * a.ld + lane * NV;
         if constexpr (!GRAD) {
             if (active) *reinterpret_cast<CV *>(a.Y + off) = os;
         } else {
@@ -291,6 +304,134 @@ __global__ __launch_bounds__(kBlock) void k_gen_spmm(DevGeneral P, GenSpmmArgs<S
     if constexpr (GRAD) block_sums_store<kMaxBasis>(s, a.partials + (size_t)blockIdx.x * kMaxSums);
 }
 
+// ---------------------------------------------------------------------------
+// Dense C: W = C V on float64 matrix cores.  A workgroup of four wavefronts
+// owns kDBM = 64 rows of C and one range of k; each wavefront owns 16 rows and
+// every 16-column tile of V (NT tiles, ld <= 16 NT), and runs
+// v_mfma_f64_16x16x4f64 over the range: A operand lane l = C[row l%16][k + l/16],
+// B operand lane l = V[k + l/16][col l%16], result register i of lane l holds
+// row l/16 + 4 i, column l%16.  C and V go through LDS in kDKC-wide k stages.
+// ---------------------------------------------------------------------------
+constexpr int kDBM = 64;
+constexpr int kDKC = 16;
+
+typedef double dense_acc_t __attribute__((ext_vector_type(4)));
+
+template <typename S, int NT>
+__global__ __launch_bounds__(kBlock) void k_dense_mfma(const double *__restrict__ C, const S *__restrict__ V,
+                                                       int64_t n, int64_t ld, int64_t kspan,
+                                                       double *__restrict__ part, const SolverState *st) {
+    if (st && st->done) return;
+    constexpr int LDP = 16 * NT;
+    __shared__ double Cs[kDBM][kDKC + 1];
+    __shared__ double Vs[kDKC][LDP + 1];
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int64_t r0 = (int64_t)blockIdx.x * kDBM;
+    const int64_t k0 = (int64_t)blockIdx.y * kspan, k1 = min(n, k0 + kspan);
+    dense_acc_t acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = dense_acc_t{0.0, 0.0, 0.0, 0.0};
+    for (int64_t kb = k0; kb < k1; kb += kDKC) {
+        for (int t = threadIdx.x; t < kDBM * kDKC; t += kBlock) {
+            const int rr = t / kDKC, kk = t % kDKC;
+            const int64_t gr = r0 + rr, gk = kb + kk;
+            Cs[rr][kk] = (gr < n && gk < k1) ? C[gr * n + gk] : 0.0;
+        }
+        for (int t = threadIdx.x; t < kDKC * LDP; t += kBlock) {
+            const int kk = t / LDP, cc = t % LDP;
+            const int64_t gk = kb + kk;
+            Vs[kk][cc] = (gk < k1 && cc < ld) ? (double)V[gk * ld + cc] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < kDKC; kk += 4) {
+            const double a = Cs[wave * 16 + (lane % 16)][kk + lane / 16];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const double b = Vs[kk + lane / 16][t * 16 + lane % 16];
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    constexpr int RW = (int)(kDenseRowBytes / sizeof(double));
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t row = r0 + wave * 16 + lane / 16 + 4 * i;
+            if (row < n) part[((int64_t)blockIdx.y * n + row) * RW + t * 16 + lane % 16] = acc[t][i];
+        }
+    }
+}
+
+enum { kDenseStore = 0, kDenseLS = 1, kDenseRefresh = 2 };
+
+// Adds the k splits of each row in split order and scales by cs.  kDenseStore:
+// W_i = cs (C V)_i in the storage type; kDenseLS (V = D): s[0] += D_i . cs (C D)_i,
+// s[6] += 2 R_i . cs (C D)_i; kDenseRefresh (V = R): s[0] += R_i . cs (C R)_i.
+template <typename S, int MODE>
+__global__ __launch_bounds__(kBlock) void k_dense_finish(const double *__restrict__ part, int ks, int64_t n,
+                                                         int64_t ld, double cs, S *W, const S *U, const S *V,
+                                                         double *partials, const SolverState *st) {
+    if (st && st->done) return;
+    constexpr int RW = (int)(kDenseRowBytes / sizeof(double));
+    double s[kLsSums] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int64_t row = (int64_t)blockIdx.x * kBlock + threadIdx.x; row < n; row += (int64_t)gridDim.x * kBlock) {
+        double d0 = 0.0, d1 = 0.0;
+        for (int c = 0; c < ld; ++c) {
+            double v = 0.0;
+            for (int k = 0; k < ks; ++k) v += part[((int64_t)k * n + row) * RW + c];
+            v *= cs;
+            if constexpr (MODE == kDenseStore) {
+                W[row * ld + c] = (S)v;
+            } else if constexpr (MODE == kDenseLS) {
+                d0 = fma((double)V[row * ld + c], v, d0);
+                d1 = fma((double)U[row * ld + c], v, d1);
+            } else {
+                d0 = fma((double)U[row * ld + c], v, d0);
+            }
+        }
+        s[0] += d0;
+        if constexpr (MODE == kDenseLS) s[6] += 2.0 * d1;
+    }
+    if constexpr (MODE != kDenseStore) block_sums_store<kLsSums>(s, partials + (size_t)blockIdx.x * kMaxSums);
+}
+
+constexpr int kDenseFinishBlocks = 256;
+
+// W = cs C V (MODE kDenseStore) or the dense sums of the LS / refresh pass into
+// partial rows (*nb rows written).  V, U: n x ld of S.
+template <typename S>
+int dense_product(hipStream_t s, const DevGeneral &P, int mode, const S *V, const S *U, int64_t ld, double cs,
+                  double *partials, const SolverState *st, int *nb) {
+    *nb = 0;
+    const int64_t n = P.n;
+    const int64_t rb = (n + kDBM - 1) / kDBM;
+    int ks = (int)std::min<int64_t>(kDenseMaxSplit, std::max<int64_t>(1, (512 + rb - 1) / rb));
+    ks = (int)std::max<int64_t>(1, std::min<int64_t>(ks, (n + kDKC - 1) / kDKC));
+    const int64_t kspan = ((n + ks - 1) / ks + kDKC - 1) / kDKC * kDKC;
+    ks = (int)((n + kspan - 1) / kspan);
+    const dim3 g((unsigned)rb, (unsigned)ks);
+    if (ld <= 16) hipLaunchKernelGGL((k_dense_mfma<S, 1>), g, dim3(kBlock), 0, s, P.cd, V, n, ld, kspan, P.dpart, st);
+    else if (ld <= 32) hipLaunchKernelGGL((k_dense_mfma<S, 2>), g, dim3(kBlock), 0, s, P.cd, V, n, ld, kspan, P.dpart, st);
+    else hipLaunchKernelGGL((k_dense_mfma<S, 4>), g, dim3(kBlock), 0, s, P.cd, V, n, ld, kspan, P.dpart, st);
+    LRSDP_CHECK_LAUNCH();
+    const int nf = gen_grid(n, kBlock) < kDenseFinishBlocks ? gen_grid(n, kBlock) : kDenseFinishBlocks;
+    if (mode == kDenseStore)
+        hipLaunchKernelGGL((k_dense_finish<S, kDenseStore>), dim3(nf), dim3(kBlock), 0, s, P.dpart, ks, n, ld, cs,
+                           (S *)P.dw, U, V, partials, st);
+    else if (mode == kDenseLS)
+        hipLaunchKernelGGL((k_dense_finish<S, kDenseLS>), dim3(nf), dim3(kBlock), 0, s, P.dpart, ks, n, ld, cs,
+                           (S *)nullptr, U, V, partials, st);
+    else
+        hipLaunchKernelGGL((k_dense_finish<S, kDenseRefresh>), dim3(nf), dim3(kBlock), 0, s, P.dpart, ks, n, ld, cs,
+                           (S *)nullptr, U, V, partials, st);
+    LRSDP_CHECK_LAUNCH();
+    if (mode != kDenseStore) *nb = nf;
+    return LRSDP_OK;
+}
+
 template <typename S>
 int gs_of_gen(int64_t ld) {
     const int ch = (int)(ld * (int64_t)sizeof(S) / 16);
@@ -300,7 +441,10 @@ int gs_of_gen(int64_t ld) {
 template <typename S, int MODE>
 int xbar_t(hipStream_t s, const DevGeneral &P, const XbarArgs<S> &a, int *nb) {
     const int gs = gs_of_gen<S>(a.ld);
-    *nb = gen_grid(P.nom, kBlock / gs);
+    // with dense C the dense sums take partial rows after the constraint rows:
+    // the positions pass keeps to half the grid so that all stay within
+    // 2 kMaxBlocks rows
+    *nb = std::min(gen_grid(P.nom, kBlock / gs), P.cd ? kMaxBlocks / 2 : kMaxBlocks);
     if (gs == 4) hipLaunchKernelGGL((k_gen_xbar<S, 4, MODE>), dim3(*nb), dim3(kBlock), 0, s, P, a);
     else if (gs == 8) hipLaunchKernelGGL((k_gen_xbar<S, 8, MODE>), dim3(*nb), dim3(kBlock), 0, s, P, a);
     else hipLaunchKernelGGL((k_gen_xbar<S, 16, MODE>), dim3(*nb), dim3(kBlock), 0, s, P, a);
@@ -338,7 +482,15 @@ int sddmm_t(hipStream_t s, const DevGeneral &P, const void *U, const void *V, in
     ConsArgs ca{P.x1, P.x2, out, q1, q2, ytil, y, sigma, partials ? partials + (size_t)nb1 * kMaxSums : nullptr,
                 st};
     if ((rc = cons_t<MODE>(s, P, ca, &nb2))) return rc;
-    *nb = MODE == kGenA ? 0 : nb1 + nb2;
+    int nb3 = 0;
+    if (P.cd && MODE != kGenA) {
+        // <C, DD^T>, <C, RD^T + DR^T> (LS, V = D) or <C, RR^T> (refresh) from the dense product
+        const S *Vd = MODE == kGenLS ? (const S *)V : (const S *)U;
+        if ((rc = dense_product<S>(s, P, MODE == kGenLS ? kDenseLS : kDenseRefresh, Vd, (const S *)U, ld, cs,
+                                   partials + (size_t)(nb1 + nb2) * kMaxSums, st, &nb3)))
+            return rc;
+    }
+    *nb = MODE == kGenA ? 0 : nb1 + nb2 + nb3;
     return LRSDP_OK;
 }
 
@@ -346,12 +498,18 @@ template <typename S, bool GRAD, int TM>
 int gen_spmm_tm(hipStream_t s, const DevGeneral &P, const GenSpmmArgs<S> &a, int *nb) {
     // values first (the gradient call of a finished subproblem skips both)
     const SolverState *skip = (GRAD && a.force_slot < 0) ? a.st : nullptr;
+    GenSpmmArgs<S> b = a;
+    if (P.cd) {
+        int nbd = 0, rc;
+        if ((rc = dense_product<S>(s, P, kDenseStore, a.V, nullptr, a.ld, a.cs, nullptr, skip, &nbd))) return rc;
+        b.addw = (const S *)P.dw;
+    }
     hipLaunchKernelGGL(k_gen_sv, dim3(gen_grid(P.nom, kBlock)), dim3(kBlock), 0, s, P, a.ytil, a.cs, skip);
     const int gs = gs_of_gen<S>(a.ld);
     *nb = gen_grid(P.n, kBlock / gs);
-    if (gs == 4) hipLaunchKernelGGL((k_gen_spmm<S, 4, GRAD, TM>), dim3(*nb), dim3(kBlock), 0, s, P, a);
-    else if (gs == 8) hipLaunchKernelGGL((k_gen_spmm<S, 8, GRAD, TM>), dim3(*nb), dim3(kBlock), 0, s, P, a);
-    else hipLaunchKernelGGL((k_gen_spmm<S, 16, GRAD, TM>), dim3(*nb), dim3(kBlock), 0, s, P, a);
+    if (gs == 4) hipLaunchKernelGGL((k_gen_spmm<S, 4, GRAD, TM>), dim3(*nb), dim3(kBlock), 0, s, P, b);
+    else if (gs == 8) hipLaunchKernelGGL((k_gen_spmm<S, 8, GRAD, TM>), dim3(*nb), dim3(kBlock), 0, s, P, b);
+    else hipLaunchKernelGGL((k_gen_spmm<S, 16, GRAD, TM>), dim3(*nb), dim3(kBlock), 0, s, P, b);
     LRSDP_CHECK_LAUNCH();
     return LRSDP_OK;
 }
@@ -391,10 +549,10 @@ int spmm_general(hipStream_t s, const DevGeneral &P, int prec, const void *V, in
                  void *Y) {
     int nb = 0;
     if (prec == LRSDP_F64) {
-        GenSpmmArgs<double> a{(const double *)V, (double *)Y, ytil, 1.0, ld, nullptr, -1, {}, nullptr};
+        GenSpmmArgs<double> a{(const double *)V, (double *)Y, ytil, 1.0, ld, nullptr, -1, {}, nullptr, nullptr};
         return gen_spmm_t<double, false>(s, P, a, &nb);
     }
-    GenSpmmArgs<float> a{(const float *)V, (float *)Y, ytil, 1.0, ld, nullptr, -1, {}, nullptr};
+    GenSpmmArgs<float> a{(const float *)V, (float *)Y, ytil, 1.0, ld, nullptr, -1, {}, nullptr, nullptr};
     return gen_spmm_t<float, false>(s, P, a, &nb);
 }
 
@@ -402,12 +560,12 @@ int gen_grad(hipStream_t s, const DevGeneral &P, int prec, const SolverState *st
              const double *ytil, void *const *gring, void *const *dring, int T, int64_t ld, double *partials,
              int force_slot, int *nb, double cs) {
     if (prec == LRSDP_F64) {
-        GenSpmmArgs<double> a{(const double *)R, nullptr, ytil, cs, ld, st, force_slot, {}, partials};
+        GenSpmmArgs<double> a{(const double *)R, nullptr, ytil, cs, ld, st, force_slot, {}, partials, nullptr};
         for (int g = 0; g <= T; ++g) a.rings.g[g] = (double *)gring[g];
         for (int d = 0; d < T; ++d) a.rings.d[d] = (double *)dring[d];
         return gen_spmm_t<double, true>(s, P, a, nb, T);
     }
-    GenSpmmArgs<float> a{(const float *)R, nullptr, ytil, cs, ld, st, force_slot, {}, partials};
+    GenSpmmArgs<float> a{(const float *)R, nullptr, ytil, cs, ld, st, force_slot, {}, partials, nullptr};
     for (int g = 0; g <= T; ++g) a.rings.g[g] = (float *)gring[g];
     for (int d = 0; d < T; ++d) a.rings.d[d] = (float *)dring[d];
     return gen_spmm_t<float, true>(s, P, a, nb, T);

@@ -88,6 +88,17 @@ struct DevCompletion {
 // whole workgroup (a trace constraint spans n positions).
 constexpr int kLongRow = 512;
 
+// Dense C of a general problem: largest order accepted, largest order chosen
+// automatically, the fraction of nonzero upper-triangle positions from which
+// the automatic choice takes dense storage, the bytes per row of the dense
+// product and its split-k partials (64 float64 columns: ld <= 32 in float64,
+// <= 64 in float32), and the largest k split.
+constexpr int64_t kDenseMaxN = 16384;
+constexpr int64_t kDenseAutoN = 8192;
+constexpr double kDenseFrac = 0.1;
+constexpr size_t kDenseRowBytes = 64 * sizeof(double);
+constexpr int kDenseMaxSplit = 8;
+
 // General problem (Section 3.4 compression).  Omega: positions (a, b), a <= b,
 // that are nonzero in C or in some A_k; the stacked constraint matrix keeps
 // only its nonzero columns, indexed by position in Omega.
@@ -108,6 +119,10 @@ struct DevGeneral {
     const int32_t *con_short = nullptr; // constraints whose row has <= kLongRow entries (a thread each)
     const int32_t *con_long = nullptr;  // the longer ones (a workgroup each)
     int64_t n_short = 0, n_long = 0;
+    // Dense storage of C (Section 3.5, last paragraph; null with sparse storage):
+    const double *cd = nullptr;         // n x n, row-major, both triangles
+    double *dw = nullptr;               // n rows of kDenseRowBytes: the dense product cs C V
+    double *dpart = nullptr;            // kDenseMaxSplit x n rows of kDenseRowBytes: split-k partials
     double *x1 = nullptr;               // |Omega| compressed outer products, and (x2) the values of
     double *x2 = nullptr;               // C - A*(y) for the SpMM (problem-owned scratch: calls on one
                                         // problem must not overlap)
@@ -130,7 +145,7 @@ struct lrsdp_problem {
     std::vector<int32_t> top_ptr, top_col, top_eid, bot_ptr, bot_row, bot_eid, samp_i, samp_j;
     std::vector<double> b;
     std::vector<int32_t> om_a, om_b, a_ptr, a_idx, at_ptr, at_idx, s_ptr, s_col, s_om, con_short, con_long;
-    std::vector<double> cval, a_val, at_val;
+    std::vector<double> cval, a_val, at_val, cdense;
     // device views (valid after upload)
     lrsdp::DevCsr csr;
     lrsdp::DevCompletion cmp;

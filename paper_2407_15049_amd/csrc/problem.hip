@@ -310,13 +310,18 @@ extern "C" int lrsdp_problem_get_info(const lrsdp_problem *prob, lrsdp_problem_i
     return LRSDP_OK;
 }
 
-extern "C" int lrsdp_problem_general(int64_t n, int64_t c_nnz, const int32_t *c_row, const int32_t *c_col,
-                                     const double *c_val, int64_t m, int64_t a_nnz, const int32_t *a_con,
-                                     const int32_t *a_row, const int32_t *a_col, const double *a_val,
-                                     const double *b, lrsdp_problem **out) {
+extern "C" int lrsdp_problem_general_ex(int64_t n, int64_t c_nnz, const int32_t *c_row, const int32_t *c_col,
+                                        const double *c_val, int64_t m, int64_t a_nnz, const int32_t *a_con,
+                                        const int32_t *a_row, const int32_t *a_col, const double *a_val,
+                                        const double *b, int c_storage, lrsdp_problem **out) {
     clear_error();
     if (!out) return set_error(LRSDP_EINVAL, "out is NULL");
     *out = nullptr;
+    if (c_storage != LRSDP_C_AUTO && c_storage != LRSDP_C_SPARSE && c_storage != LRSDP_C_DENSE)
+        return set_error(LRSDP_EINVAL, "c_storage = %d", c_storage);
+    if (c_storage == LRSDP_C_DENSE && n > kDenseMaxN)
+        return set_error(LRSDP_EINVAL, "dense C storage is for n <= %lld (n = %lld)", (long long)kDenseMaxN,
+                         (long long)n);
     if (n < 1 || n > INT32_MAX - 1) return set_error(LRSDP_EINVAL, "n = %lld out of range", (long long)n);
     if (m < 1 || m > INT32_MAX - 1) return set_error(LRSDP_EINVAL, "m = %lld out of range", (long long)m);
     if (c_nnz < 0 || a_nnz < 0 || a_nnz > INT32_MAX) return set_error(LRSDP_EINVAL, "bad entry counts");
@@ -363,10 +368,17 @@ extern "C" int lrsdp_problem_general(int64_t n, int64_t c_nnz, const int32_t *c_
         if (!as.empty() && as.back().k == e.k && as.back().pos == e.pos) as.back().v += e.v;
         else as.push_back(e);
     }
-    // Omega = positions of C and of the nonzero columns of the stacked matrix
+    // Storage of C (Section 3.5, last paragraph): a small C with many nonzeros
+    // is kept as a dense n x n matrix applied by a dense product; then Omega
+    // holds the nonzero columns of the stacked constraint matrix only.
+    const double tri = 0.5 * (double)n * (double)(n + 1);
+    const bool dense = c_storage == LRSDP_C_DENSE ||
+                       (c_storage == LRSDP_C_AUTO && n <= kDenseAutoN && (double)cs.size() >= kDenseFrac * tri);
+    // Omega = positions of C (sparse storage) and of the nonzero columns of the stacked matrix
     std::vector<int64_t> om;
-    om.reserve(cs.size() + as.size());
-    for (const auto &e : cs) om.push_back(e.first);
+    om.reserve((dense ? 0 : cs.size()) + as.size());
+    if (!dense)
+        for (const auto &e : cs) om.push_back(e.first);
     for (const auto &e : as) om.push_back(e.pos);
     std::sort(om.begin(), om.end());
     om.erase(std::unique(om.begin(), om.end()), om.end());
@@ -382,10 +394,20 @@ extern "C" int lrsdp_problem_general(int64_t n, int64_t c_nnz, const int32_t *c_
         p->om_b[o] = (int32_t)(om[o] % n);
     }
     double c_l1 = 0.0;
-    for (const auto &e : cs) {
-        const int32_t o = idx(e.first);
-        p->cval[o] = e.second;
-        c_l1 += (p->om_a[o] == p->om_b[o] ? 1.0 : 2.0) * std::fabs(e.second);
+    if (dense) {
+        p->cdense.assign((size_t)n * (size_t)n, 0.0);
+        for (const auto &e : cs) {
+            const int64_t a = e.first / n, bb = e.first % n;
+            p->cdense[(size_t)a * n + bb] = e.second;
+            p->cdense[(size_t)bb * n + a] = e.second;
+            c_l1 += (a == bb ? 1.0 : 2.0) * std::fabs(e.second);
+        }
+    } else {
+        for (const auto &e : cs) {
+            const int32_t o = idx(e.first);
+            p->cval[o] = e.second;
+            c_l1 += (p->om_a[o] == p->om_b[o] ? 1.0 : 2.0) * std::fabs(e.second);
+        }
     }
     // stacked constraint matrix by constraint rows (sorted by Omega index)
     p->a_ptr.assign(m + 1, 0);
@@ -453,12 +475,21 @@ extern "C" int lrsdp_problem_general(int64_t n, int64_t c_nnz, const int32_t *c_
     I.m = m;
     I.nnz = (int64_t)se.size();
     I.weights = kWGeneral;
+    I.c_dense = dense ? 1 : 0;
     I.max_row_nnz = max_row;
     I.c_l1 = c_l1;
     I.b_l1 = b_l1;
     I.b_inf = b_inf;
     *out = p;
     return LRSDP_OK;
+}
+
+extern "C" int lrsdp_problem_general(int64_t n, int64_t c_nnz, const int32_t *c_row, const int32_t *c_col,
+                                     const double *c_val, int64_t m, int64_t a_nnz, const int32_t *a_con,
+                                     const int32_t *a_row, const int32_t *a_col, const double *a_val,
+                                     const double *b, lrsdp_problem **out) {
+    return lrsdp_problem_general_ex(n, c_nnz, c_row, c_col, c_val, m, a_nnz, a_con, a_row, a_col, a_val, b,
+                                    LRSDP_C_AUTO, out);
 }
 
 extern "C" int lrsdp_problem_general_blocks(int64_t nblocks, const int64_t *block_n, int64_t c_nnz,
@@ -549,6 +580,9 @@ size_t plan_device(const lrsdp_problem *p, size_t *offs) {
         add(p->om_a.size() * 8);
         add(p->con_short.size() * 4);
         add(p->con_long.size() * 4);
+        add(p->cdense.size() * 8);                                      // dense C
+        add(p->cdense.empty() ? 0 : (size_t)p->info.n * kDenseRowBytes);  // dense product, one row per node
+        add(p->cdense.empty() ? 0 : (size_t)kDenseMaxSplit * p->info.n * kDenseRowBytes);  // split-k partials
     } else {
         add(p->top_ptr.size() * 4);
         add(p->top_col.size() * 4);
@@ -647,6 +681,10 @@ extern "C" int lrsdp_problem_upload(lrsdp_ctx *ctx, lrsdp_problem *p, void *dev,
         LRSDP_HIP_TRY(put(offs[16], p->con_long.data(), p->con_long.size() * 4));
         g.con_short = (const int32_t *)(base + offs[15]);
         g.con_long = (const int32_t *)(base + offs[16]);
+        LRSDP_HIP_TRY(put(offs[17], p->cdense.data(), p->cdense.size() * 8));
+        g.cd = p->cdense.empty() ? nullptr : (const double *)(base + offs[17]);
+        g.dw = p->cdense.empty() ? nullptr : (double *)(base + offs[18]);
+        g.dpart = p->cdense.empty() ? nullptr : (double *)(base + offs[19]);
         g.n_short = (int64_t)p->con_short.size();
         g.n_long = (int64_t)p->con_long.size();
         g.n = p->info.n;

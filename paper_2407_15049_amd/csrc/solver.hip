@@ -1371,7 +1371,11 @@ extern "C" int lrsdp_warmstart(lrsdp_ctx *c, const lrsdp_problem *p, const void 
     const double mean = n > 0 ? hsum[0] / (double)n : 0.0;
     if (!std::isfinite(mean) || !std::isfinite(hsum[1]))
         return set_error(LRSDP_ENUMERIC, "warm-start prediction is not finite");
-    *sigma0 = default_sigma0(p) * std::exp(std::max(log_ratio_lo, std::min(log_ratio_hi, mean)));
+    // the network predicts log(final penalty / default) of a cold solve; the
+    // warm start begins halfway there on the log scale, leaving the penalty
+    // rule room to raise it (starting at the final penalty made the first
+    // subproblems too stiff to solve within their iteration limit)
+    *sigma0 = default_sigma0(p) * std::exp(0.5 * std::max(log_ratio_lo, std::min(log_ratio_hi, mean)));
     return LRSDP_OK;
 }
 

@@ -35,11 +35,47 @@ __device__ __forceinline__ float edge_w(const DevCsr &P, int e, int32_t c) {
     else return (float)(4.0 * P.val[e]);
 }
 
+// The 16 features of one node from its stats and neighbour sums (sl = sum of
+// l_j - l_i, sl2 = its squares, swb = sum w_ij b_j, sinv = sum 1/(1+d_j),
+// sw = sum w_ij, sdd = sum d_j/(d_i+d_j), lmax = max l_j).
+__device__ __forceinline__ void write_features(const float4 si, int deg, double sl, double sl2, double swb,
+                                               double sinv, double sw, double sdd, float lmax, float dbar,
+                                               float logn20, float *out) {
+    const float d = si.x, a = si.z, l = si.w;
+    float f[kNF];
+    f[0] = l;
+    f[1] = si.y / fmaxf(a, 1.f);
+    f[2] = log1pf(a);
+    f[7] = dbar > 0.f ? log1pf(d / dbar) : 0.f;
+    f[8] = 1.f / (1.f + d);
+    f[9] = a / fmaxf(d, 1.f);
+    f[11] = logn20;
+    f[12] = log1pf(dbar);
+    f[15] = 1.f;
+    if (deg > 0) {
+        const double inv = 1.0 / (double)deg;
+        const double ml = sl * inv;  // mean of l_j - l_i
+        f[3] = (float)((double)l + ml);
+        f[4] = (float)sqrt(fmax(sl2 * inv - ml * ml, 0.0));
+        f[5] = (float)(swb * inv);
+        f[6] = (float)(sinv * inv);
+        f[10] = (float)(sw * inv);
+        f[13] = lmax - l;
+        f[14] = (float)(sdd * inv);
+    } else {
+        f[3] = f[4] = f[5] = f[6] = f[10] = f[13] = f[14] = 0.f;
+    }
+#pragma unroll
+    for (int q = 0; q < kNF; q += 4)
+        *reinterpret_cast<float4 *>(out + q) = make_float4(f[q], f[q + 1], f[q + 2], f[q + 3]);
+}
+
 // pass 1: per-node (d, s, a, l)
 template <int W>
 __global__ __launch_bounds__(kBlock) void k_node_stats(DevCsr P, float4 *stats) {
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < P.n; i += (int64_t)gridDim.x * kBlock) {
         const int b = P.row_ptr[i], e = P.row_ptr[i + 1];
+        if (e - b > kSegLen) continue;   // hub rows: k_node_stats_heavy
         double s = 0.0, a = 0.0;
         for (int k = b; k < e; ++k) {
             const double w = edge_w<W>(P, k, P.col[k]);
@@ -56,10 +92,10 @@ template <int W>
 __global__ __launch_bounds__(kBlock) void k_features(DevCsr P, const float4 *stats, float dbar, float logn20,
                                                      float *F) {
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < P.n; i += (int64_t)gridDim.x * kBlock) {
-        const float4 si = stats[i];
-        const float d = si.x, a = si.z, l = si.w;
-        const float bal = si.y / fmaxf(a, 1.f);
         const int b = P.row_ptr[i], e = P.row_ptr[i + 1];
+        if (e - b > kSegLen) continue;   // hub rows: k_features_heavy
+        const float4 si = stats[i];
+        const float d = si.x, l = si.w;
         // Neighbour sums in double: the spread feature (std of l over the
         // neighbours) cancels badly in float for hubs whose neighbours have
         // near-equal degrees.  This pass runs once per graph.
@@ -78,32 +114,92 @@ __global__ __launch_bounds__(kBlock) void k_features(DevCsr P, const float4 *sta
             lmax = fmaxf(lmax, sj.w);
             sdd += (double)sj.x / ((double)d + (double)sj.x);
         }
-        float f[kNF];
-        f[0] = l;
-        f[1] = bal;
-        f[2] = log1pf(a);
-        f[7] = dbar > 0.f ? log1pf(d / dbar) : 0.f;
-        f[8] = 1.f / (1.f + d);
-        f[9] = a / fmaxf(d, 1.f);
-        f[11] = logn20;
-        f[12] = log1pf(dbar);
-        f[15] = 1.f;
-        if (e > b) {
-            const double inv = 1.0 / (double)(e - b);
-            const double ml = sl * inv;  // mean of l_j - l_i
-            f[3] = (float)((double)l + ml);
-            f[4] = (float)sqrt(fmax(sl2 * inv - ml * ml, 0.0));
-            f[5] = (float)(swb * inv);
-            f[6] = (float)(sinv * inv);
-            f[10] = (float)(sw * inv);
-            f[13] = lmax - l;
-            f[14] = (float)(sdd * inv);
-        } else {
-            f[3] = f[4] = f[5] = f[6] = f[10] = f[13] = f[14] = 0.f;
+        write_features(si, e - b, sl, sl2, swb, sinv, sw, sdd, lmax, dbar, logn20, F + i * kNF);
+    }
+}
+
+// One workgroup per hub row (more than kSegLen neighbours): the threads stride
+// over the neighbours, the sums go through a fixed wavefront / LDS tree.
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_node_stats_heavy(DevCsr P, float4 *stats) {
+    __shared__ double sh[kBlock / 64][2];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int64_t h = blockIdx.x; h < P.n_heavy; h += gridDim.x) {
+        const int64_t i = P.heavy[h];
+        const int b = P.row_ptr[i], e = P.row_ptr[i + 1];
+        double s = 0.0, a = 0.0;
+        for (int k = b + threadIdx.x; k < e; k += kBlock) {
+            const double w = edge_w<W>(P, k, P.col[k]);
+            s += w;
+            a += fabs(w);
+        }
+        s = wave_sum(s);
+        a = wave_sum(a);
+        __syncthreads();
+        if (lane == 0) {
+            sh[wave][0] = s;
+            sh[wave][1] = a;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double ts = 0.0, ta = 0.0;
+#pragma unroll
+            for (int q = 0; q < kBlock / 64; ++q) {
+                ts += sh[q][0];
+                ta += sh[q][1];
+            }
+            stats[i] = make_float4((float)(e - b), (float)ts, (float)ta, (float)log1p((double)(e - b)));
+        }
+    }
+}
+
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_features_heavy(DevCsr P, const float4 *stats, float dbar, float logn20,
+                                                           float *F) {
+    __shared__ double sh[kBlock / 64][6];
+    __shared__ float shm[kBlock / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int64_t h = blockIdx.x; h < P.n_heavy; h += gridDim.x) {
+        const int64_t i = P.heavy[h];
+        const int b = P.row_ptr[i], e = P.row_ptr[i + 1];
+        const float4 si = stats[i];
+        const float d = si.x, l = si.w;
+        double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // sl, sl2, swb, sinv, sw, sdd
+        float lmax = -1e30f;
+        for (int k = b + threadIdx.x; k < e; k += kBlock) {
+            const int32_t c = P.col[k];
+            const double w = edge_w<W>(P, k, c);
+            const float4 sj = stats[c & 0x7fffffff];
+            const double lj = (double)sj.w - (double)l;
+            v[0] += lj;
+            v[1] += lj * lj;
+            v[2] += w * (double)(sj.y / fmaxf(sj.z, 1.f));
+            v[3] += 1.0 / (1.0 + (double)sj.x);
+            v[4] += w;
+            lmax = fmaxf(lmax, sj.w);
+            v[5] += (double)sj.x / ((double)d + (double)sj.x);
         }
 #pragma unroll
-        for (int q = 0; q < kNF; q += 4)
-            *reinterpret_cast<float4 *>(F + i * kNF + q) = make_float4(f[q], f[q + 1], f[q + 2], f[q + 3]);
+        for (int q = 0; q < 6; ++q) v[q] = wave_sum(v[q]);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) lmax = fmaxf(lmax, __shfl_xor(lmax, o, 64));
+        __syncthreads();
+        if (lane == 0) {
+#pragma unroll
+            for (int q = 0; q < 6; ++q) sh[wave][q] = v[q];
+            shm[wave] = lmax;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            float tm = -1e30f;
+            for (int w = 0; w < kBlock / 64; ++w) {
+#pragma unroll
+                for (int q = 0; q < 6; ++q) t[q] += sh[w][q];
+                tm = fmaxf(tm, shm[w]);
+            }
+            write_features(si, e - b, t[0], t[1], t[2], t[3], t[4], t[5], tm, dbar, logn20, F + i * kNF);
+        }
     }
 }
 
@@ -367,18 +463,26 @@ int ws_features(hipStream_t s, const DevCsr &P, float *F, float4 *stats) {
     const int nb = blocks_for(P.n);
     const float dbar = P.n > 0 ? (float)((double)P.nnz / (double)P.n) : 0.f;
     const float logn20 = (float)(std::log((double)P.n) / 20.0);
+    const int nh = (int)std::max<int64_t>(1, std::min<int64_t>(P.n_heavy, kMaxBlocks));
     switch (P.wmode) {
         case kWUnit:
             hipLaunchKernelGGL(k_node_stats<kWUnit>, dim3(nb), dim3(kBlock), 0, s, P, stats);
+            hipLaunchKernelGGL(k_node_stats_heavy<kWUnit>, dim3(nh), dim3(kBlock), 0, s, P, stats);
             hipLaunchKernelGGL(k_features<kWUnit>, dim3(nb), dim3(kBlock), 0, s, P, stats, dbar, logn20, F);
+            hipLaunchKernelGGL(k_features_heavy<kWUnit>, dim3(nh), dim3(kBlock), 0, s, P, stats, dbar, logn20, F);
             break;
         case kWSign:
             hipLaunchKernelGGL(k_node_stats<kWSign>, dim3(nb), dim3(kBlock), 0, s, P, stats);
+            hipLaunchKernelGGL(k_node_stats_heavy<kWSign>, dim3(nh), dim3(kBlock), 0, s, P, stats);
             hipLaunchKernelGGL(k_features<kWSign>, dim3(nb), dim3(kBlock), 0, s, P, stats, dbar, logn20, F);
+            hipLaunchKernelGGL(k_features_heavy<kWSign>, dim3(nh), dim3(kBlock), 0, s, P, stats, dbar, logn20, F);
             break;
         default:
             hipLaunchKernelGGL(k_node_stats<kWGeneral>, dim3(nb), dim3(kBlock), 0, s, P, stats);
+            hipLaunchKernelGGL(k_node_stats_heavy<kWGeneral>, dim3(nh), dim3(kBlock), 0, s, P, stats);
             hipLaunchKernelGGL(k_features<kWGeneral>, dim3(nb), dim3(kBlock), 0, s, P, stats, dbar, logn20, F);
+            hipLaunchKernelGGL(k_features_heavy<kWGeneral>, dim3(nh), dim3(kBlock), 0, s, P, stats, dbar, logn20,
+                               F);
     }
     LRSDP_CHECK_LAUNCH();
     return LRSDP_OK;

@@ -22,6 +22,7 @@ OK, NOT_CONVERGED = 0, 1
 EINVAL, ENOMEM, EHIP, ENUMERIC, EUNSUPPORTED = -1, -2, -3, -4, -5
 F64, F32, F32_BF16IN = 0, 1, 2
 MAXCUT, COMPLETION, GENERAL = 1, 2, 3
+C_AUTO, C_SPARSE, C_DENSE = 0, 1, 2
 
 
 class LrsdpUnavailable(ImportError):
@@ -67,7 +68,7 @@ class ProblemInfo(C.Structure):
     _fields_ = [
         ("kind", C.c_int), ("n", C.c_int64), ("m", C.c_int64), ("nnz", C.c_int64),
         ("n1", C.c_int64), ("n2", C.c_int64), ("weights", C.c_int), ("max_row_nnz", C.c_int64),
-        ("c_l1", C.c_double), ("b_l1", C.c_double), ("b_inf", C.c_double),
+        ("c_l1", C.c_double), ("b_l1", C.c_double), ("b_inf", C.c_double), ("c_dense", C.c_int),
     ]
 
 
@@ -92,6 +93,8 @@ _SIGS = {
     "lrsdp_problem_maxcut": (C.c_int, [_I64, _I64, _P, _P, _P, C.POINTER(_P)]),
     "lrsdp_problem_completion": (C.c_int, [_I64, _I64, _I64, _P, _P, _P, C.POINTER(_P)]),
     "lrsdp_problem_general": (C.c_int, [_I64, _I64, _P, _P, _P, _I64, _I64, _P, _P, _P, _P, _P, C.POINTER(_P)]),
+    "lrsdp_problem_general_ex": (C.c_int, [_I64, _I64, _P, _P, _P, _I64, _I64, _P, _P, _P, _P, _P, C.c_int,
+                                           C.POINTER(_P)]),
     "lrsdp_problem_general_blocks": (C.c_int, [_I64, _P, _I64, _P, _P, _P, _P, _I64, _I64, _P, _P, _P, _P, _P, _P,
                                                C.POINTER(_P)]),
     "lrsdp_problem_destroy": (None, [_P]),
@@ -242,9 +245,10 @@ class Problem:
         return cls(h)
 
     @classmethod
-    def general(cls, n, c_row, c_col, c_val, m, a_con, a_row, a_col, a_val, b):
+    def general(cls, n, c_row, c_col, c_val, m, a_con, a_row, a_col, a_val, b, c_storage=None):
         """min <C, X> s.t. <A_k, X> = b_k: C and the A_k as triplets, each
-        off-diagonal entry given once (it stands for both (r, c) and (c, r))."""
+        off-diagonal entry given once (it stands for both (r, c) and (c, r)).
+        c_storage: None (automatic), C_SPARSE or C_DENSE."""
         lib = load()
         cr, crp = _host(c_row, np.int32)
         cc, ccp = _host(c_col, np.int32)
@@ -257,8 +261,8 @@ class Problem:
         if not (len(cr) == len(cc) == len(cv)) or not (len(ak) == len(ar) == len(ac) == len(av)) or len(bb) != m:
             raise ValueError("triplet arrays of different lengths, or len(b) != m")
         h = C.c_void_p()
-        _check(lib.lrsdp_problem_general(int(n), len(cr), crp, ccp, cvp, int(m), len(ak), akp, arp, acp, avp, bp,
-                                         C.byref(h)))
+        _check(lib.lrsdp_problem_general_ex(int(n), len(cr), crp, ccp, cvp, int(m), len(ak), akp, arp, acp, avp, bp,
+                                            C_AUTO if c_storage is None else int(c_storage), C.byref(h)))
         return cls(h)
 
     @classmethod

@@ -217,3 +217,29 @@ def test_general_blocks_build_and_validation():
     with pytest.raises(L.LrsdpError) as e:
         L.Problem.general_blocks(block_n, c_blk, c_row, c_col, c_val, m, a_con, a_blk, bad_row, a_col, a_val, b)
     assert e.value.code == L.EINVAL
+
+
+def test_general_dense_storage_choice_and_validation():
+    from synth import random_general_triplets, theta_triplets
+    from synth import petersen_edges
+    u, v = petersen_edges()
+    t = theta_triplets(10, u, v)                       # C = -J: every position nonzero
+    auto = L.Problem.general(10, *t)
+    sparse = L.Problem.general(10, *t, c_storage=L.C_SPARSE)
+    dense = L.Problem.general(10, *t, c_storage=L.C_DENSE)
+    assert auto.info.c_dense == 1 and dense.info.c_dense == 1 and sparse.info.c_dense == 0
+    # dense storage: Omega keeps the constraint positions only (trace: 10 diagonal, edges: 15),
+    # and the device image holds the n x n matrix
+    assert dense.info.nnz == 10 + 2 * 15 and sparse.info.nnz == 10 * 10
+    assert dense.device_bytes() >= sparse.device_bytes() - 8 * 100 + 8 * 10 * 10
+    assert dense.info.c_l1 == sparse.info.c_l1
+    cr, cc, cv, m, ak, ar, ac, av, W = random_general_triplets(40, 25, 3, 60, 2, 9)
+    b = np.zeros(m)
+    assert L.Problem.general(40, cr, cc, cv, m, ak, ar, ac, av, b).info.c_dense == 0   # 60 of 820
+    with pytest.raises(L.LrsdpError) as e:
+        L.Problem.general(40, cr, cc, cv, m, ak, ar, ac, av, b, c_storage=7)
+    assert e.value.code == L.EINVAL
+    big = 16385
+    with pytest.raises(L.LrsdpError) as e:
+        L.Problem.general(big, [0], [1], [1.0], 1, [0], [0], [0], [1.0], [1.0], c_storage=L.C_DENSE)
+    assert e.value.code == L.EINVAL and "dense" in str(e.value)

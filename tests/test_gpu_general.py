@@ -1,5 +1,7 @@
 """GPU parity of the general-problem path (Section 3.4 compression) against the
-FP64 oracle, whose general problem is the plain full-matrix definition.
+FP64 oracle, whose general problem is the plain full-matrix definition.  Each
+per-kernel case runs with C stored on Omega and with C stored densely (Section
+3.5, last paragraph: the dense product on float64 matrix cores).
 
 Per kernel, the float64 outputs agree with the oracle within 1e-12 (maps) or
 1e-10 (reductions) of the sum of absolute values of their terms.  Float32
@@ -71,19 +73,33 @@ def case_data(case):
 CASES = ["theta_petersen", "theta_dense", "random_small", "random_ragged", "long_rows"]
 
 
-def setup(ctx, case):
+STORAGE = [L.C_SPARSE, L.C_DENSE]
+
+
+def setup(ctx, case, storage=None):
     n, t, r = case_data(case)
-    prob = L.Problem.general(n, *t).upload(ctx)
+    prob = L.Problem.general(n, *t, c_storage=storage).upload(ctx)
+    if storage is not None:
+        assert prob.info.c_dense == (storage == L.C_DENSE)
     op = general_problem(n, *t)
     return prob, op, r
 
 
+def test_automatic_storage_choice(ctx):
+    # dense when n <= 8192 and at least 10% of the upper triangle of C is nonzero
+    assert setup(ctx, "theta_dense")[0].info.c_dense == 1       # C = -J
+    assert setup(ctx, "theta_petersen")[0].info.c_dense == 1
+    assert setup(ctx, "random_ragged")[0].info.c_dense == 0     # 6000 of 2e6 positions
+    assert setup(ctx, "random_small")[0].info.c_dense == 0      # 120 of 1830
+
+
+@pytest.mark.parametrize("storage", STORAGE)
 @pytest.mark.parametrize("prec", [L.F64, L.F32])
 @pytest.mark.parametrize("case", CASES)
-def test_spmm_parity(ctx, case, prec):
+def test_spmm_parity(ctx, case, prec, storage):
     import torch
-    prob, op, r = setup(ctx, case)
-    print_case(test="gen_spmm", case=case, prec=prec)
+    prob, op, r = setup(ctx, case, storage)
+    print_case(test="gen_spmm", case=case, prec=prec, storage=storage)
     rng = np.random.default_rng(1)
     V = rounded(rng.standard_normal((op.n, r)), prec)
     ytil = rng.standard_normal(op.m)
@@ -98,12 +114,13 @@ def test_spmm_parity(ctx, case, prec):
     assert np.all(np.abs(Y[:, :r] - ref) <= TOL[prec] * bound + 1e-300)
 
 
+@pytest.mark.parametrize("storage", STORAGE)
 @pytest.mark.parametrize("prec", [L.F64, L.F32])
 @pytest.mark.parametrize("case", CASES)
-def test_constraint_map_parity(ctx, case, prec):
+def test_constraint_map_parity(ctx, case, prec, storage):
     import torch
-    prob, op, r = setup(ctx, case)
-    print_case(test="gen_constraint", case=case, prec=prec)
+    prob, op, r = setup(ctx, case, storage)
+    print_case(test="gen_constraint", case=case, prec=prec, storage=storage)
     rng = np.random.default_rng(2)
     U = rounded(rng.standard_normal((op.n, r)), prec)
     V = rounded(rng.standard_normal((op.n, r)), prec)
@@ -115,12 +132,13 @@ def test_constraint_map_parity(ctx, case, prec):
     assert np.all(np.abs(out.cpu().numpy() - ref) <= 1e-12 * bound + 1e-300)
 
 
+@pytest.mark.parametrize("storage", STORAGE)
 @pytest.mark.parametrize("prec", [L.F64, L.F32])
 @pytest.mark.parametrize("case", CASES)
-def test_linesearch_coeffs_parity(ctx, case, prec):
+def test_linesearch_coeffs_parity(ctx, case, prec, storage):
     import torch
-    prob, op, r = setup(ctx, case)
-    print_case(test="gen_ls", case=case, prec=prec)
+    prob, op, r = setup(ctx, case, storage)
+    print_case(test="gen_ls", case=case, prec=prec, storage=storage)
     rng = np.random.default_rng(3)
     R = rounded(rng.standard_normal((op.n, r)) / np.sqrt(r), prec)
     D = rounded(rng.standard_normal((op.n, r)) * 0.1, prec)
@@ -157,12 +175,13 @@ def test_linesearch_coeffs_parity(ctx, case, prec):
         assert abs(g[idx] - c[name]) <= tol * bounds[name] + 1e-300, (name, g[idx], c[name])
 
 
+@pytest.mark.parametrize("storage", STORAGE)
 @pytest.mark.parametrize("prec", [L.F64, L.F32])
 @pytest.mark.parametrize("case", CASES)
-def test_alm_step_parity(ctx, case, prec):
+def test_alm_step_parity(ctx, case, prec, storage):
     import torch
-    prob, op, r = setup(ctx, case)
-    print_case(test="gen_alm", case=case, prec=prec)
+    prob, op, r = setup(ctx, case, storage)
+    print_case(test="gen_alm", case=case, prec=prec, storage=storage)
     rng = np.random.default_rng(4)
     R = rounded(rng.standard_normal((op.n, r)) / np.sqrt(r), prec)
     y = rng.standard_normal(op.m)
@@ -195,17 +214,18 @@ def gpu_solve(ctx, prob, R0, prec, m, **kw):
     return rc, res, host(Rd, r), yd.cpu().numpy()
 
 
+@pytest.mark.parametrize("storage", STORAGE)
 @pytest.mark.parametrize("graph", ["C5", "C7", "petersen"])
-def test_theta_closed_forms(ctx, graph):
+def test_theta_closed_forms(ctx, graph, storage):
     if graph == "petersen":
         n, (u, v), want = 10, petersen_edges(), 4.0
     else:
         n = int(graph[1:])
         c = math.cos(math.pi / n)
         (u, v), want = cycle_edges(n), n * c / (1 + c)
-    print_case(test="theta", graph=graph)
+    print_case(test="theta", graph=graph, storage=storage)
     t = theta_triplets(n, u, v)
-    prob = L.Problem.general(n, *t).upload(ctx)
+    prob = L.Problem.general(n, *t, c_storage=storage).upload(ctx)
     op = general_problem(n, *t)
     R0 = init_factor(n, 6, 3)
     rc, res, R, y = gpu_solve(ctx, prob, R0, L.F64, op.m, tol=1e-8)
@@ -218,10 +238,11 @@ def test_theta_closed_forms(ctx, graph):
     assert abs(m["obj"] - res.obj) <= 1e-10 * want
 
 
+@pytest.mark.parametrize("storage", STORAGE)
 @pytest.mark.parametrize("prec", [L.F64, L.F32])
-def test_random_general_solve_matches_oracle(ctx, prec):
-    prob, op, r = setup(ctx, "random_small")
-    print_case(test="gen_solve", case="random_small", prec=prec)
+def test_random_general_solve_matches_oracle(ctx, prec, storage):
+    prob, op, r = setup(ctx, "random_small", storage)
+    print_case(test="gen_solve", case="random_small", prec=prec, storage=storage)
     R0 = init_factor(op.n, r, 4)
     rc, res, R, y = gpu_solve(ctx, prob, R0, prec, op.m)
     ores = alm_solve(op, R0, opts=OOptions())
@@ -288,9 +309,10 @@ def test_maxcut_as_general_matches_maxcut_path(ctx):
     assert abs(resg.obj - ores.obj) <= 1e-5 * abs(ores.obj)
 
 
-def test_general_certificate_parity(ctx):
-    prob, op, r = setup(ctx, "theta_dense")
-    print_case(test="gen_certify", case="theta_dense")
+@pytest.mark.parametrize("storage", STORAGE)
+def test_general_certificate_parity(ctx, storage):
+    prob, op, r = setup(ctx, "theta_dense", storage)
+    print_case(test="gen_certify", case="theta_dense", storage=storage)
     y = np.random.default_rng(9).standard_normal(op.m)
     scale = float(abs(op.C - op.A_adj(y)).sum(axis=1).max())
     cert = L.certify(ctx, prob, dev_vec(y), max_iter=300, tol=1e-9 * scale)

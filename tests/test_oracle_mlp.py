@@ -102,7 +102,8 @@ def test_warm_start_limits():
     absdeg = np.array([4.0, 8.0, 2.0])
     # t limited to [-2, 2]: (2, -2, 1) -> y0 = -t a / 4 = (-2, 4, -0.5)
     assert np.array_equal(mlp.multipliers_from_output(out, absdeg), [-2.0, 4.0, -0.5])
-    # mean second output = -1.5: inside [-2, 1] it stays, [-1, 1] lifts it to -1
-    assert np.isclose(mlp.initial_penalty(out, 10.0, -2.0, 1.0), 10.0 * np.exp(-1.5))
-    assert np.isclose(mlp.initial_penalty(out, 10.0, -1.0, 1.0), 10.0 * np.exp(-1.0))
+    # mean second output = -1.5: inside [-2, 1] it stays, [-1, 1] lifts it to -1; half of it
+    # on the log scale: sigma0 = 10 exp(-0.75) and 10 exp(-0.5)
+    assert np.isclose(mlp.initial_penalty(out, 10.0, -2.0, 1.0), 10.0 * np.exp(-0.75))
+    assert np.isclose(mlp.initial_penalty(out, 10.0, -1.0, 1.0), 10.0 * np.exp(-0.5))
     assert np.isclose(mlp.sigma_label(40.0, 10.0), np.log(4.0))
