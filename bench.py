@@ -448,7 +448,6 @@ def cert_of(args, ctx, dev, L, run, y, obj):
 
 
 TRAFFIC_PROFILES = {
-    "pair_1m": "spmm_maxcut_traffic_pair_1m_f64.md",
     "cl_10m": "spmm_maxcut_traffic_cl_10m_f64.md",
 }
 SPMM_SOURCES = [os.path.join(ROOT, "paper_2407_15049_amd", "csrc", f)
