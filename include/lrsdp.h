@@ -97,6 +97,22 @@ int lrsdp_problem_maxcut(int64_t n, int64_t n_edges, const int32_t *u,
                          const int32_t *v, const double *w,
                          lrsdp_problem **out);
 
+/* Node order of a MaxCut problem (an implementation choice; the paper leaves
+ * the order to the input).  LRSDP_ORDER_INPUT keeps the caller's labels
+ * (lrsdp_problem_maxcut).  LRSDP_ORDER_DEGREE relabels the nodes inside the
+ * library by decreasing degree, ties by increasing label: the rows of the factor
+ * that the SpMM gathers most often then share cache lines.  The problem is the
+ * same up to a symmetric permutation, so results agree with the input order up
+ * to rounding.  lrsdp_solve, lrsdp_certify, lrsdp_warmstart, lrsdp_ws_features
+ * and lrsdp_ws_targets take and return every per-node array (R, y, y0, features)
+ * in the caller's labels; the per-kernel entry points (lrsdp_k_*) work in the
+ * library's order and return EUNSUPPORTED for such a problem.  Arguments and
+ * errors otherwise as lrsdp_problem_maxcut (EINVAL for another node_order). */
+#define LRSDP_ORDER_INPUT  0
+#define LRSDP_ORDER_DEGREE 1
+int lrsdp_problem_maxcut_ex(int64_t n, int64_t n_edges, const int32_t *u, const int32_t *v,
+                            const double *w, int node_order, lrsdp_problem **out);
+
 /* Matrix completion: n1 x n2 matrix, m observed entries (i[k], j[k]) with values
  * Mij[k] (host arrays).  X has order n1 + n2, C = I, b_k = 2 Mij[k].  Rejects
  * (EINVAL) out-of-range or repeated (i, j) and non-finite values.
@@ -172,6 +188,7 @@ typedef struct {
     double  b_l1;        /* ||b||_1                                              */
     double  b_inf;       /* ||b||_inf                                            */
     int     c_dense;     /* general problems: 1 when C is stored densely         */
+    int     node_order;  /* MaxCut: LRSDP_ORDER_INPUT or LRSDP_ORDER_DEGREE      */
 } lrsdp_problem_info;
 
 int lrsdp_problem_get_info(const lrsdp_problem *prob, lrsdp_problem_info *out);

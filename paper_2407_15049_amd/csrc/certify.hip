@@ -440,7 +440,7 @@ void ritz_min(const std::vector<CertStep> &st, int k, bool has_next, double *the
 }
 
 struct CertLayout {
-    size_t q[3], w, part, steps, small, flag, by, total;
+    size_t q[3], w, part, steps, small, flag, by, yperm, total;
 };
 
 CertLayout cert_layout(int64_t n, int max_iter) {
@@ -455,6 +455,7 @@ CertLayout cert_layout(int64_t n, int max_iter) {
     L.small = o; o += al(6 * kCS * sizeof(double));   // C (2 blocks), R1, R1^{-1}, R2, R2^{-1}
     L.flag = o; o += 256;
     L.by = o; o += 256;
+    L.yperm = o; o += al((size_t)n * sizeof(double));   // y in the library's node order (relabelled MaxCut)
     L.total = o;
     return L;
 }
@@ -496,9 +497,10 @@ extern "C" int lrsdp_certify_workspace_bytes(const lrsdp_problem *p, int max_ite
     return LRSDP_OK;
 }
 
-extern "C" int lrsdp_certify(lrsdp_ctx *c, const lrsdp_problem *p, const double *y, int max_iter, double tol,
-                             uint64_t seed, void *work, size_t work_bytes, lrsdp_cert *out) {
-    clear_error();
+// y_lib: y is in the library's node order already (the solver's own calls);
+// otherwise a relabelled MaxCut problem's y is moved into that order first.
+static int certify_run(lrsdp_ctx *c, const lrsdp_problem *p, const double *y, int max_iter, double tol,
+                       uint64_t seed, void *work, size_t work_bytes, lrsdp_cert *out, bool y_lib) {
     if (!c || !p || !y || !work || !out || max_iter < 1 || !(tol >= 0.0))
         return set_error(LRSDP_EINVAL, "bad argument");
     if (!p->uploaded) return set_error(LRSDP_EINVAL, "problem has not been uploaded");
@@ -521,6 +523,11 @@ extern "C" int lrsdp_certify(lrsdp_ctx *c, const lrsdp_problem *p, const double 
     hipStream_t s = c->stream;
     const int g = grid_rows(n);
     int rc;
+    if (!y_lib && p->info.kind == LRSDP_MAXCUT && p->csr.perm) {
+        double *yp = reinterpret_cast<double *>(ws + L.yperm);
+        if ((rc = launch_permute_vec(s, y, yp, p->csr.perm, n, 0))) return rc;
+        y = yp;
+    }
 
     LRSDP_HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int), s));
     const bool mc = p->info.kind == LRSDP_MAXCUT;
@@ -600,4 +607,15 @@ extern "C" int lrsdp_certify(lrsdp_ctx *c, const lrsdp_problem *p, const double 
     out->status = status;
     out->block = kCB;
     return LRSDP_OK;
+}
+
+extern "C" int lrsdp_certify(lrsdp_ctx *c, const lrsdp_problem *p, const double *y, int max_iter, double tol,
+                             uint64_t seed, void *work, size_t work_bytes, lrsdp_cert *out) {
+    clear_error();
+    return certify_run(c, p, y, max_iter, tol, seed, work, work_bytes, out, false);
+}
+
+int lrsdp::certify_lib_order(lrsdp_ctx *c, const lrsdp_problem *p, const double *y, int max_iter, double tol,
+                             uint64_t seed, void *work, size_t work_bytes, lrsdp_cert *out) {
+    return certify_run(c, p, y, max_iter, tol, seed, work, work_bytes, out, true);
 }

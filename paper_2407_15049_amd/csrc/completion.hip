@@ -143,8 +143,8 @@ __global__ __launch_bounds__(kBlock) void k_cmp_spmm(DevCompletion P, CmpSpmmArg
                 cmp_gather<S, GS>(P.bot_ptr, P.bot_row, P.bot_eid, (int)(row - P.n1), 0, a.ytil, a.V, a.ld, lane, active,
                               acc);
         }
-        const int64_t off = row * a.ld + lane * NV;
-        const CV v = active ? *reinterpret_cast<const CV *>(a.V + off) : zero;
+        const int64_t rb = row * a.ld, off = rb + lane * NV;
+        const CV v = chunk_or_zero(a.V + rb, lane, active);
         D4 vv = widen(v), aa = widen(acc), o;
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
@@ -160,14 +160,14 @@ __global__ __launch_bounds__(kBlock) void k_cmp_spmm(DevCompletion P, CmpSpmmArg
 #pragma unroll
             for (int g = 0; g <= TM; ++g) {
                 if (g <= T) {
-                    CV bsl = (g == gk1) ? os : (active ? *reinterpret_cast<const CV *>(a.rings.g[g] + off) : zero);
+                    CV bsl = (g == gk1) ? os : chunk_or_zero<S>(a.rings.g[g] + rb, lane, active);
                     s[g] += vdot(os, bsl);
                 }
             }
 #pragma unroll
             for (int d = 0; d < TM; ++d) {
                 if (d < T) {
-                    CV bsl = active ? *reinterpret_cast<const CV *>(a.rings.d[d] + off) : zero;
+                    CV bsl = chunk_or_zero<S>(a.rings.d[d] + rb, lane, active);
                     s[kMaxMem + 1 + d] += vdot(os, bsl);
                 }
             }
@@ -201,9 +201,9 @@ __global__ __launch_bounds__(kBlock) void k_cmp_sddmm(DevCompletion P, SddArgs<S
     const CV zero = vzero(CV{});
     double s[kLsSums] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int64_t i = (int64_t)blockIdx.x * GPB + grp; i < P.n1; i += (int64_t)gridDim.x * GPB) {
-        const int64_t off = i * a.ld + lane * NV;
-        const CV ui = active ? *reinterpret_cast<const CV *>(a.U + off) : zero;
-        const CV vi = (MODE != kSddRefresh && active) ? *reinterpret_cast<const CV *>(a.V + off) : zero;
+        const int64_t ib = i * a.ld;
+        const CV ui = chunk_or_zero(a.U + ib, lane, active);
+        const CV vi = MODE != kSddRefresh ? chunk_or_zero(a.V + ib, lane, active) : zero;
         const int b = P.top_ptr[i], e = P.top_ptr[i + 1];
         // The row's samples PW at a time: each lane loads the partner index and
         // sample id of NT of them (coalesced; past the row's end it repeats the
@@ -249,14 +249,14 @@ __global__ __launch_bounds__(kBlock) void k_cmp_sddmm(DevCompletion P, SddArgs<S
 #pragma unroll
             for (int q = 0; q < SS; ++q) {
                 const int src = s0 + q;   // compile-time register and lane
-                pj[q] = (P.n1 + __shfl(cc[src / GS], src % GS, GS)) * a.ld + lane * NV;
+                pj[q] = (P.n1 + __shfl(cc[src / GS], src % GS, GS)) * a.ld;
                 kk[q] = __shfl(ee[src / GS], src % GS, GS);
             }
             CV xu[SS], xv[SS];
 #pragma unroll
             for (int q = 0; q < SS; ++q) {
-                xu[q] = active ? *reinterpret_cast<const CV *>(a.U + pj[q]) : zero;
-                xv[q] = (MODE != kSddRefresh && active) ? *reinterpret_cast<const CV *>(a.V + pj[q]) : zero;
+                xu[q] = chunk_or_zero(a.U + pj[q], lane, active);
+                xv[q] = MODE != kSddRefresh ? chunk_or_zero(a.V + pj[q], lane, active) : zero;
             }
 #pragma unroll
             for (int q = 0; q < SS; ++q) {

@@ -20,6 +20,25 @@ template <> struct Chunk<float> {
 __device__ __forceinline__ double2 vzero(double2) { return make_double2(0.0, 0.0); }
 __device__ __forceinline__ float4 vzero(float4) { return make_float4(0.f, 0.f, 0.f, 0.f); }
 
+// Chunk `lane` of the row starting at `row`, or zero when the lane holds no
+// chunk of the row (act false).  The load is unconditional: an inactive lane
+// reads the row's first chunk (in bounds whenever the row is) and discards it.
+// A conditional load would be a branch around each load, into which the
+// compiler sinks the consumers and their waits, one memory round trip each.
+template <typename S>
+__device__ __forceinline__ typename Chunk<S>::V chunk_or_zero(const S *row, int lane, bool act) {
+    using CV = typename Chunk<S>::V;
+    const CV t = *reinterpret_cast<const CV *>(row + (act ? lane * Chunk<S>::N : 0));
+    return act ? t : vzero(CV{});
+}
+
+// The same for a row given as an array of chunks.
+template <typename CV>
+__device__ __forceinline__ CV vchunk_or_zero(const CV *row_chunks, int lane, bool act) {
+    const CV t = row_chunks[act ? lane : 0];
+    return act ? t : vzero(CV{});
+}
+
 // a += w * b
 __device__ __forceinline__ void vfma(double2 &a, double w, const double2 &b) {
     a.x = fma(w, b.x, a.x);

@@ -63,9 +63,9 @@ __global__ __launch_bounds__(kBlock) void k_gen_xbar(DevGeneral P, XbarArgs<S> a
         const int32_t ia = P.om_a[o], ib = P.om_b[o];
         // a diagonal position counts X_aa once: half of the symmetric formula
         const double w = ia == ib ? 0.5 : 1.0;
-        const int64_t ra = (int64_t)ia * a.ld + lane * NV, rb = (int64_t)ib * a.ld + lane * NV;
-        const CV ua = active ? *reinterpret_cast<const CV *>(a.U + ra) : zero;
-        const CV ub = active ? *reinterpret_cast<const CV *>(a.U + rb) : zero;
+        const int64_t ra = (int64_t)ia * a.ld, rb = (int64_t)ib * a.ld;
+        const CV ua = chunk_or_zero(a.U + ra, lane, active);
+        const CV ub = chunk_or_zero(a.U + rb, lane, active);
         if constexpr (MODE == kGenRefresh) {
             const double x = w * 2.0 * group_sum<GS>(vdot(ua, ub));
             if (lane == 0) {
@@ -73,8 +73,8 @@ __global__ __launch_bounds__(kBlock) void k_gen_xbar(DevGeneral P, XbarArgs<S> a
                 s[0] += a.cs * P.cval[o] * x;
             }
         } else {
-            const CV va = active ? *reinterpret_cast<const CV *>(a.V + ra) : zero;
-            const CV vb = active ? *reinterpret_cast<const CV *>(a.V + rb) : zero;
+            const CV va = chunk_or_zero(a.V + ra, lane, active);
+            const CV vb = chunk_or_zero(a.V + rb, lane, active);
             if constexpr (MODE == kGenA) {
                 const double x = w * group_sum<GS>(vdot(ua, vb) + vdot(ub, va));
                 if (lane == 0) a.x1[o] = x;
@@ -251,8 +251,7 @@ __global__ __launch_bounds__(kBlock) void k_gen_spmm(DevGeneral P, GenSpmmArgs<S
             double w[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                v[q] = active ? *reinterpret_cast<const CV *>(a.V + (int64_t)P.s_col[e + q] * a.ld + lane * NV)
-                              : zero;
+                v[q] = chunk_or_zero(a.V + (int64_t)P.s_col[e + q] * a.ld, lane, active);
                 w[q] = P.x2[P.s_om[e + q]];
             }
 #pragma unroll
@@ -263,16 +262,15 @@ __global__ __launch_bounds__(kBlock) void k_gen_spmm(DevGeneral P, GenSpmmArgs<S
             }
         }
         for (; e < e1; ++e) {
-            const CV v0 = active ? *reinterpret_cast<const CV *>(a.V + (int64_t)P.s_col[e] * a.ld + lane * NV)
-                                 : zero;
+            const CV v0 = chunk_or_zero(a.V + (int64_t)P.s_col[e] * a.ld, lane, active);
             const double w0 = P.x2[P.s_om[e]];
             const D4 vq = widen(v0);
 #pragma unroll
             for (int c = 0; c < 4; ++c) acc.v[c] = fma(w0, vq.v[c], acc.v[c]);
         }
-        const int64_t off = row * a.ld + lane * NV;
+        const int64_t rbase = row * a.ld, off = rbase + lane * NV;
         if (a.addw) {
-            const D4 wv = widen(active ? *reinterpret_cast<const CV *>(a.addw + off) : zero);
+            const D4 wv = widen(chunk_or_zero(a.addw + rbase, lane, active));
 #pragma unroll
             for (int c = 0; c < 4; ++c) acc.v[c] += wv.v[c];
         }
@@ -288,14 +286,14 @@ __global__ __launch_bounds__(kBlock) void k_gen_spmm(DevGeneral P, GenSpmmArgs<S
 #pragma unroll
             for (int g = 0; g <= TM; ++g) {
                 if (g <= T) {
-                    CV bsl = (g == gk1) ? os : (active ? *reinterpret_cast<const CV *>(a.rings.g[g] + off) : zero);
+                    CV bsl = (g == gk1) ? os : chunk_or_zero<S>(a.rings.g[g] + rbase, lane, active);
                     s[g] += vdot(os, bsl);
                 }
             }
 #pragma unroll
             for (int d = 0; d < TM; ++d) {
                 if (d < T) {
-                    CV bsl = active ? *reinterpret_cast<const CV *>(a.rings.d[d] + off) : zero;
+                    CV bsl = chunk_or_zero<S>(a.rings.d[d] + rbase, lane, active);
                     s[kMaxMem + 1 + d] += vdot(os, bsl);
                 }
             }

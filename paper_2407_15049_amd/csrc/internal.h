@@ -45,6 +45,13 @@ constexpr int kMaxSums = 32;         // doubles of partial sums per block
 constexpr int kMaxMem = 8;           // largest L-BFGS memory
 constexpr int kMaxBasis = 2 * kMaxMem + 1;
 constexpr int kSegLen = 128;         // rows longer than this are split into segments
+// The flat streaming sweeps (L-BFGS update and combine) run one 16-byte chunk
+// per thread over as many workgroups as the array needs (fewer, grid-stride,
+// past kL1Bytes of first-level sums), each workgroup storing one compact row
+// of its dot products; a second kernel adds kL1PerL2 consecutive rows at a
+// time, in a fixed order, into the kMaxSums-stride rows the finalize kernels read.
+constexpr size_t kL1Bytes = size_t(16) << 20;
+constexpr int kL1PerL2 = kBlock;
 
 // Weight encodings of the MaxCut off-diagonal values C_ij = w_ij / 4.
 enum WeightMode { kWUnit = 0, kWSign = 1, kWGeneral = 2 };
@@ -59,6 +66,7 @@ struct DevCsr {
     const double *val = nullptr;        // nnz (kWGeneral only)
     const double *diag = nullptr;       // n   (C_ii)
     const double *hrow = nullptr;       // n   2 max(sum_j |C_ij|, 1e-3 ||vec(C)||_1 / n) (row-block H0)
+    const int32_t *perm = nullptr;      // n   caller label of internal node k (LRSDP_ORDER_DEGREE), else null
     // Work lists.  Light rows (<= kSegLen nonzeros) sorted by decreasing length
     // inside windows of consecutive rows; heavy rows split into segments.
     const int4 *light = nullptr;        // n_light {row, begin, end, 0}
@@ -133,12 +141,24 @@ struct DevGeneral {
 int spmm_general(hipStream_t s, const DevGeneral &P, int prec, const void *V, int64_t ld, const double *ytil,
                  void *Y);
 
+// Node-order moves of a relabelled MaxCut problem (perm[k] = caller label of
+// internal node k).  scatter == 0: dst[k] = src[perm[k]] (caller -> library
+// order); scatter == 1: dst[perm[k]] = src[k] (library -> caller order).
+// Rows of row_bytes (a multiple of 16) for factors, float64 entries for vectors.
+int launch_permute_rows(hipStream_t s, const void *src, void *dst, const int32_t *perm, int64_t n,
+                        int64_t row_bytes, int scatter);
+int launch_permute_vec(hipStream_t s, const double *src, double *dst, const int32_t *perm, int64_t n, int scatter);
+
+// lrsdp_certify with y in the library's node order (the solver's own calls).
+int certify_lib_order(lrsdp_ctx *c, const lrsdp_problem *p, const double *y, int max_iter, double tol,
+                      uint64_t seed, void *work, size_t work_bytes, lrsdp_cert *out);
+
 }  // namespace lrsdp
 
 struct lrsdp_problem {
     lrsdp_problem_info info{};
     // host data
-    std::vector<int32_t> row_ptr, col, heavy, heavy_seg;
+    std::vector<int32_t> row_ptr, col, heavy, heavy_seg, perm;
     std::vector<int4> light;
     std::vector<int4> seg;
     std::vector<double> val, diag, hrow;

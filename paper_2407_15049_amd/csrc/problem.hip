@@ -95,8 +95,16 @@ void build_work_lists(lrsdp_problem *p, int64_t n) {
 extern "C" int lrsdp_problem_maxcut(int64_t n, int64_t n_edges, const int32_t *u,
                                     const int32_t *v, const double *w,
                                     lrsdp_problem **out) {
+    return lrsdp_problem_maxcut_ex(n, n_edges, u, v, w, LRSDP_ORDER_INPUT, out);
+}
+
+extern "C" int lrsdp_problem_maxcut_ex(int64_t n, int64_t n_edges, const int32_t *u, const int32_t *v,
+                                       const double *w, int node_order, lrsdp_problem **out) {
     clear_error();
     if (!out) return set_error(LRSDP_EINVAL, "out is NULL");
+    if (node_order != LRSDP_ORDER_INPUT && node_order != LRSDP_ORDER_DEGREE)
+        return set_error(LRSDP_EINVAL, "node_order %d is neither LRSDP_ORDER_INPUT nor LRSDP_ORDER_DEGREE",
+                         node_order);
     *out = nullptr;
     if (n < 1 || n > INT32_MAX - 1) return set_error(LRSDP_EINVAL, "n = %lld out of range", (long long)n);
     if (n_edges < 0) return set_error(LRSDP_EINVAL, "n_edges < 0");
@@ -122,6 +130,28 @@ extern "C" int lrsdp_problem_maxcut(int64_t n, int64_t n_edges, const int32_t *u
         deg[b]++;
     }
     auto *p = new lrsdp_problem();
+    // Node order.  With LRSDP_ORDER_DEGREE, internal node k is the caller's
+    // node perm[k], nodes taken by decreasing degree and increasing label: the
+    // factor rows of the high-degree nodes, gathered by most rows of the
+    // SpMM, then sit next to each other in memory and share cache lines.
+    std::vector<int32_t> newid;   // caller label -> internal label (empty: the identity)
+    if (node_order == LRSDP_ORDER_DEGREE) {
+        int64_t dmax = 0;
+        for (int64_t i = 0; i < n; ++i) dmax = std::max(dmax, deg[i]);
+        std::vector<int64_t> start(dmax + 2, 0);   // counting sort by decreasing degree, stable in the label
+        for (int64_t i = 0; i < n; ++i) start[dmax - deg[i] + 1]++;
+        for (int64_t d = 0; d <= dmax; ++d) start[d + 1] += start[d];
+        p->perm.resize(n);
+        newid.resize(n);
+        for (int64_t i = 0; i < n; ++i) {
+            const int64_t k = start[dmax - deg[i]]++;
+            p->perm[k] = (int32_t)i;
+            newid[i] = (int32_t)k;
+        }
+        std::vector<int64_t> d2(n + 1, 0);
+        for (int64_t i = 0; i < n; ++i) d2[newid[i]] = deg[i];
+        deg.swap(d2);
+    }
     p->row_ptr.resize(n + 1);
     p->row_ptr[0] = 0;
     for (int64_t i = 0; i < n; ++i) p->row_ptr[i + 1] = (int32_t)(p->row_ptr[i] + deg[i]);
@@ -129,9 +159,10 @@ extern "C" int lrsdp_problem_maxcut(int64_t n, int64_t n_edges, const int32_t *u
     std::vector<int32_t> fill(p->row_ptr.begin(), p->row_ptr.end() - 1);
     std::vector<double> wv(nnz);
     p->col.resize(nnz);
+    const bool relabel = !newid.empty();
     for (int64_t e = 0; e < n_edges; ++e) {
         double we = w ? w[e] : 1.0;
-        int32_t a = u[e], b = v[e];
+        int32_t a = relabel ? newid[u[e]] : u[e], b = relabel ? newid[v[e]] : v[e];
         int32_t pa = fill[a]++, pb = fill[b]++;
         p->col[pa] = b;
         p->col[pb] = a;
@@ -190,8 +221,10 @@ extern "C" int lrsdp_problem_maxcut(int64_t n, int64_t n_edges, const int32_t *u
                 std::vector<int32_t> c(p->col.begin() + p->row_ptr[i], p->col.begin() + p->row_ptr[i + 1]);
                 std::sort(c.begin(), c.end());
                 int32_t d = c[std::adjacent_find(c.begin(), c.end()) - c.begin()];
+                const long long ci = p->perm.empty() ? (long long)i : (long long)p->perm[i];
+                const int cd = p->perm.empty() ? d : p->perm[d];
                 delete p;
-                return set_error(LRSDP_EINVAL, "edge (%lld, %d) appears more than once", (long long)i, d);
+                return set_error(LRSDP_EINVAL, "edge (%lld, %d) appears more than once", ci, cd);
             }
     }
     double c_l1 = 0.0;
@@ -221,6 +254,7 @@ extern "C" int lrsdp_problem_maxcut(int64_t n, int64_t n_edges, const int32_t *u
     I.c_l1 = c_l1;
     I.b_l1 = (double)n;
     I.b_inf = 1.0;
+    I.node_order = node_order;
     *out = p;
     return LRSDP_OK;
 }
@@ -562,6 +596,7 @@ size_t plan_device(const lrsdp_problem *p, size_t *offs) {
         add(p->heavy_seg.size() * 4);
         add(p->seg.size() * 256);      // segment partial sums (<= 256 B per row)
         add(p->hrow.size() * 8);
+        add(p->perm.size() * 4);
     } else if (p->info.kind == LRSDP_GENERAL) {
         add(p->om_a.size() * 4);
         add(p->om_b.size() * 4);
@@ -630,6 +665,7 @@ extern "C" int lrsdp_problem_upload(lrsdp_ctx *ctx, lrsdp_problem *p, void *dev,
         LRSDP_HIP_TRY(put(offs[6], p->heavy.data(), p->heavy.size() * 4));
         LRSDP_HIP_TRY(put(offs[7], p->heavy_seg.data(), p->heavy_seg.size() * 4));
         LRSDP_HIP_TRY(put(offs[9], p->hrow.data(), p->hrow.size() * 8));
+        LRSDP_HIP_TRY(put(offs[10], p->perm.data(), p->perm.size() * 4));
         DevCsr &c = p->csr;
         c.row_ptr = (const int32_t *)(base + offs[0]);
         c.col = (const int32_t *)(base + offs[1]);
@@ -641,6 +677,7 @@ extern "C" int lrsdp_problem_upload(lrsdp_ctx *ctx, lrsdp_problem *p, void *dev,
         c.heavy_seg = (const int32_t *)(base + offs[7]);
         c.seg_buf = base + offs[8];
         c.hrow = (const double *)(base + offs[9]);
+        c.perm = p->perm.empty() ? nullptr : (const int32_t *)(base + offs[10]);
         c.n = p->info.n;
         c.nnz = p->info.nnz;
         c.n_light = (int64_t)p->light.size();

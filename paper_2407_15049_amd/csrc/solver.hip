@@ -25,14 +25,14 @@ int launch_reduce(hipStream_t, const double *, int, int, double *);
 int launch_cubic(hipStream_t, const double *, double *);
 int launch_update_maxcut(hipStream_t, int, SolverState *, void *, const void *, const double *, const double *,
                          const double *, const double *, const double *, double *, void *const *, void *const *,
-                         int, int64_t, int64_t, double *, int *, const PcBufs * = nullptr);
+                         int, int64_t, int64_t, double *, double *, int *, const PcBufs * = nullptr);
 int launch_combine(hipStream_t, int, SolverState *, const double *, const void *const *, int, void *, int64_t,
-                   int64_t, double *, int *, uint16_t *, const void * = nullptr, const PcBufs * = nullptr);
+                   int64_t, double *, double *, int *, uint16_t *, const void * = nullptr, const PcBufs * = nullptr);
 int launch_grad_init_maxcut(hipStream_t, int, SolverState *, const void *, const void *, const double *,
                             const double *, double *, void *, int64_t, int64_t, double *, int *,
                             const PcBufs * = nullptr);
 int launch_fill(hipStream_t, int, void *, int64_t);
-int launch_rank_grow(hipStream_t, int, void *, int64_t, int64_t, int, int, uint64_t, double);
+int launch_rank_grow(hipStream_t, int, void *, int64_t, int64_t, int, int, uint64_t, double, const int32_t *);
 int launch_avg(hipStream_t, int, const void *, const void *, void *, int64_t);
 int launch_dots(hipStream_t, int, const void *, const void *const *, int, int64_t, int64_t, double *, int *);
 int launch_rowdot(hipStream_t, int, const void *, const void *, int64_t, int64_t, double *);
@@ -67,7 +67,8 @@ constexpr size_t kPartCbOff = kPartLsOff + kPartBytes;
 constexpr size_t kPartUpOff = kPartCbOff + kPartBytes;
 constexpr size_t kPartMiscOff = kPartUpOff + kPartBytes;
 constexpr size_t kSmallOff = kPartMiscOff + kPartBytes;      // 4096 doubles of small buffers
-constexpr size_t kScratchBytes = kSmallOff + 4096 * sizeof(double);
+constexpr size_t kL1Off = kSmallOff + 4096 * sizeof(double);  // first-level sums of the flat sweeps
+constexpr size_t kScratchBytes = kL1Off + kL1Bytes;
 
 template <typename T>
 T *at(void *base, size_t off) {
@@ -87,6 +88,16 @@ int check_ld(int prec, int64_t ld) {
     if (ld <= 0 || rb % 16 != 0 || rb > 256)
         return set_error(LRSDP_EINVAL, "ld = %lld: ld * element size must be a positive multiple of 16, at most 256",
                          (long long)ld);
+    return LRSDP_OK;
+}
+
+// The per-kernel entry points take per-node arrays in the library's order,
+// which is the caller's only for problems built in input order.
+static int check_input_order(const lrsdp_problem *p) {
+    if (p->csr.perm)
+        return set_error(LRSDP_EUNSUPPORTED,
+                         "the per-kernel entry points need a problem in input order (LRSDP_ORDER_INPUT); this "
+                         "one is relabelled by degree");
     return LRSDP_OK;
 }
 
@@ -390,7 +401,8 @@ int cmp_lincomb(lrsdp_ctx *c, int prec, std::initializer_list<const void *> basi
     for (double v : coef) hc[k++] = v;
     LRSDP_HIP_TRY(hipMemcpyAsync(dcoef, hc, nb * sizeof(double), hipMemcpyHostToDevice, c->stream));
     int nblk = 0, rc;
-    if ((rc = launch_combine(c->stream, prec, nullptr, dcoef, bs, nb, out, n, ld, part, &nblk, nullptr))) return rc;
+    double *l1 = at<double>(c->scratch, kL1Off);
+    if ((rc = launch_combine(c->stream, prec, nullptr, dcoef, bs, nb, out, n, ld, part, l1, &nblk, nullptr))) return rc;
     if ((rc = launch_reduce(c->stream, part, nblk, kMaxBasis + 1, dred))) return rc;
     double *hr = reinterpret_cast<double *>(static_cast<char *>(c->pinned) + 6656);
     LRSDP_HIP_TRY(hipMemcpyAsync(hr, dred, (kMaxBasis + 1) * sizeof(double), hipMemcpyDeviceToHost, c->stream));
@@ -494,6 +506,7 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
     double *part_cb = at<double>(c->scratch, kPartCbOff);
     double *part_up = at<double>(c->scratch, kPartUpOff);
     double *part_misc = at<double>(c->scratch, kPartMiscOff);
+    double *l1 = at<double>(c->scratch, kL1Off);
     const void *basis[kMaxBasis];
     for (int g = 0; g <= T; ++g) basis[g] = gring[g];
     for (int d = 0; d < T; ++d) basis[T + 1 + d] = dring[d];
@@ -607,8 +620,8 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
             LRSDP_HIP_TRY(hipMemcpyAsync(yo, y, p->info.m * sizeof(double), hipMemcpyDeviceToDevice, s));
             if (cs != 1.0 && (r2 = launch_dscale(s, yo, 1.0 / cs, p->info.m))) return r2;
             lrsdp_cert ct{};
-            if ((r2 = lrsdp_certify(c, p, yo, o->cert_iters, 0.1 * o->tol * (1.0 + p->info.c_l1), 15049, ws + w.cert,
-                                    w.cert_bytes, &ct)))
+            if ((r2 = certify_lib_order(c, p, yo, o->cert_iters, 0.1 * o->tol * (1.0 + p->info.c_l1), 15049,
+                                        ws + w.cert, w.cert_bytes, &ct)))
                 return r2;
             err2 = std::max(0.0, -ct.lambda_lb) / (1.0 + p->info.c_l1);
             ok = err2 <= o->tol;
@@ -650,7 +663,8 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
         int64_t left = o->max_iter_total - total_inner;
         int k_limit = (int)std::min<int64_t>(o->max_inner, std::max<int64_t>(left, 0));
         if ((rc = launch_init_finalize(s, st, part_misc, nb, k_limit))) break;
-        if ((rc = launch_combine(s, prec, st, nullptr, basis, 2 * T + 1, nullptr, n, ld, part_cb, &ncb, shadow, R, pc)))
+        if ((rc = launch_combine(s, prec, st, nullptr, basis, 2 * T + 1, nullptr, n, ld, part_cb, l1, &ncb, shadow, R,
+                                 pc)))
             break;
         // L-BFGS iterations in batches of B.  `it` indexes the ring slots (reset
         // by a gradient refresh); `done_it` counts every enqueued iteration.
@@ -695,7 +709,7 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
                     if (rc) break;
                 }
                 if ((rc = launch_init_finalize(s, st, part_misc, nb2, -1))) break;
-                if ((rc = launch_combine(s, prec, st, nullptr, basis, 2 * T + 1, nullptr, n, ld, part_cb, &ncb,
+                if ((rc = launch_combine(s, prec, st, nullptr, basis, 2 * T + 1, nullptr, n, ld, part_cb, l1, &ncb,
                                          shadow, R, pc)))
                     break;
             }
@@ -732,7 +746,8 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
                 if (rc) break;
                 if (o->profile) LRSDP_HIP_TRY(hipEventRecord(evs[2 * b + 1], s));
                 if ((rc = launch_lbfgs_finalize(s, st, part_up, nup))) break;
-                if ((rc = launch_combine(s, prec, st, nullptr, basis, 2 * T + 1, nullptr, n, ld, part_cb, &ncb, shadow)))
+                if ((rc = launch_combine(s, prec, st, nullptr, basis, 2 * T + 1, nullptr, n, ld, part_cb, l1, &ncb,
+                                         shadow)))
                     break;
             }
             for (int b = 0; b < B && mc; ++b, ++it, ++done_it, ++since_refresh) {
@@ -757,11 +772,11 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
                 if ((rc = launch_ls_finalize(s, st, part_ls, nls, part_cb, ncb, LRSDP_MAXCUT, 1.0))) break;
                 int nup = 0;
                 if ((rc = launch_update_maxcut(s, prec, st, R, CD, y, rn, q1, q2, ytil[it % 2], ytil[(it + 1) % 2],
-                                               gring, dring, T, n, ld, part_up, &nup, pc)))
+                                               gring, dring, T, n, ld, part_up, l1, &nup, pc)))
                     break;
                 if ((rc = launch_lbfgs_finalize(s, st, part_up, nup))) break;
-                if ((rc = launch_combine(s, prec, st, nullptr, basis, 2 * T + 1, nullptr, n, ld, part_cb, &ncb, shadow,
-                                         R, pc)))
+                if ((rc = launch_combine(s, prec, st, nullptr, basis, 2 * T + 1, nullptr, n, ld, part_cb, l1, &ncb,
+                                         shadow, R, pc)))
                     break;
             }
             if (rc) break;
@@ -817,7 +832,8 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
             // iterations or more; grow R in place (new columns from the seeded
             // generator), then exact C R and measures for the new R
             const int r_new = std::min<int64_t>(rank_cap, (3 * (int64_t)rank_cur + 1) / 2);
-            if ((rc = launch_rank_grow(s, prec, R, n, ld, rank_cur, r_new, (uint64_t)o->rank_seed, o->rank_scale)))
+            if ((rc = launch_rank_grow(s, prec, R, n, ld, rank_cur, r_new, (uint64_t)o->rank_seed, o->rank_scale,
+                                       mc ? p->csr.perm : nullptr)))
                 break;
             if (o->verbose) fprintf(stderr, "[lrsdp] rank %d -> %d\n", rank_cur, r_new);
             rank_cur = r_new;
@@ -1026,7 +1042,31 @@ extern "C" int lrsdp_solve(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *
     if ((rc = plan_workspace(p, o, &w))) return rc;
     if (ws_bytes < w.total) return set_error(LRSDP_ENOMEM, "workspace needs %zu bytes, %zu given", w.total, ws_bytes);
     LRSDP_HIP_TRY(hipSetDevice(c->device));
-    return solve_impl(c, p, o, static_cast<char *>(ws), R, y, res);
+    const int32_t *perm = p->info.kind == LRSDP_MAXCUT ? p->csr.perm : nullptr;
+    if (!perm) return solve_impl(c, p, o, static_cast<char *>(ws), R, y, res);
+    // A problem relabelled by degree: R and y move into the library's node
+    // order for the solve and back afterwards (also after a failed solve),
+    // through the front of the workspace, which the solve has not yet taken or
+    // no longer needs.
+    const int64_t n = p->info.n;
+    const size_t rbytes = (size_t)o->ld * elem_size(o->prec), fbytes = (size_t)n * rbytes;
+    const size_t yoff = (fbytes + 255) / 256 * 256;
+    if (w.total < yoff + (size_t)n * sizeof(double))
+        return set_error(LRSDP_ENOMEM, "workspace of %zu bytes cannot stage the node-order moves", w.total);
+    char *tmp = static_cast<char *>(ws);
+    double *ytmp = reinterpret_cast<double *>(tmp + yoff);
+    hipStream_t s = c->stream;
+    if ((rc = launch_permute_rows(s, R, tmp, perm, n, (int64_t)rbytes, 0))) return rc;
+    if ((rc = launch_permute_vec(s, y, ytmp, perm, n, 0))) return rc;
+    LRSDP_HIP_TRY(hipMemcpyAsync(R, tmp, fbytes, hipMemcpyDeviceToDevice, s));
+    LRSDP_HIP_TRY(hipMemcpyAsync(y, ytmp, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    const int rc_solve = solve_impl(c, p, o, static_cast<char *>(ws), R, y, res);
+    if ((rc = launch_permute_rows(s, R, tmp, perm, n, (int64_t)rbytes, 1))) return rc;
+    if ((rc = launch_permute_vec(s, y, ytmp, perm, n, 1))) return rc;
+    LRSDP_HIP_TRY(hipMemcpyAsync(R, tmp, fbytes, hipMemcpyDeviceToDevice, s));
+    LRSDP_HIP_TRY(hipMemcpyAsync(y, ytmp, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    LRSDP_HIP_TRY(hipStreamSynchronize(s));
+    return rc_solve;
 }
 
 // ---------------------------------------------------------------------------
@@ -1037,7 +1077,9 @@ extern "C" int lrsdp_k_spmm(lrsdp_ctx *c, const lrsdp_problem *p, int prec, cons
     clear_error();
     if (!c || !V || !Y) return set_error(LRSDP_EINVAL, "NULL argument");
     int rc;
-    if ((rc = check_problem(p)) || (rc = check_prec(prec)) || (rc = check_ld(prec, ld))) return rc;
+    if ((rc = check_problem(p)) || (rc = check_input_order(p)) || (rc = check_prec(prec)) ||
+        (rc = check_ld(prec, ld)))
+        return rc;
     if (V == Y) return set_error(LRSDP_EINVAL, "Y must not alias V");
     const int pr = prec == LRSDP_F64 ? LRSDP_F64 : LRSDP_F32;
     if (p->info.kind == LRSDP_MAXCUT) {
@@ -1061,7 +1103,9 @@ extern "C" int lrsdp_k_constraint(lrsdp_ctx *c, const lrsdp_problem *p, int prec
     clear_error();
     if (!c || !U || !out) return set_error(LRSDP_EINVAL, "NULL argument");
     int rc;
-    if ((rc = check_problem(p)) || (rc = check_prec(prec)) || (rc = check_ld(prec, ld))) return rc;
+    if ((rc = check_problem(p)) || (rc = check_input_order(p)) || (rc = check_prec(prec)) ||
+        (rc = check_ld(prec, ld)))
+        return rc;
     const int pr = prec == LRSDP_F64 ? LRSDP_F64 : LRSDP_F32;
     if (!V) V = U;
     if (p->info.kind == LRSDP_MAXCUT) return launch_rowdot(c->stream, pr, U, V, p->info.n, ld, out);
@@ -1079,7 +1123,9 @@ extern "C" int lrsdp_k_ls_coeffs(lrsdp_ctx *c, const lrsdp_problem *p, int prec,
     clear_error();
     if (!c || !R || !D || !y || !work || !out) return set_error(LRSDP_EINVAL, "NULL argument");
     int rc;
-    if ((rc = check_problem(p)) || (rc = check_prec(prec)) || (rc = check_ld(prec, ld))) return rc;
+    if ((rc = check_problem(p)) || (rc = check_input_order(p)) || (rc = check_prec(prec)) ||
+        (rc = check_ld(prec, ld)))
+        return rc;
     const int pr = prec == LRSDP_F64 ? LRSDP_F64 : LRSDP_F32;
     const int64_t n = p->info.n;
     const size_t arr = (size_t)n * ld * elem_size(pr);
@@ -1171,7 +1217,9 @@ extern "C" int lrsdp_k_alm(lrsdp_ctx *c, const lrsdp_problem *p, int prec, const
     clear_error();
     if (!c || !R || !y || !work || !out) return set_error(LRSDP_EINVAL, "NULL argument");
     int rc;
-    if ((rc = check_problem(p)) || (rc = check_prec(prec)) || (rc = check_ld(prec, ld))) return rc;
+    if ((rc = check_problem(p)) || (rc = check_input_order(p)) || (rc = check_prec(prec)) ||
+        (rc = check_ld(prec, ld)))
+        return rc;
     const int pr = prec == LRSDP_F64 ? LRSDP_F64 : LRSDP_F32;
     double *part = at<double>(c->scratch, kPartMiscOff);
     double *sums = at<double>(c->scratch, kSmallOff);
@@ -1237,7 +1285,8 @@ extern "C" int lrsdp_k_lbfgs_dir(lrsdp_ctx *c, int prec, int64_t n, int64_t ld, 
     }
     if ((rc = launch_two_loop_pairs(s, gram, k, coef, flag))) return rc;
     int nblk = 0;
-    if ((rc = launch_combine(s, pr, nullptr, coef, basis, nb, D, n, ld, part, &nblk, nullptr))) return rc;
+    double *l1 = at<double>(c->scratch, kL1Off);
+    if ((rc = launch_combine(s, pr, nullptr, coef, basis, nb, D, n, ld, part, l1, &nblk, nullptr))) return rc;
     int hflag = 0;
     LRSDP_HIP_TRY(hipMemcpyAsync(c->pinned, flag, sizeof(int), hipMemcpyDeviceToHost, s));
     LRSDP_HIP_TRY(hipStreamSynchronize(s));
@@ -1395,7 +1444,9 @@ extern "C" int lrsdp_k_admm(lrsdp_ctx *c, const lrsdp_problem *p, int prec, void
     clear_error();
     if (!c || !U || !V || !y || iters < 0 || !(sigma > 0)) return set_error(LRSDP_EINVAL, "bad argument");
     int rc;
-    if ((rc = check_problem(p)) || (rc = check_prec(prec)) || (rc = check_ld(prec, ld))) return rc;
+    if ((rc = check_problem(p)) || (rc = check_input_order(p)) || (rc = check_prec(prec)) ||
+        (rc = check_ld(prec, ld)))
+        return rc;
     const int pr = prec == LRSDP_F64 ? LRSDP_F64 : LRSDP_F32;
     if (p->info.kind == LRSDP_GENERAL)
         return set_error(LRSDP_EUNSUPPORTED, "the splitting phase is implemented for MaxCut and completion problems");

@@ -450,28 +450,30 @@ struct UpdateArgs {
 //   ytil_i <- y_i + sigma (1 - ||R_new,i||^2),
 //   G_{k+1} = 2 (C R_new - ytil_new o R_new) with C R_new = C R + tau C D and
 //   C R = G_k/2 + ytil_old o R_old (so C R need not be stored),
-// and the dot products of G_{k+1} with every ring slot (partials layout: G slot
-// g at g, D slot d at kMaxMem + 1 + d).
-template <typename S>
+// and the dot products of G_{k+1} with every ring slot.  TM is the largest
+// memory the instance handles (T <= TM); each workgroup stores one compact row
+// of 2 TM + 1 sums (G slots 0..TM, then D slots 0..TM-1) at a.partials.
+template <typename S, int TM>
 __global__ __launch_bounds__(kBlock) void k_update_maxcut(UpdateArgs<S> a) {
     using CV = typename Chunk<S>::V;
+    constexpr int KS = 2 * TM + 1;
     SolverState *st = a.st;
     if (st->done) return;
     const double tau = st->tau, sigma = st->sigma;
     const int T = st->T, gk = st->gk, gk1 = (gk + 1) % (T + 1), dk = st->dk;
-    double s[kMaxBasis];
+    double s[KS];
 #pragma unroll
-    for (int j = 0; j < kMaxBasis; ++j) s[j] = 0.0;
+    for (int j = 0; j < KS; ++j) s[j] = 0.0;
     const CV *D = nullptr;
     const CV *Go = nullptr;
     CV *Gn = nullptr;
 #pragma unroll
-    for (int g = 0; g <= kMaxMem; ++g) {
+    for (int g = 0; g <= TM; ++g) {
         if (g == gk) Go = reinterpret_cast<const CV *>(a.rings.g[g]);
         if (g == gk1) Gn = reinterpret_cast<CV *>(a.rings.g[g]);
     }
 #pragma unroll
-    for (int d = 0; d < kMaxMem; ++d)
+    for (int d = 0; d < TM; ++d)
         if (d == dk) D = reinterpret_cast<const CV *>(a.rings.d[d]);
     CV *R = reinterpret_cast<CV *>(a.R);
     const CV *CD = reinterpret_cast<const CV *>(a.CD);
@@ -498,7 +500,7 @@ __global__ __launch_bounds__(kBlock) void k_update_maxcut(UpdateArgs<S> a) {
         Gn[c] = gn_s;
         if (c - row * a.cpr == 0) a.ytil_out[row] = ynew;
 #pragma unroll
-        for (int g = 0; g <= kMaxMem; ++g) {
+        for (int g = 0; g <= TM; ++g) {
             if (g <= T) {
                 CV b;
                 if (g == gk1) b = gn_s;
@@ -508,14 +510,50 @@ __global__ __launch_bounds__(kBlock) void k_update_maxcut(UpdateArgs<S> a) {
             }
         }
 #pragma unroll
-        for (int dd = 0; dd < kMaxMem; ++dd) {
+        for (int dd = 0; dd < TM; ++dd) {
             if (dd < T) {
                 const CV b = (dd == dk) ? d : reinterpret_cast<const CV *>(a.rings.d[dd])[c];
-                s[kMaxMem + 1 + dd] += vdot(gn_s, b);
+                s[TM + 1 + dd] += vdot(gn_s, b);
             }
         }
     }
-    block_sums_store<kMaxBasis>(s, a.partials + (size_t)blockIdx.x * kMaxSums);
+    block_sums_store<KS>(s, a.partials + (size_t)blockIdx.x * KS);
+}
+
+// Second level of the flat sweeps' sums: workgroup b adds the compact rows
+// [b kL1PerL2, (b+1) kL1PerL2) of `in` (K doubles each, rows < nrows) in a
+// fixed tree order and writes row b of `out` at stride kMaxSums, every column
+// of it: compact sum j goes to column j for j < split, to column
+// kMaxMem + 1 + (j - split) past it (the update's D slots; split = K keeps
+// them in place) and, with last_col >= 0, the final sum to column last_col
+// (the combine's ||out||^2).  Other columns are zero.
+template <int K>
+__global__ __launch_bounds__(kL1PerL2) void k_sum_l1(const SolverState *st, const double *in, int nrows, int split,
+                                                     int last_col, double *out) {
+    if (st && st->done) return;
+    __shared__ double sh[kL1PerL2 / 64][K];
+    const int r = blockIdx.x * kL1PerL2 + threadIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const double v = wave_sum(r < nrows ? in[(size_t)r * K + k] : 0.0);
+        if (lane == 0) sh[wave][k] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < kMaxSums) {
+        const int col = threadIdx.x;
+        int j = -1;
+        const int body = last_col >= 0 ? K - 1 : K;   // sums placed by `split`
+        if (col < split && col < body) j = col;
+        else if (col >= kMaxMem + 1 && split + (col - kMaxMem - 1) < body) j = split + (col - kMaxMem - 1);
+        if (last_col >= 0 && col == last_col) j = K - 1;
+        double t = 0.0;
+        if (j >= 0) {
+#pragma unroll
+            for (int w = 0; w < kL1PerL2 / 64; ++w) t += sh[w][j];
+        }
+        out[(size_t)blockIdx.x * kMaxSums + col] = t;
+    }
 }
 
 // The update sweep with the row-block H0 (solve option precond): one lane
@@ -556,9 +594,9 @@ __global__ __launch_bounds__(kBlock) void k_update_maxcut_pc(UpdateArgs<S> a, Pc
     CV *R = reinterpret_cast<CV *>(a.R);
     const CV *CD = reinterpret_cast<const CV *>(a.CD);
     for (int64_t row = (int64_t)blockIdx.x * GPB + grp; row < pc.n; row += (int64_t)gridDim.x * GPB) {
-        const int64_t c = row * cpr + lane;
-        const CV r = active ? R[c] : zero, d = active ? D[c] : zero;
-        const CV cd = active ? CD[c] : zero, go = active ? Go[c] : zero;
+        const int64_t c0 = row * cpr, c = c0 + lane;
+        const CV r = vchunk_or_zero(R + c0, lane, active), d = vchunk_or_zero(D + c0, lane, active);
+        const CV cd = vchunk_or_zero(CD + c0, lane, active), go = vchunk_or_zero(Go + c0, lane, active);
         const double yold = a.ytil_in[row];
         const double rnn = a.rn[row] + tau * (a.q1[row] + tau * a.q2[row]);
         const double ynew = a.y[row] + sigma * (1.0 - rnn);
@@ -585,19 +623,19 @@ __global__ __launch_bounds__(kBlock) void k_update_maxcut_pc(UpdateArgs<S> a, Pc
         const CV *gp0 = reinterpret_cast<const CV *>(a.rings.g[0]);
         const CV *gp1 = reinterpret_cast<const CV *>(a.rings.g[1]);
         const CV *gp2 = reinterpret_cast<const CV *>(a.rings.g[2]);
-        const CV b0 = gk1 == 0 ? gn_s : (gk == 0 ? go : (active && T >= 0 ? gp0[c] : zero));
-        const CV b1 = gk1 == 1 ? gn_s : (gk == 1 ? go : (active && T >= 1 ? gp1[c] : zero));
-        const CV b2 = gk1 == 2 ? gn_s : (gk == 2 ? go : (active && T >= 2 ? gp2[c] : zero));
+        const CV b0 = gk1 == 0 ? gn_s : (gk == 0 ? go : (T >= 0 ? vchunk_or_zero(gp0 + c0, lane, active) : zero));
+        const CV b1 = gk1 == 1 ? gn_s : (gk == 1 ? go : (T >= 1 ? vchunk_or_zero(gp1 + c0, lane, active) : zero));
+        const CV b2 = gk1 == 2 ? gn_s : (gk == 2 ? go : (T >= 2 ? vchunk_or_zero(gp2 + c0, lane, active) : zero));
         s[0] += vdot(gn_s, b0);
         s[1] += vdot(gn_s, b1);
         if (T >= 2) s[2] += vdot(gn_s, b2);
         {
             const CV *dp0 = reinterpret_cast<const CV *>(a.rings.d[0]);
             const CV *dp1 = reinterpret_cast<const CV *>(a.rings.d[1]);
-            const CV bd0 = dk == 0 ? d : (active ? dp0[c] : zero);
+            const CV bd0 = dk == 0 ? d : vchunk_or_zero(dp0 + c0, lane, active);
             s[kPcMem + 1] += vdot(gn_s, bd0);
             if (T >= 2) {
-                const CV bd1 = dk == 1 ? d : (active ? dp1[c] : zero);
+                const CV bd1 = dk == 1 ? d : vchunk_or_zero(dp1 + c0, lane, active);
                 s[kPcMem + 2] += vdot(gn_s, bd1);
             }
         }
@@ -658,9 +696,12 @@ struct CombineArgs {
 
 // out = sum_j coef_j basis_j, and <out, basis_j> (pre-update values) for all j
 // plus <out, out>.  In the solver the output is D slot dk, itself basis entry
-// T+1+dk (read before written by the same thread).
-template <typename S, bool PC>
+// T+1+dk (read before written by the same thread).  The instance handles up to
+// KB = 2 TM + 1 basis entries; each workgroup stores one compact row of KB + 1
+// sums (the basis dots, then <out, out>) at a.partials.
+template <typename S, bool PC, int TM>
 __global__ __launch_bounds__(kBlock) void k_combine(CombineArgs<S> a) {
+    constexpr int KB = 2 * TM + 1;
     using CV = typename Chunk<S>::V;
     const SolverState *st = a.st;
     if (st && st->done) return;
@@ -670,20 +711,20 @@ __global__ __launch_bounds__(kBlock) void k_combine(CombineArgs<S> a) {
     if (st) {
         const int oj = st->T + 1 + st->dk;
 #pragma unroll
-        for (int j = 0; j < kMaxBasis; ++j)
+        for (int j = 0; j < KB; ++j)
             if (j == oj) out = const_cast<S *>(a.basis[j]);
     }
-    double cf[kMaxBasis];
+    double cf[KB];
 #pragma unroll
-    for (int j = 0; j < kMaxBasis; ++j) cf[j] = j < NB ? coef[j] : 0.0;
-    double s[kMaxBasis + 1];
+    for (int j = 0; j < KB; ++j) cf[j] = j < NB ? coef[j] : 0.0;
+    double s[KB + 1];
 #pragma unroll
-    for (int j = 0; j <= kMaxBasis; ++j) s[j] = 0.0;
+    for (int j = 0; j <= KB; ++j) s[j] = 0.0;
     constexpr bool pcon = PC;   // row-block H0: the solver's state has precond set
     const int TG = PC ? st->T : -1;                              // G slots 0..TG
     const int64_t cpr = PC ? a.nchunks / (a.pc.n > 0 ? a.pc.n : 1) : 1;  // chunks per row
     for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < a.nchunks; c += (int64_t)gridDim.x * kBlock) {
-        CV b[kMaxBasis];
+        CV b[KB];
         D4 acc{{0.0, 0.0, 0.0, 0.0}};
         if constexpr (pcon) {
             // D = P^{-1} (sum over G slots) + sum over D slots, row by row
@@ -691,7 +732,7 @@ __global__ __launch_bounds__(kBlock) void k_combine(CombineArgs<S> a) {
             const int64_t row = c / cpr;
             double ra = 0.0;
 #pragma unroll
-            for (int j = 0; j < kMaxBasis; ++j) {
+            for (int j = 0; j < KB; ++j) {
                 if (j < NB) {
                     b[j] = reinterpret_cast<const CV *>(a.basis[j])[c];
                     D4 w = widen(b[j]);
@@ -711,7 +752,7 @@ __global__ __launch_bounds__(kBlock) void k_combine(CombineArgs<S> a) {
             for (int e = 0; e < 4; ++e) acc.v[e] = fma(hi, accg.v[e] - kr * r.v[e], acc.v[e]);
         } else {
 #pragma unroll
-            for (int j = 0; j < kMaxBasis; ++j) {
+            for (int j = 0; j < KB; ++j) {
                 if (j < NB) {
                     b[j] = reinterpret_cast<const CV *>(a.basis[j])[c];
                     D4 w = widen(b[j]);
@@ -734,11 +775,11 @@ __global__ __launch_bounds__(kBlock) void k_combine(CombineArgs<S> a) {
             }
         }
 #pragma unroll
-        for (int j = 0; j < kMaxBasis; ++j)
+        for (int j = 0; j < KB; ++j)
             if (j < NB) s[j] += vdot(o, b[j]);
-        s[kMaxBasis] += vdot(o, o);
+        s[KB] += vdot(o, o);
     }
-    block_sums_store<kMaxBasis + 1>(s, a.partials + (size_t)blockIdx.x * kMaxSums);
+    block_sums_store<KB + 1>(s, a.partials + (size_t)blockIdx.x * (KB + 1));
 }
 
 template <typename S>
@@ -767,13 +808,12 @@ __global__ __launch_bounds__(kBlock) void k_grad_init_maxcut(GradInitArgs<S> a) 
     const bool active = lane * NV < a.ld;
     double s[1] = {0.0};
     for (int64_t row = (int64_t)blockIdx.x * GPB + grp; row < a.n; row += (int64_t)gridDim.x * GPB) {
-        const int64_t off = row * a.ld + lane * NV;
+        const int64_t rb = row * a.ld, off = rb + lane * NV;
         const double yt = a.y[row] + sigma * (1.0 - a.rn[row]);
         if (lane == 0) a.ytil[row] = yt;
-        const CV zero = vzero(CV{});
-        const CV rs = active ? *reinterpret_cast<const CV *>(a.R + off) : zero;
+        const CV rs = chunk_or_zero(a.R + rb, lane, active);
         D4 r = widen(rs);
-        D4 cr = widen(active ? *reinterpret_cast<const CV *>(a.CR + off) : zero);
+        D4 cr = widen(chunk_or_zero(a.CR + rb, lane, active));
         D4 g;
 #pragma unroll
         for (int c = 0; c < 4; ++c) g.v[c] = 2.0 * (cr.v[c] - yt * r.v[c]);
@@ -811,12 +851,14 @@ __device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t j) {
 
 template <typename S>
 __global__ __launch_bounds__(kBlock) void k_rank_grow(S *R, int64_t n, int64_t ld, int c0, int c1, uint64_t seed,
-                                                      double scale) {
+                                                      double scale, const int32_t *label) {
     const int w = c1 - c0;
     for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < n * w; e += (int64_t)gridDim.x * kBlock) {
         const int64_t i = e / w;
         const int c = c0 + (int)(e - i * w);
-        const uint64_t k = (uint64_t)i * 65536ull + (uint64_t)c;
+        // the draw belongs to the caller's node: a relabelled problem grows the same columns
+        const uint64_t li = label ? (uint64_t)label[i] : (uint64_t)i;
+        const uint64_t k = li * 65536ull + (uint64_t)c;
         const uint64_t x0 = splitmix64_at(seed, 2 * k), x1 = splitmix64_at(seed, 2 * k + 1);
         const double u0 = ((double)(x0 >> 11) + 0.5) * 0x1.0p-53;
         const double u1 = ((double)(x1 >> 11) + 0.5) * 0x1.0p-53;
@@ -933,50 +975,117 @@ static int update_pc(hipStream_t s, const UpdateArgs<S> &a, const PcBufs &pc, in
     return LRSDP_OK;
 }
 
+// Smallest build of the flat sweeps that holds an L-BFGS memory of T (2T + 1 ring slots).
+static int mem_build(int T) { return T <= 1 ? 1 : (T <= 2 ? 2 : (T <= 4 ? 4 : 8)); }
+
+// Workgroups of a flat sweep over nch chunks whose compact sum rows hold K doubles.
+static int flat_grid(int64_t nch, int K) {
+    const int64_t need = (nch + kBlock - 1) / kBlock;
+    const int64_t cap = (int64_t)(kL1Bytes / (sizeof(double) * (size_t)K)) / kL1PerL2 * kL1PerL2;
+    return (int)std::max<int64_t>(1, std::min(need, cap));
+}
+
+// Second level of a flat sweep's sums into `partials`; returns the row count.
+template <int K>
+static int sum_l1(hipStream_t s, const SolverState *st, const double *l1, int rows1, int split, int last_col,
+                  double *partials) {
+    const int rows2 = (rows1 + kL1PerL2 - 1) / kL1PerL2;
+    hipLaunchKernelGGL(k_sum_l1<K>, dim3(rows2), dim3(kL1PerL2), 0, s, st, l1, rows1, split, last_col, partials);
+    return rows2;
+}
+
+template <typename S, int TM>
+static int update_flat(hipStream_t s, UpdateArgs<S> a, double *partials, double *l1) {
+    constexpr int KS = 2 * TM + 1;
+    const int g = flat_grid(a.nchunks, KS);
+    a.partials = l1;
+    hipLaunchKernelGGL((k_update_maxcut<S, TM>), dim3(g), dim3(kBlock), 0, s, a);
+    return sum_l1<KS>(s, a.st, l1, g, TM + 1, -1, partials);
+}
+
+template <typename S>
+static int update_flat_t(hipStream_t s, const UpdateArgs<S> &a, int T, double *partials, double *l1) {
+    switch (mem_build(T)) {
+        case 1: return update_flat<S, 1>(s, a, partials, l1);
+        case 2: return update_flat<S, 2>(s, a, partials, l1);
+        case 4: return update_flat<S, 4>(s, a, partials, l1);
+        default: return update_flat<S, 8>(s, a, partials, l1);
+    }
+}
+
 int launch_update_maxcut(hipStream_t s, int prec, SolverState *st, void *R, const void *CD, const double *y,
                          const double *rn, const double *q1, const double *q2, const double *ytil_in,
                          double *ytil_out, void *const *gring, void *const *dring, int T, int64_t n, int64_t ld,
-                         double *partials, int *nb, const PcBufs *pc) {
+                         double *partials, double *l1, int *nb, const PcBufs *pc) {
+    if (T < 1 || T > kMaxMem) return set_error(LRSDP_EINVAL, "L-BFGS memory %d outside [1, %d]", T, kMaxMem);
     const int cpr = chunks_per_row(prec, ld);
     const int64_t nch = n * cpr;
-    *nb = grid_for(nch, kBlock);
     if (prec == LRSDP_F64) {
         UpdateArgs<double> a{st, (double *)R, (const double *)CD, y, rn, q1, q2, ytil_in, ytil_out, {}, nch, cpr,
                              partials};
         for (int g = 0; g <= T; ++g) a.rings.g[g] = (double *)gring[g];
         for (int d = 0; d < T; ++d) a.rings.d[d] = (double *)dring[d];
         if (pc) update_pc<double>(s, a, *pc, ld, cpr, nb);
-        else hipLaunchKernelGGL(k_update_maxcut<double>, dim3(*nb), dim3(kBlock), 0, s, a);
+        else *nb = update_flat_t<double>(s, a, T, partials, l1);
     } else {
         UpdateArgs<float> a{st, (float *)R, (const float *)CD, y, rn, q1, q2, ytil_in, ytil_out, {}, nch, cpr,
                             partials};
         for (int g = 0; g <= T; ++g) a.rings.g[g] = (float *)gring[g];
         for (int d = 0; d < T; ++d) a.rings.d[d] = (float *)dring[d];
         if (pc) update_pc<float>(s, a, *pc, ld, cpr, nb);
-        else hipLaunchKernelGGL(k_update_maxcut<float>, dim3(*nb), dim3(kBlock), 0, s, a);
+        else *nb = update_flat_t<float>(s, a, T, partials, l1);
     }
     LRSDP_CHECK_LAUNCH();
     return LRSDP_OK;
 }
 
+template <typename S, bool PC, int TM>
+static int combine_flat(hipStream_t s, CombineArgs<S> a, double *partials, double *l1) {
+    constexpr int K = 2 * TM + 2;
+    const int g = flat_grid(a.nchunks, K);
+    a.partials = l1;
+    hipLaunchKernelGGL((k_combine<S, PC, TM>), dim3(g), dim3(kBlock), 0, s, a);
+    return sum_l1<K>(s, a.st, l1, g, K, kMaxBasis, partials);
+}
+
+// nb basis entries need a build with 2 TM + 1 >= nb; the row-block H0 only
+// comes with memories up to kPcMem = 2.
+template <typename S, bool PC>
+static int combine_flat_t(hipStream_t s, const CombineArgs<S> &a, int nb, double *partials, double *l1) {
+    const int tm = mem_build(nb / 2);
+    if constexpr (PC) {
+        if (tm == 1) return combine_flat<S, true, 1>(s, a, partials, l1);
+        return combine_flat<S, true, 2>(s, a, partials, l1);
+    } else {
+        switch (tm) {
+            case 1: return combine_flat<S, false, 1>(s, a, partials, l1);
+            case 2: return combine_flat<S, false, 2>(s, a, partials, l1);
+            case 4: return combine_flat<S, false, 4>(s, a, partials, l1);
+            default: return combine_flat<S, false, 8>(s, a, partials, l1);
+        }
+    }
+}
+
 // basis: nb device arrays of n*ld elements; out = sum coef_j basis_j.
 int launch_combine(hipStream_t s, int prec, SolverState *st, const double *coef, const void *const *basis, int nb,
-                   void *out, int64_t n, int64_t ld, double *partials, int *nblk, uint16_t *shadow, const void *R,
-                   const PcBufs *pc) {
+                   void *out, int64_t n, int64_t ld, double *partials, double *l1, int *nblk, uint16_t *shadow,
+                   const void *R, const PcBufs *pc) {
+    if (nb < 1 || nb > kMaxBasis) return set_error(LRSDP_EINVAL, "basis of %d vectors outside [1, %d]", nb, kMaxBasis);
+    if (pc && nb > 2 * kPcMem + 1)
+        return set_error(LRSDP_EINVAL, "row-block H0 takes an L-BFGS memory of at most %d", kPcMem);
     const int64_t nch = n * ld * (prec == LRSDP_F64 ? 8 : 4) / 16;
-    *nblk = grid_for(nch, kBlock);
     const PcBufs p = pc ? *pc : PcBufs{nullptr, nullptr, nullptr, n, 0, nullptr, nullptr, 1.0};
     if (prec == LRSDP_F64) {
         CombineArgs<double> a{st, coef, {}, nb, (double *)out, nch, partials, nullptr, ld, ld, (const double *)R, p};
         for (int j = 0; j < nb; ++j) a.basis[j] = (const double *)basis[j];
-        if (pc) hipLaunchKernelGGL((k_combine<double, true>), dim3(*nblk), dim3(kBlock), 0, s, a);
-        else hipLaunchKernelGGL((k_combine<double, false>), dim3(*nblk), dim3(kBlock), 0, s, a);
+        if (pc) *nblk = combine_flat_t<double, true>(s, a, nb, partials, l1);
+        else *nblk = combine_flat_t<double, false>(s, a, nb, partials, l1);
     } else {
         CombineArgs<float> a{st, coef, {}, nb, (float *)out, nch, partials, shadow, ld, bf16_ld(ld), (const float *)R,
                              p};
         for (int j = 0; j < nb; ++j) a.basis[j] = (const float *)basis[j];
-        if (pc) hipLaunchKernelGGL((k_combine<float, true>), dim3(*nblk), dim3(kBlock), 0, s, a);
-        else hipLaunchKernelGGL((k_combine<float, false>), dim3(*nblk), dim3(kBlock), 0, s, a);
+        if (pc) *nblk = combine_flat_t<float, true>(s, a, nb, partials, l1);
+        else *nblk = combine_flat_t<float, false>(s, a, nb, partials, l1);
     }
     LRSDP_CHECK_LAUNCH();
     return LRSDP_OK;
@@ -1006,13 +1115,52 @@ int launch_grad_init_maxcut(hipStream_t s, int prec, SolverState *st, const void
 }
 
 int launch_rank_grow(hipStream_t s, int prec, void *R, int64_t n, int64_t ld, int c0, int c1, uint64_t seed,
-                     double scale) {
+                     double scale, const int32_t *label) {
     if (c1 <= c0) return LRSDP_OK;
     const int nb = grid_for(n * (c1 - c0), kBlock);
     if (prec == LRSDP_F64)
-        hipLaunchKernelGGL(k_rank_grow<double>, dim3(nb), dim3(kBlock), 0, s, (double *)R, n, ld, c0, c1, seed, scale);
+        hipLaunchKernelGGL(k_rank_grow<double>, dim3(nb), dim3(kBlock), 0, s, (double *)R, n, ld, c0, c1, seed, scale,
+                           label);
     else
-        hipLaunchKernelGGL(k_rank_grow<float>, dim3(nb), dim3(kBlock), 0, s, (float *)R, n, ld, c0, c1, seed, scale);
+        hipLaunchKernelGGL(k_rank_grow<float>, dim3(nb), dim3(kBlock), 0, s, (float *)R, n, ld, c0, c1, seed, scale,
+                           label);
+    LRSDP_CHECK_LAUNCH();
+    return LRSDP_OK;
+}
+
+// Node-order moves (declared in internal.h).
+__global__ __launch_bounds__(kBlock) void k_permute_rows(const int4 *src, int4 *dst, const int32_t *perm, int64_t n,
+                                                         int64_t cpr, int scatter) {
+    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < n * cpr; e += (int64_t)gridDim.x * kBlock) {
+        const int64_t k = e / cpr, q = e - k * cpr, j = perm[k];
+        if (scatter) dst[j * cpr + q] = src[e];
+        else dst[e] = src[j * cpr + q];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_permute_vec(const double *src, double *dst, const int32_t *perm,
+                                                        int64_t n, int scatter) {
+    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < n; k += (int64_t)gridDim.x * kBlock) {
+        if (scatter) dst[perm[k]] = src[k];
+        else dst[k] = src[perm[k]];
+    }
+}
+
+int launch_permute_rows(hipStream_t s, const void *src, void *dst, const int32_t *perm, int64_t n, int64_t row_bytes,
+                        int scatter) {
+    if (row_bytes % 16 != 0) return set_error(LRSDP_EINVAL, "row of %lld bytes is not a multiple of 16",
+                                              (long long)row_bytes);
+    if (n <= 0) return LRSDP_OK;
+    const int64_t cpr = row_bytes / 16;
+    hipLaunchKernelGGL(k_permute_rows, dim3(grid_for(n * cpr, kBlock)), dim3(kBlock), 0, s, (const int4 *)src,
+                       (int4 *)dst, perm, n, cpr, scatter);
+    LRSDP_CHECK_LAUNCH();
+    return LRSDP_OK;
+}
+
+int launch_permute_vec(hipStream_t s, const double *src, double *dst, const int32_t *perm, int64_t n, int scatter) {
+    if (n <= 0) return LRSDP_OK;
+    hipLaunchKernelGGL(k_permute_vec, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, src, dst, perm, n, scatter);
     LRSDP_CHECK_LAUNCH();
     return LRSDP_OK;
 }

@@ -145,9 +145,9 @@ __device__ __forceinline__ void load_own(const DevCsr &P, const SpmmArgs &a, int
         for (int q = 0; q < NC; ++q) {
             const int ci = lane * NC + q;
             const bool act = active && ci * NV < a.ld;
-            const int64_t off = (int64_t)row * a.ld + ci * NV;
-            o.d[q] = act ? *reinterpret_cast<const CV *>(Dn + off) : zero;
-            o.r[q] = act ? *reinterpret_cast<const CV *>((const S *)a.R + off) : zero;
+            const int64_t rb = (int64_t)row * a.ld;
+            o.d[q] = chunk_or_zero(Dn + rb, ci, act);
+            o.r[q] = chunk_or_zero((const S *)a.R + rb, ci, act);
         }
         o.diag = P.diag[row];
         o.ytil = a.ytil[row];
@@ -170,18 +170,19 @@ __device__ __forceinline__ void epilogue(const DevCsr &P, const SpmmArgs &a, int
     for (int q = 0; q < NC; ++q) vscale(acc[q], cs);
     const S dg = (S)(a.cs * (EPI == kEpiLS ? own.diag : P.diag[row]));
     const CV zero = vzero(CV{});
+    const int64_t rb = (int64_t)row * a.ld;
     int64_t off[NC];
     bool act[NC];
 #pragma unroll
     for (int q = 0; q < NC; ++q) {
         const int ci = lane * NC + q;
         act[q] = active && ci * NV < a.ld;
-        off[q] = (int64_t)row * a.ld + ci * NV;
+        off[q] = rb + ci * NV;
     }
     if constexpr (EPI == kEpiPlain) {
         CV v[NC];
         if constexpr (NC == 1) {
-            v[0] = act[0] ? *reinterpret_cast<const CV *>((const S *)a.V + off[0]) : zero;
+            v[0] = chunk_or_zero((const S *)a.V + rb, lane, act[0]);
         } else {
             // own row from the bfloat16 input (lanes past the row hold zeros)
 #pragma unroll
@@ -208,7 +209,7 @@ __device__ __forceinline__ void epilogue(const DevCsr &P, const SpmmArgs &a, int
             q2 += vdot(d, d);
             if (a.rn) rr += vdot(r, r);
             if (a.aux) {
-                const CV cr = act[q] ? *reinterpret_cast<const CV *>((const S *)a.aux + off[q]) : zero;
+                const CV cr = chunk_or_zero((const S *)a.aux + rb, lane * NC + q, act[q]);
                 p1 += vdot(cr, d);
             }
         }
@@ -231,7 +232,7 @@ __device__ __forceinline__ void epilogue(const DevCsr &P, const SpmmArgs &a, int
             if (a.rn) a.rn[row] = rr;
         }
     } else if constexpr (EPI == kEpiSplit) {  // NC = 1
-        const CV v = act[0] ? *reinterpret_cast<const CV *>((const S *)a.V + off[0]) : zero;
+        const CV v = chunk_or_zero((const S *)a.V + rb, lane, act[0]);
         vfma(acc[0], dg, v);                                   // (C V)_i
         const double coef = a.y[row] + 2.0 * a.sigma;
         D4 vv4 = widen(v), cv4 = widen(acc[0]), b4;
@@ -253,7 +254,7 @@ __device__ __forceinline__ void epilogue(const DevCsr &P, const SpmmArgs &a, int
         narrow(u4, us);
         if (act[0]) *reinterpret_cast<CV *>((S *)a.Y + off[0]) = us;
         if (a.R) {
-            const CV r = act[0] ? *reinterpret_cast<const CV *>((const S *)a.R + off[0]) : zero;
+            const CV r = chunk_or_zero((const S *)a.R + rb, lane, act[0]);
             const double ru = group_sum<GS>(vdot(r, us));
             if (lane == 0) a.y[row] += a.sigma * (1.0 - ru);
         }
@@ -261,7 +262,7 @@ __device__ __forceinline__ void epilogue(const DevCsr &P, const SpmmArgs &a, int
         double obj = 0.0, rn = 0.0;
 #pragma unroll
         for (int q = 0; q < NC; ++q) {
-            const CV r = act[q] ? *reinterpret_cast<const CV *>((const S *)a.V + off[q]) : zero;
+            const CV r = chunk_or_zero((const S *)a.V + rb, lane * NC + q, act[q]);
             vfma(acc[q], dg, r);
             if (act[q] && a.Y) *reinterpret_cast<CV *>((S *)a.Y + off[q]) = acc[q];
             obj += vdot(r, acc[q]);

@@ -70,6 +70,10 @@ __device__ __forceinline__ void write_features(const float4 si, int deg, double 
         *reinterpret_cast<float4 *>(out + q) = make_float4(f[q], f[q + 1], f[q + 2], f[q + 3]);
 }
 
+// Caller label of internal node i: per-node outputs and the statistics table
+// are in the caller's order for a problem relabelled by degree.
+__device__ __forceinline__ int64_t lab(const DevCsr &P, int64_t i) { return P.perm ? (int64_t)P.perm[i] : i; }
+
 // pass 1: per-node (d, s, a, l)
 template <int W>
 __global__ __launch_bounds__(kBlock) void k_node_stats(DevCsr P, float4 *stats) {
@@ -83,7 +87,7 @@ __global__ __launch_bounds__(kBlock) void k_node_stats(DevCsr P, float4 *stats) 
             a += fabs(w);
         }
         const float d = (float)(e - b);
-        stats[i] = make_float4(d, (float)s, (float)a, (float)log1p((double)(e - b)));
+        stats[lab(P, i)] = make_float4(d, (float)s, (float)a, (float)log1p((double)(e - b)));
     }
 }
 
@@ -94,7 +98,7 @@ __global__ __launch_bounds__(kBlock) void k_features(DevCsr P, const float4 *sta
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < P.n; i += (int64_t)gridDim.x * kBlock) {
         const int b = P.row_ptr[i], e = P.row_ptr[i + 1];
         if (e - b > kSegLen) continue;   // hub rows: k_features_heavy
-        const float4 si = stats[i];
+        const float4 si = stats[lab(P, i)];
         const float d = si.x, l = si.w;
         // Neighbour sums in double: the spread feature (std of l over the
         // neighbours) cancels badly in float for hubs whose neighbours have
@@ -104,7 +108,7 @@ __global__ __launch_bounds__(kBlock) void k_features(DevCsr P, const float4 *sta
         for (int k = b; k < e; ++k) {
             const int32_t c = P.col[k];
             const double w = edge_w<W>(P, k, c);
-            const float4 sj = stats[c & 0x7fffffff];
+            const float4 sj = stats[lab(P, c & 0x7fffffff)];
             const double lj = (double)sj.w - (double)l;
             sl += lj;
             sl2 += lj * lj;
@@ -114,7 +118,7 @@ __global__ __launch_bounds__(kBlock) void k_features(DevCsr P, const float4 *sta
             lmax = fmaxf(lmax, sj.w);
             sdd += (double)sj.x / ((double)d + (double)sj.x);
         }
-        write_features(si, e - b, sl, sl2, swb, sinv, sw, sdd, lmax, dbar, logn20, F + i * kNF);
+        write_features(si, e - b, sl, sl2, swb, sinv, sw, sdd, lmax, dbar, logn20, F + lab(P, i) * kNF);
     }
 }
 
@@ -148,7 +152,7 @@ __global__ __launch_bounds__(kBlock) void k_node_stats_heavy(DevCsr P, float4 *s
                 ts += sh[q][0];
                 ta += sh[q][1];
             }
-            stats[i] = make_float4((float)(e - b), (float)ts, (float)ta, (float)log1p((double)(e - b)));
+            stats[lab(P, i)] = make_float4((float)(e - b), (float)ts, (float)ta, (float)log1p((double)(e - b)));
         }
     }
 }
@@ -162,14 +166,14 @@ __global__ __launch_bounds__(kBlock) void k_features_heavy(DevCsr P, const float
     for (int64_t h = blockIdx.x; h < P.n_heavy; h += gridDim.x) {
         const int64_t i = P.heavy[h];
         const int b = P.row_ptr[i], e = P.row_ptr[i + 1];
-        const float4 si = stats[i];
+        const float4 si = stats[lab(P, i)];
         const float d = si.x, l = si.w;
         double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // sl, sl2, swb, sinv, sw, sdd
         float lmax = -1e30f;
         for (int k = b + threadIdx.x; k < e; k += kBlock) {
             const int32_t c = P.col[k];
             const double w = edge_w<W>(P, k, c);
-            const float4 sj = stats[c & 0x7fffffff];
+            const float4 sj = stats[lab(P, c & 0x7fffffff)];
             const double lj = (double)sj.w - (double)l;
             v[0] += lj;
             v[1] += lj * lj;
@@ -198,7 +202,7 @@ __global__ __launch_bounds__(kBlock) void k_features_heavy(DevCsr P, const float
                 for (int q = 0; q < 6; ++q) t[q] += sh[w][q];
                 tm = fmaxf(tm, shm[w]);
             }
-            write_features(si, e - b, t[0], t[1], t[2], t[3], t[4], t[5], tm, dbar, logn20, F + i * kNF);
+            write_features(si, e - b, t[0], t[1], t[2], t[3], t[4], t[5], tm, dbar, logn20, F + lab(P, i) * kNF);
         }
     }
 }

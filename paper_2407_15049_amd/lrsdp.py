@@ -23,6 +23,7 @@ EINVAL, ENOMEM, EHIP, ENUMERIC, EUNSUPPORTED = -1, -2, -3, -4, -5
 F64, F32, F32_BF16IN = 0, 1, 2
 MAXCUT, COMPLETION, GENERAL = 1, 2, 3
 C_AUTO, C_SPARSE, C_DENSE = 0, 1, 2
+ORDER_INPUT, ORDER_DEGREE = 0, 1
 
 
 class LrsdpUnavailable(ImportError):
@@ -69,6 +70,7 @@ class ProblemInfo(C.Structure):
         ("kind", C.c_int), ("n", C.c_int64), ("m", C.c_int64), ("nnz", C.c_int64),
         ("n1", C.c_int64), ("n2", C.c_int64), ("weights", C.c_int), ("max_row_nnz", C.c_int64),
         ("c_l1", C.c_double), ("b_l1", C.c_double), ("b_inf", C.c_double), ("c_dense", C.c_int),
+        ("node_order", C.c_int),
     ]
 
 
@@ -91,6 +93,7 @@ _SIGS = {
     "lrsdp_ctx_create": (C.c_int, [C.c_int, _P, C.POINTER(_P)]),
     "lrsdp_ctx_destroy": (None, [_P]),
     "lrsdp_problem_maxcut": (C.c_int, [_I64, _I64, _P, _P, _P, C.POINTER(_P)]),
+    "lrsdp_problem_maxcut_ex": (C.c_int, [_I64, _I64, _P, _P, _P, C.c_int, C.POINTER(_P)]),
     "lrsdp_problem_completion": (C.c_int, [_I64, _I64, _I64, _P, _P, _P, C.POINTER(_P)]),
     "lrsdp_problem_general": (C.c_int, [_I64, _I64, _P, _P, _P, _I64, _I64, _P, _P, _P, _P, _P, C.POINTER(_P)]),
     "lrsdp_problem_general_ex": (C.c_int, [_I64, _I64, _P, _P, _P, _I64, _I64, _P, _P, _P, _P, _P, C.c_int,
@@ -222,7 +225,9 @@ class Problem:
         self.dev = None
 
     @classmethod
-    def maxcut(cls, n, u, v, w=None):
+    def maxcut(cls, n, u, v, w=None, node_order=None):
+        """node_order: None or ORDER_INPUT (lrsdp_problem_maxcut), ORDER_DEGREE
+        (lrsdp_problem_maxcut_ex)."""
         lib = load()
         ua, up = _host(u, np.int32)
         va, vp = _host(v, np.int32)
@@ -231,7 +236,10 @@ class Problem:
         else:
             wp = None
         h = C.c_void_p()
-        _check(lib.lrsdp_problem_maxcut(int(n), len(ua), up, vp, wp, C.byref(h)))
+        if node_order is None:
+            _check(lib.lrsdp_problem_maxcut(int(n), len(ua), up, vp, wp, C.byref(h)))
+        else:
+            _check(lib.lrsdp_problem_maxcut_ex(int(n), len(ua), up, vp, wp, int(node_order), C.byref(h)))
         return cls(h)
 
     @classmethod

@@ -56,6 +56,35 @@ def test_maxcut_rejects_malformed_edges(u, v, msg):
     assert e.value.code == L.EINVAL and msg in str(e.value)
 
 
+@pytest.mark.parametrize("u,v,msg", [
+    ([0, 1], [1, 5], "outside"),
+    ([0, 2], [1, 2], "self loop"),
+    ([0, 1], [1, 0], "more than once"),
+])
+def test_degree_order_rejects_malformed_edges(u, v, msg):
+    with pytest.raises(L.LrsdpError) as e:
+        L.Problem.maxcut(5, u, v, node_order=L.ORDER_DEGREE)
+    assert e.value.code == L.EINVAL and msg in str(e.value)
+
+
+def test_degree_order_names_caller_labels_and_keeps_constants():
+    # node 3 has the largest degree, so it is internal node 0; a repeated edge is
+    # reported in the caller's labels
+    u = [3, 3, 3, 0, 3]
+    v = [0, 1, 2, 1, 4]
+    p = L.Problem.maxcut(6, u, v, node_order=L.ORDER_DEGREE)
+    q = L.Problem.maxcut(6, u, v)
+    assert p.info.node_order == L.ORDER_DEGREE and q.info.node_order == L.ORDER_INPUT
+    for f in ("n", "m", "nnz", "weights", "max_row_nnz", "c_l1", "b_l1", "b_inf"):
+        assert getattr(p.info, f) == getattr(q.info, f), f
+    with pytest.raises(L.LrsdpError) as e:
+        L.Problem.maxcut(6, u + [4], v + [3], node_order=L.ORDER_DEGREE)
+    assert e.value.code == L.EINVAL and "(3, 4)" in str(e.value)
+    with pytest.raises(L.LrsdpError) as e:
+        L.Problem.maxcut(6, u, v, node_order=7)
+    assert e.value.code == L.EINVAL
+
+
 def test_maxcut_rejects_nonfinite_weight():
     with pytest.raises(L.LrsdpError):
         L.Problem.maxcut(4, [0, 1], [1, 2], [1.0, np.nan])

@@ -6,8 +6,9 @@ multiplier objective b^T y, err1 and err3 (error measures of the experimental
 setting) of float64 and float32 solves of the two 1e6-node MaxCut instances
 (Erdos-Renyi and Chung-Lu, 5e6 edges, +-1 weights, rank 20), and checking the
 library's own report against that to 1e-10 relative (err1, which is formed
-from residuals of order 1e-7 after cancellation, to 1e-8), plus the float32
-result against the float64 one on the objective.
+from residuals of order 1e-7 after cancellation, to 1e-8; the float32
+objective, which the library takes from the SpMM's float32 accumulation, to
+1e-6), plus the float32 result against the float64 one on the objective.
 """
 
 import numpy as np
@@ -50,10 +51,14 @@ def test_oracle_remeasures_1m_solves(ctx, name):
         assert rc == L.OK
         m = K.alm_measures(op, host(Rd, r), yd.cpu().numpy())
         print("oracle", m, flush=True)
-        assert abs(m["obj"] - res.obj) <= 1e-10 * abs(m["obj"])
+        # float32 storage: the library's objective comes from the SpMM's float32
+        # accumulation (relative error of order 1e-7 per row sum), the rest of the
+        # measures from float64 sums of the stored values
+        tobj = 1e-10 if prec == L.F64 else 1e-6
+        assert abs(m["obj"] - res.obj) <= tobj * abs(m["obj"])
         assert abs(m["dual"] - res.dual) <= 1e-10 * abs(m["dual"])
         assert abs(m["err1"] - res.err1) <= 1e-8 * m["err1"] + 1e-16
-        assert abs(m["err3"] - res.err3) <= 1e-10
+        assert abs(m["err3"] - res.err3) <= tobj
         assert m["err1"] <= 1e-5 and abs(m["err3"]) <= 1e-5
         objs[prec] = m["obj"]
     # float32 storage reaches the same tolerance; the two stationary points agree
