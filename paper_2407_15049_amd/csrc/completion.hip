@@ -55,31 +55,42 @@ __device__ __forceinline__ void cmp_gather(const int32_t *__restrict__ ptr, cons
     constexpr int NT = PW / GS;             // samples per lane and pass
     constexpr int KB = 8;                   // partner rows in flight per lane
     const int b = ptr[row], e = ptr[row + 1];
+    if (b >= e) return;
+    // Indices and weights of the pass starting at k (k < e): every lane loads,
+    // past the row's end repeating the last sample (the gather below stops at
+    // the pass's count, so those entries are never used), so that no load sits
+    // behind a branch: all index loads, then all ytil gathers, are in flight
+    // together.
+    auto load_pass = [&](int k, int32_t(&j)[NT], double(&w)[NT]) {
+        const int cnt = min(PW, e - k);
+        int32_t ev[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int q = min(lane + t * GS, cnt - 1);
+            j[t] = nbr[k + q];
+            ev[t] = eid[k + q];
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) w[t] = ytil[ev[t]];
+    };
     // indices and weights of the first pass; each pass loads the next one's
-    // before its own partner rows, so their latency overlaps the gather
+    // before its own partner rows, so their latency overlaps the gather (the
+    // next weights stay float64 until the pass ends, so that no conversion
+    // waits for them early)
     int32_t jj[NT];
     S ww[NT];
+    {
+        double w0[NT];
+        load_pass(b, jj, w0);
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-        const int q = lane + t * GS;
-        const bool in = q < min(PW, e - b);
-        jj[t] = in ? nbr[b + q] : 0;
-        ww[t] = in ? (S)ytil[eid[b + q]] : (S)0;
+        for (int t = 0; t < NT; ++t) ww[t] = (S)w0[t];
     }
     for (int k0 = b; k0 < e; k0 += PW) {
         const int cnt = min(PW, e - k0);     // the same for every lane of the group
         int32_t jn[NT] = {};
-        S wn[NT] = {};
+        double wn[NT] = {};
         const int k1 = k0 + PW;
-        if (k1 < e) {
-#pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                const int q = lane + t * GS;
-                const bool in = q < min(PW, e - k1);
-                jn[t] = in ? nbr[k1 + q] : 0;
-                wn[t] = in ? (S)ytil[eid[k1 + q]] : (S)0;
-            }
-        }
+        if (k1 < e) load_pass(k1, jn, wn);
 #pragma unroll
         for (int q0 = 0; q0 < PW; q0 += KB) {
             if (q0 >= cnt) break;
@@ -103,7 +114,7 @@ __device__ __forceinline__ void cmp_gather(const int32_t *__restrict__ ptr, cons
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
             jj[t] = jn[t];
-            ww[t] = wn[t];
+            ww[t] = (S)wn[t];
         }
     }
 }
