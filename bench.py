@@ -231,6 +231,11 @@ def main():
     copy_gbs = copy_ceiling(torch, dev, args.copy_calibration) if step_times else None
 
     comparison_paths(args, ctx, dev, L, runs, paths, enabled, left, reserve_cpu, solve, log)
+    if args.cert:   # the FP64 step's multipliers (the comparison paths certify their own)
+        for run in runs:
+            rec = paths["f64"].get(run["name"])
+            if rec and run["per"][L.F64]["y"] is not None and left() > reserve_cpu + 20:
+                rec.update(cert_of(args, ctx, dev, L, run, run["per"][L.F64]["y"], rec["obj"]))
 
     cpu = None
     if not args.no_cpu_baseline and step_times:
@@ -423,11 +428,6 @@ def comparison_paths(args, ctx, dev, L, runs, paths, enabled, left, reserve_cpu,
                 torch.cuda.synchronize()
                 record(path, run, time.perf_counter() - t0, rc, res, y=y)
                 del prob2, ws, R, y
-    if args.cert:
-        for run in runs:
-            rec = paths["f64"].get(run["name"])
-            if rec and left() > reserve_cpu + 20:
-                rec.update(cert_of(args, ctx, dev, L, run, run["per"][L.F64]["y"], rec["obj"]))
 
 
 def cert_of(args, ctx, dev, L, run, y, obj):
@@ -440,8 +440,10 @@ def cert_of(args, ctx, dev, L, run, y, obj):
     c = L.certify(ctx, run["prob"], y, max_iter=args.cert_iters, tol=1e-8 * abs(obj) / run["n"], work=work)
     dt = time.perf_counter() - t0
     gap = (obj - c.dual_bound) / (1.0 + abs(obj) + abs(c.dual_bound))
-    return dict(lambda_min=c.lambda_min, cert_resid=c.resid, dual_bound_est=c.dual_bound, gap_est=gap,
-                err2=c.err2, cert_iters=c.iters, cert_s=round(dt, 3))
+    return dict(lambda_min=c.lambda_min, lambda_max_ritz=c.lambda_max, cert_resid=c.resid,
+                cert_resid_rel=c.resid / max(abs(c.lambda_min), abs(c.lambda_max), 1e-300),
+                dual_bound_est=c.dual_bound, gap_est=gap, err2=c.err2, cert_iters=c.iters, cert_status=c.status,
+                cert_s=round(dt, 3))
 
 
 TRAFFIC_PROFILES = {

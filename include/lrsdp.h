@@ -506,10 +506,14 @@ typedef struct {
                             space became invariant (resid = 0, lambda exact up to
                             rounding)                                             */
     int     block;       /* block size (8)                                        */
+    double  lambda_max;  /* largest Ritz value (<= the true lambda_max): with
+                            lambda_min, a lower estimate of ||S||_2 against
+                            which resid can be read                              */
 } lrsdp_cert;
 
 /* Device workspace for lrsdp_certify with at most max_iter steps:
- * 4 n x 8 float64 blocks plus max_iter KB and 0.3 MB of partial sums. */
+ * 4 n x 8 float64 blocks, an n-vector (y in the library's node order), max_iter
+ * KB and 0.3 MB of partial sums. */
 int lrsdp_certify_workspace_bytes(const lrsdp_problem *prob, int max_iter,
                                   size_t *bytes);
 
@@ -519,9 +523,10 @@ int lrsdp_certify_workspace_bytes(const lrsdp_problem *prob, int max_iter,
  * device memory, 256-byte aligned, of lrsdp_certify_workspace_bytes.
  * Synchronises the context stream.  Errors: EINVAL (arguments, not uploaded),
  * EUNSUPPORTED (n < 16), ENOMEM (workspace short), ENUMERIC (rank-deficient
- * start block or non-finite values).  The bound is exact up to the loss of
- * orthogonality of the Lanczos basis (re-orthogonalised only against the two
- * previous blocks).
+ * start block or non-finite values).  The Ritz values are exact up to the loss
+ * of orthogonality of the Lanczos basis (re-orthogonalised only against the two
+ * previous blocks); the bound built on them is an estimate (above).  y is in
+ * the caller's node labels for a problem relabelled by degree.
  */
 int lrsdp_certify(lrsdp_ctx *ctx, const lrsdp_problem *prob, const double *y,
                   int max_iter, double tol, uint64_t seed, void *work,

@@ -392,7 +392,8 @@ bool band_spd_solve(const std::vector<double> &band, int N, double sigma, std::v
 
 // theta = lambda_min(T_k) and the residual norm ||B_last s_last|| of its Ritz
 // pair (0 when has_next is false: the Krylov space is invariant).
-void ritz_min(const std::vector<CertStep> &st, int k, bool has_next, double *theta, double *resid) {
+void ritz_min(const std::vector<CertStep> &st, int k, bool has_next, double *theta, double *resid,
+              double *theta_max = nullptr) {
     const int N = k * kCB, W = kCB + 1;
     const std::vector<double> band = assemble_band(st, k);
     double lo = INFINITY, hi = -INFINITY, amax = 0.0;
@@ -414,6 +415,15 @@ void ritz_min(const std::vector<CertStep> &st, int k, bool has_next, double *the
         else a = mid;
     }
     *theta = 0.5 * (a + b);
+    if (theta_max) {  // the largest Ritz value: inf { sigma : count_below(sigma) >= N }
+        double a2 = lo - 1e-12 * (amax + 1.0), b2 = hi + 1e-12 * (amax + 1.0);
+        for (int it = 0; it < 200 && b2 - a2 > 4e-16 * std::max(std::fabs(a2), std::fabs(b2)) + 1e-300; ++it) {
+            const double mid = 0.5 * (a2 + b2);
+            if (count_below(band, N, mid, tiny) >= N) b2 = mid;
+            else a2 = mid;
+        }
+        *theta_max = 0.5 * (a2 + b2);
+    }
     *resid = 0.0;
     if (!has_next) return;
     // inverse iteration just below theta
@@ -546,7 +556,7 @@ static int certify_run(lrsdp_ctx *c, const lrsdp_problem *p, const double *y, in
     std::vector<CertStep> host;
     int cur = 0, prev = -1;
     int64_t done = 0;
-    double theta = NAN, resid = NAN;
+    double theta = NAN, resid = NAN, theta_max = NAN;
     int status = 1;
     for (int j = 0; j < max_iter; ++j) {
         if ((rc = apply_s(s, p, Q[cur], y, Wb))) return rc;
@@ -592,6 +602,10 @@ static int certify_run(lrsdp_ctx *c, const lrsdp_problem *p, const double *y, in
             break;
         }
     }
+    if (done > 0 && (int64_t)host.size() >= done) {   // the largest Ritz value of the final space (once)
+        double t2 = 0.0, r2 = 0.0;
+        ritz_min(host, (int)done, false, &t2, &r2, &theta_max);
+    }
     double hby = 0.0;
     LRSDP_HIP_TRY(hipMemcpyAsync(&hby, by, sizeof(double), hipMemcpyDeviceToHost, s));
     LRSDP_HIP_TRY(hipStreamSynchronize(s));
@@ -606,6 +620,7 @@ static int certify_run(lrsdp_ctx *c, const lrsdp_problem *p, const double *y, in
     out->iters = done;
     out->status = status;
     out->block = kCB;
+    out->lambda_max = theta_max;
     return LRSDP_OK;
 }
 

@@ -78,7 +78,7 @@ class Cert(C.Structure):
     _fields_ = [
         ("lambda_min", C.c_double), ("resid", C.c_double), ("lambda_lb", C.c_double),
         ("dual_bound", C.c_double), ("err2", C.c_double), ("by", C.c_double),
-        ("iters", C.c_int64), ("status", C.c_int), ("block", C.c_int),
+        ("iters", C.c_int64), ("status", C.c_int), ("block", C.c_int), ("lambda_max", C.c_double),
     ]
 
     def as_dict(self):

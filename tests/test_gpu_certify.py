@@ -83,6 +83,12 @@ def test_maxcut_lambda_min_parity(ctx, case):
     bound = certify.maxcut_dual_bound(op, y)
     assert abs(cert.dual_bound - bound) <= n * max(cert.resid, 1e-9 * scale) + 1e-9 * abs(bound)
     assert cert.err2 == pytest.approx(max(0.0, -cert.lambda_min) / (1 + op.c_l1), rel=1e-12, abs=1e-300)
+    # the largest Ritz value: a lower estimate of lambda_max, which the outer end
+    # of the Krylov space resolves quickly
+    import scipy.linalg as sla
+    S = (op.C - op.A_adj(y)).toarray()
+    lam_max = float(sla.eigvalsh(S, subset_by_index=[n - 1, n - 1])[0])
+    assert lam_max - 1e-6 * scale <= cert.lambda_max <= lam_max + 1e-9 * scale
 
 
 def test_complete_graph_closed_form(ctx):
