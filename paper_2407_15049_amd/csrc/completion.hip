@@ -269,40 +269,49 @@ __global__ __launch_bounds__(kBlock) void k_cmp_sddmm(DevCompletion P, SddArgs<S
                 xu[q] = chunk_or_zero(a.U + pj[q], lane, active);
                 xv[q] = MODE != kSddRefresh ? chunk_or_zero(a.V + pj[q], lane, active) : zero;
             }
+            // the samples' own scalars, loaded by every lane with the rows (a
+            // repeated sample past the row's end is a valid index) and taken
+            // through selects, so that no load waits inside a lane-0 branch
+            double sv0[SS], sv1[SS];
+#pragma unroll
+            for (int q = 0; q < SS; ++q) {
+                if constexpr (MODE == kSddLS) sv0[q] = a.ytil[kk[q]];
+                if constexpr (MODE == kSddRefresh) {
+                    sv0[q] = P.b[kk[q]];
+                    sv1[q] = a.y[kk[q]];
+                }
+            }
 #pragma unroll
             for (int q = 0; q < SS; ++q) {
                 const int k = kk[q];
-                const bool live = q < cnt;
+                const bool own = lane == 0 && q < cnt;
                 if constexpr (MODE == kSddA) {
                     // <A_k, U V^T> = U_i . V_{n1+j} + U_{n1+j} . V_i
                     const double d = group_sum<GS>(vdot(ui, xv[q]) + vdot(xu[q], vi));
-                    if (lane == 0 && live) a.out[k] = d;
+                    if (own) a.out[k] = d;
                 } else if constexpr (MODE == kSddLS) {
                     // R rows in xu, D rows in xv
                     const double q1 = 2.0 * group_sum<GS>(vdot(ui, xv[q]) + vdot(vi, xu[q]));
                     const double q2 = 2.0 * group_sum<GS>(vdot(vi, xv[q]));
-                    if (lane == 0 && live) {
-                        const double yt = a.ytil[k];
+                    const double yt = sv0[q];
+                    s[1] += own ? yt * q2 : 0.0;
+                    s[2] += own ? yt * q1 : 0.0;
+                    s[3] += own ? q2 * q2 : 0.0;
+                    s[4] += own ? q1 * q2 : 0.0;
+                    s[5] += own ? q1 * q1 : 0.0;
+                    if (own) {
                         if (a.q1) a.q1[k] = q1;
                         if (a.q2) a.q2[k] = q2;
-                        s[1] += yt * q2;
-                        s[2] += yt * q1;
-                        s[3] += q2 * q2;
-                        s[4] += q1 * q2;
-                        s[5] += q1 * q1;
                     }
                 } else {
                     const double ak = 2.0 * group_sum<GS>(vdot(ui, xu[q]));
-                    if (lane == 0 && live) {
-                        const double res = ak - P.b[k];
-                        double yk = a.y[k];
-                        if (a.sigma > 0.0) {
-                            yk -= a.sigma * res;
-                            a.y[k] = yk;
-                        }
+                    const double bk = sv0[q], res = ak - bk;
+                    const double yk = a.sigma > 0.0 ? sv1[q] - a.sigma * res : sv1[q];
+                    s[1] += own ? bk * yk : 0.0;
+                    s[2] += own ? res * res : 0.0;
+                    if (own) {
+                        if (a.sigma > 0.0) a.y[k] = yk;
                         if (a.out) a.out[k] = ak;
-                        s[1] += P.b[k] * yk;
-                        s[2] += res * res;
                     }
                 }
             }
