@@ -162,6 +162,10 @@ def main():
         o = opts if opts is not None else p["opts"]
         if limit is not None:
             o.time_limit_s = max(1.0, limit)
+        if ws is None and p["ws"].numel() < L.workspace_bytes(run["prob"], o):
+            # options that need more workspace (row-block H0): a larger buffer, allocated outside the timing
+            p["ws"] = None
+            p["ws"] = torch.empty(L.workspace_bytes(run["prob"], o), dtype=torch.uint8, device=dev)
         p["R"].copy_(p["R0"] if R_init is None else R_init)
         if y_init is None:
             p["y"].zero_()
