@@ -9,10 +9,11 @@ problem, the starting factor and the workspace are resident in HBM before the
 timed region; the timed region is the solve.  The problem is built with the
 library's degree node order (nodes relabelled inside the library for locality
 of the SpMM gather; the starting factor and the result stay in the graph's
-labels); the comparison path f64_input_order solves the input order.  Beside it, untimed by the step but
-timed on its own: float32 + learned warm start on the same graph (features and
-MLP inference counted in its time), with the model committed beside the
-library.
+labels); the comparison path f64_input_order solves the input order.  Beside
+it, untimed by the step but timed on its own: float32 + learned warm start on
+the same graph, and the same with the row-block H0 of the L-BFGS direction
+(features and MLP inference counted in their time), with the model committed
+beside the library.
 
 The whole run keeps to a wall-clock budget (--budget, counted from the start of
 the process, generation and upload included): warm-ups are short capped solves,
@@ -48,7 +49,7 @@ WORKLOADS = {
     "cl_50m": (["cl_50m"], "maxcut n=5e7 Chung-Lu beta=2.5 mean degree 4 (1e8 edges), unit weights, C=-L/4, "
                            "diag(X)=1, rank 26 (held out from the warm-start training graphs)"),
 }
-DEFAULT_PATHS = "f32_warm"
+DEFAULT_PATHS = "f32_warm,f32_precond_warm"
 ALL_PATHS = ["f32_warm", "f32_precond_warm", "f32", "f32_precond", "f32_bf16in", "f64_precond", "f64_input_order",
              "f64_dynrank", "f64_reopt", "f64_reopt2", "f32_dynrank_precond"]
 DYNRANK_LD = {0: 30, 1: 32}       # row stride with room for the grown rank (FP64, FP32)
