@@ -174,6 +174,20 @@ int lrsdp_problem_general_blocks(int64_t nblocks, const int64_t *block_n, int64_
                                  const int32_t *a_col, const double *a_val, const double *b,
                                  lrsdp_problem **out);
 
+/* Rank of each block's factor in the multi-block case (appendix A.2: the exact
+ * line search carries over to several blocks, X_j = R_j R_j^T, each R_j of its
+ * own width block_rank[j]).  block_rank: host array of one entry per block of
+ * lrsdp_problem_general_blocks (one entry for a problem from
+ * lrsdp_problem_general), each >= 1.  In the stacked factor R of
+ * a solve, the rows of block j keep columns < min(block_rank[j], rank) and hold
+ * zeros in the others: lrsdp_solve sets those entries of the caller's R to zero
+ * at its start, the gradient leaves them at zero, and dynamic rank growth adds
+ * columns to a block's rows only up to its rank.  Call before the upload.
+ * Errors: EINVAL (NULL, a rank < 1, already uploaded), EUNSUPPORTED (not a
+ * general problem).
+ */
+int lrsdp_problem_block_ranks(lrsdp_problem *prob, const int32_t *block_rank);
+
 void lrsdp_problem_destroy(lrsdp_problem *prob);
 
 typedef struct {

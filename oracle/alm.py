@@ -197,6 +197,9 @@ def _alm_run(prob: SDPProblem, R0: np.ndarray, y0, opts: Options, log=None, sigm
     re-optimisation round), otherwise when err1 <= tol and |err3| <= tol."""
     t0 = time.perf_counter()
     R = np.array(R0, dtype=np.float64, copy=True)
+    mask = prob.rank_mask(R.shape[1])
+    if mask is not None:      # per-block ranks: the entries past a block's rank start (and stay) at zero
+        R *= mask
     y = np.zeros(prob.m) if y0 is None else np.array(y0, dtype=np.float64, copy=True)
     if sigma is None:
         sigma = opts.sigma0 if opts.sigma0 > 0 else default_sigma0(prob)
@@ -238,6 +241,9 @@ def _alm_run(prob: SDPProblem, R0: np.ndarray, y0, opts: Options, log=None, sigm
             # columns move err1, so the penalty rule restarts its reference
             r_new = min(rank_cap, (3 * rank_cur + 1) // 2)
             R = np.hstack([R, opts.rank_scale * new_columns(prob.n, rank_cur, r_new, opts.rank_seed)])
+            mask = prob.rank_mask(r_new)
+            if mask is not None:
+                R *= mask
             rank_cur = r_new
             meas = K.alm_measures(prob, R, y)
             hist.append(dict(outer=outer, rank=rank_cur, **meas))

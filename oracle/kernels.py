@@ -50,10 +50,13 @@ def multiplier_estimate(prob: SDPProblem, R: np.ndarray, y: np.ndarray, sigma: f
 
 def gradient(prob: SDPProblem, R: np.ndarray, y: np.ndarray, sigma: float) -> np.ndarray:
     """grad_R L = 2 C R - 2 A*(y) R + 2 sigma A*(A(RR^T) - b) R  (Section 2.1,
-    in the appendix sign convention)."""
+    in the appendix sign convention).  With per-block ranks, the gradient with
+    respect to the free entries only (the others are held at zero)."""
     res = prob.A_of(R) - prob.b
-    return (2.0 * (prob.C @ R) - 2.0 * (prob.A_adj(y) @ R)
-            + 2.0 * sigma * (prob.A_adj(res) @ R))
+    G = (2.0 * (prob.C @ R) - 2.0 * (prob.A_adj(y) @ R)
+         + 2.0 * sigma * (prob.A_adj(res) @ R))
+    mask = prob.rank_mask(R.shape[1])
+    return G if mask is None else G * mask
 
 
 # ---------------------------------------------------------------------------

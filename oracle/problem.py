@@ -28,6 +28,16 @@ class SDPProblem:
     Abar: sp.csr_matrix       # m x ncols stacked constraint matrix (nonzero columns only)
     b: np.ndarray             # right-hand side, length m
     kind: str = "general"
+    # Per-row rank of the factor (several blocks with their own ranks): row i of
+    # R keeps columns < row_rank[i] and holds zeros in the others; None: every
+    # row uses every column.
+    row_rank: np.ndarray | None = None
+
+    def rank_mask(self, r: int) -> np.ndarray | None:
+        """n x r 0/1 mask of the free entries of an n x r factor (None: all free)."""
+        if self.row_rank is None:
+            return None
+        return (np.arange(r)[None, :] < self.row_rank[:, None]).astype(np.float64)
 
     # ---- the linear map and its adjoint (Section 3.3, eq. At) ----
     def A_of(self, U: np.ndarray, V: np.ndarray | None = None) -> np.ndarray:
@@ -137,11 +147,14 @@ def general_problem(n: int, c_row, c_col, c_val, m: int, a_con, a_row, a_col, a_
 
 
 def general_blocks_problem(block_n, c_blk, c_row, c_col, c_val, m, a_con, a_blk, a_row, a_col, a_val,
-                           b) -> SDPProblem:
+                           b, block_rank=None) -> SDPProblem:
     """Several PSD blocks: min sum_j <C_j, X_j> s.t. sum_j <A_kj, X_j> = b_k, read
     as one problem in X = diag(X_1, ..., X_p) with C = diag(C_j) and
     A_k = diag(A_kj) (block_diag of the per-block matrices; the triplet
-    convention of general_problem inside each block)."""
+    convention of general_problem inside each block).  block_rank: the rank of
+    each block's factor, X_j = R_j R_j^T with R_j of block_rank[j] columns (the
+    multi-block case of appendix A.2, one factor per block variable); the
+    rows of block j in the stacked factor hold zeros past column block_rank[j]."""
     block_n = [int(x) for x in block_n]
     c_blk, c_row, c_col, c_val = (np.asarray(x) for x in (c_blk, c_row, c_col, c_val))
     a_con, a_blk, a_row, a_col, a_val = (np.asarray(x) for x in (a_con, a_blk, a_row, a_col, a_val))
@@ -168,5 +181,6 @@ def general_blocks_problem(block_n, c_blk, c_row, c_col, c_val, m, a_con, a_blk,
         vals.append(Ak.data)
     col_a, col_b, Abar = _stack_constraints(n, m, np.concatenate(k_idx), np.concatenate(a_idx),
                                             np.concatenate(b_idx), np.concatenate(vals))
+    row_rank = None if block_rank is None else np.repeat(np.asarray(block_rank, dtype=np.int64), block_n)
     return SDPProblem(n=n, m=m, C=C, col_a=col_a, col_b=col_b, Abar=Abar,
-                      b=np.asarray(b, dtype=np.float64), kind="general")
+                      b=np.asarray(b, dtype=np.float64), kind="general", row_rank=row_rank)

@@ -277,6 +277,14 @@ __global__ __launch_bounds__(kBlock) void k_gen_spmm(DevGeneral P, GenSpmmArgs<S
         D4 o;
 #pragma unroll
         for (int c = 0; c < 4; ++c) o.v[c] = GRAD ? 2.0 * acc.v[c] : acc.v[c];
+        if constexpr (GRAD) {
+            if (P.row_rank) {   // block ranks: the gradient of the free entries only
+                const int lim = P.row_rank[row];
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    if (lane * NV + c >= lim) o.v[c] = 0.0;
+            }
+        }
         CV os;
         narrow(o, os);
         if constexpr (!GRAD) {
@@ -512,6 +520,15 @@ int gen_spmm_tm(hipStream_t s, const DevGeneral &P, const GenSpmmArgs<S> &a, int
     return LRSDP_OK;
 }
 
+// Block ranks: zero the entries of R past its row's rank (n x ld, storage type).
+template <typename S>
+__global__ __launch_bounds__(kBlock) void k_gen_rank_mask(const int32_t *row_rank, S *R, int64_t n, int64_t ld) {
+    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < n * ld; e += (int64_t)gridDim.x * kBlock) {
+        const int64_t i = e / ld, c = e - i * ld;
+        if (c >= row_rank[i]) R[e] = (S)0;
+    }
+}
+
 // T: L-BFGS memory of the gradient call (0 for the plain SpMM)
 template <typename S, bool GRAD>
 int gen_spmm_t(hipStream_t s, const DevGeneral &P, const GenSpmmArgs<S> &a, int *nb, int T = 0) {
@@ -521,6 +538,17 @@ int gen_spmm_t(hipStream_t s, const DevGeneral &P, const GenSpmmArgs<S> &a, int 
 }
 
 }  // namespace
+
+int gen_rank_mask(hipStream_t s, const DevGeneral &P, int prec, void *R, int64_t ld) {
+    if (!P.row_rank || P.n <= 0) return LRSDP_OK;
+    const int nb = gen_grid(P.n * ld, kBlock);
+    if (prec == LRSDP_F64)
+        hipLaunchKernelGGL(k_gen_rank_mask<double>, dim3(nb), dim3(kBlock), 0, s, P.row_rank, (double *)R, P.n, ld);
+    else
+        hipLaunchKernelGGL(k_gen_rank_mask<float>, dim3(nb), dim3(kBlock), 0, s, P.row_rank, (float *)R, P.n, ld);
+    LRSDP_CHECK_LAUNCH();
+    return LRSDP_OK;
+}
 
 // mode 0: out = A(U V^T); mode 1: line-search terms of direction V at U with
 // ytil (partials: {<C,DD^T>, ytil.q2, ytil.q1, q2.q2, q1.q2, q1.q1, <C,RD^T+DR^T>});

@@ -131,6 +131,7 @@ struct DevGeneral {
     const double *cd = nullptr;         // n x n, row-major, both triangles
     double *dw = nullptr;               // n rows of kDenseRowBytes: the dense product cs C V
     double *dpart = nullptr;            // kDenseMaxSplit x n rows of kDenseRowBytes: split-k partials
+    const int32_t *row_rank = nullptr;  // n: columns row i of R may use (block ranks), or null: all
     double *x1 = nullptr;               // |Omega| compressed outer products, and (x2) the values of
     double *x2 = nullptr;               // C - A*(y) for the SpMM (problem-owned scratch: calls on one
                                         // problem must not overlap)
@@ -166,6 +167,8 @@ struct lrsdp_problem {
     std::vector<double> b;
     std::vector<int32_t> om_a, om_b, a_ptr, a_idx, at_ptr, at_idx, s_ptr, s_col, s_om, con_short, con_long;
     std::vector<double> cval, a_val, at_val, cdense;
+    std::vector<int64_t> block_off;     // general problems of several blocks: row offsets (nblocks + 1)
+    std::vector<int32_t> row_rank;      // general problems with block ranks: columns of R per row
     // device views (valid after upload)
     lrsdp::DevCsr csr;
     lrsdp::DevCompletion cmp;

@@ -565,8 +565,28 @@ extern "C" int lrsdp_problem_general_blocks(int64_t nblocks, const int64_t *bloc
     int rc;
     if ((rc = place(c_nnz, c_blk, c_row, c_col, cr, cc, "C"))) return rc;
     if ((rc = place(a_nnz, a_blk, a_row, a_col, ar, ac, "A"))) return rc;
-    return lrsdp_problem_general(off[nblocks], c_nnz, cr.data(), cc.data(), c_val, m, a_nnz, a_con, ar.data(),
-                                 ac.data(), a_val, b, out);
+    rc = lrsdp_problem_general(off[nblocks], c_nnz, cr.data(), cc.data(), c_val, m, a_nnz, a_con, ar.data(),
+                               ac.data(), a_val, b, out);
+    if (rc == LRSDP_OK) (*out)->block_off = off;
+    return rc;
+}
+
+extern "C" int lrsdp_problem_block_ranks(lrsdp_problem *p, const int32_t *block_rank) {
+    clear_error();
+    if (!p || !block_rank) return set_error(LRSDP_EINVAL, "NULL argument");
+    if (p->info.kind != LRSDP_GENERAL)
+        return set_error(LRSDP_EUNSUPPORTED, "block ranks apply to general problems");
+    if (p->uploaded) return set_error(LRSDP_EINVAL, "set the block ranks before the upload");
+    std::vector<int64_t> off = p->block_off;
+    if (off.empty()) off = {0, p->info.n};   // lrsdp_problem_general: one block
+    const int64_t nb = (int64_t)off.size() - 1;
+    for (int64_t j = 0; j < nb; ++j)
+        if (block_rank[j] < 1)
+            return set_error(LRSDP_EINVAL, "block %lld has rank %d", (long long)j, block_rank[j]);
+    p->row_rank.resize(p->info.n);
+    for (int64_t j = 0; j < nb; ++j)
+        for (int64_t i = off[j]; i < off[j + 1]; ++i) p->row_rank[i] = block_rank[j];
+    return LRSDP_OK;
 }
 
 namespace {
@@ -618,6 +638,7 @@ size_t plan_device(const lrsdp_problem *p, size_t *offs) {
         add(p->cdense.size() * 8);                                      // dense C
         add(p->cdense.empty() ? 0 : (size_t)p->info.n * kDenseRowBytes);  // dense product, one row per node
         add(p->cdense.empty() ? 0 : (size_t)kDenseMaxSplit * p->info.n * kDenseRowBytes);  // split-k partials
+        add(p->row_rank.size() * 4);                                     // per-row rank (block ranks)
     } else {
         add(p->top_ptr.size() * 4);
         add(p->top_col.size() * 4);
@@ -722,6 +743,8 @@ extern "C" int lrsdp_problem_upload(lrsdp_ctx *ctx, lrsdp_problem *p, void *dev,
         g.cd = p->cdense.empty() ? nullptr : (const double *)(base + offs[17]);
         g.dw = p->cdense.empty() ? nullptr : (double *)(base + offs[18]);
         g.dpart = p->cdense.empty() ? nullptr : (double *)(base + offs[19]);
+        LRSDP_HIP_TRY(put(offs[20], p->row_rank.data(), p->row_rank.size() * 4));
+        g.row_rank = p->row_rank.empty() ? nullptr : (const int32_t *)(base + offs[20]);
         g.n_short = (int64_t)p->con_short.size();
         g.n_long = (int64_t)p->con_long.size();
         g.n = p->info.n;

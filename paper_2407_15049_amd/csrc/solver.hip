@@ -55,6 +55,7 @@ int gen_sddmm(hipStream_t, const DevGeneral &, int, int, const void *, const voi
               double *, const double *, double *, double, double, double *, const SolverState *, int *);
 int gen_grad(hipStream_t, const DevGeneral &, int, const SolverState *, const void *, const double *, void *const *,
              void *const *, int, int64_t, double *, int, int *, double);
+int gen_rank_mask(hipStream_t, const DevGeneral &, int, void *, int64_t);
 
 namespace {
 
@@ -587,6 +588,8 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
         }
         return launch_alm_finalize(s, st, part_misc, np, mode, cmp ? cs : 1.0);
     };
+    // block ranks (general problems): the entries of R past a block's rank start at zero
+    if (gen && (rc = gen_rank_mask(s, p->gen, prec, R, ld))) return rc;
     if ((rc = alm_refresh(0.0, 0))) return rc;
 
     int status = LRSDP_NOT_CONVERGED;
@@ -835,6 +838,7 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
             if ((rc = launch_rank_grow(s, prec, R, n, ld, rank_cur, r_new, (uint64_t)o->rank_seed, o->rank_scale,
                                        mc ? p->csr.perm : nullptr)))
                 break;
+            if (gen && (rc = gen_rank_mask(s, p->gen, prec, R, ld))) break;   // up to each block's rank
             if (o->verbose) fprintf(stderr, "[lrsdp] rank %d -> %d\n", rank_cur, r_new);
             rank_cur = r_new;
             if ((rc = alm_refresh(0.0, 0))) break;

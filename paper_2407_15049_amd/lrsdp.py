@@ -98,6 +98,7 @@ _SIGS = {
     "lrsdp_problem_general": (C.c_int, [_I64, _I64, _P, _P, _P, _I64, _I64, _P, _P, _P, _P, _P, C.POINTER(_P)]),
     "lrsdp_problem_general_ex": (C.c_int, [_I64, _I64, _P, _P, _P, _I64, _I64, _P, _P, _P, _P, _P, C.c_int,
                                            C.POINTER(_P)]),
+    "lrsdp_problem_block_ranks": (C.c_int, [_P, _P]),
     "lrsdp_problem_general_blocks": (C.c_int, [_I64, _P, _I64, _P, _P, _P, _P, _I64, _I64, _P, _P, _P, _P, _P, _P,
                                                C.POINTER(_P)]),
     "lrsdp_problem_destroy": (None, [_P]),
@@ -220,9 +221,10 @@ class Context:
 class Problem:
     """Host-built problem; ``upload`` places it in a torch-owned device buffer."""
 
-    def __init__(self, handle):
+    def __init__(self, handle, nblocks=1):
         self.handle = handle
         self.dev = None
+        self.nblocks = nblocks   # blocks of a general problem (lrsdp_problem_block_ranks reads one rank each)
 
     @classmethod
     def maxcut(cls, n, u, v, w=None, node_order=None):
@@ -274,7 +276,8 @@ class Problem:
         return cls(h)
 
     @classmethod
-    def general_blocks(cls, block_n, c_blk, c_row, c_col, c_val, m, a_con, a_blk, a_row, a_col, a_val, b):
+    def general_blocks(cls, block_n, c_blk, c_row, c_col, c_val, m, a_con, a_blk, a_row, a_col, a_val, b,
+                       block_rank=None):
         """Several PSD blocks laid out one after another in one factor; triplets
         carry a block id and block-local indices."""
         lib = load()
@@ -289,7 +292,18 @@ class Problem:
         h = C.c_void_p()
         _check(lib.lrsdp_problem_general_blocks(len(bn), bnp, len(cb), cbp, crp, ccp, cvp, int(m), len(ak), akp, abp,
                                                 arp, acp, avp, bp, C.byref(h)))
-        return cls(h)
+        prob = cls(h, nblocks=len(bn))
+        if block_rank is not None:
+            prob.set_block_ranks(block_rank)
+        return prob
+
+    def set_block_ranks(self, block_rank):
+        """lrsdp_problem_block_ranks: the rank of each block's factor (before upload)."""
+        ra, rp = _host(block_rank, np.int32)
+        if len(ra) != self.nblocks:
+            raise ValueError(f"{len(ra)} block ranks for {self.nblocks} blocks")
+        _check(load().lrsdp_problem_block_ranks(self.handle, rp))
+        return self
 
     @property
     def info(self) -> ProblemInfo:

@@ -248,6 +248,20 @@ def test_general_blocks_build_and_validation():
     assert e.value.code == L.EINVAL
 
 
+def test_block_ranks_validation():
+    from test_oracle_general import two_theta_blocks
+    p = L.Problem.general_blocks(*two_theta_blocks())
+    p.set_block_ranks([2, 3])
+    with pytest.raises(ValueError):
+        p.set_block_ranks([2])
+    with pytest.raises(L.LrsdpError) as e:
+        p.set_block_ranks([0, 3])
+    assert e.value.code == L.EINVAL
+    with pytest.raises(L.LrsdpError) as e:
+        L.Problem.maxcut(4, [0, 1], [1, 2]).set_block_ranks([1])
+    assert e.value.code == L.EUNSUPPORTED
+
+
 def test_general_dense_storage_choice_and_validation():
     from synth import random_general_triplets, theta_triplets
     from synth import petersen_edges

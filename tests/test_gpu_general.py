@@ -355,3 +355,45 @@ def test_blocks_closed_forms(ctx, case):
     assert abs(res.obj - ores.obj) <= 1e-7 * want
     m = K.alm_measures(op, R, y)
     assert abs(m["obj"] - res.obj) <= 1e-10 * want
+
+
+def test_block_ranks_iterates_and_solve_match_oracle(ctx):
+    # blocks of orders 4 and 6 with ranks 1 and 3 (trace-one blocks: the optimum
+    # is the sum of the blocks' smallest eigenvalues, reached at rank one); the
+    # caller's factor has values in the masked entries, which the solve zeroes
+    from oracle.problem import general_blocks_problem
+    from test_oracle_general import trace_blocks
+    args, mats = trace_blocks([4, 6], 7)
+    print_case(test="block_ranks", ranks=[1, 3])
+    op = general_blocks_problem(*args, block_rank=[1, 3])
+    prob = L.Problem.general_blocks(*args, block_rank=[1, 3]).upload(ctx)
+    R0 = init_factor(10, 3, 8)
+    kw = dict(max_outer=1, max_inner=6, eta0=1e-14)
+    rc, res, R, y = gpu_solve(ctx, prob, R0, L.F64, op.m, **kw)
+    ores = alm_solve(op, R0, opts=OOptions(**kw))
+    assert res.inner == ores.inner == 6
+    assert np.all(R[:4, 1:] == 0.0)
+    assert np.max(np.abs(R - ores.R)) <= 1e-9 * (1.0 + np.abs(ores.R).max())
+    rc, res, R, y = gpu_solve(ctx, prob, R0, L.F64, op.m, tol=1e-9)
+    want = sum(np.linalg.eigvalsh(M)[0] for M in mats)
+    print(res.as_dict(), "closed form", want)
+    assert rc == L.OK
+    assert res.obj == pytest.approx(want, rel=1e-6, abs=1e-7)
+    assert np.all(R[:4, 1:] == 0.0)
+
+
+@pytest.mark.parametrize("rank", [1, 2])
+def test_block_rank_one_cannot_hold_two_orthogonal_unit_rows(ctx, rank):
+    # X_00 = X_11 = 1, X_01 = 0 needs rank 2 (closed form: a rank-one factor has
+    # X_01 = +-1 once both diagonal constraints hold)
+    args = ([2], np.array([0, 0], np.int32), np.array([0, 1], np.int32), np.array([0, 1], np.int32),
+            np.array([1.0, 0.5]), 3, np.array([0, 1, 2], np.int32), np.zeros(3, np.int32),
+            np.array([0, 1, 0], np.int32), np.array([0, 1, 1], np.int32), np.ones(3), np.array([1.0, 1.0, 0.0]))
+    print_case(test="block_rank_orthogonal", rank=rank)
+    prob = L.Problem.general_blocks(*args, block_rank=[rank]).upload(ctx)
+    rc, res, R, y = gpu_solve(ctx, prob, init_factor(2, 2, 9), L.F64, 3, max_outer=30)
+    print(res.as_dict())
+    if rank == 1:
+        assert rc != L.OK and res.err1 > 0.05
+    else:
+        assert rc == L.OK and res.obj == pytest.approx(1.5, rel=1e-5)

@@ -171,3 +171,70 @@ def test_scalar_slack_block():
     assert res.converged
     assert -res.obj == pytest.approx(math.sqrt(5), rel=1e-6)
     assert np.sum(res.R[5] ** 2) <= 1e-6          # the slack ends at 0
+
+
+def trace_blocks(sizes, seed):
+    """Blocks X_j (orders `sizes`) with random symmetric C_j and tr X_j = 1 each:
+    min <C_j, X_j> over psd X_j of trace 1 is lambda_min(C_j), reached by a
+    rank-one X_j (v v^T for a unit eigenvector v)."""
+    rng = np.random.default_rng(seed)
+    c_blk, c_row, c_col, c_val, mats = [], [], [], [], []
+    a_con, a_blk, a_row, a_col, a_val = [], [], [], [], []
+    for j, nj in enumerate(sizes):
+        M = rng.standard_normal((nj, nj))
+        M = 0.5 * (M + M.T)
+        mats.append(M)
+        r, c = np.triu_indices(nj)
+        c_blk.append(np.full(len(r), j))
+        c_row.append(r)
+        c_col.append(c)
+        c_val.append(M[r, c])
+        a_con.append(np.full(nj, j))
+        a_blk.append(np.full(nj, j))
+        a_row.append(np.arange(nj))
+        a_col.append(np.arange(nj))
+        a_val.append(np.ones(nj))
+    cat = lambda xs, t=np.int32: np.concatenate(xs).astype(t)
+    args = (list(sizes), cat(c_blk), cat(c_row), cat(c_col), cat(c_val, np.float64), len(sizes), cat(a_con),
+            cat(a_blk), cat(a_row), cat(a_col), cat(a_val, np.float64), np.ones(len(sizes)))
+    return args, mats
+
+
+def test_block_rank_masks_the_gradient():
+    from oracle import kernels as K
+    from oracle.problem import general_blocks_problem
+    args, _ = trace_blocks([4, 6], 5)
+    full = general_blocks_problem(*args)
+    part = general_blocks_problem(*args, block_rank=[1, 3])
+    rng = np.random.default_rng(6)
+    R = rng.standard_normal((10, 3))
+    y = rng.standard_normal(2)
+    G, Gm = K.gradient(full, R, y, 3.0), K.gradient(part, R, y, 3.0)
+    assert np.all(Gm[:4, 1:] == 0.0)                       # block 0 keeps column 0 only
+    assert np.array_equal(Gm[:4, :1], G[:4, :1]) and np.array_equal(Gm[4:], G[4:])
+
+
+def test_block_rank_one_reaches_lambda_min():
+    # a rank-one block reaches min <C_j, X_j> = lambda_min(C_j) over trace-one psd X_j
+    from oracle.problem import general_blocks_problem
+    args, mats = trace_blocks([4, 6], 7)
+    op = general_blocks_problem(*args, block_rank=[1, 3])
+    res = alm_solve(op, init_factor(10, 3, 8), opts=Options(tol=1e-9))
+    want = sum(np.linalg.eigvalsh(M)[0] for M in mats)
+    assert res.converged
+    assert res.obj == pytest.approx(want, rel=1e-6, abs=1e-7)
+    assert np.all(res.R[:4, 1:] == 0.0)
+
+
+def test_block_rank_one_cannot_hold_two_orthogonal_unit_rows():
+    # X_00 = X_11 = 1 and X_01 = 0 need rank 2: a rank-one factor (a, b) has
+    # X_01 = ab with a^2 = b^2 = 1, so the constraints cannot all hold
+    from oracle.problem import general_blocks_problem
+    args = ([2], np.array([0, 0], np.int32), np.array([0, 1], np.int32), np.array([0, 1], np.int32),
+            np.array([1.0, 0.5]), 3, np.array([0, 1, 2], np.int32), np.zeros(3, np.int32),
+            np.array([0, 1, 0], np.int32), np.array([0, 1, 1], np.int32), np.ones(3), np.array([1.0, 1.0, 0.0]))
+    R0 = init_factor(2, 2, 9)
+    one = alm_solve(general_blocks_problem(*args, block_rank=[1]), R0, opts=Options(max_outer=30))
+    two = alm_solve(general_blocks_problem(*args, block_rank=[2]), R0, opts=Options(max_outer=30))
+    assert not one.converged and one.err1 > 0.05
+    assert two.converged and two.obj == pytest.approx(1.5, rel=1e-5)   # <C, X> = X_00 + 0.5 X_11
