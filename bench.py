@@ -351,8 +351,11 @@ def comparison_paths(args, ctx, dev, L, runs, paths, enabled, left, reserve_cpu,
 
     def opts_for(run, prec, **kw):
         p = run["per"][prec]
-        return L.default_options(prec=prec, rank=run["r"], ld=p["opts"].ld, profile=1,
-                                 verbose=int(args.verbose), **kw)
+        o = L.default_options(prec=prec, rank=run["r"], ld=p["opts"].ld, profile=1,
+                              verbose=int(args.verbose), **kw)
+        if args.short:
+            o.max_outer, o.max_inner = 1, args.short
+        return o
 
     model = None
     for path in enabled:
