@@ -546,6 +546,38 @@ int lrsdp_certify(lrsdp_ctx *ctx, const lrsdp_problem *prob, const double *y,
                   int max_iter, double tol, uint64_t seed, void *work,
                   size_t work_bytes, lrsdp_cert *out);
 
+/* ---- proof of a lower bound (small problems, host) --------------------------
+ * Proves lambda_min(S) >= lambda_lb for S = C - A*(y) (the dual slack of the
+ * error measures, Section 4.2), which the Lanczos estimate above cannot: S -
+ * shift I is formed densely on the host in float64 and factorised by
+ * Cholesky.  If every pivot is positive, the rounding analysis of Cholesky
+ * (computed factor R: R^T R = S' + E, |E| <= gamma_{n+1} |R^T||R|, gamma_k =
+ * k u / (1 - k u), u = 2^-53; IEEE float64, no underflow) bounds ||E||_2 by
+ * gamma_{n+1} ||R||_F^2; with a bound on the rounding of the formation of S'
+ * this gives lambda_lb = shift - margin.  dual_bound: the bound on the optimum
+ * of lrsdp_certify's formulas taken at lambda_lb and b^T y rounded down
+ * (MaxCut, completion; NaN for a general problem).  The caller picks shift,
+ * e.g. the Lanczos lambda_lb less a small allowance; a failed factorisation
+ * (status 1) says S - shift I is not (numerically) positive definite, i.e. the
+ * shift is too high.  Host work only: O(n^3 / 6) multiply-adds and 4 n^2
+ * doubles of host memory; the problem need not be uploaded.  y: host float64,
+ * m entries, in the caller's node labels.  Errors: EINVAL (NULL, shift or y
+ * not finite), EUNSUPPORTED (n > LRSDP_PROOF_MAX_N).
+ */
+#define LRSDP_PROOF_MAX_N 4096
+typedef struct {
+    double  shift;       /* the shift tried                                      */
+    double  lambda_lb;   /* status 0: proven lower bound on lambda_min(S)        */
+    double  margin;      /* shift - lambda_lb: the rounding allowance            */
+    double  dual_bound;  /* status 0: proven lower bound on the optimum          */
+    double  by;          /* b^T y as computed                                    */
+    int64_t pivot;       /* status 1: index of the first non-positive pivot      */
+    int     status;      /* 0: proven; 1: the factorisation failed (no bound)    */
+    int     reserved;
+} lrsdp_proof;
+int lrsdp_certify_dense(const lrsdp_problem *prob, const double *y, double shift,
+                        lrsdp_proof *out);
+
 /* Warm start for the problem: y0 (device m float64) and *sigma0 (host), with
  * the mean penalty output limited to [log_ratio_lo, log_ratio_hi] (EINVAL if
  * empty or not finite).  params of param_dtype.  work: device float32 scratch

@@ -19,6 +19,7 @@ SOURCES = [
     "problem.hip",
     "spmm_maxcut.hip",
     "certify.hip",
+    "proof.hip",
     "general.hip",
     "solver_kernels.hip",
     "entry_kernels.hip",

@@ -85,6 +85,18 @@ class Cert(C.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class Proof(C.Structure):
+    _fields_ = [
+        ("shift", C.c_double), ("lambda_lb", C.c_double), ("margin", C.c_double), ("dual_bound", C.c_double),
+        ("by", C.c_double), ("pivot", C.c_int64), ("status", C.c_int), ("reserved", C.c_int),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+
+
+PROOF_MAX_N = 4096
+
 _P = C.c_void_p
 _I64 = C.c_int64
 _SIGS = {
@@ -130,6 +142,7 @@ _SIGS = {
     "lrsdp_ws_targets": (C.c_int, [_P, _P, _P, _P, C.c_double, _P]),
     "lrsdp_certify_workspace_bytes": (C.c_int, [_P, C.c_int, C.POINTER(C.c_size_t)]),
     "lrsdp_certify": (C.c_int, [_P, _P, _P, C.c_int, C.c_double, C.c_uint64, _P, C.c_size_t, C.POINTER(Cert)]),
+    "lrsdp_certify_dense": (C.c_int, [_P, _P, C.c_double, C.POINTER(Proof)]),
 }
 
 _lib = None
@@ -490,4 +503,16 @@ def certify(ctx, prob, y, max_iter=300, tol=1e-6, seed=15049, work=None):
     out = Cert()
     _check(load().lrsdp_certify(ctx.handle, prob.handle, _ptr(y), max_iter, tol, seed, _ptr(work),
                                 work.numel() * work.element_size(), C.byref(out)))
+    return out
+
+
+def certify_dense(prob, y, shift):
+    """lrsdp_certify_dense: proof that lambda_min(C - A*(y)) >= shift - margin
+    (host Cholesky of C - A*(y) - shift I; y: host float64, m entries); returns a
+    Proof (status 0: proven, 1: the factorisation failed at `pivot`)."""
+    ya, yp = _host(y, np.float64)
+    if len(ya) != prob.info.m:
+        raise ValueError(f"y has {len(ya)} entries, the problem {prob.info.m}")
+    out = Proof()
+    _check(load().lrsdp_certify_dense(prob.handle, yp, float(shift), C.byref(out)))
     return out
