@@ -80,6 +80,9 @@ def parse():
     ap.add_argument("--completion", action="store_true",
                     help="instead of the MaxCut step: time the matrix-completion kernels (SDDMM constraint map, "
                          "gradient SpMM) and 300 L-BFGS iterations at n1 = n2 = 5e5, m = 1e7, rank 16")
+    ap.add_argument("--completion-solve", type=float, default=0.0,
+                    help="with --completion: also solve to 1e-5 at the factor rank and at the planted rank, in "
+                         "float64 and float32, each with this time limit in seconds")
     ap.add_argument("--general", action="store_true",
                     help="instead of the MaxCut step: time the general-problem kernels (compressed constraint map, "
                          "C - A*(y) SpMM) and a full solve of a general SDP with n = 1e6 (diag(X) = 1 plus 1000 "
@@ -498,7 +501,7 @@ def completion_bench(args, ctx, dev):
 
     cfg = COMPLETION
     t0 = time.perf_counter()
-    i, j, M, _, _ = completion_instance(cfg["n1"], cfg["n2"], cfg["k"], cfg["per_row"], cfg["seed"])
+    i, j, M, U, V = completion_instance(cfg["n1"], cfg["n2"], cfg["k"], cfg["per_row"], cfg["seed"])
     prob = L.Problem.completion(cfg["n1"], cfg["n2"], i, j, M).upload(ctx)
     n, m, r = prob.info.n, prob.info.m, cfg["rank"]
     log(f"completion n={n} m={m} setup {time.perf_counter() - t0:.1f}s")
@@ -547,13 +550,54 @@ def completion_bench(args, ctx, dev):
             iters=res.inner, ms_per_iter=round(1e3 * dt / max(res.inner, 1), 3), err1=res.err1)
         log(f"completion {name}: {out[name]}")
         del R, Y, R0, ws
+    solves = completion_solves(args, ctx, dev, L, prob, cfg, U, V) if args.completion_solve > 0 else None
     copy_gbs = copy_ceiling(torch, dev, args.copy_calibration)
     print(json.dumps({
         "metric": "completion kernels: SDDMM / SpMM algorithmic GB/s and L-BFGS ms per iteration",
         "unit": "GB/s", "n_gpus": 1, "dtype": "f64,f32", "data": "synthetic",
         "config": {"workload": "matrix completion n1=n2=5e5 (X of order 1e6), m=1e7 samples (20 per row), "
                                "planted rank 5, factor rank 16", **cfg},
-        "kernels": out, "copy_ceiling_gbs": copy_gbs}), flush=True)
+        "kernels": out, "solves": solves, "copy_ceiling_gbs": copy_gbs}), flush=True)
+
+
+def completion_solves(args, ctx, dev, L, prob, cfg, U, V):
+    """Time to 1e-5 of the completion SDP at the factor rank and at the planted
+    rank, float64 and float32, from the seeded Gaussian start; with the
+    recovery error of the planted M = U V^T on 100,000 seeded positions (most
+    of them unobserved): ||(R_top R_bot^T - M)_S|| / ||M_S||."""
+    import numpy as np
+    import torch
+    from synth.graphs import gaussian_factor
+    n, m = prob.info.n, prob.info.m
+    g = np.random.default_rng(cfg["seed"] + 7)
+    si = g.integers(0, cfg["n1"], 100_000)
+    sj = g.integers(0, cfg["n2"], 100_000)
+    want = np.einsum("ij,ij->i", U[si], V[sj])
+    res_all = {}
+    for r in (cfg["rank"], cfg["k"]):
+        for prec, name in [(L.F64, "f64"), (L.F32, "f32")]:
+            ld = L.padded_ld(r, prec)
+            R = torch.zeros((n, ld), dtype=L.elem_dtype(prec), device=dev)
+            R[:, :r] = torch.from_numpy(gaussian_factor(n, r, 1.0 / math.sqrt(r), cfg["seed"] + 1)).to(dev, R.dtype)
+            y = torch.zeros(m, dtype=torch.float64, device=dev)
+            opts = L.default_options(prec=prec, rank=r, ld=ld)
+            opts.time_limit_s = args.completion_solve
+            ws = torch.empty(L.workspace_bytes(prob, opts), dtype=torch.uint8, device=dev)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            rc, res = L.solve(ctx, prob, R, y, opts, workspace=ws)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t1
+            Rh = R[:, :r].double().cpu().numpy()
+            got = np.einsum("ij,ij->i", Rh[si], Rh[cfg["n1"] + sj])
+            rec = float(np.linalg.norm(got - want) / np.linalg.norm(want))
+            key = f"{name}_rank{r}"
+            res_all[key] = dict(seconds=round(dt, 3), converged=rc == L.OK, outer=res.outer, inner=res.inner,
+                                obj=res.obj, err1=res.err1, err3=res.err3,
+                                ms_per_iter=round(1e3 * dt / max(res.inner, 1), 3), recovery_rel_err=rec)
+            log(f"completion solve {key}: {res_all[key]}")
+            del R, y, ws
+    return res_all
 
 
 GENERAL = dict(n=1_000_000, c_nnz=5_000_000, extra=1000, per_con=5, rank=16, seed=15052)
