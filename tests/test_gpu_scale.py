@@ -1,4 +1,5 @@
-"""The oracle re-measures GPU solves at n = 1e6.
+"""The oracle re-measures GPU solves at n = 1e6 (MaxCut) and at order 1e6 with
+1e7 samples (matrix completion).
 
 An oracle solve at this size takes hours, so end-to-end parity here is the
 oracle recomputing, from the (R, y) the library returns, the objective, the
@@ -9,14 +10,18 @@ library's own report against that to 1e-10 relative (err1, which is formed
 from residuals of order 1e-7 after cancellation, to 1e-8; the float32
 objective, which the library takes from the SpMM's float32 accumulation, to
 1e-6), plus the float32 result against the float64 one on the objective.
+The completion case solves the 5e5 x 5e5 planted rank-5 instance (20 samples
+per row) at the planted rank and also checks the result against the planted
+matrix itself on unobserved positions.
 """
 
 import numpy as np
 import pytest
 
 from oracle import kernels as K
-from oracle.problem import maxcut_problem
-from synth import init_factor, maxcut_instance
+from oracle.problem import completion_problem, maxcut_problem
+from synth import completion_instance, init_factor, maxcut_instance
+from synth.graphs import gaussian_factor
 
 from paper_2407_15049_amd import lrsdp as L
 from gpu_util import dev_factor, host
@@ -65,3 +70,38 @@ def test_oracle_remeasures_1m_solves(ctx, name):
     # on the objective to the accuracy the stopping rule gives (|err3| <= 1e-5 on
     # both, plus the spread between stationary points of the rank-20 factorisation)
     assert abs(objs[L.F32] - objs[L.F64]) <= 1e-3 * abs(objs[L.F64])
+
+
+def test_oracle_remeasures_completion_solve_1e7_samples(ctx):
+    import torch
+    n1 = n2 = 500_000
+    k, per_row, seed = 5, 20, 15051
+    print("CASE", dict(test="scale_completion", n1=n1, n2=n2, m=n1 * per_row), flush=True)
+    i, j, M, U, V = completion_instance(n1, n2, k, per_row, seed)
+    prob = L.Problem.completion(n1, n2, i, j, M).upload(ctx)
+    op = completion_problem(n1, n2, i, j, M)
+    n, m = prob.info.n, prob.info.m
+    R0 = gaussian_factor(n, k, 1.0 / np.sqrt(k), seed + 1)
+    g = np.random.default_rng(seed + 7)
+    si, sj = g.integers(0, n1, 100_000), g.integers(0, n2, 100_000)
+    want = np.einsum("ij,ij->i", U[si], V[sj])
+    for prec in (L.F64, L.F32):
+        opts = L.default_options(prec=prec, rank=k, ld=L.padded_ld(k, prec), time_limit_s=60.0)
+        Rd = dev_factor(R0, prec)
+        yd = torch.zeros(m, dtype=torch.float64, device="cuda")
+        rc, res = L.solve(ctx, prob, Rd, yd, opts)
+        torch.cuda.synchronize()
+        print("completion", prec, res.as_dict(), flush=True)
+        assert rc == L.OK
+        R = host(Rd, k)
+        meas = K.alm_measures(op, R, yd.cpu().numpy())
+        print("oracle", meas, flush=True)
+        tobj = 1e-10 if prec == L.F64 else 1e-6
+        assert abs(meas["obj"] - res.obj) <= tobj * abs(meas["obj"])
+        assert abs(meas["dual"] - res.dual) <= 1e-10 * abs(meas["dual"])
+        assert abs(meas["err1"] - res.err1) <= 1e-8 * meas["err1"] + 1e-16
+        assert abs(meas["err3"] - res.err3) <= tobj
+        assert meas["err1"] <= 1e-5 and abs(meas["err3"]) <= 1e-5
+        # the planted matrix on 1e5 seeded positions, nearly all unobserved
+        got = np.einsum("ij,ij->i", R[si], R[n1 + sj])
+        assert np.linalg.norm(got - want) / np.linalg.norm(want) <= 0.02
