@@ -83,6 +83,10 @@ def parse():
     ap.add_argument("--completion-solve", type=float, default=0.0,
                     help="with --completion: also solve to 1e-5 at the factor rank and at the planted rank, in "
                          "float64 and float32, each with this time limit in seconds")
+    ap.add_argument("--general-dense", action="store_true",
+                    help="instead of the MaxCut step: the general path with C stored dense (n = 8192, every "
+                         "upper-triangle entry N(0, 1), diag(X) = 1, rank 24): the C - A*(y) SpMM, whose dense "
+                         "product runs on float64 matrix cores, and a solve to 1e-5, in float64")
     ap.add_argument("--general", action="store_true",
                     help="instead of the MaxCut step: time the general-problem kernels (compressed constraint map, "
                          "C - A*(y) SpMM) and a full solve of a general SDP with n = 1e6 (diag(X) = 1 plus 1000 "
@@ -114,6 +118,8 @@ def main():
         return completion_bench(args, ctx, dev)
     if args.general:
         return general_bench(args, ctx, dev)
+    if args.general_dense:
+        return general_dense_bench(args, ctx, dev)
 
     def left():
         return args.budget - (time.perf_counter() - T_START)
@@ -698,6 +704,74 @@ def general_bench(args, ctx, dev):
         "config": {"workload": "general SDP n=1e6: 5e6 random N(0,1) objective entries, diag(X)=1 plus 1000 "
                                "side constraints on 5 off-diagonal positions each (b = 0), rank 16", **cfg},
         "kernels": out}), flush=True)
+
+
+GENERAL_DENSE = dict(n=8192, rank=24, seed=15053)
+
+
+def general_dense_bench(args, ctx, dev):
+    """The general path with C stored dense: HIP-event time of lrsdp_k_spmm
+    (dense product W = C V on float64 matrix cores, then the sparse part and the
+    split-k finish) and a float64 solve to 1e-5.  The instance is the SDP
+    relaxation of a dense +-spin problem: C with every upper-triangle entry
+    N(0, 1), diag(X) = 1."""
+    import numpy as np
+    import torch
+
+    from paper_2407_15049_amd import lrsdp as L
+    from synth import init_factor
+
+    cfg = GENERAL_DENSE
+    n, r = cfg["n"], cfg["rank"]
+    t0 = time.perf_counter()
+    g = np.random.Generator(np.random.PCG64(cfg["seed"]))
+    c_row, c_col = np.triu_indices(n)
+    c_val = g.standard_normal(c_row.size)
+    diag = np.arange(n, dtype=np.int32)
+    prob = L.Problem.general(n, c_row.astype(np.int32), c_col.astype(np.int32), c_val, n, diag, diag, diag,
+                             np.ones(n), np.ones(n), c_storage=L.C_DENSE).upload(ctx)
+    del c_row, c_col, c_val
+    assert prob.info.c_dense == 1
+    log(f"general dense n={n} setup {time.perf_counter() - t0:.1f}s")
+    stream = torch.cuda.current_stream(dev)
+    prec, ld = L.F64, L.padded_ld(r, L.F64)
+    R = torch.zeros((n, ld), dtype=torch.float64, device=dev)
+    R[:, :r] = torch.from_numpy(init_factor(n, r, cfg["seed"] + 1)).to(dev)
+    y = torch.from_numpy(np.random.default_rng(cfg["seed"] + 2).standard_normal(n) * 0.1).to(dev)
+    Y = torch.empty_like(R)
+    for _ in range(3):
+        L.k_spmm(ctx, prob, prec, R, y, Y)
+    reps = 50
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record(stream)
+    for _ in range(reps):
+        L.k_spmm(ctx, prob, prec, R, y, Y)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    t_spmm = ev[0].elapsed_time(ev[1]) * 1e3 / reps
+    # algorithmic: C once (n^2 float64), V read, W and Y written once; flops 2 n^2 r
+    b_spmm = 8.0 * n * n + 3.0 * 8.0 * n * ld
+    flops = 2.0 * n * n * r
+    opts = L.default_options(prec=prec, rank=r, ld=ld, time_limit_s=120.0)
+    y0 = torch.zeros(n, dtype=torch.float64, device=dev)
+    ws = torch.empty(L.workspace_bytes(prob, opts), dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rc, res = L.solve(ctx, prob, R, y0, opts, workspace=ws)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t1
+    out = dict(spmm_us=round(t_spmm, 2), spmm_alg_bytes=b_spmm, spmm_gbs=round(b_spmm / t_spmm / 1e3, 1),
+               spmm_frac=round(b_spmm / t_spmm / 1e3 / HBM_PEAK_GBS, 4),
+               spmm_tflops=round(flops / t_spmm / 1e6, 2), solve_s=round(dt, 3), converged=rc == L.OK,
+               outer=res.outer, iters=res.inner, ms_per_iter=round(1e3 * dt / max(res.inner, 1), 3),
+               obj=res.obj, err1=res.err1, err3=res.err3)
+    log(f"general dense f64: {out}")
+    print(json.dumps({
+        "metric": "general SDP with dense C: C - A*(y) SpMM (dense product on matrix cores) and time to 1e-5",
+        "unit": "GB/s", "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "general SDP n=8192, C dense with N(0,1) upper-triangle entries, diag(X)=1, "
+                               "rank 24, C stored dense", **cfg},
+        "kernels": {"f64": out}}), flush=True)
 
 
 def cpu_baseline(runs, recs, target_s):

@@ -316,10 +316,13 @@ __global__ __launch_bounds__(kBlock) void k_gen_spmm(DevGeneral P, GenSpmmArgs<S
 // every 16-column tile of V (NT tiles, ld <= 16 NT), and runs
 // v_mfma_f64_16x16x4f64 over the range: A operand lane l = C[row l%16][k + l/16],
 // B operand lane l = V[k + l/16][col l%16], result register i of lane l holds
-// row l/16 + 4 i, column l%16.  C and V go through LDS in kDKC-wide k stages.
+// row l/16 + 4 i, column l%16.  C and V go through LDS in stages of kDKC = 64
+// values of k: a stage reads 64 rows x 512 contiguous bytes of C (each
+// iteration of the load loop four whole 512-byte row segments), all of them
+// issued before the first is stored, then 16 MFMA steps per tile.
 // ---------------------------------------------------------------------------
 constexpr int kDBM = 64;
-constexpr int kDKC = 16;
+constexpr int kDKC = 64;
 
 typedef double dense_acc_t __attribute__((ext_vector_type(4)));
 
@@ -329,6 +332,8 @@ __global__ __launch_bounds__(kBlock) void k_dense_mfma(const double *__restrict_
                                                        double *__restrict__ part, const SolverState *st) {
     if (st && st->done) return;
     constexpr int LDP = 16 * NT;
+    constexpr int CL = kDBM * kDKC / kBlock;   // C values per thread per stage
+    constexpr int VL = kDKC * LDP / kBlock;    // V values per thread per stage
     __shared__ double Cs[kDBM][kDKC + 1];
     __shared__ double Vs[kDKC][LDP + 1];
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
@@ -338,15 +343,34 @@ __global__ __launch_bounds__(kBlock) void k_dense_mfma(const double *__restrict_
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[t] = dense_acc_t{0.0, 0.0, 0.0, 0.0};
     for (int64_t kb = k0; kb < k1; kb += kDKC) {
-        for (int t = threadIdx.x; t < kDBM * kDKC; t += kBlock) {
+        double cv[CL], vv[VL];
+#pragma unroll
+        for (int e = 0; e < CL; ++e) {
+            const int t = threadIdx.x + e * kBlock;
             const int rr = t / kDKC, kk = t % kDKC;
             const int64_t gr = r0 + rr, gk = kb + kk;
-            Cs[rr][kk] = (gr < n && gk < k1) ? C[gr * n + gk] : 0.0;
+            const bool use = gr < n && gk < k1;
+            const double x = C[(use ? gr : r0) * n + (use ? gk : k0)];   // a valid address either way
+            cv[e] = use ? x : 0.0;
         }
-        for (int t = threadIdx.x; t < kDKC * LDP; t += kBlock) {
+#pragma unroll
+        for (int e = 0; e < VL; ++e) {
+            const int t = threadIdx.x + e * kBlock;
             const int kk = t / LDP, cc = t % LDP;
             const int64_t gk = kb + kk;
-            Vs[kk][cc] = (gk < k1 && cc < ld) ? (double)V[gk * ld + cc] : 0.0;
+            const bool use = gk < k1 && cc < ld;
+            const double x = (double)V[(use ? gk : k0) * ld + (use ? cc : 0)];
+            vv[e] = use ? x : 0.0;
+        }
+#pragma unroll
+        for (int e = 0; e < CL; ++e) {
+            const int t = threadIdx.x + e * kBlock;
+            Cs[t / kDKC][t % kDKC] = cv[e];
+        }
+#pragma unroll
+        for (int e = 0; e < VL; ++e) {
+            const int t = threadIdx.x + e * kBlock;
+            Vs[t / LDP][t % LDP] = vv[e];
         }
         __syncthreads();
 #pragma unroll
@@ -376,35 +400,56 @@ enum { kDenseStore = 0, kDenseLS = 1, kDenseRefresh = 2 };
 // Adds the k splits of each row in split order and scales by cs.  kDenseStore:
 // W_i = cs (C V)_i in the storage type; kDenseLS (V = D): s[0] += D_i . cs (C D)_i,
 // s[6] += 2 R_i . cs (C D)_i; kDenseRefresh (V = R): s[0] += R_i . cs (C R)_i.
-template <typename S, int MODE>
+// A group of GS lanes per row, one column each (GS >= ld), so that the split
+// partials and the rows of U, V, W are read and written as contiguous segments;
+// the row dots are summed by the block's fixed tree.
+template <typename S, int MODE, int GS>
 __global__ __launch_bounds__(kBlock) void k_dense_finish(const double *__restrict__ part, int ks, int64_t n,
                                                          int64_t ld, double cs, S *W, const S *U, const S *V,
                                                          double *partials, const SolverState *st) {
     if (st && st->done) return;
     constexpr int RW = (int)(kDenseRowBytes / sizeof(double));
+    constexpr int GPB = kBlock / GS;
+    const int lane = threadIdx.x % GS, grp = threadIdx.x / GS;
+    const bool act = lane < ld;
+    const int c = act ? lane : 0;
     double s[kLsSums] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int64_t row = (int64_t)blockIdx.x * kBlock + threadIdx.x; row < n; row += (int64_t)gridDim.x * kBlock) {
-        double d0 = 0.0, d1 = 0.0;
-        for (int c = 0; c < ld; ++c) {
-            double v = 0.0;
-            for (int k = 0; k < ks; ++k) v += part[((int64_t)k * n + row) * RW + c];
-            v *= cs;
-            if constexpr (MODE == kDenseStore) {
-                W[row * ld + c] = (S)v;
-            } else if constexpr (MODE == kDenseLS) {
-                d0 = fma((double)V[row * ld + c], v, d0);
-                d1 = fma((double)U[row * ld + c], v, d1);
-            } else {
-                d0 = fma((double)U[row * ld + c], v, d0);
-            }
+    for (int64_t row = (int64_t)blockIdx.x * GPB + grp; row < n; row += (int64_t)gridDim.x * GPB) {
+        double v = 0.0;
+        for (int k = 0; k < ks; ++k) v += part[((int64_t)k * n + row) * RW + c];
+        v *= cs;
+        if constexpr (MODE == kDenseStore) {
+            if (act) W[row * ld + c] = (S)v;
+        } else if constexpr (MODE == kDenseLS) {
+            const double dv = (double)V[row * ld + c], du = (double)U[row * ld + c];
+            s[0] += act ? dv * v : 0.0;
+            s[6] += act ? 2.0 * du * v : 0.0;
+        } else {
+            const double du = (double)U[row * ld + c];
+            s[0] += act ? du * v : 0.0;
         }
-        s[0] += d0;
-        if constexpr (MODE == kDenseLS) s[6] += 2.0 * d1;
     }
     if constexpr (MODE != kDenseStore) block_sums_store<kLsSums>(s, partials + (size_t)blockIdx.x * kMaxSums);
 }
 
 constexpr int kDenseFinishBlocks = 256;
+
+template <typename S, int GS>
+void finish_launch(hipStream_t s, const DevGeneral &P, int mode, int ks, int64_t ld, double cs, const S *U,
+                   const S *V, double *partials, const SolverState *st, int *nf) {
+    const int64_t n = P.n;
+    const int64_t need = (n + kBlock / GS - 1) / (kBlock / GS);
+    *nf = (int)std::min<int64_t>(need, kDenseFinishBlocks);
+    if (mode == kDenseStore)
+        hipLaunchKernelGGL((k_dense_finish<S, kDenseStore, GS>), dim3(*nf), dim3(kBlock), 0, s, P.dpart, ks, n, ld,
+                           cs, (S *)P.dw, U, V, partials, st);
+    else if (mode == kDenseLS)
+        hipLaunchKernelGGL((k_dense_finish<S, kDenseLS, GS>), dim3(*nf), dim3(kBlock), 0, s, P.dpart, ks, n, ld, cs,
+                           (S *)nullptr, U, V, partials, st);
+    else
+        hipLaunchKernelGGL((k_dense_finish<S, kDenseRefresh, GS>), dim3(*nf), dim3(kBlock), 0, s, P.dpart, ks, n, ld,
+                           cs, (S *)nullptr, U, V, partials, st);
+}
 
 // W = cs C V (MODE kDenseStore) or the dense sums of the LS / refresh pass into
 // partial rows (*nb rows written).  V, U: n x ld of S.
@@ -423,16 +468,9 @@ int dense_product(hipStream_t s, const DevGeneral &P, int mode, const S *V, cons
     else if (ld <= 32) hipLaunchKernelGGL((k_dense_mfma<S, 2>), g, dim3(kBlock), 0, s, P.cd, V, n, ld, kspan, P.dpart, st);
     else hipLaunchKernelGGL((k_dense_mfma<S, 4>), g, dim3(kBlock), 0, s, P.cd, V, n, ld, kspan, P.dpart, st);
     LRSDP_CHECK_LAUNCH();
-    const int nf = gen_grid(n, kBlock) < kDenseFinishBlocks ? gen_grid(n, kBlock) : kDenseFinishBlocks;
-    if (mode == kDenseStore)
-        hipLaunchKernelGGL((k_dense_finish<S, kDenseStore>), dim3(nf), dim3(kBlock), 0, s, P.dpart, ks, n, ld, cs,
-                           (S *)P.dw, U, V, partials, st);
-    else if (mode == kDenseLS)
-        hipLaunchKernelGGL((k_dense_finish<S, kDenseLS>), dim3(nf), dim3(kBlock), 0, s, P.dpart, ks, n, ld, cs,
-                           (S *)nullptr, U, V, partials, st);
-    else
-        hipLaunchKernelGGL((k_dense_finish<S, kDenseRefresh>), dim3(nf), dim3(kBlock), 0, s, P.dpart, ks, n, ld, cs,
-                           (S *)nullptr, U, V, partials, st);
+    int nf = 0;
+    if (ld <= 32) finish_launch<S, 32>(s, P, mode, ks, ld, cs, U, V, partials, st, &nf);
+    else finish_launch<S, 64>(s, P, mode, ks, ld, cs, U, V, partials, st, &nf);
     LRSDP_CHECK_LAUNCH();
     if (mode != kDenseStore) *nb = nf;
     return LRSDP_OK;
@@ -480,7 +518,7 @@ int cons_t(hipStream_t s, const DevGeneral &P, const ConsArgs &a, int *nb) {
 template <typename S, int MODE>
 int sddmm_t(hipStream_t s, const DevGeneral &P, const void *U, const void *V, int64_t ld, double *out, double *q1,
             double *q2, const double *ytil, double *y, double sigma, double cs, double *partials,
-            const SolverState *st, int *nb) {
+            const SolverState *st, int *nb, bool dense_sums) {
     XbarArgs<S> xa{(const S *)U, (const S *)V, ld, P.x1, P.x2, cs, partials, st};
     int nb1 = 0, nb2 = 0, rc;
     if ((rc = xbar_t<S, MODE>(s, P, xa, &nb1))) return rc;
@@ -489,7 +527,7 @@ int sddmm_t(hipStream_t s, const DevGeneral &P, const void *U, const void *V, in
                 st};
     if ((rc = cons_t<MODE>(s, P, ca, &nb2))) return rc;
     int nb3 = 0;
-    if (P.cd && MODE != kGenA) {
+    if (P.cd && MODE != kGenA && dense_sums) {
         // <C, DD^T>, <C, RD^T + DR^T> (LS, V = D) or <C, RR^T> (refresh) from the dense product
         const S *Vd = MODE == kGenLS ? (const S *)V : (const S *)U;
         if ((rc = dense_product<S>(s, P, MODE == kGenLS ? kDenseLS : kDenseRefresh, Vd, (const S *)U, ld, cs,
@@ -554,21 +592,24 @@ int gen_rank_mask(hipStream_t s, const DevGeneral &P, int prec, void *R, int64_t
 // ytil (partials: {<C,DD^T>, ytil.q2, ytil.q1, q2.q2, q1.q2, q1.q1, <C,RD^T+DR^T>});
 // mode 2: constraint values (into out when given) and the multiplier step,
 // partials {<C,RR^T>, b.y, ||A(RR^T) - b||^2}.  *nb = partial rows written.
+// dense_sums = false: a refresh pass whose partial sums the caller does not
+// read (constraint values only) skips the dense C product for <C, RR^T>.
 int gen_sddmm(hipStream_t s, const DevGeneral &P, int prec, int mode, const void *U, const void *V, int64_t ld,
               double *out, double *q1, double *q2, const double *ytil, double *y, double sigma, double cs,
-              double *partials, const SolverState *st, int *nb) {
+              double *partials, const SolverState *st, int *nb, bool dense_sums) {
+    const bool ds = dense_sums || mode != kGenRefresh;
     if (prec == LRSDP_F64) {
         if (mode == kGenA)
-            return sddmm_t<double, kGenA>(s, P, U, V, ld, out, q1, q2, ytil, y, sigma, cs, partials, st, nb);
+            return sddmm_t<double, kGenA>(s, P, U, V, ld, out, q1, q2, ytil, y, sigma, cs, partials, st, nb, ds);
         if (mode == kGenLS)
-            return sddmm_t<double, kGenLS>(s, P, U, V, ld, out, q1, q2, ytil, y, sigma, cs, partials, st, nb);
-        return sddmm_t<double, kGenRefresh>(s, P, U, V, ld, out, q1, q2, ytil, y, sigma, cs, partials, st, nb);
+            return sddmm_t<double, kGenLS>(s, P, U, V, ld, out, q1, q2, ytil, y, sigma, cs, partials, st, nb, ds);
+        return sddmm_t<double, kGenRefresh>(s, P, U, V, ld, out, q1, q2, ytil, y, sigma, cs, partials, st, nb, ds);
     }
     if (mode == kGenA)
-        return sddmm_t<float, kGenA>(s, P, U, V, ld, out, q1, q2, ytil, y, sigma, cs, partials, st, nb);
+        return sddmm_t<float, kGenA>(s, P, U, V, ld, out, q1, q2, ytil, y, sigma, cs, partials, st, nb, ds);
     if (mode == kGenLS)
-        return sddmm_t<float, kGenLS>(s, P, U, V, ld, out, q1, q2, ytil, y, sigma, cs, partials, st, nb);
-    return sddmm_t<float, kGenRefresh>(s, P, U, V, ld, out, q1, q2, ytil, y, sigma, cs, partials, st, nb);
+        return sddmm_t<float, kGenLS>(s, P, U, V, ld, out, q1, q2, ytil, y, sigma, cs, partials, st, nb, ds);
+    return sddmm_t<float, kGenRefresh>(s, P, U, V, ld, out, q1, q2, ytil, y, sigma, cs, partials, st, nb, ds);
 }
 
 int spmm_general(hipStream_t s, const DevGeneral &P, int prec, const void *V, int64_t ld, const double *ytil,

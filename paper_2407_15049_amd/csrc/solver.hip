@@ -52,7 +52,8 @@ int cmp_ytil(hipStream_t, const DevCompletion &, const SolverState *, double, co
              double *);
 int axpy_state(hipStream_t, int, const SolverState *, void *, const void *, int64_t, int64_t);
 int gen_sddmm(hipStream_t, const DevGeneral &, int, int, const void *, const void *, int64_t, double *, double *,
-              double *, const double *, double *, double, double, double *, const SolverState *, int *);
+              double *, const double *, double *, double, double, double *, const SolverState *, int *,
+              bool dense_sums = true);
 int gen_grad(hipStream_t, const DevGeneral &, int, const SolverState *, const void *, const double *, void *const *,
              void *const *, int, int64_t, double *, int, int *, double);
 int gen_rank_mask(hipStream_t, const DevGeneral &, int, void *, int64_t);
@@ -731,10 +732,11 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
                     // compressed pass) instead of the recurrence a += tau (q1 +
                     // tau q2): with float32 storage of R the recurrence drifts
                     // from the constraint values of the rounded R
+                    // (its partial sums are not read here: no dense C product for <C, RR^T>)
                     int nrf = 0;
                     if ((rc = axpy_state(s, prec, st, R, dring[it % T], n, ld))) break;
                     if ((rc = gen_sddmm(s, p->gen, prec, 2, R, nullptr, ld, acon, nullptr, nullptr, nullptr, y, 0.0,
-                                        cs, part_misc, st, &nrf)))
+                                        cs, part_misc, st, &nrf, false)))
                         break;
                     if ((rc = cmp_ytil(s, cv, st, 0.0, acon, y, ytil[0]))) break;
                 } else {

@@ -183,3 +183,34 @@ def test_solve_then_certify_er_1k(ctx, rank):
         assert cert.lambda_min < -1e-3
     else:
         assert gap <= 2e-5
+
+
+@pytest.mark.parametrize("rank", [10, 16])
+def test_lanczos_estimate_then_host_proof(ctx, rank):
+    """After a solve, the Lanczos estimate's lambda_lb (less 1e-7 of the
+    spectral scale) is proven by the host Cholesky of C - Diag(y) - shift I, and
+    the proven dual bound lies below the objective: the estimate and the proof
+    agree where both apply."""
+    import torch
+    u, v = erdos_renyi_edges(1000, 5000, 15049)
+    n = 1000
+    print_case(test="certify_then_proof", rank=rank)
+    prob = L.Problem.maxcut(n, u, v).upload(ctx)
+    op = maxcut_problem(n, u, v)
+    opts = L.default_options(prec=L.F64, rank=rank, ld=L.padded_ld(rank, L.F64))
+    Rd = torch.zeros((n, opts.ld), dtype=torch.float64, device="cuda")
+    Rd[:, :rank] = torch.from_numpy(init_factor(n, rank, 15050 if rank == 10 else 15051)).cuda()
+    yd = torch.zeros(n, dtype=torch.float64, device="cuda")
+    rc, res = L.solve(ctx, prob, Rd, yd, opts)
+    assert rc == L.OK
+    y = yd.cpu().numpy()
+    scale = spectral_scale(op, y)
+    cert = L.certify(ctx, prob, yd, max_iter=300, tol=1e-9 * scale)
+    proof = L.certify_dense(prob, y, cert.lambda_lb - 1e-7 * scale)
+    print(cert.as_dict(), proof.as_dict())
+    assert proof.status == 0
+    lam = certify.lambda_min(op, y)
+    assert proof.lambda_lb <= lam <= cert.lambda_min + 1e-9 * scale
+    assert proof.dual_bound <= res.obj
+    # a shift above the smallest Ritz value cannot be proven
+    assert L.certify_dense(prob, y, cert.lambda_min + 1e-6 * scale).status == 1
