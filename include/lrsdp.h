@@ -132,9 +132,9 @@ int lrsdp_problem_completion(int64_t n1, int64_t n2, int64_t m,
  * C (Section 3.4): <A_k, X> = sum over a < b of A_k,ab (X_ab + X_ba) plus
  * sum_a A_k,aa X_aa, and the solve applies C - A*(y) as one sparse matrix on
  * Omega.  Rejects (EINVAL) indices out of range, non-finite values, and
- * n or |Omega| beyond int32.  The row-block H0, the splitting phase, the
- * warm start and the certificate are not available for this kind
- * (EUNSUPPORTED).
+ * n or |Omega| beyond int32.  The row-block H0 and the warm start are not
+ * available for this kind (EUNSUPPORTED); the certificate's dual bound is NaN
+ * (no bound on trace X is stated).
  */
 int lrsdp_problem_general(int64_t n, int64_t c_nnz, const int32_t *c_row, const int32_t *c_col,
                           const double *c_val, int64_t m, int64_t a_nnz, const int32_t *a_con,
@@ -253,7 +253,7 @@ typedef struct {
     int     profile;          /* 1: time SpMM launches with HIP events         */
     int     verbose;          /* 1: print one line per ALM step to stderr      */
     int     phase2;           /* 1: switch to the splitting (ADMM) phase of
-                                 Section 2.2 once err1 <= switch_err1 (MaxCut) */
+                                 Section 2.2 once err1 <= switch_err1         */
     double  switch_err1;      /* ALM -> splitting threshold on err1            */
     int     admm_check;       /* splitting iterations between measure checks   */
     int     max_admm;         /* splitting iterations at most                  */
@@ -406,7 +406,8 @@ size_t lrsdp_k_alm_noalloc_max_bytes(void);
  * U <- argmin_U L(U, V, y), V <- argmin_V L(U, V, y), then
  * y <- y + sigma (b - A(U V^T)).  U, V device n x ld, y device m float64.
  * MaxCut: each half-step solved exactly per row (work unused, may be NULL).
- * Completion: each half-step solved by conjugate gradients (Algorithm 2)
+ * Completion and general problems: each half-step solved by conjugate
+ * gradients (Algorithm 2), C V formed once per half-step for a general C,
  * from the current iterate until ||r||_F <= cg_tol max(1, ||rhs||_F) or cg_max
  * steps; work: caller device memory, 256-byte aligned, of
  * lrsdp_admm_workspace_bytes; synchronises the stream (the CG scalars are
@@ -415,8 +416,8 @@ int lrsdp_k_admm(lrsdp_ctx *ctx, const lrsdp_problem *prob, int prec, void *U, v
                  double *y, double sigma, int iters, double cg_tol, int cg_max,
                  void *work, size_t work_bytes);
 
-/* Device workspace of lrsdp_k_admm: 0 for MaxCut; five n x ld arrays and
- * three m float64 vectors for completion. */
+/* Device workspace of lrsdp_k_admm: 0 for MaxCut; five n x ld arrays (six
+ * for a general problem) and three m float64 vectors otherwise. */
 int lrsdp_admm_workspace_bytes(const lrsdp_problem *prob, int prec, int64_t ld,
                                size_t *bytes);
 

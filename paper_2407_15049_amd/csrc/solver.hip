@@ -252,8 +252,6 @@ int plan_workspace(const lrsdp_problem *p, const lrsdp_options *o, WsPlan *w) {
     if (rc) return rc;
     if (o->precond < 0 || o->precond > 2) return set_error(LRSDP_EINVAL, "precond = %d not in {0, 1, 2}", o->precond);
     if (o->reopt < 0 || o->reopt > 2) return set_error(LRSDP_EINVAL, "reopt = %d not in {0, 1, 2}", o->reopt);
-    if (o->phase2 && p->info.kind == LRSDP_GENERAL)
-        return set_error(LRSDP_EUNSUPPORTED, "the splitting phase is implemented for MaxCut and completion problems");
     if (o->reopt && (!(o->reopt_factor > 0.0) || !(o->reopt_factor < 1.0) || o->max_reopt < 0))
         return set_error(LRSDP_EINVAL, "re-optimisation needs 0 < reopt_factor < 1 and max_reopt >= 0");
     if (o->reopt == 2 && o->cert_iters < 1) return set_error(LRSDP_EINVAL, "reopt = 2 needs cert_iters >= 1");
@@ -285,11 +283,12 @@ int plan_workspace(const lrsdp_problem *p, const lrsdp_options *o, WsPlan *w) {
     w->rho = take(o->precond ? (size_t)(o->lbfgs_mem + 1) * p->info.n * 8 : 0);
     w->kap = take(o->precond ? (size_t)p->info.n * 8 : 0);
     w->hdyn = take(o->precond == 2 ? (size_t)p->info.n * 8 : 0);
-    // completion splitting phase: CG scratch (five n x ld arrays, three m-vectors)
-    // and the copy of R kept for the fallback
-    const bool cph2 = o->phase2 && p->info.kind == LRSDP_COMPLETION;
+    // completion / general splitting phase: CG scratch (five n x ld arrays, six
+    // for a general problem, three m-vectors; the layout of cmp_admm_layout) and
+    // the copy of R kept for the fallback
+    const bool cph2 = o->phase2 && (p->info.kind == LRSDP_COMPLETION || p->info.kind == LRSDP_GENERAL);
     const size_t arr256 = (arr + 255) / 256 * 256, vec256 = ((size_t)p->info.m * 8 + 255) / 256 * 256;
-    w->cadmm = take(cph2 ? 5 * arr256 + 3 * vec256 : 0);
+    w->cadmm = take(cph2 ? (p->info.kind == LRSDP_GENERAL ? 6 : 5) * arr256 + 3 * vec256 : 0);
     w->csnap = take(cph2 ? arr : 0);
     // strict re-optimisation: multipliers of the original problem and the
     // certificate's workspace
@@ -353,39 +352,73 @@ int admm_iter(hipStream_t s, const DevCsr &P, int prec, void *U, void *V, int64_
 }
 
 // ---------------------------------------------------------------------------
-// Splitting iteration for matrix completion (Section 2.2, eqs. 2.2-2.3): each
-// half-step solves the positive definite system of eq. 2.2,
+// Splitting iteration for matrix completion and general problems (Section
+// 2.2, eqs. 2.2-2.3): each half-step solves the positive definite system of
+// eq. 2.2,
 //   A_V(U) = sigma A*(A(U V^T)) V + sigma U = B_V = -C V + A*(y) V + sigma A*(b) V + sigma V,
 // by conjugate gradients (Algorithm 2) warm-started at the current U, until
-// ||r||_F <= cg_tol max(1, ||B_V||_F).  With C = I and S(V, z) = (I - A*(z)) V
-// (the completion SpMM): B_V = sigma V - S(V, y + sigma b) and
-// A_V(X) = sigma (V - S(V, A(X V^T))) + sigma X.  The vector updates are combine
+// ||r||_F <= cg_tol max(1, ||B_V||_F).  With S(V, z) = (C - A*(z)) V (the
+// completion SpMM with C = I, or the general SpMM on Omega):
+// B_V = sigma V - S(V, y + sigma b) and
+// A_V(X) = sigma (C V - S(V, A(X V^T))) + sigma X, where C V = S(V, 0) is formed
+// once per half-step (C V = V for completion).  The vector updates are combine
 // passes (coefficients from the host, dots back to the host).
 // ---------------------------------------------------------------------------
 struct CmpAdmmBufs {
     void *B, *r, *p, *q, *S;   // n x ld
+    void *CV;                   // n x ld: C V of the half-step's fixed factor (general problems; V itself for C = I)
     double *z, *w, *zero;       // m
 };
 
+// General problems keep one more n x ld array (C V).
 size_t cmp_admm_bytes(const lrsdp_problem *p, int prec, int64_t ld) {
     const size_t arr = ((size_t)p->info.n * ld * elem_size(prec) + 255) / 256 * 256;
     const size_t vec = ((size_t)p->info.m * 8 + 255) / 256 * 256;
-    return 5 * arr + 3 * vec;
+    return (p->info.kind == LRSDP_GENERAL ? 6 : 5) * arr + 3 * vec;
 }
 
 CmpAdmmBufs cmp_admm_layout(const lrsdp_problem *p, int prec, int64_t ld, char *work) {
     const size_t arr = ((size_t)p->info.n * ld * elem_size(prec) + 255) / 256 * 256;
     const size_t vec = ((size_t)p->info.m * 8 + 255) / 256 * 256;
+    const int na = p->info.kind == LRSDP_GENERAL ? 6 : 5;
     CmpAdmmBufs b;
     b.B = work;
     b.r = work + arr;
     b.p = work + 2 * arr;
     b.q = work + 3 * arr;
     b.S = work + 4 * arr;
-    b.z = reinterpret_cast<double *>(work + 5 * arr);
-    b.w = reinterpret_cast<double *>(work + 5 * arr + vec);
-    b.zero = reinterpret_cast<double *>(work + 5 * arr + 2 * vec);
+    b.CV = na == 6 ? work + 5 * arr : nullptr;
+    b.z = reinterpret_cast<double *>(work + na * arr);
+    b.w = reinterpret_cast<double *>(work + na * arr + vec);
+    b.zero = reinterpret_cast<double *>(work + na * arr + 2 * vec);
     return b;
+}
+
+// The per-constraint kernels see only m and b: a general problem passes them
+// through a completion view.
+DevCompletion constraint_view(const lrsdp_problem *p) {
+    if (p->info.kind == LRSDP_COMPLETION) return p->cmp;
+    DevCompletion v{};
+    v.m = p->info.m;
+    v.b = p->gen.b;
+    return v;
+}
+
+// out = A(X V^T) (completion SDDMM or the general compressed outer product)
+int split_constraint(lrsdp_ctx *c, const lrsdp_problem *p, int prec, const void *X, const void *V, int64_t ld,
+                     double *out) {
+    int nb = 0;
+    if (p->info.kind == LRSDP_GENERAL)
+        return gen_sddmm(c->stream, p->gen, prec, 0, X, V, ld, out, nullptr, nullptr, nullptr, nullptr, 0.0, 1.0,
+                         nullptr, nullptr, &nb);
+    return cmp_sddmm(c->stream, p->cmp, prec, 0, X, V, ld, out, nullptr, nullptr, nullptr, nullptr, 0.0, nullptr,
+                     nullptr, &nb);
+}
+
+// Y = (C - A*(z)) V
+int split_spmm(lrsdp_ctx *c, const lrsdp_problem *p, int prec, const void *V, int64_t ld, const double *z, void *Y) {
+    if (p->info.kind == LRSDP_GENERAL) return spmm_general(c->stream, p->gen, prec, V, ld, z, Y);
+    return spmm_completion(c->stream, p->cmp, prec, V, ld, z, Y);
 }
 
 // out = sum_j coef_j basis_j; sums[j] = <out, basis_j>, sums[kMaxBasis] = ||out||^2 (host).
@@ -413,15 +446,14 @@ int cmp_lincomb(lrsdp_ctx *c, int prec, std::initializer_list<const void *> basi
     return LRSDP_OK;
 }
 
-// out = A_V(X) (sums as cmp_lincomb; sums[2] = <out, X>)
-int cmp_split_apply(lrsdp_ctx *c, const lrsdp_problem *p, int prec, const void *X, const void *V, int64_t ld,
-                    double sigma, const CmpAdmmBufs &b, void *out, double *sums) {
-    int nb = 0, rc;
-    if ((rc = cmp_sddmm(c->stream, p->cmp, prec, 0, X, V, ld, b.z, nullptr, nullptr, nullptr, nullptr, 0.0, nullptr,
-                        nullptr, &nb)))
-        return rc;
-    if ((rc = spmm_completion(c->stream, p->cmp, prec, V, ld, b.z, b.S))) return rc;
-    return cmp_lincomb(c, prec, {V, b.S, X}, {sigma, -sigma, sigma}, out, p->info.n, ld, sums);
+// out = A_V(X) = sigma A*(A(X V^T)) V + sigma X = sigma (C V - S(V, A(X V^T))) + sigma X
+// (sums as cmp_lincomb; sums[2] = <out, X>).  cv: C V (V itself for C = I).
+int cmp_split_apply(lrsdp_ctx *c, const lrsdp_problem *p, int prec, const void *X, const void *V, const void *cv,
+                    int64_t ld, double sigma, const CmpAdmmBufs &b, void *out, double *sums) {
+    int rc;
+    if ((rc = split_constraint(c, p, prec, X, V, ld, b.z))) return rc;
+    if ((rc = split_spmm(c, p, prec, V, ld, b.z, b.S))) return rc;
+    return cmp_lincomb(c, prec, {cv, b.S, X}, {sigma, -sigma, sigma}, out, p->info.n, ld, sums);
 }
 
 // U <- argmin of the half-step (CG from the current U); returns CG iterations in *its
@@ -430,18 +462,25 @@ int cmp_split_half(lrsdp_ctx *c, const lrsdp_problem *p, int prec, void *U, cons
     const int64_t n = p->info.n;
     double sums[kMaxBasis + 1];
     int rc;
-    if ((rc = cmp_ytil(c->stream, p->cmp, nullptr, sigma, b.zero, y, b.w))) return rc;     // w = y + sigma b
-    if ((rc = spmm_completion(c->stream, p->cmp, prec, V, ld, b.w, b.S))) return rc;
+    const DevCompletion cview = constraint_view(p);
+    // C V: V itself when C = I, else (C - A*(0)) V once for the half-step
+    const void *cv = V;
+    if (b.CV) {
+        if ((rc = split_spmm(c, p, prec, V, ld, b.zero, b.CV))) return rc;
+        cv = b.CV;
+    }
+    if ((rc = cmp_ytil(c->stream, cview, nullptr, sigma, b.zero, y, b.w))) return rc;     // w = y + sigma b
+    if ((rc = split_spmm(c, p, prec, V, ld, b.w, b.S))) return rc;
     if ((rc = cmp_lincomb(c, prec, {V, b.S}, {sigma, -1.0}, b.B, n, ld, sums))) return rc;
     const double eps = cg_tol * std::max(1.0, std::sqrt(std::max(sums[kMaxBasis], 0.0)));
-    if ((rc = cmp_split_apply(c, p, prec, U, V, ld, sigma, b, b.q, sums))) return rc;
+    if ((rc = cmp_split_apply(c, p, prec, U, V, cv, ld, sigma, b, b.q, sums))) return rc;
     if ((rc = cmp_lincomb(c, prec, {b.B, b.q}, {1.0, -1.0}, b.r, n, ld, sums))) return rc;
     double rr = sums[kMaxBasis];
     if ((rc = cmp_lincomb(c, prec, {b.r}, {1.0}, b.p, n, ld, sums))) return rc;
     int k = 0;
     for (; k < cg_max; ++k) {
         if (!(std::sqrt(std::max(rr, 0.0)) > eps)) break;
-        if ((rc = cmp_split_apply(c, p, prec, b.p, V, ld, sigma, b, b.q, sums))) return rc;
+        if ((rc = cmp_split_apply(c, p, prec, b.p, V, cv, ld, sigma, b, b.q, sums))) return rc;
         const double pq = sums[2];
         if (!(pq > 0.0) || !std::isfinite(pq)) return set_error(LRSDP_ENUMERIC, "splitting CG lost positive curvature");
         const double alpha = rr / pq;
@@ -459,13 +498,11 @@ int cmp_split_half(lrsdp_ctx *c, const lrsdp_problem *p, int prec, void *U, cons
 // One completion splitting iteration: U-step, V-step, y <- y + sigma (b - A(U V^T)).
 int cmp_admm_iter(lrsdp_ctx *c, const lrsdp_problem *p, int prec, void *U, void *V, int64_t ld, double *y,
                   double sigma, double cg_tol, int cg_max, const CmpAdmmBufs &b) {
-    int its = 0, rc, nb = 0;
+    int its = 0, rc;
     if ((rc = cmp_split_half(c, p, prec, U, V, ld, y, sigma, cg_tol, cg_max, b, &its))) return rc;
     if ((rc = cmp_split_half(c, p, prec, V, U, ld, y, sigma, cg_tol, cg_max, b, &its))) return rc;
-    if ((rc = cmp_sddmm(c->stream, p->cmp, prec, 0, U, V, ld, b.z, nullptr, nullptr, nullptr, nullptr, 0.0, nullptr,
-                        nullptr, &nb)))
-        return rc;
-    return cmp_ytil(c->stream, p->cmp, nullptr, sigma, b.z, y, y);
+    if ((rc = split_constraint(c, p, prec, U, V, ld, b.z))) return rc;
+    return cmp_ytil(c->stream, constraint_view(p), nullptr, sigma, b.z, y, y);
 }
 
 int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws, void *R, double *y,
@@ -850,9 +887,9 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
             hs.err1_prev = INFINITY;
             if ((rc = write_state(c, hs))) break;
         }
-        if (cmp && phase2_on && hs.err1 <= o->switch_err1) {
-            // completion splitting phase: CG half-steps (Algorithm 2), same measures,
-            // stop test and fallback as the MaxCut phase below
+        if ((cmp || gen) && phase2_on && hs.err1 <= o->switch_err1) {
+            // completion / general splitting phase: CG half-steps (Algorithm 2),
+            // same measures, stop test and fallback as the MaxCut phase below
             void *U = gring[0];
             void *Ravg = gring[1];
             const int64_t bytes = n * ld * (prec == LRSDP_F64 ? 8 : 4);
@@ -871,11 +908,19 @@ int solve_impl(lrsdp_ctx *c, lrsdp_problem *p, const lrsdp_options *o, char *ws,
                 if (rc) break;
                 if ((rc = launch_avg(s, prec, U, R, Ravg, n * ld))) break;
                 int nb1 = 0, nb2 = 0;
-                if ((rc = cmp_sddmm(s, p->cmp, prec, 2, Ravg, nullptr, ld, acon, nullptr, nullptr, nullptr, y, 0.0,
-                                    part_misc, nullptr, &nb1)))
-                    break;
-                const void *rb[1] = {Ravg};
-                if ((rc = launch_dots(s, prec, Ravg, rb, 1, n, ld, part_misc + (size_t)nb1 * kMaxSums, &nb2))) break;
+                if (gen) {
+                    // objective (cs C inside the pass), constraint values, no multiplier step
+                    if ((rc = gen_sddmm(s, p->gen, prec, 2, Ravg, nullptr, ld, acon, nullptr, nullptr, nullptr, y,
+                                        0.0, cs, part_misc, nullptr, &nb1)))
+                        break;
+                } else {
+                    if ((rc = cmp_sddmm(s, p->cmp, prec, 2, Ravg, nullptr, ld, acon, nullptr, nullptr, nullptr, y,
+                                        0.0, part_misc, nullptr, &nb1)))
+                        break;
+                    const void *rb[1] = {Ravg};
+                    if ((rc = launch_dots(s, prec, Ravg, rb, 1, n, ld, part_misc + (size_t)nb1 * kMaxSums, &nb2)))
+                        break;
+                }
                 if ((rc = launch_alm_finalize(s, st, part_misc, nb1 + nb2, 0, 1.0))) break;
                 if ((rc = read_state(c, &hs))) break;
                 if (o->verbose)
@@ -1439,8 +1484,6 @@ extern "C" int lrsdp_admm_workspace_bytes(const lrsdp_problem *p, int prec, int6
     if (!p || !bytes) return set_error(LRSDP_EINVAL, "NULL argument");
     int rc;
     if ((rc = check_prec(prec)) || (rc = check_ld(prec, ld))) return rc;
-    if (p->info.kind == LRSDP_GENERAL)
-        return set_error(LRSDP_EUNSUPPORTED, "the splitting phase is implemented for MaxCut and completion problems");
     *bytes = p->info.kind == LRSDP_MAXCUT ? 0 : cmp_admm_bytes(p, prec == LRSDP_F64 ? LRSDP_F64 : LRSDP_F32, ld);
     return LRSDP_OK;
 }
@@ -1454,8 +1497,6 @@ extern "C" int lrsdp_k_admm(lrsdp_ctx *c, const lrsdp_problem *p, int prec, void
         (rc = check_ld(prec, ld)))
         return rc;
     const int pr = prec == LRSDP_F64 ? LRSDP_F64 : LRSDP_F32;
-    if (p->info.kind == LRSDP_GENERAL)
-        return set_error(LRSDP_EUNSUPPORTED, "the splitting phase is implemented for MaxCut and completion problems");
     if (p->info.kind == LRSDP_MAXCUT) {
         for (int k = 0; k < iters; ++k)
             if ((rc = admm_iter(c->stream, p->csr, pr, U, V, ld, y, sigma))) return rc;

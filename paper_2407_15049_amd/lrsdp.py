@@ -477,7 +477,7 @@ def admm_workspace_bytes(prob, prec, ld):
 
 
 def k_admm(ctx, prob, prec, U, V, y, sigma, iters, cg_tol=1e-12, cg_max=1000, work=None):
-    """Splitting iterations in place (completion: CG half-steps; `work` is
+    """Splitting iterations in place (completion, general: CG half-steps; `work` is
     allocated here when None)."""
     import torch
     nb = admm_workspace_bytes(prob, prec, U.shape[1])

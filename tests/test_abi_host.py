@@ -220,11 +220,16 @@ def test_general_problem_build_and_validation():
             L.Problem.general(40, args["c_row"], args["c_col"], args["c_val"], m, args["a_con"], args["a_row"],
                               args["a_col"], args["a_val"], args["b"])
         assert e.value.code == L.EINVAL, kw
-    for kw in (dict(phase2=1), dict(precond=1)):
-        with pytest.raises(L.LrsdpError) as e:
-            L.workspace_bytes(p, L.default_options(prec=L.F64, rank=4, ld=4, **kw))
-        assert e.value.code == L.EUNSUPPORTED, kw
+    with pytest.raises(L.LrsdpError) as e:
+        L.workspace_bytes(p, L.default_options(prec=L.F64, rank=4, ld=4, precond=1))
+    assert e.value.code == L.EUNSUPPORTED
     assert L.workspace_bytes(p, L.default_options(prec=L.F64, rank=4, ld=4, reopt=2)) > 0
+    # the splitting phase adds its CG scratch: six n x ld arrays and three m-vectors (256-byte rounded) and R's copy
+    base = L.workspace_bytes(p, L.default_options(prec=L.F64, rank=4, ld=4))
+    ph2 = L.workspace_bytes(p, L.default_options(prec=L.F64, rank=4, ld=4, phase2=1))
+    arr, vec = (40 * 4 * 8 + 255) // 256 * 256, (m * 8 + 255) // 256 * 256
+    assert ph2 - base >= 6 * arr + 3 * vec + 40 * 4 * 8
+    assert L.admm_workspace_bytes(p, L.F64, 4) == 6 * arr + 3 * vec
 
 
 def test_general_blocks_build_and_validation():

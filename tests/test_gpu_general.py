@@ -397,3 +397,63 @@ def test_block_rank_one_cannot_hold_two_orthogonal_unit_rows(ctx, rank):
         assert rc != L.OK and res.err1 > 0.05
     else:
         assert rc == L.OK and res.obj == pytest.approx(1.5, rel=1e-5)
+
+
+@pytest.mark.parametrize("case,storage", [("random_small", L.C_SPARSE), ("theta_dense", L.C_DENSE),
+                                          ("random_small", L.C_DENSE)])
+def test_admm_step_parity(ctx, case, storage):
+    # splitting iterations (Section 2.2) on a general problem: CG half-steps with
+    # C V formed once per half-step, against the oracle's CG on eq. 2.2, both to
+    # 1e-12 of the right-hand side
+    import torch
+    from oracle.alm import admm_step
+    prob, op, r = setup(ctx, case, storage)
+    print_case(test="gen_admm", case=case, storage=storage)
+    rng = np.random.default_rng(51)
+    U = 0.3 * rng.standard_normal((op.n, r))
+    V = U + 0.03 * rng.standard_normal((op.n, r))
+    y = 0.1 * rng.standard_normal(op.m)
+    sigma = 2.0
+    Ud, Vd = dev_factor(U, L.F64), dev_factor(V, L.F64)
+    yd = torch.from_numpy(y.copy()).cuda()
+    L.k_admm(ctx, prob, L.F64, Ud, Vd, yd, sigma, 2, cg_tol=1e-12, cg_max=2000)
+    torch.cuda.synchronize()
+    Uo, Vo, yo = U, V, y
+    for _ in range(2):
+        Uo, Vo, yo = admm_step(op, Uo, Vo, yo, sigma, cg_tol=1e-12, cg_iters=2000)
+    scale = 1.0 + np.abs(Uo).max()
+    print("max |dU|", np.max(np.abs(host(Ud, r) - Uo)), "max |dy|", np.max(np.abs(yd.cpu().numpy() - yo)))
+    assert np.max(np.abs(host(Ud, r) - Uo)) <= 1e-9 * scale
+    assert np.max(np.abs(host(Vd, r) - Vo)) <= 1e-9 * scale
+    assert np.max(np.abs(yd.cpu().numpy() - yo)) <= 1e-9 * (1.0 + np.abs(yo).max()) * scale
+    assert np.all(host(Ud)[:, r:] == 0.0)
+
+
+@pytest.mark.parametrize("case", ["petersen", "random_small"])
+def test_solve_phase2_matches_oracle(ctx, case):
+    # ALM, then the splitting phase, to 1e-7 on both sides.  The random instance
+    # has several stationary points and the two sides' L-BFGS paths part after a
+    # few hundred iterations, so it switches after the first ALM step (err1 <=
+    # 0.1; four L-BFGS iterations, equal on both sides up to rounding) and the
+    # splitting phases start from the same point.
+    if case == "petersen":
+        u, v = petersen_edges()
+        n, t, r = 10, theta_triplets(10, u, v), 6
+        switch = 1e-3
+    else:
+        n, t, r = case_data(case)
+        switch = 1e-1
+    prob = L.Problem.general(n, *t).upload(ctx)
+    op = general_problem(n, *t)
+    print_case(test="gen_solve_phase2", case=case)
+    R0 = init_factor(n, r, 4)
+    rc, res, R, y = gpu_solve(ctx, prob, R0, L.F64, op.m, tol=1e-7, phase2=1, switch_err1=switch)
+    ores = alm_solve(op, R0, opts=OOptions(tol=1e-7, phase2=True, switch_err1=switch))
+    print(res.as_dict(), "oracle", ores.obj, ores.converged, ores.admm_iters, ores.admm_fallbacks)
+    assert rc == L.OK and ores.converged
+    assert res.admm_iters > 0 and res.admm_fallbacks == ores.admm_fallbacks == 0
+    assert abs(res.obj - ores.obj) <= 1e-5 * abs(ores.obj)
+    if case == "petersen":
+        assert res.obj == pytest.approx(-4.0, rel=1e-6)
+    m = K.alm_measures(op, R, y)
+    assert m["err1"] <= 1e-7 and abs(m["err3"]) <= 1e-7
