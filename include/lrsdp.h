@@ -560,13 +560,15 @@ int lrsdp_certify(lrsdp_ctx *ctx, const lrsdp_problem *prob, const double *y,
  * (MaxCut, completion; NaN for a general problem).  The caller picks shift,
  * e.g. the Lanczos lambda_lb less a small allowance; a failed factorisation
  * (status 1) says S - shift I is not (numerically) positive definite, i.e. the
- * shift is too high.  Host work only: O(n^3 / 6) multiply-adds on one thread
- * and up to 4.5 n^2 doubles of host memory while S' is formed (0.6 GB at
- * n = 4096), 2 n^2 after; the problem need not be uploaded.  y: host float64,
+ * shift is too high.  Host work only: O(n^3 / 6) multiply-adds (the rows of a
+ * 64-row block left of the block on up to 16 host threads, the same
+ * operations per entry as one thread) and up to 4.5 n^2 doubles of host memory
+ * while S' is formed (2.4 GB at n = 8192), 2 n^2 after; the problem need not be
+ * uploaded.  y: host float64,
  * m entries, in the caller's node labels.  Errors: EINVAL (NULL, shift or y
  * not finite), EUNSUPPORTED (n > LRSDP_PROOF_MAX_N).
  */
-#define LRSDP_PROOF_MAX_N 4096
+#define LRSDP_PROOF_MAX_N 8192
 typedef struct {
     double  shift;       /* the shift tried                                      */
     double  lambda_lb;   /* status 0: proven lower bound on lambda_min(S)        */

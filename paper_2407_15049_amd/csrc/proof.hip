@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <thread>
 #include <vector>
 
 #include "internal.h"
@@ -122,20 +123,52 @@ int build_dense(const lrsdp_problem *p, const double *y, double shift, Dense &d)
     return LRSDP_OK;
 }
 
-// Cholesky-Banachiewicz in place on the lower triangle (row-major): returns -1
-// on success, else the index of the first non-positive (or non-finite) pivot.
+// Cholesky-Banachiewicz in place on the lower triangle (row-major), by blocks
+// of kPB rows: the entries of a block's rows left of the block depend only on
+// earlier blocks, so host threads take those rows in parallel (each row's
+// entries in column order); the block's own triangle follows on one thread.
+// Every entry is the same sequence of operations as the one-thread algorithm,
+// so the rounding analysis is unchanged.  Returns -1 on success, else the index
+// of the first non-positive (or non-finite) pivot.
+constexpr int64_t kPB = 64;
+
+void row_left(std::vector<double> &a, int64_t n, int64_t i, int64_t j1) {
+    double *ri = &a[(size_t)(i * n)];
+    for (int64_t j = 0; j < j1; ++j) {
+        const double *rj = &a[(size_t)(j * n)];
+        double s = ri[j];
+        for (int64_t k = 0; k < j; ++k) s -= ri[k] * rj[k];
+        ri[j] = s / rj[j];
+    }
+}
+
 int64_t cholesky_rows(std::vector<double> &a, int64_t n) {
-    for (int64_t i = 0; i < n; ++i) {
-        double *ri = &a[(size_t)(i * n)];
-        for (int64_t j = 0; j <= i; ++j) {
-            const double *rj = &a[(size_t)(j * n)];
-            double s = ri[j];
-            for (int64_t k = 0; k < j; ++k) s -= ri[k] * rj[k];
-            if (j < i) {
-                ri[j] = s / rj[j];
-            } else {
-                if (!(s > 0.0) || !std::isfinite(s)) return i;
-                ri[i] = std::sqrt(s);
+    const int nt = (int)std::max<int64_t>(
+        1, std::min<int64_t>({16, (int64_t)std::thread::hardware_concurrency(), kPB}));
+    for (int64_t b0 = 0; b0 < n; b0 += kPB) {
+        const int64_t b1 = std::min(n, b0 + kPB);
+        if (b0 > 0) {
+            // rows of the block, columns [0, b0): independent rows
+            std::vector<std::thread> pool;
+            for (int t = 0; t < nt; ++t)
+                pool.emplace_back([&, t]() {
+                    for (int64_t i = b0 + t; i < b1; i += nt) row_left(a, n, i, b0);
+                });
+            for (auto &th : pool) th.join();
+        }
+        // the block's own triangle, row by row
+        for (int64_t i = b0; i < b1; ++i) {
+            double *ri = &a[(size_t)(i * n)];
+            for (int64_t j = b0; j <= i; ++j) {
+                const double *rj = &a[(size_t)(j * n)];
+                double s = ri[j];
+                for (int64_t k = 0; k < j; ++k) s -= ri[k] * rj[k];
+                if (j < i) {
+                    ri[j] = s / rj[j];
+                } else {
+                    if (!(s > 0.0) || !std::isfinite(s)) return i;
+                    ri[i] = std::sqrt(s);
+                }
             }
         }
     }

@@ -95,7 +95,7 @@ class Proof(C.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
 
 
-PROOF_MAX_N = 4096
+PROOF_MAX_N = 8192
 
 _P = C.c_void_p
 _I64 = C.c_int64
