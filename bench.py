@@ -457,10 +457,19 @@ def cert_of(args, ctx, dev, L, run, y, obj):
     c = L.certify(ctx, run["prob"], y, max_iter=args.cert_iters, tol=1e-8 * abs(obj) / run["n"], work=work)
     dt = time.perf_counter() - t0
     gap = (obj - c.dual_bound) / (1.0 + abs(obj) + abs(c.dual_bound))
-    return dict(lambda_min=c.lambda_min, lambda_max_ritz=c.lambda_max, cert_resid=c.resid,
-                cert_resid_rel=c.resid / max(abs(c.lambda_min), abs(c.lambda_max), 1e-300),
-                dual_bound_est=c.dual_bound, gap_est=gap, err2=c.err2, cert_iters=c.iters, cert_status=c.status,
-                cert_s=round(dt, 3))
+    out = dict(lambda_min=c.lambda_min, lambda_max_ritz=c.lambda_max, cert_resid=c.resid,
+               cert_resid_rel=c.resid / max(abs(c.lambda_min), abs(c.lambda_max), 1e-300),
+               dual_bound_est=c.dual_bound, gap_est=gap, err2=c.err2, cert_iters=c.iters, cert_status=c.status,
+               cert_s=round(dt, 3))
+    if run["n"] <= L.PROOF_MAX_N:
+        # small problems: prove the bound (host Cholesky of S - shift I) a little below the estimate
+        shift = c.lambda_lb - 1e-7 * max(abs(c.lambda_min), abs(c.lambda_max), 1.0)
+        t0 = time.perf_counter()
+        p = L.certify_dense(run["prob"], y.cpu().numpy(), shift)
+        out.update(proof_status=p.status, proof_lambda_lb=p.lambda_lb, proof_dual_bound=p.dual_bound,
+                   proof_gap=(obj - p.dual_bound) / (1.0 + abs(obj) + abs(p.dual_bound)) if p.status == 0 else None,
+                   proof_s=round(time.perf_counter() - t0, 3))
+    return out
 
 
 TRAFFIC_PROFILES = {
