@@ -762,6 +762,8 @@ def general_dense_bench(args, ctx, dev):
     b_spmm = 8.0 * n * n + 3.0 * 8.0 * n * ld
     flops = 2.0 * n * n * r
     opts = L.default_options(prec=prec, rank=r, ld=ld, time_limit_s=120.0)
+    if args.short:
+        opts.max_outer, opts.max_inner = 1, args.short
     y0 = torch.zeros(n, dtype=torch.float64, device=dev)
     ws = torch.empty(L.workspace_bytes(prob, opts), dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
